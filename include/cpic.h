@@ -1,0 +1,242 @@
+/*
+ * cpic.h -- C ABI of libcpic, an MI355X (gfx950) implementation of the
+ * data-parallel hot path of the colored particle-in-cell (CPIC) method of
+ * arXiv:2303.05599: leapfrog evolution of boost-invariant SU(3) Glasma fields
+ * on a periodic transverse lattice (Sec. II.A) coupled to a Wong-equation push
+ * of test particles whose colour charges are parallel-transported with the
+ * links (Sec. III.B).
+ *
+ * General conventions
+ *   - Every function returns cpic_status: 0 on success, a negative code on
+ *     failure; nothing aborts.  cpic_last_error() gives a message.
+ *   - A context owns all device memory it allocates and frees it in
+ *     cpic_destroy().  Host buffers passed in are owned by the caller; the
+ *     library reads/writes them only during the call, after synchronising
+ *     its stream.
+ *   - All device work of a context is enqueued on the HIP stream given to
+ *     cpic_create (NULL: the library creates its own default-priority
+ *     stream).  Functions that return data synchronise that stream.
+ *   - One context must not be used from two threads at once.
+ *   - Fixed seeds give bitwise-identical results from run to run.
+ *   - Units: inputs in fm and GeV as documented; internally everything is
+ *     in lattice ("hat") units: t = tau/a, p_hat = a p, m_hat = a m,
+ *     p^eta_hat = a^2 p^eta, fields g a^2 F.
+ */
+#ifndef CPIC_H
+#define CPIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t cpic_status;
+#define CPIC_OK 0
+#define CPIC_E_INVALID (-1)    /* bad argument or call order                        */
+#define CPIC_E_NOMEM (-2)      /* device or host allocation failed                  */
+#define CPIC_E_HIP (-3)        /* a HIP runtime call failed                         */
+#define CPIC_E_IC_NEWTON (-4)  /* initial-link Newton solve did not converge        */
+#define CPIC_E_NAN (-5)        /* NaN/Inf found by the diagnostics                  */
+#define CPIC_E_DRIFT (-6)      /* unitarity / Gauss / Casimir drift over threshold  */
+#define CPIC_E_CAPACITY (-7)   /* caller buffer too small                           */
+#define CPIC_E_CELL_JUMP (-8)  /* a particle moved more than one cell in one step   */
+#define CPIC_E_IO (-9)         /* checkpoint file could not be read or written      */
+
+typedef struct cpic_ctx cpic_ctx;
+typedef struct cpic_batch cpic_batch;
+
+#define CPIC_FP64 0
+#define CPIC_FP32 1
+#define CPIC_REP_FUND 0
+#define CPIC_REP_ADJ 1
+
+/*
+ * Glasma event parameters (Sec. II.A for the lattice and the MV model with
+ * N_s colour sheets [eq:MVchargecorrnum]; Sec. VII.A for the regulators).
+ *   N            lattice sites per transverse direction (N = 2^p 3^q, 4..1024)
+ *   L_fm         transverse box length; a = L/N
+ *   g2mu_GeV     MV scale g^2 mu
+ *   m_ir_GeV     infrared regulator of the Poisson kernel
+ *   uv_GeV       ultraviolet cut of the Poisson kernel (<= 0: none)
+ *   n_sheets     number of colour sheets per nucleus
+ *   dtau_over_a  leapfrog step in units of a (1/8 in Sec. VII.A)
+ *   tau_max_fm   end of the evolution; n_max = ceil(tau_max / dtau) steps
+ *   seed         seed of the colour-charge stream
+ *   precision    CPIC_FP64 or CPIC_FP32 (storage and update type)
+ *   reunit_every FP32 only: project links to SU(3) and renormalise the
+ *                colour charges every that many steps (0 = never)
+ *   record_every steps between broadening samples (a sample is also taken
+ *                after the last step)
+ */
+typedef struct {
+    int32_t N;
+    double L_fm;
+    double g2mu_GeV;
+    double m_ir_GeV;
+    double uv_GeV;
+    int32_t n_sheets;
+    double dtau_over_a;
+    double tau_max_fm;
+    uint64_t seed;
+    int32_t precision;
+    int32_t reunit_every;
+    int32_t record_every;
+} cpic_glasma_params;
+
+/*
+ * Test-particle species (toy-model initial conditions of Sec. III.B, colour
+ * charges from the Haar measure of Sec. IV.B).
+ *   n                number of test particles (0: fields only)
+ *   mass_GeV         mass; INFINITY selects the static (infinite-mass) branch
+ *                    of Sec. V.A: no motion, no colour rotation
+ *   pT_min/max_GeV   initial |p_T| uniform in [min, max) (equal: fixed)
+ *   azimuth_uniform  1: direction of p_T uniform; 0: along +x (the jets of Sec. VII.D)
+ *   tau_form_fm      formation time; the push starts at n_form = ceil(tau_form/dtau)
+ *   rep              CPIC_REP_FUND (q2 = 4, q3 = 10/3) or CPIC_REP_ADJ (q2 = 24, q3 = 0)
+ *   seed             seed of the particle stream
+ */
+typedef struct {
+    int64_t n;
+    double mass_GeV;
+    double pT_min_GeV;
+    double pT_max_GeV;
+    int32_t azimuth_uniform;
+    double tau_form_fm;
+    int32_t rep;
+    uint64_t seed;
+} cpic_particle_params;
+
+/* Create a context: validates the parameters and allocates the ping-pong
+ * field buffers (68 reals per site each), the particle records and the
+ * observable buffers.  hip_stream: a hipStream_t or NULL.  No computation. */
+cpic_status cpic_create(const cpic_glasma_params* glasma, const cpic_particle_params* particles, void* hip_stream,
+                        cpic_ctx** out);
+
+/* MV-model initial condition from the seeds (Sec. II and II.A; Haar colour
+ * charges, Sec. IV.B): Gaussian charges per sheet, FFT Poisson solve with the
+ * IR and UV regulators, Wilson lines, pure-gauge nucleus links, tau = 0 Glasma
+ * links from the lattice initial condition (Newton per link), pi(0); E = phi = 0.
+ * Particles: positions uniform, |p_T| and azimuth as configured, eta = p^eta = 0.
+ * Resets the step counter and the recorded samples.  Runs on the GPU in double
+ * precision and synchronises.  CPIC_E_IC_NEWTON if a link did not converge. */
+cpic_status cpic_init_mv(cpic_ctx* ctx);
+
+/* Advance n_steps leapfrog steps (Sec. II.A) with the particle push at each
+ * step n >= n_form (Sec. III.B).  Asynchronous; fails with CPIC_E_INVALID if it
+ * would pass n_max. */
+cpic_status cpic_step(cpic_ctx* ctx, int32_t n_steps);
+
+/* Advance until tau >= tau_target_fm (or n_max).  Asynchronous; uses HIP graphs
+ * for the bulk of the steps.  A no-op if already there. */
+cpic_status cpic_evolve(cpic_ctx* ctx, double tau_target_fm);
+
+/* Wait for the context's stream; reports CPIC_E_CELL_JUMP if any particle
+ * moved more than one cell in one step since the last check. */
+cpic_status cpic_sync(cpic_ctx* ctx);
+
+/* Current step n (tau = n dtau) and the number of broadening samples taken. */
+cpic_status cpic_current_step(const cpic_ctx* ctx, int64_t* n);
+cpic_status cpic_num_samples(const cpic_ctx* ctx, int32_t* n);
+
+/*
+ * Momentum broadening [eq:mombroad] averaged over the particles, raw classical
+ * value in GeV^2 (divide by D_R for the quantum mapping of Sec. VI), one entry
+ * per sample, oldest first:
+ *   tau_fm[k], dpT2[k] = <p_x^2 + p_y^2 - p_T(form)^2>, dpL2[k] = <p_z^2>
+ * with p^z = p^tau sinh(eta) + tau p^eta cosh(eta) (the tracked p_z for the
+ * static branch).  Any pointer may be NULL.  CPIC_E_CAPACITY if cap is smaller
+ * than the number of samples (nothing written).  Synchronises.
+ */
+cpic_status cpic_observables(cpic_ctx* ctx, double* tau_fm, double* dpT2_GeV2, double* dpL2_GeV2, int32_t cap);
+
+/* As above with all columns: out[6*k + c], c = tau_fm, <dp_T^2>, <dp_L^2>,
+ * <dp_par^2> (along the initial p_T direction), <dp_perp^2> (across it), and
+ * the number of particles averaged.  GeV^2. */
+cpic_status cpic_observables_full(cpic_ctx* ctx, double* out, int32_t cap);
+
+/*
+ * Diagnostics at the current step n (double-precision reductions):
+ *   out[0] sum_x |G(x)|^2, G the lattice Gauss residual
+ *          sum_i [E_i(x) - U_i(x-i)^+ E_i(x-i) U_i(x-i)] + i[phi, pi]
+ *          (the Gauss constraint of Sec. II)
+ *   out[1] max_x |G(x)|
+ *   out[2..5] lattice energy terms (1/t) sum Tr E^2, t sum Tr pi^2,
+ *          2t sum Re Tr(1 - U_12), (1/t) sum Tr(phi->_i - phi)^2 with the
+ *          momenta averaged to integer time (hat units, = g^2 a dE/deta)
+ *   out[6] max |U U^+ - 1| over all link entries, out[7] sum of its squares
+ *   out[8] max |q2 - q2(R)|, out[9] max |q3 - q3(R)| over the particles
+ *          (classical Casimirs [eq:q2_main], [eq:q3_main])
+ * Returns CPIC_E_NAN if any of them is not finite.  Synchronises.
+ */
+cpic_status cpic_diagnostics(cpic_ctx* ctx, double out[10]);
+
+/*
+ * Copy a part of the state to/from caller host memory, always as float64 in
+ * this layout (site s = y*N + x, x along e1), whatever the device precision:
+ *   CPIC_STATE_U         complex128 [2][N][N][3][3]  links U_x, U_y (row-major)
+ *   CPIC_STATE_PHI       float64 [N][N][8]           phi = g A_eta components
+ *   CPIC_STATE_E         float64 [2][N][N][8]        E_i = g a P^i at n - 1/2
+ *   CPIC_STATE_PI        float64 [N][N][8]           pi = g a^2 P^eta at n - 1/2
+ *   CPIC_STATE_PARTICLES float64 [n][20]             x, y, eta, p^x, p^y, p^eta
+ *                        (p^z for the static branch), Q^1..Q^8, cell x, cell y,
+ *                        last eta increment, initial direction (ux, uy), |p_T(form)|
+ *   CPIC_STATE_STEP      int64 [1]                   n (setting it clears the samples)
+ * bytes must equal the exact size (CPIC_E_CAPACITY otherwise).  Synchronises.
+ */
+#define CPIC_STATE_U 0
+#define CPIC_STATE_PHI 1
+#define CPIC_STATE_E 2
+#define CPIC_STATE_PI 3
+#define CPIC_STATE_PARTICLES 4
+#define CPIC_STATE_STEP 5
+cpic_status cpic_get_state(cpic_ctx* ctx, int32_t which, void* host_dst, size_t bytes);
+cpic_status cpic_set_state(cpic_ctx* ctx, int32_t which, const void* host_src, size_t bytes);
+
+/* Checkpoint: write / read the complete state (fields, particles, step, samples,
+ * parameters) to a file.  cpic_load requires a context created with the same
+ * lattice, precision and particle count.  A run resumed from a checkpoint is
+ * bitwise identical to an uninterrupted one.  CPIC_E_IO on file errors. */
+cpic_status cpic_save(cpic_ctx* ctx, const char* path);
+cpic_status cpic_load(cpic_ctx* ctx, const char* path);
+
+/* Field-kernel block shape (bx * by <= 256) and whether consecutive tiles are
+ * mapped onto one XCD.  Used by the tuner; takes effect for the next launch. */
+cpic_status cpic_set_launch(cpic_ctx* ctx, int32_t bx, int32_t by, int32_t xcd_remap);
+
+/* Kernel timing: when enabled, every field-update and particle-push launch
+ * is bracketed by HIP events on the context's stream.  cpic_timing returns
+ * the summed kernel times in ms and the launch counts since enabling, and
+ * synchronises. */
+cpic_status cpic_set_timing(cpic_ctx* ctx, int32_t enable);
+cpic_status cpic_timing(cpic_ctx* ctx, double* field_ms, double* push_ms, int64_t* n_field, int64_t* n_push);
+
+/* Message of the last failure (never NULL; static storage for a NULL ctx). */
+const char* cpic_last_error(const cpic_ctx* ctx);
+void cpic_destroy(cpic_ctx* ctx);
+
+/*
+ * Batched events: n_events independent Glasma events (each with its own
+ * lattice size, MV scale and particle species) evolved together; every step
+ * of every event is one work item of a single batched field launch and a
+ * single batched push launch, captured into HIP graphs.  Events whose n_max
+ * is reached drop out.  Parameter arrays have n_events entries.
+ */
+cpic_status cpic_batch_create(int32_t n_events, const cpic_glasma_params* glasma,
+                              const cpic_particle_params* particles, void* hip_stream, cpic_batch** out);
+cpic_status cpic_batch_init_mv(cpic_batch* b);
+/* run every event to its n_max; asynchronous */
+cpic_status cpic_batch_run(cpic_batch* b);
+cpic_status cpic_batch_sync(cpic_batch* b);
+/* per-event samples, layout of cpic_observables_full */
+cpic_status cpic_batch_observables(cpic_batch* b, int32_t event, double* out, int32_t cap, int32_t* n_samples);
+/* per-event state access, as cpic_get_state */
+cpic_status cpic_batch_get_state(cpic_batch* b, int32_t event, int32_t which, void* host_dst, size_t bytes);
+const char* cpic_batch_last_error(const cpic_batch* b);
+void cpic_batch_destroy(cpic_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CPIC_H */

@@ -1,0 +1,277 @@
+"""Python binding of libcpic (include/cpic.h): the colored particle-in-cell
+hot path of arXiv:2303.05599 on MI355X.
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  If the compiled library is missing this module raises; there
+is no fallback implementation.  PyTorch, when present, only supplies the HIP
+stream the library enqueues on.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcpic.so")
+
+FP64, FP32 = 0, 1
+REP_FUND, REP_ADJ = 0, 1
+STATE_U, STATE_PHI, STATE_E, STATE_PI, STATE_PARTICLES, STATE_STEP = range(6)
+ERRORS = {-1: "INVALID", -2: "NOMEM", -3: "HIP", -4: "IC_NEWTON", -5: "NAN", -6: "DRIFT", -7: "CAPACITY",
+          -8: "CELL_JUMP", -9: "IO"}
+
+
+class GlasmaParams(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("L_fm", ctypes.c_double), ("g2mu_GeV", ctypes.c_double),
+                ("m_ir_GeV", ctypes.c_double), ("uv_GeV", ctypes.c_double), ("n_sheets", ctypes.c_int32),
+                ("dtau_over_a", ctypes.c_double), ("tau_max_fm", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("precision", ctypes.c_int32), ("reunit_every", ctypes.c_int32), ("record_every", ctypes.c_int32)]
+
+
+class ParticleParams(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("mass_GeV", ctypes.c_double), ("pT_min_GeV", ctypes.c_double),
+                ("pT_max_GeV", ctypes.c_double), ("azimuth_uniform", ctypes.c_int32),
+                ("tau_form_fm", ctypes.c_double), ("rep", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+GLASMA_DEFAULTS = dict(N=32, L_fm=6.0, g2mu_GeV=2.0, m_ir_GeV=0.2, uv_GeV=10.0, n_sheets=1, dtau_over_a=0.125,
+                       tau_max_fm=1.0, seed=1, precision=FP64, reunit_every=16, record_every=8)
+PARTICLE_DEFAULTS = dict(n=0, mass_GeV=math.inf, pT_min_GeV=0.0, pT_max_GeV=0.0, azimuth_uniform=1,
+                         tau_form_fm=0.0, rep=REP_FUND, seed=2)
+
+
+class CpicError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{ERRORS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libcpic.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, d, sz, cp = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                                  ctypes.c_size_t, ctypes.c_char_p)
+        pp = ctypes.POINTER(ctypes.c_void_p)
+        sigs = {
+            "cpic_create": [ctypes.POINTER(GlasmaParams), ctypes.POINTER(ParticleParams), P, pp],
+            "cpic_init_mv": [P], "cpic_step": [P, i32], "cpic_evolve": [P, d], "cpic_sync": [P],
+            "cpic_current_step": [P, ctypes.POINTER(i64)], "cpic_num_samples": [P, ctypes.POINTER(i32)],
+            "cpic_observables": [P, P, P, P, i32], "cpic_observables_full": [P, P, i32],
+            "cpic_diagnostics": [P, P], "cpic_get_state": [P, i32, P, sz], "cpic_set_state": [P, i32, P, sz],
+            "cpic_save": [P, cp], "cpic_load": [P, cp], "cpic_set_launch": [P, i32, i32, i32],
+            "cpic_set_timing": [P, i32],
+            "cpic_timing": [P, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(i64), ctypes.POINTER(i64)],
+            "cpic_batch_create": [i32, ctypes.POINTER(GlasmaParams), ctypes.POINTER(ParticleParams), P, pp],
+            "cpic_batch_init_mv": [P], "cpic_batch_run": [P], "cpic_batch_sync": [P],
+            "cpic_batch_observables": [P, i32, P, i32, ctypes.POINTER(i32)],
+            "cpic_batch_get_state": [P, i32, i32, P, sz],
+        }
+        for name, args in sigs.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int32
+        for name in ("cpic_last_error", "cpic_batch_last_error"):
+            f = getattr(L, name)
+            f.argtypes = [P]
+            f.restype = ctypes.c_char_p
+        L.cpic_destroy.argtypes = [P]
+        L.cpic_destroy.restype = None
+        L.cpic_batch_destroy.argtypes = [P]
+        L.cpic_batch_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def current_stream():
+    """The HIP stream torch is using on the current device (None without torch/GPU)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except ImportError:
+        pass
+    return None
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _glasma(params):
+    p = dict(GLASMA_DEFAULTS)
+    p.update(params or {})
+    return GlasmaParams(**p)
+
+
+def _particles(params):
+    p = dict(PARTICLE_DEFAULTS)
+    p.update(params or {})
+    return ParticleParams(**p)
+
+
+class Context:
+    """One Glasma event with its test particles (cpic_ctx)."""
+
+    def __init__(self, glasma=None, particles=None, stream="torch"):
+        L = lib()
+        self.gp, self.pp = _glasma(glasma), _particles(particles)
+        s = current_stream() if stream == "torch" else stream
+        h = ctypes.c_void_p()
+        st = L.cpic_create(ctypes.byref(self.gp), ctypes.byref(self.pp), s, ctypes.byref(h))
+        if st:
+            raise CpicError(st, L.cpic_last_error(None).decode())
+        self.h = h
+        self.N = self.gp.N
+        self.np = self.pp.n
+
+    def _chk(self, st):
+        if st:
+            raise CpicError(st, lib().cpic_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().cpic_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def init_mv(self):
+        self._chk(lib().cpic_init_mv(self.h))
+
+    def step(self, n=1):
+        self._chk(lib().cpic_step(self.h, n))
+
+    def evolve(self, tau_fm):
+        self._chk(lib().cpic_evolve(self.h, tau_fm))
+
+    def sync(self):
+        self._chk(lib().cpic_sync(self.h))
+
+    @property
+    def n(self):
+        v = ctypes.c_int64()
+        self._chk(lib().cpic_current_step(self.h, ctypes.byref(v)))
+        return v.value
+
+    def num_samples(self):
+        v = ctypes.c_int32()
+        self._chk(lib().cpic_num_samples(self.h, ctypes.byref(v)))
+        return v.value
+
+    def observables(self):
+        """(k, 6): tau_fm, <dp_T^2>, <dp_L^2>, <dp_par^2>, <dp_perp^2>, count (GeV^2)."""
+        k = self.num_samples()
+        out = np.zeros((max(k, 1), 6))
+        self._chk(lib().cpic_observables_full(self.h, _ptr(out), k))
+        return out[:k]
+
+    def diagnostics(self):
+        out = np.zeros(10)
+        self._chk(lib().cpic_diagnostics(self.h, _ptr(out)))
+        return out
+
+    def _shape(self, which):
+        N = self.N
+        return {STATE_U: (2, N, N, 3, 3), STATE_PHI: (N, N, 8), STATE_E: (2, N, N, 8), STATE_PI: (N, N, 8),
+                STATE_PARTICLES: (self.np, 20), STATE_STEP: (1,)}[which]
+
+    def get_state(self, which):
+        dt = np.complex128 if which == STATE_U else (np.int64 if which == STATE_STEP else np.float64)
+        a = np.zeros(self._shape(which), dt)
+        self._chk(lib().cpic_get_state(self.h, which, _ptr(a), a.nbytes))
+        return a
+
+    def set_state(self, which, arr):
+        dt = np.complex128 if which == STATE_U else (np.int64 if which == STATE_STEP else np.float64)
+        a = np.ascontiguousarray(np.asarray(arr, dt).reshape(self._shape(which)))
+        self._chk(lib().cpic_set_state(self.h, which, _ptr(a), a.nbytes))
+
+    def state(self):
+        return {"U": self.get_state(STATE_U), "phi": self.get_state(STATE_PHI), "E": self.get_state(STATE_E),
+                "pi": self.get_state(STATE_PI)}
+
+    def load_state(self, st, n=0, particles=None):
+        """Install a lattice state (hat units, oracle layout) at step n."""
+        self.set_state(STATE_STEP, [n])
+        self.set_state(STATE_U, st["U"])
+        self.set_state(STATE_PHI, st["phi"])
+        self.set_state(STATE_E, st["E"])
+        self.set_state(STATE_PI, st["pi"])
+        if particles is not None:
+            self.set_state(STATE_PARTICLES, particles)
+
+    def save(self, path):
+        self._chk(lib().cpic_save(self.h, str(path).encode()))
+
+    def load(self, path):
+        self._chk(lib().cpic_load(self.h, str(path).encode()))
+
+    def set_launch(self, bx, by, xcd_remap=1):
+        self._chk(lib().cpic_set_launch(self.h, bx, by, xcd_remap))
+
+    def set_timing(self, enable=True):
+        self._chk(lib().cpic_set_timing(self.h, int(enable)))
+
+    def timing(self):
+        f, p = ctypes.c_double(), ctypes.c_double()
+        nf, npu = ctypes.c_int64(), ctypes.c_int64()
+        self._chk(lib().cpic_timing(self.h, ctypes.byref(f), ctypes.byref(p), ctypes.byref(nf), ctypes.byref(npu)))
+        return {"field_ms": f.value, "push_ms": p.value, "n_field": nf.value, "n_push": npu.value}
+
+
+class Batch:
+    """Many events evolved together (cpic_batch)."""
+
+    def __init__(self, glasma_list, particle_list, stream="torch"):
+        L = lib()
+        n = len(glasma_list)
+        self.gps = (GlasmaParams * n)(*[_glasma(g) for g in glasma_list])
+        self.pps = (ParticleParams * n)(*[_particles(p) for p in particle_list])
+        s = current_stream() if stream == "torch" else stream
+        h = ctypes.c_void_p()
+        st = L.cpic_batch_create(n, self.gps, self.pps, s, ctypes.byref(h))
+        if st:
+            raise CpicError(st, L.cpic_batch_last_error(None).decode())
+        self.h, self.n_events = h, n
+
+    def _chk(self, st):
+        if st:
+            raise CpicError(st, lib().cpic_batch_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().cpic_batch_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def init_mv(self):
+        self._chk(lib().cpic_batch_init_mv(self.h))
+
+    def run(self):
+        self._chk(lib().cpic_batch_run(self.h))
+
+    def sync(self):
+        self._chk(lib().cpic_batch_sync(self.h))
+
+    def observables(self, event):
+        ns = ctypes.c_int32()
+        cap = 4096
+        out = np.zeros((cap, 6))
+        self._chk(lib().cpic_batch_observables(self.h, event, _ptr(out), cap, ctypes.byref(ns)))
+        return out[:ns.value]
+
+    def get_state(self, event, which, shape, dtype=np.float64):
+        a = np.zeros(shape, dtype)
+        self._chk(lib().cpic_batch_get_state(self.h, event, which, _ptr(a), a.nbytes))
+        return a

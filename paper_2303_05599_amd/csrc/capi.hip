@@ -1,0 +1,810 @@
+// capi.hip -- the C ABI of libcpic (include/cpic.h): context lifecycle,
+// initial condition, stepping (eager or replayed HIP graphs), observables,
+// diagnostics, state exchange and checkpoints for one Glasma event.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/cpic.h"
+#include "internal.h"
+
+using namespace cpic;
+
+namespace {
+
+constexpr double kHbarC = 0.1973269804;  // GeV fm
+constexpr int kGraphSteps = 16;          // steps per captured graph (even: buffers return to their parity)
+
+// Initial colour vectors with the classical Casimirs of Sec. IV ([eq:q23_main]):
+// fundamental q2 = 4, q3 = 10/3 from Q^5 and Q^8 alone (as in [eq:initq0]),
+// Q8 the root of Q8^3 - 12 Q8 - 20/sqrt(3) = 0 closest to -1.062; adjoint Q^1 = sqrt(24).
+void initial_colour(int rep, double q0[8], double eig[3], double* q2, double* q3)
+{
+    for (int a = 0; a < 8; a++) q0[a] = 0;
+    if (rep == CPIC_REP_ADJ) {
+        q0[0] = std::sqrt(24.0);
+        eig[0] = -std::sqrt(6.0); eig[1] = 0; eig[2] = std::sqrt(6.0);
+        *q2 = 24; *q3 = 0;
+        return;
+    }
+    // Newton on f(q) = q^3 - 12 q - 20/sqrt(3) from -1
+    double q = -1.0;
+    for (int it = 0; it < 60; it++) {
+        const double f = q * q * q - 12 * q - 20 / std::sqrt(3.0), df = 3 * q * q - 12;
+        const double nq = q - f / df;
+        if (nq == q) break;
+        q = nq;
+    }
+    q0[7] = q;
+    q0[4] = -std::sqrt(4 - q * q);
+    // Q = Q5 T5 + Q8 T8: eigenvalues Q8/sqrt(3)/... from the 1-3 block and the 2-2 entry
+    const double s3 = std::sqrt(3.0);
+    const double d11 = q / (2 * s3);            // (T8)_22 Q8
+    const double a = q / (2 * s3), c = -q / s3; // 1-3 block diagonal
+    const double b = std::fabs(q0[4]) / 2;      // |off-diagonal|
+    const double m = 0.5 * (a + c), r = std::sqrt(0.25 * (a - c) * (a - c) + b * b);
+    double e[3] = {m - r, d11, m + r};
+    std::sort(e, e + 3);
+    for (int k = 0; k < 3; k++) eig[k] = e[k];
+    *q2 = 4;
+    *q3 = 10.0 / 3.0;
+}
+
+std::string g_static_error = "no error";
+
+}  // namespace
+
+struct cpic_ctx {
+    cpic_glasma_params gp{};
+    cpic_particle_params pp{};
+    hipStream_t st = nullptr;
+    bool own_stream = false;
+    int N = 0, V = 0, prec = 0;
+    size_t tsz = 8;
+    double a_fm = 0, a_gev = 0;
+    Schedule sc{};
+    int n = 0;    // host mirror of the device step counter
+    int cur = 0;  // buffer holding the state at step n
+    int64_t np = 0;
+    bool is_static = false;
+    double mhat = 0;
+    double q0[8]{}, q0eig[3]{}, q2ref = 0, q3ref = 0;
+    void* fbuf[2] = {nullptr, nullptr};
+    void* pr = nullptr;   // particle reals [18][np]
+    int* pcell = nullptr;  // [2][np]
+    int pblocks = 0, nslots = 0;
+    double* partials = nullptr;  // [nslots][pblocks][4]
+    double* obs = nullptr;       // [nslots][4]
+    std::vector<std::pair<int, int>> samples;  // (slot, step n after which it was taken)
+    int* d_step = nullptr;
+    int* d_err = nullptr;
+    int* d_fails = nullptr;
+    double* dpart = nullptr;  // diagnostics partials
+    double* dout = nullptr;   // diagnostics results [8 + 2]
+    int dcap = 0;
+    LaunchCfg cfg{};
+    bool initialised = false;
+    // graphs: [parity] -> executable graph of kGraphSteps steps starting from buffer `parity`
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_field, ev_push;
+    double t_field = 0, t_push = 0;
+    int64_t k_field = 0, k_push = 0;
+    std::string err;
+};
+
+static cpic_status fail(cpic_ctx* c, cpic_status code, const std::string& msg)
+{
+    if (c) c->err = msg; else g_static_error = msg;
+    return code;
+}
+static cpic_status hip_fail(cpic_ctx* c, hipError_t e, const char* where)
+{
+    return fail(c, CPIC_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+#define HIPCHK(c, x, where)                            \
+    do {                                               \
+        hipError_t e_ = (x);                           \
+        if (e_ != hipSuccess) return hip_fail(c, e_, where); \
+    } while (0)
+
+template <typename T> static Fields<T> F(cpic_ctx* c, int b) { return fields_at<T>(c->fbuf[b], c->V); }
+template <typename T> static Parts<T> P(cpic_ctx* c) { return {static_cast<T*>(c->pr), c->pcell}; }
+
+static bool valid_N(int N)
+{
+    if (N < 4 || N > 1024) return false;
+    while (N % 2 == 0) N /= 2;
+    while (N % 3 == 0) N /= 3;
+    return N == 1;
+}
+
+static void free_all(cpic_ctx* c)
+{
+    for (int p = 0; p < 2; p++)
+        if (c->gexec[p]) hipGraphExecDestroy(c->gexec[p]);
+    for (auto e : c->ev_field) hipEventDestroy(e);
+    for (auto e : c->ev_push) hipEventDestroy(e);
+    hipFree(c->fbuf[0]); hipFree(c->fbuf[1]); hipFree(c->pr); hipFree(c->pcell);
+    hipFree(c->partials); hipFree(c->obs); hipFree(c->d_step); hipFree(c->d_err); hipFree(c->d_fails);
+    hipFree(c->dpart); hipFree(c->dout);
+    if (c->own_stream && c->st) hipStreamDestroy(c->st);
+}
+
+extern "C" cpic_status cpic_create(const cpic_glasma_params* gp, const cpic_particle_params* pp, void* hip_stream,
+                                   cpic_ctx** out)
+{
+    if (!gp || !out) return fail(nullptr, CPIC_E_INVALID, "cpic_create: NULL argument");
+    *out = nullptr;
+    if (!valid_N(gp->N)) return fail(nullptr, CPIC_E_INVALID, "cpic_create: N must be 2^p 3^q in [4, 1024]");
+    if (!(gp->L_fm > 0) || !(gp->dtau_over_a > 0) || !(gp->tau_max_fm > 0) || gp->n_sheets < 1 ||
+        !(gp->g2mu_GeV >= 0) || !(gp->m_ir_GeV >= 0))
+        return fail(nullptr, CPIC_E_INVALID, "cpic_create: L, dtau, tau_max, n_sheets must be positive");
+    if (gp->precision != CPIC_FP64 && gp->precision != CPIC_FP32)
+        return fail(nullptr, CPIC_E_INVALID, "cpic_create: precision must be CPIC_FP64 or CPIC_FP32");
+    cpic_particle_params none{};
+    if (!pp) pp = &none;
+    if (pp->n < 0 || pp->n > (int64_t)1 << 30) return fail(nullptr, CPIC_E_INVALID, "cpic_create: bad particle count");
+    if (pp->n > 0 && (!(pp->mass_GeV > 0) || pp->pT_min_GeV < 0 || pp->pT_max_GeV < pp->pT_min_GeV ||
+                      pp->tau_form_fm < 0 || (pp->rep != CPIC_REP_FUND && pp->rep != CPIC_REP_ADJ)))
+        return fail(nullptr, CPIC_E_INVALID, "cpic_create: bad particle parameters");
+
+    {
+        const double steps = gp->tau_max_fm / (gp->dtau_over_a * gp->L_fm / gp->N);
+        const double form = pp->n > 0 ? pp->tau_form_fm / (gp->dtau_over_a * gp->L_fm / gp->N) : 0.0;
+        if (!(steps < 1e8) || !(form < 1e8))
+            return fail(nullptr, CPIC_E_INVALID, "cpic_create: tau_max / dtau or tau_form / dtau above 1e8 steps");
+    }
+    cpic_ctx* c = new cpic_ctx();
+    c->gp = *gp;
+    c->pp = *pp;
+    c->N = gp->N;
+    c->V = gp->N * gp->N;
+    c->prec = gp->precision;
+    c->tsz = c->prec == CPIC_FP64 ? 8 : 4;
+    c->a_fm = gp->L_fm / gp->N;
+    c->a_gev = c->a_fm / kHbarC;
+    const double dtau_fm = gp->dtau_over_a * c->a_fm;
+    const double steps = gp->tau_max_fm / dtau_fm;
+    c->sc.dt = gp->dtau_over_a;
+    c->sc.n_max = (int)std::ceil(steps - 1e-9 * steps);
+    c->np = pp->n;
+    c->is_static = std::isinf(pp->mass_GeV);
+    c->mhat = c->is_static ? 0.0 : pp->mass_GeV * c->a_gev;
+    if (pp->n > 0) {
+        const double f = pp->tau_form_fm / dtau_fm;
+        c->sc.n_form = (int)std::ceil(f - 1e-9 * f);
+    } else {
+        c->sc.n_form = c->sc.n_max;
+    }
+    c->sc.record_every = gp->record_every > 0 ? gp->record_every : (1 << 30);
+    c->sc.reunit_every = c->prec == CPIC_FP32 ? std::max(0, gp->reunit_every) : 0;
+    initial_colour(pp->rep, c->q0, c->q0eig, &c->q2ref, &c->q3ref);
+
+    hipError_t e = hipSuccess;
+    if (hip_stream) {
+        c->st = (hipStream_t)hip_stream;
+    } else {
+        e = hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking);
+        c->own_stream = e == hipSuccess;
+    }
+    const size_t fbytes = (size_t)kRealsPerSite * c->V * c->tsz;
+    for (int b = 0; b < 2 && e == hipSuccess; b++) e = hipMalloc(&c->fbuf[b], fbytes);
+    if (e == hipSuccess && c->np > 0) {
+        e = hipMalloc(&c->pr, (size_t)kPartReals * c->np * c->tsz);
+        if (e == hipSuccess) e = hipMalloc(&c->pcell, sizeof(int) * 2 * c->np);
+    }
+    c->pblocks = c->np > 0 ? push_blocks((int)c->np) : 0;
+    c->nslots = c->np > 0 ? num_slots(c->sc) : 0;
+    if (e == hipSuccess && c->nslots > 0) {
+        e = hipMalloc(&c->partials, sizeof(double) * 4 * (size_t)c->pblocks * c->nslots);
+        if (e == hipSuccess) e = hipMalloc(&c->obs, sizeof(double) * 4 * c->nslots);
+    }
+    if (e == hipSuccess) e = hipMalloc(&c->d_step, sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&c->d_err, sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&c->d_fails, sizeof(int));
+    c->dcap = std::max((c->V + 255) / 256, std::max(c->pblocks, 1));
+    if (e == hipSuccess) e = hipMalloc(&c->dpart, sizeof(double) * 8 * c->dcap);
+    if (e == hipSuccess) e = hipMalloc(&c->dout, sizeof(double) * 16);
+    if (e == hipSuccess) e = hipMemsetAsync(c->d_step, 0, sizeof(int), c->st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->d_err, 0, sizeof(int), c->st);
+    if (e == hipSuccess && c->obs) e = hipMemsetAsync(c->obs, 0, sizeof(double) * 4 * c->nslots, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    if (e != hipSuccess) {
+        const bool oom = e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation;
+        free_all(c);
+        delete c;
+        return fail(nullptr, oom ? CPIC_E_NOMEM : CPIC_E_HIP, std::string("cpic_create: ") + hipGetErrorString(e));
+    }
+    *out = c;
+    return CPIC_OK;
+}
+
+extern "C" void cpic_destroy(cpic_ctx* c)
+{
+    if (!c) return;
+    if (c->st) hipStreamSynchronize(c->st);
+    free_all(c);
+    delete c;
+}
+
+extern "C" const char* cpic_last_error(const cpic_ctx* c) { return c ? c->err.c_str() : g_static_error.c_str(); }
+
+static void drop_graphs(cpic_ctx* c)
+{
+    for (int p = 0; p < 2; p++)
+        if (c->gexec[p]) {
+            hipGraphExecDestroy(c->gexec[p]);
+            c->gexec[p] = nullptr;
+        }
+}
+
+static cpic_status reset_counters(cpic_ctx* c, int n)
+{
+    c->n = n;
+    c->samples.clear();
+    HIPCHK(c, hipMemcpyAsync(c->d_step, &c->n, sizeof(int), hipMemcpyHostToDevice, c->st), "step counter");
+    if (c->obs) HIPCHK(c, hipMemsetAsync(c->obs, 0, sizeof(double) * 4 * c->nslots, c->st), "obs reset");
+    HIPCHK(c, hipStreamSynchronize(c->st), "reset");
+    return CPIC_OK;
+}
+
+extern "C" cpic_status cpic_init_mv(cpic_ctx* c)
+{
+    if (!c) return fail(nullptr, CPIC_E_INVALID, "cpic_init_mv: NULL context");
+    ICArgs a{};
+    a.N = c->N;
+    a.n_sheets = c->gp.n_sheets;
+    a.seed = c->gp.seed;
+    a.g2mua = c->gp.g2mu_GeV * c->a_gev;
+    a.mhat = c->gp.m_ir_GeV * c->a_gev;
+    a.uvhat = c->gp.uv_GeV > 0 ? c->gp.uv_GeV * c->a_gev : 0.0;
+    a.tol = 1e-14;
+    a.maxit = 50;
+    void* dbl = c->fbuf[0];
+    void* stage = nullptr;
+    if (c->prec == CPIC_FP32) {
+        HIPCHK(c, hipMalloc(&stage, sizeof(double) * kRealsPerSite * c->V), "IC staging");
+        dbl = stage;
+    }
+    HIPCHK(c, hipMemsetAsync(c->d_fails, 0, sizeof(int), c->st), "IC");
+    hipError_t e = ic_glasma(a, fields_at<double>(dbl, c->V), c->d_fails, c->st);
+    if (e == hipSuccess && c->prec == CPIC_FP32)
+        e = convert_to_float((const double*)stage, (float*)c->fbuf[0], (size_t)kRealsPerSite * c->V, c->st);
+    if (e == hipSuccess && c->np > 0) {
+        PartICArgs pa{};
+        pa.N = c->N;
+        pa.np = (int)c->np;
+        pa.azimuth_uniform = c->pp.azimuth_uniform;
+        pa.seed = c->pp.seed;
+        pa.pt_min = c->pp.pT_min_GeV * c->a_gev;
+        pa.pt_max = c->pp.pT_max_GeV * c->a_gev;
+        for (int k = 0; k < 8; k++) pa.q0[k] = c->q0[k];
+        double* pdst = (double*)c->pr;
+        void* pstage = nullptr;
+        if (c->prec == CPIC_FP32) {
+            e = hipMalloc(&pstage, sizeof(double) * kPartReals * c->np);
+            pdst = (double*)pstage;
+        }
+        if (e == hipSuccess) e = ic_particles(pa, pdst, c->pcell, c->st);
+        if (e == hipSuccess && c->prec == CPIC_FP32)
+            e = convert_to_float(pdst, (float*)c->pr, (size_t)kPartReals * c->np, c->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+        hipFree(pstage);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    hipFree(stage);
+    if (e != hipSuccess) return hip_fail(c, e, "cpic_init_mv");
+    int fails = 0;
+    HIPCHK(c, hipMemcpy(&fails, c->d_fails, sizeof(int), hipMemcpyDeviceToHost), "IC");
+    c->cur = 0;
+    c->initialised = true;
+    cpic_status s = reset_counters(c, 0);
+    if (s) return s;
+    if (fails) return fail(c, CPIC_E_IC_NEWTON, "cpic_init_mv: initial-link Newton solve failed on " +
+                                                    std::to_string(fails) + " links");
+    return CPIC_OK;
+}
+
+// one step: field update (cur -> cur^1), push, step end (samples + counter)
+template <typename T> static cpic_status launch_one(cpic_ctx* c, int parity, bool with_events)
+{
+    const Fields<T> A = F<T>(c, parity), B = F<T>(c, parity ^ 1);
+    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
+    if (with_events) {
+        HIPCHK(c, hipEventCreate(&e0), "event"); HIPCHK(c, hipEventCreate(&e1), "event");
+        HIPCHK(c, hipEventRecord(e0, c->st), "event");
+    }
+    HIPCHK(c, launch_field_step<T>(A, B, c->N, c->sc, c->d_step, c->cfg, c->st), "field step");
+    if (with_events) {
+        HIPCHK(c, hipEventRecord(e1, c->st), "event");
+        c->ev_field.push_back(e0); c->ev_field.push_back(e1);
+    }
+    if (c->np > 0) {
+        PushArgs pa{};
+        pa.N = c->N;
+        pa.np = (int)c->np;
+        pa.is_static = c->is_static;
+        pa.mhat = c->mhat;
+        for (int k = 0; k < 3; k++) pa.q0eig[k] = c->q0eig[k];
+        pa.sc = c->sc;
+        if (with_events) {
+            HIPCHK(c, hipEventCreate(&e2), "event"); HIPCHK(c, hipEventCreate(&e3), "event");
+            HIPCHK(c, hipEventRecord(e2, c->st), "event");
+        }
+        HIPCHK(c, launch_push<T>(A, B.E, B.pi, P<T>(c), pa, c->d_step, c->partials, c->d_err, c->st), "push");
+        if (with_events) {
+            HIPCHK(c, hipEventRecord(e3, c->st), "event");
+            c->ev_push.push_back(e2); c->ev_push.push_back(e3);
+        }
+    }
+    HIPCHK(c, launch_step_end(c->sc, c->pblocks, c->partials, c->obs, c->d_step, c->st), "step end");
+    return CPIC_OK;
+}
+
+static cpic_status host_advance(cpic_ctx* c, int k)
+{
+    for (int j = 0; j < k; j++) {
+        if (c->np > 0 && is_record_step(c->sc, c->n)) c->samples.push_back({record_slot_of(c->sc, c->n), c->n});
+        c->n++;
+        c->cur ^= 1;
+    }
+    return CPIC_OK;
+}
+
+static cpic_status eager_steps(cpic_ctx* c, int k)
+{
+    for (int j = 0; j < k; j++) {
+        const bool ev = c->timing;
+        cpic_status s = c->prec == CPIC_FP64 ? launch_one<double>(c, c->cur, ev) : launch_one<float>(c, c->cur, ev);
+        if (s) return s;
+        host_advance(c, 1);
+    }
+    return CPIC_OK;
+}
+
+static cpic_status build_graph(cpic_ctx* c, int parity)
+{
+    hipGraph_t g = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal), "capture");
+    cpic_status s = CPIC_OK;
+    for (int j = 0; j < kGraphSteps && s == CPIC_OK; j++)
+        s = c->prec == CPIC_FP64 ? launch_one<double>(c, parity ^ (j & 1), false)
+                                 : launch_one<float>(c, parity ^ (j & 1), false);
+    hipError_t e = hipStreamEndCapture(c->st, &g);
+    if (s) { if (g) hipGraphDestroy(g); return s; }
+    if (e != hipSuccess) return hip_fail(c, e, "end capture");
+    e = hipGraphInstantiate(&c->gexec[parity], g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(c, e, "graph instantiate");
+    return CPIC_OK;
+}
+
+extern "C" cpic_status cpic_step(cpic_ctx* c, int32_t k)
+{
+    if (!c) return fail(nullptr, CPIC_E_INVALID, "cpic_step: NULL context");
+    if (!c->initialised) return fail(c, CPIC_E_INVALID, "cpic_step: no state (call cpic_init_mv or cpic_set_state)");
+    if (k < 0 || c->n + (int64_t)k > c->sc.n_max)
+        return fail(c, CPIC_E_INVALID, "cpic_step: would pass n_max = " + std::to_string(c->sc.n_max));
+    return eager_steps(c, k);
+}
+
+extern "C" cpic_status cpic_evolve(cpic_ctx* c, double tau_target_fm)
+{
+    if (!c) return fail(nullptr, CPIC_E_INVALID, "cpic_evolve: NULL context");
+    if (!c->initialised) return fail(c, CPIC_E_INVALID, "cpic_evolve: no state");
+    const double dtau_fm = c->sc.dt * c->a_fm;
+    const double f = tau_target_fm / dtau_fm;
+    int target;
+    if (!(f < (double)c->sc.n_max)) target = c->sc.n_max;  // also catches NaN and huge values
+    else target = std::max(0, (int)std::ceil(f - 1e-9 * std::fabs(f)));
+    if (target <= c->n) return CPIC_OK;
+    int left = target - c->n;
+    if (c->timing) return eager_steps(c, left);
+    while (left >= kGraphSteps) {
+        const int parity = c->cur;
+        if (!c->gexec[parity]) {
+            cpic_status s = build_graph(c, parity);
+            if (s) return s;
+        }
+        HIPCHK(c, hipGraphLaunch(c->gexec[parity], c->st), "graph launch");
+        host_advance(c, kGraphSteps);
+        left -= kGraphSteps;
+    }
+    return eager_steps(c, left);
+}
+
+static cpic_status collect_timing(cpic_ctx* c)
+{
+    for (size_t i = 0; i + 1 < c->ev_field.size(); i += 2) {
+        float ms = 0;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev_field[i], c->ev_field[i + 1]), "timing");
+        c->t_field += ms;
+        c->k_field++;
+        hipEventDestroy(c->ev_field[i]); hipEventDestroy(c->ev_field[i + 1]);
+    }
+    for (size_t i = 0; i + 1 < c->ev_push.size(); i += 2) {
+        float ms = 0;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev_push[i], c->ev_push[i + 1]), "timing");
+        c->t_push += ms;
+        c->k_push++;
+        hipEventDestroy(c->ev_push[i]); hipEventDestroy(c->ev_push[i + 1]);
+    }
+    c->ev_field.clear();
+    c->ev_push.clear();
+    return CPIC_OK;
+}
+
+extern "C" cpic_status cpic_sync(cpic_ctx* c)
+{
+    if (!c) return fail(nullptr, CPIC_E_INVALID, "cpic_sync: NULL context");
+    HIPCHK(c, hipStreamSynchronize(c->st), "cpic_sync");
+    if (c->timing) {
+        cpic_status s = collect_timing(c);
+        if (s) return s;
+    }
+    int err = 0;
+    HIPCHK(c, hipMemcpy(&err, c->d_err, sizeof(int), hipMemcpyDeviceToHost), "cpic_sync");
+    if (err) {
+        HIPCHK(c, hipMemset(c->d_err, 0, sizeof(int)), "cpic_sync");
+        return fail(c, CPIC_E_CELL_JUMP, std::to_string(err) + " particle moves of more than one cell");
+    }
+    return CPIC_OK;
+}
+
+extern "C" cpic_status cpic_current_step(const cpic_ctx* c, int64_t* n)
+{
+    if (!c || !n) return CPIC_E_INVALID;
+    *n = c->n;
+    return CPIC_OK;
+}
+extern "C" cpic_status cpic_num_samples(const cpic_ctx* c, int32_t* n)
+{
+    if (!c || !n) return CPIC_E_INVALID;
+    *n = (int32_t)c->samples.size();
+    return CPIC_OK;
+}
+
+extern "C" cpic_status cpic_observables_full(cpic_ctx* c, double* out, int32_t cap)
+{
+    if (!c) return fail(nullptr, CPIC_E_INVALID, "cpic_observables: NULL context");
+    const int ns = (int)c->samples.size();
+    if (cap < ns) return fail(c, CPIC_E_CAPACITY, "cpic_observables: capacity " + std::to_string(cap) + " < " +
+                                                      std::to_string(ns) + " samples");
+    cpic_status s = cpic_sync(c);
+    if (s) return s;
+    if (!ns || !out) return CPIC_OK;
+    std::vector<double> h(4 * (size_t)c->nslots);
+    HIPCHK(c, hipMemcpy(h.data(), c->obs, sizeof(double) * h.size(), hipMemcpyDeviceToHost), "observables");
+    const double inv = 1.0 / ((double)c->np * c->a_gev * c->a_gev);
+    for (int k = 0; k < ns; k++) {
+        const int slot = c->samples[k].first;
+        out[6 * k + 0] = (c->samples[k].second + 1) * c->sc.dt * c->a_fm;
+        for (int j = 0; j < 4; j++) out[6 * k + 1 + j] = h[4 * (size_t)slot + j] * inv;
+        out[6 * k + 5] = (double)c->np;
+    }
+    return CPIC_OK;
+}
+
+extern "C" cpic_status cpic_observables(cpic_ctx* c, double* tau_fm, double* dpT2, double* dpL2, int32_t cap)
+{
+    if (!c) return fail(nullptr, CPIC_E_INVALID, "cpic_observables: NULL context");
+    const int ns = (int)c->samples.size();
+    std::vector<double> full(6 * (size_t)std::max(ns, 1));
+    cpic_status s = cpic_observables_full(c, full.data(), cap < ns ? cap : ns);
+    if (s) return s;
+    for (int k = 0; k < ns; k++) {
+        if (tau_fm) tau_fm[k] = full[6 * k];
+        if (dpT2) dpT2[k] = full[6 * k + 1];
+        if (dpL2) dpL2[k] = full[6 * k + 2];
+    }
+    return CPIC_OK;
+}
+
+extern "C" cpic_status cpic_diagnostics(cpic_ctx* c, double out[10])
+{
+    if (!c || !out) return fail(c, CPIC_E_INVALID, "cpic_diagnostics: NULL argument");
+    if (!c->initialised) return fail(c, CPIC_E_INVALID, "cpic_diagnostics: no state");
+    int nb = 0;
+    hipError_t e = c->prec == CPIC_FP64
+                       ? launch_field_diag<double>(F<double>(c, c->cur), c->N, c->sc.dt, c->n, c->dpart, c->dcap, &nb, c->st)
+                       : launch_field_diag<float>(F<float>(c, c->cur), c->N, c->sc.dt, c->n, c->dpart, c->dcap, &nb, c->st);
+    HIPCHK(c, e, "field diagnostics");
+    HIPCHK(c, launch_reduce_rows(c->dpart, nb, 8, c->dout, c->st), "reduce");
+    double h[10] = {0};
+    HIPCHK(c, hipStreamSynchronize(c->st), "diagnostics");
+    HIPCHK(c, hipMemcpy(h, c->dout, sizeof(double) * 8, hipMemcpyDeviceToHost), "diagnostics");
+    if (c->np > 0) {
+        e = c->prec == CPIC_FP64 ? launch_part_diag<double>(P<double>(c), (int)c->np, c->q2ref, c->q3ref, c->dpart, c->st)
+                                 : launch_part_diag<float>(P<float>(c), (int)c->np, c->q2ref, c->q3ref, c->dpart, c->st);
+        HIPCHK(c, e, "particle diagnostics");
+        HIPCHK(c, launch_reduce_rows(c->dpart, c->pblocks, 2, c->dout + 8, c->st), "reduce");
+        HIPCHK(c, hipStreamSynchronize(c->st), "diagnostics");
+        HIPCHK(c, hipMemcpy(h + 8, c->dout + 8, sizeof(double) * 2, hipMemcpyDeviceToHost), "diagnostics");
+    }
+    std::memcpy(out, h, sizeof(h));
+    for (int k = 0; k < 10; k++)
+        if (!std::isfinite(h[k])) return fail(c, CPIC_E_NAN, "cpic_diagnostics: non-finite value in column " + std::to_string(k));
+    return CPIC_OK;
+}
+
+// ------------------------------------------------------------------ state exchange
+static size_t state_bytes(const cpic_ctx* c, int which)
+{
+    switch (which) {
+    case CPIC_STATE_U: return sizeof(double) * 36 * (size_t)c->V;
+    case CPIC_STATE_PHI: case CPIC_STATE_PI: return sizeof(double) * 8 * (size_t)c->V;
+    case CPIC_STATE_E: return sizeof(double) * 16 * (size_t)c->V;
+    case CPIC_STATE_PARTICLES: return sizeof(double) * 20 * (size_t)c->np;
+    case CPIC_STATE_STEP: return sizeof(int64_t);
+    default: return 0;
+    }
+}
+
+// device SoA (type T) <-> host interchange (double, site-major)
+template <typename T> static void soa_to_host(const std::vector<T>& d, double* h, int which, int V)
+{
+    if (which == CPIC_STATE_U) {
+        for (int i = 0; i < 2; i++)
+            for (int s = 0; s < V; s++)
+                for (int c = 0; c < 18; c++) h[((size_t)i * V + s) * 18 + c] = (double)d[((size_t)i * 18 + c) * V + s];
+    } else {
+        const int blocks = which == CPIC_STATE_E ? 2 : 1;
+        for (int i = 0; i < blocks; i++)
+            for (int s = 0; s < V; s++)
+                for (int a = 0; a < 8; a++) h[((size_t)i * V + s) * 8 + a] = (double)d[((size_t)i * 8 + a) * V + s];
+    }
+}
+template <typename T> static void host_to_soa(const double* h, std::vector<T>& d, int which, int V)
+{
+    if (which == CPIC_STATE_U) {
+        for (int i = 0; i < 2; i++)
+            for (int s = 0; s < V; s++)
+                for (int c = 0; c < 18; c++) d[((size_t)i * 18 + c) * V + s] = (T)h[((size_t)i * V + s) * 18 + c];
+    } else {
+        const int blocks = which == CPIC_STATE_E ? 2 : 1;
+        for (int i = 0; i < blocks; i++)
+            for (int s = 0; s < V; s++)
+                for (int a = 0; a < 8; a++) d[((size_t)i * 8 + a) * V + s] = (T)h[((size_t)i * V + s) * 8 + a];
+    }
+}
+static size_t field_offset(int which, int V)
+{
+    switch (which) {
+    case CPIC_STATE_U: return 0;
+    case CPIC_STATE_PHI: return 36 * (size_t)V;
+    case CPIC_STATE_E: return 44 * (size_t)V;
+    default: return 60 * (size_t)V;  // PI
+    }
+}
+// interchange particle columns: x y eta px py peta Q1..Q8 cx cy deta ux0 uy0 pt0
+static const int kXchgToDev[20] = {PX_, PY_, PETA_, PPX, PPY, PPETA, PQ0, PQ0 + 1, PQ0 + 2, PQ0 + 3, PQ0 + 4,
+                                   PQ0 + 5, PQ0 + 6, PQ0 + 7, -1, -2, PDETA, PUX0, PUY0, PPT0};
+
+template <typename T> static cpic_status get_t(cpic_ctx* c, int which, double* h)
+{
+    if (which == CPIC_STATE_PARTICLES) {
+        const size_t np = c->np;
+        std::vector<T> r(kPartReals * np);
+        std::vector<int> cell(2 * np);
+        HIPCHK(c, hipMemcpy(r.data(), c->pr, sizeof(T) * r.size(), hipMemcpyDeviceToHost), "get particles");
+        HIPCHK(c, hipMemcpy(cell.data(), c->pcell, sizeof(int) * cell.size(), hipMemcpyDeviceToHost), "get particles");
+        for (size_t p = 0; p < np; p++)
+            for (int k = 0; k < 20; k++) {
+                const int d = kXchgToDev[k];
+                h[p * 20 + k] = d >= 0 ? (double)r[(size_t)d * np + p] : (double)cell[(size_t)(-d - 1) * np + p];
+            }
+        return CPIC_OK;
+    }
+    const size_t cnt = which == CPIC_STATE_U ? 36 : (which == CPIC_STATE_E ? 16 : 8);
+    std::vector<T> d(cnt * c->V);
+    const T* src = static_cast<const T*>(c->fbuf[c->cur]) + field_offset(which, c->V);
+    HIPCHK(c, hipMemcpy(d.data(), src, sizeof(T) * d.size(), hipMemcpyDeviceToHost), "get state");
+    soa_to_host(d, h, which, c->V);
+    return CPIC_OK;
+}
+template <typename T> static cpic_status set_t(cpic_ctx* c, int which, const double* h)
+{
+    if (which == CPIC_STATE_PARTICLES) {
+        const size_t np = c->np;
+        std::vector<T> r(kPartReals * np);
+        std::vector<int> cell(2 * np);
+        for (size_t p = 0; p < np; p++)
+            for (int k = 0; k < 20; k++) {
+                const int d = kXchgToDev[k];
+                if (d >= 0) r[(size_t)d * np + p] = (T)h[p * 20 + k];
+                else cell[(size_t)(-d - 1) * np + p] = (int)h[p * 20 + k];
+            }
+        HIPCHK(c, hipMemcpy(c->pr, r.data(), sizeof(T) * r.size(), hipMemcpyHostToDevice), "set particles");
+        HIPCHK(c, hipMemcpy(c->pcell, cell.data(), sizeof(int) * cell.size(), hipMemcpyHostToDevice), "set particles");
+        return CPIC_OK;
+    }
+    const size_t cnt = which == CPIC_STATE_U ? 36 : (which == CPIC_STATE_E ? 16 : 8);
+    std::vector<T> d(cnt * c->V);
+    host_to_soa(h, d, which, c->V);
+    T* dst = static_cast<T*>(c->fbuf[c->cur]) + field_offset(which, c->V);
+    HIPCHK(c, hipMemcpy(dst, d.data(), sizeof(T) * d.size(), hipMemcpyHostToDevice), "set state");
+    return CPIC_OK;
+}
+
+extern "C" cpic_status cpic_get_state(cpic_ctx* c, int32_t which, void* dst, size_t bytes)
+{
+    if (!c || !dst) return fail(c, CPIC_E_INVALID, "cpic_get_state: NULL argument");
+    const size_t need = state_bytes(c, which);
+    if (!need && which != CPIC_STATE_PARTICLES) return fail(c, CPIC_E_INVALID, "cpic_get_state: unknown part");
+    if (bytes != need) return fail(c, CPIC_E_CAPACITY, "cpic_get_state: expected " + std::to_string(need) + " bytes");
+    HIPCHK(c, hipStreamSynchronize(c->st), "get state");
+    if (which == CPIC_STATE_STEP) {
+        const int64_t n = c->n;
+        std::memcpy(dst, &n, sizeof n);
+        return CPIC_OK;
+    }
+    if (which == CPIC_STATE_PARTICLES && c->np == 0) return CPIC_OK;
+    return c->prec == CPIC_FP64 ? get_t<double>(c, which, (double*)dst) : get_t<float>(c, which, (double*)dst);
+}
+
+extern "C" cpic_status cpic_set_state(cpic_ctx* c, int32_t which, const void* src, size_t bytes)
+{
+    if (!c || !src) return fail(c, CPIC_E_INVALID, "cpic_set_state: NULL argument");
+    const size_t need = state_bytes(c, which);
+    if (!need && which != CPIC_STATE_PARTICLES) return fail(c, CPIC_E_INVALID, "cpic_set_state: unknown part");
+    if (bytes != need) return fail(c, CPIC_E_CAPACITY, "cpic_set_state: expected " + std::to_string(need) + " bytes");
+    HIPCHK(c, hipStreamSynchronize(c->st), "set state");
+    if (which == CPIC_STATE_STEP) {
+        int64_t n;
+        std::memcpy(&n, src, sizeof n);
+        if (n < 0 || n > c->sc.n_max) return fail(c, CPIC_E_INVALID, "cpic_set_state: step out of range");
+        c->initialised = true;
+        return reset_counters(c, (int)n);
+    }
+    if (which == CPIC_STATE_PARTICLES && c->np == 0) return CPIC_OK;
+    if (which == CPIC_STATE_PARTICLES) {
+        const double* h = (const double*)src;
+        for (int64_t p = 0; p < c->np; p++) {
+            const double cx = h[p * 20 + 14], cy = h[p * 20 + 15];
+            if (!(cx >= 0 && cx < c->N && cy >= 0 && cy < c->N) || cx != std::floor(cx) || cy != std::floor(cy))
+                return fail(c, CPIC_E_INVALID, "cpic_set_state: particle cell out of range");
+            const double x = h[p * 20], y = h[p * 20 + 1];
+            if (!(x >= 0 && x < c->N && y >= 0 && y < c->N))
+                return fail(c, CPIC_E_INVALID, "cpic_set_state: particle position out of [0, N)");
+        }
+    }
+    return c->prec == CPIC_FP64 ? set_t<double>(c, which, (const double*)src) : set_t<float>(c, which, (const double*)src);
+}
+
+// ------------------------------------------------------------------ checkpoints
+namespace {
+struct CkptHeader {
+    char magic[8];
+    int32_t version, N, prec, n, cur_unused, nsamples;
+    int64_t np;
+    int32_t nslots, pad;
+    cpic_glasma_params gp;
+    cpic_particle_params pp;
+};
+}
+
+extern "C" cpic_status cpic_save(cpic_ctx* c, const char* path)
+{
+    if (!c || !path) return fail(c, CPIC_E_INVALID, "cpic_save: NULL argument");
+    HIPCHK(c, hipStreamSynchronize(c->st), "save");
+    CkptHeader h{};
+    std::memcpy(h.magic, "CPICKPT1", 8);
+    h.version = 1; h.N = c->N; h.prec = c->prec; h.n = c->n; h.nsamples = (int)c->samples.size();
+    h.np = c->np; h.nslots = c->nslots; h.gp = c->gp; h.pp = c->pp;
+    const size_t fb = (size_t)kRealsPerSite * c->V * c->tsz, pb = (size_t)kPartReals * c->np * c->tsz;
+    std::vector<char> f(fb), p(pb);
+    std::vector<int> cell(2 * c->np);
+    std::vector<double> obs(4 * (size_t)c->nslots);
+    HIPCHK(c, hipMemcpy(f.data(), c->fbuf[c->cur], fb, hipMemcpyDeviceToHost), "save");
+    if (pb) {
+        HIPCHK(c, hipMemcpy(p.data(), c->pr, pb, hipMemcpyDeviceToHost), "save");
+        HIPCHK(c, hipMemcpy(cell.data(), c->pcell, sizeof(int) * cell.size(), hipMemcpyDeviceToHost), "save");
+    }
+    if (!obs.empty()) HIPCHK(c, hipMemcpy(obs.data(), c->obs, sizeof(double) * obs.size(), hipMemcpyDeviceToHost), "save");
+    FILE* fp = std::fopen(path, "wb");
+    if (!fp) return fail(c, CPIC_E_IO, std::string("cpic_save: cannot open ") + path);
+    bool ok = std::fwrite(&h, sizeof h, 1, fp) == 1;
+    for (auto& sm : c->samples) {
+        const int32_t v[2] = {sm.first, sm.second};
+        ok = ok && std::fwrite(v, sizeof v, 1, fp) == 1;
+    }
+    ok = ok && std::fwrite(f.data(), 1, fb, fp) == fb;
+    if (pb) {
+        ok = ok && std::fwrite(p.data(), 1, pb, fp) == pb;
+        ok = ok && std::fwrite(cell.data(), sizeof(int), cell.size(), fp) == cell.size();
+    }
+    if (!obs.empty()) ok = ok && std::fwrite(obs.data(), sizeof(double), obs.size(), fp) == obs.size();
+    ok = (std::fclose(fp) == 0) && ok;
+    if (!ok) return fail(c, CPIC_E_IO, std::string("cpic_save: write failed for ") + path);
+    return CPIC_OK;
+}
+
+extern "C" cpic_status cpic_load(cpic_ctx* c, const char* path)
+{
+    if (!c || !path) return fail(c, CPIC_E_INVALID, "cpic_load: NULL argument");
+    FILE* fp = std::fopen(path, "rb");
+    if (!fp) return fail(c, CPIC_E_IO, std::string("cpic_load: cannot open ") + path);
+    CkptHeader h{};
+    bool ok = std::fread(&h, sizeof h, 1, fp) == 1 && std::memcmp(h.magic, "CPICKPT1", 8) == 0 && h.version == 1;
+    if (ok && (h.N != c->N || h.prec != c->prec || h.np != c->np || h.nslots != c->nslots || h.nsamples < 0 ||
+               h.nsamples > c->nslots || h.n < 0 || h.n > c->sc.n_max)) {
+        std::fclose(fp);
+        return fail(c, CPIC_E_INVALID, "cpic_load: checkpoint does not match this context");
+    }
+    std::vector<std::pair<int, int>> samples;
+    for (int k = 0; ok && k < h.nsamples; k++) {
+        int32_t v[2];
+        ok = std::fread(v, sizeof v, 1, fp) == 1 && v[0] >= 0 && v[0] < c->nslots;
+        samples.push_back({v[0], v[1]});
+    }
+    const size_t fb = (size_t)kRealsPerSite * c->V * c->tsz, pb = (size_t)kPartReals * c->np * c->tsz;
+    std::vector<char> f(fb), p(pb);
+    std::vector<int> cell(2 * c->np);
+    std::vector<double> obs(4 * (size_t)c->nslots);
+    ok = ok && std::fread(f.data(), 1, fb, fp) == fb;
+    if (pb) {
+        ok = ok && std::fread(p.data(), 1, pb, fp) == pb;
+        ok = ok && std::fread(cell.data(), sizeof(int), cell.size(), fp) == cell.size();
+    }
+    if (!obs.empty()) ok = ok && std::fread(obs.data(), sizeof(double), obs.size(), fp) == obs.size();
+    std::fclose(fp);
+    if (!ok) return fail(c, CPIC_E_IO, std::string("cpic_load: truncated or corrupt checkpoint ") + path);
+    for (int v : cell)
+        if (v < 0 || v >= c->N) return fail(c, CPIC_E_IO, "cpic_load: corrupt particle cells");
+    HIPCHK(c, hipStreamSynchronize(c->st), "load");
+    c->cur = 0;
+    HIPCHK(c, hipMemcpy(c->fbuf[0], f.data(), fb, hipMemcpyHostToDevice), "load");
+    if (pb) {
+        HIPCHK(c, hipMemcpy(c->pr, p.data(), pb, hipMemcpyHostToDevice), "load");
+        HIPCHK(c, hipMemcpy(c->pcell, cell.data(), sizeof(int) * cell.size(), hipMemcpyHostToDevice), "load");
+    }
+    c->n = h.n;
+    HIPCHK(c, hipMemcpy(c->d_step, &c->n, sizeof(int), hipMemcpyHostToDevice), "load");
+    if (!obs.empty()) HIPCHK(c, hipMemcpy(c->obs, obs.data(), sizeof(double) * obs.size(), hipMemcpyHostToDevice), "load");
+    c->samples = samples;
+    c->initialised = true;
+    return CPIC_OK;
+}
+
+// ------------------------------------------------------------------ tuning and timing
+extern "C" cpic_status cpic_set_launch(cpic_ctx* c, int32_t bx, int32_t by, int32_t remap)
+{
+    if (!c) return fail(nullptr, CPIC_E_INVALID, "cpic_set_launch: NULL context");
+    if (bx <= 0 || by <= 0 || bx * by > 256 || (bx * by) % 64 != 0)
+        return fail(c, CPIC_E_INVALID, "cpic_set_launch: need bx*by a multiple of 64 and <= 256");
+    c->cfg.bx = bx;
+    c->cfg.by = by;
+    c->cfg.xcd_remap = remap ? 1 : 0;
+    drop_graphs(c);
+    return CPIC_OK;
+}
+
+extern "C" cpic_status cpic_set_timing(cpic_ctx* c, int32_t enable)
+{
+    if (!c) return fail(nullptr, CPIC_E_INVALID, "cpic_set_timing: NULL context");
+    cpic_status s = cpic_sync(c);
+    if (s) return s;
+    c->timing = enable != 0;
+    c->t_field = c->t_push = 0;
+    c->k_field = c->k_push = 0;
+    return CPIC_OK;
+}
+
+extern "C" cpic_status cpic_timing(cpic_ctx* c, double* field_ms, double* push_ms, int64_t* n_field, int64_t* n_push)
+{
+    if (!c) return fail(nullptr, CPIC_E_INVALID, "cpic_timing: NULL context");
+    cpic_status s = cpic_sync(c);
+    if (s) return s;
+    if (field_ms) *field_ms = c->t_field;
+    if (push_ms) *push_ms = c->t_push;
+    if (n_field) *n_field = c->k_field;
+    if (n_push) *n_push = c->k_push;
+    return CPIC_OK;
+}

@@ -1,0 +1,261 @@
+// field.hip -- the Glasma field update: one fused kick + drift pass per
+// leapfrog step (Sec. II.A), plus the per-site diagnostics (Gauss residual,
+// lattice energy, link unitarity).
+//
+// One thread owns one site.  Links and scalars of the neighbouring sites
+// are read straight from the structure-of-arrays buffers; tiles are
+// assigned so that the workgroups that share halos run on the same XCD and
+// hit the same L2.  The step reads buffer `in` and writes buffer `out`
+// (ping-pong), so the particle push can still see U(n), phi(n), E(n-1/2),
+// pi(n-1/2) next to E(n+1/2), pi(n+1/2).
+#include "internal.h"
+#include "reduce.h"
+#include "su3.h"
+
+namespace cpic {
+
+template <typename T> __device__ __forceinline__ m3<T> ldU(const T* __restrict__ U, int i, int s, int V)
+{
+    const T* p = U + (size_t)i * 18 * V + s;
+    m3<T> m;
+#pragma unroll
+    for (int c = 0; c < 9; c++) m.e[c] = {p[(size_t)(2 * c) * V], p[(size_t)(2 * c + 1) * V]};
+    return m;
+}
+template <typename T> __device__ __forceinline__ void stU(T* __restrict__ U, int i, int s, int V, const m3<T>& m)
+{
+    T* p = U + (size_t)i * 18 * V + s;
+#pragma unroll
+    for (int c = 0; c < 9; c++) {
+        p[(size_t)(2 * c) * V] = m.e[c].re;
+        p[(size_t)(2 * c + 1) * V] = m.e[c].im;
+    }
+}
+template <typename T> __device__ __forceinline__ a8<T> ldA(const T* __restrict__ p, int s, int V)
+{
+    a8<T> r;
+#pragma unroll
+    for (int a = 0; a < 8; a++) r.v[a] = p[(size_t)a * V + s];
+    return r;
+}
+template <typename T> __device__ __forceinline__ void stA(T* __restrict__ p, int s, int V, const a8<T>& r)
+{
+#pragma unroll
+    for (int a = 0; a < 8; a++) p[(size_t)a * V + s] = r.v[a];
+}
+
+struct Nbr {
+    int s, xp, xm, yp, ym, xpym, xmyp;
+};
+__device__ __forceinline__ Nbr neighbours(int x, int y, int N)
+{
+    const int xp = x + 1 == N ? 0 : x + 1, xm = x == 0 ? N - 1 : x - 1;
+    const int yp = y + 1 == N ? 0 : y + 1, ym = y == 0 ? N - 1 : y - 1;
+    return {y * N + x, y * N + xp, y * N + xm, yp * N + x, ym * N + x, ym * N + xp, yp * N + xm};
+}
+
+// Kick forces at time t from U(t), phi(t) (lattice equations of motion, Sec. II.A):
+//   F_i  = -t (Proj U_ij + Proj U_{i,-j}) + (1/t) i[phi->_i, phi]
+//   F_pi = (1/t) sum_i (phi->_i + phi<-_i - 2 phi)
+// Also returns the plaquette trace Re Tr U_12 and the scalar-gradient
+// term sum_i |phi->_i - phi|^2 / 2 for the energy.
+template <typename T>
+__device__ __forceinline__ void kick_forces(const Fields<T>& f, int V, const Nbr& nb, T t, T inv_t, const a8<T>& PHI,
+                                            a8<T>& F1, a8<T>& F2, a8<T>& Fpi, T* re_tr_p12 = nullptr,
+                                            T* grad2 = nullptr)
+{
+    const m3<T> U1 = ldU(f.U, 0, nb.s, V), U2 = ldU(f.U, 1, nb.s, V);
+    const m3<T> U1xm = ldU(f.U, 0, nb.xm, V), U2ym = ldU(f.U, 1, nb.ym, V);
+    {   // U_12(x) = U_1(x) U_2(x+1) [U_2(x) U_1(x+2)]^+
+        const m3<T> A = mul(U1, ldU(f.U, 1, nb.xp, V));
+        const m3<T> B = mul(U2, ldU(f.U, 0, nb.yp, V));
+        const m3<T> P = mul_adj(A, B);
+        F1 = proj(P);
+#pragma unroll
+        for (int a = 0; a < 8; a++) F2.v[a] = -F1.v[a];   // Proj U_21 = -Proj U_12
+        if (re_tr_p12) *re_tr_p12 = P.e[0].re + P.e[4].re + P.e[8].re;
+    }
+    {   // U_{1,-2}(x) = U_1(x) U_2(x+1-2)^+ [U_2(x-2)^+ U_1(x-2)]^+
+        const m3<T> A = mul_adj(U1, ldU(f.U, 1, nb.xpym, V));
+        const m3<T> C = adj_mul(U2ym, ldU(f.U, 0, nb.ym, V));
+        const a8<T> p = proj(mul_adj(A, C));
+#pragma unroll
+        for (int a = 0; a < 8; a++) F1.v[a] += p.v[a];
+    }
+    {   // U_{2,-1}(x) = U_2(x) U_1(x-1+2)^+ [U_1(x-1)^+ U_2(x-1)]^+
+        const m3<T> A = mul_adj(U2, ldU(f.U, 0, nb.xmyp, V));
+        const m3<T> C = adj_mul(U1xm, ldU(f.U, 1, nb.xm, V));
+        const a8<T> p = proj(mul_adj(A, C));
+#pragma unroll
+        for (int a = 0; a < 8; a++) F2.v[a] += p.v[a];
+    }
+#pragma unroll
+    for (int a = 0; a < 8; a++) { F1.v[a] *= -t; F2.v[a] *= -t; }
+    const a8<T> f1 = transport(U1, ldA(f.phi, nb.xp, V));
+    const a8<T> f2 = transport(U2, ldA(f.phi, nb.yp, V));
+    const a8<T> b1 = transport_adj(U1xm, ldA(f.phi, nb.xm, V));
+    const a8<T> b2 = transport_adj(U2ym, ldA(f.phi, nb.ym, V));
+    const a8<T> c1 = icomm(f1, PHI), c2 = icomm(f2, PHI);
+    T g2 = 0;
+#pragma unroll
+    for (int a = 0; a < 8; a++) {
+        F1.v[a] += inv_t * c1.v[a];
+        F2.v[a] += inv_t * c2.v[a];
+        Fpi.v[a] = inv_t * (f1.v[a] + f2.v[a] + b1.v[a] + b2.v[a] - T(4) * PHI.v[a]);
+        const T d1 = f1.v[a] - PHI.v[a], d2 = f2.v[a] - PHI.v[a];
+        g2 += T(0.5) * (d1 * d1 + d2 * d2);
+    }
+    if (grad2) *grad2 = g2;
+}
+
+__device__ __forceinline__ bool tile_coords(int N, int bx, int by, int remap, int& x, int& y)
+{
+    const int ntx = (N + bx - 1) / bx, nty = (N + by - 1) / by, ntiles = ntx * nty;
+    int tile = blockIdx.x;
+    if (remap) {  // workgroups are dealt round-robin to the 8 XCDs: give each XCD a contiguous band
+        const int per = (ntiles + 7) / 8;
+        tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+        if (tile >= ntiles) return false;
+    }
+    x = (tile % ntx) * bx + threadIdx.x;
+    y = (tile / ntx) * by + threadIdx.y;
+    return x < N && y < N;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void field_step_kernel(Fields<T> in, Fields<T> out, int N, int bx, int by,
+                                                         int remap, Schedule sc, const int* __restrict__ d_step)
+{
+    int x, y;
+    if (!tile_coords(N, bx, by, remap, x, y)) return;
+    const int n = *d_step;
+    const double td = n * sc.dt, thd = (n + 0.5) * sc.dt;
+    const T t = T(td), inv_t = n > 0 ? T(1.0 / td) : T(0), dt = T(sc.dt);
+    const T eps_drift = T(sc.dt / thd), phi_drift = T(sc.dt * thd);
+    const bool kick = n > 0, reunit = is_reunit_step(sc, n);
+    const int V = N * N;
+    const Nbr nb = neighbours(x, y, N);
+    a8<T> PHI = ldA(in.phi, nb.s, V);
+    a8<T> E1 = ldA(in.E, nb.s, V), E2 = ldA(in.E + 8 * (size_t)V, nb.s, V), PI = ldA(in.pi, nb.s, V);
+    if (kick) {
+        a8<T> F1, F2, Fpi;
+        kick_forces(in, V, nb, t, inv_t, PHI, F1, F2, Fpi);
+#pragma unroll
+        for (int a = 0; a < 8; a++) {
+            E1.v[a] += dt * F1.v[a];
+            E2.v[a] += dt * F2.v[a];
+            PI.v[a] += dt * Fpi.v[a];
+        }
+    }
+    // drift: U_i <- exp(i (dt/t_half) E_i) U_i ; phi <- phi + dt t_half pi
+    m3<T> U1 = mul(expi(E1, eps_drift), ldU(in.U, 0, nb.s, V));
+    m3<T> U2 = mul(expi(E2, eps_drift), ldU(in.U, 1, nb.s, V));
+    if (reunit) {
+        U1 = reunitarize(U1);
+        U2 = reunitarize(U2);
+    }
+#pragma unroll
+    for (int a = 0; a < 8; a++) PHI.v[a] += phi_drift * PI.v[a];
+    stU(out.U, 0, nb.s, V, U1);
+    stU(out.U, 1, nb.s, V, U2);
+    stA(out.phi, nb.s, V, PHI);
+    stA(out.E, nb.s, V, E1);
+    stA(out.E + 8 * (size_t)V, nb.s, V, E2);
+    stA(out.pi, nb.s, V, PI);
+}
+
+template <typename T>
+hipError_t launch_field_step(const Fields<T>& in, const Fields<T>& out, int N, const Schedule& sc,
+                             const int* d_step, const LaunchCfg& cfg, hipStream_t st)
+{
+    if (cfg.bx <= 0 || cfg.by <= 0 || cfg.bx * cfg.by > 256) return hipErrorInvalidValue;
+    const int ntx = (N + cfg.bx - 1) / cfg.bx, nty = (N + cfg.by - 1) / cfg.by;
+    const int ntiles = ntx * nty;
+    const int grid = cfg.xcd_remap ? 8 * ((ntiles + 7) / 8) : ntiles;
+    hipLaunchKernelGGL(field_step_kernel<T>, dim3(grid), dim3(cfg.bx, cfg.by), 0, st, in, out, N, cfg.bx, cfg.by,
+                       cfg.xcd_remap, sc, d_step);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ diagnostics
+// Per block: [sum |G|^2, max |G|, K_T, K_L, V_B, V_phi, max |U U^+ - 1|, sum |U U^+ - 1|^2]
+// with the momenta averaged to integer time n: E(n) = E(n-1/2) + (dt/2) F(n).
+constexpr int kDiagCols = 8;
+
+template <typename T>
+__global__ __launch_bounds__(256) void field_diag_kernel(Fields<T> f, int N, T t, T inv_t, T half_dt, int n,
+                                                         double* partials)
+{
+    const int V = N * N;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    double v[kDiagCols] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (s < V) {
+        const int x = s % N, y = s / N;
+        const Nbr nb = neighbours(x, y, N);
+        const a8<T> PHI = ldA(f.phi, s, V), PI = ldA(f.pi, s, V);
+        const a8<T> E1 = ldA(f.E, s, V), E2 = ldA(f.E + 8 * (size_t)V, s, V);
+        // Gauss residual, sum_i [E_i(x) - U_i(x-i)^+ E_i(x-i) U_i(x-i)] + i[phi, pi]
+        const a8<T> g1 = transport_adj(ldU(f.U, 0, nb.xm, V), ldA(f.E, nb.xm, V));
+        const a8<T> g2 = transport_adj(ldU(f.U, 1, nb.ym, V), ldA(f.E + 8 * (size_t)V, nb.ym, V));
+        const a8<T> gc = icomm(PHI, PI);
+        double G2 = 0;
+        for (int a = 0; a < 8; a++) {
+            const double g = (double)E1.v[a] - g1.v[a] + E2.v[a] - g2.v[a] + gc.v[a];
+            G2 += g * g;
+        }
+        v[0] = G2;
+        v[1] = sqrt(G2);
+        a8<T> F1, F2, Fpi;
+        T retr = 0, grad2 = 0;
+        kick_forces(f, V, nb, t, inv_t, PHI, F1, F2, Fpi, &retr, &grad2);
+        const T h = n > 0 ? half_dt : T(0);
+        double e2 = 0, p2 = 0;
+        for (int a = 0; a < 8; a++) {
+            const double ea = E1.v[a] + h * F1.v[a], eb = E2.v[a] + h * F2.v[a], pa = PI.v[a] + h * Fpi.v[a];
+            e2 += 0.5 * (ea * ea + eb * eb);
+            p2 += 0.5 * pa * pa;
+        }
+        v[2] = (double)inv_t * e2;
+        v[3] = (double)t * p2;
+        v[4] = 2.0 * (double)t * (3.0 - (double)retr);
+        v[5] = (double)inv_t * (double)grad2;
+        double umax = 0, usq = 0;
+        for (int i = 0; i < 2; i++) {
+            const m3<T> u = ldU(f.U, i, s, V);
+            const m3<T> w = mul_adj(u, u);
+            for (int c = 0; c < 9; c++) {
+                const double dr = (double)w.e[c].re - ((c % 4) == 0 ? 1.0 : 0.0), di = w.e[c].im;
+                const double d = sqrt(dr * dr + di * di);
+                umax = fmax(umax, d);
+                usq += d * d;
+            }
+        }
+        v[6] = umax;
+        v[7] = usq;
+    }
+    block_reduce_store<kDiagCols>(v, (1u << 1) | (1u << 6), partials + (size_t)blockIdx.x * kDiagCols);
+}
+
+template <typename T>
+hipError_t launch_field_diag(const Fields<T>& f, int N, double dt, int n, double* partials, int nblk_cap,
+                             int* nblk_out, hipStream_t st)
+{
+    const int V = N * N, nblk = (V + 255) / 256;
+    if (nblk > nblk_cap) return hipErrorInvalidValue;
+    *nblk_out = nblk;
+    const double t = n * dt;
+    hipLaunchKernelGGL(field_diag_kernel<T>, dim3(nblk), dim3(256), 0, st, f, N, T(t), T(n > 0 ? 1.0 / t : 0.0),
+                       T(0.5 * dt), n, partials);
+    return hipGetLastError();
+}
+
+template hipError_t launch_field_step<double>(const Fields<double>&, const Fields<double>&, int, const Schedule&,
+                                              const int*, const LaunchCfg&, hipStream_t);
+template hipError_t launch_field_step<float>(const Fields<float>&, const Fields<float>&, int, const Schedule&,
+                                             const int*, const LaunchCfg&, hipStream_t);
+template hipError_t launch_field_diag<double>(const Fields<double>&, int, double, int, double*, int, int*,
+                                              hipStream_t);
+template hipError_t launch_field_diag<float>(const Fields<float>&, int, double, int, double*, int, int*,
+                                             hipStream_t);
+
+}  // namespace cpic

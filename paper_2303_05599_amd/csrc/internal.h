@@ -1,0 +1,115 @@
+// internal.h -- declarations shared by the translation units of libcpic.
+// Device data layout (structure of arrays, site index s = y*N + x):
+//   links  U[i][c][s]  i = 0 (e1), 1 (e2); c = 2*(3*row+col) + {0: re, 1: im}
+//   fields phi[a][s], E[i][a][s], pi[a][s] (8 algebra components a)
+// One field buffer set holds U, phi, E, pi contiguously (68 reals per site).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace cpic {
+
+constexpr int kRealsPerSite = 68;
+constexpr int kPartReals = 18;  // x y eta px py peta deta ux0 uy0 pt0 Q1..Q8
+enum PartCol { PX_ = 0, PY_, PETA_, PPX, PPY, PPETA, PDETA, PUX0, PUY0, PPT0, PQ0 };
+
+template <typename T> struct Fields {
+    T* U;    // [2][18][V]
+    T* phi;  // [8][V]
+    T* E;    // [2][8][V]
+    T* pi;   // [8][V]
+};
+template <typename T> inline Fields<T> fields_at(void* base, int V)
+{
+    T* p = static_cast<T*>(base);
+    return {p, p + 36 * (size_t)V, p + 44 * (size_t)V, p + 60 * (size_t)V};
+}
+
+template <typename T> struct Parts {
+    T* r;       // [18][np] (PartCol order)
+    int* cell;  // [2][np]
+};
+
+// Step schedule.  The current step n lives in device memory (one int per
+// event) so that a captured sequence of launches can be replayed for any n:
+// every kernel derives t_n, the kick/formation/recording/reunitarisation
+// decisions and the sample slot from n.  The last kernel of a step advances n.
+struct Schedule {
+    double dt;         // dtau / a
+    int n_max;         // steps to tau_max
+    int n_form;        // first step of the particle push
+    int record_every;  // samples after steps with (n+1) % record_every == 0, and after n_max - 1
+    int reunit_every;  // FP32: reunitarise links / renormalise charges after steps with (n+1) % k == 0
+};
+__host__ __device__ inline bool is_record_step(const Schedule& s, int n)
+{
+    return n >= s.n_form && n < s.n_max && ((n + 1) % s.record_every == 0 || n + 1 == s.n_max);
+}
+__host__ __device__ inline int record_slot_of(const Schedule& s, int n)
+{
+    return n / s.record_every - s.n_form / s.record_every;
+}
+__host__ __device__ inline int num_slots(const Schedule& s)
+{
+    return s.n_max > s.n_form ? record_slot_of(s, s.n_max - 1) + 1 : 0;
+}
+__host__ __device__ inline bool is_reunit_step(const Schedule& s, int n)
+{
+    return s.reunit_every > 0 && (n + 1) % s.reunit_every == 0;
+}
+
+struct LaunchCfg {
+    int bx = 64, by = 4;  // field kernel block shape
+    int xcd_remap = 1;    // map consecutive tiles onto one XCD
+};
+
+// ---- field kernels (field.hip)
+template <typename T>
+hipError_t launch_field_step(const Fields<T>& in, const Fields<T>& out, int N, const Schedule& sc,
+                             const int* d_step, const LaunchCfg& cfg, hipStream_t st);
+template <typename T>
+hipError_t launch_field_diag(const Fields<T>& f, int N, double dt, int n, double* partials, int nblk_cap,
+                             int* nblk_out, hipStream_t st);
+
+// ---- particle kernels (push.hip)
+struct PushArgs {
+    int N, np, is_static;
+    double mhat;
+    double q0eig[3];  // sorted eigenvalues of Q0 (charge renormalisation)
+    Schedule sc;
+};
+template <typename T>
+hipError_t launch_push(const Fields<T>& A, const T* E_new, const T* pi_new, const Parts<T>& P, const PushArgs& a,
+                       const int* d_step, double* partials, int* err, hipStream_t st);
+int push_blocks(int np);
+hipError_t launch_reduce_rows(const double* partials, int nrows, int ncols, double* out, hipStream_t st);
+// end of a step: on recording steps add the block partials of the step's slot
+// into obs[slot][4]; then advance the step counter
+hipError_t launch_step_end(const Schedule& sc, int nblocks, const double* partials, double* obs, int* d_step,
+                           hipStream_t st);
+template <typename T>
+hipError_t launch_part_diag(const Parts<T>& P, int np, double q2, double q3, double* partials, hipStream_t st);
+
+// ---- initial condition (ic.hip), always double precision
+struct ICArgs {
+    int N;
+    int n_sheets;
+    uint64_t seed;
+    double g2mua, mhat, uvhat;
+    double tol;
+    int maxit;
+};
+// builds U, pi (phi = E = 0) into a double buffer set; returns failures in *fails (device int)
+hipError_t ic_glasma(const ICArgs& a, Fields<double> out, int* d_fails, hipStream_t st);
+struct PartICArgs {
+    int N, np, azimuth_uniform;
+    uint64_t seed;
+    double pt_min, pt_max;
+    double q0[8];
+};
+hipError_t ic_particles(const PartICArgs& a, double* r /*[18][np]*/, int* cell, hipStream_t st);
+hipError_t convert_to_float(const double* src, float* dst, size_t n, hipStream_t st);
+
+}  // namespace cpic

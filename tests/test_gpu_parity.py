@@ -1,0 +1,292 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle
+on the same seeded inputs.
+
+Tolerance for double precision: |lib - oracle| <= 1e-11 * max(|oracle|, RMS of
+that field) per site and component over the first 50 steps (the agreement the
+method's double-precision path is held to; both implementations are exact up
+to rounding order).  Integer data (particle cells) must agree exactly.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+cp = pytest.importorskip("paper_2303_05599_amd")
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+HBARC = oracle.HBARC_GEV_FM
+
+
+def rel_err(a, ref):
+    a, ref = np.asarray(a), np.asarray(ref)
+    rms = np.sqrt(np.mean(np.abs(ref) ** 2)) if ref.size else 0.0
+    den = np.maximum(np.abs(ref), rms)
+    den = np.where(den == 0, 1.0, den)
+    return float(np.max(np.abs(a - ref) / den)) if a.size else 0.0
+
+
+def glasma(N, L=None, steps=60, **kw):
+    L = L if L is not None else 6.0 * N / 32
+    g = dict(N=N, L_fm=L, g2mu_GeV=2.0, m_ir_GeV=0.2, uv_GeV=10.0, n_sheets=1, dtau_over_a=0.125,
+             tau_max_fm=steps * (L / N) * 0.125, seed=1, precision=cp.FP64, reunit_every=0, record_every=8)
+    g.update(kw)
+    return g
+
+
+def compare_fields(st, ref, tol=TOL):
+    errs = {k: rel_err(st[k], ref[k]) for k in ("U", "phi", "E", "pi")}
+    for k, e in errs.items():
+        assert e <= tol, (k, e, errs)
+    return errs
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    cp.lib()
+    yield
+
+
+@pytest.mark.parametrize("N,n0", [(32, 3), (96, 0), (48, 1)])
+def test_field_leapfrog_fp64_random_state(N, n0):
+    """50 fused kick+drift steps from a random state; N = 96 and 48 leave ragged tiles."""
+    print(f"case N={N} n0={n0}", flush=True)
+    steps = 50
+    st = inputs.random_state(N, 100 + N, eps_link=0.4)
+    ctx = cp.Context(glasma(N, steps=n0 + steps + 1))
+    ctx.load_state(st, n=n0)
+    ctx.step(steps)
+    got = ctx.state()
+    ref = {k: v.copy() for k, v in st.items()}
+    for n in range(n0, n0 + steps):
+        oracle.field_step(N, n, 0.125, ref)
+    compare_fields(got, ref)
+
+
+@pytest.mark.parametrize("N,ns,uv", [(32, 1, 10.0), (48, 3, 4.0), (64, 2, 0.0)])
+def test_initial_condition_parity(N, ns, uv):
+    """Full MV chain: charges, FFT Poisson (radix 2/3/4), Wilson lines, Newton links, pi(0)."""
+    print(f"case IC N={N} sheets={ns} uv={uv}", flush=True)
+    L = 6.0 * N / 32
+    ctx = cp.Context(glasma(N, L, n_sheets=ns, uv_GeV=uv, seed=7))
+    ctx.init_mv()
+    got = ctx.state()
+    ref = oracle.mv_initial_condition(N, L, 2.0, 0.2, uv, ns, 7)
+    assert rel_err(got["U"], ref["U"]) < 1e-12
+    assert rel_err(got["pi"], ref["pi"]) < 1e-12
+    assert np.max(np.abs(got["E"])) == 0 and np.max(np.abs(got["phi"])) == 0
+
+
+def particle_params(n, mass, N, L, n_form, seed=2, pt=(0.0, 0.0), rep=0):
+    a_fm = L / N
+    return dict(n=n, mass_GeV=mass, pT_min_GeV=pt[0], pT_max_GeV=pt[1], azimuth_uniform=1,
+                tau_form_fm=n_form * 0.125 * a_fm, rep=rep, seed=seed)
+
+
+def test_particles_init_parity():
+    N, L = 32, 6.0
+    a = oracle.lattice_spacing(L, N)
+    ctx = cp.Context(glasma(N, L), particle_params(5000, 1.27, N, L, 0, seed=9, pt=(0.5, 3.0)))
+    ctx.init_mv()
+    got = ctx.get_state(cp.STATE_PARTICLES)
+    ref = oracle.particles_init(N, 5000, 9, 0.5 * a, 3.0 * a, True, 0)
+    assert np.array_equal(got[:, 14:16], ref[:, 14:16])
+    assert rel_err(got, ref) < 1e-13
+
+
+@pytest.mark.parametrize("is_static", [False, True])
+def test_particle_push_fp64_random_state(is_static):
+    """Rotation on cell changes (both axes), rapidity Wilson line, E/B interpolation, Euler step."""
+    print(f"case push static={is_static}", flush=True)
+    N, L, n0, n_form, steps = 32, 6.0, 5, 3, 50
+    a = oracle.lattice_spacing(L, N)
+    mhat = math.inf if is_static else 0.3
+    st = inputs.random_state(N, 41, eps_link=0.4)
+    P = inputs.random_particles(3000, N, 42, p_scale=0.6)
+    ctx = cp.Context(glasma(N, L, steps=n0 + steps),       # the last step is a sampling step
+                     particle_params(3000, math.inf if is_static else mhat / a, N, L, n_form))
+    ctx.load_state(st, n=n0, particles=P)
+    ctx.step(steps)
+    ctx.sync()
+    got = ctx.get_state(cp.STATE_PARTICLES)
+    run = oracle.Run(N, 0.125, st, P, mhat=mhat, n_form=n_form, n0=n0)
+    for _ in range(steps):
+        run.step()
+    assert run.errors == 0
+    ref = run.P
+    flips = np.sum(np.any(got[:, 14:16] != ref[:, 14:16], axis=1))
+    assert flips == 0, f"{flips} particles on a different cell"
+    assert rel_err(got, ref) <= TOL
+    compare_fields(ctx.state(), run.st)
+    obs = ctx.observables()
+    assert obs[-1, 0] == pytest.approx(run.n * 0.125 * L / N, rel=1e-14)
+    sums = run.observe() / (3000 * a * a)
+    for c in range(4):
+        assert abs(obs[-1, 1 + c] - sums[c]) <= 1e-10 * abs(sums[c]), (c, obs[-1], sums)
+
+
+def test_static_limit_config_32():
+    """The coarse static configuration: 32^2, L = 6 fm, g^2 mu = 2 GeV, m = 0.2 GeV,
+    one sheet, dtau = a/8 to 1 fm/c (43 steps), 1024 static quarks, seeds 1 and 2."""
+    N, L = 32, 6.0
+    a = oracle.lattice_spacing(L, N)
+    g = glasma(N, L, tau_max_fm=1.0, seed=1)
+    p = dict(n=1024, mass_GeV=math.inf, pT_min_GeV=0, pT_max_GeV=0, azimuth_uniform=1, tau_form_fm=0.0,
+             rep=0, seed=2)
+    ctx = cp.Context(g, p)
+    ctx.init_mv()
+    ctx.evolve(1.0)
+    assert ctx.n == 43
+    obs = ctx.observables()
+    ref = oracle.mv_initial_condition(N, L, 2.0, 0.2, 10.0, 1, 1)
+    P = oracle.particles_init(N, 1024, 2, 0.0, 0.0, True, 0)
+    run = oracle.Run(N, 0.125, ref, P, mhat=math.inf, n_form=0)
+    ref_obs = []
+    for n in range(43):
+        run.step()
+        if (n + 1) % 8 == 0 or n + 1 == 43:
+            ref_obs.append([run.n * 0.125 * L / N] + list(run.observe() / (1024 * a * a)))
+    ref_obs = np.array(ref_obs)
+    assert obs.shape[0] == ref_obs.shape[0] == 6
+    assert np.allclose(obs[:, 0], ref_obs[:, 0], rtol=1e-14)
+    for c in (1, 2, 3, 4):
+        assert rel_err(obs[:, c], ref_obs[:, c]) <= TOL
+    assert rel_err(ctx.get_state(cp.STATE_PARTICLES), run.P) <= TOL
+
+
+def test_full_chain_charm_like_64():
+    """Full chain at the paper-scale lattice spacing (a = 6 fm / 512) on a 64^2
+    patch: 4 sheets, charm quarks (m = 1.27 GeV, p_T = 0) formed at 0.1 fm/c."""
+    N, L = 64, 0.75
+    a = oracle.lattice_spacing(L, N)
+    n_form = math.ceil(0.1 / (0.125 * L / N) - 1e-9)
+    steps = n_form + 50
+    g = glasma(N, L, n_sheets=4, steps=steps, seed=3)
+    p = dict(n=2000, mass_GeV=1.27, pT_min_GeV=0, pT_max_GeV=0, azimuth_uniform=1, tau_form_fm=0.1, rep=0, seed=4)
+    ctx = cp.Context(g, p)
+    ctx.init_mv()
+    ctx.evolve(1e9)
+    ctx.sync()
+    ref = oracle.mv_initial_condition(N, L, 2.0, 0.2, 10.0, 4, 3)
+    P = oracle.particles_init(N, 2000, 4, 0.0, 0.0, True, 0)
+    run = oracle.Run(N, 0.125, ref, P, mhat=1.27 * a, n_form=n_form)
+    for _ in range(steps):
+        run.step()
+    compare_fields(ctx.state(), run.st)
+    got = ctx.get_state(cp.STATE_PARTICLES)
+    assert np.array_equal(got[:, 14:16], run.P[:, 14:16])
+    assert rel_err(got, run.P) <= TOL
+    obs = ctx.observables()
+    last = run.observe() / (2000 * a * a)
+    for c in range(4):
+        assert abs(obs[-1, 1 + c] - last[c]) <= TOL * max(abs(last[c]), 1e-300), (c, obs[-1], last)
+
+
+def test_graph_replay_equals_eager_bitwise():
+    N, L = 32, 6.0
+    g = glasma(N, L, steps=80, record_every=4)
+    p = particle_params(500, 1.27, N, L, 5, pt=(1.0, 1.0))
+    a_ctx, b_ctx = cp.Context(g, p), cp.Context(g, p)
+    for c in (a_ctx, b_ctx):
+        c.init_mv()
+    a_ctx.step(80)
+    b_ctx.evolve(1e9)          # graphs of 16 steps
+    for k in ("U", "phi", "E", "pi"):
+        assert np.array_equal(a_ctx.state()[k], b_ctx.state()[k]), k
+    assert np.array_equal(a_ctx.get_state(cp.STATE_PARTICLES), b_ctx.get_state(cp.STATE_PARTICLES))
+    assert np.array_equal(a_ctx.observables(), b_ctx.observables())
+
+
+def test_checkpoint_resume_bitwise(tmp_path):
+    N, L = 32, 6.0
+    g = glasma(N, L, steps=40, record_every=4)
+    p = particle_params(300, 1.27, N, L, 2, pt=(1.0, 1.0))
+    full = cp.Context(g, p)
+    full.init_mv()
+    full.step(40)
+    half = cp.Context(g, p)
+    half.init_mv()
+    half.step(20)
+    half.save(tmp_path / "ck.bin")
+    resumed = cp.Context(g, p)
+    resumed.load(tmp_path / "ck.bin")
+    resumed.step(20)
+    for k in ("U", "phi", "E", "pi"):
+        assert np.array_equal(full.state()[k], resumed.state()[k]), k
+    assert np.array_equal(full.get_state(cp.STATE_PARTICLES), resumed.get_state(cp.STATE_PARTICLES))
+    assert np.array_equal(full.observables(), resumed.observables())
+    # a truncated checkpoint is rejected
+    data = (tmp_path / "ck.bin").read_bytes()
+    (tmp_path / "bad.bin").write_bytes(data[: len(data) // 2])
+    with pytest.raises(cp.CpicError) as e:
+        resumed.load(tmp_path / "bad.bin")
+    assert e.value.status == -9
+
+
+def test_diagnostics_match_oracle():
+    N, L, n0 = 32, 6.0, 4
+    st = inputs.random_state(N, 77, eps_link=0.3)
+    ctx = cp.Context(glasma(N, L, steps=20))
+    ctx.load_state(st, n=n0)
+    d = ctx.diagnostics()
+    G = oracle.gauss(N, st["U"], st["phi"], st["E"], st["pi"])
+    assert d[0] == pytest.approx(np.sum(G ** 2), rel=1e-12)
+    assert d[1] == pytest.approx(np.max(np.sqrt(np.sum(G ** 2, axis=-1))), rel=1e-12)
+    t = n0 * 0.125
+    FE, Fp = oracle.forces(N, t, st["U"], st["phi"])
+    Eav = np.ascontiguousarray(st["E"] + 0.0625 * FE)
+    piav = np.ascontiguousarray(st["pi"] + 0.0625 * Fp)
+    H = oracle.energy(N, t, st["U"], st["phi"], Eav, piav)
+    assert np.allclose(d[2:6], H, rtol=1e-12, atol=1e-12)
+    mu, _ = oracle.unitarity(N, st["U"])
+    assert d[6] == pytest.approx(mu, rel=1e-3, abs=1e-15)
+
+
+def test_mv_event_invariants_fp64():
+    """Gauss law, unitarity and Casimirs on an MV event after 200 steps."""
+    N, L = 64, 0.75
+    g = glasma(N, L, n_sheets=4, steps=200, seed=5)
+    p = dict(n=4000, mass_GeV=0.2, pT_min_GeV=2.0, pT_max_GeV=2.0, azimuth_uniform=1, tau_form_fm=0.0, rep=0, seed=6)
+    ctx = cp.Context(g, p)
+    ctx.init_mv()
+    ctx.evolve(1e9)
+    d = ctx.diagnostics()
+    assert d[1] < 1e-12          # Gauss
+    assert d[6] < 1e-13          # unitarity
+    assert d[8] < 1e-11 and d[9] < 1e-11   # Casimirs
+
+
+def test_fp32_against_fp64_oracle():
+    """Float storage and update with reunitarisation and charge renormalisation every
+    16 steps: error against the double-precision oracle after 64 steps."""
+    N, L = 32, 6.0
+    a = oracle.lattice_spacing(L, N)
+    steps = 64
+    g = glasma(N, L, steps=steps, precision=cp.FP32, reunit_every=16, seed=1)
+    p = dict(n=4096, mass_GeV=math.inf, pT_min_GeV=0, pT_max_GeV=0, azimuth_uniform=1, tau_form_fm=0.0, rep=0, seed=2)
+    ctx = cp.Context(g, p)
+    ctx.init_mv()
+    ctx.evolve(1e9)
+    obs = ctx.observables()
+    d = ctx.diagnostics()
+    ref = oracle.mv_initial_condition(N, L, 2.0, 0.2, 10.0, 1, 1)
+    P = oracle.particles_init(N, 4096, 2, 0.0, 0.0, True, 0)
+    run = oracle.Run(N, 0.125, ref, P, mhat=math.inf, n_form=0)
+    for _ in range(steps):
+        run.step()
+    errs = {k: rel_err(ctx.state()[k], run.st[k]) for k in ("U", "phi", "E", "pi")}
+    last = run.observe() / (4096 * a * a)
+    e_pt = abs(obs[-1, 1] - last[0]) / abs(last[0])
+    e_pl = abs(obs[-1, 2] - last[1]) / abs(last[1])
+    print(f"FP32 field errors {errs}, <dp_T^2> rel {e_pt:.2e}, <dp_L^2> rel {e_pl:.2e}, unitarity {d[6]:.1e}")
+    assert max(errs.values()) < 2e-3
+    assert e_pt < 1e-4 and e_pl < 1e-4
+    assert d[6] < 1e-5

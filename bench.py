@@ -101,7 +101,20 @@ def main():
     ap.add_argument("--warmup", type=int, default=96)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP32 run")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
+                    help="precision of the headline run (profiling)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy (reference for the HBM counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(4):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 256 << 20, "copy_bytes_written": 256 << 20, "launches": 4}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (events shard across GPUs "
               f"without communication, see the design notes)", file=sys.stderr)
@@ -112,7 +125,7 @@ def main():
     import paper_2303_05599_amd as cp
     torch.cuda.set_device(0)
     V = 512 * 512
-    res = run_event(cp.FP64, args.steps, args.warmup)
+    res = run_event(cp.FP64 if args.precision == "fp64" else cp.FP32, args.steps, args.warmup)
     tm = res["timing"]
     ms_per_step = res["wall"] * 1e3 / args.steps
     site_rate = V * args.steps / res["wall"]

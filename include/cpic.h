@@ -201,9 +201,11 @@ cpic_status cpic_set_state(cpic_ctx* ctx, int32_t which, const void* host_src, s
 cpic_status cpic_save(cpic_ctx* ctx, const char* path);
 cpic_status cpic_load(cpic_ctx* ctx, const char* path);
 
-/* Field-kernel block shape (bx * by <= 256) and whether consecutive tiles are
- * mapped onto one XCD.  Used by the tuner; takes effect for the next launch. */
-cpic_status cpic_set_launch(cpic_ctx* ctx, int32_t bx, int32_t by, int32_t xcd_remap);
+/* Field-kernel launch: block shape (bx * by a multiple of 64, <= 256), whether
+ * consecutive tiles are mapped onto one XCD, and the occupancy the register
+ * allocator targets (waves per SIMD, 1..4; 1 = compiler default).  Used by the
+ * tuner; takes effect for the next launch. */
+cpic_status cpic_set_launch(cpic_ctx* ctx, int32_t bx, int32_t by, int32_t xcd_remap, int32_t waves);
 
 /* Kernel timing: when enabled, every field-update and particle-push launch
  * is bracketed by HIP events on the context's stream.  cpic_timing returns

@@ -68,7 +68,7 @@ def lib():
             "cpic_current_step": [P, ctypes.POINTER(i64)], "cpic_num_samples": [P, ctypes.POINTER(i32)],
             "cpic_observables": [P, P, P, P, i32], "cpic_observables_full": [P, P, i32],
             "cpic_diagnostics": [P, P], "cpic_get_state": [P, i32, P, sz], "cpic_set_state": [P, i32, P, sz],
-            "cpic_save": [P, cp], "cpic_load": [P, cp], "cpic_set_launch": [P, i32, i32, i32],
+            "cpic_save": [P, cp], "cpic_load": [P, cp], "cpic_set_launch": [P, i32, i32, i32, i32],
             "cpic_set_timing": [P, i32],
             "cpic_timing": [P, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(i64), ctypes.POINTER(i64)],
             "cpic_batch_create": [i32, ctypes.POINTER(GlasmaParams), ctypes.POINTER(ParticleParams), P, pp],
@@ -216,8 +216,8 @@ class Context:
     def load(self, path):
         self._chk(lib().cpic_load(self.h, str(path).encode()))
 
-    def set_launch(self, bx, by, xcd_remap=1):
-        self._chk(lib().cpic_set_launch(self.h, bx, by, xcd_remap))
+    def set_launch(self, bx, by, xcd_remap=1, waves=1):
+        self._chk(lib().cpic_set_launch(self.h, bx, by, xcd_remap, waves))
 
     def set_timing(self, enable=True):
         self._chk(lib().cpic_set_timing(self.h, int(enable)))

@@ -81,6 +81,10 @@ struct cpic_ctx {
     double* partials = nullptr;  // [nslots][pblocks][4]
     double* obs = nullptr;       // [nslots][4]
     std::vector<std::pair<int, int>> samples;  // (slot, step n after which it was taken)
+    int* pid = nullptr;    // original index of each particle record
+    SortBufs sb{};
+    bool static_sorted = false;
+    int sorted_at = -1;   // step before which the records were last reordered
     int* d_step = nullptr;
     int* d_err = nullptr;
     int* d_fails = nullptr;
@@ -134,6 +138,8 @@ static void free_all(cpic_ctx* c)
     hipFree(c->fbuf[0]); hipFree(c->fbuf[1]); hipFree(c->pr); hipFree(c->pcell);
     hipFree(c->partials); hipFree(c->obs); hipFree(c->d_step); hipFree(c->d_err); hipFree(c->d_fails);
     hipFree(c->dpart); hipFree(c->dout);
+    hipFree(c->pid); hipFree(c->sb.keys); hipFree(c->sb.keys2); hipFree(c->sb.vals); hipFree(c->sb.perm);
+    hipFree(c->sb.temp); hipFree(c->sb.r2); hipFree(c->sb.cell2); hipFree(c->sb.pid2);
     if (c->own_stream && c->st) hipStreamDestroy(c->st);
 }
 
@@ -197,8 +203,19 @@ extern "C" cpic_status cpic_create(const cpic_glasma_params* gp, const cpic_part
     const size_t fbytes = (size_t)kRealsPerSite * c->V * c->tsz;
     for (int b = 0; b < 2 && e == hipSuccess; b++) e = hipMalloc(&c->fbuf[b], fbytes);
     if (e == hipSuccess && c->np > 0) {
-        e = hipMalloc(&c->pr, (size_t)kPartReals * c->np * c->tsz);
-        if (e == hipSuccess) e = hipMalloc(&c->pcell, sizeof(int) * 2 * c->np);
+        const size_t np = c->np;
+        e = hipMalloc(&c->pr, (size_t)kPartReals * np * c->tsz);
+        if (e == hipSuccess) e = hipMalloc(&c->pcell, sizeof(int) * 2 * np);
+        if (e == hipSuccess) e = hipMalloc(&c->pid, sizeof(int) * np);
+        if (e == hipSuccess) e = hipMalloc(&c->sb.keys, sizeof(unsigned) * np);
+        if (e == hipSuccess) e = hipMalloc(&c->sb.keys2, sizeof(unsigned) * np);
+        if (e == hipSuccess) e = hipMalloc(&c->sb.vals, sizeof(int) * np);
+        if (e == hipSuccess) e = hipMalloc(&c->sb.perm, sizeof(int) * np);
+        if (e == hipSuccess) e = hipMalloc(&c->sb.r2, (size_t)kPartReals * np * c->tsz);
+        if (e == hipSuccess) e = hipMalloc(&c->sb.cell2, sizeof(int) * 2 * np);
+        if (e == hipSuccess) e = hipMalloc(&c->sb.pid2, sizeof(int) * np);
+        c->sb.temp_bytes = std::max<size_t>(sort_temp_bytes((int)np, c->N), 16);
+        if (e == hipSuccess) e = hipMalloc(&c->sb.temp, c->sb.temp_bytes);
     }
     c->pblocks = c->np > 0 ? push_blocks((int)c->np) : 0;
     c->nslots = c->np > 0 ? num_slots(c->sc) : 0;
@@ -235,6 +252,46 @@ extern "C" void cpic_destroy(cpic_ctx* c)
 }
 
 extern "C" const char* cpic_last_error(const cpic_ctx* c) { return c ? c->err.c_str() : g_static_error.c_str(); }
+
+static cpic_status reset_pid(cpic_ctx* c)
+{
+    if (c->np <= 0) return CPIC_OK;
+    std::vector<int> iota(c->np);
+    for (int64_t p = 0; p < c->np; p++) iota[p] = (int)p;
+    HIPCHK(c, hipMemcpy(c->pid, iota.data(), sizeof(int) * iota.size(), hipMemcpyHostToDevice), "pid");
+    c->static_sorted = false;
+    c->sorted_at = -1;
+    return CPIC_OK;
+}
+
+// Particle records are reordered by cell before step n when n is the first
+// push step or a multiple of kSortEvery (moving particles); static particles
+// never change cell and are ordered once.
+static bool is_sort_point(const cpic_ctx* c, int n)
+{
+    if (c->np <= 1 || n < c->sc.n_form || n >= c->sc.n_max) return false;
+    if (c->is_static) return !c->static_sorted;
+    return n == c->sc.n_form || n % kSortEvery == 0;
+}
+static int next_sort_point(const cpic_ctx* c, int n)
+{
+    if (c->np <= 1 || c->is_static) return 1 << 30;
+    int m = n + 1;
+    if (m <= c->sc.n_form) return c->sc.n_form;
+    m = ((m + kSortEvery - 1) / kSortEvery) * kSortEvery;
+    return m;
+}
+static cpic_status maybe_sort(cpic_ctx* c)
+{
+    if (!is_sort_point(c, c->n) || c->sorted_at == c->n) return CPIC_OK;
+    c->sorted_at = c->n;
+    hipError_t e = c->prec == CPIC_FP64
+                       ? sort_particles<double>(c->sb, (double*)c->pr, c->pcell, c->pid, (int)c->np, c->N, c->st)
+                       : sort_particles<float>(c->sb, (float*)c->pr, c->pcell, c->pid, (int)c->np, c->N, c->st);
+    if (e != hipSuccess) return hip_fail(c, e, "particle sort");
+    if (c->is_static) c->static_sorted = true;
+    return CPIC_OK;
+}
 
 static void drop_graphs(cpic_ctx* c)
 {
@@ -307,6 +364,8 @@ extern "C" cpic_status cpic_init_mv(cpic_ctx* c)
     c->initialised = true;
     cpic_status s = reset_counters(c, 0);
     if (s) return s;
+    s = reset_pid(c);
+    if (s) return s;
     if (fails) return fail(c, CPIC_E_IC_NEWTON, "cpic_init_mv: initial-link Newton solve failed on " +
                                                     std::to_string(fails) + " links");
     return CPIC_OK;
@@ -338,7 +397,7 @@ template <typename T> static cpic_status launch_one(cpic_ctx* c, int parity, boo
             HIPCHK(c, hipEventCreate(&e2), "event"); HIPCHK(c, hipEventCreate(&e3), "event");
             HIPCHK(c, hipEventRecord(e2, c->st), "event");
         }
-        HIPCHK(c, launch_push<T>(A, B.E, B.pi, P<T>(c), pa, c->d_step, c->partials, c->d_err, c->st), "push");
+        HIPCHK(c, launch_push<T>(A, B, P<T>(c), pa, c->d_step, c->partials, c->d_err, c->st), "push");
         if (with_events) {
             HIPCHK(c, hipEventRecord(e3, c->st), "event");
             c->ev_push.push_back(e2); c->ev_push.push_back(e3);
@@ -361,6 +420,8 @@ static cpic_status host_advance(cpic_ctx* c, int k)
 static cpic_status eager_steps(cpic_ctx* c, int k)
 {
     for (int j = 0; j < k; j++) {
+        cpic_status so = maybe_sort(c);
+        if (so) return so;
         const bool ev = c->timing;
         cpic_status s = c->prec == CPIC_FP64 ? launch_one<double>(c, c->cur, ev) : launch_one<float>(c, c->cur, ev);
         if (s) return s;
@@ -407,7 +468,17 @@ extern "C" cpic_status cpic_evolve(cpic_ctx* c, double tau_target_fm)
     if (target <= c->n) return CPIC_OK;
     int left = target - c->n;
     if (c->timing) return eager_steps(c, left);
-    while (left >= kGraphSteps) {
+    while (left > 0) {
+        cpic_status so = maybe_sort(c);
+        if (so) return so;
+        if (left < kGraphSteps || next_sort_point(c, c->n) < c->n + kGraphSteps) {
+            // a reorder falls inside the window: advance eagerly up to it
+            const int upto = std::min(left, std::max(1, next_sort_point(c, c->n) - c->n));
+            so = eager_steps(c, std::min(upto, left < kGraphSteps ? left : upto));
+            if (so) return so;
+            left = target - c->n;
+            continue;
+        }
         const int parity = c->cur;
         if (!c->gexec[parity]) {
             cpic_status s = build_graph(c, parity);
@@ -417,7 +488,7 @@ extern "C" cpic_status cpic_evolve(cpic_ctx* c, double tau_target_fm)
         host_advance(c, kGraphSteps);
         left -= kGraphSteps;
     }
-    return eager_steps(c, left);
+    return CPIC_OK;
 }
 
 static cpic_status collect_timing(cpic_ctx* c)
@@ -592,14 +663,18 @@ template <typename T> static cpic_status get_t(cpic_ctx* c, int which, double* h
     if (which == CPIC_STATE_PARTICLES) {
         const size_t np = c->np;
         std::vector<T> r(kPartReals * np);
-        std::vector<int> cell(2 * np);
+        std::vector<int> cell(2 * np), pid(np);
         HIPCHK(c, hipMemcpy(r.data(), c->pr, sizeof(T) * r.size(), hipMemcpyDeviceToHost), "get particles");
         HIPCHK(c, hipMemcpy(cell.data(), c->pcell, sizeof(int) * cell.size(), hipMemcpyDeviceToHost), "get particles");
-        for (size_t p = 0; p < np; p++)
+        HIPCHK(c, hipMemcpy(pid.data(), c->pid, sizeof(int) * np, hipMemcpyDeviceToHost), "get particles");
+        for (size_t p = 0; p < np; p++) {
+            const size_t row = (size_t)pid[p];
+            if (row >= np) return fail(c, CPIC_E_INVALID, "get_state: corrupt particle index");
             for (int k = 0; k < 20; k++) {
                 const int d = kXchgToDev[k];
-                h[p * 20 + k] = d >= 0 ? (double)r[(size_t)d * np + p] : (double)cell[(size_t)(-d - 1) * np + p];
+                h[row * 20 + k] = d >= 0 ? (double)r[(size_t)d * np + p] : (double)cell[(size_t)(-d - 1) * np + p];
             }
+        }
         return CPIC_OK;
     }
     const size_t cnt = which == CPIC_STATE_U ? 36 : (which == CPIC_STATE_E ? 16 : 8);
@@ -623,7 +698,7 @@ template <typename T> static cpic_status set_t(cpic_ctx* c, int which, const dou
             }
         HIPCHK(c, hipMemcpy(c->pr, r.data(), sizeof(T) * r.size(), hipMemcpyHostToDevice), "set particles");
         HIPCHK(c, hipMemcpy(c->pcell, cell.data(), sizeof(int) * cell.size(), hipMemcpyHostToDevice), "set particles");
-        return CPIC_OK;
+        return reset_pid(c);
     }
     const size_t cnt = which == CPIC_STATE_U ? 36 : (which == CPIC_STATE_E ? 16 : 8);
     std::vector<T> d(cnt * c->V);
@@ -700,12 +775,13 @@ extern "C" cpic_status cpic_save(cpic_ctx* c, const char* path)
     h.np = c->np; h.nslots = c->nslots; h.gp = c->gp; h.pp = c->pp;
     const size_t fb = (size_t)kRealsPerSite * c->V * c->tsz, pb = (size_t)kPartReals * c->np * c->tsz;
     std::vector<char> f(fb), p(pb);
-    std::vector<int> cell(2 * c->np);
+    std::vector<int> cell(2 * c->np), pid(c->np);
     std::vector<double> obs(4 * (size_t)c->nslots);
     HIPCHK(c, hipMemcpy(f.data(), c->fbuf[c->cur], fb, hipMemcpyDeviceToHost), "save");
     if (pb) {
         HIPCHK(c, hipMemcpy(p.data(), c->pr, pb, hipMemcpyDeviceToHost), "save");
         HIPCHK(c, hipMemcpy(cell.data(), c->pcell, sizeof(int) * cell.size(), hipMemcpyDeviceToHost), "save");
+        HIPCHK(c, hipMemcpy(pid.data(), c->pid, sizeof(int) * pid.size(), hipMemcpyDeviceToHost), "save");
     }
     if (!obs.empty()) HIPCHK(c, hipMemcpy(obs.data(), c->obs, sizeof(double) * obs.size(), hipMemcpyDeviceToHost), "save");
     FILE* fp = std::fopen(path, "wb");
@@ -719,6 +795,9 @@ extern "C" cpic_status cpic_save(cpic_ctx* c, const char* path)
     if (pb) {
         ok = ok && std::fwrite(p.data(), 1, pb, fp) == pb;
         ok = ok && std::fwrite(cell.data(), sizeof(int), cell.size(), fp) == cell.size();
+        ok = ok && std::fwrite(pid.data(), sizeof(int), pid.size(), fp) == pid.size();
+        const int32_t ss = c->static_sorted;
+        ok = ok && std::fwrite(&ss, sizeof ss, 1, fp) == 1;
     }
     if (!obs.empty()) ok = ok && std::fwrite(obs.data(), sizeof(double), obs.size(), fp) == obs.size();
     ok = (std::fclose(fp) == 0) && ok;
@@ -746,24 +825,37 @@ extern "C" cpic_status cpic_load(cpic_ctx* c, const char* path)
     }
     const size_t fb = (size_t)kRealsPerSite * c->V * c->tsz, pb = (size_t)kPartReals * c->np * c->tsz;
     std::vector<char> f(fb), p(pb);
-    std::vector<int> cell(2 * c->np);
+    std::vector<int> cell(2 * c->np), pid(c->np);
     std::vector<double> obs(4 * (size_t)c->nslots);
+    int32_t ss = 0;
     ok = ok && std::fread(f.data(), 1, fb, fp) == fb;
     if (pb) {
         ok = ok && std::fread(p.data(), 1, pb, fp) == pb;
         ok = ok && std::fread(cell.data(), sizeof(int), cell.size(), fp) == cell.size();
+        ok = ok && std::fread(pid.data(), sizeof(int), pid.size(), fp) == pid.size();
+        ok = ok && std::fread(&ss, sizeof ss, 1, fp) == 1;
     }
     if (!obs.empty()) ok = ok && std::fread(obs.data(), sizeof(double), obs.size(), fp) == obs.size();
     std::fclose(fp);
     if (!ok) return fail(c, CPIC_E_IO, std::string("cpic_load: truncated or corrupt checkpoint ") + path);
     for (int v : cell)
         if (v < 0 || v >= c->N) return fail(c, CPIC_E_IO, "cpic_load: corrupt particle cells");
+    {
+        std::vector<char> seen(c->np, 0);
+        for (int v : pid) {
+            if (v < 0 || v >= c->np || seen[v]) return fail(c, CPIC_E_IO, "cpic_load: corrupt particle indices");
+            seen[v] = 1;
+        }
+    }
     HIPCHK(c, hipStreamSynchronize(c->st), "load");
     c->cur = 0;
     HIPCHK(c, hipMemcpy(c->fbuf[0], f.data(), fb, hipMemcpyHostToDevice), "load");
     if (pb) {
         HIPCHK(c, hipMemcpy(c->pr, p.data(), pb, hipMemcpyHostToDevice), "load");
         HIPCHK(c, hipMemcpy(c->pcell, cell.data(), sizeof(int) * cell.size(), hipMemcpyHostToDevice), "load");
+        HIPCHK(c, hipMemcpy(c->pid, pid.data(), sizeof(int) * pid.size(), hipMemcpyHostToDevice), "load");
+        c->static_sorted = ss != 0;
+        c->sorted_at = -1;
     }
     c->n = h.n;
     HIPCHK(c, hipMemcpy(c->d_step, &c->n, sizeof(int), hipMemcpyHostToDevice), "load");
@@ -774,14 +866,16 @@ extern "C" cpic_status cpic_load(cpic_ctx* c, const char* path)
 }
 
 // ------------------------------------------------------------------ tuning and timing
-extern "C" cpic_status cpic_set_launch(cpic_ctx* c, int32_t bx, int32_t by, int32_t remap)
+extern "C" cpic_status cpic_set_launch(cpic_ctx* c, int32_t bx, int32_t by, int32_t remap, int32_t waves)
 {
     if (!c) return fail(nullptr, CPIC_E_INVALID, "cpic_set_launch: NULL context");
     if (bx <= 0 || by <= 0 || bx * by > 256 || (bx * by) % 64 != 0)
         return fail(c, CPIC_E_INVALID, "cpic_set_launch: need bx*by a multiple of 64 and <= 256");
+    if (waves < 1 || waves > 4) return fail(c, CPIC_E_INVALID, "cpic_set_launch: waves must be 1..4");
     c->cfg.bx = bx;
     c->cfg.by = by;
     c->cfg.xcd_remap = remap ? 1 : 0;
+    c->cfg.waves = waves;
     drop_graphs(c);
     return CPIC_OK;
 }

@@ -11,47 +11,27 @@
 #include "internal.h"
 #include "reduce.h"
 #include "su3.h"
+#include "bufio.h"
 
 namespace cpic {
 
-template <typename T> __device__ __forceinline__ m3<T> ldU(const T* __restrict__ U, int i, int s, int V)
-{
-    const T* p = U + (size_t)i * 18 * V + s;
-    m3<T> m;
-#pragma unroll
-    for (int c = 0; c < 9; c++) m.e[c] = {p[(size_t)(2 * c) * V], p[(size_t)(2 * c + 1) * V]};
-    return m;
-}
-template <typename T> __device__ __forceinline__ void stU(T* __restrict__ U, int i, int s, int V, const m3<T>& m)
-{
-    T* p = U + (size_t)i * 18 * V + s;
-#pragma unroll
-    for (int c = 0; c < 9; c++) {
-        p[(size_t)(2 * c) * V] = m.e[c].re;
-        p[(size_t)(2 * c + 1) * V] = m.e[c].im;
-    }
-}
-template <typename T> __device__ __forceinline__ a8<T> ldA(const T* __restrict__ p, int s, int V)
-{
-    a8<T> r;
-#pragma unroll
-    for (int a = 0; a < 8; a++) r.v[a] = p[(size_t)a * V + s];
-    return r;
-}
-template <typename T> __device__ __forceinline__ void stA(T* __restrict__ p, int s, int V, const a8<T>& r)
-{
-#pragma unroll
-    for (int a = 0; a < 8; a++) p[(size_t)a * V + s] = r.v[a];
-}
+// scheduling barrier between the phases of the stencil: keeps the machine
+// scheduler from hoisting every link load of the site to the top (which
+// would hold ~10 matrices in registers at once)
+#define CPIC_PHASE() __builtin_amdgcn_sched_barrier(0)
 
+// byte offsets (site * sizeof(T)) of a site and the neighbours its stencil reads
 struct Nbr {
-    int s, xp, xm, yp, ym, xpym, xmyp;
+    uint32_t s, xp, xm, yp, ym, xpym, xmyp;
 };
-__device__ __forceinline__ Nbr neighbours(int x, int y, int N)
+template <typename T> __device__ __forceinline__ Nbr neighbours(int x, int y, int N)
 {
     const int xp = x + 1 == N ? 0 : x + 1, xm = x == 0 ? N - 1 : x - 1;
     const int yp = y + 1 == N ? 0 : y + 1, ym = y == 0 ? N - 1 : y - 1;
-    return {y * N + x, y * N + xp, y * N + xm, yp * N + x, ym * N + x, ym * N + xp, yp * N + xm};
+    constexpr uint32_t b = sizeof(T);
+    return {(uint32_t)(y * N + x) * b,  (uint32_t)(y * N + xp) * b,  (uint32_t)(y * N + xm) * b,
+            (uint32_t)(yp * N + x) * b, (uint32_t)(ym * N + x) * b,  (uint32_t)(ym * N + xp) * b,
+            (uint32_t)(yp * N + xm) * b};
 }
 
 // Kick forces at time t from U(t), phi(t) (lattice equations of motion, Sec. II.A):
@@ -59,51 +39,69 @@ __device__ __forceinline__ Nbr neighbours(int x, int y, int N)
 //   F_pi = (1/t) sum_i (phi->_i + phi<-_i - 2 phi)
 // Also returns the plaquette trace Re Tr U_12 and the scalar-gradient
 // term sum_i |phi->_i - phi|^2 / 2 for the energy.
+// The stencil is organised by link: each of the four links touching x is
+// loaded in one phase, every product it enters is formed there, and it is
+// dropped, so at most two partial plaquettes stay in registers.
 template <typename T>
-__device__ __forceinline__ void kick_forces(const Fields<T>& f, int V, const Nbr& nb, T t, T inv_t, const a8<T>& PHI,
+__device__ __forceinline__ void kick_forces(const View<T>& f, const Nbr& nb, T t, T inv_t, const a8<T>& PHI,
                                             a8<T>& F1, a8<T>& F2, a8<T>& Fpi, T* re_tr_p12 = nullptr,
                                             T* grad2 = nullptr)
 {
-    const m3<T> U1 = ldU(f.U, 0, nb.s, V), U2 = ldU(f.U, 1, nb.s, V);
-    const m3<T> U1xm = ldU(f.U, 0, nb.xm, V), U2ym = ldU(f.U, 1, nb.ym, V);
-    {   // U_12(x) = U_1(x) U_2(x+1) [U_2(x) U_1(x+2)]^+
-        const m3<T> A = mul(U1, ldU(f.U, 1, nb.xp, V));
-        const m3<T> B = mul(U2, ldU(f.U, 0, nb.yp, V));
-        const m3<T> P = mul_adj(A, B);
+    m3<T> A12, A1m2, A2m1;
+    a8<T> lap, c1, c2;
+    T g2 = 0;
+    {   // U_1(x): U_12 = [U_1 U_2(x+1)] ..., U_{1,-2} = [U_1 U_2(x+1-2)^+] ..., phi->_1
+        const m3<T> U1 = vU(f, nb.s, 0);
+        A12 = mul(U1, vU(f, nb.xp, 1));
+        A1m2 = mul_adj(U1, vU(f, nb.xpym, 1));
+        const a8<T> f1 = transport(U1, vA(f, nb.xp, kCompPhi));
+        c1 = icomm(f1, PHI);
+#pragma unroll
+        for (int a = 0; a < 8; a++) {
+            lap.v[a] = f1.v[a] - T(4) * PHI.v[a];
+            const T d = f1.v[a] - PHI.v[a];
+            g2 += T(0.5) * d * d;
+        }
+    }
+    CPIC_PHASE();
+    {   // U_2(x): U_12 = A12 [U_2 U_1(x+2)]^+, U_{2,-1} = [U_2 U_1(x-1+2)^+] ..., phi->_2
+        const m3<T> U2 = vU(f, nb.s, 1);
+        const m3<T> P = mul_adj(A12, mul(U2, vU(f, nb.yp, 0)));
         F1 = proj(P);
 #pragma unroll
         for (int a = 0; a < 8; a++) F2.v[a] = -F1.v[a];   // Proj U_21 = -Proj U_12
         if (re_tr_p12) *re_tr_p12 = P.e[0].re + P.e[4].re + P.e[8].re;
-    }
-    {   // U_{1,-2}(x) = U_1(x) U_2(x+1-2)^+ [U_2(x-2)^+ U_1(x-2)]^+
-        const m3<T> A = mul_adj(U1, ldU(f.U, 1, nb.xpym, V));
-        const m3<T> C = adj_mul(U2ym, ldU(f.U, 0, nb.ym, V));
-        const a8<T> p = proj(mul_adj(A, C));
+        A2m1 = mul_adj(U2, vU(f, nb.xmyp, 0));
+        const a8<T> f2 = transport(U2, vA(f, nb.yp, kCompPhi));
+        c2 = icomm(f2, PHI);
 #pragma unroll
-        for (int a = 0; a < 8; a++) F1.v[a] += p.v[a];
+        for (int a = 0; a < 8; a++) {
+            lap.v[a] += f2.v[a];
+            const T d = f2.v[a] - PHI.v[a];
+            g2 += T(0.5) * d * d;
+        }
     }
-    {   // U_{2,-1}(x) = U_2(x) U_1(x-1+2)^+ [U_1(x-1)^+ U_2(x-1)]^+
-        const m3<T> A = mul_adj(U2, ldU(f.U, 0, nb.xmyp, V));
-        const m3<T> C = adj_mul(U1xm, ldU(f.U, 1, nb.xm, V));
-        const a8<T> p = proj(mul_adj(A, C));
+    CPIC_PHASE();
+    {   // U_2(x-2): U_{1,-2} = A1m2 [U_2(x-2)^+ U_1(x-2)]^+, phi<-_2
+        const m3<T> U2ym = vU(f, nb.ym, 1);
+        const a8<T> p = proj(mul_adj(A1m2, adj_mul(U2ym, vU(f, nb.ym, 0))));
+        const a8<T> b2 = transport_adj(U2ym, vA(f, nb.ym, kCompPhi));
 #pragma unroll
-        for (int a = 0; a < 8; a++) F2.v[a] += p.v[a];
+        for (int a = 0; a < 8; a++) { F1.v[a] += p.v[a]; lap.v[a] += b2.v[a]; }
     }
+    CPIC_PHASE();
+    {   // U_1(x-1): U_{2,-1} = A2m1 [U_1(x-1)^+ U_2(x-1)]^+, phi<-_1
+        const m3<T> U1xm = vU(f, nb.xm, 0);
+        const a8<T> p = proj(mul_adj(A2m1, adj_mul(U1xm, vU(f, nb.xm, 1))));
+        const a8<T> b1 = transport_adj(U1xm, vA(f, nb.xm, kCompPhi));
 #pragma unroll
-    for (int a = 0; a < 8; a++) { F1.v[a] *= -t; F2.v[a] *= -t; }
-    const a8<T> f1 = transport(U1, ldA(f.phi, nb.xp, V));
-    const a8<T> f2 = transport(U2, ldA(f.phi, nb.yp, V));
-    const a8<T> b1 = transport_adj(U1xm, ldA(f.phi, nb.xm, V));
-    const a8<T> b2 = transport_adj(U2ym, ldA(f.phi, nb.ym, V));
-    const a8<T> c1 = icomm(f1, PHI), c2 = icomm(f2, PHI);
-    T g2 = 0;
+        for (int a = 0; a < 8; a++) { F2.v[a] += p.v[a]; lap.v[a] += b1.v[a]; }
+    }
 #pragma unroll
     for (int a = 0; a < 8; a++) {
-        F1.v[a] += inv_t * c1.v[a];
-        F2.v[a] += inv_t * c2.v[a];
-        Fpi.v[a] = inv_t * (f1.v[a] + f2.v[a] + b1.v[a] + b2.v[a] - T(4) * PHI.v[a]);
-        const T d1 = f1.v[a] - PHI.v[a], d2 = f2.v[a] - PHI.v[a];
-        g2 += T(0.5) * (d1 * d1 + d2 * d2);
+        F1.v[a] = -t * F1.v[a] + inv_t * c1.v[a];
+        F2.v[a] = -t * F2.v[a] + inv_t * c2.v[a];
+        Fpi.v[a] = inv_t * lap.v[a];
     }
     if (grad2) *grad2 = g2;
 }
@@ -123,8 +121,8 @@ __device__ __forceinline__ bool tile_coords(int N, int bx, int by, int remap, in
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void field_step_kernel(Fields<T> in, Fields<T> out, int N, int bx, int by,
-                                                         int remap, Schedule sc, const int* __restrict__ d_step)
+__device__ __forceinline__ void field_step_body(const Fields<T>& in, const Fields<T>& out, int N, int bx, int by,
+                                                int remap, const Schedule& sc, const int* __restrict__ d_step)
 {
     int x, y;
     if (!tile_coords(N, bx, by, remap, x, y)) return;
@@ -133,47 +131,73 @@ __global__ __launch_bounds__(256) void field_step_kernel(Fields<T> in, Fields<T>
     const T t = T(td), inv_t = n > 0 ? T(1.0 / td) : T(0), dt = T(sc.dt);
     const T eps_drift = T(sc.dt / thd), phi_drift = T(sc.dt * thd);
     const bool kick = n > 0, reunit = is_reunit_step(sc, n);
-    const int V = N * N;
-    const Nbr nb = neighbours(x, y, N);
-    a8<T> PHI = ldA(in.phi, nb.s, V);
-    a8<T> E1 = ldA(in.E, nb.s, V), E2 = ldA(in.E + 8 * (size_t)V, nb.s, V), PI = ldA(in.pi, nb.s, V);
-    if (kick) {
-        a8<T> F1, F2, Fpi;
-        kick_forces(in, V, nb, t, inv_t, PHI, F1, F2, Fpi);
+    const uint32_t V = (uint32_t)N * N;
+    const View<T> vi = make_view<T>(in.U, kRealsPerSite, V), vo = make_view<T>(out.U, kRealsPerSite, V);
+    const Nbr nb = neighbours<T>(x, y, N);
+    a8<T> PHI = vA(vi, nb.s, kCompPhi);
+    a8<T> F1 = azero<T>(), F2 = azero<T>(), Fpi = azero<T>();
+    if (kick) kick_forces(vi, nb, t, inv_t, PHI, F1, F2, Fpi);
+    CPIC_PHASE();
+    a8<T> E1 = vA(vi, nb.s, kCompE), E2 = vA(vi, nb.s, kCompE + 8), PI = vA(vi, nb.s, kCompPi);
 #pragma unroll
-        for (int a = 0; a < 8; a++) {
-            E1.v[a] += dt * F1.v[a];
-            E2.v[a] += dt * F2.v[a];
-            PI.v[a] += dt * Fpi.v[a];
-        }
+    for (int a = 0; a < 8; a++) {
+        E1.v[a] += dt * F1.v[a];
+        E2.v[a] += dt * F2.v[a];
+        PI.v[a] += dt * Fpi.v[a];
     }
+    CPIC_PHASE();
     // drift: U_i <- exp(i (dt/t_half) E_i) U_i ; phi <- phi + dt t_half pi
-    m3<T> U1 = mul(expi(E1, eps_drift), ldU(in.U, 0, nb.s, V));
-    m3<T> U2 = mul(expi(E2, eps_drift), ldU(in.U, 1, nb.s, V));
-    if (reunit) {
-        U1 = reunitarize(U1);
-        U2 = reunitarize(U2);
-    }
+    m3<T> U1 = mul(expi(E1, eps_drift), vU(vi, nb.s, 0));
+    if (reunit) U1 = reunitarize(U1);
+    vU_st(vo, nb.s, 0, U1);
+    CPIC_PHASE();
+    m3<T> U2 = mul(expi(E2, eps_drift), vU(vi, nb.s, 1));
+    if (reunit) U2 = reunitarize(U2);
+    vU_st(vo, nb.s, 1, U2);
 #pragma unroll
     for (int a = 0; a < 8; a++) PHI.v[a] += phi_drift * PI.v[a];
-    stU(out.U, 0, nb.s, V, U1);
-    stU(out.U, 1, nb.s, V, U2);
-    stA(out.phi, nb.s, V, PHI);
-    stA(out.E, nb.s, V, E1);
-    stA(out.E + 8 * (size_t)V, nb.s, V, E2);
-    stA(out.pi, nb.s, V, PI);
+    vA_st(vo, nb.s, kCompPhi, PHI);
+    vA_st(vo, nb.s, kCompE, E1);
+    vA_st(vo, nb.s, kCompE + 8, E2);
+    vA_st(vo, nb.s, kCompPi, PI);
 }
+
+// Occupancy variants: W waves per SIMD requested from the register
+// allocator (W = 1: no request).  Chosen per lattice size and precision by
+// the launch tuner.
+template <typename T>
+__global__ __launch_bounds__(256) void field_step_kernel(Fields<T> in, Fields<T> out, int N, int bx, int by, int remap,
+                                                         Schedule sc, const int* __restrict__ d_step)
+{
+    field_step_body(in, out, N, bx, by, remap, sc, d_step);
+}
+#define CPIC_FIELD_VARIANT(W)                                                                                     \
+    template <typename T>                                                                                         \
+    __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, W))) void field_step_kernel_w##W(    \
+        Fields<T> in, Fields<T> out, int N, int bx, int by, int remap, Schedule sc, const int* __restrict__ d_step) \
+    {                                                                                                             \
+        field_step_body(in, out, N, bx, by, remap, sc, d_step);                                                   \
+    }
+CPIC_FIELD_VARIANT(2)
+CPIC_FIELD_VARIANT(3)
+CPIC_FIELD_VARIANT(4)
+#undef CPIC_FIELD_VARIANT
 
 template <typename T>
 hipError_t launch_field_step(const Fields<T>& in, const Fields<T>& out, int N, const Schedule& sc,
                              const int* d_step, const LaunchCfg& cfg, hipStream_t st)
 {
-    if (cfg.bx <= 0 || cfg.by <= 0 || cfg.bx * cfg.by > 256) return hipErrorInvalidValue;
+    if (cfg.bx <= 0 || cfg.by <= 0 || cfg.bx * cfg.by > 256 || cfg.waves < 1 || cfg.waves > 4) return hipErrorInvalidValue;
     const int ntx = (N + cfg.bx - 1) / cfg.bx, nty = (N + cfg.by - 1) / cfg.by;
     const int ntiles = ntx * nty;
     const int grid = cfg.xcd_remap ? 8 * ((ntiles + 7) / 8) : ntiles;
-    hipLaunchKernelGGL(field_step_kernel<T>, dim3(grid), dim3(cfg.bx, cfg.by), 0, st, in, out, N, cfg.bx, cfg.by,
-                       cfg.xcd_remap, sc, d_step);
+    const dim3 g(grid), b(cfg.bx, cfg.by);
+    switch (cfg.waves) {
+    case 2: hipLaunchKernelGGL(field_step_kernel_w2<T>, g, b, 0, st, in, out, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
+    case 3: hipLaunchKernelGGL(field_step_kernel_w3<T>, g, b, 0, st, in, out, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
+    case 4: hipLaunchKernelGGL(field_step_kernel_w4<T>, g, b, 0, st, in, out, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
+    default: hipLaunchKernelGGL(field_step_kernel<T>, g, b, 0, st, in, out, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step);
+    }
     return hipGetLastError();
 }
 
@@ -191,12 +215,13 @@ __global__ __launch_bounds__(256) void field_diag_kernel(Fields<T> f, int N, T t
     double v[kDiagCols] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (s < V) {
         const int x = s % N, y = s / N;
-        const Nbr nb = neighbours(x, y, N);
-        const a8<T> PHI = ldA(f.phi, s, V), PI = ldA(f.pi, s, V);
-        const a8<T> E1 = ldA(f.E, s, V), E2 = ldA(f.E + 8 * (size_t)V, s, V);
+        const View<T> vf = make_view<T>(f.U, kRealsPerSite, (uint32_t)V);
+        const Nbr nb = neighbours<T>(x, y, N);
+        const a8<T> PHI = vA(vf, nb.s, kCompPhi), PI = vA(vf, nb.s, kCompPi);
+        const a8<T> E1 = vA(vf, nb.s, kCompE), E2 = vA(vf, nb.s, kCompE + 8);
         // Gauss residual, sum_i [E_i(x) - U_i(x-i)^+ E_i(x-i) U_i(x-i)] + i[phi, pi]
-        const a8<T> g1 = transport_adj(ldU(f.U, 0, nb.xm, V), ldA(f.E, nb.xm, V));
-        const a8<T> g2 = transport_adj(ldU(f.U, 1, nb.ym, V), ldA(f.E + 8 * (size_t)V, nb.ym, V));
+        const a8<T> g1 = transport_adj(vU(vf, nb.xm, 0), vA(vf, nb.xm, kCompE));
+        const a8<T> g2 = transport_adj(vU(vf, nb.ym, 1), vA(vf, nb.ym, kCompE + 8));
         const a8<T> gc = icomm(PHI, PI);
         double G2 = 0;
         for (int a = 0; a < 8; a++) {
@@ -207,7 +232,7 @@ __global__ __launch_bounds__(256) void field_diag_kernel(Fields<T> f, int N, T t
         v[1] = sqrt(G2);
         a8<T> F1, F2, Fpi;
         T retr = 0, grad2 = 0;
-        kick_forces(f, V, nb, t, inv_t, PHI, F1, F2, Fpi, &retr, &grad2);
+        kick_forces(vf, nb, t, inv_t, PHI, F1, F2, Fpi, &retr, &grad2);
         const T h = n > 0 ? half_dt : T(0);
         double e2 = 0, p2 = 0;
         for (int a = 0; a < 8; a++) {
@@ -221,7 +246,7 @@ __global__ __launch_bounds__(256) void field_diag_kernel(Fields<T> f, int N, T t
         v[5] = (double)inv_t * (double)grad2;
         double umax = 0, usq = 0;
         for (int i = 0; i < 2; i++) {
-            const m3<T> u = ldU(f.U, i, s, V);
+            const m3<T> u = vU(vf, nb.s, i);
             const m3<T> w = mul_adj(u, u);
             for (int c = 0; c < 9; c++) {
                 const double dr = (double)w.e[c].re - ((c % 4) == 0 ? 1.0 : 0.0), di = w.e[c].im;

@@ -63,6 +63,7 @@ __host__ __device__ inline bool is_reunit_step(const Schedule& s, int n)
 struct LaunchCfg {
     int bx = 64, by = 4;  // field kernel block shape
     int xcd_remap = 1;    // map consecutive tiles onto one XCD
+    int waves = 1;        // register-allocation occupancy target of the field kernel (1 = compiler default)
 };
 
 // ---- field kernels (field.hip)
@@ -80,8 +81,9 @@ struct PushArgs {
     double q0eig[3];  // sorted eigenvalues of Q0 (charge renormalisation)
     Schedule sc;
 };
+// push at t_n: A holds U(n), phi(n), E(n-1/2), pi(n-1/2); B holds E(n+1/2), pi(n+1/2)
 template <typename T>
-hipError_t launch_push(const Fields<T>& A, const T* E_new, const T* pi_new, const Parts<T>& P, const PushArgs& a,
+hipError_t launch_push(const Fields<T>& A, const Fields<T>& B, const Parts<T>& P, const PushArgs& a,
                        const int* d_step, double* partials, int* err, hipStream_t st);
 int push_blocks(int np);
 hipError_t launch_reduce_rows(const double* partials, int nrows, int ncols, double* out, hipStream_t st);
@@ -91,6 +93,20 @@ hipError_t launch_step_end(const Schedule& sc, int nblocks, const double* partia
                            hipStream_t st);
 template <typename T>
 hipError_t launch_part_diag(const Parts<T>& P, int np, double q2, double q3, double* partials, hipStream_t st);
+
+// ---- particle ordering (sort.hip)
+struct SortBufs {
+    unsigned *keys = nullptr, *keys2 = nullptr;
+    int *vals = nullptr, *perm = nullptr;
+    void* temp = nullptr;
+    size_t temp_bytes = 0;
+    void* r2 = nullptr;  // [18][np] scratch records
+    int *cell2 = nullptr, *pid2 = nullptr;
+};
+size_t sort_temp_bytes(int np, int N);
+template <typename T>
+hipError_t sort_particles(const SortBufs& b, T* r, int* cell, int* pid, int np, int N, hipStream_t st);
+constexpr int kSortEvery = 32;  // steps between reorderings of moving particles
 
 // ---- initial condition (ic.hip), always double precision
 struct ICArgs {

@@ -11,31 +11,45 @@
 #include "internal.h"
 #include "reduce.h"
 #include "su3.h"
+#include "bufio.h"
 
 namespace cpic {
 
-template <typename T> __device__ __forceinline__ m3<T> gU(const T* __restrict__ U, int i, int s, int V)
-{
-    const T* p = U + (size_t)i * 18 * V + s;
-    m3<T> m;
-#pragma unroll
-    for (int c = 0; c < 9; c++) m.e[c] = {p[(size_t)(2 * c) * V], p[(size_t)(2 * c + 1) * V]};
-    return m;
-}
-template <typename T> __device__ __forceinline__ a8<T> gA(const T* __restrict__ p, int s, int V)
-{
-    a8<T> r;
-#pragma unroll
-    for (int a = 0; a < 8; a++) r.v[a] = p[(size_t)a * V + s];
-    return r;
-}
 __device__ __forceinline__ int wrap(int v, int N) { return v < 0 ? v + N : (v >= N ? v - N : v); }
 
 // components of A^+ Q A
 template <typename T> __device__ __forceinline__ a8<T> rotate(const m3<T>& A, const a8<T>& Q) { return transport_adj(A, Q); }
 
 // Replace the spectrum of Q by the sorted spectrum of Q0 (keeps the
-// eigenvectors): restores both classical Casimirs exactly.
+// eigenvectors): restores both classical Casimirs exactly.  Written with
+// compile-time indices only (no private arrays indexed at run time).
+template <typename T> __device__ __forceinline__ void null_vector(const m3<T>& H, T l, cx<T>* v)
+{
+    // rows of H - l: the cross product of two rows is orthogonal to both;
+    // keep the largest of the three choices
+    cx<T> m[9];
+#pragma unroll
+    for (int q = 0; q < 9; q++) m[q] = H.e[q];
+    m[0].re -= l; m[4].re -= l; m[8].re -= l;
+    T best = T(-1);
+#pragma unroll
+    for (int pr = 0; pr < 3; pr++) {
+        const int ra = pr == 2 ? 1 : 0, rb = pr == 0 ? 1 : 2;
+        cx<T> c[3];
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+            const cx<T> u = cmul(m[3 * ra + j1], m[3 * rb + j2]), w = cmul(m[3 * ra + j2], m[3 * rb + j1]);
+            c[j] = {u.re - w.re, u.im - w.im};
+        }
+        const T nn = c[0].re * c[0].re + c[0].im * c[0].im + c[1].re * c[1].re + c[1].im * c[1].im +
+                     c[2].re * c[2].re + c[2].im * c[2].im;
+        const bool take = nn > best;
+        best = take ? nn : best;
+#pragma unroll
+        for (int j = 0; j < 3; j++) v[j] = take ? c[j] : v[j];
+    }
+}
 template <typename T> __device__ a8<T> renorm_charge(const a8<T>& Q, const double* eig0)
 {
     const m3<T> H = herm(Q);
@@ -51,200 +65,219 @@ template <typename T> __device__ a8<T> renorm_charge(const a8<T>& Q, const doubl
     T arg = det / (T(2) * r * r * r);
     arg = arg > T(1) ? T(1) : (arg < T(-1) ? T(-1) : arg);
     const T th = acos(arg) / T(3);
-    T lam[3];
-    for (int k = 0; k < 3; k++) lam[k] = T(2) * r * cos(th - T(2.0943951023931954923) * k);
-    // sort ascending (lam[0] is the largest root, lam[1] the smallest)
-    int ord[3] = {1, 2, 0};
-    if (lam[ord[1]] < lam[ord[0]]) { int q = ord[0]; ord[0] = ord[1]; ord[1] = q; }
-    cx<T> v[3][3];
-    for (int k = 0; k < 2; k++) {
-        const T l = lam[ord[k]];
-        cx<T> m[9];
-        for (int q = 0; q < 9; q++) m[q] = H.e[q];
-        m[0].re -= l; m[4].re -= l; m[8].re -= l;
-        // null vector: the largest cross product of two rows
-        T best = -1;
-        for (int pr = 0; pr < 3; pr++) {
-            const int ra = pr == 2 ? 1 : 0, rb = pr == 0 ? 1 : 2;
-            cx<T> c[3];
-            for (int j = 0; j < 3; j++) {
-                const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
-                const cx<T> u = cmul(m[3 * ra + j1], m[3 * rb + j2]), w = cmul(m[3 * ra + j2], m[3 * rb + j1]);
-                c[j] = {u.re - w.re, u.im - w.im};
-            }
-            const T nn = c[0].re * c[0].re + c[0].im * c[0].im + c[1].re * c[1].re + c[1].im * c[1].im +
-                         c[2].re * c[2].re + c[2].im * c[2].im;
-            if (nn > best) {
-                best = nn;
-                for (int j = 0; j < 3; j++) v[k][j] = c[j];
-            }
-        }
-        if (k == 1) {  // orthogonalise against the first vector
-            cx<T> ip = {0, 0};
-            for (int j = 0; j < 3; j++) { cx<T> q = ccmul(v[0][j], v[1][j]); ip.re += q.re; ip.im += q.im; }
-            for (int j = 0; j < 3; j++) { cx<T> q = cmul(ip, v[0][j]); v[1][j].re -= q.re; v[1][j].im -= q.im; }
-        }
-        T nn = 0;
-        for (int j = 0; j < 3; j++) nn += v[k][j].re * v[k][j].re + v[k][j].im * v[k][j].im;
-        const T inv = T(1) / sqrt(nn);
-        for (int j = 0; j < 3; j++) { v[k][j].re *= inv; v[k][j].im *= inv; }
+    // roots 2r cos(th - 2 pi k/3) with th in [0, pi/3]: k = 0 largest,
+    // k = 1 middle, k = 2 smallest
+    const T mid = T(2) * r * cos(th - T(2.0943951023931954923));
+    const T lo = T(2) * r * cos(th - T(4.1887902047863909846));
+    cx<T> v0[3], v1[3], v2[3];
+    null_vector(H, lo, v0);
+    null_vector(H, mid, v1);
+    T n0 = 0;
+#pragma unroll
+    for (int j = 0; j < 3; j++) n0 += v0[j].re * v0[j].re + v0[j].im * v0[j].im;
+    const T i0 = T(1) / sqrt(n0);
+#pragma unroll
+    for (int j = 0; j < 3; j++) { v0[j].re *= i0; v0[j].im *= i0; }
+    cx<T> ip = {0, 0};
+#pragma unroll
+    for (int j = 0; j < 3; j++) { const cx<T> q = ccmul(v0[j], v1[j]); ip.re += q.re; ip.im += q.im; }
+    T n1 = 0;
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+        const cx<T> q = cmul(ip, v0[j]);
+        v1[j].re -= q.re; v1[j].im -= q.im;
+        n1 += v1[j].re * v1[j].re + v1[j].im * v1[j].im;
     }
+    const T i1 = T(1) / sqrt(n1);
+#pragma unroll
+    for (int j = 0; j < 3; j++) { v1[j].re *= i1; v1[j].im *= i1; }
+#pragma unroll
     for (int j = 0; j < 3; j++) {  // v2 = conj(v0 x v1)
         const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
-        const cx<T> u = cmul(v[0][j1], v[1][j2]), w = cmul(v[0][j2], v[1][j1]);
-        v[2][j] = {u.re - w.re, -(u.im - w.im)};
+        const cx<T> u = cmul(v0[j1], v1[j2]), w = cmul(v0[j2], v1[j1]);
+        v2[j] = {u.re - w.re, -(u.im - w.im)};
     }
-    // Q' = sum_k eig0_k v_k v_k^+
-    cx<T> M[9];
-    for (int q = 0; q < 9; q++) M[q] = {0, 0};
-    for (int k = 0; k < 3; k++)
-        for (int i = 0; i < 3; i++)
-            for (int j = 0; j < 3; j++) {
-                const cx<T> q = cmulc(v[k][i], v[k][j]);
-                M[3 * i + j].re += T(eig0[k]) * q.re;
-                M[3 * i + j].im += T(eig0[k]) * q.im;
-            }
-    return herm_comp(M[0], M[4], M[8], M[1], M[2], M[5]);
+    // Q' = sum_k eig0_k v_k v_k^+, only the upper triangle is needed
+    const T l0 = T(eig0[0]), l1 = T(eig0[1]), l2 = T(eig0[2]);
+    auto ent = [&](int i, int j) {
+        const cx<T> a = cmulc(v0[i], v0[j]), b = cmulc(v1[i], v1[j]), c = cmulc(v2[i], v2[j]);
+        return cx<T>{l0 * a.re + l1 * b.re + l2 * c.re, l0 * a.im + l1 * b.im + l2 * c.im};
+    };
+    return herm_comp(ent(0, 0), ent(1, 1), ent(2, 2), ent(0, 1), ent(0, 2), ent(1, 2));
 }
 
-// colour fields at site c, time t_n (Sec. III.B interpolations), hat units:
-// F[0..2] = E_x, E_y, E_eta; F[3..5] = B_x, B_y, B_eta
+// compiler barrier between phases: keeps the links of one phase from being
+// loaded (and held in registers) during another
+#define CPIC_PHASE() __builtin_amdgcn_sched_barrier(0)
+
+// Q . F for the six colour fields at site c, time t_n (Sec. III.B
+// interpolations), hat units:
+//   out[0..2] = Q.E_x, Q.E_y, Q.E_eta ; out[3..5] = Q.B_x, Q.B_y, Q.B_eta
 template <typename T>
-__device__ __forceinline__ void fields_at(const Fields<T>& A, const T* __restrict__ En, const T* __restrict__ pin,
-                                          int N, int cx, int cy, int n, T t, bool electric_only, a8<T>* F)
+__device__ __forceinline__ void forces_dot(const View<T>& A, const View<T>& B, int N, int cx, int cy, int n, T t,
+                                           bool electric_only, const a8<T>& Q, T* out)
 {
-    const int V = N * N;
+    constexpr uint32_t b = sizeof(T);
     const int xm = wrap(cx - 1, N), xp = wrap(cx + 1, N), ym = wrap(cy - 1, N), yp = wrap(cy + 1, N);
-    const int s = cy * N + cx;
-    const int s_xm = cy * N + xm, s_xp = cy * N + xp, s_ym = ym * N + cx, s_yp = yp * N + cx;
+    const uint32_t s = (uint32_t)(cy * N + cx) * b;
+    const uint32_t s_xm = (uint32_t)(cy * N + xm) * b, s_xp = (uint32_t)(cy * N + xp) * b;
+    const uint32_t s_ym = (uint32_t)(ym * N + cx) * b, s_yp = (uint32_t)(yp * N + cx) * b;
+    out[0] = out[1] = out[3] = out[4] = out[5] = T(0);
     if (n > 0) {
         const T q = T(1) / (T(4) * t);
+#pragma unroll
         for (int i = 0; i < 2; i++) {
-            const int sb = i == 0 ? s_xm : s_ym;
-            const T* Eo = A.E + (size_t)i * 8 * V;
-            const T* Enw = En + (size_t)i * 8 * V;
+            const uint32_t sb = i == 0 ? s_xm : s_ym;
+            const uint32_t ce = kCompE + 8 * i;
             a8<T> here, back;
 #pragma unroll
             for (int a = 0; a < 8; a++) {
-                here.v[a] = Eo[(size_t)a * V + s] + Enw[(size_t)a * V + s];
-                back.v[a] = Eo[(size_t)a * V + sb] + Enw[(size_t)a * V + sb];
+                here.v[a] = bld(A, s, ce + a) + bld(B, s, ce + a);
+                back.v[a] = bld(A, sb, ce + a) + bld(B, sb, ce + a);
             }
-            const a8<T> tb = transport_adj(gU(A.U, i, sb, V), back);
-#pragma unroll
-            for (int a = 0; a < 8; a++) F[i].v[a] = q * (here.v[a] + tb.v[a]);
+            // Q.(U^+ X U) = (U Q U^+).X
+            const a8<T> qb = transport(vU(A, sb, i), Q);
+            out[i] = q * (dot(Q, here) + dot(qb, back));
+            CPIC_PHASE();
         }
+        T e = 0;
 #pragma unroll
-        for (int a = 0; a < 8; a++) F[2].v[a] = T(0.5) * (A.pi[(size_t)a * V + s] + pin[(size_t)a * V + s]);
+        for (int a = 0; a < 8; a++) e += Q.v[a] * (bld(A, s, kCompPi + a) + bld(B, s, kCompPi + a));
+        out[2] = T(0.5) * e;
     } else {
-        F[0] = azero<T>();
-        F[1] = azero<T>();
+        T e = 0;
 #pragma unroll
-        for (int a = 0; a < 8; a++) F[2].v[a] = pin[(size_t)a * V + s];
+        for (int a = 0; a < 8; a++) e += Q.v[a] * bld(B, s, kCompPi + a);
+        out[2] = e;
     }
     if (electric_only) return;
+    CPIC_PHASE();
     if (n > 0) {
+        // B_x = -(phi->_y - phi<-_y)/(2t), B_y = +(phi->_x - phi<-_x)/(2t);
+        // Q.(U X U^+) = (U^+ Q U).X and Q.(U^+ X U) = (U Q U^+).X
         const T q = T(1) / (T(2) * t);
-        const m3<T> U1 = gU(A.U, 0, s, V), U2 = gU(A.U, 1, s, V);
-        const a8<T> f2 = transport(U2, gA(A.phi, s_yp, V));
-        const a8<T> b2 = transport_adj(gU(A.U, 1, s_ym, V), gA(A.phi, s_ym, V));
-        const a8<T> f1 = transport(U1, gA(A.phi, s_xp, V));
-        const a8<T> b1 = transport_adj(gU(A.U, 0, s_xm, V), gA(A.phi, s_xm, V));
+        T fy, by, fx, bx;
+        { const a8<T> w = transport_adj(vU(A, s, 1), Q);    fy = dot(w, vA(A, s_yp, kCompPhi)); }
+        CPIC_PHASE();
+        { const a8<T> w = transport(vU(A, s_ym, 1), Q);     by = dot(w, vA(A, s_ym, kCompPhi)); }
+        CPIC_PHASE();
+        { const a8<T> w = transport_adj(vU(A, s, 0), Q);    fx = dot(w, vA(A, s_xp, kCompPhi)); }
+        CPIC_PHASE();
+        { const a8<T> w = transport(vU(A, s_xm, 0), Q);     bx = dot(w, vA(A, s_xm, kCompPhi)); }
+        out[3] = -q * (fy - by);
+        out[4] = q * (fx - bx);
+        CPIC_PHASE();
+    }
+    // B_eta = -(1/4) Proj[U_12 + U_{2,-1} + U_{-1,-2} + U_{-2,1}] (clover, all
+    // counter-clockwise).  Each leaf is a product of four links; leaf k,
+    // factor f is link `dir` at (x + dx, y + dy), daggered if `dg`, packed as
+    // dx+1 | (dy+1) << 2 | dir << 4 | dg << 5.  The loop is kept rolled so
+    // only one leaf's links are live at a time.
+    //   U_12      = U_1(x) U_2(x+1) U_1(x+2)^+ U_2(x)^+
+    //   U_{2,-1}  = U_2(x) U_1(x-1+2)^+ U_2(x-1)^+ U_1(x-1)
+    //   U_{-1,-2} = U_1(x-1)^+ U_2(x-1-2)^+ U_1(x-1-2) U_2(x-2)
+    //   U_{-2,1}  = U_2(x-2)^+ U_1(x-2) U_2(x+1-2) U_1(x)^+
+    constexpr uint64_t L0 = (1 | 1 << 2 | 0 << 4 | 0 << 5) | (2 | 1 << 2 | 1 << 4 | 0 << 5) << 6 |
+                            (1 | 2 << 2 | 0 << 4 | 1 << 5) << 12 | (1 | 1 << 2 | 1 << 4 | 1 << 5) << 18;
+    constexpr uint64_t L1 = (1 | 1 << 2 | 1 << 4 | 0 << 5) | (0 | 2 << 2 | 0 << 4 | 1 << 5) << 6 |
+                            (0 | 1 << 2 | 1 << 4 | 1 << 5) << 12 | (0 | 1 << 2 | 0 << 4 | 0 << 5) << 18;
+    constexpr uint64_t L2 = (0 | 1 << 2 | 0 << 4 | 1 << 5) | (0 | 0 << 2 | 1 << 4 | 1 << 5) << 6 |
+                            (0 | 0 << 2 | 0 << 4 | 0 << 5) << 12 | (1 | 0 << 2 | 1 << 4 | 0 << 5) << 18;
+    constexpr uint64_t L3 = (1 | 0 << 2 | 1 << 4 | 1 << 5) | (1 | 0 << 2 | 0 << 4 | 0 << 5) << 6 |
+                            (2 | 0 << 2 | 1 << 4 | 0 << 5) << 12 | (1 | 1 << 2 | 0 << 4 | 1 << 5) << 18;
+    constexpr uint64_t kLeaf01 = L0 | L1 << 32, kLeaf23 = L2 | L3 << 32;
+    T be = 0;
+#pragma unroll 1
+    for (int k = 0; k < 4; k++) {
+        const uint32_t code = (uint32_t)(((k < 2 ? kLeaf01 : kLeaf23) >> (32 * (k & 1))) & 0xFFFFFFu);
+        m3<T> W;
 #pragma unroll
-        for (int a = 0; a < 8; a++) {
-            F[3].v[a] = -q * (f2.v[a] - b2.v[a]);
-            F[4].v[a] = q * (f1.v[a] - b1.v[a]);
+        for (int fct = 0; fct < 4; fct++) {
+            const uint32_t c = (code >> (6 * fct)) & 63u;
+            const int dx = (int)(c & 3u) - 1, dy = (int)((c >> 2) & 3u) - 1, dir = (c >> 4) & 1u;
+            const uint32_t so = (uint32_t)(wrap(cy + dy, N) * N + wrap(cx + dx, N)) * b;
+            m3<T> L = vU(A, so, dir);
+            if (c & 32u) L = adj(L);
+            W = fct == 0 ? L : mul(W, L);
         }
-    } else {
-        F[3] = azero<T>();
-        F[4] = azero<T>();
+        be += dot(Q, proj(W));
     }
-    // B_eta = -(1/4) Proj[U_12 + U_{2,-1} + U_{-1,-2} + U_{-2,1}] (clover, all counter-clockwise)
-    const int s_xmym = ym * N + xm, s_xmyp = yp * N + xm, s_xpym = ym * N + xp;
-    a8<T> acc;
-    {
-        const m3<T> P = mul_adj(mul(gU(A.U, 0, s, V), gU(A.U, 1, s_xp, V)), mul(gU(A.U, 1, s, V), gU(A.U, 0, s_yp, V)));
-        acc = proj(P);
-    }
-    {   // U_2(x) U_1(x-1+2)^+ U_2(x-1)^+ U_1(x-1)
-        const m3<T> P = mul(mul_adj(gU(A.U, 1, s, V), gU(A.U, 0, s_xmyp, V)),
-                            adj_mul(gU(A.U, 1, s_xm, V), gU(A.U, 0, s_xm, V)));
-        axpy(acc, T(1), proj(P));
-    }
-    {   // U_1(x-1)^+ U_2(x-1-2)^+ U_1(x-1-2) U_2(x-2)
-        const m3<T> P = mul(adj_mul(gU(A.U, 0, s_xm, V), adj(gU(A.U, 1, s_xmym, V))),
-                            mul(gU(A.U, 0, s_xmym, V), gU(A.U, 1, s_ym, V)));
-        axpy(acc, T(1), proj(P));
-    }
-    {   // U_2(x-2)^+ U_1(x-2) U_2(x+1-2) U_1(x)^+
-        const m3<T> P = mul_adj(mul(adj_mul(gU(A.U, 1, s_ym, V), gU(A.U, 0, s_ym, V)), gU(A.U, 1, s_xpym, V)),
-                                gU(A.U, 0, s, V));
-        axpy(acc, T(1), proj(P));
-    }
-#pragma unroll
-    for (int a = 0; a < 8; a++) F[5].v[a] = T(-0.25) * acc.v[a];
+    out[5] = T(-0.25) * be;
+}
+
+// particle block b of the grid -> logical block: consecutive logical blocks
+// (neighbouring cells once the particles are sorted) share one XCD's L2
+__device__ __forceinline__ int xcd_block(int nblocks)
+{
+    const int per = (nblocks + 7) / 8;
+    return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void push_kernel(Fields<T> A, const T* __restrict__ En, const T* __restrict__ pin,
-                                                   Parts<T> P, PushArgs a, const int* __restrict__ d_step,
-                                                   double* partials, int* err)
+__global__ __launch_bounds__(256) void push_kernel(Fields<T> Af, Fields<T> Bf, Parts<T> P, PushArgs a,
+                                                   const int* __restrict__ d_step, double* partials, int* err)
 {
     const int n = *d_step;
     if (n < a.sc.n_form || n >= a.sc.n_max) return;  // uniform over the grid
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nblocks = (a.np + 255) / 256;
+    const int blk = xcd_block(nblocks);
+    if (blk >= nblocks) return;                      // uniform over the block
+    const int p = blk * 256 + threadIdx.x;
     const int N = a.N, np = a.np;
+    const uint32_t V = (uint32_t)N * N;
+    const View<T> A = make_view<T>(Af.U, kRealsPerSite, V), B = make_view<T>(Bf.U, kRealsPerSite, V);
+    const View<T> R = make_view<T>(P.r, kPartReals, (uint32_t)np);
+    const View<int> C = make_view<int>(P.cell, 2, (uint32_t)np);
     const T dt = T(a.sc.dt), t = T(n * a.sc.dt);
     const int record_slot = is_record_step(a.sc, n) ? record_slot_of(a.sc, n) : -1;
     const bool renorm = is_reunit_step(a.sc, n);
     double obs[4] = {0, 0, 0, 0};
     if (p < np) {
-        T* r = P.r;
-        auto col = [&](int c) -> T& { return r[(size_t)c * np + p]; };
+        const uint32_t po = (uint32_t)p * sizeof(T), pi = (uint32_t)p * sizeof(int);
         a8<T> Q;
 #pragma unroll
-        for (int q = 0; q < 8; q++) Q.v[q] = col(PQ0 + q);
-        const T ux0 = col(PUX0), uy0 = col(PUY0), pt0 = col(PPT0);
-        T px = col(PPX), py = col(PPY), pe = col(PPETA);
-        T eta = col(PETA_);
-        a8<T> F[6];
+        for (int q = 0; q < 8; q++) Q.v[q] = bld(R, po, PQ0 + q);
+        T px = bld(R, po, PPX), py = bld(R, po, PPY), pe = bld(R, po, PPETA);
+        T eta = bld(R, po, PETA_);
+        T f[6];
         if (a.is_static) {
-            const int cx = P.cell[p], cy = P.cell[np + p];
-            fields_at(A, En, pin, N, cx, cy, n, t, true, F);
-            px += dt * dot(Q, F[0]);
-            py += dt * dot(Q, F[1]);
-            pe += dt * dot(Q, F[2]);  // p^z of the static branch
-            col(PPX) = px; col(PPY) = py; col(PPETA) = pe;
+            const int cx = bld_i(C, pi, 0), cy = bld_i(C, pi, 1);
+            forces_dot(A, B, N, cx, cy, n, t, true, Q, f);
+            px += dt * f[0];
+            py += dt * f[1];
+            pe += dt * f[2];  // p^z of the static branch
+            bst(R, po, PPX, px); bst(R, po, PPY, py); bst(R, po, PPETA, pe);
         } else {
-            const T x = col(PX_), y = col(PY_);
+            const T x = bld(R, po, PX_), y = bld(R, po, PY_);
             int nx = (int)floor(x + T(0.5)), ny = (int)floor(y + T(0.5));
             nx = nx >= N ? nx - N : nx;
             ny = ny >= N ? ny - N : ny;
             if (n > a.sc.n_form) {
-                int cx = P.cell[p], cy = P.cell[np + p];
-                const int V = N * N;
+                int cx = bld_i(C, pi, 0), cy = bld_i(C, pi, 1);
                 int d[2] = {nx - cx, ny - cy};
+#pragma unroll
                 for (int ax = 0; ax < 2; ax++) {
                     int dd = d[ax];
                     if (dd > N / 2) dd -= N;
                     if (dd < -N / 2) dd += N;
-                    const int c = cy * N + cx;
                     if (dd == 1) {
-                        Q = rotate(gU(A.U, ax, c, V), Q);
+                        Q = rotate(vU(A, (uint32_t)(cy * N + cx) * (uint32_t)sizeof(T), ax), Q);
                     } else if (dd == -1) {
                         const int cb = ax == 0 ? cy * N + wrap(cx - 1, N) : wrap(cy - 1, N) * N + cx;
-                        Q = rotate(adj(gU(A.U, ax, cb, V)), Q);
+                        Q = transport(vU(A, (uint32_t)cb * (uint32_t)sizeof(T), ax), Q);   // U Q U^+
                     } else if (dd != 0) {
                         atomicAdd(err, 1);
                     }
                     if (ax == 0) cx = nx; else cy = ny;
                 }
-                const T deta = col(PDETA);
-                if (deta != T(0)) Q = rotate(expi(gA(A.phi, ny * N + nx, V), deta), Q);
+                const T deta = bld(R, po, PDETA);
+                if (deta != T(0))
+                    Q = rotate(expi(vA(A, (uint32_t)(ny * N + nx) * (uint32_t)sizeof(T), kCompPhi), deta), Q);
             }
             if (renorm) Q = renorm_charge(Q, a.q0eig);
-            fields_at(A, En, pin, N, nx, ny, n, t, false, F);
-            const T e1 = dot(Q, F[0]), e2 = dot(Q, F[1]), ee = dot(Q, F[2]);
-            const T b1 = dot(Q, F[3]), b2 = dot(Q, F[4]), be = dot(Q, F[5]);
+            CPIC_PHASE();
+            forces_dot(A, B, N, nx, ny, n, t, false, Q, f);
+            const T e1 = f[0], e2 = f[1], ee = f[2], b1 = f[3], b2 = f[4], be = f[5];
             const T mh = T(a.mhat);
             const T ptau = sqrt(px * px + py * py + (t * pe) * (t * pe) + mh * mh);
             const T v1 = px / ptau, v2 = py / ptau, vl = t * pe / ptau;
@@ -257,16 +290,17 @@ __global__ __launch_bounds__(256) void push_kernel(Fields<T> A, const T* __restr
             const T deta = dt * pe / ptau;
             eta += deta;
             px = npx; py = npy; pe = npe;
-            col(PX_) = xn; col(PY_) = yn; col(PETA_) = eta;
-            col(PPX) = px; col(PPY) = py; col(PPETA) = pe; col(PDETA) = deta;
-            P.cell[p] = nx;
-            P.cell[np + p] = ny;
+            bst(R, po, PX_, xn); bst(R, po, PY_, yn); bst(R, po, PETA_, eta);
+            bst(R, po, PPX, px); bst(R, po, PPY, py); bst(R, po, PPETA, pe); bst(R, po, PDETA, deta);
+            bst_i(C, pi, 0, nx);
+            bst_i(C, pi, 1, ny);
         }
         if (n > a.sc.n_form || renorm) {
 #pragma unroll
-            for (int q = 0; q < 8; q++) col(PQ0 + q) = Q.v[q];
+            for (int q = 0; q < 8; q++) bst(R, po, PQ0 + q, Q.v[q]);
         }
         if (record_slot >= 0) {
+            const T ux0 = bld(R, po, PUX0), uy0 = bld(R, po, PUY0), pt0 = bld(R, po, PPT0);
             const double dpx = px, dpy = py, tn = (double)(n + 1) * a.sc.dt;
             double pz;
             if (a.is_static) {
@@ -286,18 +320,18 @@ __global__ __launch_bounds__(256) void push_kernel(Fields<T> A, const T* __restr
         }
     }
     if (record_slot >= 0)
-        block_reduce_store<4>(obs, 0u, partials + ((size_t)record_slot * gridDim.x + blockIdx.x) * 4);
+        block_reduce_store<4>(obs, 0u, partials + ((size_t)record_slot * nblocks + blk) * 4);
 }
 
 int push_blocks(int np) { return (np + 255) / 256; }
 
 template <typename T>
-hipError_t launch_push(const Fields<T>& A, const T* E_new, const T* pi_new, const Parts<T>& P, const PushArgs& a,
+hipError_t launch_push(const Fields<T>& A, const Fields<T>& B, const Parts<T>& P, const PushArgs& a,
                        const int* d_step, double* partials, int* err, hipStream_t st)
 {
     if (a.np <= 0) return hipSuccess;
-    hipLaunchKernelGGL(push_kernel<T>, dim3(push_blocks(a.np)), dim3(256), 0, st, A, E_new, pi_new, P, a, d_step,
-                       partials, err);
+    const int nb = push_blocks(a.np);
+    hipLaunchKernelGGL(push_kernel<T>, dim3(8 * ((nb + 7) / 8)), dim3(256), 0, st, A, B, P, a, d_step, partials, err);
     return hipGetLastError();
 }
 
@@ -384,9 +418,9 @@ hipError_t launch_part_diag(const Parts<T>& P, int np, double q2, double q3, dou
     return hipGetLastError();
 }
 
-template hipError_t launch_push<double>(const Fields<double>&, const double*, const double*, const Parts<double>&,
+template hipError_t launch_push<double>(const Fields<double>&, const Fields<double>&, const Parts<double>&,
                                         const PushArgs&, const int*, double*, int*, hipStream_t);
-template hipError_t launch_push<float>(const Fields<float>&, const float*, const float*, const Parts<float>&,
+template hipError_t launch_push<float>(const Fields<float>&, const Fields<float>&, const Parts<float>&,
                                        const PushArgs&, const int*, double*, int*, hipStream_t);
 template hipError_t launch_part_diag<double>(const Parts<double>&, int, double, double, double*, hipStream_t);
 template hipError_t launch_part_diag<float>(const Parts<float>&, int, double, double, double*, hipStream_t);

@@ -290,3 +290,31 @@ def test_fp32_against_fp64_oracle():
     assert max(errs.values()) < 2e-3
     assert e_pt < 1e-4 and e_pl < 1e-4
     assert d[6] < 1e-5
+
+
+def test_fp32_dynamic_particles_with_charge_renormalisation():
+    """Moving particles in float: rotations, the rapidity Wilson line and the
+    renormalisation of Q onto Q0's spectrum every 16 steps, against the double
+    oracle after 48 steps (three renormalisations)."""
+    N, L, n0, n_form, steps = 32, 6.0, 4, 2, 48
+    a = oracle.lattice_spacing(L, N)
+    st = inputs.random_state(N, 51, eps_link=0.3, e_scale=0.05, phi_scale=0.05, pi_scale=0.05)
+    P = inputs.random_particles(2000, N, 52, p_scale=0.6)
+    P[:, 6:14] = oracle.particles_init(N, 2000, 53, 0.0, 0.0, True, 0)[:, 6:14]   # Casimirs of Q0
+    ctx = cp.Context(glasma(N, L, steps=n0 + steps, precision=cp.FP32, reunit_every=16),
+                     particle_params(2000, 0.3 / a, N, L, n_form))
+    ctx.load_state(st, n=n0, particles=P)
+    ctx.step(steps)
+    d = ctx.diagnostics()
+    got = ctx.get_state(cp.STATE_PARTICLES)
+    run = oracle.Run(N, 0.125, st, P, mhat=0.3, n_form=n_form, n0=n0)
+    for _ in range(steps):
+        run.step()
+    same = np.all(got[:, 14:16] == run.P[:, 14:16], axis=1)
+    assert same.mean() > 0.99                       # float rounding may move a particle across a cell edge
+    q_err = np.max(np.abs(got[same, 6:14] - run.P[same, 6:14]))
+    p_err = np.max(np.abs(got[same, 3:6] - run.P[same, 3:6])) / np.max(np.abs(run.P[:, 3:6]))
+    print(f"FP32 dynamic: cells equal {same.mean():.4f}, max |dQ| {q_err:.2e}, rel |dp| {p_err:.2e}, "
+          f"Casimir drift {d[8]:.1e} {d[9]:.1e}")
+    assert q_err < 1e-3 and p_err < 1e-3
+    assert d[8] < 1e-4 and d[9] < 1e-4

@@ -51,6 +51,8 @@ def run_event(precision, steps, warmup):
     t_ic = time.perf_counter() - t0
     ctx.step(warmup)
     ctx.sync()
+    tune_report = ctx.tune(5)
+    launch = ctx.get_launch()
     ctx.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -69,7 +71,8 @@ def run_event(precision, steps, warmup):
     ctx.sync()
     graph_ms = (time.perf_counter() - t0) * 1e3 / max(n_left, 1)
     ctx.close()
-    return dict(wall=wall, t_ic=t_ic, timing=tm, diag=d, obs=obs, graph_ms_per_step=graph_ms)
+    return dict(wall=wall, t_ic=t_ic, timing=tm, diag=d, obs=obs, graph_ms_per_step=graph_ms, launch=launch,
+                tune_report=tune_report)
 
 
 def cpu_baseline(n_steps=6, n_part=100_000):
@@ -103,6 +106,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the FP32 run")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
                     help="precision of the headline run (profiling)")
+    ap.add_argument("--tune-report", default=None, help="write the launch tuner's table to this file")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (reference for the HBM counters)")
     args = ap.parse_args()
@@ -156,6 +160,7 @@ def main():
                      "bytes_per_launch": BYTES_PER_SITE["f64"] * V},
         "push_kernel": {"avg_launch_us": push_avg_s * 1e6, "pushes_per_s_kernel": 100_000 / push_avg_s},
         "graph_ms_per_step": res["graph_ms_per_step"],
+        "launch": res["launch"],
         "ic_seconds": res["t_ic"],
         "gauss_max": res["diag"][1], "unitarity_max": res["diag"][6],
         "dpT2_GeV2_last": float(res["obs"][-1, 1]), "dpL2_GeV2_last": float(res["obs"][-1, 2]),
@@ -171,10 +176,14 @@ def main():
                        "field_GBs": BYTES_PER_SITE["f32"] * V / f32_avg / 1e9,
                        "field_frac_hbm": BYTES_PER_SITE["f32"] * V / f32_avg / 1e9 / HBM_PEAK_GBS,
                        "push_avg_launch_us": t32["push_ms"] / max(t32["n_push"], 1) * 1e3,
+                       "launch": r32["launch"],
                        "dpT2_rel_vs_fp64": float(abs(r32["obs"][-1, 1] / res["obs"][-1, 1] - 1)),
                        "dpL2_rel_vs_fp64": float(abs(r32["obs"][-1, 2] / res["obs"][-1, 2] - 1))}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
+    if args.tune_report:
+        with open(args.tune_report, "w") as f:
+            f.write(res["tune_report"])
     print(json.dumps(out))
 
 

@@ -201,11 +201,31 @@ cpic_status cpic_set_state(cpic_ctx* ctx, int32_t which, const void* host_src, s
 cpic_status cpic_save(cpic_ctx* ctx, const char* path);
 cpic_status cpic_load(cpic_ctx* ctx, const char* path);
 
-/* Field-kernel launch: block shape (bx * by a multiple of 64, <= 256), whether
- * consecutive tiles are mapped onto one XCD, and the occupancy the register
- * allocator targets (waves per SIMD, 1..4; 1 = compiler default).  Used by the
- * tuner; takes effect for the next launch. */
-cpic_status cpic_set_launch(cpic_ctx* ctx, int32_t bx, int32_t by, int32_t xcd_remap, int32_t waves);
+/* Field-kernel launch: tile shape in sites, whether consecutive tiles are
+ * mapped onto one XCD, the occupancy the register allocator targets (waves per
+ * SIMD; 1 = compiler default) and the decomposition: link_parallel = 0, one
+ * thread per site (bx * by a multiple of 64, <= 256, waves 1..4);
+ * link_parallel = 1, one thread per link (bx * by = 128, bx a multiple of 32,
+ * waves 1..3).  Used by the tuner; takes effect for the next launch. */
+cpic_status cpic_set_launch(cpic_ctx* ctx, int32_t bx, int32_t by, int32_t xcd_remap, int32_t waves,
+                            int32_t link_parallel);
+
+/* Push work split: wavefronts per group of 64 particles (1, 2 or 4).  With few
+ * particles several wavefronts share a group (each evaluates part of the field
+ * contractions) so that the push still fills the GPU.  Default from n. */
+cpic_status cpic_set_push_lanes(cpic_ctx* ctx, int32_t lanes);
+
+/* Current launch configuration: out = {bx, by, xcd_remap, waves, push lanes,
+ * link_parallel}. */
+cpic_status cpic_get_launch(const cpic_ctx* ctx, int32_t out[6]);
+
+/* Launch tuner: times every candidate field-kernel configuration (block shape x
+ * occupancy target x XCD mapping) in place on the current state without
+ * advancing it (the free buffer is overwritten), and, once particles are being
+ * pushed, the push lanes on a saved copy of the particles; keeps the fastest.
+ * reps launches per candidate.  report (may be NULL) receives a text table.
+ * Synchronises. */
+cpic_status cpic_tune(cpic_ctx* ctx, int32_t reps, char* report, size_t cap);
 
 /* Kernel timing: when enabled, every field-update and particle-push launch
  * is bracketed by HIP events on the context's stream.  cpic_timing returns

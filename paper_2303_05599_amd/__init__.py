@@ -68,8 +68,9 @@ def lib():
             "cpic_current_step": [P, ctypes.POINTER(i64)], "cpic_num_samples": [P, ctypes.POINTER(i32)],
             "cpic_observables": [P, P, P, P, i32], "cpic_observables_full": [P, P, i32],
             "cpic_diagnostics": [P, P], "cpic_get_state": [P, i32, P, sz], "cpic_set_state": [P, i32, P, sz],
-            "cpic_save": [P, cp], "cpic_load": [P, cp], "cpic_set_launch": [P, i32, i32, i32, i32],
-            "cpic_set_timing": [P, i32],
+            "cpic_save": [P, cp], "cpic_load": [P, cp], "cpic_set_launch": [P, i32, i32, i32, i32, i32],
+            "cpic_set_timing": [P, i32], "cpic_set_push_lanes": [P, i32], "cpic_get_launch": [P, P],
+            "cpic_tune": [P, i32, P, sz],
             "cpic_timing": [P, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(i64), ctypes.POINTER(i64)],
             "cpic_batch_create": [i32, ctypes.POINTER(GlasmaParams), ctypes.POINTER(ParticleParams), P, pp],
             "cpic_batch_init_mv": [P], "cpic_batch_run": [P], "cpic_batch_sync": [P],
@@ -216,8 +217,22 @@ class Context:
     def load(self, path):
         self._chk(lib().cpic_load(self.h, str(path).encode()))
 
-    def set_launch(self, bx, by, xcd_remap=1, waves=1):
-        self._chk(lib().cpic_set_launch(self.h, bx, by, xcd_remap, waves))
+    def set_launch(self, bx, by, xcd_remap=1, waves=1, link_parallel=0):
+        self._chk(lib().cpic_set_launch(self.h, bx, by, xcd_remap, waves, link_parallel))
+
+    def set_push_lanes(self, lanes):
+        self._chk(lib().cpic_set_push_lanes(self.h, lanes))
+
+    def get_launch(self):
+        out = np.zeros(6, np.int32)
+        self._chk(lib().cpic_get_launch(self.h, _ptr(out)))
+        return dict(zip(("bx", "by", "xcd_remap", "waves", "push_lanes", "link_parallel"), out.tolist()))
+
+    def tune(self, reps=5):
+        """Time the launch candidates on the current state and keep the fastest; returns the report."""
+        buf = ctypes.create_string_buffer(16384)
+        self._chk(lib().cpic_tune(self.h, reps, buf, len(buf)))
+        return buf.value.decode()
 
     def set_timing(self, enable=True):
         self._chk(lib().cpic_set_timing(self.h, int(enable)))

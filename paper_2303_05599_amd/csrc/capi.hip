@@ -92,6 +92,7 @@ struct cpic_ctx {
     double* dout = nullptr;   // diagnostics results [8 + 2]
     int dcap = 0;
     LaunchCfg cfg{};
+    int tpp = 1;          // wavefronts per particle group in the push (1, 2, 4)
     bool initialised = false;
     // graphs: [parity] -> executable graph of kGraphSteps steps starting from buffer `parity`
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -217,16 +218,19 @@ extern "C" cpic_status cpic_create(const cpic_glasma_params* gp, const cpic_part
         c->sb.temp_bytes = std::max<size_t>(sort_temp_bytes((int)np, c->N), 16);
         if (e == hipSuccess) e = hipMalloc(&c->sb.temp, c->sb.temp_bytes);
     }
-    c->pblocks = c->np > 0 ? push_blocks((int)c->np) : 0;
+    // few particles: several wavefronts share each particle group so that the
+    // push still fills the 1024 SIMDs (tunable with cpic_tune)
+    c->tpp = c->np <= (1 << 18) ? 4 : (c->np <= (1 << 20) ? 2 : 1);
+    c->pblocks = c->np > 0 ? push_blocks((int)c->np, c->tpp) : 0;
     c->nslots = c->np > 0 ? num_slots(c->sc) : 0;
     if (e == hipSuccess && c->nslots > 0) {
-        e = hipMalloc(&c->partials, sizeof(double) * 4 * (size_t)c->pblocks * c->nslots);
+        e = hipMalloc(&c->partials, sizeof(double) * 4 * (size_t)push_blocks((int)c->np, 4) * c->nslots);
         if (e == hipSuccess) e = hipMalloc(&c->obs, sizeof(double) * 4 * c->nslots);
     }
     if (e == hipSuccess) e = hipMalloc(&c->d_step, sizeof(int));
     if (e == hipSuccess) e = hipMalloc(&c->d_err, sizeof(int));
     if (e == hipSuccess) e = hipMalloc(&c->d_fails, sizeof(int));
-    c->dcap = std::max((c->V + 255) / 256, std::max(c->pblocks, 1));
+    c->dcap = std::max((c->V + 255) / 256, std::max(c->np > 0 ? push_blocks((int)c->np, 1) : 0, 1));
     if (e == hipSuccess) e = hipMalloc(&c->dpart, sizeof(double) * 8 * c->dcap);
     if (e == hipSuccess) e = hipMalloc(&c->dout, sizeof(double) * 16);
     if (e == hipSuccess) e = hipMemsetAsync(c->d_step, 0, sizeof(int), c->st);
@@ -390,6 +394,7 @@ template <typename T> static cpic_status launch_one(cpic_ctx* c, int parity, boo
         pa.N = c->N;
         pa.np = (int)c->np;
         pa.is_static = c->is_static;
+        pa.tpp = c->tpp;
         pa.mhat = c->mhat;
         for (int k = 0; k < 3; k++) pa.q0eig[k] = c->q0eig[k];
         pa.sc = c->sc;
@@ -595,7 +600,7 @@ extern "C" cpic_status cpic_diagnostics(cpic_ctx* c, double out[10])
         e = c->prec == CPIC_FP64 ? launch_part_diag<double>(P<double>(c), (int)c->np, c->q2ref, c->q3ref, c->dpart, c->st)
                                  : launch_part_diag<float>(P<float>(c), (int)c->np, c->q2ref, c->q3ref, c->dpart, c->st);
         HIPCHK(c, e, "particle diagnostics");
-        HIPCHK(c, launch_reduce_rows(c->dpart, c->pblocks, 2, c->dout + 8, c->st), "reduce");
+        HIPCHK(c, launch_reduce_rows(c->dpart, push_blocks((int)c->np, 1), 2, c->dout + 8, c->st), "reduce");
         HIPCHK(c, hipStreamSynchronize(c->st), "diagnostics");
         HIPCHK(c, hipMemcpy(h + 8, c->dout + 8, sizeof(double) * 2, hipMemcpyDeviceToHost), "diagnostics");
     }
@@ -866,12 +871,19 @@ extern "C" cpic_status cpic_load(cpic_ctx* c, const char* path)
 }
 
 // ------------------------------------------------------------------ tuning and timing
-extern "C" cpic_status cpic_set_launch(cpic_ctx* c, int32_t bx, int32_t by, int32_t remap, int32_t waves)
+extern "C" cpic_status cpic_set_launch(cpic_ctx* c, int32_t bx, int32_t by, int32_t remap, int32_t waves,
+                                       int32_t link_parallel)
 {
     if (!c) return fail(nullptr, CPIC_E_INVALID, "cpic_set_launch: NULL context");
-    if (bx <= 0 || by <= 0 || bx * by > 256 || (bx * by) % 64 != 0)
+    if (link_parallel) {
+        if (bx <= 0 || by <= 0 || bx * by != 128 || bx % 32 != 0)
+            return fail(c, CPIC_E_INVALID, "cpic_set_launch: link-parallel tiles hold 128 sites, bx a multiple of 32");
+        if (waves < 1 || waves > 3) return fail(c, CPIC_E_INVALID, "cpic_set_launch: waves must be 1..3");
+    } else if (bx <= 0 || by <= 0 || bx * by > 256 || (bx * by) % 64 != 0) {
         return fail(c, CPIC_E_INVALID, "cpic_set_launch: need bx*by a multiple of 64 and <= 256");
+    }
     if (waves < 1 || waves > 4) return fail(c, CPIC_E_INVALID, "cpic_set_launch: waves must be 1..4");
+    c->cfg.split = link_parallel ? 1 : 0;
     c->cfg.bx = bx;
     c->cfg.by = by;
     c->cfg.xcd_remap = remap ? 1 : 0;
@@ -900,5 +912,127 @@ extern "C" cpic_status cpic_timing(cpic_ctx* c, double* field_ms, double* push_m
     if (push_ms) *push_ms = c->t_push;
     if (n_field) *n_field = c->k_field;
     if (n_push) *n_push = c->k_push;
+    return CPIC_OK;
+}
+
+// ------------------------------------------------------------------ launch tuner
+// Times candidate launch configurations in place on the current state: the
+// field kernel reads the current buffer and writes the free one (the step is
+// not advanced); the push runs on a saved copy of the particle records, which
+// is restored after every trial.  The fastest configuration is kept.
+template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::string& rep)
+{
+    const Fields<T> A = F<T>(c, c->cur), B = F<T>(c, c->cur ^ 1);
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0), "tune");
+    HIPCHK(c, hipEventCreate(&e1), "tune");
+    const int shapes[][2] = {{64, 4}, {64, 2}, {64, 1}, {128, 2}, {128, 1}, {256, 1}, {32, 8}, {32, 4}, {16, 16}};
+    LaunchCfg best = c->cfg;
+    double best_ms = 1e300;
+    char line[160];
+    std::vector<LaunchCfg> cands;
+    for (const auto& sh : shapes)
+        for (int waves = 1; waves <= 3; waves++)
+            for (int remap = 0; remap <= 1; remap++) cands.push_back(LaunchCfg{sh[0], sh[1], remap, waves, 0});
+    const int lshapes[][2] = {{128, 1}, {64, 2}, {32, 4}};
+    for (const auto& sh : lshapes)
+        for (int waves = 1; waves <= 3; waves++)
+            for (int remap = 0; remap <= 1; remap++) cands.push_back(LaunchCfg{sh[0], sh[1], remap, waves, 1});
+    for (const LaunchCfg& cfg : cands) {
+                HIPCHK(c, launch_field_step<T>(A, B, c->N, c->sc, c->d_step, cfg, c->st), "tune");  // warm-up
+                HIPCHK(c, hipEventRecord(e0, c->st), "tune");
+                for (int r = 0; r < reps; r++)
+                    HIPCHK(c, launch_field_step<T>(A, B, c->N, c->sc, c->d_step, cfg, c->st), "tune");
+                HIPCHK(c, hipEventRecord(e1, c->st), "tune");
+                HIPCHK(c, hipEventSynchronize(e1), "tune");
+                float ms = 0;
+                HIPCHK(c, hipEventElapsedTime(&ms, e0, e1), "tune");
+                const double per = ms / reps;
+                std::snprintf(line, sizeof line, "field %s bx=%d by=%d waves=%d remap=%d: %.2f us\n",
+                              cfg.split ? "link" : "site", cfg.bx, cfg.by, cfg.waves, cfg.xcd_remap, per * 1e3);
+                rep += line;
+                if (per < best_ms) { best_ms = per; best = cfg; }
+            }
+    c->cfg = best;
+    std::snprintf(line, sizeof line, "best field: %s bx=%d by=%d waves=%d remap=%d %.2f us\n",
+                  best.split ? "link" : "site", best.bx, best.by, best.waves, best.xcd_remap, best_ms * 1e3);
+    rep += line;
+    if (c->np > 0 && c->n >= c->sc.n_form && c->n < c->sc.n_max) {
+        const size_t rb = sizeof(T) * kPartReals * (size_t)c->np, cb = sizeof(int) * 2 * (size_t)c->np;
+        HIPCHK(c, hipMemcpyAsync(c->sb.r2, c->pr, rb, hipMemcpyDeviceToDevice, c->st), "tune");
+        HIPCHK(c, hipMemcpyAsync(c->sb.cell2, c->pcell, cb, hipMemcpyDeviceToDevice, c->st), "tune");
+        // the step's new momenta: run the field kernel once into the free buffer
+        HIPCHK(c, launch_field_step<T>(A, B, c->N, c->sc, c->d_step, c->cfg, c->st), "tune");
+        int best_tpp = c->tpp;
+        double best_p = 1e300;
+        for (int tpp : {1, 2, 4}) {
+            PushArgs pa{};
+            pa.N = c->N; pa.np = (int)c->np; pa.is_static = c->is_static; pa.tpp = tpp; pa.mhat = c->mhat;
+            for (int k = 0; k < 3; k++) pa.q0eig[k] = c->q0eig[k];
+            pa.sc = c->sc;
+            double tot = 0;
+            for (int r = 0; r <= reps; r++) {
+                HIPCHK(c, hipEventRecord(e0, c->st), "tune");
+                HIPCHK(c, launch_push<T>(A, B, P<T>(c), pa, c->d_step, c->partials, c->d_err, c->st), "tune");
+                HIPCHK(c, hipEventRecord(e1, c->st), "tune");
+                HIPCHK(c, hipMemcpyAsync(c->pr, c->sb.r2, rb, hipMemcpyDeviceToDevice, c->st), "tune");
+                HIPCHK(c, hipMemcpyAsync(c->pcell, c->sb.cell2, cb, hipMemcpyDeviceToDevice, c->st), "tune");
+                HIPCHK(c, hipEventSynchronize(e1), "tune");
+                float ms = 0;
+                HIPCHK(c, hipEventElapsedTime(&ms, e0, e1), "tune");
+                if (r > 0) tot += ms;
+            }
+            const double per = tot / reps;
+            std::snprintf(line, sizeof line, "push lanes=%d: %.2f us\n", tpp, per * 1e3);
+            rep += line;
+            if (per < best_p) { best_p = per; best_tpp = tpp; }
+        }
+        HIPCHK(c, hipStreamSynchronize(c->st), "tune");
+        int err = 0;
+        HIPCHK(c, hipMemcpy(c->d_err, &err, sizeof(int), hipMemcpyHostToDevice), "tune");
+        c->tpp = best_tpp;
+        c->pblocks = push_blocks((int)c->np, c->tpp);
+        std::snprintf(line, sizeof line, "best push: lanes=%d %.2f us\n", best_tpp, best_p * 1e3);
+        rep += line;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    drop_graphs(c);
+    return CPIC_OK;
+}
+
+extern "C" cpic_status cpic_tune(cpic_ctx* c, int32_t reps, char* report, size_t cap)
+{
+    if (!c) return fail(nullptr, CPIC_E_INVALID, "cpic_tune: NULL context");
+    if (!c->initialised) return fail(c, CPIC_E_INVALID, "cpic_tune: no state");
+    if (reps < 1) reps = 1;
+    if (c->timing) return fail(c, CPIC_E_INVALID, "cpic_tune: disable timing first");
+    HIPCHK(c, hipStreamSynchronize(c->st), "tune");
+    std::string rep;
+    cpic_status s = c->prec == CPIC_FP64 ? tune_t<double>(c, reps, rep) : tune_t<float>(c, reps, rep);
+    if (s) return s;
+    if (report && cap) {
+        std::strncpy(report, rep.c_str(), cap - 1);
+        report[cap - 1] = 0;
+    }
+    return CPIC_OK;
+}
+
+extern "C" cpic_status cpic_get_launch(const cpic_ctx* c, int32_t out[6])
+{
+    if (!c || !out) return CPIC_E_INVALID;
+    out[0] = c->cfg.bx; out[1] = c->cfg.by; out[2] = c->cfg.xcd_remap; out[3] = c->cfg.waves; out[4] = c->tpp;
+    out[5] = c->cfg.split;
+    return CPIC_OK;
+}
+
+extern "C" cpic_status cpic_set_push_lanes(cpic_ctx* c, int32_t lanes)
+{
+    if (!c) return fail(nullptr, CPIC_E_INVALID, "cpic_set_push_lanes: NULL context");
+    if (lanes != 1 && lanes != 2 && lanes != 4) return fail(c, CPIC_E_INVALID, "cpic_set_push_lanes: 1, 2 or 4");
+    HIPCHK(c, hipStreamSynchronize(c->st), "set push lanes");
+    c->tpp = lanes;
+    c->pblocks = c->np > 0 ? push_blocks((int)c->np, lanes) : 0;
+    drop_graphs(c);
     return CPIC_OK;
 }

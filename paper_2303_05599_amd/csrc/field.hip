@@ -162,6 +162,126 @@ __device__ __forceinline__ void field_step_body(const Fields<T>& in, const Field
     vA_st(vo, nb.s, kCompPi, PI);
 }
 
+// ---------------------------------------------------------------- link-parallel variant
+// One thread per link: half-wavefront h of a wavefront handles direction i = h
+// for the same 32 sites.  Thread (x, i) forms the two plaquettes of its link,
+// U_ij(x) and U_{i,-j}(x), the transported scalar phi->_i and phi<-_i, updates
+// E_i and drifts U_i; the pi force is the sum of both directions' scalar terms
+// (one lane exchange, lanes l and l ^ 32), and the i = 0 thread writes phi, pi.
+template <typename T>
+__device__ __forceinline__ void field_link_body(const Fields<T>& in, const Fields<T>& out, int N, int bx, int by,
+                                                int remap, const Schedule& sc, const int* __restrict__ d_step)
+{
+    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+    const int i = lane >> 5, j = 1 - i;
+    const int local = wave * 32 + (lane & 31);          // site within the block tile
+    const int ntx = (N + bx - 1) / bx, nty = (N + by - 1) / by, ntiles = ntx * nty;
+    int tile = blockIdx.x;
+    if (remap) {
+        const int per = (ntiles + 7) / 8;
+        tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    }
+    const int x = (tile % ntx) * bx + local % bx, y = (tile / ntx) * by + local / bx;
+    const bool live = tile < ntiles && x < N && y < N;
+    const int n = *d_step;
+    const double td = n * sc.dt, thd = (n + 0.5) * sc.dt;
+    const T t = T(td), inv_t = n > 0 ? T(1.0 / td) : T(0), dt = T(sc.dt);
+    const T eps_drift = T(sc.dt / thd), phi_drift = T(sc.dt * thd);
+    const bool kick = n > 0, reunit = is_reunit_step(sc, n);
+    const uint32_t V = (uint32_t)N * N;
+    const View<T> vi = make_view<T>(in.U, kRealsPerSite, V), vo = make_view<T>(out.U, kRealsPerSite, V);
+    constexpr uint32_t b = sizeof(T);
+    const int xs = live ? x : 0, ys = live ? y : 0;
+    auto site = [&](int dx, int dy) {
+        int xx = xs + dx, yy = ys + dy;
+        xx = xx < 0 ? xx + N : (xx >= N ? xx - N : xx);
+        yy = yy < 0 ? yy + N : (yy >= N ? yy - N : yy);
+        return (uint32_t)(yy * N + xx) * b;
+    };
+    // unit steps along i and j
+    const int ix = i == 0 ? 1 : 0, iy = 1 - ix, jx = iy, jy = ix;
+    const uint32_t s = site(0, 0);
+    // the link of direction d at byte offset o: components start at 18 d
+    auto link = [&](const View<T>& v, uint32_t o, int d) {
+        m3<T> m;
+#pragma unroll
+        for (int c = 0; c < 9; c++)
+            m.e[c] = {bld(v, o + (uint32_t)(18 * d) * v.cs, 2 * c), bld(v, o + (uint32_t)(18 * d) * v.cs, 2 * c + 1)};
+        return m;
+    };
+    const a8<T> PHI = vA(vi, s, kCompPhi);
+    a8<T> F = azero<T>(), lap = azero<T>();
+    if (kick) {
+        {   // U_ij(x) = U_i(x) U_j(x+i) [U_j(x) U_i(x+j)]^+
+            const m3<T> Pm = mul_adj(mul(link(vi, s, i), link(vi, site(ix, iy), j)),
+                                     mul(link(vi, s, j), link(vi, site(jx, jy), i)));
+            F = proj(Pm);
+        }
+        CPIC_PHASE();
+        {   // U_{i,-j}(x) = U_i(x) U_j(x+i-j)^+ [U_j(x-j)^+ U_i(x-j)]^+
+            const uint32_t smj = site(-jx, -jy);
+            const m3<T> Pm = mul_adj(mul_adj(link(vi, s, i), link(vi, site(ix - jx, iy - jy), j)),
+                                     adj_mul(link(vi, smj, j), link(vi, smj, i)));
+            const a8<T> p = proj(Pm);
+#pragma unroll
+            for (int a = 0; a < 8; a++) F.v[a] = -t * (F.v[a] + p.v[a]);
+        }
+        CPIC_PHASE();
+        {   // phi->_i and phi<-_i
+            const a8<T> fw = transport(link(vi, s, i), vA(vi, site(ix, iy), kCompPhi));
+            const uint32_t smi = site(-ix, -iy);
+            const a8<T> bw = transport_adj(link(vi, smi, i), vA(vi, smi, kCompPhi));
+            const a8<T> cm = icomm(fw, PHI);
+#pragma unroll
+            for (int a = 0; a < 8; a++) {
+                F.v[a] += inv_t * cm.v[a];
+                lap.v[a] = fw.v[a] + bw.v[a] - T(2) * PHI.v[a];
+            }
+        }
+    }
+    // pi force: add the other direction's scalar terms
+#pragma unroll
+    for (int a = 0; a < 8; a++) lap.v[a] += __shfl_xor(lap.v[a], 32, 64);
+    CPIC_PHASE();
+    a8<T> Ei = vA(vi, s, kCompE + 8 * i), PI = vA(vi, s, kCompPi);
+#pragma unroll
+    for (int a = 0; a < 8; a++) {
+        Ei.v[a] += dt * F.v[a];
+        PI.v[a] += dt * inv_t * lap.v[a];
+    }
+    m3<T> Ui = mul(expi(Ei, eps_drift), link(vi, s, i));
+    if (reunit) Ui = reunitarize(Ui);
+    if (!live) return;
+    vU_st(vo, s + (uint32_t)(18 * i) * vo.cs, 0, Ui);
+    vA_st(vo, s, kCompE + 8 * i, Ei);
+    if (i == 0) {
+        a8<T> ph = PHI;
+#pragma unroll
+        for (int a = 0; a < 8; a++) ph.v[a] += phi_drift * PI.v[a];
+        vA_st(vo, s, kCompPhi, ph);
+        vA_st(vo, s, kCompPi, PI);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void field_link_kernel(Fields<T> in, Fields<T> out, int N, int bx, int by, int remap,
+                                                         Schedule sc, const int* __restrict__ d_step)
+{
+    field_link_body(in, out, N, bx, by, remap, sc, d_step);
+}
+template <typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void field_link_kernel_w2(
+    Fields<T> in, Fields<T> out, int N, int bx, int by, int remap, Schedule sc, const int* __restrict__ d_step)
+{
+    field_link_body(in, out, N, bx, by, remap, sc, d_step);
+}
+template <typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void field_link_kernel_w3(
+    Fields<T> in, Fields<T> out, int N, int bx, int by, int remap, Schedule sc, const int* __restrict__ d_step)
+{
+    field_link_body(in, out, N, bx, by, remap, sc, d_step);
+}
+
 // Occupancy variants: W waves per SIMD requested from the register
 // allocator (W = 1: no request).  Chosen per lattice size and precision by
 // the launch tuner.
@@ -187,7 +307,20 @@ template <typename T>
 hipError_t launch_field_step(const Fields<T>& in, const Fields<T>& out, int N, const Schedule& sc,
                              const int* d_step, const LaunchCfg& cfg, hipStream_t st)
 {
-    if (cfg.bx <= 0 || cfg.by <= 0 || cfg.bx * cfg.by > 256 || cfg.waves < 1 || cfg.waves > 4) return hipErrorInvalidValue;
+    if (cfg.bx <= 0 || cfg.by <= 0 || cfg.waves < 1 || cfg.waves > 4) return hipErrorInvalidValue;
+    if (cfg.split) {
+        // 128 sites (256 link threads) per block
+        if (cfg.bx * cfg.by != 128 || cfg.bx % 32 != 0) return hipErrorInvalidValue;
+        const int ntiles = ((N + cfg.bx - 1) / cfg.bx) * ((N + cfg.by - 1) / cfg.by);
+        const dim3 g(cfg.xcd_remap ? 8 * ((ntiles + 7) / 8) : ntiles), blk(256);
+        switch (cfg.waves) {
+        case 2: hipLaunchKernelGGL(field_link_kernel_w2<T>, g, blk, 0, st, in, out, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
+        case 3: hipLaunchKernelGGL(field_link_kernel_w3<T>, g, blk, 0, st, in, out, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
+        default: hipLaunchKernelGGL(field_link_kernel<T>, g, blk, 0, st, in, out, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step);
+        }
+        return hipGetLastError();
+    }
+    if (cfg.bx * cfg.by > 256) return hipErrorInvalidValue;
     const int ntx = (N + cfg.bx - 1) / cfg.bx, nty = (N + cfg.by - 1) / cfg.by;
     const int ntiles = ntx * nty;
     const int grid = cfg.xcd_remap ? 8 * ((ntiles + 7) / 8) : ntiles;

@@ -64,6 +64,7 @@ struct LaunchCfg {
     int bx = 64, by = 4;  // field kernel block shape
     int xcd_remap = 1;    // map consecutive tiles onto one XCD
     int waves = 1;        // register-allocation occupancy target of the field kernel (1 = compiler default)
+    int split = 0;        // 1: one thread per link (bx * by = 128 sites per block)
 };
 
 // ---- field kernels (field.hip)
@@ -77,6 +78,7 @@ hipError_t launch_field_diag(const Fields<T>& f, int N, double dt, int n, double
 // ---- particle kernels (push.hip)
 struct PushArgs {
     int N, np, is_static;
+    int tpp;          // lanes per particle (1, 2, 4)
     double mhat;
     double q0eig[3];  // sorted eigenvalues of Q0 (charge renormalisation)
     Schedule sc;
@@ -85,7 +87,7 @@ struct PushArgs {
 template <typename T>
 hipError_t launch_push(const Fields<T>& A, const Fields<T>& B, const Parts<T>& P, const PushArgs& a,
                        const int* d_step, double* partials, int* err, hipStream_t st);
-int push_blocks(int np);
+int push_blocks(int np, int tpp);
 hipError_t launch_reduce_rows(const double* partials, int nrows, int ncols, double* out, hipStream_t st);
 // end of a step: on recording steps add the block partials of the step's slot
 // into obs[slot][4]; then advance the step counter

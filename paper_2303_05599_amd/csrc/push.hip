@@ -113,20 +113,40 @@ template <typename T> __device__ a8<T> renorm_charge(const a8<T>& Q, const doubl
 // Q . F for the six colour fields at site c, time t_n (Sec. III.B
 // interpolations), hat units:
 //   out[0..2] = Q.E_x, Q.E_y, Q.E_eta ; out[3..5] = Q.B_x, Q.B_y, Q.B_eta
-template <typename T>
+// Work split when several lanes share one particle (TPP lanes, role = lane
+// index within the particle): each role evaluates a subset of the six field
+// contractions and leaves the others zero; the lanes then add their results.
+//   TPP = 1: everything.
+//   TPP = 2: role 0 E_x, E_y, B_x, B_y; role 1 E_eta and the clover.
+//   TPP = 4: role 0 E_x and B_y; role 1 E_y and B_x; role 2 E_eta and clover
+//            leaves 0, 1; role 3 clover leaves 2, 3.
+template <int TPP> __device__ __forceinline__ bool does_E(int role, int i)
+{
+    return TPP == 1 || (TPP == 2 ? role == 0 : role == i);
+}
+template <int TPP> __device__ __forceinline__ bool does_Eeta(int role) { return TPP == 1 || (TPP == 2 ? role == 1 : role == 2); }
+template <int TPP> __device__ __forceinline__ bool does_Bt(int role, int i)   // i = 0: B_y (phi along x), 1: B_x
+{
+    return TPP == 1 || (TPP == 2 ? role == 0 : role == i);
+}
+template <int TPP> __device__ __forceinline__ int leaf_begin(int role) { return TPP == 1 ? 0 : (TPP == 2 ? (role == 1 ? 0 : 4) : (role == 2 ? 0 : (role == 3 ? 2 : 4))); }
+template <int TPP> __device__ __forceinline__ int leaf_end(int role) { return TPP == 1 ? 4 : (TPP == 2 ? 4 : (role == 2 ? 2 : 4)); }
+
+template <typename T, int TPP>
 __device__ __forceinline__ void forces_dot(const View<T>& A, const View<T>& B, int N, int cx, int cy, int n, T t,
-                                           bool electric_only, const a8<T>& Q, T* out)
+                                           bool electric_only, const a8<T>& Q, T* out, int role)
 {
     constexpr uint32_t b = sizeof(T);
     const int xm = wrap(cx - 1, N), xp = wrap(cx + 1, N), ym = wrap(cy - 1, N), yp = wrap(cy + 1, N);
     const uint32_t s = (uint32_t)(cy * N + cx) * b;
     const uint32_t s_xm = (uint32_t)(cy * N + xm) * b, s_xp = (uint32_t)(cy * N + xp) * b;
     const uint32_t s_ym = (uint32_t)(ym * N + cx) * b, s_yp = (uint32_t)(yp * N + cx) * b;
-    out[0] = out[1] = out[3] = out[4] = out[5] = T(0);
+    out[0] = out[1] = out[2] = out[3] = out[4] = out[5] = T(0);
     if (n > 0) {
         const T q = T(1) / (T(4) * t);
 #pragma unroll
         for (int i = 0; i < 2; i++) {
+            if (!does_E<TPP>(role, i)) continue;
             const uint32_t sb = i == 0 ? s_xm : s_ym;
             const uint32_t ce = kCompE + 8 * i;
             a8<T> here, back;
@@ -140,11 +160,13 @@ __device__ __forceinline__ void forces_dot(const View<T>& A, const View<T>& B, i
             out[i] = q * (dot(Q, here) + dot(qb, back));
             CPIC_PHASE();
         }
-        T e = 0;
+        if (does_Eeta<TPP>(role)) {
+            T e = 0;
 #pragma unroll
-        for (int a = 0; a < 8; a++) e += Q.v[a] * (bld(A, s, kCompPi + a) + bld(B, s, kCompPi + a));
-        out[2] = T(0.5) * e;
-    } else {
+            for (int a = 0; a < 8; a++) e += Q.v[a] * (bld(A, s, kCompPi + a) + bld(B, s, kCompPi + a));
+            out[2] = T(0.5) * e;
+        }
+    } else if (does_Eeta<TPP>(role)) {
         T e = 0;
 #pragma unroll
         for (int a = 0; a < 8; a++) e += Q.v[a] * bld(B, s, kCompPi + a);
@@ -156,17 +178,22 @@ __device__ __forceinline__ void forces_dot(const View<T>& A, const View<T>& B, i
         // B_x = -(phi->_y - phi<-_y)/(2t), B_y = +(phi->_x - phi<-_x)/(2t);
         // Q.(U X U^+) = (U^+ Q U).X and Q.(U^+ X U) = (U Q U^+).X
         const T q = T(1) / (T(2) * t);
-        T fy, by, fx, bx;
-        { const a8<T> w = transport_adj(vU(A, s, 1), Q);    fy = dot(w, vA(A, s_yp, kCompPhi)); }
-        CPIC_PHASE();
-        { const a8<T> w = transport(vU(A, s_ym, 1), Q);     by = dot(w, vA(A, s_ym, kCompPhi)); }
-        CPIC_PHASE();
-        { const a8<T> w = transport_adj(vU(A, s, 0), Q);    fx = dot(w, vA(A, s_xp, kCompPhi)); }
-        CPIC_PHASE();
-        { const a8<T> w = transport(vU(A, s_xm, 0), Q);     bx = dot(w, vA(A, s_xm, kCompPhi)); }
-        out[3] = -q * (fy - by);
-        out[4] = q * (fx - bx);
-        CPIC_PHASE();
+        if (does_Bt<TPP>(role, 1)) {
+            T fy, by;
+            { const a8<T> w = transport_adj(vU(A, s, 1), Q);    fy = dot(w, vA(A, s_yp, kCompPhi)); }
+            CPIC_PHASE();
+            { const a8<T> w = transport(vU(A, s_ym, 1), Q);     by = dot(w, vA(A, s_ym, kCompPhi)); }
+            out[3] = -q * (fy - by);
+            CPIC_PHASE();
+        }
+        if (does_Bt<TPP>(role, 0)) {
+            T fx, bx;
+            { const a8<T> w = transport_adj(vU(A, s, 0), Q);    fx = dot(w, vA(A, s_xp, kCompPhi)); }
+            CPIC_PHASE();
+            { const a8<T> w = transport(vU(A, s_xm, 0), Q);     bx = dot(w, vA(A, s_xm, kCompPhi)); }
+            out[4] = q * (fx - bx);
+            CPIC_PHASE();
+        }
     }
     // B_eta = -(1/4) Proj[U_12 + U_{2,-1} + U_{-1,-2} + U_{-2,1}] (clover, all
     // counter-clockwise).  Each leaf is a product of four links; leaf k,
@@ -188,7 +215,7 @@ __device__ __forceinline__ void forces_dot(const View<T>& A, const View<T>& B, i
     constexpr uint64_t kLeaf01 = L0 | L1 << 32, kLeaf23 = L2 | L3 << 32;
     T be = 0;
 #pragma unroll 1
-    for (int k = 0; k < 4; k++) {
+    for (int k = leaf_begin<TPP>(role); k < leaf_end<TPP>(role); k++) {
         const uint32_t code = (uint32_t)(((k < 2 ? kLeaf01 : kLeaf23) >> (32 * (k & 1))) & 0xFFFFFFu);
         m3<T> W;
 #pragma unroll
@@ -213,16 +240,27 @@ __device__ __forceinline__ int xcd_block(int nblocks)
     return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
 }
 
-template <typename T>
+// TPP wavefronts per group of 64 particles: a block of 256 threads (4 waves)
+// handles 256 / TPP particles; wave w works on particle group w / TPP in role
+// w % TPP, so every wave follows one uniform path.  The role-0 wave owns the
+// particle state: it rotates Q and publishes it in LDS; every role adds its
+// field contractions into LDS; the role-0 wave then takes the Euler step.
+template <typename T, int TPP>
 __global__ __launch_bounds__(256) void push_kernel(Fields<T> Af, Fields<T> Bf, Parts<T> P, PushArgs a,
                                                    const int* __restrict__ d_step, double* partials, int* err)
 {
     const int n = *d_step;
     if (n < a.sc.n_form || n >= a.sc.n_max) return;  // uniform over the grid
-    const int nblocks = (a.np + 255) / 256;
+    constexpr int PPB = 256 / TPP;                   // particles per block
+    constexpr int NG = 4 / TPP;                      // particle groups (of 64) per block
+    const int nblocks = (a.np + PPB - 1) / PPB;
     const int blk = xcd_block(nblocks);
     if (blk >= nblocks) return;                      // uniform over the block
-    const int p = blk * 256 + threadIdx.x;
+    const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+    const int role = wave % TPP, grp = wave / TPP;
+    const int p = blk * PPB + grp * 64 + lane;
+    __shared__ T shQ[NG][8][64];
+    __shared__ T shF[4][6][64];
     const int N = a.N, np = a.np;
     const uint32_t V = (uint32_t)N * N;
     const View<T> A = make_view<T>(Af.U, kRealsPerSite, V), B = make_view<T>(Bf.U, kRealsPerSite, V);
@@ -231,52 +269,87 @@ __global__ __launch_bounds__(256) void push_kernel(Fields<T> Af, Fields<T> Bf, P
     const T dt = T(a.sc.dt), t = T(n * a.sc.dt);
     const int record_slot = is_record_step(a.sc, n) ? record_slot_of(a.sc, n) : -1;
     const bool renorm = is_reunit_step(a.sc, n);
-    double obs[4] = {0, 0, 0, 0};
-    if (p < np) {
-        const uint32_t po = (uint32_t)p * sizeof(T), pi = (uint32_t)p * sizeof(int);
-        a8<T> Q;
+    const bool live = p < np;
+    const uint32_t po = (uint32_t)(live ? p : 0) * sizeof(T), pi = (uint32_t)(live ? p : 0) * sizeof(int);
+    a8<T> Q;
+    int nx = 0, ny = 0;
+    T x = 0, y = 0;
+    if (a.is_static) {
+        nx = bld_i(C, pi, 0);
+        ny = bld_i(C, pi, 1);
+    } else {
+        x = bld(R, po, PX_);
+        y = bld(R, po, PY_);
+        nx = (int)floor(x + T(0.5));
+        ny = (int)floor(y + T(0.5));
+        nx = nx >= N ? nx - N : nx;
+        ny = ny >= N ? ny - N : ny;
+    }
+    if (role == 0) {
 #pragma unroll
         for (int q = 0; q < 8; q++) Q.v[q] = bld(R, po, PQ0 + q);
+        if (!a.is_static && live && n > a.sc.n_form) {
+            int cx = bld_i(C, pi, 0), cy = bld_i(C, pi, 1);
+            int d[2] = {nx - cx, ny - cy};
+#pragma unroll
+            for (int ax = 0; ax < 2; ax++) {
+                int dd = d[ax];
+                if (dd > N / 2) dd -= N;
+                if (dd < -N / 2) dd += N;
+                if (dd == 1) {
+                    Q = rotate(vU(A, (uint32_t)(cy * N + cx) * (uint32_t)sizeof(T), ax), Q);
+                } else if (dd == -1) {
+                    const int cb = ax == 0 ? cy * N + wrap(cx - 1, N) : wrap(cy - 1, N) * N + cx;
+                    Q = transport(vU(A, (uint32_t)cb * (uint32_t)sizeof(T), ax), Q);   // U Q U^+
+                } else if (dd != 0) {
+                    atomicAdd(err, 1);
+                }
+                if (ax == 0) cx = nx; else cy = ny;
+            }
+            const T deta = bld(R, po, PDETA);
+            if (deta != T(0)) Q = rotate(expi(vA(A, (uint32_t)(ny * N + nx) * (uint32_t)sizeof(T), kCompPhi), deta), Q);
+        }
+        if (!a.is_static && renorm && live) Q = renorm_charge(Q, a.q0eig);
+        if (TPP > 1) {
+#pragma unroll
+            for (int q = 0; q < 8; q++) shQ[grp][q][lane] = Q.v[q];
+        }
+    }
+    if (TPP > 1) {
+        __syncthreads();
+        if (role != 0) {
+#pragma unroll
+            for (int q = 0; q < 8; q++) Q.v[q] = shQ[grp][q][lane];
+        }
+    }
+    CPIC_PHASE();
+    T f[6];
+    if (live) forces_dot<T, TPP>(A, B, N, nx, ny, n, t, a.is_static != 0, Q, f, role);
+    else f[0] = f[1] = f[2] = f[3] = f[4] = f[5] = T(0);
+    if (TPP > 1) {
+#pragma unroll
+        for (int k = 0; k < 6; k++) shF[wave][k][lane] = f[k];
+        __syncthreads();
+        if (role == 0) {
+#pragma unroll
+            for (int k = 0; k < 6; k++) {
+                T acc = shF[wave][k][lane];
+#pragma unroll
+                for (int r = 1; r < TPP; r++) acc += shF[wave + r][k][lane];
+                f[k] = acc;
+            }
+        }
+    }
+    double obs[4] = {0, 0, 0, 0};
+    if (role == 0 && live) {
         T px = bld(R, po, PPX), py = bld(R, po, PPY), pe = bld(R, po, PPETA);
         T eta = bld(R, po, PETA_);
-        T f[6];
         if (a.is_static) {
-            const int cx = bld_i(C, pi, 0), cy = bld_i(C, pi, 1);
-            forces_dot(A, B, N, cx, cy, n, t, true, Q, f);
             px += dt * f[0];
             py += dt * f[1];
             pe += dt * f[2];  // p^z of the static branch
             bst(R, po, PPX, px); bst(R, po, PPY, py); bst(R, po, PPETA, pe);
         } else {
-            const T x = bld(R, po, PX_), y = bld(R, po, PY_);
-            int nx = (int)floor(x + T(0.5)), ny = (int)floor(y + T(0.5));
-            nx = nx >= N ? nx - N : nx;
-            ny = ny >= N ? ny - N : ny;
-            if (n > a.sc.n_form) {
-                int cx = bld_i(C, pi, 0), cy = bld_i(C, pi, 1);
-                int d[2] = {nx - cx, ny - cy};
-#pragma unroll
-                for (int ax = 0; ax < 2; ax++) {
-                    int dd = d[ax];
-                    if (dd > N / 2) dd -= N;
-                    if (dd < -N / 2) dd += N;
-                    if (dd == 1) {
-                        Q = rotate(vU(A, (uint32_t)(cy * N + cx) * (uint32_t)sizeof(T), ax), Q);
-                    } else if (dd == -1) {
-                        const int cb = ax == 0 ? cy * N + wrap(cx - 1, N) : wrap(cy - 1, N) * N + cx;
-                        Q = transport(vU(A, (uint32_t)cb * (uint32_t)sizeof(T), ax), Q);   // U Q U^+
-                    } else if (dd != 0) {
-                        atomicAdd(err, 1);
-                    }
-                    if (ax == 0) cx = nx; else cy = ny;
-                }
-                const T deta = bld(R, po, PDETA);
-                if (deta != T(0))
-                    Q = rotate(expi(vA(A, (uint32_t)(ny * N + nx) * (uint32_t)sizeof(T), kCompPhi), deta), Q);
-            }
-            if (renorm) Q = renorm_charge(Q, a.q0eig);
-            CPIC_PHASE();
-            forces_dot(A, B, N, nx, ny, n, t, false, Q, f);
             const T e1 = f[0], e2 = f[1], ee = f[2], b1 = f[3], b2 = f[4], be = f[5];
             const T mh = T(a.mhat);
             const T ptau = sqrt(px * px + py * py + (t * pe) * (t * pe) + mh * mh);
@@ -294,10 +367,10 @@ __global__ __launch_bounds__(256) void push_kernel(Fields<T> Af, Fields<T> Bf, P
             bst(R, po, PPX, px); bst(R, po, PPY, py); bst(R, po, PPETA, pe); bst(R, po, PDETA, deta);
             bst_i(C, pi, 0, nx);
             bst_i(C, pi, 1, ny);
-        }
-        if (n > a.sc.n_form || renorm) {
+            if (n > a.sc.n_form || renorm) {
 #pragma unroll
-            for (int q = 0; q < 8; q++) bst(R, po, PQ0 + q, Q.v[q]);
+                for (int q = 0; q < 8; q++) bst(R, po, PQ0 + q, Q.v[q]);
+            }
         }
         if (record_slot >= 0) {
             const T ux0 = bld(R, po, PUX0), uy0 = bld(R, po, PUY0), pt0 = bld(R, po, PPT0);
@@ -323,15 +396,20 @@ __global__ __launch_bounds__(256) void push_kernel(Fields<T> Af, Fields<T> Bf, P
         block_reduce_store<4>(obs, 0u, partials + ((size_t)record_slot * nblocks + blk) * 4);
 }
 
-int push_blocks(int np) { return (np + 255) / 256; }
+int push_blocks(int np, int tpp) { const int ppb = 256 / (tpp > 0 ? tpp : 1); return (np + ppb - 1) / ppb; }
 
 template <typename T>
 hipError_t launch_push(const Fields<T>& A, const Fields<T>& B, const Parts<T>& P, const PushArgs& a,
                        const int* d_step, double* partials, int* err, hipStream_t st)
 {
     if (a.np <= 0) return hipSuccess;
-    const int nb = push_blocks(a.np);
-    hipLaunchKernelGGL(push_kernel<T>, dim3(8 * ((nb + 7) / 8)), dim3(256), 0, st, A, B, P, a, d_step, partials, err);
+    const int nb = push_blocks(a.np, a.tpp);
+    const dim3 g(8 * ((nb + 7) / 8)), b(256);
+    switch (a.tpp) {
+    case 2: hipLaunchKernelGGL((push_kernel<T, 2>), g, b, 0, st, A, B, P, a, d_step, partials, err); break;
+    case 4: hipLaunchKernelGGL((push_kernel<T, 4>), g, b, 0, st, A, B, P, a, d_step, partials, err); break;
+    default: hipLaunchKernelGGL((push_kernel<T, 1>), g, b, 0, st, A, B, P, a, d_step, partials, err);
+    }
     return hipGetLastError();
 }
 
@@ -414,7 +492,7 @@ __global__ __launch_bounds__(256) void part_diag_kernel(Parts<T> P, int np, doub
 template <typename T>
 hipError_t launch_part_diag(const Parts<T>& P, int np, double q2, double q3, double* partials, hipStream_t st)
 {
-    hipLaunchKernelGGL(part_diag_kernel<T>, dim3(push_blocks(np)), dim3(256), 0, st, P, np, q2, q3, partials);
+    hipLaunchKernelGGL(part_diag_kernel<T>, dim3(push_blocks(np, 1)), dim3(256), 0, st, P, np, q2, q3, partials);
     return hipGetLastError();
 }
 

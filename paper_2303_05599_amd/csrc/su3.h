@@ -27,14 +27,55 @@ template <typename T> struct a8 {
 template <typename T> constexpr T kInvSqrt3 = T(0.57735026918962576451);
 template <typename T> constexpr T kSqrt3Half = T(0.86602540378443864676);
 
+// fused multiply-add in the operand type (host and device)
+CPIC_HD float fmaT(float a, float b, float c) { return fmaf(a, b, c); }
+CPIC_HD double fmaT(double a, double b, double c) { return ::fma(a, b, c); }
+
 // ---------------------------------------------------------------- complex
-template <typename T> CPIC_HD cx<T> cmul(cx<T> a, cx<T> b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+template <typename T> CPIC_HD cx<T> cmul(cx<T> a, cx<T> b)
+{
+    return {fmaT(a.re, b.re, -a.im * b.im), fmaT(a.re, b.im, a.im * b.re)};
+}
 // a * conj(b)
-template <typename T> CPIC_HD cx<T> cmulc(cx<T> a, cx<T> b) { return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im}; }
+template <typename T> CPIC_HD cx<T> cmulc(cx<T> a, cx<T> b)
+{
+    return {fmaT(a.re, b.re, a.im * b.im), fmaT(a.im, b.re, -a.re * b.im)};
+}
 // conj(a) * b
-template <typename T> CPIC_HD cx<T> ccmul(cx<T> a, cx<T> b) { return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re}; }
+template <typename T> CPIC_HD cx<T> ccmul(cx<T> a, cx<T> b)
+{
+    return {fmaT(a.re, b.re, a.im * b.im), fmaT(a.re, b.im, -a.im * b.re)};
+}
 
 // ---------------------------------------------------------------- 3x3
+// Complex multiply-accumulate chains written as explicit fused multiply-adds
+// (four per complex product): the compiler does not contract a*b - c*d + acc
+// into two FMAs on its own.
+// acc += a * b
+template <typename T> CPIC_HD void cmac(cx<T>& acc, cx<T> a, cx<T> b)
+{
+    acc.re = fmaT(a.re, b.re, acc.re);
+    acc.re = fmaT(-a.im, b.im, acc.re);
+    acc.im = fmaT(a.re, b.im, acc.im);
+    acc.im = fmaT(a.im, b.re, acc.im);
+}
+// acc += a * conj(b)
+template <typename T> CPIC_HD void cmacc(cx<T>& acc, cx<T> a, cx<T> b)
+{
+    acc.re = fmaT(a.re, b.re, acc.re);
+    acc.re = fmaT(a.im, b.im, acc.re);
+    acc.im = fmaT(a.im, b.re, acc.im);
+    acc.im = fmaT(-a.re, b.im, acc.im);
+}
+// acc += conj(a) * b
+template <typename T> CPIC_HD void ccmac(cx<T>& acc, cx<T> a, cx<T> b)
+{
+    acc.re = fmaT(a.re, b.re, acc.re);
+    acc.re = fmaT(a.im, b.im, acc.re);
+    acc.im = fmaT(a.re, b.im, acc.im);
+    acc.im = fmaT(-a.im, b.re, acc.im);
+}
+
 // C = A B
 template <typename T> CPIC_HD m3<T> mul(const m3<T>& A, const m3<T>& B)
 {
@@ -43,14 +84,10 @@ template <typename T> CPIC_HD m3<T> mul(const m3<T>& A, const m3<T>& B)
     for (int i = 0; i < 3; i++)
 #pragma unroll
         for (int j = 0; j < 3; j++) {
-            T re = 0, im = 0;
-#pragma unroll
-            for (int k = 0; k < 3; k++) {
-                cx<T> a = A.e[3 * i + k], b = B.e[3 * k + j];
-                re += a.re * b.re - a.im * b.im;
-                im += a.re * b.im + a.im * b.re;
-            }
-            C.e[3 * i + j] = {re, im};
+            cx<T> acc = cmul(A.e[3 * i], B.e[j]);
+            cmac(acc, A.e[3 * i + 1], B.e[3 + j]);
+            cmac(acc, A.e[3 * i + 2], B.e[6 + j]);
+            C.e[3 * i + j] = acc;
         }
     return C;
 }
@@ -62,14 +99,10 @@ template <typename T> CPIC_HD m3<T> mul_adj(const m3<T>& A, const m3<T>& B)
     for (int i = 0; i < 3; i++)
 #pragma unroll
         for (int j = 0; j < 3; j++) {
-            T re = 0, im = 0;
-#pragma unroll
-            for (int k = 0; k < 3; k++) {
-                cx<T> a = A.e[3 * i + k], b = B.e[3 * j + k];
-                re += a.re * b.re + a.im * b.im;
-                im += a.im * b.re - a.re * b.im;
-            }
-            C.e[3 * i + j] = {re, im};
+            cx<T> acc = cmulc(A.e[3 * i], B.e[3 * j]);
+            cmacc(acc, A.e[3 * i + 1], B.e[3 * j + 1]);
+            cmacc(acc, A.e[3 * i + 2], B.e[3 * j + 2]);
+            C.e[3 * i + j] = acc;
         }
     return C;
 }
@@ -81,14 +114,10 @@ template <typename T> CPIC_HD m3<T> adj_mul(const m3<T>& A, const m3<T>& B)
     for (int i = 0; i < 3; i++)
 #pragma unroll
         for (int j = 0; j < 3; j++) {
-            T re = 0, im = 0;
-#pragma unroll
-            for (int k = 0; k < 3; k++) {
-                cx<T> a = A.e[3 * k + i], b = B.e[3 * k + j];
-                re += a.re * b.re + a.im * b.im;
-                im += a.re * b.im - a.im * b.re;
-            }
-            C.e[3 * i + j] = {re, im};
+            cx<T> acc = ccmul(A.e[i], B.e[j]);
+            ccmac(acc, A.e[3 + i], B.e[3 + j]);
+            ccmac(acc, A.e[6 + i], B.e[6 + j]);
+            C.e[3 * i + j] = acc;
         }
     return C;
 }
@@ -121,13 +150,13 @@ template <typename T> CPIC_HD a8<T> azero()
 template <typename T> CPIC_HD void axpy(a8<T>& y, T s, const a8<T>& x)
 {
 #pragma unroll
-    for (int a = 0; a < 8; a++) y.v[a] += s * x.v[a];
+    for (int a = 0; a < 8; a++) y.v[a] = fmaT(s, x.v[a], y.v[a]);
 }
 template <typename T> CPIC_HD T dot(const a8<T>& x, const a8<T>& y)
 {
-    T s = 0;
+    T s = x.v[0] * y.v[0];
 #pragma unroll
-    for (int a = 0; a < 8; a++) s += x.v[a] * y.v[a];
+    for (int a = 1; a < 8; a++) s = fmaT(x.v[a], y.v[a], s);
     return s;
 }
 
@@ -194,14 +223,10 @@ template <typename T> CPIC_HD a8<T> transport(const m3<T>& U, const a8<T>& x)
 #pragma unroll
     for (int q = 0; q < 6; q++) {
         const int i = ii[q], j = jj[q];
-        T re = 0, im = 0;
-#pragma unroll
-        for (int k = 0; k < 3; k++) {
-            cx<T> a = A.e[3 * i + k], b = U.e[3 * j + k];
-            re += a.re * b.re + a.im * b.im;
-            im += a.im * b.re - a.re * b.im;
-        }
-        m[q] = {re, im};
+        cx<T> acc = cmulc(A.e[3 * i], U.e[3 * j]);
+        cmacc(acc, A.e[3 * i + 1], U.e[3 * j + 1]);
+        cmacc(acc, A.e[3 * i + 2], U.e[3 * j + 2]);
+        m[q] = acc;
     }
     return herm_comp(m[0], m[1], m[2], m[3], m[4], m[5]);
 }
@@ -214,14 +239,10 @@ template <typename T> CPIC_HD a8<T> transport_adj(const m3<T>& U, const a8<T>& x
 #pragma unroll
     for (int q = 0; q < 6; q++) {
         const int i = ii[q], j = jj[q];
-        T re = 0, im = 0;
-#pragma unroll
-        for (int k = 0; k < 3; k++) {
-            cx<T> a = U.e[3 * k + i], b = A.e[3 * k + j];
-            re += a.re * b.re + a.im * b.im;
-            im += a.re * b.im - a.im * b.re;
-        }
-        m[q] = {re, im};
+        cx<T> acc = ccmul(U.e[i], A.e[j]);
+        ccmac(acc, U.e[3 + i], A.e[3 + j]);
+        ccmac(acc, U.e[6 + i], A.e[6 + j]);
+        m[q] = acc;
     }
     return herm_comp(m[0], m[1], m[2], m[3], m[4], m[5]);
 }
@@ -231,12 +252,12 @@ template <typename T> CPIC_HD a8<T> icomm(const a8<T>& A, const a8<T>& B)
 {
     a8<T> C = azero<T>();
     // each triple (a,b,c,f): C^c -= f (A^a B^b - A^b B^a), and cyclic
-#define CPIC_F(a, b, c, f)                                          \
-    {                                                               \
-        const T ff = (f);                                           \
-        C.v[c] -= ff * (A.v[a] * B.v[b] - A.v[b] * B.v[a]);         \
-        C.v[a] -= ff * (A.v[b] * B.v[c] - A.v[c] * B.v[b]);         \
-        C.v[b] -= ff * (A.v[c] * B.v[a] - A.v[a] * B.v[c]);         \
+#define CPIC_F(a, b, c, f)                                                          \
+    {                                                                               \
+        const T ff = (f);                                                           \
+        C.v[c] = fmaT(-ff, fmaT(A.v[a], B.v[b], -A.v[b] * B.v[a]), C.v[c]);           \
+        C.v[a] = fmaT(-ff, fmaT(A.v[b], B.v[c], -A.v[c] * B.v[b]), C.v[a]);           \
+        C.v[b] = fmaT(-ff, fmaT(A.v[c], B.v[a], -A.v[a] * B.v[c]), C.v[b]);           \
     }
     CPIC_F(0, 1, 2, T(1));
     CPIC_F(0, 3, 6, T(0.5));
@@ -283,23 +304,23 @@ template <typename T> CPIC_HD m3<T> expi(const a8<T>& x, T eps)
     constexpr int K = sizeof(T) == 8 ? 28 : 16;
 #pragma unroll
     for (int k = 1; k <= K; k++) {
-        T an = c0 * dk, bn = ak + c1 * dk, dn = bk;
+        T an = c0 * dk, bn = fmaT(c1, dk, ak), dn = bk;
         ak = an; bk = bn; dk = dn;
         fac = fac / T(k);
         const int ph = k & 3;  // i^k = 1, i, -1, -i
         const T sg = (ph < 2) ? fac : -fac;
         if (ph & 1) {
-            f0i += sg * ak; f1i += sg * bk; f2i += sg * dk;
+            f0i = fmaT(sg, ak, f0i); f1i = fmaT(sg, bk, f1i); f2i = fmaT(sg, dk, f2i);
         } else {
-            f0r += sg * ak; f1r += sg * bk; f2r += sg * dk;
+            f0r = fmaT(sg, ak, f0r); f1r = fmaT(sg, bk, f1r); f2r = fmaT(sg, dk, f2r);
         }
     }
     m3<T> R;
 #pragma unroll
     for (int q = 0; q < 9; q++) {
         cx<T> yv = Y.e[q], y2 = Y2.e[q];
-        R.e[q] = {f1r * yv.re - f1i * yv.im + f2r * y2.re - f2i * y2.im,
-                  f1r * yv.im + f1i * yv.re + f2r * y2.im + f2i * y2.re};
+        R.e[q] = {fmaT(f1r, yv.re, fmaT(-f1i, yv.im, fmaT(f2r, y2.re, -f2i * y2.im))),
+                  fmaT(f1r, yv.im, fmaT(f1i, yv.re, fmaT(f2r, y2.im, f2i * y2.re)))};
     }
     R.e[0].re += f0r; R.e[0].im += f0i;
     R.e[4].re += f0r; R.e[4].im += f0i;

@@ -55,13 +55,20 @@ def gpu():
     yield
 
 
-@pytest.mark.parametrize("N,n0", [(32, 3), (96, 0), (48, 1)])
-def test_field_leapfrog_fp64_random_state(N, n0):
-    """50 fused kick+drift steps from a random state; N = 96 and 48 leave ragged tiles."""
-    print(f"case N={N} n0={n0}", flush=True)
+LAUNCHES = {"site64x4": (64, 4, 1, 1, 0), "site256x1w2": (256, 1, 0, 2, 0), "link128x1": (128, 1, 1, 1, 1),
+            "link32x4w2": (32, 4, 0, 2, 1)}
+
+
+@pytest.mark.parametrize("N,n0,launch", [(32, 3, "site64x4"), (96, 0, "site64x4"), (48, 1, "site64x4"),
+                                         (96, 2, "link128x1"), (48, 1, "link32x4w2"), (32, 5, "site256x1w2")])
+def test_field_leapfrog_fp64_random_state(N, n0, launch):
+    """50 fused kick+drift steps from a random state; N = 96 and 48 leave ragged tiles;
+    site-parallel and link-parallel decompositions."""
+    print(f"case N={N} n0={n0} launch={launch}", flush=True)
     steps = 50
     st = inputs.random_state(N, 100 + N, eps_link=0.4)
     ctx = cp.Context(glasma(N, steps=n0 + steps + 1))
+    ctx.set_launch(*LAUNCHES[launch])
     ctx.load_state(st, n=n0)
     ctx.step(steps)
     got = ctx.state()
@@ -102,10 +109,11 @@ def test_particles_init_parity():
     assert rel_err(got, ref) < 1e-13
 
 
-@pytest.mark.parametrize("is_static", [False, True])
-def test_particle_push_fp64_random_state(is_static):
-    """Rotation on cell changes (both axes), rapidity Wilson line, E/B interpolation, Euler step."""
-    print(f"case push static={is_static}", flush=True)
+@pytest.mark.parametrize("is_static,lanes", [(False, 1), (False, 2), (False, 4), (True, 1), (True, 4)])
+def test_particle_push_fp64_random_state(is_static, lanes):
+    """Rotation on cell changes (both axes), rapidity Wilson line, E/B interpolation, Euler step,
+    with 1, 2 or 4 wavefronts sharing each particle group."""
+    print(f"case push static={is_static} lanes={lanes}", flush=True)
     N, L, n0, n_form, steps = 32, 6.0, 5, 3, 50
     a = oracle.lattice_spacing(L, N)
     mhat = math.inf if is_static else 0.3
@@ -114,6 +122,7 @@ def test_particle_push_fp64_random_state(is_static):
     ctx = cp.Context(glasma(N, L, steps=n0 + steps),       # the last step is a sampling step
                      particle_params(3000, math.inf if is_static else mhat / a, N, L, n_form))
     ctx.load_state(st, n=n0, particles=P)
+    ctx.set_push_lanes(lanes)
     ctx.step(steps)
     ctx.sync()
     got = ctx.get_state(cp.STATE_PARTICLES)
@@ -318,3 +327,26 @@ def test_fp32_dynamic_particles_with_charge_renormalisation():
           f"Casimir drift {d[8]:.1e} {d[9]:.1e}")
     assert q_err < 1e-3 and p_err < 1e-3
     assert d[8] < 1e-4 and d[9] < 1e-4
+
+
+def test_tuner_leaves_state_unchanged():
+    N, L = 64, 0.75
+    g = glasma(N, L, n_sheets=2, steps=64, seed=9)
+    p = dict(n=5000, mass_GeV=1.27, pT_min_GeV=1.0, pT_max_GeV=1.0, azimuth_uniform=1, tau_form_fm=0.0, rep=0, seed=10)
+    a_ctx, b_ctx = cp.Context(g, p), cp.Context(g, p)
+    for c in (a_ctx, b_ctx):
+        c.init_mv()
+        c.step(20)
+    before = a_ctx.state()
+    rep = a_ctx.tune(2)
+    assert "best field" in rep and "best push" in rep
+    after = a_ctx.state()
+    for k in before:
+        assert np.array_equal(before[k], after[k]), k
+    assert np.array_equal(a_ctx.get_state(cp.STATE_PARTICLES), b_ctx.get_state(cp.STATE_PARTICLES))
+    a_ctx.step(20)
+    b_ctx.step(20)
+    # a different launch shape only reorders nothing: results agree to rounding (bitwise for the field kernel)
+    for k in ("U", "phi", "E", "pi"):
+        assert np.array_equal(a_ctx.state()[k], b_ctx.state()[k]), k
+    assert rel_err(a_ctx.get_state(cp.STATE_PARTICLES), b_ctx.get_state(cp.STATE_PARTICLES)) < 1e-13

@@ -26,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+HBARC_GEV_FM = 0.1973269804
 FP64_VALU_TFLOPS = 78.6
 BYTES_PER_SITE = {"f64": 68 * 2 * 8, "f32": 68 * 2 * 4}     # read + write of U1 U2 phi E1 E2 pi
 PART_REALS_RW = 2 * 18 + 2 * 2                               # particle record read+write (reals + 2 int cells)
@@ -75,6 +76,85 @@ def run_event(precision, steps, warmup):
                 tune_report=tune_report)
 
 
+def batch_events(precision, n_events=64, seed=5):
+    """Uneven batch: N uniform over {128, 256, 384, 512}, L = 6 fm (dtau = a/8, 2N steps to
+    1.5 fm/c), g2mu ~ U[1.5, 2.5] GeV, m = 0.1 g2mu, Lambda = 10 GeV, 50 sheets; 1e4..1e5
+    beauty quarks (m = 4.18 GeV, formed at 1/(2m)) with p_T ~ U[0, 5] GeV; event e seeded 1000 + e."""
+    rng = np.random.default_rng(seed)
+    Ns = rng.choice([128, 256, 384, 512], n_events)
+    g2mu = rng.uniform(1.5, 2.5, n_events)
+    npart = rng.integers(10_000, 100_001, n_events)
+    tau_form = HBARC_GEV_FM / (2 * 4.18)
+    gl = [dict(N=int(Ns[e]), L_fm=6.0, g2mu_GeV=float(g2mu[e]), m_ir_GeV=0.1 * float(g2mu[e]), uv_GeV=10.0,
+               n_sheets=50, dtau_over_a=0.125, tau_max_fm=1.5, seed=1000 + e, precision=precision,
+               reunit_every=16, record_every=8) for e in range(n_events)]
+    pl = [dict(n=int(npart[e]), mass_GeV=4.18, pT_min_GeV=0.0, pT_max_GeV=5.0, azimuth_uniform=1,
+               tau_form_fm=tau_form, rep=0, seed=1000 + e) for e in range(n_events)]
+    return gl, pl
+
+
+def run_batch(fp64_launch):
+    """FP32 events batched (one launch per kernel and step over all events, graph-replayed)
+    against FP64 and FP32 events run one at a time; initial conditions untimed."""
+    import torch
+    import paper_2303_05599_amd as cp
+    gl32, pl = batch_events(cp.FP32)
+    site_updates = sum(g["N"] ** 2 * 2 * g["N"] for g in gl32)
+    pushes = 0
+    b = cp.Batch(gl32, pl)
+    t0 = time.perf_counter()
+    b.init_mv()
+    t_ic = time.perf_counter() - t0
+    tune = b.tune(5)
+    b.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run()
+    b.sync()
+    t_batch = time.perf_counter() - t0
+    obs32 = [b.observables(e) for e in range(len(gl32))]
+    launch = b.get_launch()
+    b.close()
+
+    def plain(precision, launch=None):
+        gl, _ = batch_events(precision)
+        total, last = 0.0, []
+        for g, p in zip(gl, pl):
+            ctx = cp.Context(g, p)
+            ctx.init_mv()
+            if launch:
+                ctx.set_launch(launch["bx"], launch["by"], launch["xcd_remap"], launch["waves"],
+                               launch["link_parallel"])
+            ctx.sync()
+            t0 = time.perf_counter()
+            ctx.evolve(1e9)
+            ctx.sync()
+            total += time.perf_counter() - t0
+            last.append(ctx.observables()[-1])
+            ctx.close()
+        return total, last
+    t64, obs64 = plain(cp.FP64, fp64_launch)
+    t32p, _ = plain(cp.FP32)
+    rel_pT = [abs(o32[-1, 1] / o64[1] - 1) for o32, o64 in zip(obs32, obs64)]
+    rel_pL = [abs(o32[-1, 2] / o64[2] - 1) for o32, o64 in zip(obs32, obs64)]
+    for g, p in zip(gl32, pl):
+        a_fm = g["L_fm"] / g["N"]
+        n_form = math.ceil(p["tau_form_fm"] / (0.125 * a_fm) - 1e-9)
+        pushes += p["n"] * (2 * g["N"] - n_form)
+    n = len(gl32)
+    return {"workload": f"{n} MV events, N in {{128,256,384,512}}, L=6 fm, 2N steps, 50 sheets, "
+                        "1e4..1e5 beauty quarks each (pT 0..5 GeV), FP32 with reunitarisation every 16 steps",
+            "events_per_s_fp32_batched": n / t_batch, "events_per_s_fp64_plain": n / t64,
+            "events_per_s_fp32_plain": n / t32p,
+            "speedup_fp32_batched_vs_fp64_plain": t64 / t_batch,
+            "site_updates_per_s_fp32_batched": site_updates / t_batch,
+            "pushes_per_s_fp32_batched": pushes / t_batch,
+            "seconds": {"fp32_batched": t_batch, "fp64_plain": t64, "fp32_plain": t32p, "batch_ic": t_ic},
+            "dpT2_rel_err_fp32_batched_vs_fp64": {"max": max(rel_pT), "mean": float(np.mean(rel_pT))},
+            "dpL2_rel_err_fp32_batched_vs_fp64": {"max": max(rel_pL), "mean": float(np.mean(rel_pL))},
+            "launch": launch, "tuner_choice": tune.strip().splitlines()[-1]}
+
+
 def cpu_baseline(n_steps=6, n_part=100_000):
     """The oracle on the host cores: 512^2 MV event (one colour sheet; the
     initial condition is not timed), n_steps leapfrog steps with the push of
@@ -103,7 +183,7 @@ def main():
     ap.add_argument("--steps", type=int, default=512)
     ap.add_argument("--warmup", type=int, default=96)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-extras", action="store_true", help="skip the FP32 run")
+    ap.add_argument("--no-extras", action="store_true", help="skip the FP32 and batched runs")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
                     help="precision of the headline run (profiling)")
     ap.add_argument("--tune-report", default=None, help="write the launch tuner's table to this file")
@@ -179,6 +259,7 @@ def main():
                        "launch": r32["launch"],
                        "dpT2_rel_vs_fp64": float(abs(r32["obs"][-1, 1] / res["obs"][-1, 1] - 1)),
                        "dpL2_rel_vs_fp64": float(abs(r32["obs"][-1, 2] / res["obs"][-1, 2] - 1))}
+        out["batch"] = run_batch(res["launch"])
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     if args.tune_report:

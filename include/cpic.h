@@ -240,20 +240,49 @@ void cpic_destroy(cpic_ctx* ctx);
 
 /*
  * Batched events: n_events independent Glasma events (each with its own
- * lattice size, MV scale and particle species) evolved together; every step
- * of every event is one work item of a single batched field launch and a
- * single batched push launch, captured into HIP graphs.  Events whose n_max
- * is reached drop out.  Parameter arrays have n_events entries.
+ * lattice size, MV scale, particle species and step count; one precision for
+ * all) evolved together.  One step of the batch is one batched field launch,
+ * one batched push launch and one batched step-end launch over every active
+ * event; each workgroup finds its (event, tile) or (event, particle block)
+ * item in a device prefix table.  Runs of steps are replayed from HIP graphs.
+ * Events that reach their n_max drop out of the work list.  Parameter arrays
+ * have n_events entries (particles may be NULL: no particles).  All events
+ * use the batch's stream (hip_stream, or a new non-blocking stream if NULL).
+ * Each event is also a full cpic_ctx internally; per-event results are read
+ * with the functions below.  Not thread-safe.
  */
 cpic_status cpic_batch_create(int32_t n_events, const cpic_glasma_params* glasma,
                               const cpic_particle_params* particles, void* hip_stream, cpic_batch** out);
+/* MV initial condition of every event (as cpic_init_mv); synchronises */
 cpic_status cpic_batch_init_mv(cpic_batch* b);
 /* run every event to its n_max; asynchronous */
 cpic_status cpic_batch_run(cpic_batch* b);
+/* advance every unfinished event by up to k steps; asynchronous */
+cpic_status cpic_batch_step(cpic_batch* b, int32_t k);
+/* wait for the batch's stream; reports the first event's particle error
+ * (CPIC_E_CELL_JUMP) as cpic_sync does */
 cpic_status cpic_batch_sync(cpic_batch* b);
-/* per-event samples, layout of cpic_observables_full */
+/* Field-tile tuner: times the batched field launch for each tile shape and
+ * XCD mapping over the current active events (state unchanged) and keeps the
+ * fastest; report as in cpic_tune.  Synchronises. */
+cpic_status cpic_batch_tune(cpic_batch* b, int32_t reps, char* report, size_t cap);
+/* batched launch shape: field tile bx x by (bx*by in {64,128,192,256}),
+ * xcd_remap 0/1, tpp = wavefronts per 64-particle group (1, 2, 4) */
+cpic_status cpic_batch_set_launch(cpic_batch* b, int32_t bx, int32_t by, int32_t xcd_remap, int32_t tpp);
+/* Launch groups: consecutive active events whose working set (both field
+ * buffer sets and the particle records) adds up to at most `bytes` share one
+ * field launch and one push launch; the groups of a step run one after the
+ * other, so each group's push can find the fields its field update has just
+ * written in the last-level cache.  0 (the default) = all active events in
+ * one group, which measured faster on uneven batches of 16-64 events. */
+cpic_status cpic_batch_set_group_bytes(cpic_batch* b, int64_t bytes);
+/* out = {bx, by, xcd_remap, tpp} */
+cpic_status cpic_batch_get_launch(const cpic_batch* b, int32_t out[4]);
+cpic_status cpic_batch_num_events(const cpic_batch* b, int32_t* n);
+cpic_status cpic_batch_current_step(const cpic_batch* b, int32_t event, int64_t* n);
+/* per-event samples, layout of cpic_observables_full; synchronises */
 cpic_status cpic_batch_observables(cpic_batch* b, int32_t event, double* out, int32_t cap, int32_t* n_samples);
-/* per-event state access, as cpic_get_state */
+/* per-event state access, as cpic_get_state; synchronises */
 cpic_status cpic_batch_get_state(cpic_batch* b, int32_t event, int32_t which, void* host_dst, size_t bytes);
 const char* cpic_batch_last_error(const cpic_batch* b);
 void cpic_batch_destroy(cpic_batch* b);

@@ -73,7 +73,11 @@ def lib():
             "cpic_tune": [P, i32, P, sz],
             "cpic_timing": [P, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(i64), ctypes.POINTER(i64)],
             "cpic_batch_create": [i32, ctypes.POINTER(GlasmaParams), ctypes.POINTER(ParticleParams), P, pp],
-            "cpic_batch_init_mv": [P], "cpic_batch_run": [P], "cpic_batch_sync": [P],
+            "cpic_batch_init_mv": [P], "cpic_batch_run": [P], "cpic_batch_step": [P, i32], "cpic_batch_sync": [P],
+            "cpic_batch_tune": [P, i32, P, sz], "cpic_batch_set_launch": [P, i32, i32, i32, i32],
+            "cpic_batch_set_group_bytes": [P, i64],
+            "cpic_batch_get_launch": [P, P], "cpic_batch_num_events": [P, ctypes.POINTER(i32)],
+            "cpic_batch_current_step": [P, i32, ctypes.POINTER(i64)],
             "cpic_batch_observables": [P, i32, P, i32, ctypes.POINTER(i32)],
             "cpic_batch_get_state": [P, i32, i32, P, sz],
         }
@@ -274,7 +278,35 @@ class Batch:
         self._chk(lib().cpic_batch_init_mv(self.h))
 
     def run(self):
+        """Evolve every event to its tau_max (asynchronous)."""
         self._chk(lib().cpic_batch_run(self.h))
+
+    def step(self, k):
+        """Advance every unfinished event by up to k steps (asynchronous)."""
+        self._chk(lib().cpic_batch_step(self.h, k))
+
+    def n(self, event):
+        v = ctypes.c_int64()
+        self._chk(lib().cpic_batch_current_step(self.h, event, ctypes.byref(v)))
+        return v.value
+
+    def tune(self, reps=5):
+        """Time the batched field launch per tile shape; keep the fastest; returns the report."""
+        buf = ctypes.create_string_buffer(8192)
+        self._chk(lib().cpic_batch_tune(self.h, reps, buf, len(buf)))
+        return buf.value.decode()
+
+    def set_launch(self, bx, by, xcd_remap=1, push_lanes=1):
+        self._chk(lib().cpic_batch_set_launch(self.h, bx, by, xcd_remap, push_lanes))
+
+    def set_group_bytes(self, nbytes):
+        """Working-set budget of one launch group (0: one group for all events)."""
+        self._chk(lib().cpic_batch_set_group_bytes(self.h, int(nbytes)))
+
+    def get_launch(self):
+        out = np.zeros(4, np.int32)
+        self._chk(lib().cpic_batch_get_launch(self.h, _ptr(out)))
+        return dict(zip(("bx", "by", "xcd_remap", "push_lanes"), out.tolist()))
 
     def sync(self):
         self._chk(lib().cpic_batch_sync(self.h))

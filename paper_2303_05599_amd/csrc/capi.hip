@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/cpic.h"
+#include "ctx.h"
 #include "internal.h"
 
 using namespace cpic;
@@ -18,7 +19,6 @@ using namespace cpic;
 namespace {
 
 constexpr double kHbarC = 0.1973269804;  // GeV fm
-constexpr int kGraphSteps = 16;          // steps per captured graph (even: buffers return to their parity)
 
 // Initial colour vectors with the classical Casimirs of Sec. IV ([eq:q23_main]):
 // fundamental q2 = 4, q3 = 10/3 from Q^5 and Q^8 alone (as in [eq:initq0]),
@@ -59,57 +59,12 @@ std::string g_static_error = "no error";
 
 }  // namespace
 
-struct cpic_ctx {
-    cpic_glasma_params gp{};
-    cpic_particle_params pp{};
-    hipStream_t st = nullptr;
-    bool own_stream = false;
-    int N = 0, V = 0, prec = 0;
-    size_t tsz = 8;
-    double a_fm = 0, a_gev = 0;
-    Schedule sc{};
-    int n = 0;    // host mirror of the device step counter
-    int cur = 0;  // buffer holding the state at step n
-    int64_t np = 0;
-    bool is_static = false;
-    double mhat = 0;
-    double q0[8]{}, q0eig[3]{}, q2ref = 0, q3ref = 0;
-    void* fbuf[2] = {nullptr, nullptr};
-    void* pr = nullptr;   // particle reals [18][np]
-    int* pcell = nullptr;  // [2][np]
-    int pblocks = 0, nslots = 0;
-    double* partials = nullptr;  // [nslots][pblocks][4]
-    double* obs = nullptr;       // [nslots][4]
-    std::vector<std::pair<int, int>> samples;  // (slot, step n after which it was taken)
-    int* pid = nullptr;    // original index of each particle record
-    SortBufs sb{};
-    bool static_sorted = false;
-    int sorted_at = -1;   // step before which the records were last reordered
-    int* d_step = nullptr;
-    int* d_err = nullptr;
-    int* d_fails = nullptr;
-    double* dpart = nullptr;  // diagnostics partials
-    double* dout = nullptr;   // diagnostics results [8 + 2]
-    int dcap = 0;
-    LaunchCfg cfg{};
-    int tpp = 1;          // wavefronts per particle group in the push (1, 2, 4)
-    bool initialised = false;
-    // graphs: [parity] -> executable graph of kGraphSteps steps starting from buffer `parity`
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};
-    // timing
-    bool timing = false;
-    std::vector<hipEvent_t> ev_field, ev_push;
-    double t_field = 0, t_push = 0;
-    int64_t k_field = 0, k_push = 0;
-    std::string err;
-};
-
-static cpic_status fail(cpic_ctx* c, cpic_status code, const std::string& msg)
+cpic_status cpic::fail(cpic_ctx* c, cpic_status code, const std::string& msg)
 {
     if (c) c->err = msg; else g_static_error = msg;
     return code;
 }
-static cpic_status hip_fail(cpic_ctx* c, hipError_t e, const char* where)
+cpic_status cpic::hip_fail(cpic_ctx* c, hipError_t e, const char* where)
 {
     return fail(c, CPIC_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
 }
@@ -277,15 +232,16 @@ static bool is_sort_point(const cpic_ctx* c, int n)
     if (c->is_static) return !c->static_sorted;
     return n == c->sc.n_form || n % kSortEvery == 0;
 }
-static int next_sort_point(const cpic_ctx* c, int n)
+int cpic::next_sort_point(const cpic_ctx* c, int n)
 {
-    if (c->np <= 1 || c->is_static) return 1 << 30;
+    if (c->np <= 1 || n + 1 > c->sc.n_max) return 1 << 30;
+    if (c->is_static) return (!c->static_sorted && n + 1 <= c->sc.n_form) ? c->sc.n_form : 1 << 30;
     int m = n + 1;
     if (m <= c->sc.n_form) return c->sc.n_form;
     m = ((m + kSortEvery - 1) / kSortEvery) * kSortEvery;
     return m;
 }
-static cpic_status maybe_sort(cpic_ctx* c)
+cpic_status cpic::maybe_sort(cpic_ctx* c)
 {
     if (!is_sort_point(c, c->n) || c->sorted_at == c->n) return CPIC_OK;
     c->sorted_at = c->n;
@@ -375,6 +331,19 @@ extern "C" cpic_status cpic_init_mv(cpic_ctx* c)
     return CPIC_OK;
 }
 
+PushArgs cpic::push_args(const cpic_ctx* c, int tpp)
+{
+    PushArgs pa{};
+    pa.N = c->N;
+    pa.np = (int)c->np;
+    pa.is_static = c->is_static;
+    pa.tpp = tpp;
+    pa.mhat = c->mhat;
+    for (int k = 0; k < 3; k++) pa.q0eig[k] = c->q0eig[k];
+    pa.sc = c->sc;
+    return pa;
+}
+
 // one step: field update (cur -> cur^1), push, step end (samples + counter)
 template <typename T> static cpic_status launch_one(cpic_ctx* c, int parity, bool with_events)
 {
@@ -390,14 +359,7 @@ template <typename T> static cpic_status launch_one(cpic_ctx* c, int parity, boo
         c->ev_field.push_back(e0); c->ev_field.push_back(e1);
     }
     if (c->np > 0) {
-        PushArgs pa{};
-        pa.N = c->N;
-        pa.np = (int)c->np;
-        pa.is_static = c->is_static;
-        pa.tpp = c->tpp;
-        pa.mhat = c->mhat;
-        for (int k = 0; k < 3; k++) pa.q0eig[k] = c->q0eig[k];
-        pa.sc = c->sc;
+        const PushArgs pa = push_args(c, c->tpp);
         if (with_events) {
             HIPCHK(c, hipEventCreate(&e2), "event"); HIPCHK(c, hipEventCreate(&e3), "event");
             HIPCHK(c, hipEventRecord(e2, c->st), "event");
@@ -412,7 +374,7 @@ template <typename T> static cpic_status launch_one(cpic_ctx* c, int parity, boo
     return CPIC_OK;
 }
 
-static cpic_status host_advance(cpic_ctx* c, int k)
+cpic_status cpic::host_advance(cpic_ctx* c, int k)
 {
     for (int j = 0; j < k; j++) {
         if (c->np > 0 && is_record_step(c->sc, c->n)) c->samples.push_back({record_slot_of(c->sc, c->n), c->n});

@@ -1,0 +1,72 @@
+// ctx.h -- the per-event context behind cpic_ctx, shared by the single-event
+// API (capi.hip) and the batched driver (batch.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/cpic.h"
+#include "internal.h"
+
+namespace cpic {
+constexpr int kGraphSteps = 16;  // steps per captured graph (even: buffers return to their parity)
+}
+
+struct cpic_ctx {
+    cpic_glasma_params gp{};
+    cpic_particle_params pp{};
+    hipStream_t st = nullptr;
+    bool own_stream = false;
+    int N = 0, V = 0, prec = 0;
+    size_t tsz = 8;
+    double a_fm = 0, a_gev = 0;
+    cpic::Schedule sc{};
+    int n = 0;    // host mirror of the device step counter
+    int cur = 0;  // buffer holding the state at step n
+    int64_t np = 0;
+    bool is_static = false;
+    double mhat = 0;
+    double q0[8]{}, q0eig[3]{}, q2ref = 0, q3ref = 0;
+    void* fbuf[2] = {nullptr, nullptr};
+    void* pr = nullptr;   // particle reals [18][np]
+    int* pcell = nullptr;  // [2][np]
+    int pblocks = 0, nslots = 0;
+    double* partials = nullptr;  // [nslots][pblocks][4]
+    double* obs = nullptr;       // [nslots][4]
+    std::vector<std::pair<int, int>> samples;  // (slot, step n after which it was taken)
+    int* pid = nullptr;    // original index of each particle record
+    cpic::SortBufs sb{};
+    bool static_sorted = false;
+    int sorted_at = -1;   // step before which the records were last reordered
+    int* d_step = nullptr;
+    int* d_err = nullptr;
+    int* d_fails = nullptr;
+    double* dpart = nullptr;  // diagnostics partials
+    double* dout = nullptr;   // diagnostics results [8 + 2]
+    int dcap = 0;
+    cpic::LaunchCfg cfg{};
+    int tpp = 1;          // wavefronts per particle group in the push (1, 2, 4)
+    bool initialised = false;
+    // graphs: [parity] -> executable graph of kGraphSteps steps starting from buffer `parity`
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_field, ev_push;
+    double t_field = 0, t_push = 0;
+    int64_t k_field = 0, k_push = 0;
+    std::string err;
+};
+
+namespace cpic {
+cpic_status fail(cpic_ctx* c, cpic_status code, const std::string& msg);
+cpic_status hip_fail(cpic_ctx* c, hipError_t e, const char* where);
+// reorder the particle records by cell if step c->n is a reordering point
+cpic_status maybe_sort(cpic_ctx* c);
+// first reordering point after step n (1 << 30 if none)
+int next_sort_point(const cpic_ctx* c, int n);
+// host bookkeeping of k launched steps (sample list, step counter, buffer parity)
+cpic_status host_advance(cpic_ctx* c, int k);
+PushArgs push_args(const cpic_ctx* c, int tpp);
+}  // namespace cpic

@@ -106,26 +106,23 @@ __device__ __forceinline__ void kick_forces(const View<T>& f, const Nbr& nb, T t
     if (grad2) *grad2 = g2;
 }
 
-__device__ __forceinline__ bool tile_coords(int N, int bx, int by, int remap, int& x, int& y)
+// Workgroups are dealt round-robin to the 8 XCDs; with remapping, logical
+// block g of `total` goes to XCD g / per, so each XCD works on a contiguous
+// band of tiles and their shared halos stay in its L2.
+__device__ __forceinline__ int logical_block(int total, int remap)
 {
-    const int ntx = (N + bx - 1) / bx, nty = (N + by - 1) / by, ntiles = ntx * nty;
-    int tile = blockIdx.x;
-    if (remap) {  // workgroups are dealt round-robin to the 8 XCDs: give each XCD a contiguous band
-        const int per = (ntiles + 7) / 8;
-        tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-        if (tile >= ntiles) return false;
-    }
-    x = (tile % ntx) * bx + threadIdx.x;
-    y = (tile / ntx) * by + threadIdx.y;
-    return x < N && y < N;
+    if (!remap) return blockIdx.x;
+    const int per = (total + 7) / 8;
+    return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
 }
 
 template <typename T>
 __device__ __forceinline__ void field_step_body(const Fields<T>& in, const Fields<T>& out, int N, int bx, int by,
-                                                int remap, const Schedule& sc, const int* __restrict__ d_step)
+                                                int tile, const Schedule& sc, const int* __restrict__ d_step)
 {
-    int x, y;
-    if (!tile_coords(N, bx, by, remap, x, y)) return;
+    const int ntx = (N + bx - 1) / bx;
+    const int x = (tile % ntx) * bx + (int)threadIdx.x, y = (tile / ntx) * by + (int)threadIdx.y;
+    if (x >= N || y >= N) return;
     const int n = *d_step;
     const double td = n * sc.dt, thd = (n + 0.5) * sc.dt;
     const T t = T(td), inv_t = n > 0 ? T(1.0 / td) : T(0), dt = T(sc.dt);
@@ -285,23 +282,70 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
 // Occupancy variants: W waves per SIMD requested from the register
 // allocator (W = 1: no request).  Chosen per lattice size and precision by
 // the launch tuner.
+__device__ __forceinline__ int field_tiles(int N, int bx, int by) { return ((N + bx - 1) / bx) * ((N + by - 1) / by); }
+
 template <typename T>
 __global__ __launch_bounds__(256) void field_step_kernel(Fields<T> in, Fields<T> out, int N, int bx, int by, int remap,
                                                          Schedule sc, const int* __restrict__ d_step)
 {
-    field_step_body(in, out, N, bx, by, remap, sc, d_step);
+    const int nt = field_tiles(N, bx, by), tile = logical_block(nt, remap);
+    if (tile < nt) field_step_body(in, out, N, bx, by, tile, sc, d_step);
 }
 #define CPIC_FIELD_VARIANT(W)                                                                                     \
     template <typename T>                                                                                         \
     __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, W))) void field_step_kernel_w##W(    \
         Fields<T> in, Fields<T> out, int N, int bx, int by, int remap, Schedule sc, const int* __restrict__ d_step) \
     {                                                                                                             \
-        field_step_body(in, out, N, bx, by, remap, sc, d_step);                                                   \
+        const int nt = field_tiles(N, bx, by), tile = logical_block(nt, remap);                                   \
+        if (tile < nt) field_step_body(in, out, N, bx, by, tile, sc, d_step);                                     \
     }
 CPIC_FIELD_VARIANT(2)
 CPIC_FIELD_VARIANT(3)
 CPIC_FIELD_VARIANT(4)
 #undef CPIC_FIELD_VARIANT
+
+// ---------------------------------------------------------------- batched events
+// One launch advances every active event by one step: logical block g maps to
+// (active event k, tile g - tile_start[k]); all events share the tile shape.
+__device__ __forceinline__ int find_event(const int* __restrict__ start, int nact, int g)
+{
+    int lo = 0, hi = nact;  // start[lo] <= g < start[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (start[mid] <= g) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void batch_field_kernel(const EventDesc* __restrict__ ev, const int* __restrict__ act,
+                                                          const int* __restrict__ tile_start, int nact, int bx, int by,
+                                                          int remap)
+{
+    const int total = tile_start[nact];
+    const int g = logical_block(total, remap);
+    if (g >= total) return;
+    const int k = find_event(tile_start, nact, g);
+    const EventDesc& d = ev[act[k]];
+    const int parity = (*d.d_step & 1) ^ d.flip;
+    const Fields<T> A = fields_at<T>(d.f[parity], d.N * d.N), B = fields_at<T>(d.f[parity ^ 1], d.N * d.N);
+    field_step_body(A, B, d.N, bx, by, g - tile_start[k], d.pa.sc, d.d_step);
+}
+
+template <typename T>
+hipError_t launch_batch_field(const EventDesc* ev, const int* act, const int* tile_start, int nact, int total_tiles,
+                              const LaunchCfg& cfg, hipStream_t st)
+{
+    if (cfg.split || cfg.bx * cfg.by > 256 || total_tiles <= 0) return hipErrorInvalidValue;
+    const int grid = cfg.xcd_remap ? 8 * ((total_tiles + 7) / 8) : total_tiles;
+    hipLaunchKernelGGL(batch_field_kernel<T>, dim3(grid), dim3(cfg.bx, cfg.by), 0, st, ev, act, tile_start, nact, cfg.bx,
+                       cfg.by, cfg.xcd_remap);
+    return hipGetLastError();
+}
+template hipError_t launch_batch_field<double>(const EventDesc*, const int*, const int*, int, int, const LaunchCfg&,
+                                               hipStream_t);
+template hipError_t launch_batch_field<float>(const EventDesc*, const int*, const int*, int, int, const LaunchCfg&,
+                                              hipStream_t);
 
 template <typename T>
 hipError_t launch_field_step(const Fields<T>& in, const Fields<T>& out, int N, const Schedule& sc,

@@ -21,7 +21,7 @@ template <typename T> struct Fields {
     T* E;    // [2][8][V]
     T* pi;   // [8][V]
 };
-template <typename T> inline Fields<T> fields_at(void* base, int V)
+template <typename T> __host__ __device__ inline Fields<T> fields_at(void* base, int V)
 {
     T* p = static_cast<T*>(base);
     return {p, p + 36 * (size_t)V, p + 44 * (size_t)V, p + 60 * (size_t)V};
@@ -67,6 +67,34 @@ struct LaunchCfg {
     int split = 0;        // 1: one thread per link (bx * by = 128 sites per block)
 };
 
+struct PushArgs {
+    int N, np, is_static;
+    int tpp;          // wavefronts per particle group (1, 2, 4)
+    double mhat;
+    double q0eig[3];  // sorted eigenvalues of Q0 (charge renormalisation)
+    Schedule sc;
+};
+
+// one event of a batch, as the batched kernels see it
+struct EventDesc {
+    void* f[2];        // field buffer sets; the state at step n is in f[(n & 1) ^ flip]
+    int flip;
+    void* pr;          // particle records [18][np]
+    int* cell;         // [2][np]
+    int N;
+    PushArgs pa;
+    int* d_step;
+    int* d_err;
+    double* partials;  // [slots][push blocks][4]
+    double* obs;       // [slots][4]
+};
+
+__host__ __device__ inline int push_blocks_d(int np, int tpp)
+{
+    const int ppb = 256 / (tpp > 0 ? tpp : 1);
+    return (np + ppb - 1) / ppb;
+}
+
 // ---- field kernels (field.hip)
 template <typename T>
 hipError_t launch_field_step(const Fields<T>& in, const Fields<T>& out, int N, const Schedule& sc,
@@ -74,20 +102,22 @@ hipError_t launch_field_step(const Fields<T>& in, const Fields<T>& out, int N, c
 template <typename T>
 hipError_t launch_field_diag(const Fields<T>& f, int N, double dt, int n, double* partials, int nblk_cap,
                              int* nblk_out, hipStream_t st);
+// batched launches over the active events act[0..nact): logical blocks
+// [start[k], start[k+1]) belong to event act[k]
+template <typename T>
+hipError_t launch_batch_field(const EventDesc* ev, const int* act, const int* tile_start, int nact, int total_tiles,
+                              const LaunchCfg& cfg, hipStream_t st);
 
 // ---- particle kernels (push.hip)
-struct PushArgs {
-    int N, np, is_static;
-    int tpp;          // lanes per particle (1, 2, 4)
-    double mhat;
-    double q0eig[3];  // sorted eigenvalues of Q0 (charge renormalisation)
-    Schedule sc;
-};
 // push at t_n: A holds U(n), phi(n), E(n-1/2), pi(n-1/2); B holds E(n+1/2), pi(n+1/2)
 template <typename T>
 hipError_t launch_push(const Fields<T>& A, const Fields<T>& B, const Parts<T>& P, const PushArgs& a,
                        const int* d_step, double* partials, int* err, hipStream_t st);
 int push_blocks(int np, int tpp);
+template <typename T>
+hipError_t launch_batch_push(const EventDesc* ev, const int* act, const int* blk_start, int nact, int total_blocks,
+                             int tpp, hipStream_t st);
+hipError_t launch_batch_step_end(const EventDesc* ev, const int* act, int nact, hipStream_t st);
 hipError_t launch_reduce_rows(const double* partials, int nrows, int ncols, double* out, hipStream_t st);
 // end of a step: on recording steps add the block partials of the step's slot
 // into obs[slot][4]; then advance the step counter

@@ -246,16 +246,15 @@ __device__ __forceinline__ int xcd_block(int nblocks)
 // particle state: it rotates Q and publishes it in LDS; every role adds its
 // field contractions into LDS; the role-0 wave then takes the Euler step.
 template <typename T, int TPP>
-__global__ __launch_bounds__(256) void push_kernel(Fields<T> Af, Fields<T> Bf, Parts<T> P, PushArgs a,
-                                                   const int* __restrict__ d_step, double* partials, int* err)
+__device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& Bf, const Parts<T>& P,
+                                          const PushArgs& a, const int* __restrict__ d_step, double* partials,
+                                          int* err, int blk)
 {
     const int n = *d_step;
-    if (n < a.sc.n_form || n >= a.sc.n_max) return;  // uniform over the grid
+    if (n < a.sc.n_form || n >= a.sc.n_max) return;  // uniform over the event
     constexpr int PPB = 256 / TPP;                   // particles per block
     constexpr int NG = 4 / TPP;                      // particle groups (of 64) per block
     const int nblocks = (a.np + PPB - 1) / PPB;
-    const int blk = xcd_block(nblocks);
-    if (blk >= nblocks) return;                      // uniform over the block
     const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
     const int role = wave % TPP, grp = wave / TPP;
     const int p = blk * PPB + grp * 64 + lane;
@@ -396,7 +395,87 @@ __global__ __launch_bounds__(256) void push_kernel(Fields<T> Af, Fields<T> Bf, P
         block_reduce_store<4>(obs, 0u, partials + ((size_t)record_slot * nblocks + blk) * 4);
 }
 
-int push_blocks(int np, int tpp) { const int ppb = 256 / (tpp > 0 ? tpp : 1); return (np + ppb - 1) / ppb; }
+template <typename T, int TPP>
+__global__ __launch_bounds__(256) void push_kernel(Fields<T> Af, Fields<T> Bf, Parts<T> P, PushArgs a,
+                                                   const int* __restrict__ d_step, double* partials, int* err)
+{
+    const int nblocks = (a.np + 256 / TPP - 1) / (256 / TPP);
+    const int blk = xcd_block(nblocks);
+    if (blk < nblocks) push_body<T, TPP>(Af, Bf, P, a, d_step, partials, err, blk);
+}
+
+// batched events: logical block g -> (active event k, block g - blk_start[k])
+__device__ __forceinline__ int find_event_p(const int* __restrict__ start, int nact, int g)
+{
+    int lo = 0, hi = nact;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (start[mid] <= g) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+template <typename T, int TPP>
+__global__ __launch_bounds__(256) void batch_push_kernel(const EventDesc* __restrict__ ev, const int* __restrict__ act,
+                                                         const int* __restrict__ blk_start, int nact)
+{
+    const int total = blk_start[nact];
+    const int g = xcd_block(total);
+    if (g >= total) return;
+    const int k = find_event_p(blk_start, nact, g);
+    const EventDesc& d = ev[act[k]];
+    const int V = d.N * d.N, parity = (*d.d_step & 1) ^ d.flip;
+    push_body<T, TPP>(fields_at<T>(d.f[parity], V), fields_at<T>(d.f[parity ^ 1], V),
+                      Parts<T>{static_cast<T*>(d.pr), d.cell}, d.pa, d.d_step, d.partials, d.d_err, g - blk_start[k]);
+}
+
+// end of a step: on recording steps the block partials of the step's slot are
+// summed (fixed order) into obs[slot]; then the step counter advances
+__device__ __forceinline__ void step_end_body(const Schedule& sc, int nblocks, const double* __restrict__ partials,
+                                              double* obs, int* d_step)
+{
+    const int n = *d_step;
+    if (nblocks > 0 && is_record_step(sc, n)) {
+        const int slot = record_slot_of(sc, n);
+        const double* src = partials + (size_t)slot * nblocks * 4;
+        double v[4] = {0, 0, 0, 0};
+        for (int r = threadIdx.x; r < nblocks; r += blockDim.x)
+            for (int c = 0; c < 4; c++) v[c] += src[(size_t)r * 4 + c];
+        block_reduce_store<4>(v, 0u, obs + (size_t)slot * 4);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *d_step = n + 1;
+}
+
+// one block per active event: the step end of each event
+__global__ __launch_bounds__(256) void batch_step_end_kernel(const EventDesc* __restrict__ ev, const int* __restrict__ act)
+{
+    const EventDesc& d = ev[act[blockIdx.x]];
+    step_end_body(d.pa.sc, d.pa.np > 0 ? push_blocks_d(d.pa.np, d.pa.tpp) : 0, d.partials, d.obs, d.d_step);
+}
+
+template <typename T>
+hipError_t launch_batch_push(const EventDesc* ev, const int* act, const int* blk_start, int nact, int total_blocks,
+                             int tpp, hipStream_t st)
+{
+    if (total_blocks <= 0) return hipSuccess;
+    const dim3 g(8 * ((total_blocks + 7) / 8)), b(256);
+    switch (tpp) {
+    case 2: hipLaunchKernelGGL((batch_push_kernel<T, 2>), g, b, 0, st, ev, act, blk_start, nact); break;
+    case 4: hipLaunchKernelGGL((batch_push_kernel<T, 4>), g, b, 0, st, ev, act, blk_start, nact); break;
+    default: hipLaunchKernelGGL((batch_push_kernel<T, 1>), g, b, 0, st, ev, act, blk_start, nact);
+    }
+    return hipGetLastError();
+}
+hipError_t launch_batch_step_end(const EventDesc* ev, const int* act, int nact, hipStream_t st)
+{
+    if (nact <= 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_step_end_kernel, dim3(nact), dim3(256), 0, st, ev, act);
+    return hipGetLastError();
+}
+template hipError_t launch_batch_push<double>(const EventDesc*, const int*, const int*, int, int, int, hipStream_t);
+template hipError_t launch_batch_push<float>(const EventDesc*, const int*, const int*, int, int, int, hipStream_t);
+
+int push_blocks(int np, int tpp) { return push_blocks_d(np, tpp); }
 
 template <typename T>
 hipError_t launch_push(const Fields<T>& A, const Fields<T>& B, const Parts<T>& P, const PushArgs& a,
@@ -416,17 +495,7 @@ hipError_t launch_push(const Fields<T>& A, const Fields<T>& B, const Parts<T>& P
 __global__ __launch_bounds__(256) void step_end_kernel(Schedule sc, int nblocks, const double* __restrict__ partials,
                                                        double* obs, int* d_step)
 {
-    const int n = *d_step;
-    if (nblocks > 0 && is_record_step(sc, n)) {
-        const int slot = record_slot_of(sc, n);
-        const double* src = partials + (size_t)slot * nblocks * 4;
-        double v[4] = {0, 0, 0, 0};
-        for (int r = threadIdx.x; r < nblocks; r += blockDim.x)
-            for (int c = 0; c < 4; c++) v[c] += src[(size_t)r * 4 + c];
-        block_reduce_store<4>(v, 0u, obs + (size_t)slot * 4);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) *d_step = n + 1;
+    step_end_body(sc, nblocks, partials, obs, d_step);
 }
 
 hipError_t launch_step_end(const Schedule& sc, int nblocks, const double* partials, double* obs, int* d_step,

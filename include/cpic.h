@@ -210,9 +210,11 @@ cpic_status cpic_load(cpic_ctx* ctx, const char* path);
 cpic_status cpic_set_launch(cpic_ctx* ctx, int32_t bx, int32_t by, int32_t xcd_remap, int32_t waves,
                             int32_t link_parallel);
 
-/* Push work split: wavefronts per group of 64 particles (1, 2 or 4).  With few
- * particles several wavefronts share a group (each evaluates part of the field
- * contractions) so that the push still fills the GPU.  Default from n. */
+/* Push work split: wavefronts per group of 64 particles (1, 2 or 4).  The
+ * helper wavefronts evaluate part of the colour fields at the particles' cells
+ * while the owner wavefront rotates the charges, which shortens the chain of
+ * dependent memory accesses per particle.  Default from n; cpic_tune times
+ * all three. */
 cpic_status cpic_set_push_lanes(cpic_ctx* ctx, int32_t lanes);
 
 /* Current launch configuration: out = {bx, by, xcd_remap, waves, push lanes,
@@ -241,15 +243,18 @@ void cpic_destroy(cpic_ctx* ctx);
 /*
  * Batched events: n_events independent Glasma events (each with its own
  * lattice size, MV scale, particle species and step count; one precision for
- * all) evolved together.  One step of the batch is one batched field launch,
- * one batched push launch and one batched step-end launch over every active
- * event; each workgroup finds its (event, tile) or (event, particle block)
- * item in a device prefix table.  Runs of steps are replayed from HIP graphs.
- * Events that reach their n_max drop out of the work list.  Parameter arrays
- * have n_events entries (particles may be NULL: no particles).  All events
- * use the batch's stream (hip_stream, or a new non-blocking stream if NULL).
- * Each event is also a full cpic_ctx internally; per-event results are read
- * with the functions below.  Not thread-safe.
+ * all) evolved together.  Events are split into launch groups whose working
+ * set fits the last-level cache (cpic_batch_set_group_bytes); the groups run
+ * one after the other, each to the end of its events.  One step of a group is
+ * one batched field launch, one batched push launch and one batched step-end
+ * launch over its active events; each workgroup reads its (event, tile) or
+ * (event, particle block) item from a device work map.  Runs of steps are
+ * replayed from HIP graphs; events that reach their n_max drop out of the
+ * work maps.  Parameter arrays have n_events entries (particles may be NULL:
+ * no particles).  All events use the batch's stream (hip_stream, or a new
+ * non-blocking stream if NULL).  Each event is also a full cpic_ctx
+ * internally; per-event results are read with the functions below.  Not
+ * thread-safe.
  */
 cpic_status cpic_batch_create(int32_t n_events, const cpic_glasma_params* glasma,
                               const cpic_particle_params* particles, void* hip_stream, cpic_batch** out);
@@ -257,7 +262,7 @@ cpic_status cpic_batch_create(int32_t n_events, const cpic_glasma_params* glasma
 cpic_status cpic_batch_init_mv(cpic_batch* b);
 /* run every event to its n_max; asynchronous */
 cpic_status cpic_batch_run(cpic_batch* b);
-/* advance every unfinished event by up to k steps; asynchronous */
+/* advance every unfinished event by up to k steps (group by group); asynchronous */
 cpic_status cpic_batch_step(cpic_batch* b, int32_t k);
 /* wait for the batch's stream; reports the first event's particle error
  * (CPIC_E_CELL_JUMP) as cpic_sync does */
@@ -269,12 +274,12 @@ cpic_status cpic_batch_tune(cpic_batch* b, int32_t reps, char* report, size_t ca
 /* batched launch shape: field tile bx x by (bx*by in {64,128,192,256}),
  * xcd_remap 0/1, tpp = wavefronts per 64-particle group (1, 2, 4) */
 cpic_status cpic_batch_set_launch(cpic_batch* b, int32_t bx, int32_t by, int32_t xcd_remap, int32_t tpp);
-/* Launch groups: consecutive active events whose working set (both field
- * buffer sets and the particle records) adds up to at most `bytes` share one
- * field launch and one push launch; the groups of a step run one after the
- * other, so each group's push can find the fields its field update has just
- * written in the last-level cache.  0 (the default) = all active events in
- * one group, which measured faster on uneven batches of 16-64 events. */
+/* Launch groups: events are taken by decreasing working set (both field
+ * buffer sets, the magnetic-field pieces for the push and the particle
+ * records) and packed into groups of at most `bytes` (a larger event forms a
+ * group of its own).  A group runs all its steps before the next group
+ * starts, so its fields stay in the last-level cache from one step to the
+ * next.  0 = all events in one group, stepped together.  Default 256 MiB. */
 cpic_status cpic_batch_set_group_bytes(cpic_batch* b, int64_t bytes);
 /* out = {bx, by, xcd_remap, tpp} */
 cpic_status cpic_batch_get_launch(const cpic_batch* b, int32_t out[4]);

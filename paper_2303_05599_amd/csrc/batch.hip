@@ -1,14 +1,16 @@
 // batch.hip -- many Glasma events evolved together (cpic_batch_* in cpic.h).
 //
 // Every event keeps its own context (buffers, step counter, samples); the
-// batch adds a device table of event descriptors and, for each set of still
-// active events, a plan: the active list and the prefix sums of their field
-// tiles and push blocks.  One step of the whole batch is three launches --
-// batched field update, batched push, batched step end -- whose workgroups
-// find their (event, tile) item by binary search in the prefix table.
-// Runs of steps between particle reorderings are replayed from HIP graphs
-// captured per plan; each event reads its step number, and so its buffer
-// parity, kick/formation/recording decisions, from its own device counter.
+// batch adds a device table of event descriptors.  Events are split into
+// launch groups whose working set fits the last-level cache; the groups run
+// one after the other, each to the end of its events.  For every set of
+// still active events of a group there is a plan: the active list and the
+// work maps (event, tile) and (event, particle block), one entry per
+// workgroup.  One step of a group is three launches -- batched field
+// update, batched push, batched step end.  Runs of steps between particle
+// reorderings are replayed from HIP graphs captured per plan; each event
+// reads its step number, and so its buffer parity, kick/formation/recording
+// decisions, from its own device counter.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,18 +28,18 @@ using namespace cpic;
 namespace {
 
 constexpr int kBatchGraphSteps = 16;
-
-// Consecutive active events act[first .. first + count) launched together.
-struct Group {
-    int first = 0, count = 0;
-    int total_tiles = 0, total_blocks = 0;
-    size_t tiles_off = 0, blocks_off = 0;  // offsets (ints) of the prefix tables in d_idx
-};
+// Events are run in groups whose working set (both field buffer sets, the
+// magnetic-field pieces and the particle records) stays within about this
+// much, so that from one step to the next (and from a group's field update
+// to its push) the data is served from the 256 MB last-level cache.
+constexpr size_t kDefaultGroupBytes = (size_t)256 << 20;
 
 struct Plan {
-    std::vector<int> act;
-    std::vector<Group> groups;
-    int* d_idx = nullptr;  // act[nact], then per group tile_start[count + 1], blk_start[count + 1]
+    std::vector<int> act;          // active events (descriptor indices)
+    int* d_act = nullptr;          // [nact]
+    int2* d_tiles = nullptr;       // (event, tile) per field workgroup
+    int2* d_blocks = nullptr;      // (event, particle block) per push workgroup
+    int total_tiles = 0, total_blocks = 0;
     hipGraphExec_t graph = nullptr;
 };
 
@@ -54,7 +56,7 @@ struct cpic_batch {
     // shortens each wave's chain of dependent loads (measured fastest from
     // 5e4 to 3.5e6 particles per launch)
     int tpp = 4;
-    size_t group_bytes = 0;  // working-set budget of a launch group; 0: all active events in one launch
+    size_t group_bytes = kDefaultGroupBytes;  // working-set budget of a launch group; 0: one group
     EventDesc* d_desc = nullptr;
     std::vector<EventDesc> desc;  // host copy (kept alive for the asynchronous upload)
     std::map<std::vector<int>, Plan> plans;
@@ -82,7 +84,9 @@ static void drop_plans(cpic_batch* b)
 {
     for (auto& kv : b->plans) {
         if (kv.second.graph) hipGraphExecDestroy(kv.second.graph);
-        hipFree(kv.second.d_idx);
+        hipFree(kv.second.d_act);
+        hipFree(kv.second.d_tiles);
+        hipFree(kv.second.d_blocks);
     }
     b->plans.clear();
 }
@@ -100,6 +104,7 @@ static cpic_status upload_desc(cpic_batch* b)
         d.f[1] = c->fbuf[1];
         d.flip = c->cur ^ (c->n & 1);
         d.pr = c->pr;
+        d.aux = c->aux;
         d.cell = c->pcell;
         d.N = c->N;
         d.pa = push_args(c, b->tpp);
@@ -122,24 +127,32 @@ static int field_tiles_host(int N, const LaunchCfg& cfg)
 
 static size_t working_set(const cpic_ctx* c)
 {
-    return 2 * (size_t)kRealsPerSite * c->V * c->tsz + (size_t)c->np * (kPartReals * c->tsz + 2 * sizeof(int));
+    return (2 * (size_t)kRealsPerSite + (c->aux ? kAuxReals : 0)) * c->V * c->tsz +
+           (size_t)c->np * (kPartReals * c->tsz + 2 * sizeof(int));
 }
 
-// split the active list into launch groups of at most group_bytes working set
-static std::vector<std::pair<int, int>> group_ranges(const cpic_batch* b, const std::vector<int>& act)
+// Launch groups: events by decreasing working set, packed greedily up to
+// group_bytes (an event larger than the budget forms a group of its own);
+// group_bytes = 0 puts every event in one group.
+static std::vector<std::vector<int>> launch_groups(const cpic_batch* b)
 {
-    std::vector<std::pair<int, int>> r;
+    std::vector<int> order(b->ev.size());
+    for (size_t e = 0; e < order.size(); e++) order[e] = (int)e;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return working_set(b->ev[x]) > working_set(b->ev[y]); });
+    std::vector<std::vector<int>> groups;
     size_t acc = 0;
-    for (int k = 0; k < (int)act.size(); k++) {
-        const size_t w = working_set(b->ev[act[k]]);
-        if (r.empty() || (b->group_bytes && acc + w > b->group_bytes)) {
-            r.push_back({k, 0});
+    for (int e : order) {
+        const size_t w = working_set(b->ev[e]);
+        if (groups.empty() || (b->group_bytes && acc + w > b->group_bytes)) {
+            groups.emplace_back();
             acc = 0;
         }
-        r.back().second++;
+        groups.back().push_back(e);
         acc += w;
     }
-    return r;
+    for (auto& g : groups) std::sort(g.begin(), g.end());
+    return groups;
 }
 
 static cpic_status get_plan(cpic_batch* b, const std::vector<int>& act, Plan** out)
@@ -151,44 +164,33 @@ static cpic_status get_plan(cpic_batch* b, const std::vector<int>& act, Plan** o
     }
     Plan p;
     p.act = act;
-    std::vector<int> idx(act.begin(), act.end());
-    for (const auto& gr : group_ranges(b, act)) {
-        Group g;
-        g.first = gr.first;
-        g.count = gr.second;
-        g.tiles_off = idx.size();
-        idx.push_back(0);
-        for (int k = 0; k < g.count; k++)
-            idx.push_back(idx.back() + field_tiles_host(b->ev[act[g.first + k]]->N, b->cfg));
-        g.total_tiles = idx.back();
-        g.blocks_off = idx.size();
-        idx.push_back(0);
-        for (int k = 0; k < g.count; k++) {
-            const cpic_ctx* c = b->ev[act[g.first + k]];
-            idx.push_back(idx.back() + (c->np > 0 ? push_blocks((int)c->np, b->tpp) : 0));
-        }
-        g.total_blocks = idx.back();
-        p.groups.push_back(g);
+    std::vector<int2> tiles, blocks;
+    for (int e : act) {
+        const cpic_ctx* c = b->ev[e];
+        const int nt = field_tiles_host(c->N, b->cfg), nb = c->np > 0 ? push_blocks((int)c->np, b->tpp) : 0;
+        for (int k = 0; k < nt; k++) tiles.push_back(make_int2(e, k));
+        for (int k = 0; k < nb; k++) blocks.push_back(make_int2(e, k));
     }
-    BHIP(b, hipMalloc(&p.d_idx, sizeof(int) * idx.size()), "plan");
-    BHIP(b, hipMemcpy(p.d_idx, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice), "plan");
+    p.total_tiles = (int)tiles.size();
+    p.total_blocks = (int)blocks.size();
+    BHIP(b, hipMalloc(&p.d_act, sizeof(int) * act.size()), "plan");
+    BHIP(b, hipMalloc(&p.d_tiles, sizeof(int2) * std::max<size_t>(tiles.size(), 1)), "plan");
+    BHIP(b, hipMalloc(&p.d_blocks, sizeof(int2) * std::max<size_t>(blocks.size(), 1)), "plan");
+    BHIP(b, hipMemcpy(p.d_act, act.data(), sizeof(int) * act.size(), hipMemcpyHostToDevice), "plan");
+    BHIP(b, hipMemcpy(p.d_tiles, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice), "plan");
+    if (!blocks.empty())
+        BHIP(b, hipMemcpy(p.d_blocks, blocks.data(), sizeof(int2) * blocks.size(), hipMemcpyHostToDevice), "plan");
     auto ins = b->plans.emplace(act, p);
     *out = &ins.first->second;
     return CPIC_OK;
 }
 
-// one step of every active event: per group the field update, then the push
-// while the group's fields are cache-resident; then every event's step end
+// one step of every active event of a plan
 template <typename T> static cpic_status launch_batch_step(cpic_batch* b, const Plan& p)
 {
-    for (const Group& g : p.groups) {
-        const int* act = p.d_idx + g.first;
-        BHIP(b, launch_batch_field<T>(b->d_desc, act, p.d_idx + g.tiles_off, g.count, g.total_tiles, b->cfg, b->st),
-             "batch field");
-        BHIP(b, launch_batch_push<T>(b->d_desc, act, p.d_idx + g.blocks_off, g.count, g.total_blocks, b->tpp, b->st),
-             "batch push");
-    }
-    BHIP(b, launch_batch_step_end(b->d_desc, p.d_idx, (int)p.act.size(), b->st), "batch step end");
+    BHIP(b, launch_batch_field<T>(b->d_desc, p.d_tiles, p.total_tiles, b->cfg, b->st), "batch field");
+    BHIP(b, launch_batch_push<T>(b->d_desc, p.d_blocks, p.total_blocks, b->tpp, b->st), "batch push");
+    BHIP(b, launch_batch_step_end(b->d_desc, p.d_act, (int)p.act.size(), b->st), "batch step end");
     return CPIC_OK;
 }
 static cpic_status batch_step(cpic_batch* b, const Plan& p)
@@ -263,10 +265,10 @@ extern "C" cpic_status cpic_batch_init_mv(cpic_batch* b)
     return CPIC_OK;
 }
 
-// Advance every active event by up to max_steps batch steps (all when
-// max_steps < 0).  Segments end where an event reaches n_max or a particle
-// reordering point; inside a segment whole graphs are replayed and the rest
-// is launched step by step.
+// Advance every event by up to max_steps steps (to its end when max_steps <
+// 0), launch group after launch group.  Within a group, segments end where
+// an event reaches n_max or a particle reordering point; inside a segment
+// whole graphs are replayed and the rest is launched step by step.
 static cpic_status run_steps(cpic_batch* b, int64_t max_steps)
 {
     for (size_t e = 0; e < b->ev.size(); e++)
@@ -274,39 +276,41 @@ static cpic_status run_steps(cpic_batch* b, int64_t max_steps)
             return bfail(b, CPIC_E_INVALID, "cpic_batch_run: event " + std::to_string(e) + " has no state");
     cpic_status s = upload_desc(b);
     if (s) return s;
-    int64_t budget = max_steps < 0 ? (int64_t)1 << 40 : max_steps;
-    while (budget > 0) {
-        std::vector<int> act;
-        for (size_t e = 0; e < b->ev.size(); e++)
-            if (b->ev[e]->n < b->ev[e]->sc.n_max) act.push_back((int)e);
-        if (act.empty()) break;
-        int64_t len = budget;
-        for (int e : act) {
-            cpic_ctx* c = b->ev[e];
-            s = maybe_sort(c);
-            if (s) return bfail(b, s, "event " + std::to_string(e) + ": " + c->err);
-            len = std::min<int64_t>(len, c->sc.n_max - c->n);
-            len = std::min<int64_t>(len, next_sort_point(c, c->n) - c->n);
-        }
-        Plan* p = nullptr;
-        s = get_plan(b, act, &p);
-        if (s) return s;
-        int64_t left = len;
-        if (left >= kBatchGraphSteps && !p->graph) {
-            s = capture(b, *p);
+    for (const std::vector<int>& grp : launch_groups(b)) {
+        int64_t budget = max_steps < 0 ? (int64_t)1 << 40 : max_steps;
+        while (budget > 0) {
+            std::vector<int> act;
+            for (int e : grp)
+                if (b->ev[e]->n < b->ev[e]->sc.n_max) act.push_back(e);
+            if (act.empty()) break;
+            int64_t len = budget;
+            for (int e : act) {
+                cpic_ctx* c = b->ev[e];
+                s = maybe_sort(c);
+                if (s) return bfail(b, s, "event " + std::to_string(e) + ": " + c->err);
+                len = std::min<int64_t>(len, c->sc.n_max - c->n);
+                len = std::min<int64_t>(len, next_sort_point(c, c->n) - c->n);
+            }
+            Plan* p = nullptr;
+            s = get_plan(b, act, &p);
             if (s) return s;
+            int64_t left = len;
+            if (left >= kBatchGraphSteps && !p->graph) {
+                s = capture(b, *p);
+                if (s) return s;
+            }
+            while (left >= kBatchGraphSteps) {
+                BHIP(b, hipGraphLaunch(p->graph, b->st), "graph launch");
+                advance(b, act, kBatchGraphSteps);
+                left -= kBatchGraphSteps;
+            }
+            for (; left > 0; left--) {
+                s = batch_step(b, *p);
+                if (s) return s;
+                advance(b, act, 1);
+            }
+            budget -= len;
         }
-        while (left >= kBatchGraphSteps) {
-            BHIP(b, hipGraphLaunch(p->graph, b->st), "graph launch");
-            advance(b, act, kBatchGraphSteps);
-            left -= kBatchGraphSteps;
-        }
-        for (; left > 0; left--) {
-            s = batch_step(b, *p);
-            if (s) return s;
-            advance(b, act, 1);
-        }
-        budget -= len;
     }
     return CPIC_OK;
 }
@@ -336,75 +340,84 @@ extern "C" cpic_status cpic_batch_sync(cpic_batch* b)
 }
 
 // Field-tile tuner: the batched field launch only reads the current buffers
-// and writes the other ones, which the next step overwrites anyway, so it can
-// be repeated without changing the state.
+// and writes the other ones (and the magnetic-field pieces), which the next
+// step overwrites anyway, so it can be repeated without changing the state.
+// A candidate's time is the sum over the launch groups of one step.
 template <typename T> static cpic_status tune_batch(cpic_batch* b, int reps, std::string& rep)
 {
-    std::vector<int> act;
-    for (size_t e = 0; e < b->ev.size(); e++)
-        if (b->ev[e]->n < b->ev[e]->sc.n_max) act.push_back((int)e);
-    if (act.empty()) return CPIC_OK;
+    std::vector<std::vector<int>> groups;
+    for (const auto& g : launch_groups(b)) {
+        std::vector<int> act;
+        for (int e : g)
+            if (b->ev[e]->n < b->ev[e]->sc.n_max) act.push_back(e);
+        if (!act.empty()) groups.push_back(act);
+    }
+    if (groups.empty()) return CPIC_OK;
     cpic_status s = upload_desc(b);
     if (s) return s;
     static const int shapes[][2] = {{64, 1}, {128, 1}, {256, 1}, {32, 2}, {64, 2}, {128, 2},
                                     {16, 4}, {32, 4}, {64, 4}, {32, 8}, {16, 16}};
+    size_t most = 1;  // largest work map over shapes and groups
+    for (const auto& sh : shapes)
+        for (const auto& g : groups) {
+            LaunchCfg cfg{};
+            cfg.bx = sh[0];
+            cfg.by = sh[1];
+            size_t n = 0;
+            for (int ev : g) n += (size_t)field_tiles_host(b->ev[ev]->N, cfg);
+            most = std::max(most, n);
+        }
+    int2* d_map = nullptr;
+    BHIP(b, hipMalloc(&d_map, sizeof(int2) * most), "tune");
     hipEvent_t e0, e1;
-    BHIP(b, hipEventCreate(&e0), "tune");
-    BHIP(b, hipEventCreate(&e1), "tune");
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
     const LaunchCfg keep = b->cfg;
     LaunchCfg best = keep;
     float best_ms = 1e30f;
-    std::vector<int> idx;
-    int* d_idx = nullptr;
-    BHIP(b, hipMalloc(&d_idx, sizeof(int) * (3 * act.size() + 2)), "tune");
     char line[160];
+    std::vector<int2> map;
     for (const auto& sh : shapes)
-        for (int remap = 0; remap < 2; remap++) {
+        for (int remap = 0; remap < 2 && e == hipSuccess; remap++) {
             LaunchCfg cfg{};
             cfg.bx = sh[0];
             cfg.by = sh[1];
             cfg.xcd_remap = remap;
-            const int na = (int)act.size();
-            idx.assign(3 * (size_t)na + 2, 0);
-            int* tiles = idx.data() + na;
-            for (int k = 0; k < na; k++) {
-                idx[k] = act[k];
-                tiles[k + 1] = tiles[k] + field_tiles_host(b->ev[act[k]]->N, cfg);
+            float total = 0;
+            for (const auto& g : groups) {
+                map.clear();
+                for (int ev : g)
+                    for (int k = 0, nt = field_tiles_host(b->ev[ev]->N, cfg); k < nt; k++) map.push_back(make_int2(ev, k));
+                const int nt = (int)map.size();
+                if (e == hipSuccess) e = hipMemcpy(d_map, map.data(), sizeof(int2) * map.size(), hipMemcpyHostToDevice);
+                if (e == hipSuccess) e = launch_batch_field<T>(b->d_desc, d_map, nt, cfg, b->st);  // warm-up
+                if (e == hipSuccess) e = hipEventRecord(e0, b->st);
+                for (int r = 0; r < reps && e == hipSuccess; r++) e = launch_batch_field<T>(b->d_desc, d_map, nt, cfg, b->st);
+                if (e == hipSuccess) e = hipEventRecord(e1, b->st);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                total += ms / reps;
             }
-            hipError_t e = hipMemcpy(d_idx, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice);
-            for (int r = 0; r < 2 && e == hipSuccess; r++)  // warm-up
-                e = launch_batch_field<T>(b->d_desc, d_idx, d_idx + na, na, tiles[na], cfg, b->st);
-            if (e == hipSuccess) e = hipEventRecord(e0, b->st);
-            for (int r = 0; r < reps && e == hipSuccess; r++)
-                e = launch_batch_field<T>(b->d_desc, d_idx, d_idx + na, na, tiles[na], cfg, b->st);
-            if (e == hipSuccess) e = hipEventRecord(e1, b->st);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e != hipSuccess) {
-                hipFree(d_idx);
-                hipEventDestroy(e0);
-                hipEventDestroy(e1);
-                return bhip(b, e, "tune");
-            }
-            ms /= reps;
-            std::snprintf(line, sizeof line, "batch field %3dx%-3d remap %d : %9.2f us\n", cfg.bx, cfg.by, remap,
-                          ms * 1e3);
+            if (e != hipSuccess) break;
+            std::snprintf(line, sizeof line, "batch field %3dx%-3d remap %d : %9.2f us per step (%zu groups)\n",
+                          cfg.bx, cfg.by, remap, total * 1e3, groups.size());
             rep += line;
-            if (ms < best_ms) {
-                best_ms = ms;
+            if (total < best_ms) {
+                best_ms = total;
                 best = cfg;
             }
         }
-    hipFree(d_idx);
+    hipFree(d_map);
     hipEventDestroy(e0);
     hipEventDestroy(e1);
+    if (e != hipSuccess) return bhip(b, e, "tune");
     std::snprintf(line, sizeof line, "chosen: %dx%d remap %d (%.2f us)\n", best.bx, best.by, best.xcd_remap,
                   best_ms * 1e3);
     rep += line;
     if (best.bx != keep.bx || best.by != keep.by || best.xcd_remap != keep.xcd_remap) {
         b->cfg = best;
-        drop_plans(b);  // tile prefix tables and graphs depend on the tile shape
+        drop_plans(b);  // work maps and graphs depend on the tile shape
     }
     return CPIC_OK;
 }

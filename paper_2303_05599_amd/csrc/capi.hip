@@ -91,7 +91,7 @@ static void free_all(cpic_ctx* c)
         if (c->gexec[p]) hipGraphExecDestroy(c->gexec[p]);
     for (auto e : c->ev_field) hipEventDestroy(e);
     for (auto e : c->ev_push) hipEventDestroy(e);
-    hipFree(c->fbuf[0]); hipFree(c->fbuf[1]); hipFree(c->pr); hipFree(c->pcell);
+    hipFree(c->fbuf[0]); hipFree(c->fbuf[1]); hipFree(c->pr); hipFree(c->pcell); hipFree(c->aux);
     hipFree(c->partials); hipFree(c->obs); hipFree(c->d_step); hipFree(c->d_err); hipFree(c->d_fails);
     hipFree(c->dpart); hipFree(c->dout);
     hipFree(c->pid); hipFree(c->sb.keys); hipFree(c->sb.keys2); hipFree(c->sb.vals); hipFree(c->sb.perm);
@@ -162,6 +162,7 @@ extern "C" cpic_status cpic_create(const cpic_glasma_params* gp, const cpic_part
         const size_t np = c->np;
         e = hipMalloc(&c->pr, (size_t)kPartReals * np * c->tsz);
         if (e == hipSuccess) e = hipMalloc(&c->pcell, sizeof(int) * 2 * np);
+        if (e == hipSuccess && !c->is_static) e = hipMalloc(&c->aux, (size_t)kAuxReals * c->V * c->tsz);
         if (e == hipSuccess) e = hipMalloc(&c->pid, sizeof(int) * np);
         if (e == hipSuccess) e = hipMalloc(&c->sb.keys, sizeof(unsigned) * np);
         if (e == hipSuccess) e = hipMalloc(&c->sb.keys2, sizeof(unsigned) * np);
@@ -353,7 +354,7 @@ template <typename T> static cpic_status launch_one(cpic_ctx* c, int parity, boo
         HIPCHK(c, hipEventCreate(&e0), "event"); HIPCHK(c, hipEventCreate(&e1), "event");
         HIPCHK(c, hipEventRecord(e0, c->st), "event");
     }
-    HIPCHK(c, launch_field_step<T>(A, B, c->N, c->sc, c->d_step, c->cfg, c->st), "field step");
+    HIPCHK(c, launch_field_step<T>(A, B, static_cast<T*>(c->aux), c->N, c->sc, c->d_step, c->cfg, c->st), "field step");
     if (with_events) {
         HIPCHK(c, hipEventRecord(e1, c->st), "event");
         c->ev_field.push_back(e0); c->ev_field.push_back(e1);
@@ -364,7 +365,8 @@ template <typename T> static cpic_status launch_one(cpic_ctx* c, int parity, boo
             HIPCHK(c, hipEventCreate(&e2), "event"); HIPCHK(c, hipEventCreate(&e3), "event");
             HIPCHK(c, hipEventRecord(e2, c->st), "event");
         }
-        HIPCHK(c, launch_push<T>(A, B, P<T>(c), pa, c->d_step, c->partials, c->d_err, c->st), "push");
+        HIPCHK(c, launch_push<T>(A, B, static_cast<const T*>(c->aux), P<T>(c), pa, c->d_step, c->partials, c->d_err,
+                                 c->st), "push");
         if (with_events) {
             HIPCHK(c, hipEventRecord(e3, c->st), "event");
             c->ev_push.push_back(e2); c->ev_push.push_back(e3);
@@ -885,6 +887,7 @@ extern "C" cpic_status cpic_timing(cpic_ctx* c, double* field_ms, double* push_m
 template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::string& rep)
 {
     const Fields<T> A = F<T>(c, c->cur), B = F<T>(c, c->cur ^ 1);
+    T* const X = static_cast<T*>(c->aux);
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0), "tune");
     HIPCHK(c, hipEventCreate(&e1), "tune");
@@ -901,10 +904,10 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
         for (int waves = 1; waves <= 3; waves++)
             for (int remap = 0; remap <= 1; remap++) cands.push_back(LaunchCfg{sh[0], sh[1], remap, waves, 1});
     for (const LaunchCfg& cfg : cands) {
-                HIPCHK(c, launch_field_step<T>(A, B, c->N, c->sc, c->d_step, cfg, c->st), "tune");  // warm-up
+                HIPCHK(c, launch_field_step<T>(A, B, X, c->N, c->sc, c->d_step, cfg, c->st), "tune");  // warm-up
                 HIPCHK(c, hipEventRecord(e0, c->st), "tune");
                 for (int r = 0; r < reps; r++)
-                    HIPCHK(c, launch_field_step<T>(A, B, c->N, c->sc, c->d_step, cfg, c->st), "tune");
+                    HIPCHK(c, launch_field_step<T>(A, B, X, c->N, c->sc, c->d_step, cfg, c->st), "tune");
                 HIPCHK(c, hipEventRecord(e1, c->st), "tune");
                 HIPCHK(c, hipEventSynchronize(e1), "tune");
                 float ms = 0;
@@ -924,18 +927,15 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
         HIPCHK(c, hipMemcpyAsync(c->sb.r2, c->pr, rb, hipMemcpyDeviceToDevice, c->st), "tune");
         HIPCHK(c, hipMemcpyAsync(c->sb.cell2, c->pcell, cb, hipMemcpyDeviceToDevice, c->st), "tune");
         // the step's new momenta: run the field kernel once into the free buffer
-        HIPCHK(c, launch_field_step<T>(A, B, c->N, c->sc, c->d_step, c->cfg, c->st), "tune");
+        HIPCHK(c, launch_field_step<T>(A, B, X, c->N, c->sc, c->d_step, c->cfg, c->st), "tune");
         int best_tpp = c->tpp;
         double best_p = 1e300;
         for (int tpp : {1, 2, 4}) {
-            PushArgs pa{};
-            pa.N = c->N; pa.np = (int)c->np; pa.is_static = c->is_static; pa.tpp = tpp; pa.mhat = c->mhat;
-            for (int k = 0; k < 3; k++) pa.q0eig[k] = c->q0eig[k];
-            pa.sc = c->sc;
+            const PushArgs pa = push_args(c, tpp);
             double tot = 0;
             for (int r = 0; r <= reps; r++) {
                 HIPCHK(c, hipEventRecord(e0, c->st), "tune");
-                HIPCHK(c, launch_push<T>(A, B, P<T>(c), pa, c->d_step, c->partials, c->d_err, c->st), "tune");
+                HIPCHK(c, launch_push<T>(A, B, X, P<T>(c), pa, c->d_step, c->partials, c->d_err, c->st), "tune");
                 HIPCHK(c, hipEventRecord(e1, c->st), "tune");
                 HIPCHK(c, hipMemcpyAsync(c->pr, c->sb.r2, rb, hipMemcpyDeviceToDevice, c->st), "tune");
                 HIPCHK(c, hipMemcpyAsync(c->pcell, c->sb.cell2, cb, hipMemcpyDeviceToDevice, c->st), "tune");

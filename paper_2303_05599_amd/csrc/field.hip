@@ -42,11 +42,16 @@ template <typename T> __device__ __forceinline__ Nbr neighbours(int x, int y, in
 // The stencil is organised by link: each of the four links touching x is
 // loaded in one phase, every product it enters is formed there, and it is
 // dropped, so at most two partial plaquettes stay in registers.
-template <typename T>
+// With AUX and `aux_on`, the per-site pieces of the magnetic fields that the
+// particle push assembles at its cell are written to `aux` (24 components):
+//   G   = Proj U_12(x)                       (the clover leaves are transports of G)
+//   D_x = phi->_1(x) - phi<-_1(x),  D_y = phi->_2(x) - phi<-_2(x)
+template <typename T, bool AUX = false>
 __device__ __forceinline__ void kick_forces(const View<T>& f, const Nbr& nb, T t, T inv_t, const a8<T>& PHI,
                                             a8<T>& F1, a8<T>& F2, a8<T>& Fpi, T* re_tr_p12 = nullptr,
-                                            T* grad2 = nullptr)
+                                            T* grad2 = nullptr, const View<T>* aux = nullptr, bool aux_on = false)
 {
+    a8<T> dx, dy;
     m3<T> A12, A1m2, A2m1;
     a8<T> lap, c1, c2;
     T g2 = 0;
@@ -55,6 +60,7 @@ __device__ __forceinline__ void kick_forces(const View<T>& f, const Nbr& nb, T t
         A12 = mul(U1, vU(f, nb.xp, 1));
         A1m2 = mul_adj(U1, vU(f, nb.xpym, 1));
         const a8<T> f1 = transport(U1, vA(f, nb.xp, kCompPhi));
+        if (AUX) dx = f1;
         c1 = icomm(f1, PHI);
 #pragma unroll
         for (int a = 0; a < 8; a++) {
@@ -68,11 +74,13 @@ __device__ __forceinline__ void kick_forces(const View<T>& f, const Nbr& nb, T t
         const m3<T> U2 = vU(f, nb.s, 1);
         const m3<T> P = mul_adj(A12, mul(U2, vU(f, nb.yp, 0)));
         F1 = proj(P);
+        if (AUX && aux_on) vA_st(*aux, nb.s, 0, F1);
 #pragma unroll
         for (int a = 0; a < 8; a++) F2.v[a] = -F1.v[a];   // Proj U_21 = -Proj U_12
         if (re_tr_p12) *re_tr_p12 = P.e[0].re + P.e[4].re + P.e[8].re;
         A2m1 = mul_adj(U2, vU(f, nb.xmyp, 0));
         const a8<T> f2 = transport(U2, vA(f, nb.yp, kCompPhi));
+        if (AUX) dy = f2;
         c2 = icomm(f2, PHI);
 #pragma unroll
         for (int a = 0; a < 8; a++) {
@@ -88,6 +96,11 @@ __device__ __forceinline__ void kick_forces(const View<T>& f, const Nbr& nb, T t
         const a8<T> b2 = transport_adj(U2ym, vA(f, nb.ym, kCompPhi));
 #pragma unroll
         for (int a = 0; a < 8; a++) { F1.v[a] += p.v[a]; lap.v[a] += b2.v[a]; }
+        if (AUX && aux_on) {
+#pragma unroll
+            for (int a = 0; a < 8; a++) dy.v[a] -= b2.v[a];
+            vA_st(*aux, nb.s, 16, dy);
+        }
     }
     CPIC_PHASE();
     {   // U_1(x-1): U_{2,-1} = A2m1 [U_1(x-1)^+ U_2(x-1)]^+, phi<-_1
@@ -96,6 +109,11 @@ __device__ __forceinline__ void kick_forces(const View<T>& f, const Nbr& nb, T t
         const a8<T> b1 = transport_adj(U1xm, vA(f, nb.xm, kCompPhi));
 #pragma unroll
         for (int a = 0; a < 8; a++) { F2.v[a] += p.v[a]; lap.v[a] += b1.v[a]; }
+        if (AUX && aux_on) {
+#pragma unroll
+            for (int a = 0; a < 8; a++) dx.v[a] -= b1.v[a];
+            vA_st(*aux, nb.s, 8, dx);
+        }
     }
 #pragma unroll
     for (int a = 0; a < 8; a++) {
@@ -116,9 +134,9 @@ __device__ __forceinline__ int logical_block(int total, int remap)
     return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
 }
 
-template <typename T>
-__device__ __forceinline__ void field_step_body(const Fields<T>& in, const Fields<T>& out, int N, int bx, int by,
-                                                int tile, const Schedule& sc, const int* __restrict__ d_step)
+template <typename T, bool AUX>
+__device__ __forceinline__ void field_step_body(const Fields<T>& in, const Fields<T>& out, T* aux, int N, int bx,
+                                                int by, int tile, const Schedule& sc, const int* __restrict__ d_step)
 {
     const int ntx = (N + bx - 1) / bx;
     const int x = (tile % ntx) * bx + (int)threadIdx.x, y = (tile / ntx) * by + (int)threadIdx.y;
@@ -133,7 +151,14 @@ __device__ __forceinline__ void field_step_body(const Fields<T>& in, const Field
     const Nbr nb = neighbours<T>(x, y, N);
     a8<T> PHI = vA(vi, nb.s, kCompPhi);
     a8<T> F1 = azero<T>(), F2 = azero<T>(), Fpi = azero<T>();
-    if (kick) kick_forces(vi, nb, t, inv_t, PHI, F1, F2, Fpi);
+    // the push reads the magnetic-field pieces from the first push step on
+    // (at n = 0, t = 1/t = 0 make the forces vanish, so the kick is still skipped)
+    const bool aux_on = AUX && n >= sc.n_form;
+    if (kick || aux_on) {
+        View<T> va;
+        if (AUX) va = make_view<T>(aux, kAuxReals, V);
+        kick_forces<T, AUX>(vi, nb, t, inv_t, PHI, F1, F2, Fpi, nullptr, nullptr, &va, aux_on);
+    }
     CPIC_PHASE();
     a8<T> E1 = vA(vi, nb.s, kCompE), E2 = vA(vi, nb.s, kCompE + 8), PI = vA(vi, nb.s, kCompPi);
 #pragma unroll
@@ -165,9 +190,9 @@ __device__ __forceinline__ void field_step_body(const Fields<T>& in, const Field
 // U_ij(x) and U_{i,-j}(x), the transported scalar phi->_i and phi<-_i, updates
 // E_i and drifts U_i; the pi force is the sum of both directions' scalar terms
 // (one lane exchange, lanes l and l ^ 32), and the i = 0 thread writes phi, pi.
-template <typename T>
-__device__ __forceinline__ void field_link_body(const Fields<T>& in, const Fields<T>& out, int N, int bx, int by,
-                                                int remap, const Schedule& sc, const int* __restrict__ d_step)
+template <typename T, bool AUX>
+__device__ __forceinline__ void field_link_body(const Fields<T>& in, const Fields<T>& out, T* aux, int N, int bx,
+                                                int by, int remap, const Schedule& sc, const int* __restrict__ d_step)
 {
     const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
     const int i = lane >> 5, j = 1 - i;
@@ -208,11 +233,17 @@ __device__ __forceinline__ void field_link_body(const Fields<T>& in, const Field
     };
     const a8<T> PHI = vA(vi, s, kCompPhi);
     a8<T> F = azero<T>(), lap = azero<T>();
-    if (kick) {
+    // the push reads the magnetic-field pieces (G = Proj U_12 from the i = 0
+    // thread, D_i = phi->_i - phi<-_i) from the first push step on
+    const bool aux_on = AUX && n >= sc.n_form && live;
+    View<T> va;
+    if (AUX) va = make_view<T>(aux, 24, V);
+    if (kick || aux_on) {
         {   // U_ij(x) = U_i(x) U_j(x+i) [U_j(x) U_i(x+j)]^+
             const m3<T> Pm = mul_adj(mul(link(vi, s, i), link(vi, site(ix, iy), j)),
                                      mul(link(vi, s, j), link(vi, site(jx, jy), i)));
             F = proj(Pm);
+            if (AUX && aux_on && i == 0) vA_st(va, s, 0, F);
         }
         CPIC_PHASE();
         {   // U_{i,-j}(x) = U_i(x) U_j(x+i-j)^+ [U_j(x-j)^+ U_i(x-j)]^+
@@ -234,7 +265,14 @@ __device__ __forceinline__ void field_link_body(const Fields<T>& in, const Field
                 F.v[a] += inv_t * cm.v[a];
                 lap.v[a] = fw.v[a] + bw.v[a] - T(2) * PHI.v[a];
             }
+            if (AUX && aux_on) {
+                a8<T> d;
+#pragma unroll
+                for (int a = 0; a < 8; a++) d.v[a] = fw.v[a] - bw.v[a];
+                vA_st(va, s, 8 + 8 * i, d);
+            }
         }
+        if (!kick) F = lap = azero<T>();
     }
     // pi force: add the other direction's scalar terms
 #pragma unroll
@@ -260,23 +298,23 @@ __device__ __forceinline__ void field_link_body(const Fields<T>& in, const Field
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void field_link_kernel(Fields<T> in, Fields<T> out, int N, int bx, int by, int remap,
-                                                         Schedule sc, const int* __restrict__ d_step)
+template <typename T, bool AUX>
+__global__ __launch_bounds__(256) void field_link_kernel(Fields<T> in, Fields<T> out, T* aux, int N, int bx, int by,
+                                                         int remap, Schedule sc, const int* __restrict__ d_step)
 {
-    field_link_body(in, out, N, bx, by, remap, sc, d_step);
+    field_link_body<T, AUX>(in, out, aux, N, bx, by, remap, sc, d_step);
 }
-template <typename T>
+template <typename T, bool AUX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void field_link_kernel_w2(
-    Fields<T> in, Fields<T> out, int N, int bx, int by, int remap, Schedule sc, const int* __restrict__ d_step)
+    Fields<T> in, Fields<T> out, T* aux, int N, int bx, int by, int remap, Schedule sc, const int* __restrict__ d_step)
 {
-    field_link_body(in, out, N, bx, by, remap, sc, d_step);
+    field_link_body<T, AUX>(in, out, aux, N, bx, by, remap, sc, d_step);
 }
-template <typename T>
+template <typename T, bool AUX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void field_link_kernel_w3(
-    Fields<T> in, Fields<T> out, int N, int bx, int by, int remap, Schedule sc, const int* __restrict__ d_step)
+    Fields<T> in, Fields<T> out, T* aux, int N, int bx, int by, int remap, Schedule sc, const int* __restrict__ d_step)
 {
-    field_link_body(in, out, N, bx, by, remap, sc, d_step);
+    field_link_body<T, AUX>(in, out, aux, N, bx, by, remap, sc, d_step);
 }
 
 // Occupancy variants: W waves per SIMD requested from the register
@@ -284,20 +322,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
 // the launch tuner.
 __device__ __forceinline__ int field_tiles(int N, int bx, int by) { return ((N + bx - 1) / bx) * ((N + by - 1) / by); }
 
-template <typename T>
-__global__ __launch_bounds__(256) void field_step_kernel(Fields<T> in, Fields<T> out, int N, int bx, int by, int remap,
-                                                         Schedule sc, const int* __restrict__ d_step)
+template <typename T, bool AUX>
+__global__ __launch_bounds__(256) void field_step_kernel(Fields<T> in, Fields<T> out, T* aux, int N, int bx, int by,
+                                                         int remap, Schedule sc, const int* __restrict__ d_step)
 {
     const int nt = field_tiles(N, bx, by), tile = logical_block(nt, remap);
-    if (tile < nt) field_step_body(in, out, N, bx, by, tile, sc, d_step);
+    if (tile < nt) field_step_body<T, AUX>(in, out, aux, N, bx, by, tile, sc, d_step);
 }
 #define CPIC_FIELD_VARIANT(W)                                                                                     \
-    template <typename T>                                                                                         \
+    template <typename T, bool AUX>                                                                               \
     __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, W))) void field_step_kernel_w##W(    \
-        Fields<T> in, Fields<T> out, int N, int bx, int by, int remap, Schedule sc, const int* __restrict__ d_step) \
+        Fields<T> in, Fields<T> out, T* aux, int N, int bx, int by, int remap, Schedule sc,                       \
+        const int* __restrict__ d_step)                                                                           \
     {                                                                                                             \
         const int nt = field_tiles(N, bx, by), tile = logical_block(nt, remap);                                   \
-        if (tile < nt) field_step_body(in, out, N, bx, by, tile, sc, d_step);                                     \
+        if (tile < nt) field_step_body<T, AUX>(in, out, aux, N, bx, by, tile, sc, d_step);                        \
     }
 CPIC_FIELD_VARIANT(2)
 CPIC_FIELD_VARIANT(3)
@@ -305,62 +344,56 @@ CPIC_FIELD_VARIANT(4)
 #undef CPIC_FIELD_VARIANT
 
 // ---------------------------------------------------------------- batched events
-// One launch advances every active event by one step: logical block g maps to
-// (active event k, tile g - tile_start[k]); all events share the tile shape.
-__device__ __forceinline__ int find_event(const int* __restrict__ start, int nact, int g)
-{
-    int lo = 0, hi = nact;  // start[lo] <= g < start[hi]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (start[mid] <= g) lo = mid; else hi = mid;
-    }
-    return lo;
-}
-
+// One launch advances every event of a launch group by one step: logical
+// block g works on tile map[g].y of event map[g].x; all events share the tile
+// shape.
 template <typename T>
-__global__ __launch_bounds__(256) void batch_field_kernel(const EventDesc* __restrict__ ev, const int* __restrict__ act,
-                                                          const int* __restrict__ tile_start, int nact, int bx, int by,
+__global__ __launch_bounds__(256) void batch_field_kernel(const EventDesc* __restrict__ ev,
+                                                          const int2* __restrict__ map, int total, int bx, int by,
                                                           int remap)
 {
-    const int total = tile_start[nact];
     const int g = logical_block(total, remap);
     if (g >= total) return;
-    const int k = find_event(tile_start, nact, g);
-    const EventDesc& d = ev[act[k]];
-    const int parity = (*d.d_step & 1) ^ d.flip;
+    // the work item is uniform over the workgroup: keep it (and every address
+    // derived from it) in scalar registers
+    const int2 m = map[g];
+    const int e = __builtin_amdgcn_readfirstlane(m.x), tile = __builtin_amdgcn_readfirstlane(m.y);
+    const EventDesc& d = ev[e];
+    const int parity = __builtin_amdgcn_readfirstlane((*d.d_step & 1) ^ d.flip);
     const Fields<T> A = fields_at<T>(d.f[parity], d.N * d.N), B = fields_at<T>(d.f[parity ^ 1], d.N * d.N);
-    field_step_body(A, B, d.N, bx, by, g - tile_start[k], d.pa.sc, d.d_step);
+    // events without dynamic particles have no magnetic-field pieces to write
+    if (d.aux)
+        field_step_body<T, true>(A, B, static_cast<T*>(d.aux), d.N, bx, by, tile, d.pa.sc, d.d_step);
+    else
+        field_step_body<T, false>(A, B, nullptr, d.N, bx, by, tile, d.pa.sc, d.d_step);
 }
 
 template <typename T>
-hipError_t launch_batch_field(const EventDesc* ev, const int* act, const int* tile_start, int nact, int total_tiles,
-                              const LaunchCfg& cfg, hipStream_t st)
+hipError_t launch_batch_field(const EventDesc* ev, const int2* map, int total_tiles, const LaunchCfg& cfg,
+                              hipStream_t st)
 {
     if (cfg.split || cfg.bx * cfg.by > 256 || total_tiles <= 0) return hipErrorInvalidValue;
     const int grid = cfg.xcd_remap ? 8 * ((total_tiles + 7) / 8) : total_tiles;
-    hipLaunchKernelGGL(batch_field_kernel<T>, dim3(grid), dim3(cfg.bx, cfg.by), 0, st, ev, act, tile_start, nact, cfg.bx,
+    hipLaunchKernelGGL(batch_field_kernel<T>, dim3(grid), dim3(cfg.bx, cfg.by), 0, st, ev, map, total_tiles, cfg.bx,
                        cfg.by, cfg.xcd_remap);
     return hipGetLastError();
 }
-template hipError_t launch_batch_field<double>(const EventDesc*, const int*, const int*, int, int, const LaunchCfg&,
-                                               hipStream_t);
-template hipError_t launch_batch_field<float>(const EventDesc*, const int*, const int*, int, int, const LaunchCfg&,
-                                              hipStream_t);
+template hipError_t launch_batch_field<double>(const EventDesc*, const int2*, int, const LaunchCfg&, hipStream_t);
+template hipError_t launch_batch_field<float>(const EventDesc*, const int2*, int, const LaunchCfg&, hipStream_t);
 
-template <typename T>
-hipError_t launch_field_step(const Fields<T>& in, const Fields<T>& out, int N, const Schedule& sc,
-                             const int* d_step, const LaunchCfg& cfg, hipStream_t st)
+template <typename T, bool AUX>
+static hipError_t launch_field_step_t(const Fields<T>& in, const Fields<T>& out, T* aux, int N, const Schedule& sc,
+                                      const int* d_step, const LaunchCfg& cfg, hipStream_t st)
 {
-    if (cfg.bx <= 0 || cfg.by <= 0 || cfg.waves < 1 || cfg.waves > 4) return hipErrorInvalidValue;
     if (cfg.split) {
         // 128 sites (256 link threads) per block
         if (cfg.bx * cfg.by != 128 || cfg.bx % 32 != 0) return hipErrorInvalidValue;
         const int ntiles = ((N + cfg.bx - 1) / cfg.bx) * ((N + cfg.by - 1) / cfg.by);
         const dim3 g(cfg.xcd_remap ? 8 * ((ntiles + 7) / 8) : ntiles), blk(256);
         switch (cfg.waves) {
-        case 2: hipLaunchKernelGGL(field_link_kernel_w2<T>, g, blk, 0, st, in, out, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
-        case 3: hipLaunchKernelGGL(field_link_kernel_w3<T>, g, blk, 0, st, in, out, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
-        default: hipLaunchKernelGGL(field_link_kernel<T>, g, blk, 0, st, in, out, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step);
+        case 2: hipLaunchKernelGGL((field_link_kernel_w2<T, AUX>), g, blk, 0, st, in, out, aux, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
+        case 3: hipLaunchKernelGGL((field_link_kernel_w3<T, AUX>), g, blk, 0, st, in, out, aux, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
+        default: hipLaunchKernelGGL((field_link_kernel<T, AUX>), g, blk, 0, st, in, out, aux, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step);
         }
         return hipGetLastError();
     }
@@ -370,12 +403,21 @@ hipError_t launch_field_step(const Fields<T>& in, const Fields<T>& out, int N, c
     const int grid = cfg.xcd_remap ? 8 * ((ntiles + 7) / 8) : ntiles;
     const dim3 g(grid), b(cfg.bx, cfg.by);
     switch (cfg.waves) {
-    case 2: hipLaunchKernelGGL(field_step_kernel_w2<T>, g, b, 0, st, in, out, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
-    case 3: hipLaunchKernelGGL(field_step_kernel_w3<T>, g, b, 0, st, in, out, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
-    case 4: hipLaunchKernelGGL(field_step_kernel_w4<T>, g, b, 0, st, in, out, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
-    default: hipLaunchKernelGGL(field_step_kernel<T>, g, b, 0, st, in, out, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step);
+    case 2: hipLaunchKernelGGL((field_step_kernel_w2<T, AUX>), g, b, 0, st, in, out, aux, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
+    case 3: hipLaunchKernelGGL((field_step_kernel_w3<T, AUX>), g, b, 0, st, in, out, aux, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
+    case 4: hipLaunchKernelGGL((field_step_kernel_w4<T, AUX>), g, b, 0, st, in, out, aux, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
+    default: hipLaunchKernelGGL((field_step_kernel<T, AUX>), g, b, 0, st, in, out, aux, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step);
     }
     return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_field_step(const Fields<T>& in, const Fields<T>& out, T* aux, int N, const Schedule& sc,
+                             const int* d_step, const LaunchCfg& cfg, hipStream_t st)
+{
+    if (cfg.bx <= 0 || cfg.by <= 0 || cfg.waves < 1 || cfg.waves > 4) return hipErrorInvalidValue;
+    return aux ? launch_field_step_t<T, true>(in, out, aux, N, sc, d_step, cfg, st)
+               : launch_field_step_t<T, false>(in, out, nullptr, N, sc, d_step, cfg, st);
 }
 
 // ------------------------------------------------------------------ diagnostics
@@ -451,9 +493,9 @@ hipError_t launch_field_diag(const Fields<T>& f, int N, double dt, int n, double
     return hipGetLastError();
 }
 
-template hipError_t launch_field_step<double>(const Fields<double>&, const Fields<double>&, int, const Schedule&,
-                                              const int*, const LaunchCfg&, hipStream_t);
-template hipError_t launch_field_step<float>(const Fields<float>&, const Fields<float>&, int, const Schedule&,
+template hipError_t launch_field_step<double>(const Fields<double>&, const Fields<double>&, double*, int,
+                                              const Schedule&, const int*, const LaunchCfg&, hipStream_t);
+template hipError_t launch_field_step<float>(const Fields<float>&, const Fields<float>&, float*, int, const Schedule&,
                                              const int*, const LaunchCfg&, hipStream_t);
 template hipError_t launch_field_diag<double>(const Fields<double>&, int, double, int, double*, int, int*,
                                               hipStream_t);

@@ -80,6 +80,7 @@ struct EventDesc {
     void* f[2];        // field buffer sets; the state at step n is in f[(n & 1) ^ flip]
     int flip;
     void* pr;          // particle records [18][np]
+    void* aux;         // [24][V] magnetic-field pieces (NULL without dynamic particles)
     int* cell;         // [2][np]
     int N;
     PushArgs pa;
@@ -89,6 +90,7 @@ struct EventDesc {
     double* obs;       // [slots][4]
 };
 
+// particle blocks of the push: 256 / tpp particles per block
 __host__ __device__ inline int push_blocks_d(int np, int tpp)
 {
     const int ppb = 256 / (tpp > 0 ? tpp : 1);
@@ -96,27 +98,30 @@ __host__ __device__ inline int push_blocks_d(int np, int tpp)
 }
 
 // ---- field kernels (field.hip)
+// aux (may be NULL): [24][V] magnetic-field pieces for the push, written from
+// step n_form on: Proj U_12 (8), phi->_x - phi<-_x (8), phi->_y - phi<-_y (8)
+constexpr int kAuxReals = 24;
 template <typename T>
-hipError_t launch_field_step(const Fields<T>& in, const Fields<T>& out, int N, const Schedule& sc,
+hipError_t launch_field_step(const Fields<T>& in, const Fields<T>& out, T* aux, int N, const Schedule& sc,
                              const int* d_step, const LaunchCfg& cfg, hipStream_t st);
 template <typename T>
 hipError_t launch_field_diag(const Fields<T>& f, int N, double dt, int n, double* partials, int nblk_cap,
                              int* nblk_out, hipStream_t st);
-// batched launches over the active events act[0..nact): logical blocks
-// [start[k], start[k+1]) belong to event act[k]
+// batched launches: logical block g works on tile (particle block) map[g].y
+// of event map[g].x of the descriptor table
 template <typename T>
-hipError_t launch_batch_field(const EventDesc* ev, const int* act, const int* tile_start, int nact, int total_tiles,
-                              const LaunchCfg& cfg, hipStream_t st);
+hipError_t launch_batch_field(const EventDesc* ev, const int2* map, int total_tiles, const LaunchCfg& cfg,
+                              hipStream_t st);
 
 // ---- particle kernels (push.hip)
-// push at t_n: A holds U(n), phi(n), E(n-1/2), pi(n-1/2); B holds E(n+1/2), pi(n+1/2)
+// push at t_n: A holds U(n), phi(n), E(n-1/2), pi(n-1/2); B holds E(n+1/2), pi(n+1/2);
+// aux the magnetic-field pieces of step n (unused for static particles)
 template <typename T>
-hipError_t launch_push(const Fields<T>& A, const Fields<T>& B, const Parts<T>& P, const PushArgs& a,
+hipError_t launch_push(const Fields<T>& A, const Fields<T>& B, const T* aux, const Parts<T>& P, const PushArgs& a,
                        const int* d_step, double* partials, int* err, hipStream_t st);
 int push_blocks(int np, int tpp);
 template <typename T>
-hipError_t launch_batch_push(const EventDesc* ev, const int* act, const int* blk_start, int nact, int total_blocks,
-                             int tpp, hipStream_t st);
+hipError_t launch_batch_push(const EventDesc* ev, const int2* map, int total_blocks, int tpp, hipStream_t st);
 hipError_t launch_batch_step_end(const EventDesc* ev, const int* act, int nact, hipStream_t st);
 hipError_t launch_reduce_rows(const double* partials, int nrows, int ncols, double* out, hipStream_t st);
 // end of a step: on recording steps add the block partials of the step's slot

@@ -110,126 +110,115 @@ template <typename T> __device__ a8<T> renorm_charge(const a8<T>& Q, const doubl
 // loaded (and held in registers) during another
 #define CPIC_PHASE() __builtin_amdgcn_sched_barrier(0)
 
-// Q . F for the six colour fields at site c, time t_n (Sec. III.B
-// interpolations), hat units:
-//   out[0..2] = Q.E_x, Q.E_y, Q.E_eta ; out[3..5] = Q.B_x, Q.B_y, Q.B_eta
-// Work split when several lanes share one particle (TPP lanes, role = lane
-// index within the particle): each role evaluates a subset of the six field
-// contractions and leaves the others zero; the lanes then add their results.
-//   TPP = 1: everything.
-//   TPP = 2: role 0 E_x, E_y, B_x, B_y; role 1 E_eta and the clover.
-//   TPP = 4: role 0 E_x and B_y; role 1 E_y and B_x; role 2 E_eta and clover
-//            leaves 0, 1; role 3 clover leaves 2, 3.
-template <int TPP> __device__ __forceinline__ bool does_E(int role, int i)
-{
-    return TPP == 1 || (TPP == 2 ? role == 0 : role == i);
-}
-template <int TPP> __device__ __forceinline__ bool does_Eeta(int role) { return TPP == 1 || (TPP == 2 ? role == 1 : role == 2); }
-template <int TPP> __device__ __forceinline__ bool does_Bt(int role, int i)   // i = 0: B_y (phi along x), 1: B_x
-{
-    return TPP == 1 || (TPP == 2 ? role == 0 : role == i);
-}
-template <int TPP> __device__ __forceinline__ int leaf_begin(int role) { return TPP == 1 ? 0 : (TPP == 2 ? (role == 1 ? 0 : 4) : (role == 2 ? 0 : (role == 3 ? 2 : 4))); }
-template <int TPP> __device__ __forceinline__ int leaf_end(int role) { return TPP == 1 ? 4 : (TPP == 2 ? 4 : (role == 2 ? 2 : 4)); }
+// The colour fields at the particle's cell c at time t_n (Sec. III.B
+// interpolations, hat units) enter the push only through Q.F, so each field
+// is first evaluated as an algebra vector F that does not involve Q:
+//   E_i  = (1/4t) [E_i(c) + U_i(c-i)^+ E_i(c-i) U_i(c-i)], E summed over the
+//          two half steps (n > 0; E_i = 0 at n = 0)
+//   E_eta = (pi(n-1/2) + pi(n+1/2))(c) / 2   (n > 0), pi(1/2)(c) at n = 0
+//   B_x  = -(1/2t) [U_y(c) phi(c+y) U_y(c)^+ - U_y(c-y)^+ phi(c-y) U_y(c-y)] = -(1/2t) D_y(c)
+//   B_y  = +(1/2t) [U_x(c) phi(c+x) U_x(c)^+ - U_x(c-x)^+ phi(c-x) U_x(c-x)] = +(1/2t) D_x(c)
+//   B_eta = -(1/4) Proj[U_12 + U_{2,-1} + U_{-1,-2} + U_{-2,1}] (clover, all
+//          counter-clockwise).
+// Each clover leaf is the plaquette of a neighbouring cell carried to c by
+// the links between: with G(x) = Proj U_12(x) and unitary links,
+//   Proj U_{2,-1}(c)  = U_1(c-1)^+ G(c-1) U_1(c-1)
+//   Proj U_{-1,-2}(c) = U_1(c-1)^+ U_2(c-1-2)^+ G(c-1-2) U_2(c-1-2) U_1(c-1)
+//   Proj U_{-2,1}(c)  = U_2(c-2)^+ G(c-2) U_2(c-2)
+// The field update writes G and D_x, D_y for every site (the aux buffer), so
+// the push reads four G's and three links instead of sixteen links.
+// Six jobs: E_x, E_y, E_eta, B_x, B_y, B_eta.  The TPP waves that share a
+// group of 64 particles split them; the owner wave (role 0) meanwhile rotates
+// Q, and contracts everything with Q at the end.
+enum PushJob { kJobEx = 0, kJobEy, kJobEeta, kJobBx, kJobBy, kJobBeta, kJobs };
 
-template <typename T, int TPP>
-__device__ __forceinline__ void forces_dot(const View<T>& A, const View<T>& B, int N, int cx, int cy, int n, T t,
-                                           bool electric_only, const a8<T>& Q, T* out, int role)
+// Job -> (wave, LDS slot within the wave), 4 bits per job in job order
+//   TPP 2: owner E_x E_eta B_x B_y | wave 1: E_y (slot 0), B_eta (slot 1)
+//   TPP 4: owner E_eta B_x B_y | 1: E_x | 2: E_y | 3: B_eta
+constexpr uint32_t pack_jobs(int e_x, int e_y, int e_eta, int b_x, int b_y, int b_eta)
+{
+    return (uint32_t)e_x | (uint32_t)e_y << 4 | (uint32_t)e_eta << 8 | (uint32_t)b_x << 12 | (uint32_t)b_y << 16 |
+           (uint32_t)b_eta << 20;
+}
+template <int TPP> __device__ __forceinline__ int job_wave(int j)
+{
+    constexpr uint32_t tab = TPP == 2 ? pack_jobs(0, 1, 0, 0, 0, 1) : TPP == 4 ? pack_jobs(1, 2, 0, 0, 0, 3) : 0;
+    return (int)((tab >> (4 * j)) & 15u);
+}
+template <int TPP> __device__ __forceinline__ int job_slot(int j)
+{
+    constexpr uint32_t tab = TPP == 2 ? pack_jobs(0, 0, 0, 0, 0, 1) : 0;
+    return (int)((tab >> (4 * j)) & 15u);
+}
+template <int TPP> constexpr int kSlots = TPP == 2 ? 2 : 1;  // LDS slots per helper wave
+
+// the cell and the neighbours the push reads, as byte offsets into a component array
+struct Cell {
+    uint32_t s, s_xm, s_ym, s_xmym;
+};
+template <typename T> __device__ __forceinline__ Cell make_cell(int cx, int cy, int N)
 {
     constexpr uint32_t b = sizeof(T);
-    const int xm = wrap(cx - 1, N), xp = wrap(cx + 1, N), ym = wrap(cy - 1, N), yp = wrap(cy + 1, N);
-    const uint32_t s = (uint32_t)(cy * N + cx) * b;
-    const uint32_t s_xm = (uint32_t)(cy * N + xm) * b, s_xp = (uint32_t)(cy * N + xp) * b;
-    const uint32_t s_ym = (uint32_t)(ym * N + cx) * b, s_yp = (uint32_t)(yp * N + cx) * b;
-    out[0] = out[1] = out[2] = out[3] = out[4] = out[5] = T(0);
-    if (n > 0) {
+    const int xm = wrap(cx - 1, N), ym = wrap(cy - 1, N);
+    return {(uint32_t)(cy * N + cx) * b, (uint32_t)(cy * N + xm) * b, (uint32_t)(ym * N + cx) * b,
+            (uint32_t)(ym * N + xm) * b};
+}
+
+__device__ __forceinline__ bool job_active(int j, int n, bool electric_only)
+{
+    if (j == kJobEeta) return true;
+    if (j <= kJobEy) return n > 0;
+    if (j <= kJobBy) return n > 0 && !electric_only;
+    return !electric_only;
+}
+
+template <typename T>
+__device__ __forceinline__ a8<T> job_field(int j, const View<T>& A, const View<T>& B, const View<T>& X, const Cell& c,
+                                           int n, T t)
+{
+    a8<T> F;
+    if (j <= kJobEy) {
+        const int i = j;
+        const uint32_t sb = i == 0 ? c.s_xm : c.s_ym;
+        const uint32_t ce = kCompE + 8 * i;
+        a8<T> here, back;
+#pragma unroll
+        for (int a = 0; a < 8; a++) {
+            here.v[a] = bld(A, c.s, ce + a) + bld(B, c.s, ce + a);
+            back.v[a] = bld(A, sb, ce + a) + bld(B, sb, ce + a);
+        }
+        const a8<T> tb = transport_adj(vU(A, sb, i), back);
         const T q = T(1) / (T(4) * t);
 #pragma unroll
-        for (int i = 0; i < 2; i++) {
-            if (!does_E<TPP>(role, i)) continue;
-            const uint32_t sb = i == 0 ? s_xm : s_ym;
-            const uint32_t ce = kCompE + 8 * i;
-            a8<T> here, back;
+        for (int a = 0; a < 8; a++) F.v[a] = q * (here.v[a] + tb.v[a]);
+    } else if (j == kJobEeta) {
+        if (n > 0) {
 #pragma unroll
-            for (int a = 0; a < 8; a++) {
-                here.v[a] = bld(A, s, ce + a) + bld(B, s, ce + a);
-                back.v[a] = bld(A, sb, ce + a) + bld(B, sb, ce + a);
-            }
-            // Q.(U^+ X U) = (U Q U^+).X
-            const a8<T> qb = transport(vU(A, sb, i), Q);
-            out[i] = q * (dot(Q, here) + dot(qb, back));
-            CPIC_PHASE();
+            for (int a = 0; a < 8; a++) F.v[a] = T(0.5) * (bld(A, c.s, kCompPi + a) + bld(B, c.s, kCompPi + a));
+        } else {
+            F = vA(B, c.s, kCompPi);
         }
-        if (does_Eeta<TPP>(role)) {
-            T e = 0;
+    } else if (j <= kJobBy) {
+        // B_x = -(1/2t) D_y (aux components 16..23), B_y = +(1/2t) D_x (8..15)
+        const bool bx = j == kJobBx;
+        const T q = (bx ? T(-1) : T(1)) / (T(2) * t);
+        const a8<T> D = vA(X, c.s, bx ? 16u : 8u);
 #pragma unroll
-            for (int a = 0; a < 8; a++) e += Q.v[a] * (bld(A, s, kCompPi + a) + bld(B, s, kCompPi + a));
-            out[2] = T(0.5) * e;
-        }
-    } else if (does_Eeta<TPP>(role)) {
-        T e = 0;
+        for (int a = 0; a < 8; a++) F.v[a] = q * D.v[a];
+    } else {
+        const a8<T> g2 = transport_adj(vU(A, c.s_ym, 1), vA(X, c.s_ym, 0));
+        CPIC_PHASE();
+        const a8<T> g12 = transport_adj(vU(A, c.s_xmym, 1), vA(X, c.s_xmym, 0));
+        a8<T> g1 = vA(X, c.s_xm, 0);
 #pragma unroll
-        for (int a = 0; a < 8; a++) e += Q.v[a] * bld(B, s, kCompPi + a);
-        out[2] = e;
+        for (int a = 0; a < 8; a++) g1.v[a] += g12.v[a];
+        CPIC_PHASE();
+        const a8<T> g1t = transport_adj(vU(A, c.s_xm, 0), g1);
+        const a8<T> g0 = vA(X, c.s, 0);
+#pragma unroll
+        for (int a = 0; a < 8; a++) F.v[a] = T(-0.25) * (g0.v[a] + g1t.v[a] + g2.v[a]);
     }
-    if (electric_only) return;
-    CPIC_PHASE();
-    if (n > 0) {
-        // B_x = -(phi->_y - phi<-_y)/(2t), B_y = +(phi->_x - phi<-_x)/(2t);
-        // Q.(U X U^+) = (U^+ Q U).X and Q.(U^+ X U) = (U Q U^+).X
-        const T q = T(1) / (T(2) * t);
-        if (does_Bt<TPP>(role, 1)) {
-            T fy, by;
-            { const a8<T> w = transport_adj(vU(A, s, 1), Q);    fy = dot(w, vA(A, s_yp, kCompPhi)); }
-            CPIC_PHASE();
-            { const a8<T> w = transport(vU(A, s_ym, 1), Q);     by = dot(w, vA(A, s_ym, kCompPhi)); }
-            out[3] = -q * (fy - by);
-            CPIC_PHASE();
-        }
-        if (does_Bt<TPP>(role, 0)) {
-            T fx, bx;
-            { const a8<T> w = transport_adj(vU(A, s, 0), Q);    fx = dot(w, vA(A, s_xp, kCompPhi)); }
-            CPIC_PHASE();
-            { const a8<T> w = transport(vU(A, s_xm, 0), Q);     bx = dot(w, vA(A, s_xm, kCompPhi)); }
-            out[4] = q * (fx - bx);
-            CPIC_PHASE();
-        }
-    }
-    // B_eta = -(1/4) Proj[U_12 + U_{2,-1} + U_{-1,-2} + U_{-2,1}] (clover, all
-    // counter-clockwise).  Each leaf is a product of four links; leaf k,
-    // factor f is link `dir` at (x + dx, y + dy), daggered if `dg`, packed as
-    // dx+1 | (dy+1) << 2 | dir << 4 | dg << 5.  The loop is kept rolled so
-    // only one leaf's links are live at a time.
-    //   U_12      = U_1(x) U_2(x+1) U_1(x+2)^+ U_2(x)^+
-    //   U_{2,-1}  = U_2(x) U_1(x-1+2)^+ U_2(x-1)^+ U_1(x-1)
-    //   U_{-1,-2} = U_1(x-1)^+ U_2(x-1-2)^+ U_1(x-1-2) U_2(x-2)
-    //   U_{-2,1}  = U_2(x-2)^+ U_1(x-2) U_2(x+1-2) U_1(x)^+
-    constexpr uint64_t L0 = (1 | 1 << 2 | 0 << 4 | 0 << 5) | (2 | 1 << 2 | 1 << 4 | 0 << 5) << 6 |
-                            (1 | 2 << 2 | 0 << 4 | 1 << 5) << 12 | (1 | 1 << 2 | 1 << 4 | 1 << 5) << 18;
-    constexpr uint64_t L1 = (1 | 1 << 2 | 1 << 4 | 0 << 5) | (0 | 2 << 2 | 0 << 4 | 1 << 5) << 6 |
-                            (0 | 1 << 2 | 1 << 4 | 1 << 5) << 12 | (0 | 1 << 2 | 0 << 4 | 0 << 5) << 18;
-    constexpr uint64_t L2 = (0 | 1 << 2 | 0 << 4 | 1 << 5) | (0 | 0 << 2 | 1 << 4 | 1 << 5) << 6 |
-                            (0 | 0 << 2 | 0 << 4 | 0 << 5) << 12 | (1 | 0 << 2 | 1 << 4 | 0 << 5) << 18;
-    constexpr uint64_t L3 = (1 | 0 << 2 | 1 << 4 | 1 << 5) | (1 | 0 << 2 | 0 << 4 | 0 << 5) << 6 |
-                            (2 | 0 << 2 | 1 << 4 | 0 << 5) << 12 | (1 | 1 << 2 | 0 << 4 | 1 << 5) << 18;
-    constexpr uint64_t kLeaf01 = L0 | L1 << 32, kLeaf23 = L2 | L3 << 32;
-    T be = 0;
-#pragma unroll 1
-    for (int k = leaf_begin<TPP>(role); k < leaf_end<TPP>(role); k++) {
-        const uint32_t code = (uint32_t)(((k < 2 ? kLeaf01 : kLeaf23) >> (32 * (k & 1))) & 0xFFFFFFu);
-        m3<T> W;
-#pragma unroll
-        for (int fct = 0; fct < 4; fct++) {
-            const uint32_t c = (code >> (6 * fct)) & 63u;
-            const int dx = (int)(c & 3u) - 1, dy = (int)((c >> 2) & 3u) - 1, dir = (c >> 4) & 1u;
-            const uint32_t so = (uint32_t)(wrap(cy + dy, N) * N + wrap(cx + dx, N)) * b;
-            m3<T> L = vU(A, so, dir);
-            if (c & 32u) L = adj(L);
-            W = fct == 0 ? L : mul(W, L);
-        }
-        be += dot(Q, proj(W));
-    }
-    out[5] = T(-0.25) * be;
+    return F;
 }
 
 // particle block b of the grid -> logical block: consecutive logical blocks
@@ -240,37 +229,41 @@ __device__ __forceinline__ int xcd_block(int nblocks)
     return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
 }
 
-// TPP wavefronts per group of 64 particles: a block of 256 threads (4 waves)
-// handles 256 / TPP particles; wave w works on particle group w / TPP in role
-// w % TPP, so every wave follows one uniform path.  The role-0 wave owns the
-// particle state: it rotates Q and publishes it in LDS; every role adds its
-// field contractions into LDS; the role-0 wave then takes the Euler step.
+// TPP wavefronts per group of 64 particles: a block of 256 threads holds
+// 256 / TPP particles.  Wave w works on particle group w / TPP in role
+// w % TPP, so every wave follows one uniform path.  The role-0 wave owns the particle state: it
+// rotates Q while the helper waves evaluate their field vectors into LDS; after
+// one barrier it contracts all of them with Q and takes the Euler step.
+template <int TPP> constexpr int kPushPPB = 256 / TPP;  // particles per block
+
 template <typename T, int TPP>
-__device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& Bf, const Parts<T>& P,
+__device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& Bf, const T* aux, const Parts<T>& P,
                                           const PushArgs& a, const int* __restrict__ d_step, double* partials,
                                           int* err, int blk)
 {
     const int n = *d_step;
     if (n < a.sc.n_form || n >= a.sc.n_max) return;  // uniform over the event
-    constexpr int PPB = 256 / TPP;                   // particles per block
-    constexpr int NG = 4 / TPP;                      // particle groups (of 64) per block
+    constexpr int PPB = kPushPPB<TPP>;
+    constexpr int NG = PPB / 64;                     // particle groups per block
+    constexpr int S = kSlots<TPP>;
     const int nblocks = (a.np + PPB - 1) / PPB;
     const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
     const int role = wave % TPP, grp = wave / TPP;
     const int p = blk * PPB + grp * 64 + lane;
-    __shared__ T shQ[NG][8][64];
-    __shared__ T shF[4][6][64];
+    // helper-wave field vectors: row ((grp * (TPP-1) + role-1) * S + slot) * 8 + a
+    __shared__ T shF[TPP > 1 ? NG * (TPP - 1) * S * 8 : 1][64];
     const int N = a.N, np = a.np;
     const uint32_t V = (uint32_t)N * N;
     const View<T> A = make_view<T>(Af.U, kRealsPerSite, V), B = make_view<T>(Bf.U, kRealsPerSite, V);
+    const View<T> X = make_view<T>(aux ? aux : Af.U, kAuxReals, V);  // not read for static particles
     const View<T> R = make_view<T>(P.r, kPartReals, (uint32_t)np);
     const View<int> C = make_view<int>(P.cell, 2, (uint32_t)np);
     const T dt = T(a.sc.dt), t = T(n * a.sc.dt);
     const int record_slot = is_record_step(a.sc, n) ? record_slot_of(a.sc, n) : -1;
     const bool renorm = is_reunit_step(a.sc, n);
+    const bool eonly = a.is_static != 0;
     const bool live = p < np;
     const uint32_t po = (uint32_t)(live ? p : 0) * sizeof(T), pi = (uint32_t)(live ? p : 0) * sizeof(int);
-    a8<T> Q;
     int nx = 0, ny = 0;
     T x = 0, y = 0;
     if (a.is_static) {
@@ -284,6 +277,9 @@ __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& 
         nx = nx >= N ? nx - N : nx;
         ny = ny >= N ? ny - N : ny;
     }
+    const Cell cell = make_cell<T>(nx, ny, N);
+    a8<T> Q;
+    T f[6] = {0, 0, 0, 0, 0, 0};
     if (role == 0) {
 #pragma unroll
         for (int q = 0; q < 8; q++) Q.v[q] = bld(R, po, PQ0 + q);
@@ -306,36 +302,57 @@ __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& 
                 if (ax == 0) cx = nx; else cy = ny;
             }
             const T deta = bld(R, po, PDETA);
-            if (deta != T(0)) Q = rotate(expi(vA(A, (uint32_t)(ny * N + nx) * (uint32_t)sizeof(T), kCompPhi), deta), Q);
+            if (deta != T(0)) Q = rotate(expi(vA(A, cell.s, kCompPhi), deta), Q);
         }
-        if (!a.is_static && renorm && live) Q = renorm_charge(Q, a.q0eig);
-        if (TPP > 1) {
+        // charges are renormalised in single precision only (double-precision
+        // contexts never schedule it); leaving it out of the double kernel
+        // also keeps its trigonometric calls from needing scratch memory
+        if constexpr (sizeof(T) == 4)
+            if (!a.is_static && renorm && live) Q = renorm_charge(Q, a.q0eig);
+        CPIC_PHASE();
+        if (live) {
+#pragma unroll 1
+            for (int j = 0; j < kJobs; j++) {
+                if (job_wave<TPP>(j) != 0 || !job_active(j, n, eonly)) continue;
+                const T dq = dot(Q, job_field<T>(j, A, B, X, cell, n, t));
+                const int k = j;  // job j yields force component j
 #pragma unroll
-            for (int q = 0; q < 8; q++) shQ[grp][q][lane] = Q.v[q];
+                for (int kk = 0; kk < 6; kk++) f[kk] += kk == k ? dq : T(0);
+            }
+        }
+    } else if (TPP > 1) {
+        const int row0 = (grp * (TPP - 1) + role - 1) * S * 8;
+#pragma unroll
+        for (int r = 0; r < S * 8; r++) shF[row0 + r][lane] = T(0);
+        if (live) {
+#pragma unroll 1
+            for (int j = 0; j < kJobs; j++) {
+                if (job_wave<TPP>(j) != role || !job_active(j, n, eonly)) continue;
+                const a8<T> F = job_field<T>(j, A, B, X, cell, n, t);
+                const int r = row0 + job_slot<TPP>(j) * 8;
+#pragma unroll
+                for (int q = 0; q < 8; q++) shF[r + q][lane] += F.v[q];
+            }
         }
     }
     if (TPP > 1) {
         __syncthreads();
-        if (role != 0) {
+        if (role == 0 && live) {
 #pragma unroll
-            for (int q = 0; q < 8; q++) Q.v[q] = shQ[grp][q][lane];
-        }
-    }
-    CPIC_PHASE();
-    T f[6];
-    if (live) forces_dot<T, TPP>(A, B, N, nx, ny, n, t, a.is_static != 0, Q, f, role);
-    else f[0] = f[1] = f[2] = f[3] = f[4] = f[5] = T(0);
-    if (TPP > 1) {
+            for (int j = 0; j < kJobs; j++) {
+                const int w = job_wave<TPP>(j);
+                bool first = w != 0;  // the first job of each helper (wave, slot) stands for the slot
 #pragma unroll
-        for (int k = 0; k < 6; k++) shF[wave][k][lane] = f[k];
-        __syncthreads();
-        if (role == 0) {
+                for (int i = 0; i < j; i++)
+                    if (job_wave<TPP>(i) == w && job_slot<TPP>(i) == job_slot<TPP>(j)) first = false;
+                if (!first) continue;
+                const int r = ((grp * (TPP - 1) + w - 1) * S + job_slot<TPP>(j)) * 8;
+                T dq = Q.v[0] * shF[r][lane];
 #pragma unroll
-            for (int k = 0; k < 6; k++) {
-                T acc = shF[wave][k][lane];
+                for (int q = 1; q < 8; q++) dq = fmaT(Q.v[q], shF[r + q][lane], dq);
+                const int k = j;  // job j yields force component j
 #pragma unroll
-                for (int r = 1; r < TPP; r++) acc += shF[wave + r][k][lane];
-                f[k] = acc;
+                for (int kk = 0; kk < 6; kk++) f[kk] += kk == k ? dq : T(0);
             }
         }
     }
@@ -396,36 +413,29 @@ __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& 
 }
 
 template <typename T, int TPP>
-__global__ __launch_bounds__(256) void push_kernel(Fields<T> Af, Fields<T> Bf, Parts<T> P, PushArgs a,
+__global__ __launch_bounds__(256) void push_kernel(Fields<T> Af, Fields<T> Bf, const T* aux, Parts<T> P, PushArgs a,
                                                    const int* __restrict__ d_step, double* partials, int* err)
 {
-    const int nblocks = (a.np + 256 / TPP - 1) / (256 / TPP);
+    const int nblocks = (a.np + kPushPPB<TPP> - 1) / kPushPPB<TPP>;
     const int blk = xcd_block(nblocks);
-    if (blk < nblocks) push_body<T, TPP>(Af, Bf, P, a, d_step, partials, err, blk);
+    if (blk < nblocks) push_body<T, TPP>(Af, Bf, aux, P, a, d_step, partials, err, blk);
 }
 
-// batched events: logical block g -> (active event k, block g - blk_start[k])
-__device__ __forceinline__ int find_event_p(const int* __restrict__ start, int nact, int g)
-{
-    int lo = 0, hi = nact;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (start[mid] <= g) lo = mid; else hi = mid;
-    }
-    return lo;
-}
+// batched events: logical block g works on particle block map[g].y of event map[g].x
 template <typename T, int TPP>
-__global__ __launch_bounds__(256) void batch_push_kernel(const EventDesc* __restrict__ ev, const int* __restrict__ act,
-                                                         const int* __restrict__ blk_start, int nact)
+__global__ __launch_bounds__(256) void batch_push_kernel(const EventDesc* __restrict__ ev, const int2* __restrict__ map,
+                                                         int total)
 {
-    const int total = blk_start[nact];
     const int g = xcd_block(total);
     if (g >= total) return;
-    const int k = find_event_p(blk_start, nact, g);
-    const EventDesc& d = ev[act[k]];
-    const int V = d.N * d.N, parity = (*d.d_step & 1) ^ d.flip;
-    push_body<T, TPP>(fields_at<T>(d.f[parity], V), fields_at<T>(d.f[parity ^ 1], V),
-                      Parts<T>{static_cast<T*>(d.pr), d.cell}, d.pa, d.d_step, d.partials, d.d_err, g - blk_start[k]);
+    // the work item is uniform over the workgroup: keep it (and every address
+    // derived from it) in scalar registers
+    const int2 m = map[g];
+    const int e = __builtin_amdgcn_readfirstlane(m.x), blk = __builtin_amdgcn_readfirstlane(m.y);
+    const EventDesc& d = ev[e];
+    const int V = d.N * d.N, parity = __builtin_amdgcn_readfirstlane((*d.d_step & 1) ^ d.flip);
+    push_body<T, TPP>(fields_at<T>(d.f[parity], V), fields_at<T>(d.f[parity ^ 1], V), static_cast<const T*>(d.aux),
+                      Parts<T>{static_cast<T*>(d.pr), d.cell}, d.pa, d.d_step, d.partials, d.d_err, blk);
 }
 
 // end of a step: on recording steps the block partials of the step's slot are
@@ -454,15 +464,14 @@ __global__ __launch_bounds__(256) void batch_step_end_kernel(const EventDesc* __
 }
 
 template <typename T>
-hipError_t launch_batch_push(const EventDesc* ev, const int* act, const int* blk_start, int nact, int total_blocks,
-                             int tpp, hipStream_t st)
+hipError_t launch_batch_push(const EventDesc* ev, const int2* map, int total_blocks, int tpp, hipStream_t st)
 {
     if (total_blocks <= 0) return hipSuccess;
     const dim3 g(8 * ((total_blocks + 7) / 8)), b(256);
     switch (tpp) {
-    case 2: hipLaunchKernelGGL((batch_push_kernel<T, 2>), g, b, 0, st, ev, act, blk_start, nact); break;
-    case 4: hipLaunchKernelGGL((batch_push_kernel<T, 4>), g, b, 0, st, ev, act, blk_start, nact); break;
-    default: hipLaunchKernelGGL((batch_push_kernel<T, 1>), g, b, 0, st, ev, act, blk_start, nact);
+    case 2: hipLaunchKernelGGL((batch_push_kernel<T, 2>), g, b, 0, st, ev, map, total_blocks); break;
+    case 4: hipLaunchKernelGGL((batch_push_kernel<T, 4>), g, b, 0, st, ev, map, total_blocks); break;
+    default: hipLaunchKernelGGL((batch_push_kernel<T, 1>), g, b, 0, st, ev, map, total_blocks);
     }
     return hipGetLastError();
 }
@@ -472,22 +481,23 @@ hipError_t launch_batch_step_end(const EventDesc* ev, const int* act, int nact, 
     hipLaunchKernelGGL(batch_step_end_kernel, dim3(nact), dim3(256), 0, st, ev, act);
     return hipGetLastError();
 }
-template hipError_t launch_batch_push<double>(const EventDesc*, const int*, const int*, int, int, int, hipStream_t);
-template hipError_t launch_batch_push<float>(const EventDesc*, const int*, const int*, int, int, int, hipStream_t);
+template hipError_t launch_batch_push<double>(const EventDesc*, const int2*, int, int, hipStream_t);
+template hipError_t launch_batch_push<float>(const EventDesc*, const int2*, int, int, hipStream_t);
 
 int push_blocks(int np, int tpp) { return push_blocks_d(np, tpp); }
 
 template <typename T>
-hipError_t launch_push(const Fields<T>& A, const Fields<T>& B, const Parts<T>& P, const PushArgs& a,
+hipError_t launch_push(const Fields<T>& A, const Fields<T>& B, const T* aux, const Parts<T>& P, const PushArgs& a,
                        const int* d_step, double* partials, int* err, hipStream_t st)
 {
     if (a.np <= 0) return hipSuccess;
+    if (!a.is_static && !aux) return hipErrorInvalidValue;
     const int nb = push_blocks(a.np, a.tpp);
     const dim3 g(8 * ((nb + 7) / 8)), b(256);
     switch (a.tpp) {
-    case 2: hipLaunchKernelGGL((push_kernel<T, 2>), g, b, 0, st, A, B, P, a, d_step, partials, err); break;
-    case 4: hipLaunchKernelGGL((push_kernel<T, 4>), g, b, 0, st, A, B, P, a, d_step, partials, err); break;
-    default: hipLaunchKernelGGL((push_kernel<T, 1>), g, b, 0, st, A, B, P, a, d_step, partials, err);
+    case 2: hipLaunchKernelGGL((push_kernel<T, 2>), g, b, 0, st, A, B, aux, P, a, d_step, partials, err); break;
+    case 4: hipLaunchKernelGGL((push_kernel<T, 4>), g, b, 0, st, A, B, aux, P, a, d_step, partials, err); break;
+    default: hipLaunchKernelGGL((push_kernel<T, 1>), g, b, 0, st, A, B, aux, P, a, d_step, partials, err);
     }
     return hipGetLastError();
 }
@@ -565,9 +575,9 @@ hipError_t launch_part_diag(const Parts<T>& P, int np, double q2, double q3, dou
     return hipGetLastError();
 }
 
-template hipError_t launch_push<double>(const Fields<double>&, const Fields<double>&, const Parts<double>&,
-                                        const PushArgs&, const int*, double*, int*, hipStream_t);
-template hipError_t launch_push<float>(const Fields<float>&, const Fields<float>&, const Parts<float>&,
+template hipError_t launch_push<double>(const Fields<double>&, const Fields<double>&, const double*,
+                                        const Parts<double>&, const PushArgs&, const int*, double*, int*, hipStream_t);
+template hipError_t launch_push<float>(const Fields<float>&, const Fields<float>&, const float*, const Parts<float>&,
                                        const PushArgs&, const int*, double*, int*, hipStream_t);
 template hipError_t launch_part_diag<double>(const Parts<double>&, int, double, double, double*, hipStream_t);
 template hipError_t launch_part_diag<float>(const Parts<float>&, int, double, double, double*, hipStream_t);

@@ -109,7 +109,7 @@ def test_particles_init_parity():
     assert rel_err(got, ref) < 1e-13
 
 
-@pytest.mark.parametrize("is_static,lanes", [(False, 1), (False, 2), (False, 4), (True, 1), (True, 4)])
+@pytest.mark.parametrize("is_static,lanes", [(False, 1), (False, 2), (False, 4), (True, 1), (True, 2), (True, 4)])
 def test_particle_push_fp64_random_state(is_static, lanes):
     """Rotation on cell changes (both axes), rapidity Wilson line, E/B interpolation, Euler step,
     with 1, 2 or 4 wavefronts sharing each particle group."""

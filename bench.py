@@ -124,7 +124,7 @@ def run_batch(fp64_launch):
             ctx.init_mv()
             if launch:
                 ctx.set_launch(launch["bx"], launch["by"], launch["xcd_remap"], launch["waves"],
-                               launch["link_parallel"])
+                               launch["variant"])
             ctx.sync()
             t0 = time.perf_counter()
             ctx.evolve(1e9)

@@ -203,12 +203,15 @@ cpic_status cpic_load(cpic_ctx* ctx, const char* path);
 
 /* Field-kernel launch: tile shape in sites, whether consecutive tiles are
  * mapped onto one XCD, the occupancy the register allocator targets (waves per
- * SIMD; 1 = compiler default) and the decomposition: link_parallel = 0, one
- * thread per site (bx * by a multiple of 64, <= 256, waves 1..4);
- * link_parallel = 1, one thread per link (bx * by = 128, bx a multiple of 32,
- * waves 1..3).  Used by the tuner; takes effect for the next launch. */
+ * SIMD; 1 = compiler default) and the kernel variant:
+ *   0  one thread per site, stencil read from global memory (bx * by a
+ *      multiple of 64, <= 256, waves 1..4);
+ *   1  one thread per link (bx * by = 128, bx a multiple of 32, waves 1..3);
+ *   2  one thread per site, links and scalars of the tile and its halo staged
+ *      in LDS first (bx x by one of 64x4, 32x4, 64x2, 32x8, 16x8; waves 1).
+ * Used by the tuner; takes effect for the next launch. */
 cpic_status cpic_set_launch(cpic_ctx* ctx, int32_t bx, int32_t by, int32_t xcd_remap, int32_t waves,
-                            int32_t link_parallel);
+                            int32_t variant);
 
 /* Push work split: wavefronts per group of 64 particles (1, 2 or 4).  The
  * helper wavefronts evaluate part of the colour fields at the particles' cells
@@ -218,7 +221,7 @@ cpic_status cpic_set_launch(cpic_ctx* ctx, int32_t bx, int32_t by, int32_t xcd_r
 cpic_status cpic_set_push_lanes(cpic_ctx* ctx, int32_t lanes);
 
 /* Current launch configuration: out = {bx, by, xcd_remap, waves, push lanes,
- * link_parallel}. */
+ * variant}. */
 cpic_status cpic_get_launch(const cpic_ctx* ctx, int32_t out[6]);
 
 /* Launch tuner: times every candidate field-kernel configuration (block shape x

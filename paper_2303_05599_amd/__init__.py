@@ -221,8 +221,9 @@ class Context:
     def load(self, path):
         self._chk(lib().cpic_load(self.h, str(path).encode()))
 
-    def set_launch(self, bx, by, xcd_remap=1, waves=1, link_parallel=0):
-        self._chk(lib().cpic_set_launch(self.h, bx, by, xcd_remap, waves, link_parallel))
+    def set_launch(self, bx, by, xcd_remap=1, waves=1, variant=0):
+        """Field-kernel launch; variant 0 site-parallel, 1 link-parallel, 2 LDS halo tiles."""
+        self._chk(lib().cpic_set_launch(self.h, bx, by, xcd_remap, waves, variant))
 
     def set_push_lanes(self, lanes):
         self._chk(lib().cpic_set_push_lanes(self.h, lanes))
@@ -230,7 +231,7 @@ class Context:
     def get_launch(self):
         out = np.zeros(6, np.int32)
         self._chk(lib().cpic_get_launch(self.h, _ptr(out)))
-        return dict(zip(("bx", "by", "xcd_remap", "waves", "push_lanes", "link_parallel"), out.tolist()))
+        return dict(zip(("bx", "by", "xcd_remap", "waves", "push_lanes", "variant"), out.tolist()))
 
     def tune(self, reps=5):
         """Time the launch candidates on the current state and keep the fastest; returns the report."""

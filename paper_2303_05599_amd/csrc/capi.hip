@@ -836,18 +836,26 @@ extern "C" cpic_status cpic_load(cpic_ctx* c, const char* path)
 
 // ------------------------------------------------------------------ tuning and timing
 extern "C" cpic_status cpic_set_launch(cpic_ctx* c, int32_t bx, int32_t by, int32_t remap, int32_t waves,
-                                       int32_t link_parallel)
+                                       int32_t variant)
 {
     if (!c) return fail(nullptr, CPIC_E_INVALID, "cpic_set_launch: NULL context");
-    if (link_parallel) {
+    if (variant == 1) {
         if (bx <= 0 || by <= 0 || bx * by != 128 || bx % 32 != 0)
             return fail(c, CPIC_E_INVALID, "cpic_set_launch: link-parallel tiles hold 128 sites, bx a multiple of 32");
         if (waves < 1 || waves > 3) return fail(c, CPIC_E_INVALID, "cpic_set_launch: waves must be 1..3");
-    } else if (bx <= 0 || by <= 0 || bx * by > 256 || (bx * by) % 64 != 0) {
-        return fail(c, CPIC_E_INVALID, "cpic_set_launch: need bx*by a multiple of 64 and <= 256");
+    } else if (variant == 2) {
+        const bool shape = (bx == 64 && by == 4) || (bx == 32 && by == 4) || (bx == 64 && by == 2) ||
+                           (bx == 32 && by == 8) || (bx == 16 && by == 8);
+        if (!shape) return fail(c, CPIC_E_INVALID, "cpic_set_launch: LDS tiles are 64x4, 32x4, 64x2, 32x8 or 16x8");
+        if (waves != 1) return fail(c, CPIC_E_INVALID, "cpic_set_launch: LDS tiles take waves = 1");
+    } else if (variant == 0) {
+        if (bx <= 0 || by <= 0 || bx * by > 256 || (bx * by) % 64 != 0)
+            return fail(c, CPIC_E_INVALID, "cpic_set_launch: need bx*by a multiple of 64 and <= 256");
+    } else {
+        return fail(c, CPIC_E_INVALID, "cpic_set_launch: variant must be 0, 1 or 2");
     }
     if (waves < 1 || waves > 4) return fail(c, CPIC_E_INVALID, "cpic_set_launch: waves must be 1..4");
-    c->cfg.split = link_parallel ? 1 : 0;
+    c->cfg.split = variant;
     c->cfg.bx = bx;
     c->cfg.by = by;
     c->cfg.xcd_remap = remap ? 1 : 0;
@@ -884,6 +892,8 @@ extern "C" cpic_status cpic_timing(cpic_ctx* c, double* field_ms, double* push_m
 // field kernel reads the current buffer and writes the free one (the step is
 // not advanced); the push runs on a saved copy of the particle records, which
 // is restored after every trial.  The fastest configuration is kept.
+static const char* const kVariantName[3] = {"site", "link", "tile"};
+
 template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::string& rep)
 {
     const Fields<T> A = F<T>(c, c->cur), B = F<T>(c, c->cur ^ 1);
@@ -903,6 +913,9 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
     for (const auto& sh : lshapes)
         for (int waves = 1; waves <= 3; waves++)
             for (int remap = 0; remap <= 1; remap++) cands.push_back(LaunchCfg{sh[0], sh[1], remap, waves, 1});
+    const int tshapes[][2] = {{64, 4}, {32, 4}, {64, 2}, {32, 8}, {16, 8}};
+    for (const auto& sh : tshapes)
+        for (int remap = 0; remap <= 1; remap++) cands.push_back(LaunchCfg{sh[0], sh[1], remap, 1, 2});
     for (const LaunchCfg& cfg : cands) {
                 HIPCHK(c, launch_field_step<T>(A, B, X, c->N, c->sc, c->d_step, cfg, c->st), "tune");  // warm-up
                 HIPCHK(c, hipEventRecord(e0, c->st), "tune");
@@ -914,13 +927,13 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
                 HIPCHK(c, hipEventElapsedTime(&ms, e0, e1), "tune");
                 const double per = ms / reps;
                 std::snprintf(line, sizeof line, "field %s bx=%d by=%d waves=%d remap=%d: %.2f us\n",
-                              cfg.split ? "link" : "site", cfg.bx, cfg.by, cfg.waves, cfg.xcd_remap, per * 1e3);
+                              kVariantName[cfg.split], cfg.bx, cfg.by, cfg.waves, cfg.xcd_remap, per * 1e3);
                 rep += line;
                 if (per < best_ms) { best_ms = per; best = cfg; }
             }
     c->cfg = best;
     std::snprintf(line, sizeof line, "best field: %s bx=%d by=%d waves=%d remap=%d %.2f us\n",
-                  best.split ? "link" : "site", best.bx, best.by, best.waves, best.xcd_remap, best_ms * 1e3);
+                  kVariantName[best.split], best.bx, best.by, best.waves, best.xcd_remap, best_ms * 1e3);
     rep += line;
     if (c->np > 0 && c->n >= c->sc.n_form && c->n < c->sc.n_max) {
         const size_t rb = sizeof(T) * kPartReals * (size_t)c->np, cb = sizeof(int) * 2 * (size_t)c->np;

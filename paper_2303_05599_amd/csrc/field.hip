@@ -34,6 +34,35 @@ template <typename T> __device__ __forceinline__ Nbr neighbours(int x, int y, in
             (uint32_t)(yp * N + xm) * b};
 }
 
+// Where the stencil reads links and scalars: straight from the global buffer
+// (sites as byte offsets) or from a halo tile staged in LDS (sites as tile
+// indices).  Same interface, so one stencil serves both kernels.
+template <typename T> struct GlobalSrc {
+    View<T> v;
+    __device__ __forceinline__ m3<T> U(uint32_t s, int i) const { return vU(v, s, i); }
+    __device__ __forceinline__ a8<T> A(uint32_t s, uint32_t c0) const { return vA(v, s, c0); }
+};
+// LDS halo tile: component c of tile site h at l[c * HS + h], components 0..43
+// (links, then phi) in the buffer-set order
+template <typename T, int HS> struct LdsSrc {
+    const T* l;
+    __device__ __forceinline__ m3<T> U(uint32_t h, int i) const
+    {
+        m3<T> m;
+#pragma unroll
+        for (int c = 0; c < 9; c++)
+            m.e[c] = {l[(18 * i + 2 * c) * HS + h], l[(18 * i + 2 * c + 1) * HS + h]};
+        return m;
+    }
+    __device__ __forceinline__ a8<T> A(uint32_t h, uint32_t c0) const
+    {
+        a8<T> r;
+#pragma unroll
+        for (int a = 0; a < 8; a++) r.v[a] = l[(c0 + a) * HS + h];
+        return r;
+    }
+};
+
 // Kick forces at time t from U(t), phi(t) (lattice equations of motion, Sec. II.A):
 //   F_i  = -t (Proj U_ij + Proj U_{i,-j}) + (1/t) i[phi->_i, phi]
 //   F_pi = (1/t) sum_i (phi->_i + phi<-_i - 2 phi)
@@ -46,20 +75,22 @@ template <typename T> __device__ __forceinline__ Nbr neighbours(int x, int y, in
 // particle push assembles at its cell are written to `aux` (24 components):
 //   G   = Proj U_12(x)                       (the clover leaves are transports of G)
 //   D_x = phi->_1(x) - phi<-_1(x),  D_y = phi->_2(x) - phi<-_2(x)
-template <typename T, bool AUX = false>
-__device__ __forceinline__ void kick_forces(const View<T>& f, const Nbr& nb, T t, T inv_t, const a8<T>& PHI,
+// (aux_s: the site's byte offset in the aux buffer).
+template <typename T, bool AUX = false, typename Src>
+__device__ __forceinline__ void kick_forces(const Src& f, const Nbr& nb, T t, T inv_t, const a8<T>& PHI,
                                             a8<T>& F1, a8<T>& F2, a8<T>& Fpi, T* re_tr_p12 = nullptr,
-                                            T* grad2 = nullptr, const View<T>* aux = nullptr, bool aux_on = false)
+                                            T* grad2 = nullptr, const View<T>* aux = nullptr, bool aux_on = false,
+                                            uint32_t aux_s = 0)
 {
     a8<T> dx, dy;
     m3<T> A12, A1m2, A2m1;
     a8<T> lap, c1, c2;
     T g2 = 0;
     {   // U_1(x): U_12 = [U_1 U_2(x+1)] ..., U_{1,-2} = [U_1 U_2(x+1-2)^+] ..., phi->_1
-        const m3<T> U1 = vU(f, nb.s, 0);
-        A12 = mul(U1, vU(f, nb.xp, 1));
-        A1m2 = mul_adj(U1, vU(f, nb.xpym, 1));
-        const a8<T> f1 = transport(U1, vA(f, nb.xp, kCompPhi));
+        const m3<T> U1 = f.U(nb.s, 0);
+        A12 = mul(U1, f.U(nb.xp, 1));
+        A1m2 = mul_adj(U1, f.U(nb.xpym, 1));
+        const a8<T> f1 = transport(U1, f.A(nb.xp, kCompPhi));
         if (AUX) dx = f1;
         c1 = icomm(f1, PHI);
 #pragma unroll
@@ -71,15 +102,15 @@ __device__ __forceinline__ void kick_forces(const View<T>& f, const Nbr& nb, T t
     }
     CPIC_PHASE();
     {   // U_2(x): U_12 = A12 [U_2 U_1(x+2)]^+, U_{2,-1} = [U_2 U_1(x-1+2)^+] ..., phi->_2
-        const m3<T> U2 = vU(f, nb.s, 1);
-        const m3<T> P = mul_adj(A12, mul(U2, vU(f, nb.yp, 0)));
+        const m3<T> U2 = f.U(nb.s, 1);
+        const m3<T> P = mul_adj(A12, mul(U2, f.U(nb.yp, 0)));
         F1 = proj(P);
-        if (AUX && aux_on) vA_st(*aux, nb.s, 0, F1);
+        if (AUX && aux_on) vA_st(*aux, aux_s, 0, F1);
 #pragma unroll
         for (int a = 0; a < 8; a++) F2.v[a] = -F1.v[a];   // Proj U_21 = -Proj U_12
         if (re_tr_p12) *re_tr_p12 = P.e[0].re + P.e[4].re + P.e[8].re;
-        A2m1 = mul_adj(U2, vU(f, nb.xmyp, 0));
-        const a8<T> f2 = transport(U2, vA(f, nb.yp, kCompPhi));
+        A2m1 = mul_adj(U2, f.U(nb.xmyp, 0));
+        const a8<T> f2 = transport(U2, f.A(nb.yp, kCompPhi));
         if (AUX) dy = f2;
         c2 = icomm(f2, PHI);
 #pragma unroll
@@ -91,28 +122,28 @@ __device__ __forceinline__ void kick_forces(const View<T>& f, const Nbr& nb, T t
     }
     CPIC_PHASE();
     {   // U_2(x-2): U_{1,-2} = A1m2 [U_2(x-2)^+ U_1(x-2)]^+, phi<-_2
-        const m3<T> U2ym = vU(f, nb.ym, 1);
-        const a8<T> p = proj(mul_adj(A1m2, adj_mul(U2ym, vU(f, nb.ym, 0))));
-        const a8<T> b2 = transport_adj(U2ym, vA(f, nb.ym, kCompPhi));
+        const m3<T> U2ym = f.U(nb.ym, 1);
+        const a8<T> p = proj(mul_adj(A1m2, adj_mul(U2ym, f.U(nb.ym, 0))));
+        const a8<T> b2 = transport_adj(U2ym, f.A(nb.ym, kCompPhi));
 #pragma unroll
         for (int a = 0; a < 8; a++) { F1.v[a] += p.v[a]; lap.v[a] += b2.v[a]; }
         if (AUX && aux_on) {
 #pragma unroll
             for (int a = 0; a < 8; a++) dy.v[a] -= b2.v[a];
-            vA_st(*aux, nb.s, 16, dy);
+            vA_st(*aux, aux_s, 16, dy);
         }
     }
     CPIC_PHASE();
     {   // U_1(x-1): U_{2,-1} = A2m1 [U_1(x-1)^+ U_2(x-1)]^+, phi<-_1
-        const m3<T> U1xm = vU(f, nb.xm, 0);
-        const a8<T> p = proj(mul_adj(A2m1, adj_mul(U1xm, vU(f, nb.xm, 1))));
-        const a8<T> b1 = transport_adj(U1xm, vA(f, nb.xm, kCompPhi));
+        const m3<T> U1xm = f.U(nb.xm, 0);
+        const a8<T> p = proj(mul_adj(A2m1, adj_mul(U1xm, f.U(nb.xm, 1))));
+        const a8<T> b1 = transport_adj(U1xm, f.A(nb.xm, kCompPhi));
 #pragma unroll
         for (int a = 0; a < 8; a++) { F2.v[a] += p.v[a]; lap.v[a] += b1.v[a]; }
         if (AUX && aux_on) {
 #pragma unroll
             for (int a = 0; a < 8; a++) dx.v[a] -= b1.v[a];
-            vA_st(*aux, nb.s, 8, dx);
+            vA_st(*aux, aux_s, 8, dx);
         }
     }
 #pragma unroll
@@ -157,7 +188,7 @@ __device__ __forceinline__ void field_step_body(const Fields<T>& in, const Field
     if (kick || aux_on) {
         View<T> va;
         if (AUX) va = make_view<T>(aux, kAuxReals, V);
-        kick_forces<T, AUX>(vi, nb, t, inv_t, PHI, F1, F2, Fpi, nullptr, nullptr, &va, aux_on);
+        kick_forces<T, AUX>(GlobalSrc<T>{vi}, nb, t, inv_t, PHI, F1, F2, Fpi, nullptr, nullptr, &va, aux_on, nb.s);
     }
     CPIC_PHASE();
     a8<T> E1 = vA(vi, nb.s, kCompE), E2 = vA(vi, nb.s, kCompE + 8), PI = vA(vi, nb.s, kCompPi);
@@ -182,6 +213,94 @@ __device__ __forceinline__ void field_step_body(const Fields<T>& in, const Field
     vA_st(vo, nb.s, kCompE, E1);
     vA_st(vo, nb.s, kCompE + 8, E2);
     vA_st(vo, nb.s, kCompPi, PI);
+}
+
+// ---------------------------------------------------------------- LDS halo-tile variant
+// One workgroup of BX x BY threads owns a BX x BY tile.  It first stages the
+// links and scalars of the tile and its one-site halo ring in LDS with
+// coalesced loads (each global value read once per tile instead of once per
+// stencil use), then every thread runs the stencil out of LDS; E and pi of
+// its own site come straight from global memory.
+template <typename T, bool AUX, int BX, int BY>
+__device__ __forceinline__ void field_tile_body(const Fields<T>& in, const Fields<T>& out, T* aux, int N, int tile,
+                                                const Schedule& sc, const int* __restrict__ d_step)
+{
+    constexpr int HX = BX + 2, HY = BY + 2, HS = HX * HY, NT = BX * BY, NC = 44;
+    __shared__ T lds[NC * HS];
+    const int ntx = (N + BX - 1) / BX;
+    const int x0 = (tile % ntx) * BX, y0 = (tile / ntx) * BY;
+    const int tid = (int)threadIdx.x;
+    const uint32_t V = (uint32_t)N * N;
+    const View<T> vi = make_view<T>(in.U, kRealsPerSite, V), vo = make_view<T>(out.U, kRealsPerSite, V);
+    // stage: thread tid loads tile sites h = tid, tid + NT, ... (all 44 components)
+#pragma unroll
+    for (int h0 = 0; h0 < HS; h0 += NT) {
+        const int h = h0 + tid;
+        if (h < HS) {
+            const int hy = h / HX, hx = h - hy * HX;
+            const int gx = (x0 + hx - 1 + N) % N, gy = (y0 + hy - 1 + N) % N;
+            const uint32_t go = (uint32_t)(gy * N + gx) * (uint32_t)sizeof(T);
+            T v[NC];
+#pragma unroll
+            for (int c = 0; c < NC; c++) v[c] = bld(vi, go, (uint32_t)c);
+#pragma unroll
+            for (int c = 0; c < NC; c++) lds[c * HS + h] = v[c];
+        }
+    }
+    __syncthreads();
+    const int tx = tid % BX, ty = tid / BX;
+    const int x = x0 + tx, y = y0 + ty;
+    if (x >= N || y >= N) return;
+    const int n = *d_step;
+    const double td = n * sc.dt, thd = (n + 0.5) * sc.dt;
+    const T t = T(td), inv_t = n > 0 ? T(1.0 / td) : T(0), dt = T(sc.dt);
+    const T eps_drift = T(sc.dt / thd), phi_drift = T(sc.dt * thd);
+    const bool kick = n > 0, reunit = is_reunit_step(sc, n);
+    const uint32_t hs = (uint32_t)((ty + 1) * HX + tx + 1);
+    const Nbr nb{hs, hs + 1, hs - 1, hs + HX, hs - HX, hs + 1 - HX, hs - 1 + HX};
+    const uint32_t gs = (uint32_t)(y * N + x) * (uint32_t)sizeof(T);
+    const LdsSrc<T, HS> src{lds};
+    a8<T> PHI = src.A(hs, kCompPhi);
+    a8<T> F1 = azero<T>(), F2 = azero<T>(), Fpi = azero<T>();
+    // the push reads the magnetic-field pieces from the first push step on
+    // (at n = 0, t = 1/t = 0 make the forces vanish, so the kick is still skipped)
+    const bool aux_on = AUX && n >= sc.n_form;
+    if (kick || aux_on) {
+        View<T> va;
+        if (AUX) va = make_view<T>(aux, kAuxReals, V);
+        kick_forces<T, AUX>(src, nb, t, inv_t, PHI, F1, F2, Fpi, nullptr, nullptr, &va, aux_on, gs);
+    }
+    CPIC_PHASE();
+    a8<T> E1 = vA(vi, gs, kCompE), E2 = vA(vi, gs, kCompE + 8), PI = vA(vi, gs, kCompPi);
+#pragma unroll
+    for (int a = 0; a < 8; a++) {
+        E1.v[a] += dt * F1.v[a];
+        E2.v[a] += dt * F2.v[a];
+        PI.v[a] += dt * Fpi.v[a];
+    }
+    CPIC_PHASE();
+    // drift: U_i <- exp(i (dt/t_half) E_i) U_i ; phi <- phi + dt t_half pi
+    m3<T> U1 = mul(expi(E1, eps_drift), src.U(hs, 0));
+    if (reunit) U1 = reunitarize(U1);
+    vU_st(vo, gs, 0, U1);
+    CPIC_PHASE();
+    m3<T> U2 = mul(expi(E2, eps_drift), src.U(hs, 1));
+    if (reunit) U2 = reunitarize(U2);
+    vU_st(vo, gs, 1, U2);
+#pragma unroll
+    for (int a = 0; a < 8; a++) PHI.v[a] += phi_drift * PI.v[a];
+    vA_st(vo, gs, kCompPhi, PHI);
+    vA_st(vo, gs, kCompE, E1);
+    vA_st(vo, gs, kCompE + 8, E2);
+    vA_st(vo, gs, kCompPi, PI);
+}
+
+template <typename T, bool AUX, int BX, int BY>
+__global__ __launch_bounds__(BX * BY) void field_tile_kernel(Fields<T> in, Fields<T> out, T* aux, int N, int remap,
+                                                             Schedule sc, const int* __restrict__ d_step)
+{
+    const int nt = ((N + BX - 1) / BX) * ((N + BY - 1) / BY), tile = logical_block(nt, remap);
+    if (tile < nt) field_tile_body<T, AUX, BX, BY>(in, out, aux, N, tile, sc, d_step);
 }
 
 // ---------------------------------------------------------------- link-parallel variant
@@ -381,10 +500,30 @@ hipError_t launch_batch_field(const EventDesc* ev, const int2* map, int total_ti
 template hipError_t launch_batch_field<double>(const EventDesc*, const int2*, int, const LaunchCfg&, hipStream_t);
 template hipError_t launch_batch_field<float>(const EventDesc*, const int2*, int, const LaunchCfg&, hipStream_t);
 
+template <typename T, bool AUX, int BX, int BY>
+static hipError_t launch_tile(const Fields<T>& in, const Fields<T>& out, T* aux, int N, const Schedule& sc,
+                              const int* d_step, int remap, hipStream_t st)
+{
+    const int ntiles = ((N + BX - 1) / BX) * ((N + BY - 1) / BY);
+    const dim3 g(remap ? 8 * ((ntiles + 7) / 8) : ntiles), blk(BX * BY);
+    hipLaunchKernelGGL((field_tile_kernel<T, AUX, BX, BY>), g, blk, 0, st, in, out, aux, N, remap, sc, d_step);
+    return hipGetLastError();
+}
+
 template <typename T, bool AUX>
 static hipError_t launch_field_step_t(const Fields<T>& in, const Fields<T>& out, T* aux, int N, const Schedule& sc,
                                       const int* d_step, const LaunchCfg& cfg, hipStream_t st)
 {
+    if (cfg.split == 2) {
+        // LDS halo tiles of the instantiated shapes
+        const int r = cfg.xcd_remap;
+        if (cfg.bx == 64 && cfg.by == 4) return launch_tile<T, AUX, 64, 4>(in, out, aux, N, sc, d_step, r, st);
+        if (cfg.bx == 32 && cfg.by == 4) return launch_tile<T, AUX, 32, 4>(in, out, aux, N, sc, d_step, r, st);
+        if (cfg.bx == 64 && cfg.by == 2) return launch_tile<T, AUX, 64, 2>(in, out, aux, N, sc, d_step, r, st);
+        if (cfg.bx == 32 && cfg.by == 8) return launch_tile<T, AUX, 32, 8>(in, out, aux, N, sc, d_step, r, st);
+        if (cfg.bx == 16 && cfg.by == 8) return launch_tile<T, AUX, 16, 8>(in, out, aux, N, sc, d_step, r, st);
+        return hipErrorInvalidValue;
+    }
     if (cfg.split) {
         // 128 sites (256 link threads) per block
         if (cfg.bx * cfg.by != 128 || cfg.bx % 32 != 0) return hipErrorInvalidValue;
@@ -451,7 +590,7 @@ __global__ __launch_bounds__(256) void field_diag_kernel(Fields<T> f, int N, T t
         v[1] = sqrt(G2);
         a8<T> F1, F2, Fpi;
         T retr = 0, grad2 = 0;
-        kick_forces(vf, nb, t, inv_t, PHI, F1, F2, Fpi, &retr, &grad2);
+        kick_forces<T>(GlobalSrc<T>{vf}, nb, t, inv_t, PHI, F1, F2, Fpi, &retr, &grad2);
         const T h = n > 0 ? half_dt : T(0);
         double e2 = 0, p2 = 0;
         for (int a = 0; a < 8; a++) {

@@ -64,7 +64,8 @@ struct LaunchCfg {
     int bx = 64, by = 4;  // field kernel block shape
     int xcd_remap = 1;    // map consecutive tiles onto one XCD
     int waves = 1;        // register-allocation occupancy target of the field kernel (1 = compiler default)
-    int split = 0;        // 1: one thread per link (bx * by = 128 sites per block)
+    int split = 0;        // kernel variant: 0 one thread per site, 1 one thread per link (128 sites per
+                          // block), 2 one thread per site with the tile and its halo staged in LDS
 };
 
 struct PushArgs {

@@ -56,14 +56,18 @@ def gpu():
 
 
 LAUNCHES = {"site64x4": (64, 4, 1, 1, 0), "site256x1w2": (256, 1, 0, 2, 0), "link128x1": (128, 1, 1, 1, 1),
-            "link32x4w2": (32, 4, 0, 2, 1)}
+            "link32x4w2": (32, 4, 0, 2, 1), "tile64x4": (64, 4, 1, 1, 2), "tile32x8": (32, 8, 0, 1, 2),
+            "tile16x8": (16, 8, 1, 1, 2), "tile64x2": (64, 2, 0, 1, 2), "tile32x4": (32, 4, 1, 1, 2)}
 
 
 @pytest.mark.parametrize("N,n0,launch", [(32, 3, "site64x4"), (96, 0, "site64x4"), (48, 1, "site64x4"),
-                                         (96, 2, "link128x1"), (48, 1, "link32x4w2"), (32, 5, "site256x1w2")])
+                                         (96, 2, "link128x1"), (48, 1, "link32x4w2"), (32, 5, "site256x1w2"),
+                                         (96, 1, "tile64x4"), (48, 2, "tile32x8"), (12, 0, "tile16x8"),
+                                         (36, 3, "tile64x2"), (64, 1, "tile32x4")])
 def test_field_leapfrog_fp64_random_state(N, n0, launch):
-    """50 fused kick+drift steps from a random state; N = 96 and 48 leave ragged tiles;
-    site-parallel and link-parallel decompositions."""
+    """50 fused kick+drift steps from a random state; N = 96, 48, 36 and 12 leave ragged
+    tiles (12 is smaller than the 16 x 8 tile); site-parallel, link-parallel and LDS
+    halo-tile decompositions."""
     print(f"case N={N} n0={n0} launch={launch}", flush=True)
     steps = 50
     st = inputs.random_state(N, 100 + N, eps_link=0.4)
@@ -171,9 +175,13 @@ def test_static_limit_config_32():
     assert rel_err(ctx.get_state(cp.STATE_PARTICLES), run.P) <= TOL
 
 
-def test_full_chain_charm_like_64():
+@pytest.mark.parametrize("launch", [None, "tile64x4", "link128x1"])
+def test_full_chain_charm_like_64(launch):
     """Full chain at the paper-scale lattice spacing (a = 6 fm / 512) on a 64^2
-    patch: 4 sheets, charm quarks (m = 1.27 GeV, p_T = 0) formed at 0.1 fm/c."""
+    patch: 4 sheets, charm quarks (m = 1.27 GeV, p_T = 0) formed at 0.1 fm/c; the
+    field update in each decomposition also writes the magnetic-field pieces
+    the push reads."""
+    print(f"case full chain launch={launch}", flush=True)
     N, L = 64, 0.75
     a = oracle.lattice_spacing(L, N)
     n_form = math.ceil(0.1 / (0.125 * L / N) - 1e-9)
@@ -181,6 +189,8 @@ def test_full_chain_charm_like_64():
     g = glasma(N, L, n_sheets=4, steps=steps, seed=3)
     p = dict(n=2000, mass_GeV=1.27, pT_min_GeV=0, pT_max_GeV=0, azimuth_uniform=1, tau_form_fm=0.1, rep=0, seed=4)
     ctx = cp.Context(g, p)
+    if launch:
+        ctx.set_launch(*LAUNCHES[launch])
     ctx.init_mv()
     ctx.evolve(1e9)
     ctx.sync()
@@ -197,6 +207,32 @@ def test_full_chain_charm_like_64():
     last = run.observe() / (2000 * a * a)
     for c in range(4):
         assert abs(obs[-1, 1 + c] - last[c]) <= TOL * max(abs(last[c]), 1e-300), (c, obs[-1], last)
+
+
+@pytest.mark.parametrize("launch", ["site64x4", "tile16x8", "link32x4w2"])
+def test_particles_formed_at_tau_zero(launch):
+    """Dynamic particles formed at tau = 0 (n_form = 0): at n = 0 the kick is
+    skipped but the magnetic-field pieces (clover, scalar gradients) must still
+    be written for the push; 24 steps on a 32^2 MV event against the oracle."""
+    print(f"case tau_form=0 launch={launch}", flush=True)
+    N, L, steps = 32, 6.0, 24
+    a = oracle.lattice_spacing(L, N)
+    g = glasma(N, L, steps=steps, seed=5)
+    p = dict(n=700, mass_GeV=2.0, pT_min_GeV=0.5, pT_max_GeV=2.0, azimuth_uniform=1, tau_form_fm=0.0, rep=0, seed=6)
+    ctx = cp.Context(g, p)
+    ctx.set_launch(*LAUNCHES[launch])
+    ctx.init_mv()
+    ctx.step(steps)
+    ctx.sync()
+    ref = oracle.mv_initial_condition(N, L, 2.0, 0.2, 10.0, 1, 5)
+    P = oracle.particles_init(N, 700, 6, 0.5 * a, 2.0 * a, True, 0)
+    run = oracle.Run(N, 0.125, ref, P, mhat=2.0 * a, n_form=0)
+    for _ in range(steps):
+        run.step()
+    compare_fields(ctx.state(), run.st)
+    got = ctx.get_state(cp.STATE_PARTICLES)
+    assert np.array_equal(got[:, 14:16], run.P[:, 14:16])
+    assert rel_err(got, run.P) <= TOL
 
 
 def test_graph_replay_equals_eager_bitwise():

@@ -1,8 +1,10 @@
 // sort.hip -- periodic reordering of the particle records by lattice cell.
 //
 // The push gathers the fields around each particle's nearest grid point.
-// With particles in cell order, the 64 lanes of a wavefront read
-// neighbouring sites, so their gathers share cache lines.  The order is
+// Particles are ordered by 16 x 16 cell tiles (tile-major, then row-major
+// inside the tile): the 64 lanes of a wavefront and the workgroups that run
+// together on one XCD then read a compact patch of the lattice, whose cache
+// lines (16 sites of one row in double precision) they share.  The order is
 // found with a stable radix sort of the cell keys (deterministic), the
 // records are permuted into a scratch copy and copied back so that buffer
 // addresses (captured in HIP graphs) never change.  pid tracks each record's
@@ -13,11 +15,28 @@
 
 namespace cpic {
 
+constexpr int kSortTile = 16;
+
+__host__ __device__ inline unsigned sort_key_bound(int N)
+{
+    const unsigned nt = (unsigned)((N + kSortTile - 1) / kSortTile);
+    return nt * nt * kSortTile * kSortTile;
+}
+static int key_bits(int N)
+{
+    int bits = 1;
+    while ((1u << bits) < sort_key_bound(N)) bits++;
+    return bits;
+}
+
 __global__ void cell_keys_kernel(const int* __restrict__ cell, int np, int N, unsigned* keys, int* vals)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
-    keys[p] = (unsigned)(cell[np + p] * N + cell[p]);
+    const int cx = cell[p], cy = cell[np + p];
+    const int nt = (N + kSortTile - 1) / kSortTile;
+    const int tile = (cy / kSortTile) * nt + cx / kSortTile;
+    keys[p] = (unsigned)(tile * kSortTile * kSortTile + (cy % kSortTile) * kSortTile + cx % kSortTile);
     vals[p] = p;
 }
 
@@ -38,10 +57,8 @@ __global__ void permute_kernel(const T* __restrict__ r, const int* __restrict__ 
 size_t sort_temp_bytes(int np, int N)
 {
     size_t bytes = 0;
-    int bits = 1;
-    while ((1u << bits) < (unsigned)N * (unsigned)N) bits++;
     hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (unsigned*)nullptr, (unsigned*)nullptr, (int*)nullptr,
-                                       (int*)nullptr, np, 0, bits);
+                                       (int*)nullptr, np, 0, key_bits(N));
     return bytes;
 }
 
@@ -49,8 +66,7 @@ template <typename T>
 hipError_t sort_particles(const SortBufs& b, T* r, int* cell, int* pid, int np, int N, hipStream_t st)
 {
     if (np <= 1) return hipSuccess;
-    int bits = 1;
-    while ((1u << bits) < (unsigned)N * (unsigned)N) bits++;
+    const int bits = key_bits(N);
     const int blocks = (np + 255) / 256;
     hipLaunchKernelGGL(cell_keys_kernel, dim3(blocks), dim3(256), 0, st, cell, np, N, b.keys, b.vals);
     size_t bytes = b.temp_bytes;

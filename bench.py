@@ -27,9 +27,17 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 HBARC_GEV_FM = 0.1973269804
-FP64_VALU_TFLOPS = 78.6
-BYTES_PER_SITE = {"f64": 68 * 2 * 8, "f32": 68 * 2 * 4}     # read + write of U1 U2 phi E1 E2 pi
-PART_REALS_RW = 2 * 18 + 2 * 2                               # particle record read+write (reals + 2 int cells)
+# Algorithmic bytes per unit of work (per site-update of the field kernel, per
+# particle push): the field update reads and writes the 68 reals of a site
+# (U_x, U_y, phi, E_x, E_y, pi) and, with dynamic particles, writes the 24
+# reals of magnetic-field pieces the push reads (a partial force table); the
+# push moves its record (about 17 words each way), the six force fields at one
+# site (48 reals), phi at the cell (8) and a link on one step in eight.
+SITE_BYTES = {"f64": 68 * 2 * 8, "f32": 68 * 2 * 4}
+AUX_BYTES = {"f64": 24 * 8, "f32": 24 * 4}
+PUSH_BYTES = {"f64": 730, "f32": 370}
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_512_fp64.txt")
+KERNEL_SOURCES = os.path.join(ROOT, "paper_2303_05599_amd", "csrc")
 
 
 def glasma_512(precision, N=512, L=6.0, seed=3):
@@ -43,7 +51,7 @@ def charm(n=100_000, seed=4):
                 seed=seed)
 
 
-def run_event(precision, steps, warmup):
+def run_event(precision, steps, warmup, tune=True):
     import torch
     import paper_2303_05599_amd as cp
     ctx = cp.Context(glasma_512(precision), charm())
@@ -52,7 +60,7 @@ def run_event(precision, steps, warmup):
     t_ic = time.perf_counter() - t0
     ctx.step(warmup)
     ctx.sync()
-    tune_report = ctx.tune(5)
+    tune_report = ctx.tune(5) if tune else "not tuned (library defaults)\n"
     launch = ctx.get_launch()
     ctx.set_timing(True)
     torch.cuda.synchronize()
@@ -177,6 +185,142 @@ def cpu_baseline(n_steps=6, n_part=100_000):
                        f"{dt:.1f} s wall")
 
 
+def kernel_source_hash():
+    """sha256 over the HIP sources: a stored counter reading is only used for the
+    kernels it was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(KERNEL_SOURCES)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(KERNEL_SOURCES, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def read_pmc_summary(path=PMC_SUMMARY):
+    if not os.path.exists(path):
+        return None
+    d = {}
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#") and "=" in line:
+                k, v = line.split("=", 1)
+                d[k.strip()] = v.strip()
+    return d if d.get("source_sha256") == kernel_source_hash() else None
+
+
+def kernel_names(launch, precision):
+    t = "double" if precision == "fp64" else "float"
+    v = launch["variant"]
+    if v == 2:
+        field = f"field_tile_kernel<{t}, true, {launch['bx']}, {launch['by']}>"
+    elif v == 1:
+        field = "field_link_kernel" + ("" if launch["waves"] == 1 else f"_w{launch['waves']}") + f"<{t}, true>"
+    else:
+        field = "field_step_kernel" + ("" if launch["waves"] == 1 else f"_w{launch['waves']}") + f"<{t}, true>"
+    return field, f"push_kernel<{t}, {launch['push_lanes']}>"
+
+
+def rooflines(res, precision, n_part, V):
+    """Per-kernel roofline entries from the live HIP-event kernel times."""
+    tm = res["timing"]
+    dt = "f64" if precision == "fp64" else "f32"
+    field_s = tm["field_ms"] / max(tm["n_field"], 1) * 1e-3
+    push_s = tm["push_ms"] / max(tm["n_push"], 1) * 1e-3
+    fname, pname = kernel_names(res["launch"], precision)
+    out = {}
+    for key, name, secs, unit_bytes, units, unit in (
+            ("field", fname, field_s, SITE_BYTES[dt] + AUX_BYTES[dt], V, "site-update"),
+            ("push", pname, push_s, PUSH_BYTES[dt], n_part, "particle-push")):
+        bpl = unit_bytes * units
+        ach = bpl / secs / 1e9
+        out[key] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": name,
+                    "avg_launch_us": secs * 1e6, "bytes_per_launch": bpl,
+                    "bytes_per_unit": unit_bytes, "units_per_launch": units, "work_unit": unit}
+    pmc = read_pmc_summary() if precision == "fp64" else None
+    for key in out:
+        if pmc and pmc.get(f"{key}.kernel") == out[key]["kernel"]:
+            out[key]["traffic"] = float(pmc[f"{key}.fetch_bytes"]) + float(pmc[f"{key}.write_bytes"])
+            out[key]["traffic_read"] = float(pmc[f"{key}.fetch_bytes"])
+            out[key]["traffic_written"] = float(pmc[f"{key}.write_bytes"])
+    return out
+
+
+def pmc_summary(out_path, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, command):
+    """Condense four rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE of the bench
+    workload and of the 256 MiB copy) into the key = value summary read above."""
+    import csv
+    import glob
+
+    def per_kernel(d, counter):
+        rows = []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            rows += [r for r in csv.DictReader(open(f)) if r["Counter_Name"] == counter]
+        by = {}
+        for r in rows:
+            key = (r["Kernel_Name"], int(r["Dispatch_Id"]))
+            by[key] = by.get(key, 0.0) + float(r["Counter_Value"])
+        kern, last = {}, {}
+        for (name, disp), v in sorted(by.items(), key=lambda kv: kv[0][1]):
+            kern.setdefault(name, []).append(v)
+            last[name] = disp
+        return kern, last
+
+    def short(name):
+        return name.replace("void ", "").replace("cpic::", "").split("(")[0]
+
+    (cf, _), (cw, _) = per_kernel(copy_fetch_dir, "FETCH_SIZE"), per_kernel(copy_write_dir, "WRITE_SIZE")
+    copy_kernel = max(cf, key=lambda k: max(cf[k]))
+    copy_bytes = 256 << 20
+    f_fetch = copy_bytes / (max(cf[copy_kernel]) * 1024)
+    f_write = copy_bytes / (max(cw[copy_kernel]) * 1024)
+    (kf, last), (kw, _) = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
+    lines = ["# rocprofv3 PMC summary: HBM traffic per dispatch, 512^2 FP64 MV event with 1e5 charm quarks",
+             "# (the bench.py workload).  FETCH_SIZE and WRITE_SIZE (KiB per dispatch, mean of the last",
+             "# 16 dispatches of each kernel in the timed region) are scaled by the ratio of the bytes a",
+             "# 256 MiB device copy moves to what the same counters read for it.",
+             "# commands (from /tmp, TMPDIR=/tmp; R = repository root):"]
+    lines += ["#   " + c for c in command.split(";")]
+    lines += [f"source_sha256 = {kernel_source_hash()}",
+              f"copy_kernel = {short(copy_kernel)}",
+              f"copy_fetch_kib = {max(cf[copy_kernel]):.1f}", f"copy_write_kib = {max(cw[copy_kernel]):.1f}",
+              f"copy_fetch_factor = {f_fetch:.4f}", f"copy_write_factor = {f_write:.4f}"]
+    for key, pat in (("field", "field_"), ("push", "push_kernel")):
+        names = [k for k in kf if pat in k]
+        if not names:
+            continue
+        name = max(names, key=lambda k: last[k])   # the tuned configuration runs last (timed and graph steps)
+        fe = kf[name][-16:]
+        wr = kw.get(name, [0.0])[-16:]
+        fkib, wkib = sum(fe) / len(fe), sum(wr) / len(wr)
+        lines += [f"{key}.kernel = {short(name)}", f"{key}.dispatches = {len(fe)}",
+                  f"{key}.fetch_kib = {fkib:.1f}", f"{key}.write_kib = {wkib:.1f}",
+                  f"{key}.fetch_bytes = {fkib * 1024 * f_fetch:.0f}",
+                  f"{key}.write_bytes = {wkib * 1024 * f_write:.0f}"]
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def trace_summary(out_path, trace_dir, command, top=12):
+    """Markdown table of a rocprofv3 --kernel-trace --stats run."""
+    import csv
+    import glob
+    f = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)[0]
+    rows = list(csv.DictReader(open(f)))
+    lines = [f"# rocprofv3 kernel statistics", "", "Command (from /tmp, TMPDIR=/tmp; R = repository root):", "",
+             "```", command, "```", "", "| kernel | calls | total ms | average us | % |", "|---|---|---|---|---|"]
+    for r in rows[:top]:
+        name = r["Name"].replace("void ", "").replace("cpic::", "").split("(")[0]
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                     f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.1f} |")
+    with open(out_path, "w") as fo:
+        fo.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,7 +333,22 @@ def main():
     ap.add_argument("--tune-report", default=None, help="write the launch tuner's table to this file")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (reference for the HBM counters)")
+    ap.add_argument("--pmc-summary", nargs=5, metavar=("OUT", "FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR",
+                                                       "COPY_WRITE_DIR"),
+                    help="condense rocprofv3 --pmc output directories into a profiles/ summary")
+    ap.add_argument("--trace-summary", nargs=2, metavar=("OUT", "TRACE_DIR"),
+                    help="condense a rocprofv3 --kernel-trace --stats directory into a markdown table")
+    ap.add_argument("--command", default="", help="command line recorded in a summary")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the library's default launch shapes (for counter runs, where the tuner's timings "
+                         "are distorted by the serialised dispatches)")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary, args.command)
+        return
+    if args.trace_summary:
+        trace_summary(*args.trace_summary, args.command)
+        return
     if args.copy_calibration:
         import torch
         a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
@@ -209,14 +368,14 @@ def main():
     import paper_2303_05599_amd as cp
     torch.cuda.set_device(0)
     V = 512 * 512
-    res = run_event(cp.FP64 if args.precision == "fp64" else cp.FP32, args.steps, args.warmup)
-    tm = res["timing"]
+    n_part = 100_000
+    res = run_event(cp.FP64 if args.precision == "fp64" else cp.FP32, args.steps, args.warmup, not args.no_tune)
     ms_per_step = res["wall"] * 1e3 / args.steps
     site_rate = V * args.steps / res["wall"]
-    push_rate = 100_000 * args.steps / res["wall"]
-    field_avg_s = tm["field_ms"] / max(tm["n_field"], 1) * 1e-3
-    push_avg_s = tm["push_ms"] / max(tm["n_push"], 1) * 1e-3
-    achieved = BYTES_PER_SITE["f64"] * V / field_avg_s / 1e9
+    push_rate = n_part * args.steps / res["wall"]
+    kern = rooflines(res, args.precision, n_part, V)
+    dominant = max(kern, key=lambda k: kern[k]["avg_launch_us"])
+    dt = "f64" if args.precision == "fp64" else "f32"
     out = {
         "metric": "site-updates/s + particle-pushes/s at 512^2, % HBM peak; FP32-batched vs FP64",
         "value": site_rate,
@@ -228,17 +387,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": dt,
         "data": "synthetic",
         "config": {"workload": "MV Glasma 512^2, L=6 fm, g2mu=2 GeV, 50 sheets, dtau=a/8, 1e5 charm quarks "
-                               "(m=1.27 GeV, pT=0, tau_form=0.1 fm/c), FP64",
-                   "lattice": 512, "particles": 100_000, "precision": "fp64"},
+                               f"(m=1.27 GeV, pT=0, tau_form=0.1 fm/c), {args.precision.upper()}",
+                   "lattice": 512, "particles": n_part, "precision": args.precision},
         "pushes_per_s": push_rate,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "field_step_kernel<double>", "avg_launch_us": field_avg_s * 1e6,
-                     "bytes_per_launch": BYTES_PER_SITE["f64"] * V},
-        "push_kernel": {"avg_launch_us": push_avg_s * 1e6, "pushes_per_s_kernel": 100_000 / push_avg_s},
+        "roofline": dict(kern[dominant], dominant=dominant),
+        "kernels": kern,
         "graph_ms_per_step": res["graph_ms_per_step"],
         "launch": res["launch"],
         "ic_seconds": res["t_ic"],
@@ -247,15 +403,12 @@ def main():
     }
     if not args.no_extras:
         r32 = run_event(cp.FP32, args.steps, args.warmup)
-        t32 = r32["timing"]
-        f32_avg = t32["field_ms"] / max(t32["n_field"], 1) * 1e-3
+        k32 = rooflines(r32, "fp32", n_part, V)
         out["fp32"] = {"site_updates_per_s": V * args.steps / r32["wall"],
-                       "pushes_per_s": 100_000 * args.steps / r32["wall"],
+                       "pushes_per_s": n_part * args.steps / r32["wall"],
                        "ms_per_step": r32["wall"] * 1e3 / args.steps,
-                       "field_avg_launch_us": f32_avg * 1e6,
-                       "field_GBs": BYTES_PER_SITE["f32"] * V / f32_avg / 1e9,
-                       "field_frac_hbm": BYTES_PER_SITE["f32"] * V / f32_avg / 1e9 / HBM_PEAK_GBS,
-                       "push_avg_launch_us": t32["push_ms"] / max(t32["n_push"], 1) * 1e3,
+                       "graph_ms_per_step": r32["graph_ms_per_step"],
+                       "kernels": k32,
                        "launch": r32["launch"],
                        "dpT2_rel_vs_fp64": float(abs(r32["obs"][-1, 1] / res["obs"][-1, 1] - 1)),
                        "dpL2_rel_vs_fp64": float(abs(r32["obs"][-1, 2] / res["obs"][-1, 2] - 1))}

@@ -177,6 +177,10 @@ extern "C" cpic_status cpic_create(const cpic_glasma_params* gp, const cpic_part
     // few particles: several wavefronts share each particle group so that the
     // push still fills the 1024 SIMDs (tunable with cpic_tune)
     c->tpp = c->np <= (1 << 18) ? 4 : (c->np <= (1 << 20) ? 2 : 1);
+    // field update: LDS halo tiles of 64 x 4 sites (the tuner's usual pick at 256^2 .. 1024^2)
+    c->cfg.split = 2;
+    c->cfg.bx = 64;
+    c->cfg.by = 4;
     c->pblocks = c->np > 0 ? push_blocks((int)c->np, c->tpp) : 0;
     c->nslots = c->np > 0 ? num_slots(c->sc) : 0;
     if (e == hipSuccess && c->nslots > 0) {

@@ -249,8 +249,8 @@ void cpic_destroy(cpic_ctx* ctx);
  * all) evolved together.  Events are split into launch groups whose working
  * set fits the last-level cache (cpic_batch_set_group_bytes); the groups run
  * one after the other, each to the end of its events.  One step of a group is
- * one batched field launch, one batched push launch and one batched step-end
- * launch over its active events; each workgroup reads its (event, tile) or
+ * one batched field launch and one batched push launch (which also advances
+ * the step counters) over its active events; each workgroup reads its (event, tile) or
  * (event, particle block) item from a device work map.  Runs of steps are
  * replayed from HIP graphs; events that reach their n_max drop out of the
  * work maps.  Parameter arrays have n_events entries (particles may be NULL:

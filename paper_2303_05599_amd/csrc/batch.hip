@@ -6,11 +6,11 @@
 // one after the other, each to the end of its events.  For every set of
 // still active events of a group there is a plan: the active list and the
 // work maps (event, tile) and (event, particle block), one entry per
-// workgroup.  One step of a group is three launches -- batched field
-// update, batched push, batched step end.  Runs of steps between particle
-// reorderings are replayed from HIP graphs captured per plan; each event
-// reads its step number, and so its buffer parity, kick/formation/recording
-// decisions, from its own device counter.
+// workgroup.  One step of a group is two launches: the batched field update
+// and the batched push, which also advances the events' step counters.  Runs
+// of steps between particle reorderings are replayed from HIP graphs captured
+// per plan; each event reads its step number, and so its buffer parity and
+// its kick/formation/recording decisions, from its own device counter.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -111,7 +111,6 @@ static cpic_status upload_desc(cpic_batch* b)
         d.d_step = c->d_step;
         d.d_err = c->d_err;
         d.partials = c->partials;
-        d.obs = c->obs;
     }
     if (!b->d_desc) BHIP(b, hipMalloc(&b->d_desc, sizeof(EventDesc) * ne), "descriptor table");
     BHIP(b, hipMemcpyAsync(b->d_desc, b->desc.data(), sizeof(EventDesc) * ne, hipMemcpyHostToDevice, b->st),
@@ -167,7 +166,8 @@ static cpic_status get_plan(cpic_batch* b, const std::vector<int>& act, Plan** o
     std::vector<int2> tiles, blocks;
     for (int e : act) {
         const cpic_ctx* c = b->ev[e];
-        const int nt = field_tiles_host(c->N, b->cfg), nb = c->np > 0 ? push_blocks((int)c->np, b->tpp) : 0;
+        // an event without particles keeps one push workgroup, which advances its step counter
+        const int nt = field_tiles_host(c->N, b->cfg), nb = c->np > 0 ? push_blocks((int)c->np, b->tpp) : 1;
         for (int k = 0; k < nt; k++) tiles.push_back(make_int2(e, k));
         for (int k = 0; k < nb; k++) blocks.push_back(make_int2(e, k));
     }
@@ -185,12 +185,11 @@ static cpic_status get_plan(cpic_batch* b, const std::vector<int>& act, Plan** o
     return CPIC_OK;
 }
 
-// one step of every active event of a plan
+// one step of every active event of a plan (the push also advances the step counters)
 template <typename T> static cpic_status launch_batch_step(cpic_batch* b, const Plan& p)
 {
     BHIP(b, launch_batch_field<T>(b->d_desc, p.d_tiles, p.total_tiles, b->cfg, b->st), "batch field");
     BHIP(b, launch_batch_push<T>(b->d_desc, p.d_blocks, p.total_blocks, b->tpp, b->st), "batch push");
-    BHIP(b, launch_batch_step_end(b->d_desc, p.d_act, (int)p.act.size(), b->st), "batch step end");
     return CPIC_OK;
 }
 static cpic_status batch_step(cpic_batch* b, const Plan& p)

@@ -184,16 +184,16 @@ extern "C" cpic_status cpic_create(const cpic_glasma_params* gp, const cpic_part
     c->pblocks = c->np > 0 ? push_blocks((int)c->np, c->tpp) : 0;
     c->nslots = c->np > 0 ? num_slots(c->sc) : 0;
     if (e == hipSuccess && c->nslots > 0) {
-        e = hipMalloc(&c->partials, sizeof(double) * 4 * (size_t)push_blocks((int)c->np, 4) * c->nslots);
+        e = hipMalloc(&c->partials, sizeof(double) * 4 * (size_t)obs_groups((int)c->np) * c->nslots);
         if (e == hipSuccess) e = hipMalloc(&c->obs, sizeof(double) * 4 * c->nslots);
     }
-    if (e == hipSuccess) e = hipMalloc(&c->d_step, sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&c->d_step, 2 * sizeof(int));
     if (e == hipSuccess) e = hipMalloc(&c->d_err, sizeof(int));
     if (e == hipSuccess) e = hipMalloc(&c->d_fails, sizeof(int));
     c->dcap = std::max((c->V + 255) / 256, std::max(c->np > 0 ? push_blocks((int)c->np, 1) : 0, 1));
     if (e == hipSuccess) e = hipMalloc(&c->dpart, sizeof(double) * 8 * c->dcap);
     if (e == hipSuccess) e = hipMalloc(&c->dout, sizeof(double) * 16);
-    if (e == hipSuccess) e = hipMemsetAsync(c->d_step, 0, sizeof(int), c->st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->d_step, 0, 2 * sizeof(int), c->st);
     if (e == hipSuccess) e = hipMemsetAsync(c->d_err, 0, sizeof(int), c->st);
     if (e == hipSuccess && c->obs) e = hipMemsetAsync(c->obs, 0, sizeof(double) * 4 * c->nslots, c->st);
     if (e == hipSuccess) e = hipStreamSynchronize(c->st);
@@ -271,6 +271,7 @@ static cpic_status reset_counters(cpic_ctx* c, int n)
 {
     c->n = n;
     c->samples.clear();
+    c->obs_reduced = 0;
     HIPCHK(c, hipMemcpyAsync(c->d_step, &c->n, sizeof(int), hipMemcpyHostToDevice, c->st), "step counter");
     if (c->obs) HIPCHK(c, hipMemsetAsync(c->obs, 0, sizeof(double) * 4 * c->nslots, c->st), "obs reset");
     HIPCHK(c, hipStreamSynchronize(c->st), "reset");
@@ -376,7 +377,8 @@ template <typename T> static cpic_status launch_one(cpic_ctx* c, int parity, boo
             c->ev_push.push_back(e2); c->ev_push.push_back(e3);
         }
     }
-    HIPCHK(c, launch_step_end(c->sc, c->pblocks, c->partials, c->obs, c->d_step, c->st), "step end");
+    // the push advances the step counter; without particles a one-thread kernel does
+    if (c->np == 0) HIPCHK(c, launch_step_advance(c->d_step, c->st), "step advance");
     return CPIC_OK;
 }
 
@@ -502,6 +504,20 @@ extern "C" cpic_status cpic_sync(cpic_ctx* c)
     return CPIC_OK;
 }
 
+// Sum the per-group partials of every sample taken since the last call into
+// obs[slot] (groups in order, fixed-order block reduction).
+static cpic_status reduce_samples(cpic_ctx* c)
+{
+    const int groups = obs_groups((int)c->np);
+    for (size_t k = (size_t)c->obs_reduced; k < c->samples.size(); k++) {
+        const int slot = c->samples[k].first;
+        HIPCHK(c, launch_reduce_rows(c->partials + (size_t)slot * groups * 4, groups, 4, c->obs + (size_t)slot * 4,
+                                     c->st), "observables");
+    }
+    c->obs_reduced = (int)c->samples.size();
+    return CPIC_OK;
+}
+
 extern "C" cpic_status cpic_current_step(const cpic_ctx* c, int64_t* n)
 {
     if (!c || !n) return CPIC_E_INVALID;
@@ -521,7 +537,9 @@ extern "C" cpic_status cpic_observables_full(cpic_ctx* c, double* out, int32_t c
     const int ns = (int)c->samples.size();
     if (cap < ns) return fail(c, CPIC_E_CAPACITY, "cpic_observables: capacity " + std::to_string(cap) + " < " +
                                                       std::to_string(ns) + " samples");
-    cpic_status s = cpic_sync(c);
+    cpic_status s = reduce_samples(c);
+    if (s) return s;
+    s = cpic_sync(c);
     if (s) return s;
     if (!ns || !out) return CPIC_OK;
     std::vector<double> h(4 * (size_t)c->nslots);
@@ -741,6 +759,8 @@ struct CkptHeader {
 extern "C" cpic_status cpic_save(cpic_ctx* c, const char* path)
 {
     if (!c || !path) return fail(c, CPIC_E_INVALID, "cpic_save: NULL argument");
+    cpic_status rs = reduce_samples(c);
+    if (rs) return rs;
     HIPCHK(c, hipStreamSynchronize(c->st), "save");
     CkptHeader h{};
     std::memcpy(h.magic, "CPICKPT1", 8);
@@ -834,6 +854,7 @@ extern "C" cpic_status cpic_load(cpic_ctx* c, const char* path)
     HIPCHK(c, hipMemcpy(c->d_step, &c->n, sizeof(int), hipMemcpyHostToDevice), "load");
     if (!obs.empty()) HIPCHK(c, hipMemcpy(c->obs, obs.data(), sizeof(double) * obs.size(), hipMemcpyHostToDevice), "load");
     c->samples = samples;
+    c->obs_reduced = (int)samples.size();
     c->initialised = true;
     return CPIC_OK;
 }
@@ -969,6 +990,8 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
         HIPCHK(c, hipStreamSynchronize(c->st), "tune");
         int err = 0;
         HIPCHK(c, hipMemcpy(c->d_err, &err, sizeof(int), hipMemcpyHostToDevice), "tune");
+        // the trial pushes advanced the step counter: put it back
+        HIPCHK(c, hipMemcpy(c->d_step, &c->n, sizeof(int), hipMemcpyHostToDevice), "tune");
         c->tpp = best_tpp;
         c->pblocks = push_blocks((int)c->np, c->tpp);
         std::snprintf(line, sizeof line, "best push: lanes=%d %.2f us\n", best_tpp, best_p * 1e3);

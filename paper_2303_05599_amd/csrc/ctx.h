@@ -34,8 +34,9 @@ struct cpic_ctx {
     void* aux = nullptr;  // [24][V] magnetic-field pieces for the push (dynamic particles only)
     int* pcell = nullptr;  // [2][np]
     int pblocks = 0, nslots = 0;
-    double* partials = nullptr;  // [nslots][pblocks][4]
-    double* obs = nullptr;       // [nslots][4]
+    double* partials = nullptr;  // [nslots][particle groups of 64][4]
+    double* obs = nullptr;       // [nslots][4], summed from partials when samples are read
+    int obs_reduced = 0;         // samples[0 .. obs_reduced) are summed into obs
     std::vector<std::pair<int, int>> samples;  // (slot, step n after which it was taken)
     int* pid = nullptr;    // original index of each particle record
     cpic::SortBufs sb{};

@@ -167,12 +167,14 @@ __device__ __forceinline__ int logical_block(int total, int remap)
 
 template <typename T, bool AUX>
 __device__ __forceinline__ void field_step_body(const Fields<T>& in, const Fields<T>& out, T* aux, int N, int bx,
-                                                int by, int tile, const Schedule& sc, const int* __restrict__ d_step)
+                                                int by, int tile, const Schedule& sc, int* d_step)
 {
     const int ntx = (N + bx - 1) / bx;
     const int x = (tile % ntx) * bx + (int)threadIdx.x, y = (tile / ntx) * by + (int)threadIdx.y;
     if (x >= N || y >= N) return;
-    const int n = *d_step;
+    const int n = d_step[0];
+    // hand the step to this step's push (which advances d_step[0])
+    if (tile == 0 && threadIdx.x == 0 && threadIdx.y == 0) d_step[1] = n;
     const double td = n * sc.dt, thd = (n + 0.5) * sc.dt;
     const T t = T(td), inv_t = n > 0 ? T(1.0 / td) : T(0), dt = T(sc.dt);
     const T eps_drift = T(sc.dt / thd), phi_drift = T(sc.dt * thd);
@@ -223,7 +225,7 @@ __device__ __forceinline__ void field_step_body(const Fields<T>& in, const Field
 // its own site come straight from global memory.
 template <typename T, bool AUX, int BX, int BY>
 __device__ __forceinline__ void field_tile_body(const Fields<T>& in, const Fields<T>& out, T* aux, int N, int tile,
-                                                const Schedule& sc, const int* __restrict__ d_step)
+                                                const Schedule& sc, int* d_step)
 {
     constexpr int HX = BX + 2, HY = BY + 2, HS = HX * HY, NT = BX * BY, NC = 44;
     __shared__ T lds[NC * HS];
@@ -251,7 +253,8 @@ __device__ __forceinline__ void field_tile_body(const Fields<T>& in, const Field
     const int tx = tid % BX, ty = tid / BX;
     const int x = x0 + tx, y = y0 + ty;
     if (x >= N || y >= N) return;
-    const int n = *d_step;
+    const int n = d_step[0];
+    if (tile == 0 && tid == 0) d_step[1] = n;  // the step of this step's push
     const double td = n * sc.dt, thd = (n + 0.5) * sc.dt;
     const T t = T(td), inv_t = n > 0 ? T(1.0 / td) : T(0), dt = T(sc.dt);
     const T eps_drift = T(sc.dt / thd), phi_drift = T(sc.dt * thd);
@@ -297,7 +300,7 @@ __device__ __forceinline__ void field_tile_body(const Fields<T>& in, const Field
 
 template <typename T, bool AUX, int BX, int BY>
 __global__ __launch_bounds__(BX * BY) void field_tile_kernel(Fields<T> in, Fields<T> out, T* aux, int N, int remap,
-                                                             Schedule sc, const int* __restrict__ d_step)
+                                                             Schedule sc, int* d_step)
 {
     const int nt = ((N + BX - 1) / BX) * ((N + BY - 1) / BY), tile = logical_block(nt, remap);
     if (tile < nt) field_tile_body<T, AUX, BX, BY>(in, out, aux, N, tile, sc, d_step);
@@ -311,7 +314,7 @@ __global__ __launch_bounds__(BX * BY) void field_tile_kernel(Fields<T> in, Field
 // (one lane exchange, lanes l and l ^ 32), and the i = 0 thread writes phi, pi.
 template <typename T, bool AUX>
 __device__ __forceinline__ void field_link_body(const Fields<T>& in, const Fields<T>& out, T* aux, int N, int bx,
-                                                int by, int remap, const Schedule& sc, const int* __restrict__ d_step)
+                                                int by, int remap, const Schedule& sc, int* d_step)
 {
     const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
     const int i = lane >> 5, j = 1 - i;
@@ -324,7 +327,8 @@ __device__ __forceinline__ void field_link_body(const Fields<T>& in, const Field
     }
     const int x = (tile % ntx) * bx + local % bx, y = (tile / ntx) * by + local / bx;
     const bool live = tile < ntiles && x < N && y < N;
-    const int n = *d_step;
+    const int n = d_step[0];
+    if (tile == 0 && threadIdx.x == 0) d_step[1] = n;  // the step of this step's push
     const double td = n * sc.dt, thd = (n + 0.5) * sc.dt;
     const T t = T(td), inv_t = n > 0 ? T(1.0 / td) : T(0), dt = T(sc.dt);
     const T eps_drift = T(sc.dt / thd), phi_drift = T(sc.dt * thd);
@@ -419,19 +423,19 @@ __device__ __forceinline__ void field_link_body(const Fields<T>& in, const Field
 
 template <typename T, bool AUX>
 __global__ __launch_bounds__(256) void field_link_kernel(Fields<T> in, Fields<T> out, T* aux, int N, int bx, int by,
-                                                         int remap, Schedule sc, const int* __restrict__ d_step)
+                                                         int remap, Schedule sc, int* d_step)
 {
     field_link_body<T, AUX>(in, out, aux, N, bx, by, remap, sc, d_step);
 }
 template <typename T, bool AUX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void field_link_kernel_w2(
-    Fields<T> in, Fields<T> out, T* aux, int N, int bx, int by, int remap, Schedule sc, const int* __restrict__ d_step)
+    Fields<T> in, Fields<T> out, T* aux, int N, int bx, int by, int remap, Schedule sc, int* d_step)
 {
     field_link_body<T, AUX>(in, out, aux, N, bx, by, remap, sc, d_step);
 }
 template <typename T, bool AUX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void field_link_kernel_w3(
-    Fields<T> in, Fields<T> out, T* aux, int N, int bx, int by, int remap, Schedule sc, const int* __restrict__ d_step)
+    Fields<T> in, Fields<T> out, T* aux, int N, int bx, int by, int remap, Schedule sc, int* d_step)
 {
     field_link_body<T, AUX>(in, out, aux, N, bx, by, remap, sc, d_step);
 }
@@ -443,7 +447,7 @@ __device__ __forceinline__ int field_tiles(int N, int bx, int by) { return ((N +
 
 template <typename T, bool AUX>
 __global__ __launch_bounds__(256) void field_step_kernel(Fields<T> in, Fields<T> out, T* aux, int N, int bx, int by,
-                                                         int remap, Schedule sc, const int* __restrict__ d_step)
+                                                         int remap, Schedule sc, int* d_step)
 {
     const int nt = field_tiles(N, bx, by), tile = logical_block(nt, remap);
     if (tile < nt) field_step_body<T, AUX>(in, out, aux, N, bx, by, tile, sc, d_step);
@@ -452,7 +456,7 @@ __global__ __launch_bounds__(256) void field_step_kernel(Fields<T> in, Fields<T>
     template <typename T, bool AUX>                                                                               \
     __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, W))) void field_step_kernel_w##W(    \
         Fields<T> in, Fields<T> out, T* aux, int N, int bx, int by, int remap, Schedule sc,                       \
-        const int* __restrict__ d_step)                                                                           \
+        int* d_step)                                                                           \
     {                                                                                                             \
         const int nt = field_tiles(N, bx, by), tile = logical_block(nt, remap);                                   \
         if (tile < nt) field_step_body<T, AUX>(in, out, aux, N, bx, by, tile, sc, d_step);                        \
@@ -478,7 +482,7 @@ __global__ __launch_bounds__(256) void batch_field_kernel(const EventDesc* __res
     const int2 m = map[g];
     const int e = __builtin_amdgcn_readfirstlane(m.x), tile = __builtin_amdgcn_readfirstlane(m.y);
     const EventDesc& d = ev[e];
-    const int parity = __builtin_amdgcn_readfirstlane((*d.d_step & 1) ^ d.flip);
+    const int parity = __builtin_amdgcn_readfirstlane((d.d_step[0] & 1) ^ d.flip);
     const Fields<T> A = fields_at<T>(d.f[parity], d.N * d.N), B = fields_at<T>(d.f[parity ^ 1], d.N * d.N);
     // events without dynamic particles have no magnetic-field pieces to write
     if (d.aux)
@@ -502,7 +506,7 @@ template hipError_t launch_batch_field<float>(const EventDesc*, const int2*, int
 
 template <typename T, bool AUX, int BX, int BY>
 static hipError_t launch_tile(const Fields<T>& in, const Fields<T>& out, T* aux, int N, const Schedule& sc,
-                              const int* d_step, int remap, hipStream_t st)
+                              int* d_step, int remap, hipStream_t st)
 {
     const int ntiles = ((N + BX - 1) / BX) * ((N + BY - 1) / BY);
     const dim3 g(remap ? 8 * ((ntiles + 7) / 8) : ntiles), blk(BX * BY);
@@ -512,7 +516,7 @@ static hipError_t launch_tile(const Fields<T>& in, const Fields<T>& out, T* aux,
 
 template <typename T, bool AUX>
 static hipError_t launch_field_step_t(const Fields<T>& in, const Fields<T>& out, T* aux, int N, const Schedule& sc,
-                                      const int* d_step, const LaunchCfg& cfg, hipStream_t st)
+                                      int* d_step, const LaunchCfg& cfg, hipStream_t st)
 {
     if (cfg.split == 2) {
         // LDS halo tiles of the instantiated shapes
@@ -552,7 +556,7 @@ static hipError_t launch_field_step_t(const Fields<T>& in, const Fields<T>& out,
 
 template <typename T>
 hipError_t launch_field_step(const Fields<T>& in, const Fields<T>& out, T* aux, int N, const Schedule& sc,
-                             const int* d_step, const LaunchCfg& cfg, hipStream_t st)
+                             int* d_step, const LaunchCfg& cfg, hipStream_t st)
 {
     if (cfg.bx <= 0 || cfg.by <= 0 || cfg.waves < 1 || cfg.waves > 4) return hipErrorInvalidValue;
     return aux ? launch_field_step_t<T, true>(in, out, aux, N, sc, d_step, cfg, st)
@@ -633,9 +637,9 @@ hipError_t launch_field_diag(const Fields<T>& f, int N, double dt, int n, double
 }
 
 template hipError_t launch_field_step<double>(const Fields<double>&, const Fields<double>&, double*, int,
-                                              const Schedule&, const int*, const LaunchCfg&, hipStream_t);
+                                              const Schedule&, int*, const LaunchCfg&, hipStream_t);
 template hipError_t launch_field_step<float>(const Fields<float>&, const Fields<float>&, float*, int, const Schedule&,
-                                             const int*, const LaunchCfg&, hipStream_t);
+                                             int*, const LaunchCfg&, hipStream_t);
 template hipError_t launch_field_diag<double>(const Fields<double>&, int, double, int, double*, int, int*,
                                               hipStream_t);
 template hipError_t launch_field_diag<float>(const Fields<float>&, int, double, int, double*, int, int*,

@@ -85,10 +85,9 @@ struct EventDesc {
     int* cell;         // [2][np]
     int N;
     PushArgs pa;
-    int* d_step;
+    int* d_step;       // [2] (see the step counter protocol)
     int* d_err;
-    double* partials;  // [slots][push blocks][4]
-    double* obs;       // [slots][4]
+    double* partials;  // [slots][particle groups][4]
 };
 
 // particle blocks of the push: 256 / tpp particles per block
@@ -104,7 +103,7 @@ __host__ __device__ inline int push_blocks_d(int np, int tpp)
 constexpr int kAuxReals = 24;
 template <typename T>
 hipError_t launch_field_step(const Fields<T>& in, const Fields<T>& out, T* aux, int N, const Schedule& sc,
-                             const int* d_step, const LaunchCfg& cfg, hipStream_t st);
+                             int* d_step, const LaunchCfg& cfg, hipStream_t st);
 template <typename T>
 hipError_t launch_field_diag(const Fields<T>& f, int N, double dt, int n, double* partials, int nblk_cap,
                              int* nblk_out, hipStream_t st);
@@ -119,16 +118,17 @@ hipError_t launch_batch_field(const EventDesc* ev, const int2* map, int total_ti
 // aux the magnetic-field pieces of step n (unused for static particles)
 template <typename T>
 hipError_t launch_push(const Fields<T>& A, const Fields<T>& B, const T* aux, const Parts<T>& P, const PushArgs& a,
-                       const int* d_step, double* partials, int* err, hipStream_t st);
+                       int* d_step, double* partials, int* err, hipStream_t st);
 int push_blocks(int np, int tpp);
 template <typename T>
 hipError_t launch_batch_push(const EventDesc* ev, const int2* map, int total_blocks, int tpp, hipStream_t st);
-hipError_t launch_batch_step_end(const EventDesc* ev, const int* act, int nact, hipStream_t st);
 hipError_t launch_reduce_rows(const double* partials, int nrows, int ncols, double* out, hipStream_t st);
-// end of a step: on recording steps add the block partials of the step's slot
-// into obs[slot][4]; then advance the step counter
-hipError_t launch_step_end(const Schedule& sc, int nblocks, const double* partials, double* obs, int* d_step,
-                           hipStream_t st);
+// Step counter protocol: d_step[0] is the current step n; the field update
+// copies it to d_step[1]; the push (or, without particles, the step advance)
+// sets d_step[0] = d_step[1] + 1.
+hipError_t launch_step_advance(int* d_step, hipStream_t st);
+// samples: partials[slot][group of 64 particles][4]
+inline int obs_groups(int np) { return (np + 63) / 64; }
 template <typename T>
 hipError_t launch_part_diag(const Parts<T>& P, int np, double q2, double q3, double* partials, hipStream_t st);
 

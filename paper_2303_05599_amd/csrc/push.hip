@@ -236,17 +236,17 @@ __device__ __forceinline__ int xcd_block(int nblocks)
 // one barrier it contracts all of them with Q and takes the Euler step.
 template <int TPP> constexpr int kPushPPB = 256 / TPP;  // particles per block
 
+// Observables: on recording steps the owner wave of each group of 64 writes
+// the group's four double-precision sums to partials[slot][group][4]; they
+// are added over the groups, in group order, when the samples are read.
 template <typename T, int TPP>
 __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& Bf, const T* aux, const Parts<T>& P,
-                                          const PushArgs& a, const int* __restrict__ d_step, double* partials,
-                                          int* err, int blk)
+                                          const PushArgs& a, int n, double* partials, int* err, int blk)
 {
-    const int n = *d_step;
     if (n < a.sc.n_form || n >= a.sc.n_max) return;  // uniform over the event
     constexpr int PPB = kPushPPB<TPP>;
     constexpr int NG = PPB / 64;                     // particle groups per block
     constexpr int S = kSlots<TPP>;
-    const int nblocks = (a.np + PPB - 1) / PPB;
     const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
     const int role = wave % TPP, grp = wave / TPP;
     const int p = blk * PPB + grp * 64 + lane;
@@ -408,17 +408,36 @@ __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& 
             obs[3] = perp * perp;
         }
     }
-    if (record_slot >= 0)
-        block_reduce_store<4>(obs, 0u, partials + ((size_t)record_slot * nblocks + blk) * 4);
+    if (record_slot >= 0 && role == 0) {
+        const int ngroups = (np + 63) / 64, group = blk * NG + grp;
+        double* dst = partials + ((size_t)record_slot * ngroups + group) * 4;
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            const double v = wave_sum(obs[c]);
+            if (lane == 0 && group < ngroups) dst[c] = v;
+        }
+    }
+}
+
+// The field update of step n copies n into d_step[1]; the push reads it there
+// and its first block advances d_step[0] to n + 1 (no other kernel of the
+// push reads d_step[0], and the next field update starts after the push).
+__device__ __forceinline__ int push_step(int* d_step, int blk)
+{
+    const int n = d_step[1];
+    if (blk == 0 && threadIdx.x == 0) d_step[0] = n + 1;
+    return n;
 }
 
 template <typename T, int TPP>
 __global__ __launch_bounds__(256) void push_kernel(Fields<T> Af, Fields<T> Bf, const T* aux, Parts<T> P, PushArgs a,
-                                                   const int* __restrict__ d_step, double* partials, int* err)
+                                                   int* d_step, double* partials, int* err)
 {
     const int nblocks = (a.np + kPushPPB<TPP> - 1) / kPushPPB<TPP>;
     const int blk = xcd_block(nblocks);
-    if (blk < nblocks) push_body<T, TPP>(Af, Bf, aux, P, a, d_step, partials, err, blk);
+    if (blk >= nblocks) return;
+    const int n = push_step(d_step, blk);
+    push_body<T, TPP>(Af, Bf, aux, P, a, n, partials, err, blk);
 }
 
 // batched events: logical block g works on particle block map[g].y of event map[g].x
@@ -433,34 +452,11 @@ __global__ __launch_bounds__(256) void batch_push_kernel(const EventDesc* __rest
     const int2 m = map[g];
     const int e = __builtin_amdgcn_readfirstlane(m.x), blk = __builtin_amdgcn_readfirstlane(m.y);
     const EventDesc& d = ev[e];
-    const int V = d.N * d.N, parity = __builtin_amdgcn_readfirstlane((*d.d_step & 1) ^ d.flip);
+    const int n = __builtin_amdgcn_readfirstlane(push_step(d.d_step, blk));
+    if (d.pa.np == 0) return;  // an event without particles only advances its step
+    const int V = d.N * d.N, parity = (n & 1) ^ d.flip;
     push_body<T, TPP>(fields_at<T>(d.f[parity], V), fields_at<T>(d.f[parity ^ 1], V), static_cast<const T*>(d.aux),
-                      Parts<T>{static_cast<T*>(d.pr), d.cell}, d.pa, d.d_step, d.partials, d.d_err, blk);
-}
-
-// end of a step: on recording steps the block partials of the step's slot are
-// summed (fixed order) into obs[slot]; then the step counter advances
-__device__ __forceinline__ void step_end_body(const Schedule& sc, int nblocks, const double* __restrict__ partials,
-                                              double* obs, int* d_step)
-{
-    const int n = *d_step;
-    if (nblocks > 0 && is_record_step(sc, n)) {
-        const int slot = record_slot_of(sc, n);
-        const double* src = partials + (size_t)slot * nblocks * 4;
-        double v[4] = {0, 0, 0, 0};
-        for (int r = threadIdx.x; r < nblocks; r += blockDim.x)
-            for (int c = 0; c < 4; c++) v[c] += src[(size_t)r * 4 + c];
-        block_reduce_store<4>(v, 0u, obs + (size_t)slot * 4);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) *d_step = n + 1;
-}
-
-// one block per active event: the step end of each event
-__global__ __launch_bounds__(256) void batch_step_end_kernel(const EventDesc* __restrict__ ev, const int* __restrict__ act)
-{
-    const EventDesc& d = ev[act[blockIdx.x]];
-    step_end_body(d.pa.sc, d.pa.np > 0 ? push_blocks_d(d.pa.np, d.pa.tpp) : 0, d.partials, d.obs, d.d_step);
+                      Parts<T>{static_cast<T*>(d.pr), d.cell}, d.pa, n, d.partials, d.d_err, blk);
 }
 
 template <typename T>
@@ -475,12 +471,6 @@ hipError_t launch_batch_push(const EventDesc* ev, const int2* map, int total_blo
     }
     return hipGetLastError();
 }
-hipError_t launch_batch_step_end(const EventDesc* ev, const int* act, int nact, hipStream_t st)
-{
-    if (nact <= 0) return hipSuccess;
-    hipLaunchKernelGGL(batch_step_end_kernel, dim3(nact), dim3(256), 0, st, ev, act);
-    return hipGetLastError();
-}
 template hipError_t launch_batch_push<double>(const EventDesc*, const int2*, int, int, hipStream_t);
 template hipError_t launch_batch_push<float>(const EventDesc*, const int2*, int, int, hipStream_t);
 
@@ -488,7 +478,7 @@ int push_blocks(int np, int tpp) { return push_blocks_d(np, tpp); }
 
 template <typename T>
 hipError_t launch_push(const Fields<T>& A, const Fields<T>& B, const T* aux, const Parts<T>& P, const PushArgs& a,
-                       const int* d_step, double* partials, int* err, hipStream_t st)
+                       int* d_step, double* partials, int* err, hipStream_t st)
 {
     if (a.np <= 0) return hipSuccess;
     if (!a.is_static && !aux) return hipErrorInvalidValue;
@@ -502,16 +492,14 @@ hipError_t launch_push(const Fields<T>& A, const Fields<T>& B, const T* aux, con
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void step_end_kernel(Schedule sc, int nblocks, const double* __restrict__ partials,
-                                                       double* obs, int* d_step)
+// step end of an event without particles (no push): advance the step counter
+__global__ void step_advance_kernel(int* d_step)
 {
-    step_end_body(sc, nblocks, partials, obs, d_step);
+    if (threadIdx.x == 0) d_step[0] = d_step[1] + 1;
 }
-
-hipError_t launch_step_end(const Schedule& sc, int nblocks, const double* partials, double* obs, int* d_step,
-                           hipStream_t st)
+hipError_t launch_step_advance(int* d_step, hipStream_t st)
 {
-    hipLaunchKernelGGL(step_end_kernel, dim3(1), dim3(256), 0, st, sc, nblocks, partials, obs, d_step);
+    hipLaunchKernelGGL(step_advance_kernel, dim3(1), dim3(64), 0, st, d_step);
     return hipGetLastError();
 }
 
@@ -576,9 +564,9 @@ hipError_t launch_part_diag(const Parts<T>& P, int np, double q2, double q3, dou
 }
 
 template hipError_t launch_push<double>(const Fields<double>&, const Fields<double>&, const double*,
-                                        const Parts<double>&, const PushArgs&, const int*, double*, int*, hipStream_t);
+                                        const Parts<double>&, const PushArgs&, int*, double*, int*, hipStream_t);
 template hipError_t launch_push<float>(const Fields<float>&, const Fields<float>&, const float*, const Parts<float>&,
-                                       const PushArgs&, const int*, double*, int*, hipStream_t);
+                                       const PushArgs&, int*, double*, int*, hipStream_t);
 template hipError_t launch_part_diag<double>(const Parts<double>&, int, double, double, double*, hipStream_t);
 template hipError_t launch_part_diag<float>(const Parts<float>&, int, double, double, double*, hipStream_t);
 

@@ -233,9 +233,10 @@ cpic_status cpic_get_launch(const cpic_ctx* ctx, int32_t out[6]);
 cpic_status cpic_tune(cpic_ctx* ctx, int32_t reps, char* report, size_t cap);
 
 /* Kernel timing: when enabled, every field-update and particle-push launch
- * is bracketed by HIP events on the context's stream.  cpic_timing returns
- * the summed kernel times in ms and the launch counts since enabling, and
- * synchronises. */
+ * records its own start and stop times in HIP events attached to the launch
+ * (steps are then launched one by one instead of from graphs).  cpic_timing
+ * returns the summed kernel times in ms and the launch counts since enabling,
+ * and synchronises. */
 cpic_status cpic_set_timing(cpic_ctx* ctx, int32_t enable);
 cpic_status cpic_timing(cpic_ctx* ctx, double* field_ms, double* push_ms, int64_t* n_field, int64_t* n_push);
 

@@ -354,31 +354,25 @@ PushArgs cpic::push_args(const cpic_ctx* c, int tpp)
 template <typename T> static cpic_status launch_one(cpic_ctx* c, int parity, bool with_events)
 {
     const Fields<T> A = F<T>(c, parity), B = F<T>(c, parity ^ 1);
-    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
+    KTimer tf, tp;
     if (with_events) {
-        HIPCHK(c, hipEventCreate(&e0), "event"); HIPCHK(c, hipEventCreate(&e1), "event");
-        HIPCHK(c, hipEventRecord(e0, c->st), "event");
+        HIPCHK(c, hipEventCreate(&tf.start), "event"); HIPCHK(c, hipEventCreate(&tf.stop), "event");
+        c->ev_field.push_back(tf.start); c->ev_field.push_back(tf.stop);
     }
-    HIPCHK(c, launch_field_step<T>(A, B, static_cast<T*>(c->aux), c->N, c->sc, c->d_step, c->cfg, c->st), "field step");
-    if (with_events) {
-        HIPCHK(c, hipEventRecord(e1, c->st), "event");
-        c->ev_field.push_back(e0); c->ev_field.push_back(e1);
-    }
+    HIPCHK(c, launch_field_step<T>(A, B, static_cast<T*>(c->aux), c->N, c->sc, c->d_step, c->cfg, c->st, tf),
+           "field step");
     if (c->np > 0) {
         const PushArgs pa = push_args(c, c->tpp);
         if (with_events) {
-            HIPCHK(c, hipEventCreate(&e2), "event"); HIPCHK(c, hipEventCreate(&e3), "event");
-            HIPCHK(c, hipEventRecord(e2, c->st), "event");
+            HIPCHK(c, hipEventCreate(&tp.start), "event"); HIPCHK(c, hipEventCreate(&tp.stop), "event");
+            c->ev_push.push_back(tp.start); c->ev_push.push_back(tp.stop);
         }
         HIPCHK(c, launch_push<T>(A, B, static_cast<const T*>(c->aux), P<T>(c), pa, c->d_step, c->partials, c->d_err,
-                                 c->st), "push");
-        if (with_events) {
-            HIPCHK(c, hipEventRecord(e3, c->st), "event");
-            c->ev_push.push_back(e2); c->ev_push.push_back(e3);
-        }
+                                 c->st, tp), "push");
+    } else {
+        // the push advances the step counter; without particles a one-thread kernel does
+        HIPCHK(c, launch_step_advance(c->d_step, c->st), "step advance");
     }
-    // the push advances the step counter; without particles a one-thread kernel does
-    if (c->np == 0) HIPCHK(c, launch_step_advance(c->d_step, c->st), "step advance");
     return CPIC_OK;
 }
 

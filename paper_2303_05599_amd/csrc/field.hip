@@ -506,26 +506,26 @@ template hipError_t launch_batch_field<float>(const EventDesc*, const int2*, int
 
 template <typename T, bool AUX, int BX, int BY>
 static hipError_t launch_tile(const Fields<T>& in, const Fields<T>& out, T* aux, int N, const Schedule& sc,
-                              int* d_step, int remap, hipStream_t st)
+                              int* d_step, int remap, hipStream_t st, const KTimer& tm)
 {
     const int ntiles = ((N + BX - 1) / BX) * ((N + BY - 1) / BY);
     const dim3 g(remap ? 8 * ((ntiles + 7) / 8) : ntiles), blk(BX * BY);
-    hipLaunchKernelGGL((field_tile_kernel<T, AUX, BX, BY>), g, blk, 0, st, in, out, aux, N, remap, sc, d_step);
+    klaunch(tm, field_tile_kernel<T, AUX, BX, BY>, g, blk, st, in, out, aux, N, remap, sc, d_step);
     return hipGetLastError();
 }
 
 template <typename T, bool AUX>
 static hipError_t launch_field_step_t(const Fields<T>& in, const Fields<T>& out, T* aux, int N, const Schedule& sc,
-                                      int* d_step, const LaunchCfg& cfg, hipStream_t st)
+                                      int* d_step, const LaunchCfg& cfg, hipStream_t st, const KTimer& tm)
 {
     if (cfg.split == 2) {
         // LDS halo tiles of the instantiated shapes
         const int r = cfg.xcd_remap;
-        if (cfg.bx == 64 && cfg.by == 4) return launch_tile<T, AUX, 64, 4>(in, out, aux, N, sc, d_step, r, st);
-        if (cfg.bx == 32 && cfg.by == 4) return launch_tile<T, AUX, 32, 4>(in, out, aux, N, sc, d_step, r, st);
-        if (cfg.bx == 64 && cfg.by == 2) return launch_tile<T, AUX, 64, 2>(in, out, aux, N, sc, d_step, r, st);
-        if (cfg.bx == 32 && cfg.by == 8) return launch_tile<T, AUX, 32, 8>(in, out, aux, N, sc, d_step, r, st);
-        if (cfg.bx == 16 && cfg.by == 8) return launch_tile<T, AUX, 16, 8>(in, out, aux, N, sc, d_step, r, st);
+        if (cfg.bx == 64 && cfg.by == 4) return launch_tile<T, AUX, 64, 4>(in, out, aux, N, sc, d_step, r, st, tm);
+        if (cfg.bx == 32 && cfg.by == 4) return launch_tile<T, AUX, 32, 4>(in, out, aux, N, sc, d_step, r, st, tm);
+        if (cfg.bx == 64 && cfg.by == 2) return launch_tile<T, AUX, 64, 2>(in, out, aux, N, sc, d_step, r, st, tm);
+        if (cfg.bx == 32 && cfg.by == 8) return launch_tile<T, AUX, 32, 8>(in, out, aux, N, sc, d_step, r, st, tm);
+        if (cfg.bx == 16 && cfg.by == 8) return launch_tile<T, AUX, 16, 8>(in, out, aux, N, sc, d_step, r, st, tm);
         return hipErrorInvalidValue;
     }
     if (cfg.split) {
@@ -534,9 +534,9 @@ static hipError_t launch_field_step_t(const Fields<T>& in, const Fields<T>& out,
         const int ntiles = ((N + cfg.bx - 1) / cfg.bx) * ((N + cfg.by - 1) / cfg.by);
         const dim3 g(cfg.xcd_remap ? 8 * ((ntiles + 7) / 8) : ntiles), blk(256);
         switch (cfg.waves) {
-        case 2: hipLaunchKernelGGL((field_link_kernel_w2<T, AUX>), g, blk, 0, st, in, out, aux, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
-        case 3: hipLaunchKernelGGL((field_link_kernel_w3<T, AUX>), g, blk, 0, st, in, out, aux, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
-        default: hipLaunchKernelGGL((field_link_kernel<T, AUX>), g, blk, 0, st, in, out, aux, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step);
+        case 2: klaunch(tm, field_link_kernel_w2<T, AUX>, g, blk, st, in, out, aux, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
+        case 3: klaunch(tm, field_link_kernel_w3<T, AUX>, g, blk, st, in, out, aux, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
+        default: klaunch(tm, field_link_kernel<T, AUX>, g, blk, st, in, out, aux, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step);
         }
         return hipGetLastError();
     }
@@ -546,21 +546,21 @@ static hipError_t launch_field_step_t(const Fields<T>& in, const Fields<T>& out,
     const int grid = cfg.xcd_remap ? 8 * ((ntiles + 7) / 8) : ntiles;
     const dim3 g(grid), b(cfg.bx, cfg.by);
     switch (cfg.waves) {
-    case 2: hipLaunchKernelGGL((field_step_kernel_w2<T, AUX>), g, b, 0, st, in, out, aux, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
-    case 3: hipLaunchKernelGGL((field_step_kernel_w3<T, AUX>), g, b, 0, st, in, out, aux, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
-    case 4: hipLaunchKernelGGL((field_step_kernel_w4<T, AUX>), g, b, 0, st, in, out, aux, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
-    default: hipLaunchKernelGGL((field_step_kernel<T, AUX>), g, b, 0, st, in, out, aux, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step);
+    case 2: klaunch(tm, field_step_kernel_w2<T, AUX>, g, b, st, in, out, aux, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
+    case 3: klaunch(tm, field_step_kernel_w3<T, AUX>, g, b, st, in, out, aux, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
+    case 4: klaunch(tm, field_step_kernel_w4<T, AUX>, g, b, st, in, out, aux, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
+    default: klaunch(tm, field_step_kernel<T, AUX>, g, b, st, in, out, aux, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step);
     }
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_field_step(const Fields<T>& in, const Fields<T>& out, T* aux, int N, const Schedule& sc,
-                             int* d_step, const LaunchCfg& cfg, hipStream_t st)
+                             int* d_step, const LaunchCfg& cfg, hipStream_t st, const KTimer& tm)
 {
     if (cfg.bx <= 0 || cfg.by <= 0 || cfg.waves < 1 || cfg.waves > 4) return hipErrorInvalidValue;
-    return aux ? launch_field_step_t<T, true>(in, out, aux, N, sc, d_step, cfg, st)
-               : launch_field_step_t<T, false>(in, out, nullptr, N, sc, d_step, cfg, st);
+    return aux ? launch_field_step_t<T, true>(in, out, aux, N, sc, d_step, cfg, st, tm)
+               : launch_field_step_t<T, false>(in, out, nullptr, N, sc, d_step, cfg, st, tm);
 }
 
 // ------------------------------------------------------------------ diagnostics
@@ -637,9 +637,9 @@ hipError_t launch_field_diag(const Fields<T>& f, int N, double dt, int n, double
 }
 
 template hipError_t launch_field_step<double>(const Fields<double>&, const Fields<double>&, double*, int,
-                                              const Schedule&, int*, const LaunchCfg&, hipStream_t);
+                                              const Schedule&, int*, const LaunchCfg&, hipStream_t, const KTimer&);
 template hipError_t launch_field_step<float>(const Fields<float>&, const Fields<float>&, float*, int, const Schedule&,
-                                             int*, const LaunchCfg&, hipStream_t);
+                                             int*, const LaunchCfg&, hipStream_t, const KTimer&);
 template hipError_t launch_field_diag<double>(const Fields<double>&, int, double, int, double*, int, int*,
                                               hipStream_t);
 template hipError_t launch_field_diag<float>(const Fields<float>&, int, double, int, double*, int, int*,

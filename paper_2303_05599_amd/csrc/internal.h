@@ -4,6 +4,7 @@
 //   fields phi[a][s], E[i][a][s], pi[a][s] (8 algebra components a)
 // One field buffer set holds U, phi, E, pi contiguously (68 reals per site).
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -97,13 +98,27 @@ __host__ __device__ inline int push_blocks_d(int np, int tpp)
     return (np + ppb - 1) / ppb;
 }
 
+// Optional kernel timing: with `start` set, the launch records the kernel's
+// own start and stop times in the two events (no extra queue packets).
+struct KTimer {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+template <typename F, typename... Args>
+inline void klaunch(const KTimer& tm, F kernel, dim3 grid, dim3 block, hipStream_t st, Args... args)
+{
+    if (tm.start)
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, st, tm.start, tm.stop, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
+}
+
 // ---- field kernels (field.hip)
 // aux (may be NULL): [24][V] magnetic-field pieces for the push, written from
 // step n_form on: Proj U_12 (8), phi->_x - phi<-_x (8), phi->_y - phi<-_y (8)
 constexpr int kAuxReals = 24;
 template <typename T>
 hipError_t launch_field_step(const Fields<T>& in, const Fields<T>& out, T* aux, int N, const Schedule& sc,
-                             int* d_step, const LaunchCfg& cfg, hipStream_t st);
+                             int* d_step, const LaunchCfg& cfg, hipStream_t st, const KTimer& tm = KTimer{});
 template <typename T>
 hipError_t launch_field_diag(const Fields<T>& f, int N, double dt, int n, double* partials, int nblk_cap,
                              int* nblk_out, hipStream_t st);
@@ -118,7 +133,7 @@ hipError_t launch_batch_field(const EventDesc* ev, const int2* map, int total_ti
 // aux the magnetic-field pieces of step n (unused for static particles)
 template <typename T>
 hipError_t launch_push(const Fields<T>& A, const Fields<T>& B, const T* aux, const Parts<T>& P, const PushArgs& a,
-                       int* d_step, double* partials, int* err, hipStream_t st);
+                       int* d_step, double* partials, int* err, hipStream_t st, const KTimer& tm = KTimer{});
 int push_blocks(int np, int tpp);
 template <typename T>
 hipError_t launch_batch_push(const EventDesc* ev, const int2* map, int total_blocks, int tpp, hipStream_t st);

@@ -478,16 +478,16 @@ int push_blocks(int np, int tpp) { return push_blocks_d(np, tpp); }
 
 template <typename T>
 hipError_t launch_push(const Fields<T>& A, const Fields<T>& B, const T* aux, const Parts<T>& P, const PushArgs& a,
-                       int* d_step, double* partials, int* err, hipStream_t st)
+                       int* d_step, double* partials, int* err, hipStream_t st, const KTimer& tm)
 {
     if (a.np <= 0) return hipSuccess;
     if (!a.is_static && !aux) return hipErrorInvalidValue;
     const int nb = push_blocks(a.np, a.tpp);
     const dim3 g(8 * ((nb + 7) / 8)), b(256);
     switch (a.tpp) {
-    case 2: hipLaunchKernelGGL((push_kernel<T, 2>), g, b, 0, st, A, B, aux, P, a, d_step, partials, err); break;
-    case 4: hipLaunchKernelGGL((push_kernel<T, 4>), g, b, 0, st, A, B, aux, P, a, d_step, partials, err); break;
-    default: hipLaunchKernelGGL((push_kernel<T, 1>), g, b, 0, st, A, B, aux, P, a, d_step, partials, err);
+    case 2: klaunch(tm, push_kernel<T, 2>, g, b, st, A, B, aux, P, a, d_step, partials, err); break;
+    case 4: klaunch(tm, push_kernel<T, 4>, g, b, st, A, B, aux, P, a, d_step, partials, err); break;
+    default: klaunch(tm, push_kernel<T, 1>, g, b, st, A, B, aux, P, a, d_step, partials, err);
     }
     return hipGetLastError();
 }
@@ -564,9 +564,10 @@ hipError_t launch_part_diag(const Parts<T>& P, int np, double q2, double q3, dou
 }
 
 template hipError_t launch_push<double>(const Fields<double>&, const Fields<double>&, const double*,
-                                        const Parts<double>&, const PushArgs&, int*, double*, int*, hipStream_t);
+                                        const Parts<double>&, const PushArgs&, int*, double*, int*, hipStream_t,
+                                        const KTimer&);
 template hipError_t launch_push<float>(const Fields<float>&, const Fields<float>&, const float*, const Parts<float>&,
-                                       const PushArgs&, int*, double*, int*, hipStream_t);
+                                       const PushArgs&, int*, double*, int*, hipStream_t, const KTimer&);
 template hipError_t launch_part_diag<double>(const Parts<double>&, int, double, double, double*, hipStream_t);
 template hipError_t launch_part_diag<float>(const Parts<float>&, int, double, double, double*, hipStream_t);
 

@@ -213,7 +213,9 @@ def read_pmc_summary(path=PMC_SUMMARY):
 def kernel_names(launch, precision):
     t = "double" if precision == "fp64" else "float"
     v = launch["variant"]
-    if v == 2:
+    if v == 3:
+        field = f"field_ctile_kernel<{t}, true, {launch['bx']}, {launch['by']}>"
+    elif v == 2:
         field = f"field_tile_kernel<{t}, true, {launch['bx']}, {launch['by']}>"
     elif v == 1:
         field = "field_link_kernel" + ("" if launch["waves"] == 1 else f"_w{launch['waves']}") + f"<{t}, true>"

@@ -208,7 +208,10 @@ cpic_status cpic_load(cpic_ctx* ctx, const char* path);
  *      multiple of 64, <= 256, waves 1..4);
  *   1  one thread per link (bx * by = 128, bx a multiple of 32, waves 1..3);
  *   2  one thread per site, links and scalars of the tile and its halo staged
- *      in LDS first (bx x by one of 64x4, 32x4, 64x2, 32x8, 16x8; waves 1).
+ *      in LDS first (bx x by one of 64x4, 32x4, 64x2, 32x8, 16x8; waves 1);
+ *   3  as 2 with only the first two rows of each link in LDS (the third is
+ *      rebuilt) and the scalars read from global memory, so that two
+ *      workgroups share a CU (64x4, 32x8, 16x16, 32x4; waves 1).
  * Used by the tuner; takes effect for the next launch. */
 cpic_status cpic_set_launch(cpic_ctx* ctx, int32_t bx, int32_t by, int32_t xcd_remap, int32_t waves,
                             int32_t variant);
@@ -275,8 +278,9 @@ cpic_status cpic_batch_sync(cpic_batch* b);
  * XCD mapping over the current active events (state unchanged) and keeps the
  * fastest; report as in cpic_tune.  Synchronises. */
 cpic_status cpic_batch_tune(cpic_batch* b, int32_t reps, char* report, size_t cap);
-/* batched launch shape: field tile bx x by (bx*by in {64,128,192,256}),
- * xcd_remap 0/1, tpp = wavefronts per 64-particle group (1, 2, 4) */
+/* batched launch shape: compressed-link LDS field tiles bx x by (64x4, 32x8,
+ * 16x16 or 32x4), xcd_remap 0/1, tpp = wavefronts per 64-particle group
+ * (1, 2, 4) */
 cpic_status cpic_batch_set_launch(cpic_batch* b, int32_t bx, int32_t by, int32_t xcd_remap, int32_t tpp);
 /* Launch groups: events are taken by decreasing working set (both field
  * buffer sets, the magnetic-field pieces for the push and the particle

@@ -248,8 +248,10 @@ extern "C" cpic_status cpic_batch_create(int32_t n_events, const cpic_glasma_par
         }
         b->ev.push_back(c);
     }
-    // FP32 site kernel: 64 x 4 tiles; FP64: 128 x 1 (cpic_batch_tune refines both)
-    if (b->prec == CPIC_FP64) { b->cfg.bx = 128; b->cfg.by = 1; }
+    // compressed-link LDS tiles of 64 x 4 sites (cpic_batch_tune picks among the shapes)
+    b->cfg.split = 3;
+    b->cfg.bx = 64;
+    b->cfg.by = 4;
     *out = b;
     return CPIC_OK;
 }
@@ -354,12 +356,12 @@ template <typename T> static cpic_status tune_batch(cpic_batch* b, int reps, std
     if (groups.empty()) return CPIC_OK;
     cpic_status s = upload_desc(b);
     if (s) return s;
-    static const int shapes[][2] = {{64, 1}, {128, 1}, {256, 1}, {32, 2}, {64, 2}, {128, 2},
-                                    {16, 4}, {32, 4}, {64, 4}, {32, 8}, {16, 16}};
+    static const int shapes[][2] = {{64, 4}, {32, 8}, {16, 16}, {32, 4}};
     size_t most = 1;  // largest work map over shapes and groups
     for (const auto& sh : shapes)
         for (const auto& g : groups) {
             LaunchCfg cfg{};
+            cfg.split = 3;
             cfg.bx = sh[0];
             cfg.by = sh[1];
             size_t n = 0;
@@ -379,6 +381,7 @@ template <typename T> static cpic_status tune_batch(cpic_batch* b, int reps, std
     for (const auto& sh : shapes)
         for (int remap = 0; remap < 2 && e == hipSuccess; remap++) {
             LaunchCfg cfg{};
+            cfg.split = 3;
             cfg.bx = sh[0];
             cfg.by = sh[1];
             cfg.xcd_remap = remap;
@@ -439,8 +442,9 @@ extern "C" cpic_status cpic_batch_tune(cpic_batch* b, int32_t reps, char* report
 extern "C" cpic_status cpic_batch_set_launch(cpic_batch* b, int32_t bx, int32_t by, int32_t xcd_remap, int32_t tpp)
 {
     if (!b) return bfail(nullptr, CPIC_E_INVALID, "cpic_batch_set_launch: NULL");
-    if (bx < 1 || by < 1 || bx * by > 256 || (bx * by) % 64 != 0 || (tpp != 1 && tpp != 2 && tpp != 4))
-        return bfail(b, CPIC_E_INVALID, "cpic_batch_set_launch: bx*by must be 64, 128, 192 or 256; tpp 1, 2 or 4");
+    const bool shape = (bx == 64 && by == 4) || (bx == 32 && by == 8) || (bx == 16 && by == 16) || (bx == 32 && by == 4);
+    if (!shape || (tpp != 1 && tpp != 2 && tpp != 4))
+        return bfail(b, CPIC_E_INVALID, "cpic_batch_set_launch: tiles 64x4, 32x8, 16x16 or 32x4; tpp 1, 2 or 4");
     b->cfg.bx = bx;
     b->cfg.by = by;
     b->cfg.xcd_remap = xcd_remap ? 1 : 0;

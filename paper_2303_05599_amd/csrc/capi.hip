@@ -177,8 +177,8 @@ extern "C" cpic_status cpic_create(const cpic_glasma_params* gp, const cpic_part
     // few particles: several wavefronts share each particle group so that the
     // push still fills the 1024 SIMDs (tunable with cpic_tune)
     c->tpp = c->np <= (1 << 18) ? 4 : (c->np <= (1 << 20) ? 2 : 1);
-    // field update: LDS halo tiles of 64 x 4 sites (the tuner's usual pick at 256^2 .. 1024^2)
-    c->cfg.split = 2;
+    // field update: compressed-link LDS tiles of 64 x 4 sites (the tuner's usual pick at 512^2)
+    c->cfg.split = 3;
     c->cfg.bx = 64;
     c->cfg.by = 4;
     c->pblocks = c->np > 0 ? push_blocks((int)c->np, c->tpp) : 0;
@@ -867,11 +867,16 @@ extern "C" cpic_status cpic_set_launch(cpic_ctx* c, int32_t bx, int32_t by, int3
                            (bx == 32 && by == 8) || (bx == 16 && by == 8);
         if (!shape) return fail(c, CPIC_E_INVALID, "cpic_set_launch: LDS tiles are 64x4, 32x4, 64x2, 32x8 or 16x8");
         if (waves != 1) return fail(c, CPIC_E_INVALID, "cpic_set_launch: LDS tiles take waves = 1");
+    } else if (variant == 3) {
+        const bool shape = (bx == 64 && by == 4) || (bx == 32 && by == 8) || (bx == 16 && by == 16) ||
+                           (bx == 32 && by == 4);
+        if (!shape) return fail(c, CPIC_E_INVALID, "cpic_set_launch: compressed LDS tiles are 64x4, 32x8, 16x16 or 32x4");
+        if (waves != 1) return fail(c, CPIC_E_INVALID, "cpic_set_launch: LDS tiles take waves = 1");
     } else if (variant == 0) {
         if (bx <= 0 || by <= 0 || bx * by > 256 || (bx * by) % 64 != 0)
             return fail(c, CPIC_E_INVALID, "cpic_set_launch: need bx*by a multiple of 64 and <= 256");
     } else {
-        return fail(c, CPIC_E_INVALID, "cpic_set_launch: variant must be 0, 1 or 2");
+        return fail(c, CPIC_E_INVALID, "cpic_set_launch: variant must be 0, 1, 2 or 3");
     }
     if (waves < 1 || waves > 4) return fail(c, CPIC_E_INVALID, "cpic_set_launch: waves must be 1..4");
     c->cfg.split = variant;
@@ -911,7 +916,7 @@ extern "C" cpic_status cpic_timing(cpic_ctx* c, double* field_ms, double* push_m
 // field kernel reads the current buffer and writes the free one (the step is
 // not advanced); the push runs on a saved copy of the particle records, which
 // is restored after every trial.  The fastest configuration is kept.
-static const char* const kVariantName[3] = {"site", "link", "tile"};
+static const char* const kVariantName[4] = {"site", "link", "tile", "ctile"};
 
 template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::string& rep)
 {
@@ -935,6 +940,9 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
     const int tshapes[][2] = {{64, 4}, {32, 4}, {64, 2}, {32, 8}, {16, 8}};
     for (const auto& sh : tshapes)
         for (int remap = 0; remap <= 1; remap++) cands.push_back(LaunchCfg{sh[0], sh[1], remap, 1, 2});
+    const int cshapes[][2] = {{64, 4}, {32, 8}, {16, 16}, {32, 4}};
+    for (const auto& sh : cshapes)
+        for (int remap = 0; remap <= 1; remap++) cands.push_back(LaunchCfg{sh[0], sh[1], remap, 1, 3});
     for (const LaunchCfg& cfg : cands) {
                 HIPCHK(c, launch_field_step<T>(A, B, X, c->N, c->sc, c->d_step, cfg, c->st), "tune");  // warm-up
                 HIPCHK(c, hipEventRecord(e0, c->st), "tune");

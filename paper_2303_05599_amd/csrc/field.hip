@@ -306,6 +306,173 @@ __global__ __launch_bounds__(BX * BY) void field_tile_kernel(Fields<T> in, Field
     if (tile < nt) field_tile_body<T, AUX, BX, BY>(in, out, aux, N, tile, sc, d_step);
 }
 
+// ---------------------------------------------------------------- compressed-link LDS tiles
+// As the halo-tile variant, but LDS holds only the first two rows of each
+// link (12 of 18 reals; the third row of an SU(3) matrix is the complex
+// conjugate of the cross product of the first two) and the scalars are read
+// from global memory (L1/L2).  Smaller LDS tiles let two workgroups share a
+// CU, and the stencil forms each plaquette in one phase from links re-read
+// out of LDS, so no partial products stay live across phases.
+template <typename T, int HS> struct LdsLinks2 {
+    const T* l;  // [24][HS]: rows 0, 1 of U_x, then of U_y
+    __device__ __forceinline__ m3<T> U(uint32_t h, int i) const
+    {
+        m3<T> m;
+#pragma unroll
+        for (int c = 0; c < 6; c++) m.e[c] = {l[(12 * i + 2 * c) * HS + h], l[(12 * i + 2 * c + 1) * HS + h]};
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+            const cx<T> p = cmul(m.e[j1], m.e[3 + j2]), q = cmul(m.e[j2], m.e[3 + j1]);
+            m.e[6 + j] = {p.re - q.re, q.im - p.im};
+        }
+        return m;
+    }
+};
+
+template <typename T, bool AUX, int BX, int BY>
+__device__ __forceinline__ void field_ctile_body(const Fields<T>& in, const Fields<T>& out, T* aux, int N, int tile,
+                                                 const Schedule& sc, int* d_step)
+{
+    constexpr int HX = BX + 2, HY = BY + 2, HS = HX * HY, NT = BX * BY, NC = 24;
+    __shared__ T lds[NC * HS];
+    const int ntx = (N + BX - 1) / BX;
+    const int x0 = (tile % ntx) * BX, y0 = (tile / ntx) * BY;
+    const int tid = (int)threadIdx.x;
+    const uint32_t V = (uint32_t)N * N;
+    const View<T> vi = make_view<T>(in.U, kRealsPerSite, V), vo = make_view<T>(out.U, kRealsPerSite, V);
+    // stage rows 0, 1 of both links (buffer components 0..11 and 18..29)
+#pragma unroll
+    for (int h0 = 0; h0 < HS; h0 += NT) {
+        const int h = h0 + tid;
+        if (h < HS) {
+            const int hy = h / HX, hx = h - hy * HX;
+            const int gx = (x0 + hx - 1 + N) % N, gy = (y0 + hy - 1 + N) % N;
+            const uint32_t go = (uint32_t)(gy * N + gx) * (uint32_t)sizeof(T);
+            T v[NC];
+#pragma unroll
+            for (int c = 0; c < NC; c++) v[c] = bld(vi, go, (uint32_t)(c < 12 ? c : c + 6));
+#pragma unroll
+            for (int c = 0; c < NC; c++) lds[c * HS + h] = v[c];
+        }
+    }
+    __syncthreads();
+    const int tx = tid % BX, ty = tid / BX;
+    const int x = x0 + tx, y = y0 + ty;
+    if (x >= N || y >= N) return;
+    const int n = d_step[0];
+    if (tile == 0 && tid == 0) d_step[1] = n;  // the step of this step's push
+    const double td = n * sc.dt, thd = (n + 0.5) * sc.dt;
+    const T t = T(td), inv_t = n > 0 ? T(1.0 / td) : T(0), dt = T(sc.dt);
+    const T eps_drift = T(sc.dt / thd), phi_drift = T(sc.dt * thd);
+    const bool kick = n > 0, reunit = is_reunit_step(sc, n);
+    const uint32_t s = (uint32_t)((ty + 1) * HX + tx + 1);  // tile site
+    const uint32_t xp = s + 1, xm = s - 1, yp = s + HX, ym = s - HX, xpym = s + 1 - HX, xmyp = s - 1 + HX;
+    const Nbr g = neighbours<T>(x, y, N);                   // global sites (scalars, E, pi, outputs)
+    const LdsLinks2<T, HS> L{lds};
+    a8<T> PHI = vA(vi, g.s, kCompPhi);
+    a8<T> F1 = azero<T>(), F2 = azero<T>(), Fpi = azero<T>();
+    // the push reads the magnetic-field pieces from the first push step on
+    // (at n = 0, t = 1/t = 0 make the forces vanish, so the kick is still skipped)
+    const bool aux_on = AUX && aux != nullptr && n >= sc.n_form;
+    a8<T> G, DX, DY;  // magnetic-field pieces, stored last (keeps them out of the stencil's register peak)
+    if (kick || aux_on) {
+        {   // U_12(x) = U_1(x) U_2(x+1) U_1(x+2)^+ U_2(x)^+
+            m3<T> M = mul(L.U(s, 0), L.U(xp, 1));
+            M = mul_adj(M, L.U(yp, 0));
+            M = mul_adj(M, L.U(s, 1));
+            F1 = proj(M);
+            G = F1;
+#pragma unroll
+            for (int a = 0; a < 8; a++) F2.v[a] = -F1.v[a];
+        }
+        CPIC_PHASE();
+        {   // U_{1,-2}(x) = U_1(x) U_2(x+1-2)^+ U_1(x-2)^+ U_2(x-2)
+            m3<T> M = mul_adj(L.U(s, 0), L.U(xpym, 1));
+            M = mul_adj(M, L.U(ym, 0));
+            M = mul(M, L.U(ym, 1));
+            const a8<T> p = proj(M);
+#pragma unroll
+            for (int a = 0; a < 8; a++) F1.v[a] += p.v[a];
+        }
+        CPIC_PHASE();
+        {   // U_{2,-1}(x) = U_2(x) U_1(x-1+2)^+ U_2(x-1)^+ U_1(x-1)
+            m3<T> M = mul_adj(L.U(s, 1), L.U(xmyp, 0));
+            M = mul_adj(M, L.U(xm, 1));
+            M = mul(M, L.U(xm, 0));
+            const a8<T> p = proj(M);
+#pragma unroll
+            for (int a = 0; a < 8; a++) F2.v[a] += p.v[a];
+        }
+        CPIC_PHASE();
+        a8<T> lap;
+        {   // phi->_1, phi<-_1
+            const a8<T> f1 = transport(L.U(s, 0), vA(vi, g.xp, kCompPhi));
+            const a8<T> c1 = icomm(f1, PHI);
+            const a8<T> b1 = transport_adj(L.U(xm, 0), vA(vi, g.xm, kCompPhi));
+            a8<T> d;
+#pragma unroll
+            for (int a = 0; a < 8; a++) {
+                F1.v[a] = -t * F1.v[a] + inv_t * c1.v[a];
+                lap.v[a] = f1.v[a] + b1.v[a] - T(4) * PHI.v[a];
+                d.v[a] = f1.v[a] - b1.v[a];
+            }
+            DX = d;
+        }
+        CPIC_PHASE();
+        {   // phi->_2, phi<-_2
+            const a8<T> f2 = transport(L.U(s, 1), vA(vi, g.yp, kCompPhi));
+            const a8<T> c2 = icomm(f2, PHI);
+            const a8<T> b2 = transport_adj(L.U(ym, 1), vA(vi, g.ym, kCompPhi));
+            a8<T> d;
+#pragma unroll
+            for (int a = 0; a < 8; a++) {
+                F2.v[a] = -t * F2.v[a] + inv_t * c2.v[a];
+                Fpi.v[a] = inv_t * (lap.v[a] + f2.v[a] + b2.v[a]);
+                d.v[a] = f2.v[a] - b2.v[a];
+            }
+            DY = d;
+        }
+    }
+    CPIC_PHASE();
+    a8<T> E1 = vA(vi, g.s, kCompE), E2 = vA(vi, g.s, kCompE + 8), PI = vA(vi, g.s, kCompPi);
+#pragma unroll
+    for (int a = 0; a < 8; a++) {
+        E1.v[a] += dt * F1.v[a];
+        E2.v[a] += dt * F2.v[a];
+        PI.v[a] += dt * Fpi.v[a];
+    }
+    CPIC_PHASE();
+    // drift: U_i <- exp(i (dt/t_half) E_i) U_i ; phi <- phi + dt t_half pi
+    m3<T> U1 = mul(expi(E1, eps_drift), L.U(s, 0));
+    if (reunit) U1 = reunitarize(U1);
+    vU_st(vo, g.s, 0, U1);
+    CPIC_PHASE();
+    m3<T> U2 = mul(expi(E2, eps_drift), L.U(s, 1));
+    if (reunit) U2 = reunitarize(U2);
+    vU_st(vo, g.s, 1, U2);
+#pragma unroll
+    for (int a = 0; a < 8; a++) PHI.v[a] += phi_drift * PI.v[a];
+    vA_st(vo, g.s, kCompPhi, PHI);
+    vA_st(vo, g.s, kCompE, E1);
+    vA_st(vo, g.s, kCompE + 8, E2);
+    vA_st(vo, g.s, kCompPi, PI);
+    if (AUX && aux_on) {
+        const View<T> va = make_view<T>(aux, kAuxReals, V);
+        vA_st(va, g.s, 0, G);
+        vA_st(va, g.s, 8, DX);
+        vA_st(va, g.s, 16, DY);
+    }
+}
+
+template <typename T, bool AUX, int BX, int BY>
+__global__ __launch_bounds__(BX * BY) void field_ctile_kernel(Fields<T> in, Fields<T> out, T* aux, int N, int remap,
+                                                              Schedule sc, int* d_step)
+{
+    const int nt = ((N + BX - 1) / BX) * ((N + BY - 1) / BY), tile = logical_block(nt, remap);
+    if (tile < nt) field_ctile_body<T, AUX, BX, BY>(in, out, aux, N, tile, sc, d_step);
+}
+
 // ---------------------------------------------------------------- link-parallel variant
 // One thread per link: half-wavefront h of a wavefront handles direction i = h
 // for the same 32 sites.  Thread (x, i) forms the two plaquettes of its link,
@@ -470,10 +637,9 @@ CPIC_FIELD_VARIANT(4)
 // One launch advances every event of a launch group by one step: logical
 // block g works on tile map[g].y of event map[g].x; all events share the tile
 // shape.
-template <typename T>
-__global__ __launch_bounds__(256) void batch_field_kernel(const EventDesc* __restrict__ ev,
-                                                          const int2* __restrict__ map, int total, int bx, int by,
-                                                          int remap)
+template <typename T, int BX, int BY>
+__global__ __launch_bounds__(BX * BY) void batch_field_kernel(const EventDesc* __restrict__ ev,
+                                                              const int2* __restrict__ map, int total, int remap)
 {
     const int g = logical_block(total, remap);
     if (g >= total) return;
@@ -484,21 +650,29 @@ __global__ __launch_bounds__(256) void batch_field_kernel(const EventDesc* __res
     const EventDesc& d = ev[e];
     const int parity = __builtin_amdgcn_readfirstlane((d.d_step[0] & 1) ^ d.flip);
     const Fields<T> A = fields_at<T>(d.f[parity], d.N * d.N), B = fields_at<T>(d.f[parity ^ 1], d.N * d.N);
-    // events without dynamic particles have no magnetic-field pieces to write
-    if (d.aux)
-        field_step_body<T, true>(A, B, static_cast<T*>(d.aux), d.N, bx, by, tile, d.pa.sc, d.d_step);
-    else
-        field_step_body<T, false>(A, B, nullptr, d.N, bx, by, tile, d.pa.sc, d.d_step);
+    // events without dynamic particles have no magnetic-field pieces (aux = NULL)
+    field_ctile_body<T, true, BX, BY>(A, B, static_cast<T*>(d.aux), d.N, tile, d.pa.sc, d.d_step);
 }
 
+template <typename T, int BX, int BY>
+static void launch_batch_field_t(const EventDesc* ev, const int2* map, int total_tiles, int remap, hipStream_t st)
+{
+    const int grid = remap ? 8 * ((total_tiles + 7) / 8) : total_tiles;
+    hipLaunchKernelGGL((batch_field_kernel<T, BX, BY>), dim3(grid), dim3(BX * BY), 0, st, ev, map, total_tiles, remap);
+}
+
+// compressed-link LDS tiles (variant 3) of the instantiated shapes
 template <typename T>
 hipError_t launch_batch_field(const EventDesc* ev, const int2* map, int total_tiles, const LaunchCfg& cfg,
                               hipStream_t st)
 {
-    if (cfg.split || cfg.bx * cfg.by > 256 || total_tiles <= 0) return hipErrorInvalidValue;
-    const int grid = cfg.xcd_remap ? 8 * ((total_tiles + 7) / 8) : total_tiles;
-    hipLaunchKernelGGL(batch_field_kernel<T>, dim3(grid), dim3(cfg.bx, cfg.by), 0, st, ev, map, total_tiles, cfg.bx,
-                       cfg.by, cfg.xcd_remap);
+    if (cfg.split != 3 || total_tiles <= 0) return hipErrorInvalidValue;
+    const int r = cfg.xcd_remap;
+    if (cfg.bx == 64 && cfg.by == 4) launch_batch_field_t<T, 64, 4>(ev, map, total_tiles, r, st);
+    else if (cfg.bx == 32 && cfg.by == 8) launch_batch_field_t<T, 32, 8>(ev, map, total_tiles, r, st);
+    else if (cfg.bx == 16 && cfg.by == 16) launch_batch_field_t<T, 16, 16>(ev, map, total_tiles, r, st);
+    else if (cfg.bx == 32 && cfg.by == 4) launch_batch_field_t<T, 32, 4>(ev, map, total_tiles, r, st);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 template hipError_t launch_batch_field<double>(const EventDesc*, const int2*, int, const LaunchCfg&, hipStream_t);
@@ -514,10 +688,29 @@ static hipError_t launch_tile(const Fields<T>& in, const Fields<T>& out, T* aux,
     return hipGetLastError();
 }
 
+template <typename T, bool AUX, int BX, int BY>
+static hipError_t launch_ctile(const Fields<T>& in, const Fields<T>& out, T* aux, int N, const Schedule& sc,
+                               int* d_step, int remap, hipStream_t st, const KTimer& tm)
+{
+    const int ntiles = ((N + BX - 1) / BX) * ((N + BY - 1) / BY);
+    const dim3 g(remap ? 8 * ((ntiles + 7) / 8) : ntiles), blk(BX * BY);
+    klaunch(tm, field_ctile_kernel<T, AUX, BX, BY>, g, blk, st, in, out, aux, N, remap, sc, d_step);
+    return hipGetLastError();
+}
+
 template <typename T, bool AUX>
 static hipError_t launch_field_step_t(const Fields<T>& in, const Fields<T>& out, T* aux, int N, const Schedule& sc,
                                       int* d_step, const LaunchCfg& cfg, hipStream_t st, const KTimer& tm)
 {
+    if (cfg.split == 3) {
+        // compressed-link LDS tiles of the instantiated shapes
+        const int r = cfg.xcd_remap;
+        if (cfg.bx == 64 && cfg.by == 4) return launch_ctile<T, AUX, 64, 4>(in, out, aux, N, sc, d_step, r, st, tm);
+        if (cfg.bx == 32 && cfg.by == 8) return launch_ctile<T, AUX, 32, 8>(in, out, aux, N, sc, d_step, r, st, tm);
+        if (cfg.bx == 16 && cfg.by == 16) return launch_ctile<T, AUX, 16, 16>(in, out, aux, N, sc, d_step, r, st, tm);
+        if (cfg.bx == 32 && cfg.by == 4) return launch_ctile<T, AUX, 32, 4>(in, out, aux, N, sc, d_step, r, st, tm);
+        return hipErrorInvalidValue;
+    }
     if (cfg.split == 2) {
         // LDS halo tiles of the instantiated shapes
         const int r = cfg.xcd_remap;

@@ -66,7 +66,8 @@ struct LaunchCfg {
     int xcd_remap = 1;    // map consecutive tiles onto one XCD
     int waves = 1;        // register-allocation occupancy target of the field kernel (1 = compiler default)
     int split = 0;        // kernel variant: 0 one thread per site, 1 one thread per link (128 sites per
-                          // block), 2 one thread per site with the tile and its halo staged in LDS
+                          // block), 2 one thread per site with the tile and its halo staged in LDS,
+                          // 3 as 2 with two rows per link in LDS and the scalars from global memory
 };
 
 struct PushArgs {

@@ -57,13 +57,16 @@ def gpu():
 
 LAUNCHES = {"site64x4": (64, 4, 1, 1, 0), "site256x1w2": (256, 1, 0, 2, 0), "link128x1": (128, 1, 1, 1, 1),
             "link32x4w2": (32, 4, 0, 2, 1), "tile64x4": (64, 4, 1, 1, 2), "tile32x8": (32, 8, 0, 1, 2),
-            "tile16x8": (16, 8, 1, 1, 2), "tile64x2": (64, 2, 0, 1, 2), "tile32x4": (32, 4, 1, 1, 2)}
+            "tile16x8": (16, 8, 1, 1, 2), "tile64x2": (64, 2, 0, 1, 2), "tile32x4": (32, 4, 1, 1, 2),
+            "ctile64x4": (64, 4, 1, 1, 3), "ctile32x8": (32, 8, 0, 1, 3), "ctile16x16": (16, 16, 1, 1, 3),
+            "ctile32x4": (32, 4, 0, 1, 3)}
 
 
 @pytest.mark.parametrize("N,n0,launch", [(32, 3, "site64x4"), (96, 0, "site64x4"), (48, 1, "site64x4"),
                                          (96, 2, "link128x1"), (48, 1, "link32x4w2"), (32, 5, "site256x1w2"),
                                          (96, 1, "tile64x4"), (48, 2, "tile32x8"), (12, 0, "tile16x8"),
-                                         (36, 3, "tile64x2"), (64, 1, "tile32x4")])
+                                         (36, 3, "tile64x2"), (64, 1, "tile32x4"), (96, 2, "ctile64x4"),
+                                         (48, 1, "ctile32x8"), (12, 0, "ctile16x16"), (36, 3, "ctile32x4")])
 def test_field_leapfrog_fp64_random_state(N, n0, launch):
     """50 fused kick+drift steps from a random state; N = 96, 48, 36 and 12 leave ragged
     tiles (12 is smaller than the 16 x 8 tile); site-parallel, link-parallel and LDS
@@ -175,7 +178,7 @@ def test_static_limit_config_32():
     assert rel_err(ctx.get_state(cp.STATE_PARTICLES), run.P) <= TOL
 
 
-@pytest.mark.parametrize("launch", [None, "tile64x4", "link128x1"])
+@pytest.mark.parametrize("launch", [None, "tile64x4", "link128x1", "ctile32x8"])
 def test_full_chain_charm_like_64(launch):
     """Full chain at the paper-scale lattice spacing (a = 6 fm / 512) on a 64^2
     patch: 4 sheets, charm quarks (m = 1.27 GeV, p_T = 0) formed at 0.1 fm/c; the
@@ -209,7 +212,7 @@ def test_full_chain_charm_like_64(launch):
         assert abs(obs[-1, 1 + c] - last[c]) <= TOL * max(abs(last[c]), 1e-300), (c, obs[-1], last)
 
 
-@pytest.mark.parametrize("launch", ["site64x4", "tile16x8", "link32x4w2"])
+@pytest.mark.parametrize("launch", ["site64x4", "tile16x8", "link32x4w2", "ctile16x16"])
 def test_particles_formed_at_tau_zero(launch):
     """Dynamic particles formed at tau = 0 (n_form = 0): at n = 0 the kick is
     skipped but the magnetic-field pieces (clover, scalar gradients) must still
@@ -382,7 +385,8 @@ def test_tuner_leaves_state_unchanged():
     assert np.array_equal(a_ctx.get_state(cp.STATE_PARTICLES), b_ctx.get_state(cp.STATE_PARTICLES))
     a_ctx.step(20)
     b_ctx.step(20)
-    # a different launch shape only reorders nothing: results agree to rounding (bitwise for the field kernel)
+    # the tuned launch may use another decomposition of the same stencil, whose
+    # products associate differently: results agree to rounding
     for k in ("U", "phi", "E", "pi"):
-        assert np.array_equal(a_ctx.state()[k], b_ctx.state()[k]), k
-    assert rel_err(a_ctx.get_state(cp.STATE_PARTICLES), b_ctx.get_state(cp.STATE_PARTICLES)) < 1e-13
+        assert rel_err(a_ctx.state()[k], b_ctx.state()[k]) < 1e-12, k
+    assert rel_err(a_ctx.get_state(cp.STATE_PARTICLES), b_ctx.get_state(cp.STATE_PARTICLES)) < 1e-12

@@ -29,12 +29,12 @@ HBM_PEAK_GBS = 8000.0
 HBARC_GEV_FM = 0.1973269804
 # Algorithmic bytes per unit of work (per site-update of the field kernel, per
 # particle push): the field update reads and writes the 68 reals of a site
-# (U_x, U_y, phi, E_x, E_y, pi) and, with dynamic particles, writes the 24
-# reals of magnetic-field pieces the push reads (a partial force table); the
-# push moves its record (about 17 words each way), the six force fields at one
-# site (48 reals), phi at the cell (8) and a link on one step in eight.
+# (U_x, U_y, phi, E_x, E_y, pi) and, with particles, writes the 48 reals of
+# per-site field pieces the push reads (a force table); the push moves its
+# record (about 17 words each way), the six force fields at one site (48
+# reals), phi at the cell (8) and a link on one step in eight.
 SITE_BYTES = {"f64": 68 * 2 * 8, "f32": 68 * 2 * 4}
-AUX_BYTES = {"f64": 24 * 8, "f32": 24 * 4}
+AUX_BYTES = {"f64": 48 * 8, "f32": 48 * 4}
 PUSH_BYTES = {"f64": 730, "f32": 370}
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_512_fp64.txt")
 KERNEL_SOURCES = os.path.join(ROOT, "paper_2303_05599_amd", "csrc")

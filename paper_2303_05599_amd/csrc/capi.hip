@@ -162,7 +162,7 @@ extern "C" cpic_status cpic_create(const cpic_glasma_params* gp, const cpic_part
         const size_t np = c->np;
         e = hipMalloc(&c->pr, (size_t)kPartReals * np * c->tsz);
         if (e == hipSuccess) e = hipMalloc(&c->pcell, sizeof(int) * 2 * np);
-        if (e == hipSuccess && !c->is_static) e = hipMalloc(&c->aux, (size_t)kAuxReals * c->V * c->tsz);
+        if (e == hipSuccess) e = hipMalloc(&c->aux, (size_t)kAuxReals * c->V * c->tsz);
         if (e == hipSuccess) e = hipMalloc(&c->pid, sizeof(int) * np);
         if (e == hipSuccess) e = hipMalloc(&c->sb.keys, sizeof(unsigned) * np);
         if (e == hipSuccess) e = hipMalloc(&c->sb.keys2, sizeof(unsigned) * np);

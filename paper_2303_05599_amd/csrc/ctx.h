@@ -31,7 +31,7 @@ struct cpic_ctx {
     double q0[8]{}, q0eig[3]{}, q2ref = 0, q3ref = 0;
     void* fbuf[2] = {nullptr, nullptr};
     void* pr = nullptr;   // particle reals [18][np]
-    void* aux = nullptr;  // [24][V] magnetic-field pieces for the push (dynamic particles only)
+    void* aux = nullptr;  // [48][V] per-site field pieces for the push (events with particles)
     int* pcell = nullptr;  // [2][np]
     int pblocks = 0, nslots = 0;
     double* partials = nullptr;  // [nslots][particle groups of 64][4]

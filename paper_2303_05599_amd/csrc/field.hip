@@ -72,9 +72,10 @@ template <typename T, int HS> struct LdsSrc {
 // loaded in one phase, every product it enters is formed there, and it is
 // dropped, so at most two partial plaquettes stay in registers.
 // With AUX and `aux_on`, the per-site pieces of the magnetic fields that the
-// particle push assembles at its cell are written to `aux` (24 components):
+// particle push assembles at its cell are written to `aux`:
 //   G   = Proj U_12(x)                       (the clover leaves are transports of G)
 //   D_x = phi->_1(x) - phi<-_1(x),  D_y = phi->_2(x) - phi<-_2(x)
+// (the callers add the sums of E_x, E_y, pi over the two half steps).
 // (aux_s: the site's byte offset in the aux buffer).
 template <typename T, bool AUX = false, typename Src>
 __device__ __forceinline__ void kick_forces(const Src& f, const Nbr& nb, T t, T inv_t, const a8<T>& PHI,
@@ -105,7 +106,7 @@ __device__ __forceinline__ void kick_forces(const Src& f, const Nbr& nb, T t, T 
         const m3<T> U2 = f.U(nb.s, 1);
         const m3<T> P = mul_adj(A12, mul(U2, f.U(nb.yp, 0)));
         F1 = proj(P);
-        if (AUX && aux_on) vA_st(*aux, aux_s, 0, F1);
+        if (AUX && aux_on) vA_st(*aux, aux_s, kAuxG, F1);
 #pragma unroll
         for (int a = 0; a < 8; a++) F2.v[a] = -F1.v[a];   // Proj U_21 = -Proj U_12
         if (re_tr_p12) *re_tr_p12 = P.e[0].re + P.e[4].re + P.e[8].re;
@@ -130,7 +131,7 @@ __device__ __forceinline__ void kick_forces(const Src& f, const Nbr& nb, T t, T 
         if (AUX && aux_on) {
 #pragma unroll
             for (int a = 0; a < 8; a++) dy.v[a] -= b2.v[a];
-            vA_st(*aux, aux_s, 16, dy);
+            vA_st(*aux, aux_s, kAuxDy, dy);
         }
     }
     CPIC_PHASE();
@@ -143,7 +144,7 @@ __device__ __forceinline__ void kick_forces(const Src& f, const Nbr& nb, T t, T 
         if (AUX && aux_on) {
 #pragma unroll
             for (int a = 0; a < 8; a++) dx.v[a] -= b1.v[a];
-            vA_st(*aux, aux_s, 8, dx);
+            vA_st(*aux, aux_s, kAuxDx, dx);
         }
     }
 #pragma unroll
@@ -194,11 +195,20 @@ __device__ __forceinline__ void field_step_body(const Fields<T>& in, const Field
     }
     CPIC_PHASE();
     a8<T> E1 = vA(vi, nb.s, kCompE), E2 = vA(vi, nb.s, kCompE + 8), PI = vA(vi, nb.s, kCompPi);
+    a8<T> S1, S2, SP;  // sums of the momenta over the two half steps, for the push
 #pragma unroll
     for (int a = 0; a < 8; a++) {
+        S1.v[a] = E1.v[a]; S2.v[a] = E2.v[a]; SP.v[a] = PI.v[a];
         E1.v[a] += dt * F1.v[a];
         E2.v[a] += dt * F2.v[a];
         PI.v[a] += dt * Fpi.v[a];
+        S1.v[a] += E1.v[a]; S2.v[a] += E2.v[a]; SP.v[a] += PI.v[a];
+    }
+    if (AUX && aux_on) {
+        const View<T> va = make_view<T>(aux, kAuxReals, V);
+        vA_st(va, nb.s, kAuxS1, S1);
+        vA_st(va, nb.s, kAuxS2, S2);
+        vA_st(va, nb.s, kAuxP, SP);
     }
     CPIC_PHASE();
     // drift: U_i <- exp(i (dt/t_half) E_i) U_i ; phi <- phi + dt t_half pi
@@ -275,11 +285,20 @@ __device__ __forceinline__ void field_tile_body(const Fields<T>& in, const Field
     }
     CPIC_PHASE();
     a8<T> E1 = vA(vi, gs, kCompE), E2 = vA(vi, gs, kCompE + 8), PI = vA(vi, gs, kCompPi);
+    a8<T> S1, S2, SP;  // sums of the momenta over the two half steps, for the push
 #pragma unroll
     for (int a = 0; a < 8; a++) {
+        S1.v[a] = E1.v[a]; S2.v[a] = E2.v[a]; SP.v[a] = PI.v[a];
         E1.v[a] += dt * F1.v[a];
         E2.v[a] += dt * F2.v[a];
         PI.v[a] += dt * Fpi.v[a];
+        S1.v[a] += E1.v[a]; S2.v[a] += E2.v[a]; SP.v[a] += PI.v[a];
+    }
+    if (AUX && aux_on) {
+        const View<T> va = make_view<T>(aux, kAuxReals, V);
+        vA_st(va, gs, kAuxS1, S1);
+        vA_st(va, gs, kAuxS2, S2);
+        vA_st(va, gs, kAuxP, SP);
     }
     CPIC_PHASE();
     // drift: U_i <- exp(i (dt/t_half) E_i) U_i ; phi <- phi + dt t_half pi
@@ -436,11 +455,20 @@ __device__ __forceinline__ void field_ctile_body(const Fields<T>& in, const Fiel
     }
     CPIC_PHASE();
     a8<T> E1 = vA(vi, g.s, kCompE), E2 = vA(vi, g.s, kCompE + 8), PI = vA(vi, g.s, kCompPi);
+    a8<T> S1, S2, SP;  // sums of the momenta over the two half steps, for the push
 #pragma unroll
     for (int a = 0; a < 8; a++) {
+        S1.v[a] = E1.v[a]; S2.v[a] = E2.v[a]; SP.v[a] = PI.v[a];
         E1.v[a] += dt * F1.v[a];
         E2.v[a] += dt * F2.v[a];
         PI.v[a] += dt * Fpi.v[a];
+        S1.v[a] += E1.v[a]; S2.v[a] += E2.v[a]; SP.v[a] += PI.v[a];
+    }
+    if (AUX && aux_on) {
+        const View<T> va = make_view<T>(aux, kAuxReals, V);
+        vA_st(va, g.s, kAuxS1, S1);
+        vA_st(va, g.s, kAuxS2, S2);
+        vA_st(va, g.s, kAuxP, SP);
     }
     CPIC_PHASE();
     // drift: U_i <- exp(i (dt/t_half) E_i) U_i ; phi <- phi + dt t_half pi
@@ -459,9 +487,9 @@ __device__ __forceinline__ void field_ctile_body(const Fields<T>& in, const Fiel
     vA_st(vo, g.s, kCompPi, PI);
     if (AUX && aux_on) {
         const View<T> va = make_view<T>(aux, kAuxReals, V);
-        vA_st(va, g.s, 0, G);
-        vA_st(va, g.s, 8, DX);
-        vA_st(va, g.s, 16, DY);
+        vA_st(va, g.s, kAuxG, G);
+        vA_st(va, g.s, kAuxDx, DX);
+        vA_st(va, g.s, kAuxDy, DY);
     }
 }
 
@@ -527,13 +555,13 @@ __device__ __forceinline__ void field_link_body(const Fields<T>& in, const Field
     // thread, D_i = phi->_i - phi<-_i) from the first push step on
     const bool aux_on = AUX && n >= sc.n_form && live;
     View<T> va;
-    if (AUX) va = make_view<T>(aux, 24, V);
+    if (AUX) va = make_view<T>(aux, kAuxReals, V);
     if (kick || aux_on) {
         {   // U_ij(x) = U_i(x) U_j(x+i) [U_j(x) U_i(x+j)]^+
             const m3<T> Pm = mul_adj(mul(link(vi, s, i), link(vi, site(ix, iy), j)),
                                      mul(link(vi, s, j), link(vi, site(jx, jy), i)));
             F = proj(Pm);
-            if (AUX && aux_on && i == 0) vA_st(va, s, 0, F);
+            if (AUX && aux_on && i == 0) vA_st(va, s, kAuxG, F);
         }
         CPIC_PHASE();
         {   // U_{i,-j}(x) = U_i(x) U_j(x+i-j)^+ [U_j(x-j)^+ U_i(x-j)]^+
@@ -559,7 +587,7 @@ __device__ __forceinline__ void field_link_body(const Fields<T>& in, const Field
                 a8<T> d;
 #pragma unroll
                 for (int a = 0; a < 8; a++) d.v[a] = fw.v[a] - bw.v[a];
-                vA_st(va, s, 8 + 8 * i, d);
+                vA_st(va, s, i == 0 ? kAuxDx : kAuxDy, d);
             }
         }
         if (!kick) F = lap = azero<T>();
@@ -569,10 +597,17 @@ __device__ __forceinline__ void field_link_body(const Fields<T>& in, const Field
     for (int a = 0; a < 8; a++) lap.v[a] += __shfl_xor(lap.v[a], 32, 64);
     CPIC_PHASE();
     a8<T> Ei = vA(vi, s, kCompE + 8 * i), PI = vA(vi, s, kCompPi);
+    a8<T> Si, SP;  // sums of the momenta over the two half steps, for the push
 #pragma unroll
     for (int a = 0; a < 8; a++) {
+        Si.v[a] = Ei.v[a]; SP.v[a] = PI.v[a];
         Ei.v[a] += dt * F.v[a];
         PI.v[a] += dt * inv_t * lap.v[a];
+        Si.v[a] += Ei.v[a]; SP.v[a] += PI.v[a];
+    }
+    if (AUX && aux_on) {
+        vA_st(va, s, i == 0 ? kAuxS1 : kAuxS2, Si);
+        if (i == 0) vA_st(va, s, kAuxP, SP);
     }
     m3<T> Ui = mul(expi(Ei, eps_drift), link(vi, s, i));
     if (reunit) Ui = reunitarize(Ui);
@@ -650,7 +685,7 @@ __global__ __launch_bounds__(BX * BY) void batch_field_kernel(const EventDesc* _
     const EventDesc& d = ev[e];
     const int parity = __builtin_amdgcn_readfirstlane((d.d_step[0] & 1) ^ d.flip);
     const Fields<T> A = fields_at<T>(d.f[parity], d.N * d.N), B = fields_at<T>(d.f[parity ^ 1], d.N * d.N);
-    // events without dynamic particles have no magnetic-field pieces (aux = NULL)
+    // events without particles have no field pieces to write (aux = NULL)
     field_ctile_body<T, true, BX, BY>(A, B, static_cast<T*>(d.aux), d.N, tile, d.pa.sc, d.d_step);
 }
 

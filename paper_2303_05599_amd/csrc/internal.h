@@ -83,7 +83,7 @@ struct EventDesc {
     void* f[2];        // field buffer sets; the state at step n is in f[(n & 1) ^ flip]
     int flip;
     void* pr;          // particle records [18][np]
-    void* aux;         // [24][V] magnetic-field pieces (NULL without dynamic particles)
+    void* aux;         // [48][V] field pieces for the push (NULL without particles)
     int* cell;         // [2][np]
     int N;
     PushArgs pa;
@@ -114,9 +114,12 @@ inline void klaunch(const KTimer& tm, F kernel, dim3 grid, dim3 block, hipStream
 }
 
 // ---- field kernels (field.hip)
-// aux (may be NULL): [24][V] magnetic-field pieces for the push, written from
-// step n_form on: Proj U_12 (8), phi->_x - phi<-_x (8), phi->_y - phi<-_y (8)
-constexpr int kAuxReals = 24;
+// aux (may be NULL): [48][V] per-site pieces of the colour fields for the
+// push, written by the field update of the same step from step n_form on:
+//   G = Proj U_12, D_x = phi->_x - phi<-_x, D_y = phi->_y - phi<-_y,
+//   S_x, S_y, P = E_x, E_y, pi summed over the half steps n - 1/2 and n + 1/2
+constexpr int kAuxReals = 48;
+constexpr uint32_t kAuxG = 0, kAuxDx = 8, kAuxDy = 16, kAuxS1 = 24, kAuxS2 = 32, kAuxP = 40;
 template <typename T>
 hipError_t launch_field_step(const Fields<T>& in, const Fields<T>& out, T* aux, int N, const Schedule& sc,
                              int* d_step, const LaunchCfg& cfg, hipStream_t st, const KTimer& tm = KTimer{});
@@ -131,7 +134,7 @@ hipError_t launch_batch_field(const EventDesc* ev, const int2* map, int total_ti
 
 // ---- particle kernels (push.hip)
 // push at t_n: A holds U(n), phi(n), E(n-1/2), pi(n-1/2); B holds E(n+1/2), pi(n+1/2);
-// aux the magnetic-field pieces of step n (unused for static particles)
+// aux the field pieces of step n
 template <typename T>
 hipError_t launch_push(const Fields<T>& A, const Fields<T>& B, const T* aux, const Parts<T>& P, const PushArgs& a,
                        int* d_step, double* partials, int* err, hipStream_t st, const KTimer& tm = KTimer{});

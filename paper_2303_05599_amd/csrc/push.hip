@@ -178,43 +178,40 @@ __device__ __forceinline__ a8<T> job_field(int j, const View<T>& A, const View<T
 {
     a8<T> F;
     if (j <= kJobEy) {
+        // E_i from the half-step sums S_i = E_i(n-1/2) + E_i(n+1/2) of the aux buffer
         const int i = j;
         const uint32_t sb = i == 0 ? c.s_xm : c.s_ym;
-        const uint32_t ce = kCompE + 8 * i;
-        a8<T> here, back;
-#pragma unroll
-        for (int a = 0; a < 8; a++) {
-            here.v[a] = bld(A, c.s, ce + a) + bld(B, c.s, ce + a);
-            back.v[a] = bld(A, sb, ce + a) + bld(B, sb, ce + a);
-        }
-        const a8<T> tb = transport_adj(vU(A, sb, i), back);
+        const uint32_t cs = i == 0 ? kAuxS1 : kAuxS2;
+        const a8<T> here = vA(X, c.s, cs);
+        const a8<T> tb = transport_adj(vU(A, sb, i), vA(X, sb, cs));
         const T q = T(1) / (T(4) * t);
 #pragma unroll
         for (int a = 0; a < 8; a++) F.v[a] = q * (here.v[a] + tb.v[a]);
     } else if (j == kJobEeta) {
         if (n > 0) {
+            const a8<T> P = vA(X, c.s, kAuxP);
 #pragma unroll
-            for (int a = 0; a < 8; a++) F.v[a] = T(0.5) * (bld(A, c.s, kCompPi + a) + bld(B, c.s, kCompPi + a));
+            for (int a = 0; a < 8; a++) F.v[a] = T(0.5) * P.v[a];
         } else {
             F = vA(B, c.s, kCompPi);
         }
     } else if (j <= kJobBy) {
-        // B_x = -(1/2t) D_y (aux components 16..23), B_y = +(1/2t) D_x (8..15)
+        // B_x = -(1/2t) D_y, B_y = +(1/2t) D_x
         const bool bx = j == kJobBx;
         const T q = (bx ? T(-1) : T(1)) / (T(2) * t);
-        const a8<T> D = vA(X, c.s, bx ? 16u : 8u);
+        const a8<T> D = vA(X, c.s, bx ? kAuxDy : kAuxDx);
 #pragma unroll
         for (int a = 0; a < 8; a++) F.v[a] = q * D.v[a];
     } else {
-        const a8<T> g2 = transport_adj(vU(A, c.s_ym, 1), vA(X, c.s_ym, 0));
+        const a8<T> g2 = transport_adj(vU(A, c.s_ym, 1), vA(X, c.s_ym, kAuxG));
         CPIC_PHASE();
-        const a8<T> g12 = transport_adj(vU(A, c.s_xmym, 1), vA(X, c.s_xmym, 0));
-        a8<T> g1 = vA(X, c.s_xm, 0);
+        const a8<T> g12 = transport_adj(vU(A, c.s_xmym, 1), vA(X, c.s_xmym, kAuxG));
+        a8<T> g1 = vA(X, c.s_xm, kAuxG);
 #pragma unroll
         for (int a = 0; a < 8; a++) g1.v[a] += g12.v[a];
         CPIC_PHASE();
         const a8<T> g1t = transport_adj(vU(A, c.s_xm, 0), g1);
-        const a8<T> g0 = vA(X, c.s, 0);
+        const a8<T> g0 = vA(X, c.s, kAuxG);
 #pragma unroll
         for (int a = 0; a < 8; a++) F.v[a] = T(-0.25) * (g0.v[a] + g1t.v[a] + g2.v[a]);
     }
@@ -255,7 +252,7 @@ __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& 
     const int N = a.N, np = a.np;
     const uint32_t V = (uint32_t)N * N;
     const View<T> A = make_view<T>(Af.U, kRealsPerSite, V), B = make_view<T>(Bf.U, kRealsPerSite, V);
-    const View<T> X = make_view<T>(aux ? aux : Af.U, kAuxReals, V);  // not read for static particles
+    const View<T> X = make_view<T>(aux, kAuxReals, V);
     const View<T> R = make_view<T>(P.r, kPartReals, (uint32_t)np);
     const View<int> C = make_view<int>(P.cell, 2, (uint32_t)np);
     const T dt = T(a.sc.dt), t = T(n * a.sc.dt);
@@ -481,7 +478,7 @@ hipError_t launch_push(const Fields<T>& A, const Fields<T>& B, const T* aux, con
                        int* d_step, double* partials, int* err, hipStream_t st, const KTimer& tm)
 {
     if (a.np <= 0) return hipSuccess;
-    if (!a.is_static && !aux) return hipErrorInvalidValue;
+    if (!aux) return hipErrorInvalidValue;
     const int nb = push_blocks(a.np, a.tpp);
     const dim3 g(8 * ((nb + 7) / 8)), b(256);
     switch (a.tpp) {

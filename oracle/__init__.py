@@ -68,6 +68,7 @@ def lib():
             "orc_particle_fields": (None, [i, i, d, i, p, p, p, p, p, p, p]),
             "orc_particles_step": (i, [i, i, i, d, d, i, p, p, p, p, p, p, i, p]),
             "orc_particles_observe": (None, [d, d, i, i, p, p]),
+            "orc_jet_step": (None, [i, i, i, d, d, i, p, p, p, p, p, p, p, p]),
             "orc_generator": (None, [i, p]),
             "orc_proj": (None, [p, p]),
             "orc_expi": (None, [p, d, p]),
@@ -282,15 +283,43 @@ def particles_observe(t, mhat, is_static, P):
     return out
 
 
+class Jets:
+    """Light-like jet limit of the momentum broadening (Sec. V.B,
+    [eq:mombroadjets]): straight paths along +x at the speed of light, one per
+    lattice site, starting at x = site + x_off at step n_form.  W (N,N,3,3) is
+    each path's Wilson line, F (N,N,3,8) the accumulated transported force
+    sum_n w f~_i(t_n), i = x, y, z (see orc_jet_step for the discretisation)."""
+
+    def __init__(self, N, dt, n_form=0, x_off=0.0, stride=1):
+        assert 0 < dt <= 1 and stride >= 1 and 0 <= x_off < 1
+        self.N, self.dt, self.n_form, self.x_off, self.stride = N, dt, n_form, float(x_off), int(stride)
+        self.W = np.zeros((N, N, 3, 3), np.complex128)
+        self.F = np.zeros((N, N, 3, 8))
+
+    def step(self, n, U, phi, E_old, E_new, pi_old, pi_new):
+        """Step n with U(n), phi(n), E(n -+ 1/2), pi(n -+ 1/2) (the push's inputs)."""
+        lib().orc_jet_step(self.N, n, self.n_form, self.dt, self.x_off, self.stride, _ptr(U), _ptr(phi),
+                           _ptr(E_old), _ptr(E_new), _ptr(pi_old), _ptr(pi_new), _ptr(self.W), _ptr(self.F))
+
+    def observe(self, rep=0):
+        """<dp_i^2>, i = x, y, z, in hat units for charges of representation rep:
+        a charge rotated uniformly over its orbit has <Q^a Q^b> = delta^ab q2 / 8
+        ([eq:qnpointfct_main]), so <(Q.F_i)^2> = q2 / 8 |F_i|^2, averaged over
+        the paths."""
+        q = q0(rep)
+        q2 = float(np.dot(q, q))
+        return q2 / 8.0 * np.mean(np.sum(self.F ** 2, axis=-1), axis=(0, 1))
+
+
 class Run:
     """Interleaved field leapfrog and particle push (Sec. II.A and III.B).
 
     step n: the fields go U(n), phi(n), E(n-1/2), pi(n-1/2) -> U(n+1), phi(n+1),
     E(n+1/2), pi(n+1/2); then, if n >= n_form, the particles are pushed at t_n
     with U(n), phi(n), E(n +- 1/2), pi(n +- 1/2).  mhat = inf selects the static
-    branch."""
+    branch.  An optional Jets object is stepped with the same inputs as the push."""
 
-    def __init__(self, N, dt, state, particles=None, mhat=math.inf, n_form=0, n0=0):
+    def __init__(self, N, dt, state, particles=None, mhat=math.inf, n_form=0, n0=0, jets=None):
         self.N, self.dt, self.n = N, dt, n0
         self.st = {k: np.ascontiguousarray(state[k]).copy() for k in ("U", "phi", "E", "pi")}
         self.P = None if particles is None else np.ascontiguousarray(particles).copy()
@@ -298,11 +327,13 @@ class Run:
         self.mhat = 0.0 if self.is_static else float(mhat)
         self.n_form = n_form
         self.errors = 0
+        self.jets = jets
 
     def step(self):
         N, n, st = self.N, self.n, self.st
         push = self.P is not None and self.P.shape[0] > 0 and n >= self.n_form
-        if push:
+        jets = self.jets is not None and n >= self.jets.n_form
+        if push or jets:
             U_n, phi_n = st["U"].copy(), st["phi"].copy()
             E_old, pi_old = st["E"].copy(), st["pi"].copy()
         field_step(N, n, self.dt, st)
@@ -310,6 +341,8 @@ class Run:
             self.errors += lib().orc_particles_step(
                 N, n, self.n_form, self.dt, self.mhat, int(self.is_static), _ptr(U_n), _ptr(phi_n),
                 _ptr(E_old), _ptr(st["E"]), _ptr(pi_old), _ptr(st["pi"]), self.P.shape[0], _ptr(self.P))
+        if jets:
+            self.jets.step(n, U_n, phi_n, E_old, st["E"], pi_old, st["pi"])
         self.n += 1
 
     def observe(self):

@@ -888,6 +888,69 @@ void orc_particles_observe(double t, double mhat, int is_static, int np, const d
     out[0] = s0; out[1] = s1; out[2] = s2; out[3] = s3;
 }
 
+/*
+ * Light-like jet limit (Sec. V.B, [eq:mombroadjets]): one step of the
+ * integral of the transported Lorentz force along straight paths in +x at the
+ * speed of light, one path per lattice site, formed at step n_form.
+ *
+ * Path p = y*N + i starts at x = i + x_off in row y.  After m = n - n_form
+ * steps it is at x = i + x_off + m dt, so its nearest grid point is
+ * i + k(m) with k(m) = floor(x_off + m dt + 1/2) (mod N).
+ *   - m = 0: W = 1, F = 0.
+ *   - Wilson line (reading): when the nearest grid point moves from c to
+ *     c + x, W <- W U_x(c), with the link at t_n.  W is then the ordered
+ *     product of the x links crossed so far, and Tr(Q_0 W f W^+) is the
+ *     force that a charge carried along by the colour rotation of Sec. III.B
+ *     feels (f~ = W f W^+).
+ *   - Force components for velocity +x, at the nearest grid point c, from
+ *     the fields of orc_particle_fields:
+ *       f_x = E_x,  f_y = E_y - B_eta,  f_z = E_eta + B_y.
+ *   - The time integral is a sum over the steps with m % stride == 0, each
+ *     weighted by stride * dt (stride = 1: every step, like the Euler push;
+ *     stride = 1/dt: steps of one lattice spacing).
+ * W: [V][3][3] complex, F: [V][3][8] (f_x, f_y, f_z components).
+ * Requires dt <= 1 (at most one cell per step).
+ */
+void orc_jet_step(int N, int n, int n_form, double dt, double x_off, int stride, const cplx *U, const double *phi,
+                  const double *E_old, const double *E_new, const double *pi_old, const double *pi_new, cplx *W,
+                  double *F)
+{
+    build_generators();
+    const int V = N * N;
+    const int m = n - n_form;
+    if (m < 0) return;
+    const long k = (long)floor(x_off + m * dt + 0.5);
+    const long kp = m > 0 ? (long)floor(x_off + (m - 1) * dt + 0.5) : k;
+#pragma omp parallel for schedule(static)
+    for (int p = 0; p < V; p++) {
+        const int i = p % N, y = p / N;
+        M3 *w = (M3 *)(W + (size_t)p * 9);
+        double *Fp = F + (size_t)p * 24;
+        if (m == 0) {
+            *w = m_id();
+            memset(Fp, 0, sizeof(double) * 24);
+        } else if (k != kp) {
+            const int c_old = y * N + (int)(((i + kp) % N + N) % N);
+            *w = m_mul(*w, link(U, N, 0, c_old));
+        }
+        if (m % stride != 0) continue;
+        const int c = y * N + (int)(((i + k) % N + N) % N);
+        double f[48];
+        orc_particle_fields(N, n, dt, c, U, phi, E_old, E_new, pi_old, pi_new, f);
+        double comp[3][8];
+        for (int a = 0; a < 8; a++) {
+            comp[0][a] = f[a];
+            comp[1][a] = f[8 + a] - f[40 + a];
+            comp[2][a] = f[16 + a] + f[32 + a];
+        }
+        for (int j = 0; j < 3; j++) {
+            double ft[8];
+            mat_to_alg(m_mul3(*w, alg_to_mat(comp[j]), m_adj(*w)), ft);
+            for (int a = 0; a < 8; a++) Fp[8 * j + a] += stride * dt * ft[a];
+        }
+    }
+}
+
 /* ------------------- exports used only by the oracle's own pins ------------------- */
 /* T^a as 3x3 complex, row-major (a = 0..7) */
 void orc_generator(int a, cplx *out)

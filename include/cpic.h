@@ -183,6 +183,10 @@ cpic_status cpic_diagnostics(cpic_ctx* ctx, double out[10]);
  *                        (p^z for the static branch), Q^1..Q^8, cell x, cell y,
  *                        last eta increment, initial direction (ux, uy), |p_T(form)|
  *   CPIC_STATE_STEP      int64 [1]                   n (setting it clears the samples)
+ *   CPIC_STATE_JET_W     complex128 [N][N][3][3]     Wilson line of the light-like path
+ *                        starting in site (y, x) (get only; cpic_jets_enable)
+ *   CPIC_STATE_JET_F     float64 [N][N][3][8]        its integrated transported force
+ *                        components F_x, F_y, F_z (get only)
  * bytes must equal the exact size (CPIC_E_CAPACITY otherwise).  Synchronises.
  */
 #define CPIC_STATE_U 0
@@ -191,6 +195,8 @@ cpic_status cpic_diagnostics(cpic_ctx* ctx, double out[10]);
 #define CPIC_STATE_PI 3
 #define CPIC_STATE_PARTICLES 4
 #define CPIC_STATE_STEP 5
+#define CPIC_STATE_JET_W 6
+#define CPIC_STATE_JET_F 7
 cpic_status cpic_get_state(cpic_ctx* ctx, int32_t which, void* host_dst, size_t bytes);
 cpic_status cpic_set_state(cpic_ctx* ctx, int32_t which, const void* host_src, size_t bytes);
 
@@ -242,6 +248,52 @@ cpic_status cpic_tune(cpic_ctx* ctx, int32_t reps, char* report, size_t cap);
  * and synchronises. */
 cpic_status cpic_set_timing(cpic_ctx* ctx, int32_t enable);
 cpic_status cpic_timing(cpic_ctx* ctx, double* field_ms, double* push_ms, int64_t* n_field, int64_t* n_push);
+
+/*
+ * Light-like jet limit of the momentum broadening (Sec. V.B,
+ * [eq:mombroadjets]).  A parton moving along +x at the speed of light feels
+ * f_x = E_x, f_y = E_y - B_eta, f_z = E_eta + B_y (the fields of Sec. III.B at
+ * its nearest grid point), seen through the Wilson line W of the x links it
+ * has crossed: f~ = W f W^+.  Its broadening is g^2 times the double time
+ * integral of the correlator of f~, i.e. <dp_i^2> = (q2/8) |F_i|^2 with
+ * F_i = sum_n w f~_i(t_n) for charges rotated uniformly over their orbit
+ * ([eq:qnpointfct_main]; q2 the classical quadratic Casimir of rep).
+ *
+ * The library follows one straight path per lattice site, through the same
+ * event: path (y, x) starts at x + x_offset in row y at the first step n_f
+ * with t_{n_f} >= tau_form / a.  After m steps it is at x + x_offset + m dt;
+ * when its nearest grid point moves from c to c + x, W <- W U_x(c) with the
+ * link at that step.  The force is evaluated every `stride` steps with
+ * weight stride * dtau (stride 1: every step, as the particle push does;
+ * stride = a / dtau: steps of one lattice spacing).  Samples are taken at
+ * the same steps as the particle samples.
+ *
+ *   x_offset    start of every path inside its cell, in [0, 1)
+ *   stride      >= 1
+ *   tau_form_fm formation time of the paths (jets form at 0)
+ *   rep         CPIC_REP_FUND or CPIC_REP_ADJ: the charges <dp^2> is quoted for
+ *
+ * cpic_jets_enable allocates the paths' state (42 reals per site) and, if the
+ * context has no particles, the per-site field pieces the paths read (48
+ * reals per site).  Call it once, before the paths' formation step is
+ * reached; CPIC_E_INVALID otherwise, or if dtau > a.  Every later step then
+ * launches one more kernel.  Checkpoints include the paths.
+ */
+typedef struct {
+    double x_offset;
+    int32_t stride;
+    double tau_form_fm;
+    int32_t rep;
+} cpic_jet_params;
+cpic_status cpic_jets_enable(cpic_ctx* ctx, const cpic_jet_params* params);
+/* Samples of the light-like broadening: out[4*k + c], c = tau_fm, <dp_x^2>,
+ * <dp_y^2>, <dp_z^2> (GeV^2, averaged over the N^2 paths, fixed-order double
+ * precision sums).  *n_samples (may be NULL) receives the sample count;
+ * CPIC_E_CAPACITY if cap is smaller (nothing written).  Synchronises. */
+cpic_status cpic_jets_observables(cpic_ctx* ctx, double* out, int32_t cap, int32_t* n_samples);
+/* Summed kernel time (ms) and launch count of the light-like path kernel
+ * since cpic_set_timing enabled timing.  Synchronises. */
+cpic_status cpic_jets_timing(cpic_ctx* ctx, double* ms, int64_t* launches);
 
 /* Message of the last failure (never NULL; static storage for a NULL ctx). */
 const char* cpic_last_error(const cpic_ctx* ctx);

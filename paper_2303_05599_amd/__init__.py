@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libcpic.so")
 
 FP64, FP32 = 0, 1
 REP_FUND, REP_ADJ = 0, 1
-STATE_U, STATE_PHI, STATE_E, STATE_PI, STATE_PARTICLES, STATE_STEP = range(6)
+STATE_U, STATE_PHI, STATE_E, STATE_PI, STATE_PARTICLES, STATE_STEP, STATE_JET_W, STATE_JET_F = range(8)
 ERRORS = {-1: "INVALID", -2: "NOMEM", -3: "HIP", -4: "IC_NEWTON", -5: "NAN", -6: "DRIFT", -7: "CAPACITY",
           -8: "CELL_JUMP", -9: "IO"}
 
@@ -35,6 +35,11 @@ class ParticleParams(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("mass_GeV", ctypes.c_double), ("pT_min_GeV", ctypes.c_double),
                 ("pT_max_GeV", ctypes.c_double), ("azimuth_uniform", ctypes.c_int32),
                 ("tau_form_fm", ctypes.c_double), ("rep", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+class JetParams(ctypes.Structure):
+    _fields_ = [("x_offset", ctypes.c_double), ("stride", ctypes.c_int32), ("tau_form_fm", ctypes.c_double),
+                ("rep", ctypes.c_int32)]
 
 
 GLASMA_DEFAULTS = dict(N=32, L_fm=6.0, g2mu_GeV=2.0, m_ir_GeV=0.2, uv_GeV=10.0, n_sheets=1, dtau_over_a=0.125,
@@ -80,6 +85,9 @@ def lib():
             "cpic_batch_current_step": [P, i32, ctypes.POINTER(i64)],
             "cpic_batch_observables": [P, i32, P, i32, ctypes.POINTER(i32)],
             "cpic_batch_get_state": [P, i32, i32, P, sz],
+            "cpic_jets_enable": [P, ctypes.POINTER(JetParams)],
+            "cpic_jets_observables": [P, P, i32, ctypes.POINTER(i32)],
+            "cpic_jets_timing": [P, ctypes.POINTER(d), ctypes.POINTER(i64)],
         }
         for name, args in sigs.items():
             f = getattr(L, name)
@@ -188,16 +196,19 @@ class Context:
     def _shape(self, which):
         N = self.N
         return {STATE_U: (2, N, N, 3, 3), STATE_PHI: (N, N, 8), STATE_E: (2, N, N, 8), STATE_PI: (N, N, 8),
-                STATE_PARTICLES: (self.np, 20), STATE_STEP: (1,)}[which]
+                STATE_PARTICLES: (self.np, 20), STATE_STEP: (1,), STATE_JET_W: (N, N, 3, 3),
+                STATE_JET_F: (N, N, 3, 8)}[which]
 
     def get_state(self, which):
-        dt = np.complex128 if which == STATE_U else (np.int64 if which == STATE_STEP else np.float64)
+        dt = (np.complex128 if which in (STATE_U, STATE_JET_W) else
+              (np.int64 if which == STATE_STEP else np.float64))
         a = np.zeros(self._shape(which), dt)
         self._chk(lib().cpic_get_state(self.h, which, _ptr(a), a.nbytes))
         return a
 
     def set_state(self, which, arr):
-        dt = np.complex128 if which == STATE_U else (np.int64 if which == STATE_STEP else np.float64)
+        dt = (np.complex128 if which in (STATE_U, STATE_JET_W) else
+              (np.int64 if which == STATE_STEP else np.float64))
         a = np.ascontiguousarray(np.asarray(arr, dt).reshape(self._shape(which)))
         self._chk(lib().cpic_set_state(self.h, which, _ptr(a), a.nbytes))
 
@@ -241,6 +252,29 @@ class Context:
 
     def set_timing(self, enable=True):
         self._chk(lib().cpic_set_timing(self.h, int(enable)))
+
+    def enable_jets(self, x_offset=0.0, stride=1, tau_form_fm=0.0, rep=REP_FUND):
+        """Light-like jet limit: one straight path along +x per site (cpic_jets_enable)."""
+        jp = JetParams(x_offset=x_offset, stride=stride, tau_form_fm=tau_form_fm, rep=rep)
+        self._chk(lib().cpic_jets_enable(self.h, ctypes.byref(jp)))
+
+    def jet_observables(self):
+        """(k, 4): tau_fm, <dp_x^2>, <dp_y^2>, <dp_z^2> of the light-like paths (GeV^2)."""
+        cap = max(self.num_jet_samples(), 1)
+        ns = ctypes.c_int32()
+        out = np.zeros((cap, 4))
+        self._chk(lib().cpic_jets_observables(self.h, _ptr(out), cap, ctypes.byref(ns)))
+        return out[:ns.value]
+
+    def num_jet_samples(self):
+        ns = ctypes.c_int32()
+        self._chk(lib().cpic_jets_observables(self.h, None, 1 << 30, ctypes.byref(ns)))
+        return ns.value
+
+    def jets_timing(self):
+        ms, k = ctypes.c_double(), ctypes.c_int64()
+        self._chk(lib().cpic_jets_timing(self.h, ctypes.byref(ms), ctypes.byref(k)))
+        return {"jets_ms": ms.value, "n_jets": k.value}
 
     def timing(self):
         f, p = ctypes.c_double(), ctypes.c_double()

@@ -91,6 +91,8 @@ static void free_all(cpic_ctx* c)
         if (c->gexec[p]) hipGraphExecDestroy(c->gexec[p]);
     for (auto e : c->ev_field) hipEventDestroy(e);
     for (auto e : c->ev_push) hipEventDestroy(e);
+    for (auto e : c->ev_jets) hipEventDestroy(e);
+    hipFree(c->jW); hipFree(c->jF); hipFree(c->jpartials); hipFree(c->jobs);
     hipFree(c->fbuf[0]); hipFree(c->fbuf[1]); hipFree(c->pr); hipFree(c->pcell); hipFree(c->aux);
     hipFree(c->partials); hipFree(c->obs); hipFree(c->d_step); hipFree(c->d_err); hipFree(c->d_fails);
     hipFree(c->dpart); hipFree(c->dout);
@@ -145,6 +147,7 @@ extern "C" cpic_status cpic_create(const cpic_glasma_params* gp, const cpic_part
     } else {
         c->sc.n_form = c->sc.n_max;
     }
+    c->sc.n_aux = c->sc.n_form;
     c->sc.record_every = gp->record_every > 0 ? gp->record_every : (1 << 30);
     c->sc.reunit_every = c->prec == CPIC_FP32 ? std::max(0, gp->reunit_every) : 0;
     initial_colour(pp->rep, c->q0, c->q0eig, &c->q2ref, &c->q3ref);
@@ -272,8 +275,11 @@ static cpic_status reset_counters(cpic_ctx* c, int n)
     c->n = n;
     c->samples.clear();
     c->obs_reduced = 0;
+    c->jsamples.clear();
+    c->jobs_reduced = 0;
     HIPCHK(c, hipMemcpyAsync(c->d_step, &c->n, sizeof(int), hipMemcpyHostToDevice, c->st), "step counter");
     if (c->obs) HIPCHK(c, hipMemsetAsync(c->obs, 0, sizeof(double) * 4 * c->nslots, c->st), "obs reset");
+    if (c->jobs) HIPCHK(c, hipMemsetAsync(c->jobs, 0, sizeof(double) * 4 * c->jslots, c->st), "obs reset");
     HIPCHK(c, hipStreamSynchronize(c->st), "reset");
     return CPIC_OK;
 }
@@ -350,11 +356,12 @@ PushArgs cpic::push_args(const cpic_ctx* c, int tpp)
     return pa;
 }
 
-// one step: field update (cur -> cur^1), push, step end (samples + counter)
+// one step: field update (cur -> cur^1), push (advances the step counter),
+// light-like paths
 template <typename T> static cpic_status launch_one(cpic_ctx* c, int parity, bool with_events)
 {
     const Fields<T> A = F<T>(c, parity), B = F<T>(c, parity ^ 1);
-    KTimer tf, tp;
+    KTimer tf, tp, tj;
     if (with_events) {
         HIPCHK(c, hipEventCreate(&tf.start), "event"); HIPCHK(c, hipEventCreate(&tf.stop), "event");
         c->ev_field.push_back(tf.start); c->ev_field.push_back(tf.stop);
@@ -373,6 +380,15 @@ template <typename T> static cpic_status launch_one(cpic_ctx* c, int parity, boo
         // the push advances the step counter; without particles a one-thread kernel does
         HIPCHK(c, launch_step_advance(c->d_step, c->st), "step advance");
     }
+    if (c->jets) {
+        // reads the step from d_step[1], which only the next field update changes
+        if (with_events) {
+            HIPCHK(c, hipEventCreate(&tj.start), "event"); HIPCHK(c, hipEventCreate(&tj.stop), "event");
+            c->ev_jets.push_back(tj.start); c->ev_jets.push_back(tj.stop);
+        }
+        HIPCHK(c, launch_jets<T>(A, B, static_cast<const T*>(c->aux), static_cast<T*>(c->jW), static_cast<T*>(c->jF),
+                                 c->ja, c->d_step, c->jpartials, c->st, tj), "light-like paths");
+    }
     return CPIC_OK;
 }
 
@@ -380,6 +396,8 @@ cpic_status cpic::host_advance(cpic_ctx* c, int k)
 {
     for (int j = 0; j < k; j++) {
         if (c->np > 0 && is_record_step(c->sc, c->n)) c->samples.push_back({record_slot_of(c->sc, c->n), c->n});
+        if (c->jets && is_record_step(c->ja.sc, c->n))
+            c->jsamples.push_back({record_slot_of(c->ja.sc, c->n), c->n});
         c->n++;
         c->cur ^= 1;
     }
@@ -476,8 +494,16 @@ static cpic_status collect_timing(cpic_ctx* c)
         c->k_push++;
         hipEventDestroy(c->ev_push[i]); hipEventDestroy(c->ev_push[i + 1]);
     }
+    for (size_t i = 0; i + 1 < c->ev_jets.size(); i += 2) {
+        float ms = 0;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev_jets[i], c->ev_jets[i + 1]), "timing");
+        c->t_jets += ms;
+        c->k_jets++;
+        hipEventDestroy(c->ev_jets[i]); hipEventDestroy(c->ev_jets[i + 1]);
+    }
     c->ev_field.clear();
     c->ev_push.clear();
+    c->ev_jets.clear();
     return CPIC_OK;
 }
 
@@ -509,6 +535,13 @@ static cpic_status reduce_samples(cpic_ctx* c)
                                      c->st), "observables");
     }
     c->obs_reduced = (int)c->samples.size();
+    const int jg = jet_groups(c->V);
+    for (size_t k = (size_t)c->jobs_reduced; k < c->jsamples.size(); k++) {
+        const int slot = c->jsamples[k].first;
+        HIPCHK(c, launch_reduce_rows(c->jpartials + (size_t)slot * jg * 4, jg, 4, c->jobs + (size_t)slot * 4, c->st),
+               "light-like observables");
+    }
+    c->jobs_reduced = (int)c->jsamples.size();
     return CPIC_OK;
 }
 
@@ -599,6 +632,8 @@ static size_t state_bytes(const cpic_ctx* c, int which)
     case CPIC_STATE_E: return sizeof(double) * 16 * (size_t)c->V;
     case CPIC_STATE_PARTICLES: return sizeof(double) * 20 * (size_t)c->np;
     case CPIC_STATE_STEP: return sizeof(int64_t);
+    case CPIC_STATE_JET_W: return c->jets ? sizeof(double) * 18 * (size_t)c->V : 0;
+    case CPIC_STATE_JET_F: return c->jets ? sizeof(double) * 24 * (size_t)c->V : 0;
     default: return 0;
     }
 }
@@ -645,6 +680,15 @@ static const int kXchgToDev[20] = {PX_, PY_, PETA_, PPX, PPY, PPETA, PQ0, PQ0 + 
 
 template <typename T> static cpic_status get_t(cpic_ctx* c, int which, double* h)
 {
+    if (which == CPIC_STATE_JET_W || which == CPIC_STATE_JET_F) {
+        const int nc = which == CPIC_STATE_JET_W ? 18 : 24;
+        std::vector<T> d((size_t)nc * c->V);
+        HIPCHK(c, hipMemcpy(d.data(), which == CPIC_STATE_JET_W ? c->jW : c->jF, sizeof(T) * d.size(),
+                            hipMemcpyDeviceToHost), "get paths");
+        for (int s = 0; s < c->V; s++)
+            for (int k = 0; k < nc; k++) h[(size_t)s * nc + k] = (double)d[(size_t)k * c->V + s];
+        return CPIC_OK;
+    }
     if (which == CPIC_STATE_PARTICLES) {
         const size_t np = c->np;
         std::vector<T> r(kPartReals * np);
@@ -697,7 +741,8 @@ extern "C" cpic_status cpic_get_state(cpic_ctx* c, int32_t which, void* dst, siz
 {
     if (!c || !dst) return fail(c, CPIC_E_INVALID, "cpic_get_state: NULL argument");
     const size_t need = state_bytes(c, which);
-    if (!need && which != CPIC_STATE_PARTICLES) return fail(c, CPIC_E_INVALID, "cpic_get_state: unknown part");
+    if (!need && which != CPIC_STATE_PARTICLES)
+        return fail(c, CPIC_E_INVALID, "cpic_get_state: unknown part (or light-like paths not enabled)");
     if (bytes != need) return fail(c, CPIC_E_CAPACITY, "cpic_get_state: expected " + std::to_string(need) + " bytes");
     HIPCHK(c, hipStreamSynchronize(c->st), "get state");
     if (which == CPIC_STATE_STEP) {
@@ -712,6 +757,8 @@ extern "C" cpic_status cpic_get_state(cpic_ctx* c, int32_t which, void* dst, siz
 extern "C" cpic_status cpic_set_state(cpic_ctx* c, int32_t which, const void* src, size_t bytes)
 {
     if (!c || !src) return fail(c, CPIC_E_INVALID, "cpic_set_state: NULL argument");
+    if (which == CPIC_STATE_JET_W || which == CPIC_STATE_JET_F)
+        return fail(c, CPIC_E_INVALID, "cpic_set_state: the light-like paths are read-only");
     const size_t need = state_bytes(c, which);
     if (!need && which != CPIC_STATE_PARTICLES) return fail(c, CPIC_E_INVALID, "cpic_set_state: unknown part");
     if (bytes != need) return fail(c, CPIC_E_CAPACITY, "cpic_set_state: expected " + std::to_string(need) + " bytes");
@@ -744,7 +791,7 @@ struct CkptHeader {
     char magic[8];
     int32_t version, N, prec, n, cur_unused, nsamples;
     int64_t np;
-    int32_t nslots, pad;
+    int32_t nslots, jets;  // jets: 1 if the light-like path section follows the particle section
     cpic_glasma_params gp;
     cpic_particle_params pp;
 };
@@ -759,7 +806,7 @@ extern "C" cpic_status cpic_save(cpic_ctx* c, const char* path)
     CkptHeader h{};
     std::memcpy(h.magic, "CPICKPT1", 8);
     h.version = 1; h.N = c->N; h.prec = c->prec; h.n = c->n; h.nsamples = (int)c->samples.size();
-    h.np = c->np; h.nslots = c->nslots; h.gp = c->gp; h.pp = c->pp;
+    h.np = c->np; h.nslots = c->nslots; h.gp = c->gp; h.pp = c->pp; h.jets = c->jets;
     const size_t fb = (size_t)kRealsPerSite * c->V * c->tsz, pb = (size_t)kPartReals * c->np * c->tsz;
     std::vector<char> f(fb), p(pb);
     std::vector<int> cell(2 * c->np), pid(c->np);
@@ -771,6 +818,15 @@ extern "C" cpic_status cpic_save(cpic_ctx* c, const char* path)
         HIPCHK(c, hipMemcpy(pid.data(), c->pid, sizeof(int) * pid.size(), hipMemcpyDeviceToHost), "save");
     }
     if (!obs.empty()) HIPCHK(c, hipMemcpy(obs.data(), c->obs, sizeof(double) * obs.size(), hipMemcpyDeviceToHost), "save");
+    const size_t jwb = c->jets ? (size_t)18 * c->V * c->tsz : 0, jfb = c->jets ? (size_t)24 * c->V * c->tsz : 0;
+    std::vector<char> jw(jwb), jf(jfb);
+    std::vector<double> jobs(c->jets ? 4 * (size_t)c->jslots : 0);
+    if (c->jets) {
+        HIPCHK(c, hipMemcpy(jw.data(), c->jW, jwb, hipMemcpyDeviceToHost), "save");
+        HIPCHK(c, hipMemcpy(jf.data(), c->jF, jfb, hipMemcpyDeviceToHost), "save");
+        if (!jobs.empty())
+            HIPCHK(c, hipMemcpy(jobs.data(), c->jobs, sizeof(double) * jobs.size(), hipMemcpyDeviceToHost), "save");
+    }
     FILE* fp = std::fopen(path, "wb");
     if (!fp) return fail(c, CPIC_E_IO, std::string("cpic_save: cannot open ") + path);
     bool ok = std::fwrite(&h, sizeof h, 1, fp) == 1;
@@ -787,6 +843,17 @@ extern "C" cpic_status cpic_save(cpic_ctx* c, const char* path)
         ok = ok && std::fwrite(&ss, sizeof ss, 1, fp) == 1;
     }
     if (!obs.empty()) ok = ok && std::fwrite(obs.data(), sizeof(double), obs.size(), fp) == obs.size();
+    if (c->jets) {
+        const double xo = c->ja.x_off;
+        const int32_t jh[4] = {c->ja.stride, c->ja.sc.n_form, c->jslots, (int32_t)c->jsamples.size()};
+        ok = ok && std::fwrite(&xo, sizeof xo, 1, fp) == 1 && std::fwrite(jh, sizeof jh, 1, fp) == 1;
+        for (auto& sm : c->jsamples) {
+            const int32_t v[2] = {sm.first, sm.second};
+            ok = ok && std::fwrite(v, sizeof v, 1, fp) == 1;
+        }
+        ok = ok && std::fwrite(jw.data(), 1, jwb, fp) == jwb && std::fwrite(jf.data(), 1, jfb, fp) == jfb;
+        if (!jobs.empty()) ok = ok && std::fwrite(jobs.data(), sizeof(double), jobs.size(), fp) == jobs.size();
+    }
     ok = (std::fclose(fp) == 0) && ok;
     if (!ok) return fail(c, CPIC_E_IO, std::string("cpic_save: write failed for ") + path);
     return CPIC_OK;
@@ -800,7 +867,7 @@ extern "C" cpic_status cpic_load(cpic_ctx* c, const char* path)
     CkptHeader h{};
     bool ok = std::fread(&h, sizeof h, 1, fp) == 1 && std::memcmp(h.magic, "CPICKPT1", 8) == 0 && h.version == 1;
     if (ok && (h.N != c->N || h.prec != c->prec || h.np != c->np || h.nslots != c->nslots || h.nsamples < 0 ||
-               h.nsamples > c->nslots || h.n < 0 || h.n > c->sc.n_max)) {
+               h.nsamples > c->nslots || h.n < 0 || h.n > c->sc.n_max || (h.jets != 0) != c->jets)) {
         std::fclose(fp);
         return fail(c, CPIC_E_INVALID, "cpic_load: checkpoint does not match this context");
     }
@@ -823,7 +890,29 @@ extern "C" cpic_status cpic_load(cpic_ctx* c, const char* path)
         ok = ok && std::fread(&ss, sizeof ss, 1, fp) == 1;
     }
     if (!obs.empty()) ok = ok && std::fread(obs.data(), sizeof(double), obs.size(), fp) == obs.size();
+    const size_t jwb = c->jets ? (size_t)18 * c->V * c->tsz : 0, jfb = c->jets ? (size_t)24 * c->V * c->tsz : 0;
+    std::vector<char> jw(jwb), jf(jfb);
+    std::vector<double> jobs(c->jets ? 4 * (size_t)c->jslots : 0);
+    std::vector<std::pair<int, int>> jsamples;
+    bool jmatch = true;
+    if (ok && c->jets) {
+        double xo = 0;
+        int32_t jh[4] = {0, 0, 0, 0};
+        ok = std::fread(&xo, sizeof xo, 1, fp) == 1 && std::fread(jh, sizeof jh, 1, fp) == 1;
+        jmatch = xo == c->ja.x_off && jh[0] == c->ja.stride && jh[1] == c->ja.sc.n_form && jh[2] == c->jslots &&
+                 jh[3] >= 0 && jh[3] <= c->jslots;
+        for (int k = 0; ok && jmatch && k < jh[3]; k++) {
+            int32_t v[2];
+            ok = std::fread(v, sizeof v, 1, fp) == 1 && v[0] >= 0 && v[0] < c->jslots;
+            jsamples.push_back({v[0], v[1]});
+        }
+        if (jmatch) {
+            ok = ok && std::fread(jw.data(), 1, jwb, fp) == jwb && std::fread(jf.data(), 1, jfb, fp) == jfb;
+            if (!jobs.empty()) ok = ok && std::fread(jobs.data(), sizeof(double), jobs.size(), fp) == jobs.size();
+        }
+    }
     std::fclose(fp);
+    if (!jmatch) return fail(c, CPIC_E_INVALID, "cpic_load: light-like path parameters differ from the checkpoint's");
     if (!ok) return fail(c, CPIC_E_IO, std::string("cpic_load: truncated or corrupt checkpoint ") + path);
     for (int v : cell)
         if (v < 0 || v >= c->N) return fail(c, CPIC_E_IO, "cpic_load: corrupt particle cells");
@@ -849,6 +938,14 @@ extern "C" cpic_status cpic_load(cpic_ctx* c, const char* path)
     if (!obs.empty()) HIPCHK(c, hipMemcpy(c->obs, obs.data(), sizeof(double) * obs.size(), hipMemcpyHostToDevice), "load");
     c->samples = samples;
     c->obs_reduced = (int)samples.size();
+    if (c->jets) {
+        HIPCHK(c, hipMemcpy(c->jW, jw.data(), jwb, hipMemcpyHostToDevice), "load");
+        HIPCHK(c, hipMemcpy(c->jF, jf.data(), jfb, hipMemcpyHostToDevice), "load");
+        if (!jobs.empty())
+            HIPCHK(c, hipMemcpy(c->jobs, jobs.data(), sizeof(double) * jobs.size(), hipMemcpyHostToDevice), "load");
+        c->jsamples = jsamples;
+        c->jobs_reduced = (int)jsamples.size();
+    }
     c->initialised = true;
     return CPIC_OK;
 }
@@ -894,8 +991,8 @@ extern "C" cpic_status cpic_set_timing(cpic_ctx* c, int32_t enable)
     cpic_status s = cpic_sync(c);
     if (s) return s;
     c->timing = enable != 0;
-    c->t_field = c->t_push = 0;
-    c->k_field = c->k_push = 0;
+    c->t_field = c->t_push = c->t_jets = 0;
+    c->k_field = c->k_push = c->k_jets = 0;
     return CPIC_OK;
 }
 
@@ -1038,5 +1135,96 @@ extern "C" cpic_status cpic_set_push_lanes(cpic_ctx* c, int32_t lanes)
     c->tpp = lanes;
     c->pblocks = c->np > 0 ? push_blocks((int)c->np, lanes) : 0;
     drop_graphs(c);
+    return CPIC_OK;
+}
+
+// ------------------------------------------------------------------ light-like jet limit
+extern "C" cpic_status cpic_jets_enable(cpic_ctx* c, const cpic_jet_params* jp)
+{
+    if (!c || !jp) return fail(c, CPIC_E_INVALID, "cpic_jets_enable: NULL argument");
+    if (c->jets) return fail(c, CPIC_E_INVALID, "cpic_jets_enable: already enabled");
+    if (!(jp->x_offset >= 0 && jp->x_offset < 1) || jp->stride < 1 || !(jp->tau_form_fm >= 0) ||
+        (jp->rep != CPIC_REP_FUND && jp->rep != CPIC_REP_ADJ))
+        return fail(c, CPIC_E_INVALID, "cpic_jets_enable: need 0 <= x_offset < 1, stride >= 1, tau_form >= 0, a valid rep");
+    if (!(c->sc.dt <= 1))
+        return fail(c, CPIC_E_INVALID, "cpic_jets_enable: needs dtau <= a (at most one cell per step)");
+    const double dtau_fm = c->sc.dt * c->a_fm;
+    const double f = jp->tau_form_fm / dtau_fm;
+    if (!(f < 1e8)) return fail(c, CPIC_E_INVALID, "cpic_jets_enable: tau_form / dtau above 1e8 steps");
+    const int n_form = std::min(c->sc.n_max, (int)std::ceil(f - 1e-9 * f));
+    if (c->initialised && c->n > n_form)
+        return fail(c, CPIC_E_INVALID, "cpic_jets_enable: the paths would form before the current step");
+    HIPCHK(c, hipStreamSynchronize(c->st), "jets");
+    JetArgs ja{};
+    ja.N = c->N;
+    ja.stride = jp->stride;
+    ja.x_off = jp->x_offset;
+    ja.sc = c->sc;
+    ja.sc.n_form = n_form;
+    const int jslots = num_slots(ja.sc);
+    const size_t V = c->V;
+    hipError_t e = hipSuccess;
+    void *W = nullptr, *Fp = nullptr, *aux = nullptr;
+    double *part = nullptr, *obs = nullptr;
+    e = hipMalloc(&W, 18 * V * c->tsz);
+    if (e == hipSuccess) e = hipMalloc(&Fp, 24 * V * c->tsz);
+    if (e == hipSuccess && !c->aux) e = hipMalloc(&aux, (size_t)kAuxReals * V * c->tsz);
+    if (e == hipSuccess && jslots > 0) e = hipMalloc(&part, sizeof(double) * 4 * (size_t)jet_groups(c->V) * jslots);
+    if (e == hipSuccess && jslots > 0) e = hipMalloc(&obs, sizeof(double) * 4 * (size_t)jslots);
+    if (e == hipSuccess && obs) e = hipMemsetAsync(obs, 0, sizeof(double) * 4 * (size_t)jslots, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    if (e != hipSuccess) {
+        hipFree(W); hipFree(Fp); hipFree(aux); hipFree(part); hipFree(obs);
+        const bool oom = e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation;
+        return fail(c, oom ? CPIC_E_NOMEM : CPIC_E_HIP, std::string("cpic_jets_enable: ") + hipGetErrorString(e));
+    }
+    if (aux) c->aux = aux;
+    c->jW = W;
+    c->jF = Fp;
+    c->jpartials = part;
+    c->jobs = obs;
+    c->jslots = jslots;
+    c->ja = ja;
+    double q0[8], eig[3], q3 = 0;
+    initial_colour(jp->rep, q0, eig, &c->jet_q2, &q3);
+    c->sc.n_aux = std::min(c->sc.n_aux, n_form);
+    c->jsamples.clear();
+    c->jobs_reduced = 0;
+    c->jets = true;
+    drop_graphs(c);
+    return CPIC_OK;
+}
+
+extern "C" cpic_status cpic_jets_observables(cpic_ctx* c, double* out, int32_t cap, int32_t* n_samples)
+{
+    if (!c) return fail(nullptr, CPIC_E_INVALID, "cpic_jets_observables: NULL context");
+    if (!c->jets) return fail(c, CPIC_E_INVALID, "cpic_jets_observables: light-like paths not enabled");
+    const int ns = (int)c->jsamples.size();
+    if (n_samples) *n_samples = ns;
+    if (cap < ns) return fail(c, CPIC_E_CAPACITY, "cpic_jets_observables: capacity " + std::to_string(cap) + " < " +
+                                                      std::to_string(ns) + " samples");
+    cpic_status s = reduce_samples(c);
+    if (s) return s;
+    s = cpic_sync(c);
+    if (s) return s;
+    if (!ns || !out) return CPIC_OK;
+    std::vector<double> h(4 * (size_t)c->jslots);
+    HIPCHK(c, hipMemcpy(h.data(), c->jobs, sizeof(double) * h.size(), hipMemcpyDeviceToHost), "jets observables");
+    const double scale = c->jet_q2 / 8.0 / ((double)c->V * c->a_gev * c->a_gev);
+    for (int k = 0; k < ns; k++) {
+        const int slot = c->jsamples[k].first;
+        out[4 * k] = (c->jsamples[k].second + 1) * c->sc.dt * c->a_fm;
+        for (int j = 0; j < 3; j++) out[4 * k + 1 + j] = h[4 * (size_t)slot + j] * scale;
+    }
+    return CPIC_OK;
+}
+
+extern "C" cpic_status cpic_jets_timing(cpic_ctx* c, double* ms, int64_t* launches)
+{
+    if (!c) return fail(nullptr, CPIC_E_INVALID, "cpic_jets_timing: NULL context");
+    cpic_status s = cpic_sync(c);
+    if (s) return s;
+    if (ms) *ms = c->t_jets;
+    if (launches) *launches = c->k_jets;
     return CPIC_OK;
 }

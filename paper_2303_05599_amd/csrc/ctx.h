@@ -53,11 +53,22 @@ struct cpic_ctx {
     bool initialised = false;
     // graphs: [parity] -> executable graph of kGraphSteps steps starting from buffer `parity`
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    // light-like paths (cpic_jets_enable)
+    bool jets = false;
+    cpic::JetArgs ja{};
+    double jet_q2 = 0;             // q2 of the representation the broadening is quoted for
+    void* jW = nullptr;            // [18][V] Wilson lines
+    void* jF = nullptr;            // [24][V] integrated transported forces
+    int jslots = 0;
+    double* jpartials = nullptr;   // [jslots][path groups of 64][4]
+    double* jobs = nullptr;        // [jslots][4]
+    int jobs_reduced = 0;
+    std::vector<std::pair<int, int>> jsamples;  // (slot, step n after which it was taken)
     // timing
     bool timing = false;
-    std::vector<hipEvent_t> ev_field, ev_push;
-    double t_field = 0, t_push = 0;
-    int64_t k_field = 0, k_push = 0;
+    std::vector<hipEvent_t> ev_field, ev_push, ev_jets;
+    double t_field = 0, t_push = 0, t_jets = 0;
+    int64_t k_field = 0, k_push = 0, k_jets = 0;
     std::string err;
 };
 

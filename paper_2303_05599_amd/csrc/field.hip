@@ -187,7 +187,7 @@ __device__ __forceinline__ void field_step_body(const Fields<T>& in, const Field
     a8<T> F1 = azero<T>(), F2 = azero<T>(), Fpi = azero<T>();
     // the push reads the magnetic-field pieces from the first push step on
     // (at n = 0, t = 1/t = 0 make the forces vanish, so the kick is still skipped)
-    const bool aux_on = AUX && n >= sc.n_form;
+    const bool aux_on = AUX && n >= sc.n_aux;
     if (kick || aux_on) {
         View<T> va;
         if (AUX) va = make_view<T>(aux, kAuxReals, V);
@@ -277,7 +277,7 @@ __device__ __forceinline__ void field_tile_body(const Fields<T>& in, const Field
     a8<T> F1 = azero<T>(), F2 = azero<T>(), Fpi = azero<T>();
     // the push reads the magnetic-field pieces from the first push step on
     // (at n = 0, t = 1/t = 0 make the forces vanish, so the kick is still skipped)
-    const bool aux_on = AUX && n >= sc.n_form;
+    const bool aux_on = AUX && n >= sc.n_aux;
     if (kick || aux_on) {
         View<T> va;
         if (AUX) va = make_view<T>(aux, kAuxReals, V);
@@ -393,7 +393,7 @@ __device__ __forceinline__ void field_ctile_body(const Fields<T>& in, const Fiel
     a8<T> F1 = azero<T>(), F2 = azero<T>(), Fpi = azero<T>();
     // the push reads the magnetic-field pieces from the first push step on
     // (at n = 0, t = 1/t = 0 make the forces vanish, so the kick is still skipped)
-    const bool aux_on = AUX && aux != nullptr && n >= sc.n_form;
+    const bool aux_on = AUX && aux != nullptr && n >= sc.n_aux;
     a8<T> G, DX, DY;  // magnetic-field pieces, stored last (keeps them out of the stencil's register peak)
     if (kick || aux_on) {
         {   // U_12(x) = U_1(x) U_2(x+1) U_1(x+2)^+ U_2(x)^+
@@ -553,7 +553,7 @@ __device__ __forceinline__ void field_link_body(const Fields<T>& in, const Field
     a8<T> F = azero<T>(), lap = azero<T>();
     // the push reads the magnetic-field pieces (G = Proj U_12 from the i = 0
     // thread, D_i = phi->_i - phi<-_i) from the first push step on
-    const bool aux_on = AUX && n >= sc.n_form && live;
+    const bool aux_on = AUX && n >= sc.n_aux && live;
     View<T> va;
     if (AUX) va = make_view<T>(aux, kAuxReals, V);
     if (kick || aux_on) {

@@ -41,6 +41,7 @@ struct Schedule {
     double dt;         // dtau / a
     int n_max;         // steps to tau_max
     int n_form;        // first step of the particle push
+    int n_aux;         // first step whose field update writes the aux buffer
     int record_every;  // samples after steps with (n+1) % record_every == 0, and after n_max - 1
     int reunit_every;  // FP32: reunitarise links / renormalise charges after steps with (n+1) % k == 0
 };
@@ -115,7 +116,7 @@ inline void klaunch(const KTimer& tm, F kernel, dim3 grid, dim3 block, hipStream
 
 // ---- field kernels (field.hip)
 // aux (may be NULL): [48][V] per-site pieces of the colour fields for the
-// push, written by the field update of the same step from step n_form on:
+// push, written by the field update of the same step from step n_aux on:
 //   G = Proj U_12, D_x = phi->_x - phi<-_x, D_y = phi->_y - phi<-_y,
 //   S_x, S_y, P = E_x, E_y, pi summed over the half steps n - 1/2 and n + 1/2
 constexpr int kAuxReals = 48;
@@ -150,6 +151,22 @@ hipError_t launch_step_advance(int* d_step, hipStream_t st);
 inline int obs_groups(int np) { return (np + 63) / 64; }
 template <typename T>
 hipError_t launch_part_diag(const Parts<T>& P, int np, double q2, double q3, double* partials, hipStream_t st);
+
+// ---- light-like path integral (jets.hip)
+// One path per site p = y*N + i, along +x at the speed of light from
+// x = i + x_off at step sc.n_form; W [18][V] its Wilson line (row-major
+// re/im), F [24][V] the integrated transported force components x, y, z.
+struct JetArgs {
+    int N;
+    int stride;    // force evaluated on every stride-th step, weight stride * dt
+    double x_off;  // start inside the cell, [0, 1)
+    Schedule sc;   // n_form: first step of the paths; samples as for particles
+};
+template <typename T>
+hipError_t launch_jets(const Fields<T>& A, const Fields<T>& B, const T* aux, T* W, T* F, const JetArgs& a,
+                       const int* d_step, double* partials, hipStream_t st, const KTimer& tm = KTimer{});
+// samples: partials[slot][group of 64 paths][4] (|F_x|^2, |F_y|^2, |F_z|^2, 0)
+__host__ __device__ inline int jet_groups(int V) { return (V + 63) / 64; }
 
 // ---- particle ordering (sort.hip)
 struct SortBufs {

@@ -1,0 +1,148 @@
+// jets.hip -- the light-like jet limit of the momentum broadening
+// (Sec. V.B, [eq:mombroadjets]).
+//
+// A parton moving along +x at the speed of light picks up the colour Lorentz
+// force f_x = E_x, f_y = E_y - B_eta, f_z = E_eta + B_y, seen through the
+// Wilson line W of the links it has crossed: f~ = W f W^+.  Its broadening
+// is <dp_i^2> = (q2/8) |F_i|^2 for charges rotated uniformly over their
+// orbit, F_i = sum_n w f~_i(t_n).  The kernel follows one straight path per
+// lattice site: all paths of a step sit at the same offset k from their
+// start, so the lanes of a wavefront read consecutive sites (a coalesced
+// stream through the lattice, like the field update).
+//
+// Per step and path: W is multiplied by the crossed x link when the nearest
+// grid point moves (once per 1/dt steps), the five fields f needs are read
+// at the nearest grid point from U(n), pi(n+1/2) and the aux pieces of the
+// field update, transported with W and added to F.  On recording steps each
+// wavefront writes the double-precision sums of |F_i|^2 over its 64 paths.
+#include "cellfields.h"
+#include "reduce.h"
+
+namespace cpic {
+
+// cell offset of every path after m steps: floor(x_off + m dt + 1/2),
+// evaluated without contraction so that it matches a plain double evaluation
+__device__ __forceinline__ int path_offset(double x_off, int m, double dt)
+{
+#pragma clang fp contract(off)
+    return (int)floor(x_off + (double)m * dt + 0.5);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void jet_kernel(Fields<T> Af, Fields<T> Bf, const T* aux, T* Wb, T* Fb, JetArgs a,
+                                                  const int* d_step, double* partials)
+{
+    const int N = a.N, V = N * N;
+    const int nblocks = (V + 255) / 256;
+    const int blk = xcd_block(nblocks);
+    if (blk >= nblocks) return;
+    const int n = d_step[1];
+    if (n < a.sc.n_form || n >= a.sc.n_max) return;  // uniform over the grid
+    const int m = n - a.sc.n_form;
+    const int k = path_offset(a.x_off, m, a.sc.dt);
+    const int kp = m > 0 ? path_offset(a.x_off, m - 1, a.sc.dt) : k;
+    const bool hop = k != kp, eval = m % a.stride == 0, rec = is_record_step(a.sc, n);
+    if (!(m == 0 || hop || eval || rec)) return;
+
+    const int p = blk * 256 + (int)threadIdx.x;
+    const bool live = p < V;
+    const int q = live ? p : 0;
+    const int y = q / N, i = q - y * N;
+    const uint32_t po = (uint32_t)q * (uint32_t)sizeof(T);
+    const View<T> A = make_view<T>(Af.U, kRealsPerSite, V), B = make_view<T>(Bf.U, kRealsPerSite, V);
+    const View<T> X = make_view<T>(aux, kAuxReals, V);
+    const View<T> WV = make_view<T>(Wb, 18, V), FV = make_view<T>(Fb, 24, V);
+
+    m3<T> w;
+    if (m == 0) {
+        w = identity<T>();
+    } else {
+#pragma unroll
+        for (int c = 0; c < 9; c++) w.e[c] = {bld(WV, po, 2 * c), bld(WV, po, 2 * c + 1)};
+    }
+    if (hop) {
+        // the path left cell i + kp for i + kp + 1: W <- W U_x(i + kp), links at t_n
+        const int xo = (i + kp % N) % N;  // kp >= 0
+        w = mul(w, vU(A, (uint32_t)(y * N + xo) * (uint32_t)sizeof(T), 0));
+        if constexpr (sizeof(T) == 4) w = reunitarize(w);
+    }
+    if ((m == 0 || hop) && live) {
+#pragma unroll
+        for (int c = 0; c < 9; c++) {
+            bst(WV, po, 2 * c, w.e[c].re);
+            bst(WV, po, 2 * c + 1, w.e[c].im);
+        }
+    }
+
+    a8<T> F[3];
+#pragma unroll
+    for (int j = 0; j < 3; j++) F[j] = m == 0 ? azero<T>() : vA(FV, po, 8 * j);
+    if (eval) {
+        const int x = (i + k % N) % N;
+        const Cell cell = make_cell<T>(x, y, N);
+        const T t = T(n * a.sc.dt);
+        a8<T> f[3];
+        f[2] = job_field<T>(kJobEeta, A, B, X, cell, n, t);
+        CPIC_PHASE();
+        const a8<T> beta = job_field<T>(kJobBeta, A, B, X, cell, n, t);
+        if (n > 0) {
+            CPIC_PHASE();
+            f[0] = job_field<T>(kJobEx, A, B, X, cell, n, t);
+            CPIC_PHASE();
+            f[1] = job_field<T>(kJobEy, A, B, X, cell, n, t);
+            const a8<T> by = job_field<T>(kJobBy, A, B, X, cell, n, t);
+#pragma unroll
+            for (int c = 0; c < 8; c++) f[2].v[c] += by.v[c];
+        } else {
+            f[0] = azero<T>();
+            f[1] = azero<T>();
+        }
+#pragma unroll
+        for (int c = 0; c < 8; c++) f[1].v[c] -= beta.v[c];
+        const T wgt = T(a.stride * a.sc.dt);
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            const a8<T> ft = transport(w, f[j]);
+#pragma unroll
+            for (int c = 0; c < 8; c++) F[j].v[c] += wgt * ft.v[c];
+        }
+        if (live) {
+#pragma unroll
+            for (int j = 0; j < 3; j++) vA_st(FV, po, 8 * j, F[j]);
+        }
+    } else if (m == 0 && live) {
+#pragma unroll
+        for (int j = 0; j < 3; j++) vA_st(FV, po, 8 * j, F[j]);
+    }
+
+    if (rec) {
+        const int lane = (int)threadIdx.x & 63, group = p >> 6, ngroups = jet_groups(V);
+        double* dst = partials + ((size_t)record_slot_of(a.sc, n) * ngroups + group) * 4;
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            double s = 0;
+            if (live)
+#pragma unroll
+                for (int c = 0; c < 8; c++) s += (double)F[j].v[c] * (double)F[j].v[c];
+            const double v = wave_sum(s);
+            if (lane == 0 && group < ngroups) dst[j] = v;
+        }
+        if (lane == 0 && group < ngroups) dst[3] = 0.0;
+    }
+}
+
+template <typename T>
+hipError_t launch_jets(const Fields<T>& A, const Fields<T>& B, const T* aux, T* W, T* F, const JetArgs& a,
+                       const int* d_step, double* partials, hipStream_t st, const KTimer& tm)
+{
+    if (!aux || !W || !F || a.N <= 0 || a.stride < 1 || !(a.sc.dt > 0 && a.sc.dt <= 1)) return hipErrorInvalidValue;
+    const int V = a.N * a.N, nb = (V + 255) / 256;
+    klaunch(tm, jet_kernel<T>, dim3(8 * ((nb + 7) / 8)), dim3(256), st, A, B, aux, W, F, a, d_step, partials);
+    return hipGetLastError();
+}
+template hipError_t launch_jets<double>(const Fields<double>&, const Fields<double>&, const double*, double*, double*,
+                                        const JetArgs&, const int*, double*, hipStream_t, const KTimer&);
+template hipError_t launch_jets<float>(const Fields<float>&, const Fields<float>&, const float*, float*, float*,
+                                       const JetArgs&, const int*, double*, hipStream_t, const KTimer&);
+
+}  // namespace cpic

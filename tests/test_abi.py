@@ -56,7 +56,8 @@ def test_struct_layout_matches_header(tmp_path):
     import paper_2303_05599_amd as cp
     probe = tmp_path / "probe.c"
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "cpic.h"', "int main(void){"]
-    for cname, py in (("cpic_glasma_params", cp.GlasmaParams), ("cpic_particle_params", cp.ParticleParams)):
+    for cname, py in (("cpic_glasma_params", cp.GlasmaParams), ("cpic_particle_params", cp.ParticleParams),
+                     ("cpic_jet_params", cp.JetParams)):
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
         for f, _ in py._fields_:
             lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
@@ -68,7 +69,8 @@ def test_struct_layout_matches_header(tmp_path):
     for line in subprocess.check_output([str(exe)], text=True).splitlines():
         name, field, val = line.split()
         got[(name, field)] = int(val)
-    for cname, py in (("cpic_glasma_params", cp.GlasmaParams), ("cpic_particle_params", cp.ParticleParams)):
+    for cname, py in (("cpic_glasma_params", cp.GlasmaParams), ("cpic_particle_params", cp.ParticleParams),
+                     ("cpic_jet_params", cp.JetParams)):
         assert got[(cname, "size")] == ctypes.sizeof(py)
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

@@ -1,0 +1,275 @@
+"""GPU tests of the light-like jet limit (cpic_jets_*, Sec. V.B [eq:mombroadjets]).
+
+  * parity with the oracle's path integral (Wilson lines, integrated forces,
+    samples) at 1e-11 in double precision, over ragged lattices, strides,
+    start offsets, formation steps, field-kernel variants, with and without
+    particles in the same event;
+  * single precision against the oracle within the FP32 budget;
+  * graph replay, eager stepping and checkpoint resume give the same bits;
+  * at the full 512^2 size, where the oracle is too slow: particles with
+    p^x -> infinity placed on the paths get dp_i = Q_0 . F_i from the push
+    kernel (the paper's Fig. 3b comparison, per particle), and the
+    near-light-like quarks of the jets workload (m = 0.01 GeV, p_T = 10 GeV)
+    broaden like the light-like paths within the finite-energy deflection.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+
+cp = pytest.importorskip("paper_2303_05599_amd")
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+DT = 0.125
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    cp.lib()
+    yield
+
+
+def rel_err(a, ref):
+    a, ref = np.asarray(a), np.asarray(ref)
+    rms = np.sqrt(np.mean(np.abs(ref) ** 2)) if ref.size else 0.0
+    den = np.maximum(np.abs(ref), rms)
+    den = np.where(den == 0, 1.0, den)
+    return float(np.max(np.abs(a - ref) / den)) if a.size else 0.0
+
+
+def event(N, steps, precision=cp.FP64, seed=41, a_fm=None, n_sheets=2):
+    L = N * a_fm if a_fm else 6.0 * N / 32
+    return dict(N=N, L_fm=L, g2mu_GeV=2.0, m_ir_GeV=0.2, uv_GeV=10.0, n_sheets=n_sheets, dtau_over_a=DT,
+                tau_max_fm=steps * DT * L / N, seed=seed, precision=precision,
+                reunit_every=16 if precision == cp.FP32 else 0, record_every=8)
+
+
+def oracle_run(g, steps, x_off, stride, nf_jet, part=None, rep=0):
+    """Oracle evolution of the same event; returns (run, jets, jet samples in GeV^2)."""
+    N, L = g["N"], g["L_fm"]
+    a = oracle.lattice_spacing(L, N)
+    st = oracle.mv_initial_condition(N, L, g["g2mu_GeV"], g["m_ir_GeV"], g["uv_GeV"], g["n_sheets"], g["seed"])
+    jets = oracle.Jets(N, DT, nf_jet, x_off, stride)
+    P, mhat, nf = None, math.inf, 0
+    if part:
+        P = oracle.particles_init(N, part["n"], part["seed"], 0.0, 0.0, True, 0)
+        mhat = part["mass_GeV"] * a if math.isfinite(part["mass_GeV"]) else math.inf
+        nf = part["nf"]
+    run = oracle.Run(N, DT, st, P, mhat=mhat, n_form=nf, jets=jets)
+    samples = []
+    for n in range(steps):
+        run.step()
+        if n >= nf_jet and ((n + 1) % 8 == 0 or n + 1 == steps):
+            samples.append([(n + 1) * DT * L / N, *(jets.observe(rep) / (a * a))])
+    return run, jets, np.array(samples)
+
+
+CASES = {
+    # N, steps, x_off, stride, jet formation step, particles, field launch
+    "ragged12": (12, 40, 0.0, 1, 0, None, None),
+    "n48_stride8_particles": (48, 60, 0.37, 8, 3, dict(n=500, mass_GeV=1.27, nf=5, seed=43), None),
+    "n64_static_stride3": (64, 50, 0.9, 3, 0, dict(n=300, mass_GeV=math.inf, nf=2, seed=44), None),
+    "n36_site_kernel": (36, 45, 0.5, 1, 2, None, (64, 4, 1, 1, 0)),
+    "n24_link_kernel": (24, 33, 0.125, 2, 1, dict(n=64, mass_GeV=0.5, nf=0, seed=45), (128, 1, 1, 1, 1)),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_jets_against_oracle(case):
+    N, steps, x_off, stride, nfj, part, launch = CASES[case]
+    print(f"case jets {case}", flush=True)
+    g = event(N, steps)
+    pp = None
+    if part:
+        pp = dict(n=part["n"], mass_GeV=part["mass_GeV"], pT_min_GeV=0.0, pT_max_GeV=0.0, azimuth_uniform=1,
+                  tau_form_fm=part["nf"] * DT * g["L_fm"] / N, rep=0, seed=part["seed"])
+    ctx = cp.Context(g, pp)
+    if launch:
+        ctx.set_launch(*launch)
+    ctx.enable_jets(x_offset=x_off, stride=stride, tau_form_fm=nfj * DT * g["L_fm"] / N, rep=cp.REP_ADJ)
+    ctx.init_mv()
+    ctx.evolve(1e9)
+    ctx.sync()
+    run, jets, samples = oracle_run(g, steps, x_off, stride, nfj, part, rep=1)
+    assert ctx.n == steps
+    W = ctx.get_state(cp.STATE_JET_W)
+    F = ctx.get_state(cp.STATE_JET_F)
+    assert rel_err(W, jets.W) <= TOL
+    assert rel_err(F, jets.F) <= TOL, rel_err(F, jets.F)
+    assert np.max(np.abs(F)) > 0.01
+    obs = ctx.jet_observables()
+    assert obs.shape == samples.shape
+    assert np.allclose(obs[:, 0], samples[:, 0], rtol=1e-14)
+    assert rel_err(obs[:, 1:], samples[:, 1:]) <= 1e-10
+    if part:
+        gp = ctx.get_state(cp.STATE_PARTICLES)
+        assert np.array_equal(gp[:, 14:16], run.P[:, 14:16])
+        assert rel_err(gp, run.P) <= TOL
+    ctx.close()
+
+
+def test_jets_fp32_against_oracle():
+    """Single precision (fields, Wilson lines and sums in float, W
+    reunitarised after every crossing) against the double-precision oracle:
+    the FP32 budget of the field tests (2e-3 after 64 steps)."""
+    N, steps = 32, 64
+    g = event(N, steps, precision=cp.FP32)
+    ctx = cp.Context(g, None)
+    ctx.enable_jets(x_offset=0.2, stride=1)
+    ctx.init_mv()
+    ctx.evolve(1e9)
+    _, jets, samples = oracle_run(g, steps, 0.2, 1, 0)
+    F = ctx.get_state(cp.STATE_JET_F)
+    assert rel_err(F, jets.F) < 2e-3
+    W = ctx.get_state(cp.STATE_JET_W).reshape(-1, 3, 3)
+    dev = np.abs(W @ np.conj(np.swapaxes(W, -1, -2)) - np.eye(3)).max()
+    assert dev < 1e-5
+    obs = ctx.jet_observables()
+    assert rel_err(obs[:, 1:], samples[:, 1:]) < 1e-3
+    ctx.close()
+
+
+def test_jets_graph_eager_and_checkpoint_bitwise(tmp_path):
+    N, steps = 48, 70
+    g = event(N, steps)
+    pp = dict(n=256, mass_GeV=1.0, pT_min_GeV=0.5, pT_max_GeV=1.0, azimuth_uniform=1, tau_form_fm=0.0, rep=0,
+              seed=7)
+    out = []
+    for mode in ("graph", "eager", "resume"):
+        ctx = cp.Context(g, pp)
+        ctx.enable_jets(x_offset=0.6, stride=2, tau_form_fm=0.0)
+        ctx.init_mv()
+        if mode == "graph":
+            ctx.evolve(1e9)
+        elif mode == "eager":
+            ctx.set_timing(True)
+            ctx.step(steps)
+            t = ctx.jets_timing()
+            assert t["n_jets"] == steps and t["jets_ms"] > 0
+        else:
+            ctx.step(29)
+            path = tmp_path / "ck.bin"
+            ctx.save(path)
+            ctx.close()
+            ctx = cp.Context(g, pp)
+            ctx.enable_jets(x_offset=0.6, stride=2, tau_form_fm=0.0)
+            ctx.load(path)
+            assert ctx.n == 29
+            ctx.evolve(1e9)
+        ctx.sync()
+        out.append((ctx.get_state(cp.STATE_JET_W), ctx.get_state(cp.STATE_JET_F), ctx.jet_observables(),
+                    ctx.observables()))
+        ctx.close()
+    for other in out[1:]:
+        for a, b in zip(out[0], other):
+            assert np.array_equal(a, b)
+
+
+def test_jets_call_order_errors():
+    g = event(12, 20)
+    ctx = cp.Context(g, None)
+    with pytest.raises(cp.CpicError):
+        ctx.get_state(cp.STATE_JET_F)
+    with pytest.raises(cp.CpicError):
+        ctx.enable_jets(x_offset=1.0)
+    with pytest.raises(cp.CpicError):
+        ctx.enable_jets(stride=0)
+    ctx.init_mv()
+    ctx.step(3)
+    with pytest.raises(cp.CpicError):
+        ctx.enable_jets(tau_form_fm=0.0)      # formation step already passed
+    ctx.enable_jets(tau_form_fm=5 * DT * g["L_fm"] / 12)
+    with pytest.raises(cp.CpicError):
+        ctx.enable_jets(tau_form_fm=1.0)      # twice
+    with pytest.raises(cp.CpicError):
+        ctx.set_state(cp.STATE_JET_W, np.zeros((12, 12, 3, 3), np.complex128))
+    ctx.evolve(1e9)
+    assert len(ctx.jet_observables()) == 3     # after steps 7, 15 and the last one, 19
+    ctx.close()
+
+
+def light_like_particles(ctx, N, x_off, pT_hat, rng):
+    """Move the context's particles onto the paths: x = i + x_off, y = j + 0.2,
+    p^x = pT_hat (hat units), p^y = p^eta = 0."""
+    P = ctx.get_state(cp.STATE_PARTICLES)
+    n = P.shape[0]
+    site = rng.choice(N * N, size=n, replace=False)
+    ys, xs = np.divmod(site, N)
+    P[:, 0], P[:, 1] = xs + x_off, ys + 0.2
+    P[:, 2] = 0.0
+    P[:, 3], P[:, 4], P[:, 5] = pT_hat, 0.0, 0.0
+    P[:, 14], P[:, 15] = np.floor(P[:, 0] + 0.5) % N, np.floor(P[:, 1] + 0.5) % N
+    P[:, 16] = 0.0
+    P[:, 17], P[:, 18], P[:, 19] = 1.0, 0.0, 0.0
+    ctx.set_state(cp.STATE_PARTICLES, P)
+    return P, site
+
+
+def test_light_like_particles_match_jets_full_size():
+    """512^2, 50 sheets, FP64: 4096 particles with p^x = 1e7 (hat units) on
+    the paths.  Over 200 steps the push must give dp_x, dp_y = Q_0 . F_x,y of
+    the path it rides (to the ~1e-7 its finite energy leaves)."""
+    N, steps, x_off = 512, 200, 0.3
+    g = event(N, steps, n_sheets=50, seed=3, a_fm=6.0 / 512)
+    pp = dict(n=4096, mass_GeV=1e-3, pT_min_GeV=0.0, pT_max_GeV=0.0, azimuth_uniform=1, tau_form_fm=0.0, rep=0,
+              seed=4)
+    ctx = cp.Context(g, pp)
+    ctx.enable_jets(x_offset=x_off)
+    ctx.init_mv()
+    P0, site = light_like_particles(ctx, N, x_off, 1e7, np.random.default_rng(5))
+    ctx.evolve(1e9)
+    P = ctx.get_state(cp.STATE_PARTICLES)
+    F = ctx.get_state(cp.STATE_JET_F).reshape(N * N, 3, 8)[site]
+    assert np.array_equal(P[:, 15], P0[:, 15])            # no particle left its row
+    pred = np.einsum("na,nka->nk", P0[:, 6:14], F)
+    for k, got in ((0, P[:, 3] - P0[:, 3]), (1, P[:, 4] - P0[:, 4])):
+        rms = np.sqrt(np.mean(pred[:, k] ** 2))
+        assert rms > 0.01
+        assert np.max(np.abs(got - pred[:, k])) < 1e-5 * rms
+    ctx.close()
+
+
+def test_jets_workload_near_light_like_quarks():
+    """The jets workload (512^2 event in FP32, 1e6 quarks with m = 0.01 GeV and
+    p_T = 10 GeV at uniform azimuth, formed at tau = 0) beside the light-like
+    paths of the same event, to 1 fm/c.  At p/m = 1000 the quarks move at the
+    speed of light to 5e-7, but a transverse kick of ~1 GeV turns a 10 GeV
+    quark by ~0.1 rad, so its path and the colour it meets drift from the
+    straight line.  Across and longitudinal broadenings must agree with the
+    light-like limit within 10 % (measured: 2 % and 3 %).  Along the motion the broadening of
+    [eq:mombroad], p^2 - p_T0^2, also holds 2 p_T0 <dp_par> (the quarks' mean
+    momentum change), which the limit leaves out: there the variance of
+    p_par - p_T0, taken from the particle records, is compared, also within
+    10 %."""
+    N = 512
+    g = event(N, 683, precision=cp.FP32, n_sheets=50, seed=3, a_fm=6.0 / 512)
+    pp = dict(n=1_000_000, mass_GeV=0.01, pT_min_GeV=10.0, pT_max_GeV=10.0, azimuth_uniform=1, tau_form_fm=0.0,
+              rep=0, seed=4)
+    ctx = cp.Context(g, pp)
+    ctx.enable_jets(x_offset=0.3)
+    ctx.init_mv()
+    ctx.evolve(1e9)
+    obs = ctx.observables()
+    jet = ctx.jet_observables()
+    assert obs.shape[0] == jet.shape[0]
+    assert np.allclose(obs[:, 0], jet[:, 0])
+    last, lj = obs[-1], jet[-1]
+    P = ctx.get_state(cp.STATE_PARTICLES)
+    a = oracle.lattice_spacing(g["L_fm"], N)
+    dpar = (P[:, 3] * P[:, 17] + P[:, 4] * P[:, 18] - P[:, 19]) / a
+    var_par = float(np.mean(dpar ** 2))
+    print("quarks par/perp/L", last[3], last[4], last[2], "var(p_par - p_T0)", var_par, "mean", dpar.mean(),
+          "paths x/y/z", lj[1], lj[2], lj[3], flush=True)
+    assert abs(last[4] / lj[2] - 1) < 0.10
+    assert abs(last[2] / lj[3] - 1) < 0.10
+    assert abs(var_par / lj[1] - 1) < 0.10
+    # the definition of [eq:mombroad] along the motion: <p^2 - p_T0^2> = var + 2 p_T0 <dp_par> + <dp_par>^2
+    assert last[3] == pytest.approx(var_par + 2 * 10.0 * dpar.mean(), rel=2e-3, abs=2e-3)
+    ctx.close()

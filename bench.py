@@ -10,8 +10,10 @@ timed region; W warm-up steps (past the formation step) are not timed, then
 K steps are timed with a barrier and synchronisation on both sides.
 
 Extra keys report the same event in single precision (reunitarisation every
-16 steps) and the batched multi-event mode; the CPU oracle is timed on a
-bounded sample of the same workload on the host cores.
+16 steps), the jets workload (the same event in single precision with 1e6
+near-light-like quarks and the light-like path integral of Sec. V.B) and
+the batched multi-event mode; the CPU oracle is timed on a bounded sample of
+the same workload on the host cores.
 """
 import argparse
 import json
@@ -36,6 +38,11 @@ HBARC_GEV_FM = 0.1973269804
 SITE_BYTES = {"f64": 68 * 2 * 8, "f32": 68 * 2 * 4}
 AUX_BYTES = {"f64": 48 * 8, "f32": 48 * 4}
 PUSH_BYTES = {"f64": 730, "f32": 370}
+# light-like paths, per path and step: the Wilson line (18 reals) read, the
+# three integrated forces (24 reals) read and written, and the fields at the
+# path's cell read once per site: x and y links (36), the half-step sums of
+# E_x, E_y and pi, D_x and G of the aux buffer (40)
+JET_BYTES = {"f64": 142 * 8, "f32": 142 * 4}
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_512_fp64.txt")
 KERNEL_SOURCES = os.path.join(ROOT, "paper_2303_05599_amd", "csrc")
 
@@ -51,7 +58,13 @@ def charm(n=100_000, seed=4):
                 seed=seed)
 
 
-def run_event(precision, steps, warmup, tune=True):
+def jet_quarks(n=1_000_000, seed=4):
+    """Near-light-like quarks: m = 0.01 GeV, p_T = 10 GeV, uniform azimuth, formed at tau = 0."""
+    return dict(n=n, mass_GeV=0.01, pT_min_GeV=10.0, pT_max_GeV=10.0, azimuth_uniform=1, tau_form_fm=0.0, rep=0,
+                seed=seed)
+
+
+def run_event(precision, steps, warmup, tune=True, particles=None, jets=False):
     """One 512^2 event: IC (timed separately), warm-up steps past formation, the
     launch tuner, a graph-replayed stretch (its rate is reported as an extra),
     then the timed region: `steps` steps with per-kernel HIP-event timing.  The
@@ -59,7 +72,9 @@ def run_event(precision, steps, warmup, tune=True):
     kernel are exactly the timed ones."""
     import torch
     import paper_2303_05599_amd as cp
-    ctx = cp.Context(glasma_512(precision), charm())
+    ctx = cp.Context(glasma_512(precision), particles or charm())
+    if jets:
+        ctx.enable_jets(x_offset=0.3)
     t0 = time.perf_counter()
     ctx.init_mv()
     t_ic = time.perf_counter() - t0
@@ -84,12 +99,15 @@ def run_event(precision, steps, warmup, tune=True):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     tm = ctx.timing()
+    if jets:
+        tm.update(ctx.jets_timing())
     ctx.set_timing(False)
     d = ctx.diagnostics()
     obs = ctx.observables()
+    jobs = ctx.jet_observables() if jets else None
     ctx.close()
-    return dict(wall=wall, t_ic=t_ic, timing=tm, diag=d, obs=obs, graph_ms_per_step=graph_ms, launch=launch,
-                tune_report=tune_report)
+    return dict(wall=wall, t_ic=t_ic, timing=tm, diag=d, obs=obs, jet_obs=jobs, graph_ms_per_step=graph_ms,
+                launch=launch, tune_report=tune_report)
 
 
 def batch_events(precision, n_events=64, seed=5):
@@ -171,6 +189,32 @@ def run_batch(fp64_launch):
             "launch": launch, "tuner_choice": tune.strip().splitlines()[-1]}
 
 
+def run_jets(steps, warmup, V):
+    """The jets workload: the 512^2 event in FP32 with 1e6 near-light-like quarks
+    and the light-like path integral over all 512^2 starting sites (the
+    limit the quarks are compared with); the same timed region as the
+    headline run."""
+    import paper_2303_05599_amd as cp
+    n_part = 1_000_000
+    r = run_event(cp.FP32, steps, warmup, True, jet_quarks(n_part), jets=True)
+    k = rooflines(r, "fp32", n_part, V)
+    last, lj = r["obs"][-1], r["jet_obs"][-1]
+    return {"workload": "MV Glasma 512^2 (as above) in FP32 with reunitarisation every 16 steps, 1e6 quarks "
+                        "m=0.01 GeV, pT=10 GeV, uniform azimuth, formed at tau=0, plus one light-like path "
+                        "along +x per site",
+            "ms_per_step": r["wall"] * 1e3 / steps,
+            "site_updates_per_s": V * steps / r["wall"],
+            "pushes_per_s": n_part * steps / r["wall"],
+            "path_steps_per_s": V * steps / r["wall"],
+            "graph_ms_per_step": r["graph_ms_per_step"],
+            "kernels": k, "launch": r["launch"],
+            "tau_fm": float(last[0]),
+            "quarks_GeV2": {"dpT2": float(last[1]), "dpL2": float(last[2]), "dp_par2": float(last[3]),
+                            "dp_perp2": float(last[4]), "anisotropy_L_over_T": float(last[2] / last[1])},
+            "light_like_GeV2": {"dpx2": float(lj[1]), "dpy2": float(lj[2]), "dpz2": float(lj[3]),
+                                "anisotropy_z_over_y": float(lj[3] / lj[2])}}
+
+
 def cpu_baseline(n_steps=6, n_part=100_000):
     """The oracle on the host cores: 512^2 MV event (one colour sheet; the
     initial condition is not timed), n_steps leapfrog steps with the push of
@@ -229,7 +273,7 @@ def kernel_names(launch, precision):
         field = "field_link_kernel" + ("" if launch["waves"] == 1 else f"_w{launch['waves']}") + f"<{t}, true>"
     else:
         field = "field_step_kernel" + ("" if launch["waves"] == 1 else f"_w{launch['waves']}") + f"<{t}, true>"
-    return field, f"push_kernel<{t}, {launch['push_lanes']}>"
+    return field, f"push_kernel<{t}, {launch['push_lanes']}>", f"jet_kernel<{t}>"
 
 
 def rooflines(res, precision, n_part, V):
@@ -238,11 +282,13 @@ def rooflines(res, precision, n_part, V):
     dt = "f64" if precision == "fp64" else "f32"
     field_s = tm["field_ms"] / max(tm["n_field"], 1) * 1e-3
     push_s = tm["push_ms"] / max(tm["n_push"], 1) * 1e-3
-    fname, pname = kernel_names(res["launch"], precision)
+    fname, pname, jname = kernel_names(res["launch"], precision)
     out = {}
-    for key, name, secs, unit_bytes, units, unit in (
-            ("field", fname, field_s, SITE_BYTES[dt] + AUX_BYTES[dt], V, "site-update"),
-            ("push", pname, push_s, PUSH_BYTES[dt], n_part, "particle-push")):
+    entries = [("field", fname, field_s, SITE_BYTES[dt] + AUX_BYTES[dt], V, "site-update"),
+               ("push", pname, push_s, PUSH_BYTES[dt], n_part, "particle-push")]
+    if tm.get("n_jets"):
+        entries.append(("jets", jname, tm["jets_ms"] / tm["n_jets"] * 1e-3, JET_BYTES[dt], V, "path-step"))
+    for key, name, secs, unit_bytes, units, unit in entries:
         bpl = unit_bytes * units
         ach = bpl / secs / 1e9
         out[key] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -433,6 +479,7 @@ def main():
                        "launch": r32["launch"],
                        "dpT2_rel_vs_fp64": float(abs(r32["obs"][-1, 1] / res["obs"][-1, 1] - 1)),
                        "dpL2_rel_vs_fp64": float(abs(r32["obs"][-1, 2] / res["obs"][-1, 2] - 1))}
+        out["jets"] = run_jets(args.steps, args.warmup, V)
         out["batch"] = run_batch(res["launch"])
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()

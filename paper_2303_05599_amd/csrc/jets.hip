@@ -14,7 +14,7 @@
 // grid point moves (once per 1/dt steps), the five fields f needs are read
 // at the nearest grid point from U(n), pi(n+1/2) and the aux pieces of the
 // field update, transported with W and added to F.  On recording steps each
-// wavefront writes the double-precision sums of |F_i|^2 over its 64 paths.
+// wavefront writes the double-precision sum of |F_i|^2 over its 64 paths.
 #include "cellfields.h"
 #include "reduce.h"
 
@@ -28,14 +28,21 @@ __device__ __forceinline__ int path_offset(double x_off, int m, double dt)
     return (int)floor(x_off + (double)m * dt + 0.5);
 }
 
+// Three wavefronts share a group of 64 paths, one per force component
+// (role 0: f_x, 1: f_y, 2: f_z): each reads the group's Wilson lines, applies
+// a crossing, evaluates and transports its own component and adds it to its
+// part of F.  Role 0 stores the Wilson lines.  Splitting by component keeps
+// each wavefront's chain of dependent loads and its live registers short.
+constexpr int kJetRoles = 3;
+
 template <typename T>
-__global__ __launch_bounds__(256) void jet_kernel(Fields<T> Af, Fields<T> Bf, const T* aux, T* Wb, T* Fb, JetArgs a,
-                                                  const int* d_step, double* partials)
+__global__ __launch_bounds__(64 * kJetRoles) void jet_kernel(Fields<T> Af, Fields<T> Bf, const T* aux, T* Wb, T* Fb,
+                                                             JetArgs a, const int* d_step, double* partials)
 {
     const int N = a.N, V = N * N;
-    const int nblocks = (V + 255) / 256;
-    const int blk = xcd_block(nblocks);
-    if (blk >= nblocks) return;
+    const int ngroups = jet_groups(V);
+    const int group = xcd_block(ngroups);
+    if (group >= ngroups) return;
     const int n = d_step[1];
     if (n < a.sc.n_form || n >= a.sc.n_max) return;  // uniform over the grid
     const int m = n - a.sc.n_form;
@@ -44,7 +51,8 @@ __global__ __launch_bounds__(256) void jet_kernel(Fields<T> Af, Fields<T> Bf, co
     const bool hop = k != kp, eval = m % a.stride == 0, rec = is_record_step(a.sc, n);
     if (!(m == 0 || hop || eval || rec)) return;
 
-    const int p = blk * 256 + (int)threadIdx.x;
+    const int role = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = (int)threadIdx.x & 63;
+    const int p = group * 64 + lane;
     const bool live = p < V;
     const int q = live ? p : 0;
     const int y = q / N, i = q - y * N;
@@ -66,68 +74,62 @@ __global__ __launch_bounds__(256) void jet_kernel(Fields<T> Af, Fields<T> Bf, co
         w = mul(w, vU(A, (uint32_t)(y * N + xo) * (uint32_t)sizeof(T), 0));
         if constexpr (sizeof(T) == 4) w = reunitarize(w);
     }
-    if ((m == 0 || hop) && live) {
+    if (m == 0 || hop) {  // uniform over the grid
+        // every wavefront of the group has read the old Wilson line (the
+        // barrier waits for its loads) before role 0 overwrites it
+        __syncthreads();
+        if (role == 0 && live) {
 #pragma unroll
-        for (int c = 0; c < 9; c++) {
-            bst(WV, po, 2 * c, w.e[c].re);
-            bst(WV, po, 2 * c + 1, w.e[c].im);
+            for (int c = 0; c < 9; c++) {
+                bst(WV, po, 2 * c, w.e[c].re);
+                bst(WV, po, 2 * c + 1, w.e[c].im);
+            }
         }
     }
+    CPIC_PHASE();
 
-    a8<T> F[3];
-#pragma unroll
-    for (int j = 0; j < 3; j++) F[j] = m == 0 ? azero<T>() : vA(FV, po, 8 * j);
+    // this wavefront's component: transported with W, added to F_role
+    const uint32_t fc = 8 * (uint32_t)role;
+    a8<T> Fj = m == 0 ? azero<T>() : vA(FV, po, fc);
     if (eval) {
         const int x = (i + k % N) % N;
         const Cell cell = make_cell<T>(x, y, N);
         const T t = T(n * a.sc.dt);
-        a8<T> f[3];
-        f[2] = job_field<T>(kJobEeta, A, B, X, cell, n, t);
-        CPIC_PHASE();
-        const a8<T> beta = job_field<T>(kJobBeta, A, B, X, cell, n, t);
-        if (n > 0) {
+        a8<T> f = azero<T>();
+        if (role == 0) {
+            if (n > 0) f = job_field<T>(kJobEx, A, B, X, cell, n, t);             // f_x = E_x
+        } else if (role == 1) {
+            if (n > 0) f = job_field<T>(kJobEy, A, B, X, cell, n, t);             // f_y = E_y - B_eta
             CPIC_PHASE();
-            f[0] = job_field<T>(kJobEx, A, B, X, cell, n, t);
-            CPIC_PHASE();
-            f[1] = job_field<T>(kJobEy, A, B, X, cell, n, t);
-            const a8<T> by = job_field<T>(kJobBy, A, B, X, cell, n, t);
+            const a8<T> beta = job_field<T>(kJobBeta, A, B, X, cell, n, t);
 #pragma unroll
-            for (int c = 0; c < 8; c++) f[2].v[c] += by.v[c];
+            for (int c = 0; c < 8; c++) f.v[c] -= beta.v[c];
         } else {
-            f[0] = azero<T>();
-            f[1] = azero<T>();
-        }
+            f = job_field<T>(kJobEeta, A, B, X, cell, n, t);                      // f_z = E_eta + B_y
+            if (n > 0) {
+                const a8<T> by = job_field<T>(kJobBy, A, B, X, cell, n, t);
 #pragma unroll
-        for (int c = 0; c < 8; c++) f[1].v[c] -= beta.v[c];
+                for (int c = 0; c < 8; c++) f.v[c] += by.v[c];
+            }
+        }
+        const a8<T> ft = transport(w, f);
         const T wgt = T(a.stride * a.sc.dt);
 #pragma unroll
-        for (int j = 0; j < 3; j++) {
-            const a8<T> ft = transport(w, f[j]);
-#pragma unroll
-            for (int c = 0; c < 8; c++) F[j].v[c] += wgt * ft.v[c];
-        }
-        if (live) {
-#pragma unroll
-            for (int j = 0; j < 3; j++) vA_st(FV, po, 8 * j, F[j]);
-        }
-    } else if (m == 0 && live) {
-#pragma unroll
-        for (int j = 0; j < 3; j++) vA_st(FV, po, 8 * j, F[j]);
+        for (int c = 0; c < 8; c++) Fj.v[c] += wgt * ft.v[c];
+        if (live) vA_st(FV, po, fc, Fj);
     }
 
     if (rec) {
-        const int lane = (int)threadIdx.x & 63, group = p >> 6, ngroups = jet_groups(V);
+        double sq = 0;
+        if (live)
+#pragma unroll
+            for (int c = 0; c < 8; c++) sq += (double)Fj.v[c] * (double)Fj.v[c];
+        const double v = wave_sum(sq);
         double* dst = partials + ((size_t)record_slot_of(a.sc, n) * ngroups + group) * 4;
-#pragma unroll
-        for (int j = 0; j < 3; j++) {
-            double s = 0;
-            if (live)
-#pragma unroll
-                for (int c = 0; c < 8; c++) s += (double)F[j].v[c] * (double)F[j].v[c];
-            const double v = wave_sum(s);
-            if (lane == 0 && group < ngroups) dst[j] = v;
+        if (lane == 0) {
+            dst[role] = v;
+            if (role == 0) dst[3] = 0.0;
         }
-        if (lane == 0 && group < ngroups) dst[3] = 0.0;
     }
 }
 
@@ -136,8 +138,9 @@ hipError_t launch_jets(const Fields<T>& A, const Fields<T>& B, const T* aux, T* 
                        const int* d_step, double* partials, hipStream_t st, const KTimer& tm)
 {
     if (!aux || !W || !F || a.N <= 0 || a.stride < 1 || !(a.sc.dt > 0 && a.sc.dt <= 1)) return hipErrorInvalidValue;
-    const int V = a.N * a.N, nb = (V + 255) / 256;
-    klaunch(tm, jet_kernel<T>, dim3(8 * ((nb + 7) / 8)), dim3(256), st, A, B, aux, W, F, a, d_step, partials);
+    const int nb = jet_groups(a.N * a.N);
+    klaunch(tm, jet_kernel<T>, dim3(8 * ((nb + 7) / 8)), dim3(64 * kJetRoles), st, A, B, aux, W, F, a, d_step,
+            partials);
     return hipGetLastError();
 }
 template hipError_t launch_jets<double>(const Fields<double>&, const Fields<double>&, const double*, double*, double*,

@@ -189,14 +189,14 @@ def run_batch(fp64_launch):
             "launch": launch, "tuner_choice": tune.strip().splitlines()[-1]}
 
 
-def run_jets(steps, warmup, V):
+def run_jets(steps, warmup, V, tune=True):
     """The jets workload: the 512^2 event in FP32 with 1e6 near-light-like quarks
     and the light-like path integral over all 512^2 starting sites (the
     limit the quarks are compared with); the same timed region as the
     headline run."""
     import paper_2303_05599_amd as cp
     n_part = 1_000_000
-    r = run_event(cp.FP32, steps, warmup, True, jet_quarks(n_part), jets=True)
+    r = run_event(cp.FP32, steps, warmup, tune, jet_quarks(n_part), jets=True)
     k = rooflines(r, "fp32", n_part, V)
     last, lj = r["obs"][-1], r["jet_obs"][-1]
     return {"workload": "MV Glasma 512^2 (as above) in FP32 with reunitarisation every 16 steps, 1e6 quarks "
@@ -405,6 +405,8 @@ def main():
     ap.add_argument("--trace-summary", nargs=3, metavar=("OUT", "TRACE_DIR", "TIMED_STEPS"),
                     help="condense a rocprofv3 --kernel-trace --stats directory into a markdown table")
     ap.add_argument("--command", default="", help="command line recorded in a summary")
+    ap.add_argument("--jets-only", action="store_true",
+                    help="run only the jets workload and print its JSON (for profiling; not the benchmark line)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the library's default launch shapes (for counter runs, where the tuner's timings "
                          "are distorted by the serialised dispatches)")
@@ -436,6 +438,9 @@ def main():
     torch.cuda.set_device(0)
     V = 512 * 512
     n_part = 100_000
+    if args.jets_only:
+        print(json.dumps(run_jets(args.steps, args.warmup, V, not args.no_tune)))
+        return
     res = run_event(cp.FP64 if args.precision == "fp64" else cp.FP32, args.steps, args.warmup, not args.no_tune)
     ms_per_step = res["wall"] * 1e3 / args.steps
     site_rate = V * args.steps / res["wall"]

@@ -66,7 +66,8 @@ def lib():
             "orc_casimirs": (None, [p, p, p]),
             "orc_particles_init": (None, [i, i, u64, d, d, i, i, p]),
             "orc_particle_fields": (None, [i, i, d, i, p, p, p, p, p, p, p]),
-            "orc_particles_step": (i, [i, i, i, d, d, i, p, p, p, p, p, p, i, p]),
+            "orc_particles_step": (i, [i, i, i, d, d, i, i, p, p, p, p, p, p, i, p]),
+            "orc_link_generator": (None, [p, p]),
             "orc_particles_observe": (None, [d, d, i, i, p, p]),
             "orc_jet_step": (None, [i, i, i, d, d, i, p, p, p, p, p, p, p, p]),
             "orc_generator": (None, [i, p]),
@@ -270,6 +271,13 @@ def particles_init(N, n, seed, pt_min_hat, pt_max_hat, azimuth_uniform=True, rep
     return P
 
 
+def link_generator(U) -> np.ndarray:
+    """Components a^a of -i log U (principal matrix logarithm), U = exp(i a^a T^a)."""
+    out = np.zeros(8)
+    lib().orc_link_generator(_ptr(np.ascontiguousarray(U, np.complex128)), _ptr(out))
+    return out
+
+
 def particle_fields(N, n, dt, site, U, phi, E_old, E_new, pi_old, pi_new):
     out = np.zeros((6, 8))
     lib().orc_particle_fields(N, n, dt, site, _ptr(U), _ptr(phi), _ptr(E_old), _ptr(E_new),
@@ -317,9 +325,12 @@ class Run:
     step n: the fields go U(n), phi(n), E(n-1/2), pi(n-1/2) -> U(n+1), phi(n+1),
     E(n+1/2), pi(n+1/2); then, if n >= n_form, the particles are pushed at t_n
     with U(n), phi(n), E(n +- 1/2), pi(n +- 1/2).  mhat = inf selects the static
-    branch.  An optional Jets object is stepped with the same inputs as the push."""
+    branch.  color = "cpic" rotates the charges with the links (Eq. colorrotnum),
+    "log" integrates dQ/dt = i[Q, A.v] with A from the matrix logarithm of the
+    links (the alternative of Sec. III.B).  An optional Jets object is stepped
+    with the same inputs as the push."""
 
-    def __init__(self, N, dt, state, particles=None, mhat=math.inf, n_form=0, n0=0, jets=None):
+    def __init__(self, N, dt, state, particles=None, mhat=math.inf, n_form=0, n0=0, jets=None, color="cpic"):
         self.N, self.dt, self.n = N, dt, n0
         self.st = {k: np.ascontiguousarray(state[k]).copy() for k in ("U", "phi", "E", "pi")}
         self.P = None if particles is None else np.ascontiguousarray(particles).copy()
@@ -328,6 +339,7 @@ class Run:
         self.n_form = n_form
         self.errors = 0
         self.jets = jets
+        self.color_mode = {"cpic": 0, "log": 1}[color]
 
     def step(self):
         N, n, st = self.N, self.n, self.st
@@ -339,7 +351,7 @@ class Run:
         field_step(N, n, self.dt, st)
         if push:
             self.errors += lib().orc_particles_step(
-                N, n, self.n_form, self.dt, self.mhat, int(self.is_static), _ptr(U_n), _ptr(phi_n),
+                N, n, self.n_form, self.dt, self.mhat, int(self.is_static), self.color_mode, _ptr(U_n), _ptr(phi_n),
                 _ptr(E_old), _ptr(st["E"]), _ptr(pi_old), _ptr(st["pi"]), self.P.shape[0], _ptr(self.P))
         if jets:
             self.jets.step(n, U_n, phi_n, E_old, st["E"], pi_old, st["pi"])

@@ -153,6 +153,67 @@ static M3 expi_alg(const double *x, double scale)
     return m_exp(m_scale(alg_to_mat(y), I));
 }
 
+/* inverse of a 3x3 complex matrix: adjugate over determinant */
+static M3 m_inv(M3 a)
+{
+    M3 c;
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            const int i1 = (j + 1) % 3, i2 = (j + 2) % 3, j1 = (i + 1) % 3, j2 = (i + 2) % 3;
+            c.e[i][j] = a.e[i1][j1] * a.e[i2][j2] - a.e[i1][j2] * a.e[i2][j1];
+        }
+    const cplx det = a.e[0][0] * c.e[0][0] + a.e[0][1] * c.e[1][0] + a.e[0][2] * c.e[2][0];
+    return m_scale(c, 1.0 / det);
+}
+static double m_dist(M3 a, M3 b)
+{
+    double d = 0;
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) d += cabs(a.e[i][j] - b.e[i][j]);
+    return d;
+}
+/* principal square root (no eigenvalue on the negative real axis) by the
+ * Denman-Beavers iteration Y <- (Y + Z^-1)/2, Z <- (Z + Y^-1)/2 from Y = M,
+ * Z = 1: Y -> M^(1/2), Z -> M^(-1/2) */
+static M3 m_sqrt(M3 M)
+{
+    M3 Y = M, Z = m_id();
+    for (int k = 0; k < 100; k++) {
+        M3 Yn = m_scale(m_add(Y, m_inv(Z)), 0.5);
+        M3 Zn = m_scale(m_add(Z, m_inv(Y)), 0.5);
+        const double d = m_dist(Yn, Y);
+        Y = Yn;
+        Z = Zn;
+        if (d < 1e-17) break;
+    }
+    return Y;
+}
+/* principal logarithm by inverse scaling and squaring: log M = 2^s log(M^(1/2^s))
+ * with square roots until M^(1/2^s) is within 0.05 of 1, then the series
+ * log(1 + E) = E - E^2/2 + E^3/3 - ... */
+static M3 m_log(M3 M)
+{
+    int s = 0;
+    while (m_dist(M, m_id()) > 0.05 && s < 60) {
+        M = m_sqrt(M);
+        s++;
+    }
+    const M3 E = m_sub(M, m_id());
+    M3 sum = m_zero(), pw = m_id();
+    for (int k = 1; k <= 40; k++) {
+        pw = m_mul(pw, E);
+        sum = m_add(sum, m_scale(pw, (k % 2 ? 1.0 : -1.0) / k));
+    }
+    return m_scale(sum, ldexp(1.0, s));
+}
+/* components a^a of the Hermitian generator of a link: U = exp(i a^a T^a),
+ * a = -i log U (principal branch; the trace part, nonzero only beyond the
+ * branch of traceless generators, is dropped by the projection onto T^a) */
+static void link_generator(M3 U, double *a)
+{
+    mat_to_alg(m_scale(m_log(U), -I), a);
+}
+
 /* Gram-Schmidt on rows 1 and 2, row 3 = conj(r1 x r2): a unitary matrix
  * with unit determinant.  Used as the starting point of the initial-link
  * solve (reading of the lattice initial condition, Sec. II.A). */
@@ -789,12 +850,22 @@ static void rotate_q(double *Q, M3 A)
  *       x += dt v_x, y += dt v_y, eta += dt p^eta/p^tau, periodic wrap.
  * Static branch (infinite mass, the limit of Sec. V.A): no motion and no
  * rotation; p^x, p^y, p^z += dt (e_x, e_y, e_eta), p^z kept in the p^eta column.
+ *
+ * color_mode 1 replaces the colour rotation of step 1 by the alternative of
+ * Sec. III.B: the charge follows dQ/dt = i[Q, A_x v_x + A_y v_y + phi v_eta]
+ * with the gauge fields taken from the links by the matrix logarithm,
+ * a A_i(x + i/2) = -i log U_i(x) (hat units), stepped by explicit Euler with
+ * the rest of the particle's variables (reading): Q_{n+1} = Q_n + dt i[Q_n, M_n].
+ * A_x is taken on the x link whose midpoint is nearest to the particle,
+ * (floor(x), NGP row), A_y on the y link at (NGP column, floor(y)), phi at
+ * the nearest grid point, all at t_n; v_eta = p^eta / p^tau.
+ *
  * Returns the number of particles whose grid point moved by more than one
  * cell along an axis (an error).
  */
-int orc_particles_step(int N, int n, int n_form, double dt, double mhat, int is_static, const cplx *U,
-                       const double *phi, const double *E_old, const double *E_new, const double *pi_old,
-                       const double *pi_new, int np, double *P)
+int orc_particles_step(int N, int n, int n_form, double dt, double mhat, int is_static, int color_mode,
+                       const cplx *U, const double *phi, const double *E_old, const double *E_new,
+                       const double *pi_old, const double *pi_new, int np, double *P)
 {
     build_generators();
     int errors = 0;
@@ -814,21 +885,22 @@ int orc_particles_step(int N, int n, int n_form, double dt, double mhat, int is_
         int cx = (int)r[P_CX], cy = (int)r[P_CY];
         int nx = ((int)floor(r[P_X] + 0.5)) % N, ny = ((int)floor(r[P_Y] + 0.5)) % N;
         if (n > n_form) {
+            const int rotate = color_mode == 0;
             int d[2] = {nx - cx, ny - cy};
             for (int ax = 0; ax < 2; ax++) {
                 if (d[ax] > N / 2) d[ax] -= N;
                 if (d[ax] < -N / 2) d[ax] += N;
                 int c = cy * N + cx;
                 if (d[ax] == 1) {
-                    rotate_q(r + P_Q, link(U, N, ax, c));
+                    if (rotate) rotate_q(r + P_Q, link(U, N, ax, c));
                 } else if (d[ax] == -1) {
-                    rotate_q(r + P_Q, m_adj(link(U, N, ax, step_dir(c, ax, -1, N))));
+                    if (rotate) rotate_q(r + P_Q, m_adj(link(U, N, ax, step_dir(c, ax, -1, N))));
                 } else if (d[ax] != 0) {
                     errors++;
                 }
                 if (ax == 0) cx = nx; else cy = ny;
             }
-            rotate_q(r + P_Q, expi_alg(phi + 8 * (size_t)(ny * N + nx), r[P_DETA]));
+            if (rotate) rotate_q(r + P_Q, expi_alg(phi + 8 * (size_t)(ny * N + nx), r[P_DETA]));
         }
         int s = ny * N + nx;
         orc_particle_fields(N, n, dt, s, U, phi, E_old, E_new, pi_old, pi_new, f);
@@ -838,6 +910,18 @@ int orc_particles_step(int N, int n, int n_form, double dt, double mhat, int is_
         double px = r[P_PX], py = r[P_PY], pe = r[P_PETA];
         double ptau = sqrt(px * px + py * py + (t * pe) * (t * pe) + mhat * mhat);
         double v1 = px / ptau, v2 = py / ptau, vl = t * pe / ptau;
+        if (color_mode == 1) {
+            /* Q_{n+1} = Q_n + dt i[Q_n, M_n], from the state at n */
+            const int lx = ((int)floor(r[P_X])) % N, ly = ((int)floor(r[P_Y])) % N;
+            double gx[8], gy[8], M[8], dq[8];
+            link_generator(link(U, N, 0, ny * N + lx), gx);
+            link_generator(link(U, N, 1, ly * N + nx), gy);
+            const double veta = pe / ptau;
+            for (int a = 0; a < 8; a++) M[a] = v1 * gx[a] + v2 * gy[a] + veta * phi[(size_t)(ny * N + nx) * 8 + a];
+            const M3 Qm = alg_to_mat(Q), Mm = alg_to_mat(M);
+            mat_to_alg(m_scale(m_sub(m_mul(Qm, Mm), m_mul(Mm, Qm)), I), dq);
+            for (int a = 0; a < 8; a++) r[P_Q + a] += dt * dq[a];
+        }
         r[P_PX] = px + dt * (e1 + be * v2 - b2 * vl);
         r[P_PY] = py + dt * (e2 - be * v1 + b1 * vl);
         if (n > 0) r[P_PETA] = pe + dt * (ee - b1 * v2 + b2 * v1 - 2.0 * pe) / t;
@@ -965,6 +1049,14 @@ void orc_proj(const cplx *M, double *out)
     M3 m;
     memcpy(&m, M, sizeof m);
     proj(m, out);
+}
+/* components of -i log U (principal logarithm) */
+void orc_link_generator(const cplx *U, double *out)
+{
+    build_generators();
+    M3 m;
+    memcpy(&m, U, sizeof m);
+    link_generator(m, out);
 }
 /* exp(i scale x^a T^a) */
 void orc_expi(const double *x, double scale, cplx *out)

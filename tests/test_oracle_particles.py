@@ -83,7 +83,7 @@ def test_colour_rotation_known_links():
         P[0, 6:14] = Q
         P[0, 14], P[0, 15] = x_prev, y_prev
         P[0, 17] = 1.0
-        err = oracle.lib().orc_particles_step(N, 4, 1, dt, 1e9, 0, oracle._ptr(st["U"]), oracle._ptr(z1),
+        err = oracle.lib().orc_particles_step(N, 4, 1, dt, 1e9, 0, 0, oracle._ptr(st["U"]), oracle._ptr(z1),
                                               oracle._ptr(z2), oracle._ptr(z2), oracle._ptr(z1), oracle._ptr(z1),
                                               1, oracle._ptr(P))
         assert err == 0
@@ -102,7 +102,7 @@ def test_colour_rotation_known_links():
     assert np.allclose(one(1, 1, 2.1, 1.9), comps(W.conj().T @ Qm @ W, T), atol=1e-13)
     # a jump of two cells is reported
     P = np.zeros((1, 20)); P[0, 0] = 4.0; P[0, 14] = 2; P[0, 17] = 1
-    assert oracle.lib().orc_particles_step(N, 4, 1, dt, 1.0, 0, oracle._ptr(st["U"]), oracle._ptr(z1),
+    assert oracle.lib().orc_particles_step(N, 4, 1, dt, 1.0, 0, 0, oracle._ptr(st["U"]), oracle._ptr(z1),
                                            oracle._ptr(z2), oracle._ptr(z2), oracle._ptr(z1), oracle._ptr(z1),
                                            1, oracle._ptr(P)) == 1
 
@@ -135,7 +135,7 @@ def test_magnetic_force_does_no_work():
     P = oracle.particles_init(N, 50, 5, 0.4, 0.4, True, 0)
     for step in range(40):
         before = P.copy()
-        oracle.lib().orc_particles_step(N, n + step, n, dt, 0.3, 0, oracle._ptr(st["U"]), oracle._ptr(z1),
+        oracle.lib().orc_particles_step(N, n + step, n, dt, 0.3, 0, 0, oracle._ptr(st["U"]), oracle._ptr(z1),
                                         oracle._ptr(z2), oracle._ptr(z2), oracle._ptr(z1), oracle._ptr(z1),
                                         P.shape[0], oracle._ptr(P))
         b = before[:, 8] * 2 * math.sin(theta / 2)           # Q^3 is unchanged by diagonal links

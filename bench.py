@@ -53,9 +53,9 @@ def glasma_512(precision, N=512, L=6.0, seed=3):
                 tau_max_fm=1.5, seed=seed, precision=precision, reunit_every=16, record_every=8)
 
 
-def charm(n=100_000, seed=4):
+def charm(n=100_000, seed=4, color_update=0):
     return dict(n=n, mass_GeV=1.27, pT_min_GeV=0.0, pT_max_GeV=0.0, azimuth_uniform=1, tau_form_fm=0.1, rep=0,
-                seed=seed)
+                seed=seed, color_update=color_update)
 
 
 def jet_quarks(n=1_000_000, seed=4):
@@ -215,6 +215,25 @@ def run_jets(steps, warmup, V, tune=True):
                                 "anisotropy_z_over_y": float(lj[3] / lj[2])}}
 
 
+def run_color_log(steps, warmup, V, ref):
+    """The headline event with the alternative colour update of Sec. III.B
+    (charges stepped by dQ/dt = i[Q, A.v] with A from the matrix logarithm of
+    the links) over the same timed region; its broadening next to the
+    rotation's."""
+    import paper_2303_05599_amd as cp
+    n_part = 100_000
+    r = run_event(cp.FP64, steps, warmup, True, charm(n_part, color_update=cp.COLOR_LOG))
+    k = rooflines(r, "fp64", n_part, V)
+    k["push"]["kernel"] = k["push"]["kernel"].replace(", false>", ", true>")
+    return {"workload": "the headline event (FP64) with the charges updated from the matrix logarithm of the links",
+            "ms_per_step": r["wall"] * 1e3 / steps,
+            "pushes_per_s": n_part * steps / r["wall"],
+            "push_kernel": k["push"], "launch": r["launch"],
+            "dpT2_rel_vs_rotation": float(r["obs"][-1, 1] / ref["obs"][-1, 1] - 1),
+            "dpL2_rel_vs_rotation": float(r["obs"][-1, 2] / ref["obs"][-1, 2] - 1),
+            "casimir_q2_max_drift": float(r["diag"][8])}
+
+
 def cpu_baseline(n_steps=6, n_part=100_000):
     """The oracle on the host cores: 512^2 MV event (one colour sheet; the
     initial condition is not timed), n_steps leapfrog steps with the push of
@@ -273,7 +292,7 @@ def kernel_names(launch, precision):
         field = "field_link_kernel" + ("" if launch["waves"] == 1 else f"_w{launch['waves']}") + f"<{t}, true>"
     else:
         field = "field_step_kernel" + ("" if launch["waves"] == 1 else f"_w{launch['waves']}") + f"<{t}, true>"
-    return field, f"push_kernel<{t}, {launch['push_lanes']}>", f"jet_kernel<{t}>"
+    return field, f"push_kernel<{t}, {launch['push_lanes']}, false>", f"jet_kernel<{t}>"
 
 
 def rooflines(res, precision, n_part, V):
@@ -485,6 +504,7 @@ def main():
                        "dpT2_rel_vs_fp64": float(abs(r32["obs"][-1, 1] / res["obs"][-1, 1] - 1)),
                        "dpL2_rel_vs_fp64": float(abs(r32["obs"][-1, 2] / res["obs"][-1, 2] - 1))}
         out["jets"] = run_jets(args.steps, args.warmup, V)
+        out["color_log"] = run_color_log(args.steps, args.warmup, V, res)
         out["batch"] = run_batch(res["launch"])
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()

@@ -96,7 +96,19 @@ typedef struct {
  *   tau_form_fm      formation time; the push starts at n_form = ceil(tau_form/dtau)
  *   rep              CPIC_REP_FUND (q2 = 4, q3 = 10/3) or CPIC_REP_ADJ (q2 = 24, q3 = 0)
  *   seed             seed of the particle stream
+ *   color_update     CPIC_COLOR_ROTATE (default): the charges are rotated with
+ *                    the links crossed and the rapidity Wilson line
+ *                    [eq:colorrotnum], which keeps their Casimirs exactly;
+ *                    CPIC_COLOR_LOG: the alternative of Sec. III.B, dQ/dtau =
+ *                    ig[Q, A_mu] p^mu/p^tau with the transverse gauge fields
+ *                    from the matrix logarithm of the links (a A_i = -i log U_i
+ *                    on the link whose midpoint is nearest), stepped by
+ *                    explicit Euler with the rest of the particle (the Casimirs
+ *                    then drift at first order in dtau; no renormalisation).
+ *                    Single events only (cpic_batch_create rejects it).
  */
+#define CPIC_COLOR_ROTATE 0
+#define CPIC_COLOR_LOG 1
 typedef struct {
     int64_t n;
     double mass_GeV;
@@ -106,6 +118,7 @@ typedef struct {
     double tau_form_fm;
     int32_t rep;
     uint64_t seed;
+    int32_t color_update;
 } cpic_particle_params;
 
 /* Create a context: validates the parameters and allocates the ping-pong

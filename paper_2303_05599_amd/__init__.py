@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libcpic.so")
 
 FP64, FP32 = 0, 1
 REP_FUND, REP_ADJ = 0, 1
+COLOR_ROTATE, COLOR_LOG = 0, 1
 STATE_U, STATE_PHI, STATE_E, STATE_PI, STATE_PARTICLES, STATE_STEP, STATE_JET_W, STATE_JET_F = range(8)
 ERRORS = {-1: "INVALID", -2: "NOMEM", -3: "HIP", -4: "IC_NEWTON", -5: "NAN", -6: "DRIFT", -7: "CAPACITY",
           -8: "CELL_JUMP", -9: "IO"}
@@ -34,7 +35,8 @@ class GlasmaParams(ctypes.Structure):
 class ParticleParams(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("mass_GeV", ctypes.c_double), ("pT_min_GeV", ctypes.c_double),
                 ("pT_max_GeV", ctypes.c_double), ("azimuth_uniform", ctypes.c_int32),
-                ("tau_form_fm", ctypes.c_double), ("rep", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("tau_form_fm", ctypes.c_double), ("rep", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("color_update", ctypes.c_int32)]
 
 
 class JetParams(ctypes.Structure):
@@ -45,7 +47,7 @@ class JetParams(ctypes.Structure):
 GLASMA_DEFAULTS = dict(N=32, L_fm=6.0, g2mu_GeV=2.0, m_ir_GeV=0.2, uv_GeV=10.0, n_sheets=1, dtau_over_a=0.125,
                        tau_max_fm=1.0, seed=1, precision=FP64, reunit_every=16, record_every=8)
 PARTICLE_DEFAULTS = dict(n=0, mass_GeV=math.inf, pT_min_GeV=0.0, pT_max_GeV=0.0, azimuth_uniform=1,
-                         tau_form_fm=0.0, rep=REP_FUND, seed=2)
+                         tau_form_fm=0.0, rep=REP_FUND, seed=2, color_update=COLOR_ROTATE)
 
 
 class CpicError(RuntimeError):

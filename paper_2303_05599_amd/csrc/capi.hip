@@ -116,7 +116,8 @@ extern "C" cpic_status cpic_create(const cpic_glasma_params* gp, const cpic_part
     if (!pp) pp = &none;
     if (pp->n < 0 || pp->n > (int64_t)1 << 30) return fail(nullptr, CPIC_E_INVALID, "cpic_create: bad particle count");
     if (pp->n > 0 && (!(pp->mass_GeV > 0) || pp->pT_min_GeV < 0 || pp->pT_max_GeV < pp->pT_min_GeV ||
-                      pp->tau_form_fm < 0 || (pp->rep != CPIC_REP_FUND && pp->rep != CPIC_REP_ADJ)))
+                      pp->tau_form_fm < 0 || (pp->rep != CPIC_REP_FUND && pp->rep != CPIC_REP_ADJ) ||
+                      (pp->color_update != CPIC_COLOR_ROTATE && pp->color_update != CPIC_COLOR_LOG)))
         return fail(nullptr, CPIC_E_INVALID, "cpic_create: bad particle parameters");
 
     {
@@ -350,6 +351,7 @@ PushArgs cpic::push_args(const cpic_ctx* c, int tpp)
     pa.np = (int)c->np;
     pa.is_static = c->is_static;
     pa.tpp = tpp;
+    pa.color_log = !c->is_static && c->pp.color_update == CPIC_COLOR_LOG;
     pa.mhat = c->mhat;
     for (int k = 0; k < 3; k++) pa.q0eig[k] = c->q0eig[k];
     pa.sc = c->sc;

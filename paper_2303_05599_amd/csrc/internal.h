@@ -74,6 +74,7 @@ struct LaunchCfg {
 struct PushArgs {
     int N, np, is_static;
     int tpp;          // wavefronts per particle group (1, 2, 4)
+    int color_log;    // 1: colour update from the matrix logarithm of the links instead of the rotation
     double mhat;
     double q0eig[3];  // sorted eigenvalues of Q0 (charge renormalisation)
     Schedule sc;

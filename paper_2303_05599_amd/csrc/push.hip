@@ -136,7 +136,16 @@ template <int TPP> constexpr int kPushPPB = 256 / TPP;  // particles per block
 // Observables: on recording steps the owner wave of each group of 64 writes
 // the group's four double-precision sums to partials[slot][group][4]; they
 // are added over the groups, in group order, when the samples are read.
-template <typename T, int TPP>
+//
+// LOGQ selects the alternative colour update of Sec. III.B instead of the
+// rotation with the links: dQ/dt = i[Q, A_x v_x + A_y v_y + phi v_eta], with
+// the gauge fields from the matrix logarithm of the links (A_x on the x link
+// whose midpoint is nearest to the particle, (floor(x), NGP row); A_y on
+// (NGP column, floor(y)); phi at the grid point; all at t_n), stepped by
+// explicit Euler with the state at n like the rest of the particle.  The
+// charges are then not renormalised (their Casimir drift is part of the
+// method).
+template <typename T, int TPP, bool LOGQ>
 __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& Bf, const T* aux, const Parts<T>& P,
                                           const PushArgs& a, int n, double* partials, int* err, int blk)
 {
@@ -180,7 +189,7 @@ __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& 
     if (role == 0) {
 #pragma unroll
         for (int q = 0; q < 8; q++) Q.v[q] = bld(R, po, PQ0 + q);
-        if (!a.is_static && live && n > a.sc.n_form) {
+        if (!LOGQ && !a.is_static && live && n > a.sc.n_form) {
             int cx = bld_i(C, pi, 0), cy = bld_i(C, pi, 1);
             int d[2] = {nx - cx, ny - cy};
 #pragma unroll
@@ -204,7 +213,7 @@ __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& 
         // charges are renormalised in single precision only (double-precision
         // contexts never schedule it); leaving it out of the double kernel
         // also keeps its trigonometric calls from needing scratch memory
-        if constexpr (sizeof(T) == 4)
+        if constexpr (sizeof(T) == 4 && !LOGQ)
             if (!a.is_static && renorm && live) Q = renorm_charge(Q, a.q0eig);
         CPIC_PHASE();
         if (live) {
@@ -270,6 +279,22 @@ __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& 
             const T npx = px + dt * (e1 + be * v2 - b2 * vl);
             const T npy = py + dt * (e2 - be * v1 + b1 * vl);
             const T npe = n > 0 ? pe + dt * (ee - b1 * v2 + b2 * v1 - T(2) * pe) / t : pe;
+            if constexpr (LOGQ) {
+                // Q_{n+1} = Q_n + dt i[Q_n, M_n]
+                CPIC_PHASE();
+                const int lx = min((int)floor(x), N - 1), ly = min((int)floor(y), N - 1);
+                constexpr T tol = sizeof(T) == 8 ? T(1e-15) : T(1e-7);
+                const a8<T> gx = link_generator(vU(A, (uint32_t)(ny * N + lx) * (uint32_t)sizeof(T), 0), tol, 50);
+                const a8<T> gy = link_generator(vU(A, (uint32_t)(ly * N + nx) * (uint32_t)sizeof(T), 1), tol, 50);
+                const a8<T> ph = vA(A, cell.s, kCompPhi);
+                const T veta = pe / ptau;
+                a8<T> M;
+#pragma unroll
+                for (int c = 0; c < 8; c++) M.v[c] = v1 * gx.v[c] + v2 * gy.v[c] + veta * ph.v[c];
+                const a8<T> dq = icomm(Q, M);
+#pragma unroll
+                for (int c = 0; c < 8; c++) Q.v[c] += dt * dq.v[c];
+            }
             T xn = x + dt * v1, yn = y + dt * v2;
             if (xn >= T(N)) xn -= T(N); else if (xn < T(0)) xn += T(N);
             if (yn >= T(N)) yn -= T(N); else if (yn < T(0)) yn += T(N);
@@ -280,7 +305,7 @@ __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& 
             bst(R, po, PPX, px); bst(R, po, PPY, py); bst(R, po, PPETA, pe); bst(R, po, PDETA, deta);
             bst_i(C, pi, 0, nx);
             bst_i(C, pi, 1, ny);
-            if (n > a.sc.n_form || renorm) {
+            if (LOGQ || n > a.sc.n_form || renorm) {
 #pragma unroll
                 for (int q = 0; q < 8; q++) bst(R, po, PQ0 + q, Q.v[q]);
             }
@@ -326,7 +351,7 @@ __device__ __forceinline__ int push_step(int* d_step, int blk)
     return n;
 }
 
-template <typename T, int TPP>
+template <typename T, int TPP, bool LOGQ = false>
 __global__ __launch_bounds__(256) void push_kernel(Fields<T> Af, Fields<T> Bf, const T* aux, Parts<T> P, PushArgs a,
                                                    int* d_step, double* partials, int* err)
 {
@@ -334,7 +359,7 @@ __global__ __launch_bounds__(256) void push_kernel(Fields<T> Af, Fields<T> Bf, c
     const int blk = xcd_block(nblocks);
     if (blk >= nblocks) return;
     const int n = push_step(d_step, blk);
-    push_body<T, TPP>(Af, Bf, aux, P, a, n, partials, err, blk);
+    push_body<T, TPP, LOGQ>(Af, Bf, aux, P, a, n, partials, err, blk);
 }
 
 // batched events: logical block g works on particle block map[g].y of event map[g].x
@@ -352,7 +377,7 @@ __global__ __launch_bounds__(256) void batch_push_kernel(const EventDesc* __rest
     const int n = __builtin_amdgcn_readfirstlane(push_step(d.d_step, blk));
     if (d.pa.np == 0) return;  // an event without particles only advances its step
     const int V = d.N * d.N, parity = (n & 1) ^ d.flip;
-    push_body<T, TPP>(fields_at<T>(d.f[parity], V), fields_at<T>(d.f[parity ^ 1], V), static_cast<const T*>(d.aux),
+    push_body<T, TPP, false>(fields_at<T>(d.f[parity], V), fields_at<T>(d.f[parity ^ 1], V), static_cast<const T*>(d.aux),
                       Parts<T>{static_cast<T*>(d.pr), d.cell}, d.pa, n, d.partials, d.d_err, blk);
 }
 
@@ -381,6 +406,14 @@ hipError_t launch_push(const Fields<T>& A, const Fields<T>& B, const T* aux, con
     if (!aux) return hipErrorInvalidValue;
     const int nb = push_blocks(a.np, a.tpp);
     const dim3 g(8 * ((nb + 7) / 8)), b(256);
+    if (a.color_log) {
+        switch (a.tpp) {
+        case 2: klaunch(tm, push_kernel<T, 2, true>, g, b, st, A, B, aux, P, a, d_step, partials, err); break;
+        case 4: klaunch(tm, push_kernel<T, 4, true>, g, b, st, A, B, aux, P, a, d_step, partials, err); break;
+        default: klaunch(tm, push_kernel<T, 1, true>, g, b, st, A, B, aux, P, a, d_step, partials, err);
+        }
+        return hipGetLastError();
+    }
     switch (a.tpp) {
     case 2: klaunch(tm, push_kernel<T, 2>, g, b, st, A, B, aux, P, a, d_step, partials, err); break;
     case 4: klaunch(tm, push_kernel<T, 4>, g, b, st, A, B, aux, P, a, d_step, partials, err); break;

@@ -329,6 +329,30 @@ template <typename T> CPIC_HD m3<T> expi(const a8<T>& x, T eps)
     return R;
 }
 
+// Generator of a link: the traceless Hermitian X with exp(iX) = U up to a
+// centre element (the traceless part of -i log U, principal branch), found
+// by the fixed-point iteration X <- X + Proj[exp(-iX/2) U exp(-iX/2)] from
+// X = Proj[U].  For commuting X and U the error e (per eigenphase) maps to
+// e - sin e, so the iteration converges cubically from any eigenphase in
+// (-pi, pi); the symmetric splitting keeps the leading commutator out of
+// the correction.  Stops when the correction is below tol or after maxit.
+template <typename T> CPIC_HD a8<T> link_generator(const m3<T>& U, T tol, int maxit)
+{
+    a8<T> X = proj(U);
+    for (int k = 0; k < maxit; k++) {
+        const m3<T> H = expi(X, T(-0.5));
+        const a8<T> D = proj(mul(mul(H, U), H));
+        T m = 0;
+#pragma unroll
+        for (int a = 0; a < 8; a++) {
+            X.v[a] += D.v[a];
+            m = fmax(m, fabs(D.v[a]));
+        }
+        if (m <= tol) break;
+    }
+    return X;
+}
+
 // nearest-SU(3) style projection used to remove rounding drift: Gram-Schmidt
 // on rows 1 and 2, row 3 = conj(r1 x r2) (unit determinant by construction)
 template <typename T> CPIC_HD m3<T> reunitarize(const m3<T>& W)

@@ -23,6 +23,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcpic_oracle.so")
 SRC_PATH = os.path.join(HERE, "cpic_oracle.c")
+SRC_PATHS = [SRC_PATH, os.path.join(HERE, "cpic_oracle_su2.c")]
 HBARC_GEV_FM = 0.1973269804
 NCOL = 20  # particle record columns (see COLUMNS)
 COLUMNS = ["x", "y", "eta", "px", "py", "peta"] + [f"Q{a}" for a in range(1, 9)] + [
@@ -31,10 +32,11 @@ COLUMNS = ["x", "y", "eta", "px", "py", "peta"] + [f"Q{a}" for a in range(1, 9)]
 
 def build(force: bool = False) -> str:
     """Compile the oracle's C part (gcc, -O2, OpenMP, IEEE double)."""
-    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
+    newest = max(os.path.getmtime(p) for p in SRC_PATHS)
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < newest:
         tmp = LIB_PATH + f".tmp{os.getpid()}"
         subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared",
-                               "-o", tmp, SRC_PATH, "-lm"])
+                               "-o", tmp, *SRC_PATHS, "-lm"])
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
 

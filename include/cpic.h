@@ -69,6 +69,12 @@ typedef struct cpic_batch cpic_batch;
  *                colour charges every that many steps (0 = never)
  *   record_every steps between broadening samples (a sample is also taken
  *                after the last step)
+ *   n_colors     gauge group SU(n_colors): 3 (or 0, the default) or 2.  The
+ *                SU(2) variant (links as unit quaternions, three colour
+ *                components, charges from the Darboux parametrisation of
+ *                Sec. IV.A) runs single events with the rotation colour update;
+ *                light-like paths, the matrix-logarithm update, batches and
+ *                the launch tuner are SU(3) only.
  */
 typedef struct {
     int32_t N;
@@ -83,6 +89,7 @@ typedef struct {
     int32_t precision;
     int32_t reunit_every;
     int32_t record_every;
+    int32_t n_colors;
 } cpic_glasma_params;
 
 /*
@@ -94,7 +101,8 @@ typedef struct {
  *   pT_min/max_GeV   initial |p_T| uniform in [min, max) (equal: fixed)
  *   azimuth_uniform  1: direction of p_T uniform; 0: along +x (the jets of Sec. VII.D)
  *   tau_form_fm      formation time; the push starts at n_form = ceil(tau_form/dtau)
- *   rep              CPIC_REP_FUND (q2 = 4, q3 = 10/3) or CPIC_REP_ADJ (q2 = 24, q3 = 0)
+ *   rep              CPIC_REP_FUND (q2 = 4, q3 = 10/3) or CPIC_REP_ADJ (q2 = 24, q3 = 0);
+ *                    SU(2): q2 = 3/2 or 6, q3 = 0 ([eq:q23c23])
  *   seed             seed of the particle stream
  *   color_update     CPIC_COLOR_ROTATE (default): the charges are rotated with
  *                    the links crossed and the rapidity Wilson line
@@ -192,6 +200,8 @@ cpic_status cpic_diagnostics(cpic_ctx* ctx, double out[10]);
  *   CPIC_STATE_PHI       float64 [N][N][8]           phi = g A_eta components
  *   CPIC_STATE_E         float64 [2][N][N][8]        E_i = g a P^i at n - 1/2
  *   CPIC_STATE_PI        float64 [N][N][8]           pi = g a^2 P^eta at n - 1/2
+ *                        (SU(2): [3][3] -> [2][2] and 8 -> 3 components; the
+ *                        particle records keep 20 columns, Q^4..Q^8 zero)
  *   CPIC_STATE_PARTICLES float64 [n][20]             x, y, eta, p^x, p^y, p^eta
  *                        (p^z for the static branch), Q^1..Q^8, cell x, cell y,
  *                        last eta increment, initial direction (ux, uy), |p_T(form)|

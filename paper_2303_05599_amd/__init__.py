@@ -29,7 +29,8 @@ class GlasmaParams(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int32), ("L_fm", ctypes.c_double), ("g2mu_GeV", ctypes.c_double),
                 ("m_ir_GeV", ctypes.c_double), ("uv_GeV", ctypes.c_double), ("n_sheets", ctypes.c_int32),
                 ("dtau_over_a", ctypes.c_double), ("tau_max_fm", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("precision", ctypes.c_int32), ("reunit_every", ctypes.c_int32), ("record_every", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("reunit_every", ctypes.c_int32), ("record_every", ctypes.c_int32),
+                ("n_colors", ctypes.c_int32)]
 
 
 class ParticleParams(ctypes.Structure):
@@ -45,7 +46,7 @@ class JetParams(ctypes.Structure):
 
 
 GLASMA_DEFAULTS = dict(N=32, L_fm=6.0, g2mu_GeV=2.0, m_ir_GeV=0.2, uv_GeV=10.0, n_sheets=1, dtau_over_a=0.125,
-                       tau_max_fm=1.0, seed=1, precision=FP64, reunit_every=16, record_every=8)
+                       tau_max_fm=1.0, seed=1, precision=FP64, reunit_every=16, record_every=8, n_colors=3)
 PARTICLE_DEFAULTS = dict(n=0, mass_GeV=math.inf, pT_min_GeV=0.0, pT_max_GeV=0.0, azimuth_uniform=1,
                          tau_form_fm=0.0, rep=REP_FUND, seed=2, color_update=COLOR_ROTATE)
 
@@ -197,6 +198,9 @@ class Context:
 
     def _shape(self, which):
         N = self.N
+        if self.gp.n_colors == 2:
+            return {STATE_U: (2, N, N, 2, 2), STATE_PHI: (N, N, 3), STATE_E: (2, N, N, 3), STATE_PI: (N, N, 3),
+                    STATE_PARTICLES: (self.np, 20), STATE_STEP: (1,)}[which]
         return {STATE_U: (2, N, N, 3, 3), STATE_PHI: (N, N, 8), STATE_E: (2, N, N, 8), STATE_PI: (N, N, 8),
                 STATE_PARTICLES: (self.np, 20), STATE_STEP: (1,), STATE_JET_W: (N, N, 3, 3),
                 STATE_JET_F: (N, N, 3, 8)}[which]

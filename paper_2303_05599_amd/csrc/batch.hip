@@ -228,6 +228,9 @@ extern "C" cpic_status cpic_batch_create(int32_t n_events, const cpic_glasma_par
     for (int e = 1; e < n_events; e++)
         if (gp[e].precision != gp[0].precision)
             return bfail(nullptr, CPIC_E_INVALID, "cpic_batch_create: all events must share one precision");
+    for (int e = 0; e < n_events; e++)
+        if (gp[e].n_colors == 2)
+            return bfail(nullptr, CPIC_E_INVALID, "cpic_batch_create: batches hold SU(3) events only");
     for (int e = 0; pp && e < n_events; e++)
         if (pp[e].n > 0 && pp[e].color_update != CPIC_COLOR_ROTATE)
             return bfail(nullptr, CPIC_E_INVALID,

@@ -75,6 +75,7 @@ cpic_status cpic::hip_fail(cpic_ctx* c, hipError_t e, const char* where)
     } while (0)
 
 template <typename T> static Fields<T> F(cpic_ctx* c, int b) { return fields_at<T>(c->fbuf[b], c->V); }
+template <typename T> static Fields2<T> F2(cpic_ctx* c, int b) { return fields2_at<T>(c->fbuf[b], c->V); }
 template <typename T> static Parts<T> P(cpic_ctx* c) { return {static_cast<T*>(c->pr), c->pcell}; }
 
 static bool valid_N(int N)
@@ -112,8 +113,12 @@ extern "C" cpic_status cpic_create(const cpic_glasma_params* gp, const cpic_part
         return fail(nullptr, CPIC_E_INVALID, "cpic_create: L, dtau, tau_max, n_sheets must be positive");
     if (gp->precision != CPIC_FP64 && gp->precision != CPIC_FP32)
         return fail(nullptr, CPIC_E_INVALID, "cpic_create: precision must be CPIC_FP64 or CPIC_FP32");
+    if (gp->n_colors != 0 && gp->n_colors != 2 && gp->n_colors != 3)
+        return fail(nullptr, CPIC_E_INVALID, "cpic_create: n_colors must be 2 or 3 (0: 3)");
     cpic_particle_params none{};
     if (!pp) pp = &none;
+    if (gp->n_colors == 2 && pp->n > 0 && pp->color_update != CPIC_COLOR_ROTATE)
+        return fail(nullptr, CPIC_E_INVALID, "cpic_create: the SU(2) variant rotates the charges with the links");
     if (pp->n < 0 || pp->n > (int64_t)1 << 30) return fail(nullptr, CPIC_E_INVALID, "cpic_create: bad particle count");
     if (pp->n > 0 && (!(pp->mass_GeV > 0) || pp->pT_min_GeV < 0 || pp->pT_max_GeV < pp->pT_min_GeV ||
                       pp->tau_form_fm < 0 || (pp->rep != CPIC_REP_FUND && pp->rep != CPIC_REP_ADJ) ||
@@ -133,6 +138,8 @@ extern "C" cpic_status cpic_create(const cpic_glasma_params* gp, const cpic_part
     c->V = gp->N * gp->N;
     c->prec = gp->precision;
     c->tsz = c->prec == CPIC_FP64 ? 8 : 4;
+    c->nc = gp->n_colors == 2 ? 2 : 3;
+    c->rps = c->nc == 2 ? kRealsPerSite2 : kRealsPerSite;
     c->a_fm = gp->L_fm / gp->N;
     c->a_gev = c->a_fm / kHbarC;
     const double dtau_fm = gp->dtau_over_a * c->a_fm;
@@ -152,6 +159,10 @@ extern "C" cpic_status cpic_create(const cpic_glasma_params* gp, const cpic_part
     c->sc.record_every = gp->record_every > 0 ? gp->record_every : (1 << 30);
     c->sc.reunit_every = c->prec == CPIC_FP32 ? std::max(0, gp->reunit_every) : 0;
     initial_colour(pp->rep, c->q0, c->q0eig, &c->q2ref, &c->q3ref);
+    if (c->nc == 2) {  // [eq:q23c23] for N_c = 2: q2 = D_R C_2(R) = 3/2 (F), 6 (A); q3 = 0
+        c->q2ref = pp->rep == CPIC_REP_ADJ ? 6.0 : 1.5;
+        c->q3ref = 0;
+    }
 
     hipError_t e = hipSuccess;
     if (hip_stream) {
@@ -160,13 +171,13 @@ extern "C" cpic_status cpic_create(const cpic_glasma_params* gp, const cpic_part
         e = hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking);
         c->own_stream = e == hipSuccess;
     }
-    const size_t fbytes = (size_t)kRealsPerSite * c->V * c->tsz;
+    const size_t fbytes = (size_t)c->rps * c->V * c->tsz;
     for (int b = 0; b < 2 && e == hipSuccess; b++) e = hipMalloc(&c->fbuf[b], fbytes);
     if (e == hipSuccess && c->np > 0) {
         const size_t np = c->np;
         e = hipMalloc(&c->pr, (size_t)kPartReals * np * c->tsz);
         if (e == hipSuccess) e = hipMalloc(&c->pcell, sizeof(int) * 2 * np);
-        if (e == hipSuccess) e = hipMalloc(&c->aux, (size_t)kAuxReals * c->V * c->tsz);
+        if (e == hipSuccess && c->nc == 3) e = hipMalloc(&c->aux, (size_t)kAuxReals * c->V * c->tsz);
         if (e == hipSuccess) e = hipMalloc(&c->pid, sizeof(int) * np);
         if (e == hipSuccess) e = hipMalloc(&c->sb.keys, sizeof(unsigned) * np);
         if (e == hipSuccess) e = hipMalloc(&c->sb.keys2, sizeof(unsigned) * np);
@@ -180,7 +191,7 @@ extern "C" cpic_status cpic_create(const cpic_glasma_params* gp, const cpic_part
     }
     // few particles: several wavefronts share each particle group so that the
     // push still fills the 1024 SIMDs (tunable with cpic_tune)
-    c->tpp = c->np <= (1 << 18) ? 4 : (c->np <= (1 << 20) ? 2 : 1);
+    c->tpp = c->nc == 2 ? 1 : (c->np <= (1 << 18) ? 4 : (c->np <= (1 << 20) ? 2 : 1));
     // field update: compressed-link LDS tiles of 64 x 4 sites (the tuner's usual pick at 512^2)
     c->cfg.split = 3;
     c->cfg.bx = 64;
@@ -300,13 +311,14 @@ extern "C" cpic_status cpic_init_mv(cpic_ctx* c)
     void* dbl = c->fbuf[0];
     void* stage = nullptr;
     if (c->prec == CPIC_FP32) {
-        HIPCHK(c, hipMalloc(&stage, sizeof(double) * kRealsPerSite * c->V), "IC staging");
+        HIPCHK(c, hipMalloc(&stage, sizeof(double) * c->rps * c->V), "IC staging");
         dbl = stage;
     }
     HIPCHK(c, hipMemsetAsync(c->d_fails, 0, sizeof(int), c->st), "IC");
-    hipError_t e = ic_glasma(a, fields_at<double>(dbl, c->V), c->d_fails, c->st);
+    hipError_t e = c->nc == 2 ? ic_glasma2(a, fields2_at<double>(dbl, c->V), c->st)
+                              : ic_glasma(a, fields_at<double>(dbl, c->V), c->d_fails, c->st);
     if (e == hipSuccess && c->prec == CPIC_FP32)
-        e = convert_to_float((const double*)stage, (float*)c->fbuf[0], (size_t)kRealsPerSite * c->V, c->st);
+        e = convert_to_float((const double*)stage, (float*)c->fbuf[0], (size_t)c->rps * c->V, c->st);
     if (e == hipSuccess && c->np > 0) {
         PartICArgs pa{};
         pa.N = c->N;
@@ -322,7 +334,8 @@ extern "C" cpic_status cpic_init_mv(cpic_ctx* c)
             e = hipMalloc(&pstage, sizeof(double) * kPartReals * c->np);
             pdst = (double*)pstage;
         }
-        if (e == hipSuccess) e = ic_particles(pa, pdst, c->pcell, c->st);
+        if (e == hipSuccess)
+            e = c->nc == 2 ? ic_particles2(pa, c->q2ref, pdst, c->pcell, c->st) : ic_particles(pa, pdst, c->pcell, c->st);
         if (e == hipSuccess && c->prec == CPIC_FP32)
             e = convert_to_float(pdst, (float*)c->pr, (size_t)kPartReals * c->np, c->st);
         if (e == hipSuccess) e = hipStreamSynchronize(c->st);
@@ -360,8 +373,32 @@ PushArgs cpic::push_args(const cpic_ctx* c, int tpp)
 
 // one step: field update (cur -> cur^1), push (advances the step counter),
 // light-like paths
+// SU(2) step: field update, push (or the step advance without particles)
+template <typename T> static cpic_status launch_one_su2(cpic_ctx* c, int parity, bool with_events)
+{
+    const Fields2<T> A = F2<T>(c, parity), B = F2<T>(c, parity ^ 1);
+    KTimer tf, tp;
+    if (with_events) {
+        HIPCHK(c, hipEventCreate(&tf.start), "event"); HIPCHK(c, hipEventCreate(&tf.stop), "event");
+        c->ev_field.push_back(tf.start); c->ev_field.push_back(tf.stop);
+    }
+    HIPCHK(c, launch_su2_field<T>(A, B, c->N, c->sc, c->d_step, c->st, tf), "SU(2) field step");
+    if (c->np > 0) {
+        if (with_events) {
+            HIPCHK(c, hipEventCreate(&tp.start), "event"); HIPCHK(c, hipEventCreate(&tp.stop), "event");
+            c->ev_push.push_back(tp.start); c->ev_push.push_back(tp.stop);
+        }
+        HIPCHK(c, launch_su2_push<T>(A, B, P<T>(c), push_args(c, 1), c->d_step, c->partials, c->d_err, c->st, tp),
+               "SU(2) push");
+    } else {
+        HIPCHK(c, launch_step_advance(c->d_step, c->st), "step advance");
+    }
+    return CPIC_OK;
+}
+
 template <typename T> static cpic_status launch_one(cpic_ctx* c, int parity, bool with_events)
 {
+    if (c->nc == 2) return launch_one_su2<T>(c, parity, with_events);
     const Fields<T> A = F<T>(c, parity), B = F<T>(c, parity ^ 1);
     KTimer tf, tp, tj;
     if (with_events) {
@@ -603,9 +640,15 @@ extern "C" cpic_status cpic_diagnostics(cpic_ctx* c, double out[10])
     if (!c || !out) return fail(c, CPIC_E_INVALID, "cpic_diagnostics: NULL argument");
     if (!c->initialised) return fail(c, CPIC_E_INVALID, "cpic_diagnostics: no state");
     int nb = 0;
-    hipError_t e = c->prec == CPIC_FP64
-                       ? launch_field_diag<double>(F<double>(c, c->cur), c->N, c->sc.dt, c->n, c->dpart, c->dcap, &nb, c->st)
-                       : launch_field_diag<float>(F<float>(c, c->cur), c->N, c->sc.dt, c->n, c->dpart, c->dcap, &nb, c->st);
+    hipError_t e;
+    if (c->nc == 2)
+        e = c->prec == CPIC_FP64
+                ? launch_su2_diag<double>(F2<double>(c, c->cur), c->N, c->sc.dt, c->n, c->dpart, c->dcap, &nb, c->st)
+                : launch_su2_diag<float>(F2<float>(c, c->cur), c->N, c->sc.dt, c->n, c->dpart, c->dcap, &nb, c->st);
+    else
+        e = c->prec == CPIC_FP64
+                ? launch_field_diag<double>(F<double>(c, c->cur), c->N, c->sc.dt, c->n, c->dpart, c->dcap, &nb, c->st)
+                : launch_field_diag<float>(F<float>(c, c->cur), c->N, c->sc.dt, c->n, c->dpart, c->dcap, &nb, c->st);
     HIPCHK(c, e, "field diagnostics");
     HIPCHK(c, launch_reduce_rows(c->dpart, nb, 8, c->dout, c->st), "reduce");
     double h[10] = {0};
@@ -626,12 +669,15 @@ extern "C" cpic_status cpic_diagnostics(cpic_ctx* c, double out[10])
 }
 
 // ------------------------------------------------------------------ state exchange
+// algebra components and complex link entries per site and direction
+static int ncomp(const cpic_ctx* c) { return c->nc == 2 ? 3 : 8; }
+static int nlink(const cpic_ctx* c) { return c->nc == 2 ? 4 : 9; }
 static size_t state_bytes(const cpic_ctx* c, int which)
 {
     switch (which) {
-    case CPIC_STATE_U: return sizeof(double) * 36 * (size_t)c->V;
-    case CPIC_STATE_PHI: case CPIC_STATE_PI: return sizeof(double) * 8 * (size_t)c->V;
-    case CPIC_STATE_E: return sizeof(double) * 16 * (size_t)c->V;
+    case CPIC_STATE_U: return sizeof(double) * 2 * 2 * nlink(c) * (size_t)c->V;
+    case CPIC_STATE_PHI: case CPIC_STATE_PI: return sizeof(double) * ncomp(c) * (size_t)c->V;
+    case CPIC_STATE_E: return sizeof(double) * 2 * ncomp(c) * (size_t)c->V;
     case CPIC_STATE_PARTICLES: return sizeof(double) * 20 * (size_t)c->np;
     case CPIC_STATE_STEP: return sizeof(int64_t);
     case CPIC_STATE_JET_W: return c->jets ? sizeof(double) * 18 * (size_t)c->V : 0;
@@ -676,6 +722,56 @@ static size_t field_offset(int which, int V)
     default: return 60 * (size_t)V;  // PI
     }
 }
+// SU(2) buffer set: U [2][4][V] quaternions (w, a1, a2, a3) for
+// U = w + i a.sigma = [[w + i a3, a2 + i a1], [-a2 + i a1, w - i a3]];
+// phi [3][V], E [2][3][V], pi [3][V]
+static size_t field_offset2(int which, int V)
+{
+    switch (which) {
+    case CPIC_STATE_U: return 0;
+    case CPIC_STATE_PHI: return 8 * (size_t)V;
+    case CPIC_STATE_E: return 11 * (size_t)V;
+    default: return 17 * (size_t)V;
+    }
+}
+template <typename T> static void su2_to_host(const std::vector<T>& d, double* h, int which, int V)
+{
+    if (which == CPIC_STATE_U) {
+        for (int i = 0; i < 2; i++)
+            for (int s = 0; s < V; s++) {
+                const double w = d[((size_t)i * 4 + 0) * V + s], a1 = d[((size_t)i * 4 + 1) * V + s],
+                             a2 = d[((size_t)i * 4 + 2) * V + s], a3 = d[((size_t)i * 4 + 3) * V + s];
+                double* m = h + ((size_t)i * V + s) * 8;  // 2x2 complex, row-major, re/im
+                m[0] = w;   m[1] = a3;
+                m[2] = a2;  m[3] = a1;
+                m[4] = -a2; m[5] = a1;
+                m[6] = w;   m[7] = -a3;
+            }
+    } else {
+        const int blocks = which == CPIC_STATE_E ? 2 : 1;
+        for (int i = 0; i < blocks; i++)
+            for (int s = 0; s < V; s++)
+                for (int a = 0; a < 3; a++) h[((size_t)i * V + s) * 3 + a] = (double)d[((size_t)i * 3 + a) * V + s];
+    }
+}
+template <typename T> static void host_to_su2(const double* h, std::vector<T>& d, int which, int V)
+{
+    if (which == CPIC_STATE_U) {
+        for (int i = 0; i < 2; i++)
+            for (int s = 0; s < V; s++) {
+                const double* m = h + ((size_t)i * V + s) * 8;
+                d[((size_t)i * 4 + 0) * V + s] = (T)m[0];
+                d[((size_t)i * 4 + 1) * V + s] = (T)m[3];
+                d[((size_t)i * 4 + 2) * V + s] = (T)m[2];
+                d[((size_t)i * 4 + 3) * V + s] = (T)m[1];
+            }
+    } else {
+        const int blocks = which == CPIC_STATE_E ? 2 : 1;
+        for (int i = 0; i < blocks; i++)
+            for (int s = 0; s < V; s++)
+                for (int a = 0; a < 3; a++) d[((size_t)i * 3 + a) * V + s] = (T)h[((size_t)i * V + s) * 3 + a];
+    }
+}
 // interchange particle columns: x y eta px py peta Q1..Q8 cx cy deta ux0 uy0 pt0
 static const int kXchgToDev[20] = {PX_, PY_, PETA_, PPX, PPY, PPETA, PQ0, PQ0 + 1, PQ0 + 2, PQ0 + 3, PQ0 + 4,
                                    PQ0 + 5, PQ0 + 6, PQ0 + 7, -1, -2, PDETA, PUX0, PUY0, PPT0};
@@ -708,6 +804,14 @@ template <typename T> static cpic_status get_t(cpic_ctx* c, int which, double* h
         }
         return CPIC_OK;
     }
+    if (c->nc == 2) {
+        const size_t cnt = which == CPIC_STATE_U ? 8 : (which == CPIC_STATE_E ? 6 : 3);
+        std::vector<T> d(cnt * c->V);
+        const T* src = static_cast<const T*>(c->fbuf[c->cur]) + field_offset2(which, c->V);
+        HIPCHK(c, hipMemcpy(d.data(), src, sizeof(T) * d.size(), hipMemcpyDeviceToHost), "get state");
+        su2_to_host(d, h, which, c->V);
+        return CPIC_OK;
+    }
     const size_t cnt = which == CPIC_STATE_U ? 36 : (which == CPIC_STATE_E ? 16 : 8);
     std::vector<T> d(cnt * c->V);
     const T* src = static_cast<const T*>(c->fbuf[c->cur]) + field_offset(which, c->V);
@@ -730,6 +834,14 @@ template <typename T> static cpic_status set_t(cpic_ctx* c, int which, const dou
         HIPCHK(c, hipMemcpy(c->pr, r.data(), sizeof(T) * r.size(), hipMemcpyHostToDevice), "set particles");
         HIPCHK(c, hipMemcpy(c->pcell, cell.data(), sizeof(int) * cell.size(), hipMemcpyHostToDevice), "set particles");
         return reset_pid(c);
+    }
+    if (c->nc == 2) {
+        const size_t cnt = which == CPIC_STATE_U ? 8 : (which == CPIC_STATE_E ? 6 : 3);
+        std::vector<T> d(cnt * c->V);
+        host_to_su2(h, d, which, c->V);
+        T* dst = static_cast<T*>(c->fbuf[c->cur]) + field_offset2(which, c->V);
+        HIPCHK(c, hipMemcpy(dst, d.data(), sizeof(T) * d.size(), hipMemcpyHostToDevice), "set state");
+        return CPIC_OK;
     }
     const size_t cnt = which == CPIC_STATE_U ? 36 : (which == CPIC_STATE_E ? 16 : 8);
     std::vector<T> d(cnt * c->V);
@@ -809,7 +921,7 @@ extern "C" cpic_status cpic_save(cpic_ctx* c, const char* path)
     std::memcpy(h.magic, "CPICKPT1", 8);
     h.version = 1; h.N = c->N; h.prec = c->prec; h.n = c->n; h.nsamples = (int)c->samples.size();
     h.np = c->np; h.nslots = c->nslots; h.gp = c->gp; h.pp = c->pp; h.jets = c->jets;
-    const size_t fb = (size_t)kRealsPerSite * c->V * c->tsz, pb = (size_t)kPartReals * c->np * c->tsz;
+    const size_t fb = (size_t)c->rps * c->V * c->tsz, pb = (size_t)kPartReals * c->np * c->tsz;
     std::vector<char> f(fb), p(pb);
     std::vector<int> cell(2 * c->np), pid(c->np);
     std::vector<double> obs(4 * (size_t)c->nslots);
@@ -869,7 +981,8 @@ extern "C" cpic_status cpic_load(cpic_ctx* c, const char* path)
     CkptHeader h{};
     bool ok = std::fread(&h, sizeof h, 1, fp) == 1 && std::memcmp(h.magic, "CPICKPT1", 8) == 0 && h.version == 1;
     if (ok && (h.N != c->N || h.prec != c->prec || h.np != c->np || h.nslots != c->nslots || h.nsamples < 0 ||
-               h.nsamples > c->nslots || h.n < 0 || h.n > c->sc.n_max || (h.jets != 0) != c->jets)) {
+               h.nsamples > c->nslots || h.n < 0 || h.n > c->sc.n_max || (h.jets != 0) != c->jets ||
+               (h.gp.n_colors == 2 ? 2 : 3) != c->nc)) {
         std::fclose(fp);
         return fail(c, CPIC_E_INVALID, "cpic_load: checkpoint does not match this context");
     }
@@ -879,7 +992,7 @@ extern "C" cpic_status cpic_load(cpic_ctx* c, const char* path)
         ok = std::fread(v, sizeof v, 1, fp) == 1 && v[0] >= 0 && v[0] < c->nslots;
         samples.push_back({v[0], v[1]});
     }
-    const size_t fb = (size_t)kRealsPerSite * c->V * c->tsz, pb = (size_t)kPartReals * c->np * c->tsz;
+    const size_t fb = (size_t)c->rps * c->V * c->tsz, pb = (size_t)kPartReals * c->np * c->tsz;
     std::vector<char> f(fb), p(pb);
     std::vector<int> cell(2 * c->np), pid(c->np);
     std::vector<double> obs(4 * (size_t)c->nslots);
@@ -957,6 +1070,7 @@ extern "C" cpic_status cpic_set_launch(cpic_ctx* c, int32_t bx, int32_t by, int3
                                        int32_t variant)
 {
     if (!c) return fail(nullptr, CPIC_E_INVALID, "cpic_set_launch: NULL context");
+    if (c->nc == 2) return fail(c, CPIC_E_INVALID, "cpic_set_launch: the SU(2) variant has one launch shape");
     if (variant == 1) {
         if (bx <= 0 || by <= 0 || bx * by != 128 || bx % 32 != 0)
             return fail(c, CPIC_E_INVALID, "cpic_set_launch: link-parallel tiles hold 128 sites, bx a multiple of 32");
@@ -1112,8 +1226,12 @@ extern "C" cpic_status cpic_tune(cpic_ctx* c, int32_t reps, char* report, size_t
     if (c->timing) return fail(c, CPIC_E_INVALID, "cpic_tune: disable timing first");
     HIPCHK(c, hipStreamSynchronize(c->st), "tune");
     std::string rep;
-    cpic_status s = c->prec == CPIC_FP64 ? tune_t<double>(c, reps, rep) : tune_t<float>(c, reps, rep);
-    if (s) return s;
+    if (c->nc == 2) {
+        rep = "SU(2): one launch shape (256 sites or particles per workgroup); nothing to tune\n";
+    } else {
+        cpic_status s = c->prec == CPIC_FP64 ? tune_t<double>(c, reps, rep) : tune_t<float>(c, reps, rep);
+        if (s) return s;
+    }
     if (report && cap) {
         std::strncpy(report, rep.c_str(), cap - 1);
         report[cap - 1] = 0;
@@ -1133,6 +1251,7 @@ extern "C" cpic_status cpic_set_push_lanes(cpic_ctx* c, int32_t lanes)
 {
     if (!c) return fail(nullptr, CPIC_E_INVALID, "cpic_set_push_lanes: NULL context");
     if (lanes != 1 && lanes != 2 && lanes != 4) return fail(c, CPIC_E_INVALID, "cpic_set_push_lanes: 1, 2 or 4");
+    if (c->nc == 2 && lanes != 1) return fail(c, CPIC_E_INVALID, "cpic_set_push_lanes: the SU(2) push takes 1");
     HIPCHK(c, hipStreamSynchronize(c->st), "set push lanes");
     c->tpp = lanes;
     c->pblocks = c->np > 0 ? push_blocks((int)c->np, lanes) : 0;
@@ -1145,6 +1264,7 @@ extern "C" cpic_status cpic_jets_enable(cpic_ctx* c, const cpic_jet_params* jp)
 {
     if (!c || !jp) return fail(c, CPIC_E_INVALID, "cpic_jets_enable: NULL argument");
     if (c->jets) return fail(c, CPIC_E_INVALID, "cpic_jets_enable: already enabled");
+    if (c->nc == 2) return fail(c, CPIC_E_INVALID, "cpic_jets_enable: SU(3) only");
     if (!(jp->x_offset >= 0 && jp->x_offset < 1) || jp->stride < 1 || !(jp->tau_form_fm >= 0) ||
         (jp->rep != CPIC_REP_FUND && jp->rep != CPIC_REP_ADJ))
         return fail(c, CPIC_E_INVALID, "cpic_jets_enable: need 0 <= x_offset < 1, stride >= 1, tau_form >= 0, a valid rep");

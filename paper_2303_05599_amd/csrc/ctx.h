@@ -20,6 +20,8 @@ struct cpic_ctx {
     hipStream_t st = nullptr;
     bool own_stream = false;
     int N = 0, V = 0, prec = 0;
+    int nc = 3;     // SU(N_c): 3, or 2 for the SU(2) variant
+    int rps = 68;   // reals per site of a field buffer set (68 for SU(3), 20 for SU(2))
     size_t tsz = 8;
     double a_fm = 0, a_gev = 0;
     cpic::Schedule sc{};

@@ -14,6 +14,7 @@
 
 #include "internal.h"
 #include "philox.h"
+#include "su2.h"
 #include "su3.h"
 
 namespace cpic {
@@ -21,21 +22,25 @@ namespace cpic {
 using d2 = double2;
 
 // ------------------------------------------------------------------ charges
-// out[(sheet*4 + pair)*V + s] = (rho^{2 pair}, rho^{2 pair + 1}) for the sheet
-// index sheet0 + sheet of nucleus `nucleus`; stream key (seed, 1 + nucleus),
-// counter (s, sheet, block, 0), block b holding colours 4b .. 4b+3.
-__global__ void charges_kernel(d2* out, int V, uint64_t seed, int nucleus, int sheet0, double sigma)
+// out[(sheet*pairs + pair)*V + s] = (rho^{2 pair}, rho^{2 pair + 1}) for the
+// sheet index sheet0 + sheet of nucleus `nucleus`; stream key (seed,
+// 1 + nucleus), counter (s, sheet, block, 0), block b holding colours
+// 4b .. 4b+3.  pairs = 4 for SU(3) (colours 0..7), 2 for SU(2) (colours 0..2
+// and an unused fourth).
+__global__ void charges_kernel(d2* out, int V, uint64_t seed, int nucleus, int sheet0, double sigma, int pairs)
 {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     const int sh = blockIdx.y;
     if (s >= V) return;
     double z[8];
     for (int b = 0; b < 2; b++) {
+        if (2 * b >= pairs) break;
         const u64x4 r = philox4x64((uint64_t)s, (uint64_t)(sheet0 + sh), (uint64_t)b, 0, seed, 1 + (uint64_t)nucleus);
         box_muller(r.v[0], r.v[1], z[4 * b], z[4 * b + 1]);
         box_muller(r.v[2], r.v[3], z[4 * b + 2], z[4 * b + 3]);
     }
-    for (int p = 0; p < 4; p++) out[((size_t)sh * 4 + p) * V + s] = make_double2(sigma * z[2 * p], sigma * z[2 * p + 1]);
+    for (int p = 0; p < pairs; p++)
+        out[((size_t)sh * pairs + p) * V + s] = make_double2(sigma * z[2 * p], sigma * z[2 * p + 1]);
 }
 
 // ------------------------------------------------------------------ FFT
@@ -179,6 +184,37 @@ __global__ void wilson_kernel(const d2* __restrict__ alpha, int nsh, int V, doub
         v = mul(v, expi(a, -1.0));
     }
     stM(Vdag, s, V, v);
+}
+
+// SU(2): V^+ as quaternions [4][V]; colours (0, 1) from pair 0, colour 2 from pair 1
+__global__ void identity2_kernel(double* Q, int V)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+    Q[s] = 1.0;
+    Q[(size_t)V + s] = Q[2 * (size_t)V + s] = Q[3 * (size_t)V + s] = 0.0;
+}
+__device__ __forceinline__ q4<double> ldQ(const double* p, int s, int V)
+{
+    return {p[s], p[(size_t)V + s], p[2 * (size_t)V + s], p[3 * (size_t)V + s]};
+}
+__device__ __forceinline__ void stQ(double* p, int s, int V, const q4<double>& q)
+{
+    p[s] = q.w;
+    p[(size_t)V + s] = q.x;
+    p[2 * (size_t)V + s] = q.y;
+    p[3 * (size_t)V + s] = q.z;
+}
+__global__ void wilson2_kernel(const d2* __restrict__ alpha, int nsh, int V, double* Vdag)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+    q4<double> v = ldQ(Vdag, s, V);
+    for (int sh = 0; sh < nsh; sh++) {
+        const d2 w0 = alpha[((size_t)sh * 2) * V + s], w1 = alpha[((size_t)sh * 2 + 1) * V + s];
+        v = qmul(v, qexpi(v3<double>{{w0.x, w0.y, w1.x}}, -1.0));
+    }
+    stQ(Vdag, s, V, v);
 }
 
 // U^X_i(x) = V(x) V(x+i)^+ = (V^+(x))^+ V^+(x+i)
@@ -373,17 +409,21 @@ __global__ void convert_kernel(const double* __restrict__ s, float* __restrict__
         if (e_ != hipSuccess) return e_;     \
     } while (0)
 
+// one nucleus: Wilson line V^+ of its sheets (SU(3): [18][V] matrices; SU(2):
+// [4][V] quaternions)
 static hipError_t nucleus_wilson(const ICArgs& a, int nucleus, d2* buf, d2* tmp, int chunk, double* Vdag,
-                                 const Radices& R, hipStream_t st)
+                                 const Radices& R, hipStream_t st, int nc = 3)
 {
     const int N = a.N, V = N * N;
+    const int pairs = nc == 2 ? 2 : 4;
     const double sigma = a.g2mua / sqrt((double)a.n_sheets);
-    hipLaunchKernelGGL(identity_kernel, dim3((V + 255) / 256), dim3(256), 0, st, Vdag, V);
+    if (nc == 2) hipLaunchKernelGGL(identity2_kernel, dim3((V + 255) / 256), dim3(256), 0, st, Vdag, V);
+    else hipLaunchKernelGGL(identity_kernel, dim3((V + 255) / 256), dim3(256), 0, st, Vdag, V);
     for (int s0 = 0; s0 < a.n_sheets; s0 += chunk) {
         const int nsh = a.n_sheets - s0 < chunk ? a.n_sheets - s0 : chunk;
-        const int nf = 4 * nsh;
+        const int nf = pairs * nsh;
         hipLaunchKernelGGL(charges_kernel, dim3((V + 255) / 256, nsh), dim3(256), 0, st, buf, V, a.seed, nucleus, s0,
-                           sigma);
+                           sigma, pairs);
         hipLaunchKernelGGL(fft_rows_kernel, dim3(nf * N), dim3(256), 0, st, buf, N, -1, R);
         hipLaunchKernelGGL(transpose_kernel, dim3((N + 31) / 32, (N + 31) / 32, nf), dim3(32, 8), 0, st, buf, tmp, N);
         hipLaunchKernelGGL(fft_rows_kernel, dim3(nf * N), dim3(256), 0, st, tmp, N, -1, R);
@@ -393,7 +433,8 @@ static hipError_t nucleus_wilson(const ICArgs& a, int nucleus, d2* buf, d2* tmp,
         hipLaunchKernelGGL(fft_rows_kernel, dim3(nf * N), dim3(256), 0, st, tmp, N, +1, R);
         hipLaunchKernelGGL(transpose_kernel, dim3((N + 31) / 32, (N + 31) / 32, nf), dim3(32, 8), 0, st, tmp, buf, N);
         hipLaunchKernelGGL(fft_rows_kernel, dim3(nf * N), dim3(256), 0, st, buf, N, +1, R);
-        hipLaunchKernelGGL(wilson_kernel, dim3((V + 255) / 256), dim3(256), 0, st, buf, nsh, V, Vdag);
+        if (nc == 2) hipLaunchKernelGGL(wilson2_kernel, dim3((V + 255) / 256), dim3(256), 0, st, buf, nsh, V, Vdag);
+        else hipLaunchKernelGGL(wilson_kernel, dim3((V + 255) / 256), dim3(256), 0, st, buf, nsh, V, Vdag);
         CK(hipGetLastError());
     }
     return hipSuccess;
@@ -432,6 +473,124 @@ hipError_t ic_glasma(const ICArgs& a, Fields<double> out, int* d_fails, hipStrea
     if (e == hipSuccess) e = e2;
     hipFree(buf); hipFree(tmp); hipFree(Vdag); hipFree(UA); hipFree(UB);
     return e;
+}
+
+// ------------------------------------------------------------------ SU(2)
+// U^X_i(x) = V(x) V(x+i)^+ on quaternions [2][4][V]
+__global__ void pure_gauge2_kernel(const double* __restrict__ Vdag, int N, double* UX)
+{
+    const int V = N * N;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+    const int x = s % N, y = s / N;
+    const int sx = y * N + (x + 1 == N ? 0 : x + 1), sy = (y + 1 == N ? 0 : y + 1) * N + x;
+    const q4<double> here = qadj(ldQ(Vdag, s, V));
+    stQ(UX, s, V, qmul(here, ldQ(Vdag, sx, V)));
+    stQ(UX + 4 * (size_t)V, s, V, qmul(here, ldQ(Vdag, sy, V)));
+}
+// tau = 0 links: W = U^A + U^B is a real multiple of an SU(2) element S, and
+// U = S^2 = W W / |W|^2 solves Proj[W (1 + U^+)] = 0 (W (1 + U^+) = W + W^+ |W|^0
+// is then a multiple of 1)
+__global__ void links2_kernel(const double* __restrict__ UA, const double* __restrict__ UB, int V, double* U)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= 2 * V) return;
+    const int i = k / V, s = k - i * V;
+    const size_t o = (size_t)i * 4 * V;
+    const q4<double> W = qadd(ldQ(UA + o, s, V), ldQ(UB + o, s, V));
+    const double n2 = W.w * W.w + W.x * W.x + W.y * W.y + W.z * W.z;
+    const q4<double> S2 = qmul(W, W);
+    stQ(U + o, s, V, {S2.w / n2, S2.x / n2, S2.y / n2, S2.z / n2});
+}
+// pi(0) of the SU(3) kernel on quaternions
+__global__ void pi02_kernel(const double* __restrict__ UA, const double* __restrict__ UB, const double* __restrict__ U,
+                            int N, double* pi)
+{
+    const int V = N * N;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+    const int x = s % N, y = s / N;
+    q4<double> acc = {0, 0, 0, 0};
+    for (int i = 0; i < 2; i++) {
+        const int sm = i == 0 ? y * N + (x == 0 ? N - 1 : x - 1) : (y == 0 ? N - 1 : y - 1) * N + x;
+        const size_t o = (size_t)i * 4 * V;
+        const q4<double> P1 = qmul(qsub(ldQ(U + o, s, V), qone<double>()),
+                                   qsub(qadj(ldQ(UB + o, s, V)), qadj(ldQ(UA + o, s, V))));
+        const q4<double> P2 = qmul(qsub(qadj(ldQ(U + o, sm, V)), qone<double>()),
+                                   qsub(ldQ(UB + o, sm, V), ldQ(UA + o, sm, V)));
+        acc = qadd(acc, qadd(P1, P2));
+    }
+    const v3<double> p = qproj(acc);
+    for (int a = 0; a < 3; a++) pi[(size_t)a * V + s] = 0.5 * p.v[a];
+}
+
+hipError_t ic_glasma2(const ICArgs& a, Fields2<double> out, hipStream_t st)
+{
+    const int N = a.N, V = N * N;
+    const Radices R = radices_of(N);
+    if (R.n < 0 || N > kMaxFFT || N < 4) return hipErrorInvalidValue;
+    const size_t per_sheet = (size_t)2 * V * sizeof(d2);
+    int chunk = (int)((size_t)256 << 20) / (int)(per_sheet > 0 ? per_sheet : 1);
+    chunk = chunk < 1 ? 1 : (chunk > a.n_sheets ? a.n_sheets : chunk);
+    d2 *buf = nullptr, *tmp = nullptr;
+    double *Vdag = nullptr, *UA = nullptr, *UB = nullptr;
+    hipError_t e = hipMalloc(&buf, per_sheet * chunk);
+    if (e == hipSuccess) e = hipMalloc(&tmp, per_sheet * chunk);
+    if (e == hipSuccess) e = hipMalloc(&Vdag, sizeof(double) * 4 * V);
+    if (e == hipSuccess) e = hipMalloc(&UA, sizeof(double) * 8 * V);
+    if (e == hipSuccess) e = hipMalloc(&UB, sizeof(double) * 8 * V);
+    if (e == hipSuccess) e = nucleus_wilson(a, 0, buf, tmp, chunk, Vdag, R, st, 2);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(pure_gauge2_kernel, dim3((V + 255) / 256), dim3(256), 0, st, Vdag, N, UA);
+        e = nucleus_wilson(a, 1, buf, tmp, chunk, Vdag, R, st, 2);
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(pure_gauge2_kernel, dim3((V + 255) / 256), dim3(256), 0, st, Vdag, N, UB);
+        hipLaunchKernelGGL(links2_kernel, dim3((2 * V + 255) / 256), dim3(256), 0, st, UA, UB, V, out.U);
+        hipLaunchKernelGGL(pi02_kernel, dim3((V + 255) / 256), dim3(256), 0, st, UA, UB, out.U, N, out.pi);
+        const size_t nz = (size_t)9 * V;  // phi (3V) and E (6V) are adjacent
+        hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, st, out.phi, nz);
+        e = hipGetLastError();
+    }
+    hipError_t e2 = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = e2;
+    hipFree(buf); hipFree(tmp); hipFree(Vdag); hipFree(UA); hipFree(UB);
+    return e;
+}
+
+// SU(2) particles: block 0 as for SU(3); the charge from the Darboux
+// parametrisation (Sec. IV.A) with J^2 = q2: words 0, 1 of block 1 give
+// phi = 2 pi u and xi = J (2 u' - 1), Q = (cos phi rho, sin phi rho, xi),
+// rho = sqrt(J^2 - xi^2).  Records keep the SU(3) layout (Q^4..Q^8 = 0).
+__global__ void particles2_kernel(PartICArgs a, double J, double* r, int* cell)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int np = a.np, N = a.N;
+    if (p >= np) return;
+    const u64x4 w = philox4x64((uint64_t)p, 0, 0, 0, a.seed, 3);
+    const u64x4 v = philox4x64((uint64_t)p, 1, 0, 0, a.seed, 3);
+    const double x = N * u01_co(w.v[0]), y = N * u01_co(w.v[1]);
+    const double phi0 = a.azimuth_uniform ? 2.0 * M_PI * u01_co(w.v[2]) : 0.0;
+    const double pt = a.pt_min + (a.pt_max - a.pt_min) * u01_co(w.v[3]);
+    const double ph = 2.0 * M_PI * u01_co(v.v[0]), xi = J * (2.0 * u01_co(v.v[1]) - 1.0);
+    const double rho = sqrt(J * J - xi * xi);
+    const double cph = cos(phi0), sph = sin(phi0);
+    auto col = [&](int c) -> double& { return r[(size_t)c * np + p]; };
+    col(PX_) = x; col(PY_) = y; col(PETA_) = 0;
+    col(PPX) = pt * cph; col(PPY) = pt * sph; col(PPETA) = 0; col(PDETA) = 0;
+    col(PUX0) = cph; col(PUY0) = sph; col(PPT0) = pt;
+    col(PQ0) = cos(ph) * rho; col(PQ0 + 1) = sin(ph) * rho; col(PQ0 + 2) = xi;
+    for (int c = 3; c < 8; c++) col(PQ0 + c) = 0.0;
+    int nx = (int)floor(x + 0.5), ny = (int)floor(y + 0.5);
+    cell[p] = nx >= N ? nx - N : nx;
+    cell[np + p] = ny >= N ? ny - N : ny;
+}
+
+hipError_t ic_particles2(const PartICArgs& a, double q2, double* r, int* cell, hipStream_t st)
+{
+    if (a.np <= 0) return hipSuccess;
+    hipLaunchKernelGGL(particles2_kernel, dim3((a.np + 127) / 128), dim3(128), 0, st, a, sqrt(q2), r, cell);
+    return hipGetLastError();
 }
 
 hipError_t ic_particles(const PartICArgs& a, double* r, int* cell, hipStream_t st)

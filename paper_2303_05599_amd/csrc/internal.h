@@ -28,6 +28,21 @@ template <typename T> __host__ __device__ inline Fields<T> fields_at(void* base,
     return {p, p + 36 * (size_t)V, p + 44 * (size_t)V, p + 60 * (size_t)V};
 }
 
+// SU(2) buffer set (20 reals per site): U[i][4][V] quaternions (w, a1, a2, a3),
+// phi[3][V], E[2][3][V], pi[3][V]
+constexpr int kRealsPerSite2 = 20;
+template <typename T> struct Fields2 {
+    T* U;
+    T* phi;
+    T* E;
+    T* pi;
+};
+template <typename T> __host__ __device__ inline Fields2<T> fields2_at(void* base, int V)
+{
+    T* p = static_cast<T*>(base);
+    return {p, p + 8 * (size_t)V, p + 11 * (size_t)V, p + 17 * (size_t)V};
+}
+
 template <typename T> struct Parts {
     T* r;       // [18][np] (PartCol order)
     int* cell;  // [2][np]
@@ -169,6 +184,17 @@ hipError_t launch_jets(const Fields<T>& A, const Fields<T>& B, const T* aux, T* 
 // samples: partials[slot][group of 64 paths][4] (|F_x|^2, |F_y|^2, |F_z|^2, 0)
 __host__ __device__ inline int jet_groups(int V) { return (V + 63) / 64; }
 
+// ---- SU(2) variant (su2.hip): site-parallel field update, one thread per particle
+template <typename T>
+hipError_t launch_su2_field(const Fields2<T>& in, const Fields2<T>& out, int N, const Schedule& sc, int* d_step,
+                            hipStream_t st, const KTimer& tm = KTimer{});
+template <typename T>
+hipError_t launch_su2_push(const Fields2<T>& A, const Fields2<T>& B, const Parts<T>& P, const PushArgs& a,
+                           int* d_step, double* partials, int* err, hipStream_t st, const KTimer& tm = KTimer{});
+template <typename T>
+hipError_t launch_su2_diag(const Fields2<T>& f, int N, double dt, int n, double* partials, int nblk_cap,
+                           int* nblk_out, hipStream_t st);
+
 // ---- particle ordering (sort.hip)
 struct SortBufs {
     unsigned *keys = nullptr, *keys2 = nullptr;
@@ -201,6 +227,9 @@ struct PartICArgs {
     double q0[8];
 };
 hipError_t ic_particles(const PartICArgs& a, double* r /*[18][np]*/, int* cell, hipStream_t st);
+// SU(2) variant: links, pi(0) into a double Fields2 set; Darboux charges with |Q|^2 = q2
+hipError_t ic_glasma2(const ICArgs& a, Fields2<double> out, hipStream_t st);
+hipError_t ic_particles2(const PartICArgs& a, double q2, double* r, int* cell, hipStream_t st);
 hipError_t convert_to_float(const double* src, float* dst, size_t n, hipStream_t st);
 
 }  // namespace cpic

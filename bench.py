@@ -43,14 +43,19 @@ PUSH_BYTES = {"f64": 730, "f32": 370}
 # path's cell read once per site: x and y links (36), the half-step sums of
 # E_x, E_y and pi, D_x and G of the aux buffer (40)
 JET_BYTES = {"f64": 142 * 8, "f32": 142 * 4}
+# SU(2) variant: a site holds 20 reals (two quaternion links, phi, E_x, E_y,
+# pi), read and written once; a push moves its record (13 words each way: the
+# SU(2) columns), the six force fields at one site (18 reals), phi at the cell
+# (3) and a link (4 reals) every eighth step
+SITE_BYTES_SU2 = {"f64": 20 * 2 * 8, "f32": 20 * 2 * 4}
+PUSH_BYTES_SU2 = {"f64": (26 + 18 + 3 + 0.5) * 8, "f32": (26 + 18 + 3 + 0.5) * 4}
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_512_fp64.txt")
 KERNEL_SOURCES = os.path.join(ROOT, "paper_2303_05599_amd", "csrc")
 
 
-def glasma_512(precision, N=512, L=6.0, seed=3):
-    import paper_2303_05599_amd as cp
+def glasma_512(precision, N=512, L=6.0, seed=3, n_colors=3):
     return dict(N=N, L_fm=L, g2mu_GeV=2.0, m_ir_GeV=0.2, uv_GeV=10.0, n_sheets=50, dtau_over_a=0.125,
-                tau_max_fm=1.5, seed=seed, precision=precision, reunit_every=16, record_every=8)
+                tau_max_fm=1.5, seed=seed, precision=precision, reunit_every=16, record_every=8, n_colors=n_colors)
 
 
 def charm(n=100_000, seed=4, color_update=0):
@@ -64,7 +69,7 @@ def jet_quarks(n=1_000_000, seed=4):
                 seed=seed)
 
 
-def run_event(precision, steps, warmup, tune=True, particles=None, jets=False):
+def run_event(precision, steps, warmup, tune=True, particles=None, jets=False, n_colors=3):
     """One 512^2 event: IC (timed separately), warm-up steps past formation, the
     launch tuner, a graph-replayed stretch (its rate is reported as an extra),
     then the timed region: `steps` steps with per-kernel HIP-event timing.  The
@@ -72,7 +77,7 @@ def run_event(precision, steps, warmup, tune=True, particles=None, jets=False):
     kernel are exactly the timed ones."""
     import torch
     import paper_2303_05599_amd as cp
-    ctx = cp.Context(glasma_512(precision), particles or charm())
+    ctx = cp.Context(glasma_512(precision, n_colors=n_colors), particles or charm())
     if jets:
         ctx.enable_jets(x_offset=0.3)
     t0 = time.perf_counter()
@@ -232,6 +237,30 @@ def run_color_log(steps, warmup, V, ref):
             "dpT2_rel_vs_rotation": float(r["obs"][-1, 1] / ref["obs"][-1, 1] - 1),
             "dpL2_rel_vs_rotation": float(r["obs"][-1, 2] / ref["obs"][-1, 2] - 1),
             "casimir_q2_max_drift": float(r["diag"][8])}
+
+
+def run_su2(steps, warmup, V):
+    """The headline event and charm quarks in the SU(2) variant (links as
+    quaternions, Darboux charges), FP64, the same timed region."""
+    import paper_2303_05599_amd as cp
+    n_part = 100_000
+    r = run_event(cp.FP64, steps, warmup, False, charm(n_part), n_colors=2)
+    tm = r["timing"]
+    out = {"workload": "MV Glasma 512^2 as the headline event, gauge group SU(2), 1e5 charm quarks, FP64",
+           "ms_per_step": r["wall"] * 1e3 / steps,
+           "site_updates_per_s": V * steps / r["wall"],
+           "pushes_per_s": n_part * steps / r["wall"], "kernels": {}}
+    for key, ms, k, unit_bytes, units, name in (
+            ("field", tm["field_ms"], tm["n_field"], SITE_BYTES_SU2["f64"], V, "su2_field_kernel<double>"),
+            ("push", tm["push_ms"], tm["n_push"], PUSH_BYTES_SU2["f64"], n_part, "su2_push_kernel<double>")):
+        secs = ms / max(k, 1) * 1e-3
+        ach = unit_bytes * units / secs / 1e9
+        out["kernels"][key] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": ach / HBM_PEAK_GBS, "kernel": name, "avg_launch_us": secs * 1e6,
+                               "bytes_per_unit": unit_bytes, "units_per_launch": units}
+    out["dpT2_GeV2_last"] = float(r["obs"][-1, 1])
+    out["gauss_max"] = float(r["diag"][1])
+    return out
 
 
 def cpu_baseline(n_steps=6, n_part=100_000):
@@ -505,6 +534,7 @@ def main():
                        "dpL2_rel_vs_fp64": float(abs(r32["obs"][-1, 2] / res["obs"][-1, 2] - 1))}
         out["jets"] = run_jets(args.steps, args.warmup, V)
         out["color_log"] = run_color_log(args.steps, args.warmup, V, res)
+        out["su2"] = run_su2(args.steps, args.warmup, V)
         out["batch"] = run_batch(res["launch"])
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()

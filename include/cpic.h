@@ -252,6 +252,21 @@ cpic_status cpic_set_launch(cpic_ctx* ctx, int32_t bx, int32_t by, int32_t xcd_r
  * all three. */
 cpic_status cpic_set_push_lanes(cpic_ctx* ctx, int32_t lanes);
 
+/* Where the push takes the colour fields at a particle's cell:
+ *   CPIC_PUSH_GATHER  evaluated per particle from the per-site pieces the
+ *                     field update writes (default for fewer particles
+ *                     than sites);
+ *   CPIC_PUSH_TABLE   evaluated once per site into a force table (48 reals
+ *                     per site, one more kernel per step) that the push reads
+ *                     at the cell (default for more particles than sites).
+ * Both give the same arithmetic per particle.  SU(3) with the rotation
+ * colour update only; cpic_tune times both.  Kernel timing counts the table
+ * kernel as push time. */
+#define CPIC_PUSH_GATHER 0
+#define CPIC_PUSH_TABLE 1
+cpic_status cpic_set_push_mode(cpic_ctx* ctx, int32_t mode);
+cpic_status cpic_get_push_mode(const cpic_ctx* ctx, int32_t* mode);
+
 /* Current launch configuration: out = {bx, by, xcd_remap, waves, push lanes,
  * variant}. */
 cpic_status cpic_get_launch(const cpic_ctx* ctx, int32_t out[6]);

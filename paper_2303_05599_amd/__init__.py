@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libcpic.so")
 FP64, FP32 = 0, 1
 REP_FUND, REP_ADJ = 0, 1
 COLOR_ROTATE, COLOR_LOG = 0, 1
+PUSH_GATHER, PUSH_TABLE = 0, 1
 STATE_U, STATE_PHI, STATE_E, STATE_PI, STATE_PARTICLES, STATE_STEP, STATE_JET_W, STATE_JET_F = range(8)
 ERRORS = {-1: "INVALID", -2: "NOMEM", -3: "HIP", -4: "IC_NEWTON", -5: "NAN", -6: "DRIFT", -7: "CAPACITY",
           -8: "CELL_JUMP", -9: "IO"}
@@ -89,6 +90,7 @@ def lib():
             "cpic_batch_observables": [P, i32, P, i32, ctypes.POINTER(i32)],
             "cpic_batch_get_state": [P, i32, i32, P, sz],
             "cpic_jets_enable": [P, ctypes.POINTER(JetParams)],
+            "cpic_set_push_mode": [P, i32], "cpic_get_push_mode": [P, ctypes.POINTER(i32)],
             "cpic_jets_observables": [P, P, i32, ctypes.POINTER(i32)],
             "cpic_jets_timing": [P, ctypes.POINTER(d), ctypes.POINTER(i64)],
         }
@@ -244,6 +246,15 @@ class Context:
 
     def set_push_lanes(self, lanes):
         self._chk(lib().cpic_set_push_lanes(self.h, lanes))
+
+    def set_push_mode(self, mode):
+        """PUSH_GATHER (fields per particle) or PUSH_TABLE (per-site force table)."""
+        self._chk(lib().cpic_set_push_mode(self.h, mode))
+
+    def push_mode(self):
+        v = ctypes.c_int32()
+        self._chk(lib().cpic_get_push_mode(self.h, ctypes.byref(v)))
+        return v.value
 
     def get_launch(self):
         out = np.zeros(6, np.int32)

@@ -93,6 +93,8 @@ static void free_all(cpic_ctx* c)
     for (auto e : c->ev_field) hipEventDestroy(e);
     for (auto e : c->ev_push) hipEventDestroy(e);
     for (auto e : c->ev_jets) hipEventDestroy(e);
+    for (auto e : c->ev_table) hipEventDestroy(e);
+    hipFree(c->ftab);
     hipFree(c->jW); hipFree(c->jF); hipFree(c->jpartials); hipFree(c->jobs);
     hipFree(c->fbuf[0]); hipFree(c->fbuf[1]); hipFree(c->pr); hipFree(c->pcell); hipFree(c->aux);
     hipFree(c->partials); hipFree(c->obs); hipFree(c->d_step); hipFree(c->d_err); hipFree(c->d_fails);
@@ -192,6 +194,9 @@ extern "C" cpic_status cpic_create(const cpic_glasma_params* gp, const cpic_part
     // few particles: several wavefronts share each particle group so that the
     // push still fills the 1024 SIMDs (tunable with cpic_tune)
     c->tpp = c->nc == 2 ? 1 : (c->np <= (1 << 18) ? 4 : (c->np <= (1 << 20) ? 2 : 1));
+    // more particles than sites: evaluate the fields once per site (force table)
+    c->push_table = c->nc == 3 && c->np > c->V && c->pp.color_update == CPIC_COLOR_ROTATE;
+    if (e == hipSuccess && c->push_table) e = hipMalloc(&c->ftab, (size_t)48 * c->V * c->tsz);
     // field update: compressed-link LDS tiles of 64 x 4 sites (the tuner's usual pick at 512^2)
     c->cfg.split = 3;
     c->cfg.bx = 64;
@@ -407,7 +412,18 @@ template <typename T> static cpic_status launch_one(cpic_ctx* c, int parity, boo
     }
     HIPCHK(c, launch_field_step<T>(A, B, static_cast<T*>(c->aux), c->N, c->sc, c->d_step, c->cfg, c->st, tf),
            "field step");
-    if (c->np > 0) {
+    if (c->np > 0 && c->push_table) {
+        KTimer tt;
+        if (with_events) {
+            HIPCHK(c, hipEventCreate(&tt.start), "event"); HIPCHK(c, hipEventCreate(&tt.stop), "event");
+            c->ev_table.push_back(tt.start); c->ev_table.push_back(tt.stop);
+            HIPCHK(c, hipEventCreate(&tp.start), "event"); HIPCHK(c, hipEventCreate(&tp.stop), "event");
+            c->ev_push.push_back(tp.start); c->ev_push.push_back(tp.stop);
+        }
+        HIPCHK(c, launch_push_table<T>(A, B, static_cast<const T*>(c->aux), static_cast<T*>(c->ftab), P<T>(c),
+                                       push_args(c, 1), c->d_step, c->partials, c->d_err, c->st, tt, tp),
+               "table push");
+    } else if (c->np > 0) {
         const PushArgs pa = push_args(c, c->tpp);
         if (with_events) {
             HIPCHK(c, hipEventCreate(&tp.start), "event"); HIPCHK(c, hipEventCreate(&tp.stop), "event");
@@ -533,6 +549,13 @@ static cpic_status collect_timing(cpic_ctx* c)
         c->k_push++;
         hipEventDestroy(c->ev_push[i]); hipEventDestroy(c->ev_push[i + 1]);
     }
+    for (size_t i = 0; i + 1 < c->ev_table.size(); i += 2) {  // the table kernel counts as push time
+        float ms = 0;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev_table[i], c->ev_table[i + 1]), "timing");
+        c->t_push += ms;
+        hipEventDestroy(c->ev_table[i]); hipEventDestroy(c->ev_table[i + 1]);
+    }
+    c->ev_table.clear();
     for (size_t i = 0; i + 1 < c->ev_jets.size(); i += 2) {
         float ms = 0;
         HIPCHK(c, hipEventElapsedTime(&ms, c->ev_jets[i], c->ev_jets[i + 1]), "timing");
@@ -1202,6 +1225,27 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
             rep += line;
             if (per < best_p) { best_p = per; best_tpp = tpp; }
         }
+        bool table = false;
+        if (c->nc == 3 && c->pp.color_update == CPIC_COLOR_ROTATE) {
+            if (!c->ftab) HIPCHK(c, hipMalloc(&c->ftab, (size_t)48 * c->V * c->tsz), "tune");
+            double tot = 0;
+            for (int r = 0; r <= reps; r++) {
+                HIPCHK(c, hipEventRecord(e0, c->st), "tune");
+                HIPCHK(c, launch_push_table<T>(A, B, X, static_cast<T*>(c->ftab), P<T>(c), push_args(c, 1), c->d_step,
+                                               c->partials, c->d_err, c->st), "tune");
+                HIPCHK(c, hipEventRecord(e1, c->st), "tune");
+                HIPCHK(c, hipMemcpyAsync(c->pr, c->sb.r2, rb, hipMemcpyDeviceToDevice, c->st), "tune");
+                HIPCHK(c, hipMemcpyAsync(c->pcell, c->sb.cell2, cb, hipMemcpyDeviceToDevice, c->st), "tune");
+                HIPCHK(c, hipEventSynchronize(e1), "tune");
+                float ms = 0;
+                HIPCHK(c, hipEventElapsedTime(&ms, e0, e1), "tune");
+                if (r > 0) tot += ms;
+            }
+            const double per = tot / reps;
+            std::snprintf(line, sizeof line, "push with force table: %.2f us\n", per * 1e3);
+            rep += line;
+            if (per < best_p) { best_p = per; table = true; }
+        }
         HIPCHK(c, hipStreamSynchronize(c->st), "tune");
         int err = 0;
         HIPCHK(c, hipMemcpy(c->d_err, &err, sizeof(int), hipMemcpyHostToDevice), "tune");
@@ -1209,7 +1253,9 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
         HIPCHK(c, hipMemcpy(c->d_step, &c->n, sizeof(int), hipMemcpyHostToDevice), "tune");
         c->tpp = best_tpp;
         c->pblocks = push_blocks((int)c->np, c->tpp);
-        std::snprintf(line, sizeof line, "best push: lanes=%d %.2f us\n", best_tpp, best_p * 1e3);
+        c->push_table = table;
+        if (table) std::snprintf(line, sizeof line, "best push: force table %.2f us\n", best_p * 1e3);
+        else std::snprintf(line, sizeof line, "best push: lanes=%d %.2f us\n", best_tpp, best_p * 1e3);
         rep += line;
     }
     hipEventDestroy(e0);
@@ -1348,5 +1394,27 @@ extern "C" cpic_status cpic_jets_timing(cpic_ctx* c, double* ms, int64_t* launch
     if (s) return s;
     if (ms) *ms = c->t_jets;
     if (launches) *launches = c->k_jets;
+    return CPIC_OK;
+}
+
+extern "C" cpic_status cpic_set_push_mode(cpic_ctx* c, int32_t mode)
+{
+    if (!c) return fail(nullptr, CPIC_E_INVALID, "cpic_set_push_mode: NULL context");
+    if (mode != CPIC_PUSH_GATHER && mode != CPIC_PUSH_TABLE)
+        return fail(c, CPIC_E_INVALID, "cpic_set_push_mode: CPIC_PUSH_GATHER or CPIC_PUSH_TABLE");
+    if (mode == CPIC_PUSH_TABLE && (c->nc != 3 || c->pp.color_update != CPIC_COLOR_ROTATE))
+        return fail(c, CPIC_E_INVALID, "cpic_set_push_mode: the force table serves the SU(3) rotation update");
+    HIPCHK(c, hipStreamSynchronize(c->st), "set push mode");
+    if (mode == CPIC_PUSH_TABLE && !c->ftab)
+        HIPCHK(c, hipMalloc(&c->ftab, (size_t)48 * c->V * c->tsz), "force table");
+    c->push_table = mode == CPIC_PUSH_TABLE;
+    drop_graphs(c);
+    return CPIC_OK;
+}
+
+extern "C" cpic_status cpic_get_push_mode(const cpic_ctx* c, int32_t* mode)
+{
+    if (!c || !mode) return CPIC_E_INVALID;
+    *mode = c->push_table ? CPIC_PUSH_TABLE : CPIC_PUSH_GATHER;
     return CPIC_OK;
 }

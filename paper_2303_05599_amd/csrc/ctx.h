@@ -52,6 +52,8 @@ struct cpic_ctx {
     int dcap = 0;
     cpic::LaunchCfg cfg{};
     int tpp = 1;          // wavefronts per particle group in the push (1, 2, 4)
+    int push_table = 0;   // 1: fields from a per-site force table (dense ensembles)
+    void* ftab = nullptr; // [48][V] force table
     bool initialised = false;
     // graphs: [parity] -> executable graph of kGraphSteps steps starting from buffer `parity`
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -68,7 +70,7 @@ struct cpic_ctx {
     std::vector<std::pair<int, int>> jsamples;  // (slot, step n after which it was taken)
     // timing
     bool timing = false;
-    std::vector<hipEvent_t> ev_field, ev_push, ev_jets;
+    std::vector<hipEvent_t> ev_field, ev_push, ev_jets, ev_table;
     double t_field = 0, t_push = 0, t_jets = 0;
     int64_t k_field = 0, k_push = 0, k_jets = 0;
     std::string err;

@@ -156,6 +156,13 @@ template <typename T>
 hipError_t launch_push(const Fields<T>& A, const Fields<T>& B, const T* aux, const Parts<T>& P, const PushArgs& a,
                        int* d_step, double* partials, int* err, hipStream_t st, const KTimer& tm = KTimer{});
 int push_blocks(int np, int tpp);
+// dense ensembles: the six field vectors of every site into table [48][V]
+// (force_table_kernel), then a push that reads them at the cell (one
+// wavefront per 64 particles); tm_table / tm_push time the two launches
+template <typename T>
+hipError_t launch_push_table(const Fields<T>& A, const Fields<T>& B, const T* aux, T* table, const Parts<T>& P,
+                             const PushArgs& a, int* d_step, double* partials, int* err, hipStream_t st,
+                             const KTimer& tm_table = KTimer{}, const KTimer& tm_push = KTimer{});
 template <typename T>
 hipError_t launch_batch_push(const EventDesc* ev, const int2* map, int total_blocks, int tpp, hipStream_t st);
 hipError_t launch_reduce_rows(const double* partials, int nrows, int ncols, double* out, hipStream_t st);

@@ -145,9 +145,14 @@ template <int TPP> constexpr int kPushPPB = 256 / TPP;  // particles per block
 // explicit Euler with the state at n like the rest of the particle.  The
 // charges are then not renormalised (their Casimir drift is part of the
 // method).
-template <typename T, int TPP, bool LOGQ>
+//
+// TABLE reads the six field vectors at the cell from the per-site force
+// table of this step (force_table_kernel) instead of evaluating them: the
+// choice for dense ensembles, where several particles share a cell.
+template <typename T, int TPP, bool LOGQ, bool TABLE = false>
 __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& Bf, const T* aux, const Parts<T>& P,
-                                          const PushArgs& a, int n, double* partials, int* err, int blk)
+                                          const PushArgs& a, int n, double* partials, int* err, int blk,
+                                          const T* table = nullptr)
 {
     if (n < a.sc.n_form || n >= a.sc.n_max) return;  // uniform over the event
     constexpr int PPB = kPushPPB<TPP>;
@@ -220,7 +225,9 @@ __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& 
 #pragma unroll 1
             for (int j = 0; j < kJobs; j++) {
                 if (job_wave<TPP>(j) != 0 || !job_active(j, n, eonly)) continue;
-                const T dq = dot(Q, job_field<T>(j, A, B, X, cell, n, t));
+                T dq;
+                if constexpr (TABLE) dq = dot(Q, vA(make_view<T>(table, 48, V), cell.s, 8 * (uint32_t)j));
+                else dq = dot(Q, job_field<T>(j, A, B, X, cell, n, t));
                 const int k = j;  // job j yields force component j
 #pragma unroll
                 for (int kk = 0; kk < 6; kk++) f[kk] += kk == k ? dq : T(0);
@@ -362,6 +369,46 @@ __global__ __launch_bounds__(256) void push_kernel(Fields<T> Af, Fields<T> Bf, c
     push_body<T, TPP, LOGQ>(Af, Bf, aux, P, a, n, partials, err, blk);
 }
 
+// one wavefront per group of 64 particles, fields from the force table
+template <typename T>
+__global__ __launch_bounds__(256) void push_table_kernel(Fields<T> Af, Fields<T> Bf, const T* table, Parts<T> P,
+                                                         PushArgs a, int* d_step, double* partials, int* err)
+{
+    const int nblocks = (a.np + 255) / 256;
+    const int blk = xcd_block(nblocks);
+    if (blk >= nblocks) return;
+    const int n = push_step(d_step, blk);
+    push_body<T, 1, false, true>(Af, Bf, nullptr, P, a, n, partials, err, blk, table);
+}
+
+// The six field vectors (E_x, E_y, E_eta, B_x, B_y, B_eta, 8 components
+// each, [48][V]) at every site at t_n, from the same per-site arithmetic
+// the push applies at a particle's cell.  Runs between the field update
+// (which provides n in d_step[1]) and the table push.
+template <typename T>
+__global__ __launch_bounds__(256) void force_table_kernel(Fields<T> Af, Fields<T> Bf, const T* aux, T* table, int N,
+                                                          Schedule sc, bool electric_only, const int* d_step)
+{
+    const int V = N * N, nb = (V + 255) / 256;
+    const int blk = xcd_block(nb);
+    if (blk >= nb) return;
+    const int n = d_step[1];
+    if (n < sc.n_form || n >= sc.n_max) return;
+    const int s = blk * 256 + (int)threadIdx.x;
+    if (s >= V) return;
+    const View<T> A = make_view<T>(Af.U, kRealsPerSite, V), B = make_view<T>(Bf.U, kRealsPerSite, V);
+    const View<T> X = make_view<T>(aux, kAuxReals, V), TB = make_view<T>(table, 48, V);
+    const Cell cell = make_cell<T>(s % N, s / N, N);
+    const T t = T(n * sc.dt);
+#pragma unroll 1
+    for (int j = 0; j < kJobs; j++) {
+        a8<T> F = azero<T>();
+        if (job_active(j, n, electric_only)) F = job_field<T>(j, A, B, X, cell, n, t);
+        vA_st(TB, (uint32_t)s * (uint32_t)sizeof(T), 8 * (uint32_t)j, F);
+        CPIC_PHASE();
+    }
+}
+
 // batched events: logical block g works on particle block map[g].y of event map[g].x
 template <typename T, int TPP>
 __global__ __launch_bounds__(256) void batch_push_kernel(const EventDesc* __restrict__ ev, const int2* __restrict__ map,
@@ -397,6 +444,28 @@ template hipError_t launch_batch_push<double>(const EventDesc*, const int2*, int
 template hipError_t launch_batch_push<float>(const EventDesc*, const int2*, int, int, hipStream_t);
 
 int push_blocks(int np, int tpp) { return push_blocks_d(np, tpp); }
+
+template <typename T>
+hipError_t launch_push_table(const Fields<T>& A, const Fields<T>& B, const T* aux, T* table, const Parts<T>& P,
+                             const PushArgs& a, int* d_step, double* partials, int* err, hipStream_t st,
+                             const KTimer& tm_table, const KTimer& tm_push)
+{
+    if (a.np <= 0) return hipSuccess;
+    if (!aux || !table) return hipErrorInvalidValue;
+    const int nbt = (a.N * a.N + 255) / 256;
+    klaunch(tm_table, force_table_kernel<T>, dim3(8 * ((nbt + 7) / 8)), dim3(256), st, A, B, aux, table, a.N, a.sc,
+            a.is_static != 0, (const int*)d_step);
+    const int nb = (a.np + 255) / 256;
+    klaunch(tm_push, push_table_kernel<T>, dim3(8 * ((nb + 7) / 8)), dim3(256), st, A, B, (const T*)table, P, a,
+            d_step, partials, err);
+    return hipGetLastError();
+}
+template hipError_t launch_push_table<double>(const Fields<double>&, const Fields<double>&, const double*, double*,
+                                              const Parts<double>&, const PushArgs&, int*, double*, int*, hipStream_t,
+                                              const KTimer&, const KTimer&);
+template hipError_t launch_push_table<float>(const Fields<float>&, const Fields<float>&, const float*, float*,
+                                             const Parts<float>&, const PushArgs&, int*, double*, int*, hipStream_t,
+                                             const KTimer&, const KTimer&);
 
 template <typename T>
 hipError_t launch_push(const Fields<T>& A, const Fields<T>& B, const T* aux, const Parts<T>& P, const PushArgs& a,

@@ -64,6 +64,7 @@ def alone(g, p, lanes):
     ctx = cp.Context(g, p)
     ctx.init_mv()
     if ctx.np:
+        ctx.set_push_mode(cp.PUSH_GATHER)   # the batched push evaluates the fields per particle
         ctx.set_push_lanes(lanes)
     ctx.evolve(1e9)
     ctx.sync()

@@ -116,10 +116,12 @@ def test_particles_init_parity():
     assert rel_err(got, ref) < 1e-13
 
 
-@pytest.mark.parametrize("is_static,lanes", [(False, 1), (False, 2), (False, 4), (True, 1), (True, 2), (True, 4)])
+@pytest.mark.parametrize("is_static,lanes", [(False, 1), (False, 2), (False, 4), (True, 1), (True, 2), (True, 4),
+                                             (False, "table"), (True, "table")])
 def test_particle_push_fp64_random_state(is_static, lanes):
     """Rotation on cell changes (both axes), rapidity Wilson line, E/B interpolation, Euler step,
-    with 1, 2 or 4 wavefronts sharing each particle group."""
+    with 1, 2 or 4 wavefronts sharing each particle group, or with the fields
+    taken from the per-site force table."""
     print(f"case push static={is_static} lanes={lanes}", flush=True)
     N, L, n0, n_form, steps = 32, 6.0, 5, 3, 50
     a = oracle.lattice_spacing(L, N)
@@ -129,7 +131,12 @@ def test_particle_push_fp64_random_state(is_static, lanes):
     ctx = cp.Context(glasma(N, L, steps=n0 + steps),       # the last step is a sampling step
                      particle_params(3000, math.inf if is_static else mhat / a, N, L, n_form))
     ctx.load_state(st, n=n0, particles=P)
-    ctx.set_push_lanes(lanes)
+    if lanes == "table":
+        ctx.set_push_mode(cp.PUSH_TABLE)
+    else:
+        ctx.set_push_mode(cp.PUSH_GATHER)
+        ctx.set_push_lanes(lanes)
+    assert ctx.push_mode() == (cp.PUSH_TABLE if lanes == "table" else cp.PUSH_GATHER)
     ctx.step(steps)
     ctx.sync()
     got = ctx.get_state(cp.STATE_PARTICLES)
@@ -390,3 +397,25 @@ def test_tuner_leaves_state_unchanged():
     for k in ("U", "phi", "E", "pi"):
         assert rel_err(a_ctx.state()[k], b_ctx.state()[k]) < 1e-12, k
     assert rel_err(a_ctx.get_state(cp.STATE_PARTICLES), b_ctx.get_state(cp.STATE_PARTICLES)) < 1e-12
+
+
+def test_force_table_matches_gather_push():
+    """A dense ensemble (4 particles per site) in both push modes, graph-replayed
+    past the formation step: the same records to rounding (the same per-site
+    arithmetic, evaluated at different places)."""
+    N, L = 48, 4.8
+    g = glasma(N, L, n_sheets=2, steps=60, seed=13)
+    p = dict(n=4 * N * N, mass_GeV=1.27, pT_min_GeV=0.0, pT_max_GeV=3.0, azimuth_uniform=1, tau_form_fm=0.3, rep=0,
+             seed=14)
+    out = []
+    for mode in (cp.PUSH_GATHER, cp.PUSH_TABLE):
+        ctx = cp.Context(g, p)
+        assert ctx.push_mode() == cp.PUSH_TABLE          # the default for more particles than sites
+        ctx.set_push_mode(mode)
+        ctx.init_mv()
+        ctx.evolve(1e9)
+        out.append((ctx.get_state(cp.STATE_PARTICLES), ctx.observables()))
+        ctx.close()
+    assert np.array_equal(out[0][0][:, 14:16], out[1][0][:, 14:16])
+    assert rel_err(out[1][0], out[0][0]) < 1e-13
+    assert rel_err(out[1][1], out[0][1]) < 1e-13

@@ -87,6 +87,7 @@ def run_event(precision, steps, warmup, tune=True, particles=None, jets=False, n
     ctx.sync()
     tune_report = ctx.tune(5) if tune else "not tuned (library defaults)\n"
     launch = ctx.get_launch()
+    launch["push_mode"] = "table" if ctx.push_mode() == cp.PUSH_TABLE else "gather"
     # graph-replayed rate (not the headline number)
     n_graph = max(0, min(256, 1024 - warmup - steps))
     graph_ms = None
@@ -321,7 +322,11 @@ def kernel_names(launch, precision):
         field = "field_link_kernel" + ("" if launch["waves"] == 1 else f"_w{launch['waves']}") + f"<{t}, true>"
     else:
         field = "field_step_kernel" + ("" if launch["waves"] == 1 else f"_w{launch['waves']}") + f"<{t}, true>"
-    return field, f"push_kernel<{t}, {launch['push_lanes']}, false>", f"jet_kernel<{t}>"
+    if launch.get("push_mode") == "table":
+        push = f"force_table_kernel<{t}> + push_table_kernel<{t}>"
+    else:
+        push = f"push_kernel<{t}, {launch['push_lanes']}, false>"
+    return field, push, f"jet_kernel<{t}>"
 
 
 def rooflines(res, precision, n_part, V):

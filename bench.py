@@ -318,7 +318,8 @@ def kernel_names(launch, precision):
     t = "double" if precision == "fp64" else "float"
     v = launch["variant"]
     if v == 3:
-        field = f"field_ctile_kernel<{t}, true, {launch['bx']}, {launch['by']}>"
+        cp = 2 if launch.get("nt_store") else 0
+        field = f"field_ctile_kernel<{t}, true, {launch['bx']}, {launch['by']}, {cp}>"
     elif v == 2:
         field = f"field_tile_kernel<{t}, true, {launch['bx']}, {launch['by']}>"
     elif v == 1:

@@ -268,8 +268,12 @@ cpic_status cpic_set_push_mode(cpic_ctx* ctx, int32_t mode);
 cpic_status cpic_get_push_mode(const cpic_ctx* ctx, int32_t* mode);
 
 /* Current launch configuration: out = {bx, by, xcd_remap, waves, push lanes,
- * variant}. */
-cpic_status cpic_get_launch(const cpic_ctx* ctx, int32_t out[6]);
+ * variant, non-temporal link stores}.  The last is chosen at creation (and by
+ * cpic_jets_enable): 1 where the old state, the new state and the per-site
+ * field pieces the push reads exceed the 256 MB last-level cache together
+ * (FP64 at 512^2), so that the new links and scalar, which the push does not
+ * read, bypass it; results are the same either way. */
+cpic_status cpic_get_launch(const cpic_ctx* ctx, int32_t out[7]);
 
 /* Launch tuner: times every candidate field-kernel configuration (block shape x
  * occupancy target x XCD mapping) in place on the current state without

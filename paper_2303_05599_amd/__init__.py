@@ -257,9 +257,9 @@ class Context:
         return v.value
 
     def get_launch(self):
-        out = np.zeros(6, np.int32)
+        out = np.zeros(7, np.int32)
         self._chk(lib().cpic_get_launch(self.h, _ptr(out)))
-        return dict(zip(("bx", "by", "xcd_remap", "waves", "push_lanes", "variant"), out.tolist()))
+        return dict(zip(("bx", "by", "xcd_remap", "waves", "push_lanes", "variant", "nt_store"), out.tolist()))
 
     def tune(self, reps=5):
         """Time the launch candidates on the current state and keep the fastest; returns the report."""

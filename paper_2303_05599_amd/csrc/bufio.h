@@ -38,12 +38,16 @@ template <typename T> __device__ __forceinline__ T bld(const View<T>& v, uint32_
     else
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(v.r, voff, comp * v.cs, 0));
 }
-template <typename T> __device__ __forceinline__ void bst(const View<T>& v, uint32_t voff, uint32_t comp, T x)
+// cache policy of a store: 0 default, kStoreNT non-temporal (data the next
+// kernel does not read: it should not displace data that it does)
+constexpr int kStoreNT = 2;
+template <typename T, int CP = 0>
+__device__ __forceinline__ void bst(const View<T>& v, uint32_t voff, uint32_t comp, T x)
 {
     if constexpr (sizeof(T) == 8)
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), v.r, voff, comp * v.cs, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), v.r, voff, comp * v.cs, CP);
     else
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), v.r, voff, comp * v.cs, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), v.r, voff, comp * v.cs, CP);
 }
 __device__ __forceinline__ int bld_i(const View<int>& v, uint32_t voff, uint32_t comp)
 {
@@ -65,12 +69,13 @@ template <typename T> __device__ __forceinline__ m3<T> vU(const View<T>& v, uint
         m.e[c] = {bld(v, voff, kCompU + 18 * i + 2 * c), bld(v, voff, kCompU + 18 * i + 2 * c + 1)};
     return m;
 }
-template <typename T> __device__ __forceinline__ void vU_st(const View<T>& v, uint32_t voff, int i, const m3<T>& m)
+template <typename T, int CP = 0>
+__device__ __forceinline__ void vU_st(const View<T>& v, uint32_t voff, int i, const m3<T>& m)
 {
 #pragma unroll
     for (int c = 0; c < 9; c++) {
-        bst(v, voff, kCompU + 18 * i + 2 * c, m.e[c].re);
-        bst(v, voff, kCompU + 18 * i + 2 * c + 1, m.e[c].im);
+        bst<T, CP>(v, voff, kCompU + 18 * i + 2 * c, m.e[c].re);
+        bst<T, CP>(v, voff, kCompU + 18 * i + 2 * c + 1, m.e[c].im);
     }
 }
 template <typename T> __device__ __forceinline__ a8<T> vA(const View<T>& v, uint32_t voff, uint32_t comp0)
@@ -80,10 +85,11 @@ template <typename T> __device__ __forceinline__ a8<T> vA(const View<T>& v, uint
     for (int a = 0; a < 8; a++) r.v[a] = bld(v, voff, comp0 + a);
     return r;
 }
-template <typename T> __device__ __forceinline__ void vA_st(const View<T>& v, uint32_t voff, uint32_t comp0, const a8<T>& r)
+template <typename T, int CP = 0>
+__device__ __forceinline__ void vA_st(const View<T>& v, uint32_t voff, uint32_t comp0, const a8<T>& r)
 {
 #pragma unroll
-    for (int a = 0; a < 8; a++) bst(v, voff, comp0 + a, r.v[a]);
+    for (int a = 0; a < 8; a++) bst<T, CP>(v, voff, comp0 + a, r.v[a]);
 }
 
 }  // namespace cpic

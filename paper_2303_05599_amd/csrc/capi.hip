@@ -104,6 +104,21 @@ static void free_all(cpic_ctx* c)
     if (c->own_stream && c->st) hipStreamDestroy(c->st);
 }
 
+// Store policy of the field update.  After the field update a step reads the
+// old state, the aux pieces, the force table, the particle records and the
+// light-like paths; where these and the new state together exceed the 256 MB
+// last-level cache (FP64 at 512^2: 400 MB with 1e5 particles; the FP32 jets
+// workload: 360 MB), the new links and scalar, which the rest of the step
+// does not read, are stored non-temporal so that they do not displace what
+// it does.
+static void set_store_policy(cpic_ctx* c)
+{
+    double reals = (2.0 * c->rps + kAuxReals) * (double)c->V + (double)kPartReals * (double)c->np;
+    if (c->push_table) reals += 48.0 * (double)c->V;
+    if (c->jets) reals += 42.0 * (double)c->V;
+    c->cfg.nt_store = c->aux != nullptr && reals * (double)c->tsz > 256.0 * 1024 * 1024;
+}
+
 extern "C" cpic_status cpic_create(const cpic_glasma_params* gp, const cpic_particle_params* pp, void* hip_stream,
                                    cpic_ctx** out)
 {
@@ -201,6 +216,7 @@ extern "C" cpic_status cpic_create(const cpic_glasma_params* gp, const cpic_part
     c->cfg.split = 3;
     c->cfg.bx = 64;
     c->cfg.by = 4;
+    set_store_policy(c);
     c->pblocks = c->np > 0 ? push_blocks((int)c->np, c->tpp) : 0;
     c->nslots = c->np > 0 ? num_slots(c->sc) : 0;
     if (e == hipSuccess && c->nslots > 0) {
@@ -1179,6 +1195,7 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
     const int cshapes[][2] = {{64, 4}, {32, 8}, {16, 16}, {32, 4}};
     for (const auto& sh : cshapes)
         for (int remap = 0; remap <= 1; remap++) cands.push_back(LaunchCfg{sh[0], sh[1], remap, 1, 3});
+    for (LaunchCfg& cfg : cands) cfg.nt_store = c->cfg.nt_store;
     for (const LaunchCfg& cfg : cands) {
                 HIPCHK(c, launch_field_step<T>(A, B, X, c->N, c->sc, c->d_step, cfg, c->st), "tune");  // warm-up
                 HIPCHK(c, hipEventRecord(e0, c->st), "tune");
@@ -1195,8 +1212,9 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
                 if (per < best_ms) { best_ms = per; best = cfg; }
             }
     c->cfg = best;
-    std::snprintf(line, sizeof line, "best field: %s bx=%d by=%d waves=%d remap=%d %.2f us\n",
-                  kVariantName[best.split], best.bx, best.by, best.waves, best.xcd_remap, best_ms * 1e3);
+    std::snprintf(line, sizeof line, "best field: %s bx=%d by=%d waves=%d remap=%d %.2f us%s\n",
+                  kVariantName[best.split], best.bx, best.by, best.waves, best.xcd_remap, best_ms * 1e3,
+                  best.split == 3 && best.nt_store ? " (non-temporal link stores)" : "");
     rep += line;
     if (c->np > 0 && c->n >= c->sc.n_form && c->n < c->sc.n_max) {
         const size_t rb = sizeof(T) * kPartReals * (size_t)c->np, cb = sizeof(int) * 2 * (size_t)c->np;
@@ -1254,6 +1272,7 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
         c->tpp = best_tpp;
         c->pblocks = push_blocks((int)c->np, c->tpp);
         c->push_table = table;
+        set_store_policy(c);
         if (table) std::snprintf(line, sizeof line, "best push: force table %.2f us\n", best_p * 1e3);
         else std::snprintf(line, sizeof line, "best push: lanes=%d %.2f us\n", best_tpp, best_p * 1e3);
         rep += line;
@@ -1285,11 +1304,11 @@ extern "C" cpic_status cpic_tune(cpic_ctx* c, int32_t reps, char* report, size_t
     return CPIC_OK;
 }
 
-extern "C" cpic_status cpic_get_launch(const cpic_ctx* c, int32_t out[6])
+extern "C" cpic_status cpic_get_launch(const cpic_ctx* c, int32_t out[7])
 {
     if (!c || !out) return CPIC_E_INVALID;
     out[0] = c->cfg.bx; out[1] = c->cfg.by; out[2] = c->cfg.xcd_remap; out[3] = c->cfg.waves; out[4] = c->tpp;
-    out[5] = c->cfg.split;
+    out[5] = c->cfg.split; out[6] = c->cfg.nt_store;
     return CPIC_OK;
 }
 
@@ -1359,6 +1378,7 @@ extern "C" cpic_status cpic_jets_enable(cpic_ctx* c, const cpic_jet_params* jp)
     c->jsamples.clear();
     c->jobs_reduced = 0;
     c->jets = true;
+    set_store_policy(c);
     drop_graphs(c);
     return CPIC_OK;
 }
@@ -1408,6 +1428,7 @@ extern "C" cpic_status cpic_set_push_mode(cpic_ctx* c, int32_t mode)
     if (mode == CPIC_PUSH_TABLE && !c->ftab)
         HIPCHK(c, hipMalloc(&c->ftab, (size_t)48 * c->V * c->tsz), "force table");
     c->push_table = mode == CPIC_PUSH_TABLE;
+    set_store_policy(c);
     drop_graphs(c);
     return CPIC_OK;
 }

@@ -349,7 +349,7 @@ template <typename T, int HS> struct LdsLinks2 {
     }
 };
 
-template <typename T, bool AUX, int BX, int BY>
+template <typename T, bool AUX, int BX, int BY, int CP = 0>
 __device__ __forceinline__ void field_ctile_body(const Fields<T>& in, const Fields<T>& out, T* aux, int N, int tile,
                                                  const Schedule& sc, int* d_step)
 {
@@ -472,16 +472,20 @@ __device__ __forceinline__ void field_ctile_body(const Fields<T>& in, const Fiel
     }
     CPIC_PHASE();
     // drift: U_i <- exp(i (dt/t_half) E_i) U_i ; phi <- phi + dt t_half pi
+    // CP: cache policy of the new links and scalar.  The push reads the old
+    // links and the aux pieces, not the new state: where the three do not fit
+    // in the last-level cache together, the new links and scalar go out
+    // non-temporal so that they do not displace what the push reads next.
     m3<T> U1 = mul(expi(E1, eps_drift), L.U(s, 0));
     if (reunit) U1 = reunitarize(U1);
-    vU_st(vo, g.s, 0, U1);
+    vU_st<T, CP>(vo, g.s, 0, U1);
     CPIC_PHASE();
     m3<T> U2 = mul(expi(E2, eps_drift), L.U(s, 1));
     if (reunit) U2 = reunitarize(U2);
-    vU_st(vo, g.s, 1, U2);
+    vU_st<T, CP>(vo, g.s, 1, U2);
 #pragma unroll
     for (int a = 0; a < 8; a++) PHI.v[a] += phi_drift * PI.v[a];
-    vA_st(vo, g.s, kCompPhi, PHI);
+    vA_st<T, CP>(vo, g.s, kCompPhi, PHI);
     vA_st(vo, g.s, kCompE, E1);
     vA_st(vo, g.s, kCompE + 8, E2);
     vA_st(vo, g.s, kCompPi, PI);
@@ -493,12 +497,12 @@ __device__ __forceinline__ void field_ctile_body(const Fields<T>& in, const Fiel
     }
 }
 
-template <typename T, bool AUX, int BX, int BY>
+template <typename T, bool AUX, int BX, int BY, int CP>
 __global__ __launch_bounds__(BX * BY) void field_ctile_kernel(Fields<T> in, Fields<T> out, T* aux, int N, int remap,
                                                               Schedule sc, int* d_step)
 {
     const int nt = ((N + BX - 1) / BX) * ((N + BY - 1) / BY), tile = logical_block(nt, remap);
-    if (tile < nt) field_ctile_body<T, AUX, BX, BY>(in, out, aux, N, tile, sc, d_step);
+    if (tile < nt) field_ctile_body<T, AUX, BX, BY, CP>(in, out, aux, N, tile, sc, d_step);
 }
 
 // ---------------------------------------------------------------- link-parallel variant
@@ -725,11 +729,14 @@ static hipError_t launch_tile(const Fields<T>& in, const Fields<T>& out, T* aux,
 
 template <typename T, bool AUX, int BX, int BY>
 static hipError_t launch_ctile(const Fields<T>& in, const Fields<T>& out, T* aux, int N, const Schedule& sc,
-                               int* d_step, int remap, hipStream_t st, const KTimer& tm)
+                               int* d_step, int remap, int nt_store, hipStream_t st, const KTimer& tm)
 {
     const int ntiles = ((N + BX - 1) / BX) * ((N + BY - 1) / BY);
     const dim3 g(remap ? 8 * ((ntiles + 7) / 8) : ntiles), blk(BX * BY);
-    klaunch(tm, field_ctile_kernel<T, AUX, BX, BY>, g, blk, st, in, out, aux, N, remap, sc, d_step);
+    if (AUX && nt_store)
+        klaunch(tm, field_ctile_kernel<T, AUX, BX, BY, kStoreNT>, g, blk, st, in, out, aux, N, remap, sc, d_step);
+    else
+        klaunch(tm, field_ctile_kernel<T, AUX, BX, BY, 0>, g, blk, st, in, out, aux, N, remap, sc, d_step);
     return hipGetLastError();
 }
 
@@ -739,11 +746,11 @@ static hipError_t launch_field_step_t(const Fields<T>& in, const Fields<T>& out,
 {
     if (cfg.split == 3) {
         // compressed-link LDS tiles of the instantiated shapes
-        const int r = cfg.xcd_remap;
-        if (cfg.bx == 64 && cfg.by == 4) return launch_ctile<T, AUX, 64, 4>(in, out, aux, N, sc, d_step, r, st, tm);
-        if (cfg.bx == 32 && cfg.by == 8) return launch_ctile<T, AUX, 32, 8>(in, out, aux, N, sc, d_step, r, st, tm);
-        if (cfg.bx == 16 && cfg.by == 16) return launch_ctile<T, AUX, 16, 16>(in, out, aux, N, sc, d_step, r, st, tm);
-        if (cfg.bx == 32 && cfg.by == 4) return launch_ctile<T, AUX, 32, 4>(in, out, aux, N, sc, d_step, r, st, tm);
+        const int r = cfg.xcd_remap, nts = cfg.nt_store;
+        if (cfg.bx == 64 && cfg.by == 4) return launch_ctile<T, AUX, 64, 4>(in, out, aux, N, sc, d_step, r, nts, st, tm);
+        if (cfg.bx == 32 && cfg.by == 8) return launch_ctile<T, AUX, 32, 8>(in, out, aux, N, sc, d_step, r, nts, st, tm);
+        if (cfg.bx == 16 && cfg.by == 16) return launch_ctile<T, AUX, 16, 16>(in, out, aux, N, sc, d_step, r, nts, st, tm);
+        if (cfg.bx == 32 && cfg.by == 4) return launch_ctile<T, AUX, 32, 4>(in, out, aux, N, sc, d_step, r, nts, st, tm);
         return hipErrorInvalidValue;
     }
     if (cfg.split == 2) {

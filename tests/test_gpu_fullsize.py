@@ -14,6 +14,9 @@ library's next state must agree with it: every site and every particle.
     measured 1.1e-5), 1e-5 for the particle records;
   * the jets workload (FP32, 1e6 quarks m = 0.01 GeV, p_T = 10 GeV, with the
     force-table push) and its light-like paths.
+The FP64 headline event and the jets workload run with non-temporal stores
+of the new links and scalar (their working sets exceed the last-level cache),
+the FP32 headline event without.
 """
 import math
 
@@ -77,6 +80,9 @@ def test_headline_event_one_step(precision):
     ctx.step(80)                      # past the formation step 69
     print(f"case headline 512^2 {precision}: {ctx.tune(3).strip().splitlines()[-1]}", flush=True)
     ctx.step(3)                       # steps in the tuned configuration before the checked one
+    # FP64: old state, new state, aux pieces and particles exceed the 256 MB
+    # last-level cache, so the new links go out non-temporal (checked here too)
+    assert ctx.get_launch()["nt_store"] == (1 if prec == cp.FP64 else 0)
     run, st1, P1 = one_step_against_oracle(ctx, 1.27 * a, 69)
     tol = 1e-11 if prec == cp.FP64 else 1e-5
     ftol = 1e-11 if prec == cp.FP64 else 5e-5
@@ -101,6 +107,7 @@ def test_jets_workload_one_step():
     ctx.step(40)
     print(f"case jets 512^2: {ctx.tune(3).strip().splitlines()[-1]}", flush=True)
     assert ctx.push_mode() in (cp.PUSH_TABLE, cp.PUSH_GATHER)
+    assert ctx.get_launch()["nt_store"] == 1
     ctx.step(3)
     jets = oracle.Jets(N, DT, 0, 0.3, 1)
     run, st1, P1 = one_step_against_oracle(ctx, 0.01 * a, 0, jets)

@@ -106,9 +106,15 @@ template <typename T> __device__ a8<T> renorm_charge(const a8<T>& Q, const doubl
 // Six field jobs (cellfields.h).  The TPP waves that share a group of 64
 // particles split them; the owner wave (role 0) meanwhile rotates Q, and
 // contracts everything with Q at the end.
-// Job -> (wave, LDS slot within the wave), 4 bits per job in job order
-//   TPP 2: owner E_x E_eta B_x B_y | wave 1: E_y (slot 0), B_eta (slot 1)
-//   TPP 4: owner E_eta B_x B_y | 1: E_x | 2: E_y | 3: B_eta
+// TPP 2, job -> (wave, LDS slot within the wave), 4 bits per job in job order:
+//   owner E_x E_eta B_x B_y | wave 1: E_y (slot 0), B_eta (slot 1)
+// TPP 4 (push_helper4): the owner only rotates Q; the helpers split the jobs
+// by the link they transport with, so that each issues all its gathers at
+// once and transports with at most two links:
+//   1: U_x(c-x): E_x, B_y, the clover leaf U_x(c-x)^+ G(c-x) U_x(c-x)
+//   2: U_y(c-y): E_y, B_x, the leaf U_y(c-y)^+ G(c-y) U_y(c-y)
+//   3: U_y(c-x-y), U_x(c-x): the leaf through c-x-y plus G(c), and E_eta
+// B_eta is the sum of the three waves' leaves (the transport is linear).
 constexpr uint32_t pack_jobs(int e_x, int e_y, int e_eta, int b_x, int b_y, int b_eta)
 {
     return (uint32_t)e_x | (uint32_t)e_y << 4 | (uint32_t)e_eta << 8 | (uint32_t)b_x << 12 | (uint32_t)b_y << 16 |
@@ -116,7 +122,7 @@ constexpr uint32_t pack_jobs(int e_x, int e_y, int e_eta, int b_x, int b_y, int 
 }
 template <int TPP> __device__ __forceinline__ int job_wave(int j)
 {
-    constexpr uint32_t tab = TPP == 2 ? pack_jobs(0, 1, 0, 0, 0, 1) : TPP == 4 ? pack_jobs(1, 2, 0, 0, 0, 3) : 0;
+    constexpr uint32_t tab = TPP == 2 ? pack_jobs(0, 1, 0, 0, 0, 1) : 0;
     return (int)((tab >> (4 * j)) & 15u);
 }
 template <int TPP> __device__ __forceinline__ int job_slot(int j)
@@ -124,7 +130,49 @@ template <int TPP> __device__ __forceinline__ int job_slot(int j)
     constexpr uint32_t tab = TPP == 2 ? pack_jobs(0, 0, 0, 0, 0, 1) : 0;
     return (int)((tab >> (4 * j)) & 15u);
 }
-template <int TPP> constexpr int kSlots = TPP == 2 ? 2 : 1;  // LDS slots per helper wave
+template <int TPP> constexpr int kSlots = TPP == 4 ? 3 : (TPP == 2 ? 2 : 1);  // LDS slots per helper wave
+
+// The field vectors of helper wave `role` (1..3) of a four-wave group, for
+// slots 0..2 (zero where the job is inactive at step n).
+template <typename T>
+__device__ __forceinline__ void push_helper4(int role, const View<T>& A, const View<T>& B, const View<T>& X,
+                                             const Cell& c, int n, T t, bool eonly, a8<T> (&F)[3])
+{
+    const T qe = T(1) / (T(4) * t), qb = T(1) / (T(2) * t);
+    const bool on_e = n > 0, on_bt = n > 0 && !eonly, on_be = !eonly;
+    if (role == 3) {
+        const m3<T> Ly = vU(A, c.s_xmym, 1), Lx = vU(A, c.s_xm, 0);
+        const a8<T> g12 = vA(X, c.s_xmym, kAuxG), g0 = vA(X, c.s, kAuxG);
+        // E_eta from P (n > 0) or from pi(1/2) (n = 0), through one selected buffer
+        const bool first = n == 0;
+        const a8<T> Pv = vA(first ? B : X, c.s, first ? (uint32_t)kCompPi : (uint32_t)kAuxP);
+        const a8<T> leaf = transport_adj(Lx, transport_adj(Ly, g12));
+        const T h = first ? T(1) : T(0.5);
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            F[0].v[q] = on_be ? T(-0.25) * (g0.v[q] + leaf.v[q]) : T(0);
+            F[1].v[q] = h * Pv.v[q];
+            F[2].v[q] = T(0);
+        }
+        return;
+    }
+    // role 1: direction x, role 2: direction y
+    const int i = role - 1;
+    const uint32_t sb = i == 0 ? c.s_xm : c.s_ym;
+    const uint32_t cs = i == 0 ? kAuxS1 : kAuxS2;
+    const m3<T> L = vU(A, sb, i);
+    const a8<T> here = vA(X, c.s, cs), back = vA(X, sb, cs), gb = vA(X, sb, kAuxG);
+    const a8<T> D = vA(X, c.s, i == 0 ? kAuxDx : kAuxDy);
+    const a8<T> tb = transport_adj(L, back), tg = transport_adj(L, gb);
+    // B_y = +(1/2t) D_x, B_x = -(1/2t) D_y
+    const T qd = i == 0 ? qb : -qb;
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+        F[0].v[q] = on_e ? qe * (here.v[q] + tb.v[q]) : T(0);
+        F[1].v[q] = on_bt ? qd * D.v[q] : T(0);
+        F[2].v[q] = on_be ? T(-0.25) * tg.v[q] : T(0);
+    }
+}
 
 // TPP wavefronts per group of 64 particles: a block of 256 threads holds
 // 256 / TPP particles.  Wave w works on particle group w / TPP in role
@@ -191,29 +239,33 @@ __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& 
     const Cell cell = make_cell<T>(nx, ny, N);
     a8<T> Q;
     T f[6] = {0, 0, 0, 0, 0, 0};
+    T px = 0, py = 0, pe = 0, eta = 0;
     if (role == 0) {
 #pragma unroll
         for (int q = 0; q < 8; q++) Q.v[q] = bld(R, po, PQ0 + q);
+        px = bld(R, po, PPX);
+        py = bld(R, po, PPY);
+        pe = bld(R, po, PPETA);
+        eta = bld(R, po, PETA_);
         if (!LOGQ && !a.is_static && live && n > a.sc.n_form) {
-            int cx = bld_i(C, pi, 0), cy = bld_i(C, pi, 1);
-            int d[2] = {nx - cx, ny - cy};
-#pragma unroll
-            for (int ax = 0; ax < 2; ax++) {
-                int dd = d[ax];
-                if (dd > N / 2) dd -= N;
-                if (dd < -N / 2) dd += N;
-                if (dd == 1) {
-                    Q = rotate(vU(A, (uint32_t)(cy * N + cx) * (uint32_t)sizeof(T), ax), Q);
-                } else if (dd == -1) {
-                    const int cb = ax == 0 ? cy * N + wrap(cx - 1, N) : wrap(cy - 1, N) * N + cx;
-                    Q = transport(vU(A, (uint32_t)cb * (uint32_t)sizeof(T), ax), Q);   // U Q U^+
-                } else if (dd != 0) {
-                    atomicAdd(err, 1);
-                }
-                if (ax == 0) cx = nx; else cy = ny;
-            }
+            // the links crossed since the last step (x first, then y from the
+            // new column) and the scalar at the cell, gathered together
+            const int cx = bld_i(C, pi, 0), cy = bld_i(C, pi, 1);
             const T deta = bld(R, po, PDETA);
-            if (deta != T(0)) Q = rotate(expi(vA(A, cell.s, kCompPhi), deta), Q);
+            int dx = nx - cx, dy = ny - cy;
+            dx = dx > N / 2 ? dx - N : (dx < -N / 2 ? dx + N : dx);
+            dy = dy > N / 2 ? dy - N : (dy < -N / 2 ? dy + N : dy);
+            if (dx < -1 || dx > 1) atomicAdd(err, 1);
+            if (dy < -1 || dy > 1) atomicAdd(err, 1);
+            m3<T> Lx, Ly;
+            if (dx != 0) Lx = vU(A, (uint32_t)(cy * N + (dx > 0 ? cx : wrap(cx - 1, N))) * (uint32_t)sizeof(T), 0);
+            if (dy != 0) Ly = vU(A, (uint32_t)((dy > 0 ? cy : wrap(cy - 1, N)) * N + nx) * (uint32_t)sizeof(T), 1);
+            const a8<T> ph = vA(A, cell.s, kCompPhi);
+            if (dx == 1) Q = rotate(Lx, Q);
+            else if (dx == -1) Q = transport(Lx, Q);  // U Q U^+
+            if (dy == 1) Q = rotate(Ly, Q);
+            else if (dy == -1) Q = transport(Ly, Q);
+            if (deta != T(0)) Q = rotate(expi(ph, deta), Q);
         }
         // charges are renormalised in single precision only (double-precision
         // contexts never schedule it); leaving it out of the double kernel
@@ -233,6 +285,14 @@ __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& 
                 for (int kk = 0; kk < 6; kk++) f[kk] += kk == k ? dq : T(0);
             }
         }
+    } else if (TPP == 4) {
+        const int row0 = (grp * (TPP - 1) + role - 1) * S * 8;
+        a8<T> F[3];
+        push_helper4<T>(role, A, B, X, cell, n, t, eonly, F);
+#pragma unroll
+        for (int k = 0; k < 3; k++)
+#pragma unroll
+            for (int q = 0; q < 8; q++) shF[row0 + 8 * k + q][lane] = live ? F[k].v[q] : T(0);
     } else if (TPP > 1) {
         const int row0 = (grp * (TPP - 1) + role - 1) * S * 8;
 #pragma unroll
@@ -248,7 +308,25 @@ __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& 
             }
         }
     }
-    if (TPP > 1) {
+    if (TPP == 4) {
+        __syncthreads();
+        if (role == 0 && live) {
+            // Q . (vector in helper wave w, slot k)
+            auto qdot = [&](int w, int k) {
+                const int r = ((grp * (TPP - 1) + w - 1) * S + k) * 8;
+                T dq = Q.v[0] * shF[r][lane];
+#pragma unroll
+                for (int q = 1; q < 8; q++) dq = fmaT(Q.v[q], shF[r + q][lane], dq);
+                return dq;
+            };
+            f[kJobEx] = qdot(1, 0);
+            f[kJobBy] = qdot(1, 1);
+            f[kJobEy] = qdot(2, 0);
+            f[kJobBx] = qdot(2, 1);
+            f[kJobEeta] = qdot(3, 1);
+            f[kJobBeta] = qdot(3, 0) + qdot(1, 2) + qdot(2, 2);
+        }
+    } else if (TPP > 1) {
         __syncthreads();
         if (role == 0 && live) {
 #pragma unroll
@@ -271,8 +349,6 @@ __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& 
     }
     double obs[4] = {0, 0, 0, 0};
     if (role == 0 && live) {
-        T px = bld(R, po, PPX), py = bld(R, po, PPY), pe = bld(R, po, PPETA);
-        T eta = bld(R, po, PETA_);
         if (a.is_static) {
             px += dt * f[0];
             py += dt * f[1];

@@ -268,18 +268,23 @@ cpic_status cpic_set_push_mode(cpic_ctx* ctx, int32_t mode);
 cpic_status cpic_get_push_mode(const cpic_ctx* ctx, int32_t* mode);
 
 /* Current launch configuration: out = {bx, by, xcd_remap, waves, push lanes,
- * variant, non-temporal link stores}.  The last is chosen at creation (and by
- * cpic_jets_enable): 1 where the old state, the new state and the per-site
- * field pieces the push reads exceed the 256 MB last-level cache together
- * (FP64 at 512^2), so that the new links and scalar, which the push does not
- * read, bypass it; results are the same either way. */
+ * variant, non-temporal link stores}.  The last is set at creation (and by
+ * cpic_jets_enable, cpic_set_push_mode): 1 where the state, the new state
+ * and what the rest of the step reads exceed the 256 MB last-level cache
+ * together (FP64 at 512^2), so that the new links and scalar, which the push
+ * does not read, bypass it; cpic_tune may change it.  Results are the same
+ * either way. */
 cpic_status cpic_get_launch(const cpic_ctx* ctx, int32_t out[7]);
 
 /* Launch tuner: times every candidate field-kernel configuration (block shape x
  * occupancy target x XCD mapping) in place on the current state without
  * advancing it (the free buffer is overwritten), and, once particles are being
- * pushed, the push lanes on a saved copy of the particles; keeps the fastest.
- * reps launches per candidate.  report (may be NULL) receives a text table.
+ * pushed, the push lanes and the force table on a saved copy of the
+ * particles.  Then the three fastest field configurations, each with both
+ * store policies, run two whole steps from a saved copy of the state (one
+ * extra field buffer set, allocated for the duration), which is restored
+ * afterwards; the fastest step decides.  reps launches per candidate.  report
+ * (may be NULL) receives a text table whose last line is the choice.
  * Synchronises. */
 cpic_status cpic_tune(cpic_ctx* ctx, int32_t reps, char* report, size_t cap);
 

@@ -1180,6 +1180,7 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
     const int shapes[][2] = {{64, 4}, {64, 2}, {64, 1}, {128, 2}, {128, 1}, {256, 1}, {32, 8}, {32, 4}, {16, 16}};
     LaunchCfg best = c->cfg;
     double best_ms = 1e300;
+    std::vector<std::pair<double, LaunchCfg>> timed;
     char line[160];
     std::vector<LaunchCfg> cands;
     for (const auto& sh : shapes)
@@ -1210,6 +1211,7 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
                               kVariantName[cfg.split], cfg.bx, cfg.by, cfg.waves, cfg.xcd_remap, per * 1e3);
                 rep += line;
                 if (per < best_ms) { best_ms = per; best = cfg; }
+                timed.push_back({per, cfg});
             }
     c->cfg = best;
     std::snprintf(line, sizeof line, "best field: %s bx=%d by=%d waves=%d remap=%d %.2f us%s\n",
@@ -1276,6 +1278,87 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
         if (table) std::snprintf(line, sizeof line, "best push: force table %.2f us\n", best_p * 1e3);
         else std::snprintf(line, sizeof line, "best push: lanes=%d %.2f us\n", best_tpp, best_p * 1e3);
         rep += line;
+    }
+    // In the step: the field kernel shares the caches with the push and the
+    // light-like paths, which the isolated timings above do not see.  The
+    // three fastest field launches, each with both store policies, run two
+    // real steps (both buffer parities) from the current state, which is
+    // restored after every trial; the fastest step pair decides.
+    if (c->n + 2 <= c->sc.n_max && timed.size() > 0) {
+        std::sort(timed.begin(), timed.end(),
+                  [](const std::pair<double, LaunchCfg>& a, const std::pair<double, LaunchCfg>& b) { return a.first < b.first; });
+        const size_t fbytes = (size_t)c->rps * c->V * c->tsz;
+        const size_t rb = sizeof(T) * kPartReals * (size_t)c->np, cb = sizeof(int) * 2 * (size_t)c->np;
+        const size_t wb = (size_t)18 * c->V * c->tsz, fb = (size_t)24 * c->V * c->tsz;
+        void *bk = nullptr, *bw = nullptr, *bf = nullptr;
+        hipError_t he = hipMalloc(&bk, fbytes);
+        if (he == hipSuccess && c->jets) he = hipMalloc(&bw, wb);
+        if (he == hipSuccess && c->jets) he = hipMalloc(&bf, fb);
+        auto release = [&]() { hipFree(bk); hipFree(bw); hipFree(bf); };
+        if (he != hipSuccess) {
+            release();
+            rep += "step trials skipped: no memory for the state copy\n";
+        } else {
+            const int zero = 0;
+            auto copy = [&](void* dst, const void* src, size_t bytes) {
+                return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->st);
+            };
+            hipError_t te = copy(bk, c->fbuf[c->cur], fbytes);
+            if (te == hipSuccess && c->np > 0) te = copy(c->sb.r2, c->pr, rb);
+            if (te == hipSuccess && c->np > 0) te = copy(c->sb.cell2, c->pcell, cb);
+            if (te == hipSuccess && c->jets) te = copy(bw, c->jW, wb);
+            if (te == hipSuccess && c->jets) te = copy(bf, c->jF, fb);
+            auto restore = [&]() {
+                hipError_t r = copy(c->fbuf[c->cur], bk, fbytes);
+                if (r == hipSuccess && c->np > 0) r = copy(c->pr, c->sb.r2, rb);
+                if (r == hipSuccess && c->np > 0) r = copy(c->pcell, c->sb.cell2, cb);
+                if (r == hipSuccess && c->jets) r = copy(c->jW, bw, wb);
+                if (r == hipSuccess && c->jets) r = copy(c->jF, bf, fb);
+                if (r == hipSuccess) r = hipStreamSynchronize(c->st);
+                if (r == hipSuccess) r = hipMemcpy(c->d_step, &c->n, sizeof(int), hipMemcpyHostToDevice);
+                if (r == hipSuccess) r = hipMemcpy(c->d_err, &zero, sizeof(int), hipMemcpyHostToDevice);
+                return r;
+            };
+            const LaunchCfg keep = c->cfg;
+            LaunchCfg best_step = keep;
+            double best_pair = 1e300;
+            const size_t ntop = std::min<size_t>(3, timed.size());
+            for (size_t k = 0; k < ntop && te == hipSuccess; k++)
+                for (int nt = 0; nt <= 1 && te == hipSuccess; nt++) {
+                    LaunchCfg cfg = timed[k].second;
+                    if (cfg.split != 3 && nt == 1) continue;  // the store policy exists for the compressed tiles
+                    cfg.nt_store = cfg.split == 3 ? nt : 0;
+                    c->cfg = cfg;
+                    double tot = 0;
+                    for (int r = 0; r <= reps && te == hipSuccess; r++) {
+                        te = hipEventRecord(e0, c->st);
+                        cpic_status ls = CPIC_OK;
+                        if (te == hipSuccess) ls = launch_one<T>(c, c->cur, false);
+                        if (te == hipSuccess && !ls) ls = launch_one<T>(c, c->cur ^ 1, false);
+                        if (ls) { c->cfg = keep; restore(); release(); return ls; }
+                        if (te == hipSuccess) te = hipEventRecord(e1, c->st);
+                        if (te == hipSuccess) te = hipEventSynchronize(e1);
+                        float ms = 0;
+                        if (te == hipSuccess) te = hipEventElapsedTime(&ms, e0, e1);
+                        if (te == hipSuccess) te = restore();
+                        if (r > 0) tot += ms;
+                    }
+                    if (te != hipSuccess) break;
+                    const double per = tot / reps / 2;
+                    std::snprintf(line, sizeof line, "step with field %s bx=%d by=%d waves=%d remap=%d nt=%d: %.2f us\n",
+                                  kVariantName[cfg.split], cfg.bx, cfg.by, cfg.waves, cfg.xcd_remap, cfg.nt_store,
+                                  per * 1e3);
+                    rep += line;
+                    if (per < best_pair) { best_pair = per; best_step = cfg; }
+                }
+            release();
+            if (te != hipSuccess) { c->cfg = keep; return hip_fail(c, te, "tune"); }
+            c->cfg = best_step;
+            std::snprintf(line, sizeof line, "chosen: field %s bx=%d by=%d waves=%d remap=%d nt=%d, step %.2f us\n",
+                          kVariantName[best_step.split], best_step.bx, best_step.by, best_step.waves,
+                          best_step.xcd_remap, best_step.nt_store, best_pair * 1e3);
+            rep += line;
+        }
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);

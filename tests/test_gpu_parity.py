@@ -381,15 +381,20 @@ def test_tuner_leaves_state_unchanged():
     p = dict(n=5000, mass_GeV=1.27, pT_min_GeV=1.0, pT_max_GeV=1.0, azimuth_uniform=1, tau_form_fm=0.0, rep=0, seed=10)
     a_ctx, b_ctx = cp.Context(g, p), cp.Context(g, p)
     for c in (a_ctx, b_ctx):
+        c.enable_jets(x_offset=0.3)
         c.init_mv()
         c.step(20)
     before = a_ctx.state()
     rep = a_ctx.tune(2)
-    assert "best field" in rep and "best push" in rep
+    # isolated trials, then whole steps from a saved copy of the state
+    assert "best field" in rep and "best push" in rep and "step with field" in rep
+    assert rep.strip().splitlines()[-1].startswith("chosen:")
     after = a_ctx.state()
     for k in before:
         assert np.array_equal(before[k], after[k]), k
     assert np.array_equal(a_ctx.get_state(cp.STATE_PARTICLES), b_ctx.get_state(cp.STATE_PARTICLES))
+    for w in (cp.STATE_JET_W, cp.STATE_JET_F):
+        assert np.array_equal(a_ctx.get_state(w), b_ctx.get_state(w))
     a_ctx.step(20)
     b_ctx.step(20)
     # the tuned launch may use another decomposition of the same stencil, whose
@@ -397,6 +402,9 @@ def test_tuner_leaves_state_unchanged():
     for k in ("U", "phi", "E", "pi"):
         assert rel_err(a_ctx.state()[k], b_ctx.state()[k]) < 1e-12, k
     assert rel_err(a_ctx.get_state(cp.STATE_PARTICLES), b_ctx.get_state(cp.STATE_PARTICLES)) < 1e-12
+    assert rel_err(a_ctx.get_state(cp.STATE_JET_F), b_ctx.get_state(cp.STATE_JET_F)) < 1e-12
+    oa, ob = a_ctx.observables(), b_ctx.observables()
+    assert oa.shape == ob.shape and rel_err(oa, ob) < 1e-12
 
 
 def test_force_table_matches_gather_push():

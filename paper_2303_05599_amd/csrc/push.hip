@@ -436,8 +436,11 @@ __device__ __forceinline__ int push_step(int* d_step, int blk)
     return n;
 }
 
+// at most 168 VGPRs (three waves per SIMD): the double-precision four-wave
+// push otherwise takes 170 and drops to two; the logarithm variant keeps the
+// compiler's choice (it would spill)
 template <typename T, int TPP, bool LOGQ = false>
-__global__ __launch_bounds__(256) void push_kernel(Fields<T> Af, Fields<T> Bf, const T* aux, Parts<T> P, PushArgs a,
+__global__ __launch_bounds__(256, LOGQ ? 1 : 3) void push_kernel(Fields<T> Af, Fields<T> Bf, const T* aux, Parts<T> P, PushArgs a,
                                                    int* d_step, double* partials, int* err)
 {
     const int nblocks = (a.np + kPushPPB<TPP> - 1) / kPushPPB<TPP>;
@@ -489,7 +492,7 @@ __global__ __launch_bounds__(256) void force_table_kernel(Fields<T> Af, Fields<T
 
 // batched events: logical block g works on particle block map[g].y of event map[g].x
 template <typename T, int TPP>
-__global__ __launch_bounds__(256) void batch_push_kernel(const EventDesc* __restrict__ ev, const int2* __restrict__ map,
+__global__ __launch_bounds__(256, 3) void batch_push_kernel(const EventDesc* __restrict__ ev, const int2* __restrict__ map,
                                                          int total)
 {
     const int g = xcd_block(total);

@@ -95,7 +95,9 @@ typedef struct {
 /*
  * Test-particle species (toy-model initial conditions of Sec. III.B, colour
  * charges from the Haar measure of Sec. IV.B).
- *   n                number of test particles (0: fields only)
+ *   n                number of test particles (0: fields only); at most
+ *                    14,913,080 in FP64 and 29,826,161 in FP32 (the records,
+ *                    18 reals each, stay below 2 GiB), else CPIC_E_INVALID
  *   mass_GeV         mass; INFINITY selects the static (infinite-mass) branch
  *                    of Sec. V.A: no motion, no colour rotation
  *   pT_min/max_GeV   initial |p_T| uniform in [min, max) (equal: fixed)

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -136,7 +137,13 @@ extern "C" cpic_status cpic_create(const cpic_glasma_params* gp, const cpic_part
     if (!pp) pp = &none;
     if (gp->n_colors == 2 && pp->n > 0 && pp->color_update != CPIC_COLOR_ROTATE)
         return fail(nullptr, CPIC_E_INVALID, "cpic_create: the SU(2) variant rotates the charges with the links");
-    if (pp->n < 0 || pp->n > (int64_t)1 << 30) return fail(nullptr, CPIC_E_INVALID, "cpic_create: bad particle count");
+    // particle records are addressed through 32-bit buffer offsets: a
+    // component array and the whole record set must stay below 2 GiB
+    const int64_t tsz_p = gp->precision == CPIC_FP64 ? 8 : 4;
+    if (pp->n < 0 || pp->n > (int64_t)INT32_MAX / (kPartReals * tsz_p))
+        return fail(nullptr, CPIC_E_INVALID,
+                    "cpic_create: particle count out of range (records must stay below 2 GiB: at most " +
+                        std::to_string((int64_t)INT32_MAX / (kPartReals * tsz_p)) + " in this precision)");
     if (pp->n > 0 && (!(pp->mass_GeV > 0) || pp->pT_min_GeV < 0 || pp->pT_max_GeV < pp->pT_min_GeV ||
                       pp->tau_form_fm < 0 || (pp->rep != CPIC_REP_FUND && pp->rep != CPIC_REP_ADJ) ||
                       (pp->color_update != CPIC_COLOR_ROTATE && pp->color_update != CPIC_COLOR_LOG)))

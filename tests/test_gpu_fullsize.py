@@ -13,7 +13,11 @@ library's next state must agree with it: every site and every particle.
     nearly-identity plaquettes with cancellation, then t dt ~ 10 scales it;
     measured 1.1e-5), 1e-5 for the particle records;
   * the jets workload (FP32, 1e6 quarks m = 0.01 GeV, p_T = 10 GeV, with the
-    force-table push) and its light-like paths.
+    force-table push) and its light-like paths;
+  * the largest sizes the library accepts: a 1024^2 lattice with the largest
+    double-precision particle count (14,913,080, records just below 2 GiB),
+    every site and a random sample of 4096 particles (the oracle pushes
+    particles independently of each other).
 The FP64 headline event and the jets workload run with non-temporal stores
 of the new links and scalar (their working sets exceed the last-level cache),
 the FP32 headline event without.
@@ -119,4 +123,37 @@ def test_jets_workload_one_step():
     assert rel_err(P1[same], run.P[same]) <= 1e-5
     assert rel_err(ctx.get_state(cp.STATE_JET_F), jets.F) <= 1e-5
     assert rel_err(ctx.get_state(cp.STATE_JET_W), jets.W) <= 1e-5
+    ctx.close()
+
+
+def test_max_sizes_one_step():
+    Nmax, npmax = 1024, (2**31 - 1) // (18 * 8)
+    g = dict(N=Nmax, L_fm=12.0, g2mu_GeV=2.0, m_ir_GeV=0.2, uv_GeV=10.0, n_sheets=4, dtau_over_a=DT,
+             tau_max_fm=16 * DT * 12.0 / Nmax, seed=5, precision=cp.FP64, reunit_every=0, record_every=8)
+    a = oracle.lattice_spacing(12.0, Nmax)
+    p = dict(n=npmax, mass_GeV=1.27, pT_min_GeV=0.0, pT_max_GeV=2.0, azimuth_uniform=1, tau_form_fm=0.0, rep=0, seed=6)
+    with pytest.raises(cp.CpicError):
+        cp.Context(g, dict(p, n=npmax + 1))
+    ctx = cp.Context(g, p)
+    ctx.init_mv()
+    ctx.step(6)
+    print(f"case max sizes {Nmax}^2, {npmax} particles: {ctx.tune(2).strip().splitlines()[-1]}", flush=True)
+    ctx.step(2)
+    st = ctx.state()
+    P = ctx.get_state(cp.STATE_PARTICLES)
+    assert P.shape[0] == npmax
+    n0 = ctx.n
+    ctx.step(1)
+    P1 = ctx.get_state(cp.STATE_PARTICLES)
+    idx = np.sort(np.random.default_rng(7).choice(npmax, 4096, replace=False))
+    idx[-1] = npmax - 1                              # the last record
+    run = oracle.Run(Nmax, DT, st, P[idx], mhat=1.27 * a, n_form=0, n0=n0)
+    del P
+    run.step()
+    assert run.errors == 0
+    st1 = ctx.state()
+    for k in ("U", "phi", "E", "pi"):
+        assert rel_err(st1[k], run.st[k]) <= 1e-11, (k, rel_err(st1[k], run.st[k]))
+    assert np.array_equal(P1[idx, 14:16], run.P[:, 14:16])
+    assert rel_err(P1[idx], run.P) <= 1e-11
     ctx.close()

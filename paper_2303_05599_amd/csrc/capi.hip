@@ -1179,6 +1179,9 @@ static const char* const kVariantName[4] = {"site", "link", "tile", "ctile"};
 
 template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::string& rep)
 {
+    // the trial pushes may count cell jumps: the counter is put back afterwards
+    int err0 = 0;
+    HIPCHK(c, hipMemcpy(&err0, c->d_err, sizeof(int), hipMemcpyDeviceToHost), "tune");
     const Fields<T> A = F<T>(c, c->cur), B = F<T>(c, c->cur ^ 1);
     T* const X = static_cast<T*>(c->aux);
     hipEvent_t e0, e1;
@@ -1274,8 +1277,7 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
             if (per < best_p) { best_p = per; table = true; }
         }
         HIPCHK(c, hipStreamSynchronize(c->st), "tune");
-        int err = 0;
-        HIPCHK(c, hipMemcpy(c->d_err, &err, sizeof(int), hipMemcpyHostToDevice), "tune");
+        HIPCHK(c, hipMemcpy(c->d_err, &err0, sizeof(int), hipMemcpyHostToDevice), "tune");
         // the trial pushes advanced the step counter: put it back
         HIPCHK(c, hipMemcpy(c->d_step, &c->n, sizeof(int), hipMemcpyHostToDevice), "tune");
         c->tpp = best_tpp;
@@ -1306,7 +1308,6 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
             release();
             rep += "step trials skipped: no memory for the state copy\n";
         } else {
-            const int zero = 0;
             auto copy = [&](void* dst, const void* src, size_t bytes) {
                 return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->st);
             };
@@ -1323,7 +1324,7 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
                 if (r == hipSuccess && c->jets) r = copy(c->jF, bf, fb);
                 if (r == hipSuccess) r = hipStreamSynchronize(c->st);
                 if (r == hipSuccess) r = hipMemcpy(c->d_step, &c->n, sizeof(int), hipMemcpyHostToDevice);
-                if (r == hipSuccess) r = hipMemcpy(c->d_err, &zero, sizeof(int), hipMemcpyHostToDevice);
+                if (r == hipSuccess) r = hipMemcpy(c->d_err, &err0, sizeof(int), hipMemcpyHostToDevice);
                 return r;
             };
             const LaunchCfg keep = c->cfg;

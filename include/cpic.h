@@ -242,7 +242,8 @@ cpic_status cpic_load(cpic_ctx* ctx, const char* path);
  *      in LDS first (bx x by one of 64x4, 32x4, 64x2, 32x8, 16x8; waves 1);
  *   3  as 2 with only the first two rows of each link in LDS (the third is
  *      rebuilt) and the scalars read from global memory, so that two
- *      workgroups share a CU (64x4, 32x8, 16x16, 32x4; waves 1).
+ *      workgroups share a CU (64x4, 32x8, 16x16, 32x4; waves 1), or one
+ *      workgroup of 512 threads with a smaller halo (64x8).
  * Used by the tuner; takes effect for the next launch. */
 cpic_status cpic_set_launch(cpic_ctx* ctx, int32_t bx, int32_t by, int32_t xcd_remap, int32_t waves,
                             int32_t variant);

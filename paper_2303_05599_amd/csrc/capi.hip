@@ -1128,8 +1128,9 @@ extern "C" cpic_status cpic_set_launch(cpic_ctx* c, int32_t bx, int32_t by, int3
         if (waves != 1) return fail(c, CPIC_E_INVALID, "cpic_set_launch: LDS tiles take waves = 1");
     } else if (variant == 3) {
         const bool shape = (bx == 64 && by == 4) || (bx == 32 && by == 8) || (bx == 16 && by == 16) ||
-                           (bx == 32 && by == 4);
-        if (!shape) return fail(c, CPIC_E_INVALID, "cpic_set_launch: compressed LDS tiles are 64x4, 32x8, 16x16 or 32x4");
+                           (bx == 32 && by == 4) || (bx == 64 && by == 8);
+        if (!shape)
+            return fail(c, CPIC_E_INVALID, "cpic_set_launch: compressed LDS tiles are 64x4, 32x8, 16x16, 32x4 or 64x8");
         if (waves != 1) return fail(c, CPIC_E_INVALID, "cpic_set_launch: LDS tiles take waves = 1");
     } else if (variant == 0) {
         if (bx <= 0 || by <= 0 || bx * by > 256 || (bx * by) % 64 != 0)
@@ -1203,7 +1204,7 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
     const int tshapes[][2] = {{64, 4}, {32, 4}, {64, 2}, {32, 8}, {16, 8}};
     for (const auto& sh : tshapes)
         for (int remap = 0; remap <= 1; remap++) cands.push_back(LaunchCfg{sh[0], sh[1], remap, 1, 2});
-    const int cshapes[][2] = {{64, 4}, {32, 8}, {16, 16}, {32, 4}};
+    const int cshapes[][2] = {{64, 4}, {32, 8}, {16, 16}, {32, 4}, {64, 8}};
     for (const auto& sh : cshapes)
         for (int remap = 0; remap <= 1; remap++) cands.push_back(LaunchCfg{sh[0], sh[1], remap, 1, 3});
     for (LaunchCfg& cfg : cands) cfg.nt_store = c->cfg.nt_store;

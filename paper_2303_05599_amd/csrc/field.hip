@@ -751,6 +751,7 @@ static hipError_t launch_field_step_t(const Fields<T>& in, const Fields<T>& out,
         if (cfg.bx == 32 && cfg.by == 8) return launch_ctile<T, AUX, 32, 8>(in, out, aux, N, sc, d_step, r, nts, st, tm);
         if (cfg.bx == 16 && cfg.by == 16) return launch_ctile<T, AUX, 16, 16>(in, out, aux, N, sc, d_step, r, nts, st, tm);
         if (cfg.bx == 32 && cfg.by == 4) return launch_ctile<T, AUX, 32, 4>(in, out, aux, N, sc, d_step, r, nts, st, tm);
+        if (cfg.bx == 64 && cfg.by == 8) return launch_ctile<T, AUX, 64, 8>(in, out, aux, N, sc, d_step, r, nts, st, tm);
         return hipErrorInvalidValue;
     }
     if (cfg.split == 2) {

@@ -59,14 +59,15 @@ LAUNCHES = {"site64x4": (64, 4, 1, 1, 0), "site256x1w2": (256, 1, 0, 2, 0), "lin
             "link32x4w2": (32, 4, 0, 2, 1), "tile64x4": (64, 4, 1, 1, 2), "tile32x8": (32, 8, 0, 1, 2),
             "tile16x8": (16, 8, 1, 1, 2), "tile64x2": (64, 2, 0, 1, 2), "tile32x4": (32, 4, 1, 1, 2),
             "ctile64x4": (64, 4, 1, 1, 3), "ctile32x8": (32, 8, 0, 1, 3), "ctile16x16": (16, 16, 1, 1, 3),
-            "ctile32x4": (32, 4, 0, 1, 3)}
+            "ctile32x4": (32, 4, 0, 1, 3), "ctile64x8": (64, 8, 1, 1, 3)}
 
 
 @pytest.mark.parametrize("N,n0,launch", [(32, 3, "site64x4"), (96, 0, "site64x4"), (48, 1, "site64x4"),
                                          (96, 2, "link128x1"), (48, 1, "link32x4w2"), (32, 5, "site256x1w2"),
                                          (96, 1, "tile64x4"), (48, 2, "tile32x8"), (12, 0, "tile16x8"),
                                          (36, 3, "tile64x2"), (64, 1, "tile32x4"), (96, 2, "ctile64x4"),
-                                         (48, 1, "ctile32x8"), (12, 0, "ctile16x16"), (36, 3, "ctile32x4")])
+                                         (48, 1, "ctile32x8"), (12, 0, "ctile16x16"), (36, 3, "ctile32x4"),
+                                         (72, 2, "ctile64x8")])
 def test_field_leapfrog_fp64_random_state(N, n0, launch):
     """50 fused kick+drift steps from a random state; N = 96, 48, 36 and 12 leave ragged
     tiles (12 is smaller than the 16 x 8 tile); site-parallel, link-parallel and LDS

@@ -284,9 +284,11 @@ cpic_status cpic_get_launch(const cpic_ctx* ctx, int32_t out[7]);
  * advancing it (the free buffer is overwritten), and, once particles are being
  * pushed, the push lanes and the force table on a saved copy of the
  * particles.  Then the three fastest field configurations, each with both
- * store policies, run two whole steps from a saved copy of the state (one
- * extra field buffer set, allocated for the duration), which is restored
- * afterwards; the fastest step decides.  reps launches per candidate.  report
+ * store policies, and the configuration before tuning run two whole steps
+ * from a saved copy of the state (one extra field buffer set, allocated for
+ * the duration), which is restored afterwards; the fastest step decides, but
+ * the configuration before tuning stays unless another is at least 2 %
+ * faster per step (timing noise does not flip between equals).  reps launches per candidate.  report
  * (may be NULL) receives a text table whose last line is the choice.
  * Synchronises. */
 cpic_status cpic_tune(cpic_ctx* ctx, int32_t reps, char* report, size_t cap);

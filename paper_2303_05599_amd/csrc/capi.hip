@@ -219,10 +219,11 @@ extern "C" cpic_status cpic_create(const cpic_glasma_params* gp, const cpic_part
     // more particles than sites: evaluate the fields once per site (force table)
     c->push_table = c->nc == 3 && c->np > c->V && c->pp.color_update == CPIC_COLOR_ROTATE;
     if (e == hipSuccess && c->push_table) e = hipMalloc(&c->ftab, (size_t)48 * c->V * c->tsz);
-    // field update: compressed-link LDS tiles of 64 x 4 sites (the tuner's usual pick at 512^2)
+    // field update: compressed-link LDS tiles of 64 x 8 sites (the tuner's pick
+    // at 512^2, 1-2 % per step ahead of 64 x 4)
     c->cfg.split = 3;
     c->cfg.bx = 64;
-    c->cfg.by = 4;
+    c->cfg.by = 8;
     set_store_policy(c);
     c->pblocks = c->np > 0 ? push_blocks((int)c->np, c->tpp) : 0;
     c->nslots = c->np > 0 ? num_slots(c->sc) : 0;
@@ -1183,6 +1184,7 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
     // the trial pushes may count cell jumps: the counter is put back afterwards
     int err0 = 0;
     HIPCHK(c, hipMemcpy(&err0, c->d_err, sizeof(int), hipMemcpyDeviceToHost), "tune");
+    const LaunchCfg orig = c->cfg;  // the configuration before tuning (default or set by the caller)
     const Fields<T> A = F<T>(c, c->cur), B = F<T>(c, c->cur ^ 1);
     T* const X = static_cast<T*>(c->aux);
     hipEvent_t e0, e1;
@@ -1329,14 +1331,29 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
                 return r;
             };
             const LaunchCfg keep = c->cfg;
-            LaunchCfg best_step = keep;
-            double best_pair = 1e300;
+            auto same = [](const LaunchCfg& a, const LaunchCfg& b) {
+                return a.bx == b.bx && a.by == b.by && a.xcd_remap == b.xcd_remap && a.waves == b.waves &&
+                       a.split == b.split && a.nt_store == b.nt_store;
+            };
+            // the trials: the three fastest in isolation with both store
+            // policies, and the configuration before tuning
+            std::vector<LaunchCfg> trials;
             const size_t ntop = std::min<size_t>(3, timed.size());
-            for (size_t k = 0; k < ntop && te == hipSuccess; k++)
-                for (int nt = 0; nt <= 1 && te == hipSuccess; nt++) {
+            for (size_t k = 0; k < ntop; k++)
+                for (int nt = 0; nt <= 1; nt++) {
                     LaunchCfg cfg = timed[k].second;
                     if (cfg.split != 3 && nt == 1) continue;  // the store policy exists for the compressed tiles
                     cfg.nt_store = cfg.split == 3 ? nt : 0;
+                    trials.push_back(cfg);
+                }
+            bool have_orig = false;
+            for (const LaunchCfg& t : trials) have_orig = have_orig || same(t, orig);
+            if (!have_orig) trials.push_back(orig);
+            LaunchCfg best_step = keep;
+            double best_pair = 1e300, orig_pair = 1e300;
+            for (size_t k = 0; k < trials.size() && te == hipSuccess; k++) {
+                {
+                    const LaunchCfg cfg = trials[k];
                     c->cfg = cfg;
                     double tot = 0;
                     for (int r = 0; r <= reps && te == hipSuccess; r++) {
@@ -1359,9 +1376,17 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
                                   per * 1e3);
                     rep += line;
                     if (per < best_pair) { best_pair = per; best_step = cfg; }
+                    if (same(cfg, orig)) orig_pair = per;
                 }
+            }
             release();
             if (te != hipSuccess) { c->cfg = keep; return hip_fail(c, te, "tune"); }
+            // a change of configuration has to gain at least 2 % per step, so
+            // that timing noise does not flip the choice between equals
+            if (orig_pair <= 1.02 * best_pair) {
+                best_step = orig;
+                best_pair = orig_pair;
+            }
             c->cfg = best_step;
             std::snprintf(line, sizeof line, "chosen: field %s bx=%d by=%d waves=%d remap=%d nt=%d, step %.2f us\n",
                           kVariantName[best_step.split], best_step.bx, best_step.by, best_step.waves,

@@ -157,6 +157,32 @@ def test_particle_push_fp64_random_state(is_static, lanes):
         assert abs(obs[-1, 1 + c] - sums[c]) <= 1e-10 * abs(sums[c]), (c, obs[-1], sums)
 
 
+@pytest.mark.parametrize("N,launch", [(4, "ctile64x8"), (4, "site64x4"), (4, "tile16x8"), (4, "link128x1"),
+                                      (6, "ctile32x4")])
+def test_smallest_lattices(N, launch):
+    """The smallest lattices (N = 4, 6: every tile shape is larger than the
+    lattice, every neighbour wraps): fields and moving particles, which cross
+    the periodic boundary often, over 40 steps against the oracle."""
+    print(f"case smallest N={N} launch={launch}", flush=True)
+    L, n0, steps, n = 0.75 * N / 4, 2, 40, 300
+    a = oracle.lattice_spacing(L, N)
+    st = inputs.random_state(N, 51 + N, eps_link=0.4)
+    P = inputs.random_particles(n, N, 52 + N, p_scale=0.6)
+    ctx = cp.Context(glasma(N, L, steps=n0 + steps), particle_params(n, 0.3 / a, N, L, 0))
+    ctx.set_launch(*LAUNCHES[launch])
+    ctx.load_state(st, n=n0, particles=P)
+    ctx.step(steps)
+    ctx.sync()
+    run = oracle.Run(N, 0.125, st, P, mhat=0.3, n_form=0, n0=n0)
+    for _ in range(steps):
+        run.step()
+    assert run.errors == 0
+    got = ctx.get_state(cp.STATE_PARTICLES)
+    assert np.array_equal(got[:, 14:16], run.P[:, 14:16])
+    assert rel_err(got, run.P) <= TOL
+    compare_fields(ctx.state(), run.st)
+
+
 def test_static_limit_config_32():
     """The coarse static configuration: 32^2, L = 6 fm, g^2 mu = 2 GeV, m = 0.2 GeV,
     one sheet, dtau = a/8 to 1 fm/c (43 steps), 1024 static quarks, seeds 1 and 2."""

@@ -267,7 +267,7 @@ def run_su2(steps, warmup, V):
     return out
 
 
-def cpu_baseline(n_steps=6, n_part=100_000):
+def cpu_baseline(n_steps=40, n_part=100_000):
     """The oracle on the host cores: 512^2 MV event (one colour sheet; the
     initial condition is not timed), n_steps leapfrog steps with the push of
     n_part charm quarks active from the first step."""
@@ -286,7 +286,7 @@ def cpu_baseline(n_steps=6, n_part=100_000):
     return dict(value=N * N * n_steps / dt, unit="site-updates/s", cores=cores, kind="oracle",
                 pushes_per_s=n_part * n_steps / dt,
                 sample=f"512^2 MV event (1 sheet, IC untimed), {n_steps} steps incl. push of {n_part} charm quarks, "
-                       f"{dt:.1f} s wall")
+                       f"{dt:.1f} s wall on {cores} threads")
 
 
 def kernel_source_hash():

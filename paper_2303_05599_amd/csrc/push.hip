@@ -275,7 +275,9 @@ __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& 
         if constexpr (sizeof(T) == 4 && !LOGQ)
             if (!a.is_static && renorm && live) Q = renorm_charge(Q, a.q0eig);
         CPIC_PHASE();
-        if (live) {
+        // one or two waves: the owner evaluates its share of the jobs (with
+        // four, the helpers evaluate all of them)
+        if (TPP != 4 && live) {
 #pragma unroll 1
             for (int j = 0; j < kJobs; j++) {
                 if (job_wave<TPP>(j) != 0 || !job_active(j, n, eonly)) continue;

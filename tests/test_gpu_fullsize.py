@@ -13,7 +13,7 @@ library's next state must agree with it: every site and every particle.
     nearly-identity plaquettes with cancellation, then t dt ~ 10 scales it;
     measured 1.1e-5), 1e-5 for the particle records;
   * the jets workload (FP32, 1e6 quarks m = 0.01 GeV, p_T = 10 GeV, with the
-    force-table push) and its light-like paths;
+    force-table push) and its light-like paths, and the same in FP64 at 1e-11;
   * the largest sizes the library accepts: a 1024^2 lattice with the largest
     double-precision particle count (14,913,080, records just below 2 GiB),
     every site and a random sample of 4096 particles (the oracle pushes
@@ -102,27 +102,34 @@ def test_headline_event_one_step(precision):
     ctx.close()
 
 
-def test_jets_workload_one_step():
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_jets_workload_one_step(precision):
+    """The jets workload as benchmarked (FP32), and the same in FP64 at 1e-11."""
+    prec = cp.FP64 if precision == "fp64" else cp.FP32
     a = oracle.lattice_spacing(L, N)
     p = dict(n=1_000_000, mass_GeV=0.01, pT_min_GeV=10.0, pT_max_GeV=10.0, azimuth_uniform=1, tau_form_fm=0.0,
              rep=0, seed=4)
-    ctx = cp.Context(glasma(cp.FP32), p)
+    ctx = cp.Context(glasma(prec), p)
     ctx.enable_jets(x_offset=0.3)
     assert ctx.get_launch()["nt_store"] == 1
     ctx.init_mv()
     ctx.step(40)
-    print(f"case jets 512^2: {ctx.tune(3).strip().splitlines()[-1]}", flush=True)
+    print(f"case jets 512^2 {precision}: {ctx.tune(3).strip().splitlines()[-1]}", flush=True)
     assert ctx.push_mode() in (cp.PUSH_TABLE, cp.PUSH_GATHER)
     ctx.step(3)
     jets = oracle.Jets(N, DT, 0, 0.3, 1)
     run, st1, P1 = one_step_against_oracle(ctx, 0.01 * a, 0, jets)
+    ftol, ptol = (1e-11, 1e-11) if prec == cp.FP64 else (5e-5, 1e-5)
     for k in ("U", "phi", "E", "pi"):
-        assert rel_err(st1[k], run.st[k]) <= 5e-5, k
+        assert rel_err(st1[k], run.st[k]) <= ftol, k
     same = np.all(P1[:, 14:16] == run.P[:, 14:16], axis=1)
-    assert same.mean() > 1 - 1e-4
-    assert rel_err(P1[same], run.P[same]) <= 1e-5
-    assert rel_err(ctx.get_state(cp.STATE_JET_F), jets.F) <= 1e-5
-    assert rel_err(ctx.get_state(cp.STATE_JET_W), jets.W) <= 1e-5
+    if prec == cp.FP64:
+        assert same.all()
+    else:
+        assert same.mean() > 1 - 1e-4
+    assert rel_err(P1[same], run.P[same]) <= ptol
+    assert rel_err(ctx.get_state(cp.STATE_JET_F), jets.F) <= ptol
+    assert rel_err(ctx.get_state(cp.STATE_JET_W), jets.W) <= ptol
     ctx.close()
 
 

@@ -14,6 +14,8 @@ library's next state must agree with it: every site and every particle.
     measured 1.1e-5), 1e-5 for the particle records;
   * the jets workload (FP32, 1e6 quarks m = 0.01 GeV, p_T = 10 GeV, with the
     force-table push) and its light-like paths, and the same in FP64 at 1e-11;
+  * the headline event with the matrix-logarithm colour update, and in the
+    SU(2) variant (FP64, 1e-11);
   * the largest sizes the library accepts: a 1024^2 lattice with the largest
     double-precision particle count (14,913,080, records just below 2 GiB),
     every site and a random sample of 4096 particles (the oracle pushes
@@ -58,7 +60,7 @@ def glasma(precision):
                 seed=3, precision=precision, reunit_every=16, record_every=8)
 
 
-def one_step_against_oracle(ctx, mhat, n_form, jets=None):
+def one_step_against_oracle(ctx, mhat, n_form, jets=None, color="cpic"):
     """State at n -> library step n and oracle step n from the same state."""
     st = ctx.state()
     P = ctx.get_state(cp.STATE_PARTICLES)
@@ -67,7 +69,7 @@ def one_step_against_oracle(ctx, mhat, n_form, jets=None):
         jets.W = ctx.get_state(cp.STATE_JET_W)
         jets.F = ctx.get_state(cp.STATE_JET_F)
     ctx.step(1)
-    run = oracle.Run(N, DT, st, P, mhat=mhat, n_form=n_form, n0=n0, jets=jets)
+    run = oracle.Run(N, DT, st, P, mhat=mhat, n_form=n_form, n0=n0, jets=jets, color=color)
     run.step()
     assert run.errors == 0
     return run, ctx.state(), ctx.get_state(cp.STATE_PARTICLES)
@@ -130,6 +132,52 @@ def test_jets_workload_one_step(precision):
     assert rel_err(P1[same], run.P[same]) <= ptol
     assert rel_err(ctx.get_state(cp.STATE_JET_F), jets.F) <= ptol
     assert rel_err(ctx.get_state(cp.STATE_JET_W), jets.W) <= ptol
+    ctx.close()
+
+
+def test_color_log_headline_one_step():
+    """The headline event (FP64) with the colour update from the matrix
+    logarithm of the links (Sec. III.B alternative), one step at 1e-11."""
+    a = oracle.lattice_spacing(L, N)
+    p = dict(n=100_000, mass_GeV=1.27, pT_min_GeV=0.0, pT_max_GeV=0.0, azimuth_uniform=1, tau_form_fm=0.1, rep=0,
+             seed=4, color_update=cp.COLOR_LOG)
+    ctx = cp.Context(glasma(cp.FP64), p)
+    ctx.init_mv()
+    ctx.step(80)
+    print(f"case colour log 512^2: {ctx.tune(3).strip().splitlines()[-1]}", flush=True)
+    ctx.step(3)
+    run, st1, P1 = one_step_against_oracle(ctx, 1.27 * a, 69, color="log")
+    for k in ("U", "phi", "E", "pi"):
+        assert rel_err(st1[k], run.st[k]) <= 1e-11, k
+    assert np.array_equal(P1[:, 14:16], run.P[:, 14:16])
+    assert rel_err(P1, run.P) <= 1e-11
+    ctx.close()
+
+
+def test_su2_headline_one_step():
+    """The headline event in the SU(2) variant (FP64, 1e5 charm quarks), one
+    step against the SU(2) oracle at 1e-11."""
+    from oracle import su2
+    a = oracle.lattice_spacing(L, N)
+    g = dict(glasma(cp.FP64), n_colors=2, reunit_every=0)
+    p = dict(n=100_000, mass_GeV=1.27, pT_min_GeV=0.0, pT_max_GeV=0.0, azimuth_uniform=1, tau_form_fm=0.1, rep=0,
+             seed=4)
+    ctx = cp.Context(g, p)
+    ctx.init_mv()
+    ctx.step(80)
+    st = ctx.state()
+    P = ctx.get_state(cp.STATE_PARTICLES)
+    n0 = ctx.n
+    ctx.step(1)
+    run = su2.Run(N, DT, st, P, mhat=1.27 * a, n_form=69, n0=n0)
+    run.step()
+    assert run.errors == 0
+    st1 = ctx.state()
+    for k in ("U", "phi", "E", "pi"):
+        assert rel_err(st1[k], run.st[k]) <= 1e-11, k
+    P1 = ctx.get_state(cp.STATE_PARTICLES)
+    assert np.array_equal(P1[:, 14:16], run.P[:, 14:16])
+    assert rel_err(P1, run.P) <= 1e-11
     ctx.close()
 
 

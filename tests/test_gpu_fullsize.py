@@ -16,6 +16,8 @@ library's next state must agree with it: every site and every particle.
     force-table push) and its light-like paths, and the same in FP64 at 1e-11;
   * the headline event with the matrix-logarithm colour update, and in the
     SU(2) variant (FP64, 1e-11);
+  * the headline lattice over its first 50 steps from the initial condition,
+    with the particles formed at tau = 0 (FP64, 1e-11).
   * the largest sizes the library accepts: a 1024^2 lattice with the largest
     double-precision particle count (14,913,080, records just below 2 GiB),
     every site and a random sample of 4096 particles (the oracle pushes
@@ -132,6 +134,32 @@ def test_jets_workload_one_step(precision):
     assert rel_err(P1[same], run.P[same]) <= ptol
     assert rel_err(ctx.get_state(cp.STATE_JET_F), jets.F) <= ptol
     assert rel_err(ctx.get_state(cp.STATE_JET_W), jets.W) <= ptol
+    ctx.close()
+
+
+def test_headline_first_50_steps():
+    """The headline lattice (FP64, 512^2, 50 sheets) with 1e5 charm quarks
+    formed at tau = 0, over the first 50 steps from the initial condition
+    (after the launch tuner) against the oracle: every site and every
+    particle at 1e-11, cells exact."""
+    a = oracle.lattice_spacing(L, N)
+    p = dict(n=100_000, mass_GeV=1.27, pT_min_GeV=0.0, pT_max_GeV=1.0, azimuth_uniform=1, tau_form_fm=0.0, rep=0,
+             seed=4)
+    ctx = cp.Context(glasma(cp.FP64), p)
+    ctx.init_mv()
+    print(f"case headline first 50 steps: {ctx.tune(3).strip().splitlines()[-1]}", flush=True)
+    st0, P0 = ctx.state(), ctx.get_state(cp.STATE_PARTICLES)
+    ctx.step(50)
+    run = oracle.Run(N, DT, st0, P0, mhat=1.27 * a, n_form=0, n0=0)
+    for _ in range(50):
+        run.step()
+    assert run.errors == 0
+    st1 = ctx.state()
+    for k in ("U", "phi", "E", "pi"):
+        assert rel_err(st1[k], run.st[k]) <= 1e-11, (k, rel_err(st1[k], run.st[k]))
+    P1 = ctx.get_state(cp.STATE_PARTICLES)
+    assert np.array_equal(P1[:, 14:16], run.P[:, 14:16])
+    assert rel_err(P1, run.P) <= 1e-11, rel_err(P1, run.P)
     ctx.close()
 
 

@@ -83,10 +83,10 @@ static cpic_status bhip(cpic_batch* b, hipError_t e, const char* where)
 static void drop_plans(cpic_batch* b)
 {
     for (auto& kv : b->plans) {
-        if (kv.second.graph) hipGraphExecDestroy(kv.second.graph);
-        hipFree(kv.second.d_act);
-        hipFree(kv.second.d_tiles);
-        hipFree(kv.second.d_blocks);
+        if (kv.second.graph) (void)hipGraphExecDestroy(kv.second.graph);
+        (void)hipFree(kv.second.d_act);
+        (void)hipFree(kv.second.d_tiles);
+        (void)hipFree(kv.second.d_blocks);
     }
     b->plans.clear();
 }
@@ -205,12 +205,12 @@ static cpic_status capture(cpic_batch* b, Plan& p)
     for (int j = 0; j < kBatchGraphSteps && s == CPIC_OK; j++) s = batch_step(b, p);
     hipError_t e = hipStreamEndCapture(b->st, &g);
     if (s) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return s;
     }
     if (e != hipSuccess) return bhip(b, e, "end capture");
     e = hipGraphInstantiate(&p.graph, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) return bhip(b, e, "graph instantiate");
     return CPIC_OK;
 }
@@ -417,9 +417,9 @@ template <typename T> static cpic_status tune_batch(cpic_batch* b, int reps, std
                 best = cfg;
             }
         }
-    hipFree(d_map);
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipFree(d_map);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (e != hipSuccess) return bhip(b, e, "tune");
     std::snprintf(line, sizeof line, "chosen: %dx%d remap %d (%.2f us)\n", best.bx, best.by, best.xcd_remap,
                   best_ms * 1e3);
@@ -520,10 +520,10 @@ extern "C" const char* cpic_batch_last_error(const cpic_batch* b) { return b ? b
 extern "C" void cpic_batch_destroy(cpic_batch* b)
 {
     if (!b) return;
-    if (b->st) hipStreamSynchronize(b->st);
+    if (b->st) (void)hipStreamSynchronize(b->st);
     drop_plans(b);
-    hipFree(b->d_desc);
+    (void)hipFree(b->d_desc);
     for (auto c : b->ev) cpic_destroy(c);
-    if (b->own_stream) hipStreamDestroy(b->st);
+    if (b->own_stream) (void)hipStreamDestroy(b->st);
     delete b;
 }

@@ -90,19 +90,19 @@ static bool valid_N(int N)
 static void free_all(cpic_ctx* c)
 {
     for (int p = 0; p < 2; p++)
-        if (c->gexec[p]) hipGraphExecDestroy(c->gexec[p]);
-    for (auto e : c->ev_field) hipEventDestroy(e);
-    for (auto e : c->ev_push) hipEventDestroy(e);
-    for (auto e : c->ev_jets) hipEventDestroy(e);
-    for (auto e : c->ev_table) hipEventDestroy(e);
-    hipFree(c->ftab);
-    hipFree(c->jW); hipFree(c->jF); hipFree(c->jpartials); hipFree(c->jobs);
-    hipFree(c->fbuf[0]); hipFree(c->fbuf[1]); hipFree(c->pr); hipFree(c->pcell); hipFree(c->aux);
-    hipFree(c->partials); hipFree(c->obs); hipFree(c->d_step); hipFree(c->d_err); hipFree(c->d_fails);
-    hipFree(c->dpart); hipFree(c->dout);
-    hipFree(c->pid); hipFree(c->sb.keys); hipFree(c->sb.keys2); hipFree(c->sb.vals); hipFree(c->sb.perm);
-    hipFree(c->sb.temp); hipFree(c->sb.r2); hipFree(c->sb.cell2); hipFree(c->sb.pid2);
-    if (c->own_stream && c->st) hipStreamDestroy(c->st);
+        if (c->gexec[p]) (void)hipGraphExecDestroy(c->gexec[p]);
+    for (auto e : c->ev_field) (void)hipEventDestroy(e);
+    for (auto e : c->ev_push) (void)hipEventDestroy(e);
+    for (auto e : c->ev_jets) (void)hipEventDestroy(e);
+    for (auto e : c->ev_table) (void)hipEventDestroy(e);
+    (void)hipFree(c->ftab);
+    (void)hipFree(c->jW); (void)hipFree(c->jF); (void)hipFree(c->jpartials); (void)hipFree(c->jobs);
+    (void)hipFree(c->fbuf[0]); (void)hipFree(c->fbuf[1]); (void)hipFree(c->pr); (void)hipFree(c->pcell); (void)hipFree(c->aux);
+    (void)hipFree(c->partials); (void)hipFree(c->obs); (void)hipFree(c->d_step); (void)hipFree(c->d_err); (void)hipFree(c->d_fails);
+    (void)hipFree(c->dpart); (void)hipFree(c->dout);
+    (void)hipFree(c->pid); (void)hipFree(c->sb.keys); (void)hipFree(c->sb.keys2); (void)hipFree(c->sb.vals); (void)hipFree(c->sb.perm);
+    (void)hipFree(c->sb.temp); (void)hipFree(c->sb.r2); (void)hipFree(c->sb.cell2); (void)hipFree(c->sb.pid2);
+    if (c->own_stream && c->st) (void)hipStreamDestroy(c->st);
 }
 
 // Store policy of the field update.  After the field update a step reads the
@@ -254,7 +254,7 @@ extern "C" cpic_status cpic_create(const cpic_glasma_params* gp, const cpic_part
 extern "C" void cpic_destroy(cpic_ctx* c)
 {
     if (!c) return;
-    if (c->st) hipStreamSynchronize(c->st);
+    if (c->st) (void)hipStreamSynchronize(c->st);
     free_all(c);
     delete c;
 }
@@ -306,7 +306,7 @@ static void drop_graphs(cpic_ctx* c)
 {
     for (int p = 0; p < 2; p++)
         if (c->gexec[p]) {
-            hipGraphExecDestroy(c->gexec[p]);
+            (void)hipGraphExecDestroy(c->gexec[p]);
             c->gexec[p] = nullptr;
         }
 }
@@ -368,10 +368,10 @@ extern "C" cpic_status cpic_init_mv(cpic_ctx* c)
         if (e == hipSuccess && c->prec == CPIC_FP32)
             e = convert_to_float(pdst, (float*)c->pr, (size_t)kPartReals * c->np, c->st);
         if (e == hipSuccess) e = hipStreamSynchronize(c->st);
-        hipFree(pstage);
+        (void)hipFree(pstage);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(c->st);
-    hipFree(stage);
+    (void)hipFree(stage);
     if (e != hipSuccess) return hip_fail(c, e, "cpic_init_mv");
     int fails = 0;
     HIPCHK(c, hipMemcpy(&fails, c->d_fails, sizeof(int), hipMemcpyDeviceToHost), "IC");
@@ -505,10 +505,10 @@ static cpic_status build_graph(cpic_ctx* c, int parity)
         s = c->prec == CPIC_FP64 ? launch_one<double>(c, parity ^ (j & 1), false)
                                  : launch_one<float>(c, parity ^ (j & 1), false);
     hipError_t e = hipStreamEndCapture(c->st, &g);
-    if (s) { if (g) hipGraphDestroy(g); return s; }
+    if (s) { if (g) (void)hipGraphDestroy(g); return s; }
     if (e != hipSuccess) return hip_fail(c, e, "end capture");
     e = hipGraphInstantiate(&c->gexec[parity], g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) return hip_fail(c, e, "graph instantiate");
     return CPIC_OK;
 }
@@ -564,20 +564,20 @@ static cpic_status collect_timing(cpic_ctx* c)
         HIPCHK(c, hipEventElapsedTime(&ms, c->ev_field[i], c->ev_field[i + 1]), "timing");
         c->t_field += ms;
         c->k_field++;
-        hipEventDestroy(c->ev_field[i]); hipEventDestroy(c->ev_field[i + 1]);
+        (void)hipEventDestroy(c->ev_field[i]); (void)hipEventDestroy(c->ev_field[i + 1]);
     }
     for (size_t i = 0; i + 1 < c->ev_push.size(); i += 2) {
         float ms = 0;
         HIPCHK(c, hipEventElapsedTime(&ms, c->ev_push[i], c->ev_push[i + 1]), "timing");
         c->t_push += ms;
         c->k_push++;
-        hipEventDestroy(c->ev_push[i]); hipEventDestroy(c->ev_push[i + 1]);
+        (void)hipEventDestroy(c->ev_push[i]); (void)hipEventDestroy(c->ev_push[i + 1]);
     }
     for (size_t i = 0; i + 1 < c->ev_table.size(); i += 2) {  // the table kernel counts as push time
         float ms = 0;
         HIPCHK(c, hipEventElapsedTime(&ms, c->ev_table[i], c->ev_table[i + 1]), "timing");
         c->t_push += ms;
-        hipEventDestroy(c->ev_table[i]); hipEventDestroy(c->ev_table[i + 1]);
+        (void)hipEventDestroy(c->ev_table[i]); (void)hipEventDestroy(c->ev_table[i + 1]);
     }
     c->ev_table.clear();
     for (size_t i = 0; i + 1 < c->ev_jets.size(); i += 2) {
@@ -585,7 +585,7 @@ static cpic_status collect_timing(cpic_ctx* c)
         HIPCHK(c, hipEventElapsedTime(&ms, c->ev_jets[i], c->ev_jets[i + 1]), "timing");
         c->t_jets += ms;
         c->k_jets++;
-        hipEventDestroy(c->ev_jets[i]); hipEventDestroy(c->ev_jets[i + 1]);
+        (void)hipEventDestroy(c->ev_jets[i]); (void)hipEventDestroy(c->ev_jets[i + 1]);
     }
     c->ev_field.clear();
     c->ev_push.clear();
@@ -1306,7 +1306,7 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
         hipError_t he = hipMalloc(&bk, fbytes);
         if (he == hipSuccess && c->jets) he = hipMalloc(&bw, wb);
         if (he == hipSuccess && c->jets) he = hipMalloc(&bf, fb);
-        auto release = [&]() { hipFree(bk); hipFree(bw); hipFree(bf); };
+        auto release = [&]() { (void)hipFree(bk); (void)hipFree(bw); (void)hipFree(bf); };
         if (he != hipSuccess) {
             release();
             rep += "step trials skipped: no memory for the state copy\n";
@@ -1361,7 +1361,7 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
                         cpic_status ls = CPIC_OK;
                         if (te == hipSuccess) ls = launch_one<T>(c, c->cur, false);
                         if (te == hipSuccess && !ls) ls = launch_one<T>(c, c->cur ^ 1, false);
-                        if (ls) { c->cfg = keep; restore(); release(); return ls; }
+                        if (ls) { c->cfg = keep; (void)restore(); release(); return ls; }
                         if (te == hipSuccess) te = hipEventRecord(e1, c->st);
                         if (te == hipSuccess) te = hipEventSynchronize(e1);
                         float ms = 0;
@@ -1394,8 +1394,8 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
             rep += line;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     drop_graphs(c);
     return CPIC_OK;
 }
@@ -1478,7 +1478,7 @@ extern "C" cpic_status cpic_jets_enable(cpic_ctx* c, const cpic_jet_params* jp)
     if (e == hipSuccess && obs) e = hipMemsetAsync(obs, 0, sizeof(double) * 4 * (size_t)jslots, c->st);
     if (e == hipSuccess) e = hipStreamSynchronize(c->st);
     if (e != hipSuccess) {
-        hipFree(W); hipFree(Fp); hipFree(aux); hipFree(part); hipFree(obs);
+        (void)hipFree(W); (void)hipFree(Fp); (void)hipFree(aux); (void)hipFree(part); (void)hipFree(obs);
         const bool oom = e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation;
         return fail(c, oom ? CPIC_E_NOMEM : CPIC_E_HIP, std::string("cpic_jets_enable: ") + hipGetErrorString(e));
     }

@@ -471,7 +471,7 @@ hipError_t ic_glasma(const ICArgs& a, Fields<double> out, int* d_fails, hipStrea
     }
     hipError_t e2 = hipStreamSynchronize(st);
     if (e == hipSuccess) e = e2;
-    hipFree(buf); hipFree(tmp); hipFree(Vdag); hipFree(UA); hipFree(UB);
+    (void)hipFree(buf); (void)hipFree(tmp); (void)hipFree(Vdag); (void)hipFree(UA); (void)hipFree(UB);
     return e;
 }
 
@@ -554,7 +554,7 @@ hipError_t ic_glasma2(const ICArgs& a, Fields2<double> out, hipStream_t st)
     }
     hipError_t e2 = hipStreamSynchronize(st);
     if (e == hipSuccess) e = e2;
-    hipFree(buf); hipFree(tmp); hipFree(Vdag); hipFree(UA); hipFree(UB);
+    (void)hipFree(buf); (void)hipFree(tmp); (void)hipFree(Vdag); (void)hipFree(UA); (void)hipFree(UB);
     return e;
 }
 

@@ -57,8 +57,9 @@ __global__ void permute_kernel(const T* __restrict__ r, const int* __restrict__ 
 size_t sort_temp_bytes(int np, int N)
 {
     size_t bytes = 0;
-    hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (unsigned*)nullptr, (unsigned*)nullptr, (int*)nullptr,
-                                       (int*)nullptr, np, 0, key_bits(N));
+    // size query only: no device work, the status carries nothing more
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (unsigned*)nullptr, (unsigned*)nullptr, (int*)nullptr,
+                                             (int*)nullptr, np, 0, key_bits(N));
     return bytes;
 }
 

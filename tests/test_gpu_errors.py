@@ -8,10 +8,9 @@ normal end.
   * caller buffers of the wrong size: CPIC_E_CAPACITY, nothing written;
   * checkpoint files that cannot be read or written: CPIC_E_IO;
   * calls out of order or with bad arguments: CPIC_E_INVALID, and the
-    context stays usable afterwards.
+    context stays usable afterwards; the same for the batch API.
 """
 import ctypes
-import os
 
 import numpy as np
 import pytest
@@ -138,3 +137,35 @@ def test_calls_out_of_order_and_bad_arguments():
     ctx.sync()
     assert ctx.n == 5 and ctx.get_launch() == launch
     ctx.close()
+
+
+def test_batch_errors():
+    """The batch API: mixed precisions, a bad event index, a too small
+    observables buffer, bad launch shapes; the batch stays usable."""
+    g = glasma(16, steps=20)
+    with pytest.raises(cp.CpicError) as e:
+        cp.Batch([g, dict(g, precision=cp.FP32)], [particles(64), particles(64)])
+    assert status(e) == -1
+    b = cp.Batch([g, dict(g, N=24, L_fm=g["L_fm"] * 24 / 16)], [particles(64), dict(n=0)])
+    b.init_mv()
+    b.step(17)
+    b.sync()
+    L = cp.lib()
+    ns = ctypes.c_int32()
+    out = np.zeros((1, 6))
+    assert L.cpic_batch_observables(b.h, 0, out.ctypes.data, 1, ctypes.byref(ns)) == -7
+    assert ns.value == 2
+    for ev in (-1, 2):
+        assert L.cpic_batch_observables(b.h, ev, out.ctypes.data, 1, ctypes.byref(ns)) == -1
+        with pytest.raises(cp.CpicError) as e:
+            b.n(ev)
+        assert status(e) == -1
+    for args in ((48, 4, 1, 4), (64, 4, 1, 3)):
+        with pytest.raises(cp.CpicError) as e:
+            b.set_launch(*args)
+        assert status(e) == -1
+    b.run()
+    b.sync()
+    assert b.n(0) == 20 and b.n(1) == 20
+    assert b.observables(0).shape[0] == 3
+    b.close()

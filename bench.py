@@ -52,7 +52,8 @@ JET_BYTES = {"f64": 142 * 8, "f32": 142 * 4}
 # (3) and a link (4 reals) every eighth step
 SITE_BYTES_SU2 = {"f64": 20 * 2 * 8, "f32": 20 * 2 * 4}
 PUSH_BYTES_SU2 = {"f64": (26 + 18 + 3 + 0.5) * 8, "f32": (26 + 18 + 3 + 0.5) * 4}
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_512_fp64.txt")
+# calibrated HBM counter readings per workload (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)
+PMC_SUMMARIES = {w: os.path.join(ROOT, "profiles", f"pmc_{w}.txt") for w in ("512_fp64", "512_fp32", "jets_512_fp32")}
 KERNEL_SOURCES = os.path.join(ROOT, "paper_2303_05599_amd", "csrc")
 
 
@@ -72,7 +73,7 @@ def jet_quarks(n=1_000_000, seed=4):
                 seed=seed)
 
 
-def run_event(precision, steps, warmup, tune=True, particles=None, jets=False, n_colors=3):
+def run_event(precision, steps, warmup, tune=True, particles=None, jets=False, n_colors=3, fixed=None):
     """One 512^2 event: IC (timed separately), warm-up steps past formation, the
     launch tuner, a kernel-timing stretch (eager launches with HIP events
     attached to each kernel: the per-kernel times of the roofline entries),
@@ -89,8 +90,13 @@ def run_event(precision, steps, warmup, tune=True, particles=None, jets=False, n
     t_ic = time.perf_counter() - t0
     ctx.step(warmup)
     ctx.sync()
-    tune_report = ctx.tune(5) if tune else "not tuned (library defaults)\n"
+    if fixed:
+        ctx.set_launch(fixed[0], fixed[1], 1, 1, 3)
+        tune_report = f"fixed compressed-tile launch {fixed[0]}x{fixed[1]}\n"
+    else:
+        tune_report = ctx.tune(5) if tune else "not tuned (library defaults)\n"
     launch = ctx.get_launch()
+    launch["logq"] = (particles or {}).get("color_update", 0) == cp.COLOR_LOG
     launch["push_mode"] = "table" if ctx.push_mode() == cp.PUSH_TABLE else "gather"
     # kernel timing (eager launches); not the headline rate
     n_kt = max(16, min(128, 1024 - warmup - steps))
@@ -198,15 +204,15 @@ def run_batch(fp64_launch):
             "launch": launch, "tuner_choice": tune.strip().splitlines()[-1]}
 
 
-def run_jets(steps, warmup, V, tune=True):
+def run_jets(steps, warmup, V, tune=True, fixed=None):
     """The jets workload: the 512^2 event in FP32 with 1e6 near-light-like quarks
     and the light-like path integral over all 512^2 starting sites (the
     limit the quarks are compared with); the same timed region as the
     headline run."""
     import paper_2303_05599_amd as cp
     n_part = 1_000_000
-    r = run_event(cp.FP32, steps, warmup, tune, jet_quarks(n_part), jets=True)
-    k = rooflines(r, "fp32", n_part, V)
+    r = run_event(cp.FP32, steps, warmup, tune, jet_quarks(n_part), jets=True, fixed=fixed)
+    k = rooflines(r, "fp32", n_part, V, "jets_512_fp32")
     last, lj = r["obs"][-1], r["jet_obs"][-1]
     return {"workload": "MV Glasma 512^2 (as above) in FP32 with reunitarisation every 16 steps, 1e6 quarks "
                         "m=0.01 GeV, pT=10 GeV, uniform azimuth, formed at tau=0, plus one light-like path "
@@ -233,7 +239,6 @@ def run_color_log(steps, warmup, V, ref):
     n_part = 100_000
     r = run_event(cp.FP64, steps, warmup, True, charm(n_part, color_update=cp.COLOR_LOG))
     k = rooflines(r, "fp64", n_part, V)
-    k["push"]["kernel"] = k["push"]["kernel"].replace(", false>", ", true>")
     return {"workload": "the headline event (FP64) with the charges updated from the matrix logarithm of the links",
             "ms_per_step": r["wall"] * 1e3 / steps,
             "pushes_per_s": n_part * steps / r["wall"],
@@ -301,7 +306,9 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def read_pmc_summary(path=PMC_SUMMARY):
+def read_pmc_summary(path):
+    """kernel name -> (fetch bytes, write bytes) per dispatch, or None when the
+    summary is missing or was taken on other kernel sources."""
     if not os.path.exists(path):
         return None
     d = {}
@@ -311,7 +318,14 @@ def read_pmc_summary(path=PMC_SUMMARY):
             if line and not line.startswith("#") and "=" in line:
                 k, v = line.split("=", 1)
                 d[k.strip()] = v.strip()
-    return d if d.get("source_sha256") == kernel_source_hash() else None
+    if d.get("source_sha256") != kernel_source_hash():
+        return None
+    out = {}
+    for k, v in d.items():
+        if k.endswith(".kernel"):
+            key = k[:-len(".kernel")]
+            out[v] = (float(d[key + ".fetch_bytes"]), float(d[key + ".write_bytes"]))
+    return out
 
 
 def kernel_names(launch, precision):
@@ -329,12 +343,14 @@ def kernel_names(launch, precision):
     if launch.get("push_mode") == "table":
         push = f"force_table_kernel<{t}> + push_table_kernel<{t}>"
     else:
-        push = f"push_kernel<{t}, {launch['push_lanes']}, false>"
+        push = f"push_kernel<{t}, {launch['push_lanes']}, {'true' if launch.get('logq') else 'false'}>"
     return field, push, f"jet_kernel<{t}>"
 
 
-def rooflines(res, precision, n_part, V):
-    """Per-kernel roofline entries from the live HIP-event kernel times."""
+def rooflines(res, precision, n_part, V, pmc_workload=None):
+    """Per-kernel roofline entries from the live HIP-event kernel times; HBM
+    traffic from the counter summary of `pmc_workload` where it holds the
+    same kernel (a push shown as "a + b" adds both kernels' traffic)."""
     tm = res["timing"]
     dt = "f64" if precision == "fp64" else "f32"
     field_s = tm["field_ms"] / max(tm["n_field"], 1) * 1e-3
@@ -352,66 +368,67 @@ def rooflines(res, precision, n_part, V):
                     "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": name,
                     "avg_launch_us": secs * 1e6, "bytes_per_launch": bpl,
                     "bytes_per_unit": unit_bytes, "units_per_launch": units, "work_unit": unit}
-    pmc = read_pmc_summary() if precision == "fp64" else None
-    for key in out:
-        if pmc and pmc.get(f"{key}.kernel") == out[key]["kernel"]:
-            out[key]["traffic"] = float(pmc[f"{key}.fetch_bytes"]) + float(pmc[f"{key}.write_bytes"])
-            out[key]["traffic_read"] = float(pmc[f"{key}.fetch_bytes"])
-            out[key]["traffic_written"] = float(pmc[f"{key}.write_bytes"])
+    pmc = read_pmc_summary(PMC_SUMMARIES[pmc_workload or "512_" + precision])
+    for e in out.values():
+        parts = e["kernel"].split(" + ")
+        if pmc and all(k in pmc for k in parts):
+            fe, wr = sum(pmc[k][0] for k in parts), sum(pmc[k][1] for k in parts)
+            e.update(traffic=fe + wr, traffic_read=fe, traffic_written=wr)
     return out
 
 
-def pmc_summary(out_path, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, command):
-    """Condense four rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE of the bench
-    workload and of the 256 MiB copy) into the key = value summary read above."""
+def pmc_summary(out_path, fetch_dirs, write_dirs, copy_fetch_dir, copy_write_dir, command, title):
+    """Condense rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE of a bench workload,
+    comma-separated directories when several launch shapes were profiled, and
+    of the 256 MiB copy) into the key = value summary read above: every field,
+    push and light-like kernel with at least 16 dispatches, by name."""
     import csv
     import glob
 
-    def per_kernel(d, counter):
-        rows = []
-        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
-            rows += [r for r in csv.DictReader(open(f)) if r["Counter_Name"] == counter]
-        by = {}
-        for r in rows:
-            key = (r["Kernel_Name"], int(r["Dispatch_Id"]))
-            by[key] = by.get(key, 0.0) + float(r["Counter_Value"])
-        kern, last = {}, {}
-        for (name, disp), v in sorted(by.items(), key=lambda kv: kv[0][1]):
-            kern.setdefault(name, []).append(v)
-            last[name] = disp
-        return kern, last
+    def per_kernel(dirs, counter):
+        kern = {}
+        for d in dirs.split(","):
+            by = {}
+            for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+                for r in csv.DictReader(open(f)):
+                    if r["Counter_Name"] == counter:
+                        key = (r["Kernel_Name"], int(r["Dispatch_Id"]))
+                        by[key] = by.get(key, 0.0) + float(r["Counter_Value"])
+            for (name, _), v in sorted(by.items(), key=lambda kv: kv[0][1]):
+                kern.setdefault(short(name), []).append(v)
+        return kern
 
     def short(name):
         return name.replace("void ", "").replace("cpic::", "").split("(")[0]
 
-    (cf, _), (cw, _) = per_kernel(copy_fetch_dir, "FETCH_SIZE"), per_kernel(copy_write_dir, "WRITE_SIZE")
+    cf, cw = per_kernel(copy_fetch_dir, "FETCH_SIZE"), per_kernel(copy_write_dir, "WRITE_SIZE")
     copy_kernel = max(cf, key=lambda k: max(cf[k]))
     copy_bytes = 256 << 20
     f_fetch = copy_bytes / (max(cf[copy_kernel]) * 1024)
     f_write = copy_bytes / (max(cw[copy_kernel]) * 1024)
-    (kf, last), (kw, _) = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
-    lines = ["# rocprofv3 PMC summary: HBM traffic per dispatch, 512^2 FP64 MV event with 1e5 charm quarks",
-             "# (the bench.py workload).  FETCH_SIZE and WRITE_SIZE (KiB per dispatch, mean of the last",
-             "# 16 dispatches of each kernel in the timed region) are scaled by the ratio of the bytes a",
-             "# 256 MiB device copy moves to what the same counters read for it.",
+    kf, kw = per_kernel(fetch_dirs, "FETCH_SIZE"), per_kernel(write_dirs, "WRITE_SIZE")
+    lines = [f"# rocprofv3 PMC summary: HBM traffic per dispatch, {title}.",
+             "# FETCH_SIZE and WRITE_SIZE (KiB per dispatch, mean of the last 16 dispatches of each",
+             "# kernel: the timed region) are scaled by the ratio of the bytes a 256 MiB device copy",
+             "# moves to what the same counters read for it.",
              "# commands (from /tmp, TMPDIR=/tmp; R = repository root):"]
-    lines += ["#   " + c for c in command.split(";")]
+    lines += ["#   " + c.strip() for c in command.split(";")]
     lines += [f"source_sha256 = {kernel_source_hash()}",
-              f"copy_kernel = {short(copy_kernel)}",
+              f"copy_kernel = {copy_kernel}",
               f"copy_fetch_kib = {max(cf[copy_kernel]):.1f}", f"copy_write_kib = {max(cw[copy_kernel]):.1f}",
               f"copy_fetch_factor = {f_fetch:.4f}", f"copy_write_factor = {f_write:.4f}"]
-    for key, pat in (("field", "field_"), ("push", "push_kernel")):
-        names = [k for k in kf if pat in k and "diag" not in k]
-        if not names:
+    i = 0
+    for name in sorted(kf):
+        if not any(p in name for p in ("field_", "push_", "force_table", "jet_kernel")) or "diag" in name:
             continue
-        name = max(names, key=lambda k: last[k])   # the tuned configuration runs last (timed and graph steps)
-        fe = kf[name][-16:]
-        wr = kw.get(name, [0.0])[-16:]
-        fkib, wkib = sum(fe) / len(fe), sum(wr) / len(wr)
-        lines += [f"{key}.kernel = {short(name)}", f"{key}.dispatches = {len(fe)}",
-                  f"{key}.fetch_kib = {fkib:.1f}", f"{key}.write_kib = {wkib:.1f}",
-                  f"{key}.fetch_bytes = {fkib * 1024 * f_fetch:.0f}",
-                  f"{key}.write_bytes = {wkib * 1024 * f_write:.0f}"]
+        if len(kf[name]) < 16 or len(kw.get(name, [])) < 16:
+            continue
+        fe, wr = kf[name][-16:], kw[name][-16:]
+        fkib, wkib = sum(fe) / 16, sum(wr) / 16
+        lines += [f"k{i}.kernel = {name}", f"k{i}.fetch_kib = {fkib:.1f}", f"k{i}.write_kib = {wkib:.1f}",
+                  f"k{i}.fetch_bytes = {fkib * 1024 * f_fetch:.0f}",
+                  f"k{i}.write_bytes = {wkib * 1024 * f_write:.0f}"]
+        i += 1
     with open(out_path, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -462,6 +479,9 @@ def main():
     ap.add_argument("--trace-summary", nargs=3, metavar=("OUT", "TRACE_DIR", "TIMED_STEPS"),
                     help="condense a rocprofv3 --kernel-trace --stats directory into a markdown table")
     ap.add_argument("--command", default="", help="command line recorded in a summary")
+    ap.add_argument("--title", default="", help="workload named in a counter summary")
+    ap.add_argument("--launch", nargs=2, type=int, metavar=("BX", "BY"), default=None,
+                    help="fix the compressed-tile field launch instead of tuning (counter runs of a tuned shape)")
     ap.add_argument("--jets-only", action="store_true",
                     help="run only the jets workload and print its JSON (for profiling; not the benchmark line)")
     ap.add_argument("--no-tune", action="store_true",
@@ -469,7 +489,7 @@ def main():
                          "are distorted by the serialised dispatches)")
     args = ap.parse_args()
     if args.pmc_summary:
-        pmc_summary(*args.pmc_summary, args.command)
+        pmc_summary(*args.pmc_summary, args.command, args.title)
         return
     if args.trace_summary:
         out, tdir, last = args.trace_summary
@@ -496,9 +516,10 @@ def main():
     V = 512 * 512
     n_part = 100_000
     if args.jets_only:
-        print(json.dumps(run_jets(args.steps, args.warmup, V, not args.no_tune)))
+        print(json.dumps(run_jets(args.steps, args.warmup, V, not args.no_tune, args.launch)))
         return
-    res = run_event(cp.FP64 if args.precision == "fp64" else cp.FP32, args.steps, args.warmup, not args.no_tune)
+    res = run_event(cp.FP64 if args.precision == "fp64" else cp.FP32, args.steps, args.warmup, not args.no_tune,
+                    fixed=args.launch)
     ms_per_step = res["wall"] * 1e3 / args.steps
     site_rate = V * args.steps / res["wall"]
     push_rate = n_part * args.steps / res["wall"]

@@ -161,7 +161,9 @@ class Context:
             lib().cpic_destroy(self.h)
             self.h = None
 
-    __del__ = close
+    def __del__(self):
+        if lib is not None:     # None once the interpreter has cleared module globals at exit
+            self.close()
 
     def init_mv(self):
         self._chk(lib().cpic_init_mv(self.h))
@@ -324,7 +326,9 @@ class Batch:
             lib().cpic_batch_destroy(self.h)
             self.h = None
 
-    __del__ = close
+    def __del__(self):
+        if lib is not None:     # None once the interpreter has cleared module globals at exit
+            self.close()
 
     def init_mv(self):
         self._chk(lib().cpic_batch_init_mv(self.h))

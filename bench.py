@@ -386,16 +386,21 @@ def pmc_summary(out_path, fetch_dirs, write_dirs, copy_fetch_dir, copy_write_dir
     import glob
 
     def per_kernel(dirs, counter):
+        # per kernel, the dispatches of the run in which it ran most often: a
+        # run with a fixed tile also runs the default tile in its warm-up
         kern = {}
         for d in dirs.split(","):
-            by = {}
+            by, run = {}, {}
             for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
                 for r in csv.DictReader(open(f)):
                     if r["Counter_Name"] == counter:
                         key = (r["Kernel_Name"], int(r["Dispatch_Id"]))
                         by[key] = by.get(key, 0.0) + float(r["Counter_Value"])
             for (name, _), v in sorted(by.items(), key=lambda kv: kv[0][1]):
-                kern.setdefault(short(name), []).append(v)
+                run.setdefault(short(name), []).append(v)
+            for name, v in run.items():
+                if len(v) > len(kern.get(name, [])):
+                    kern[name] = v
         return kern
 
     def short(name):

@@ -260,8 +260,9 @@ __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& 
             if (dx < -1 || dx > 1) atomicAdd(err, 1);
             if (dy < -1 || dy > 1) atomicAdd(err, 1);
             m3<T> Lx, Ly;
-            if (dx != 0) Lx = vU(A, (uint32_t)(cy * N + (dx > 0 ? cx : wrap(cx - 1, N))) * (uint32_t)sizeof(T), 0);
-            if (dy != 0) Ly = vU(A, (uint32_t)((dy > 0 ? cy : wrap(cy - 1, N)) * N + nx) * (uint32_t)sizeof(T), 1);
+            // (as two rows, like the helpers: the third rows stay out of the push's footprint)
+            if (dx != 0) Lx = vU2(A, (uint32_t)(cy * N + (dx > 0 ? cx : wrap(cx - 1, N))) * (uint32_t)sizeof(T), 0);
+            if (dy != 0) Ly = vU2(A, (uint32_t)((dy > 0 ? cy : wrap(cy - 1, N)) * N + nx) * (uint32_t)sizeof(T), 1);
             const a8<T> ph = vA(A, cell.s, kCompPhi);
             if (dx == 1) Q = rotate(Lx, Q);
             else if (dx == -1) Q = transport(Lx, Q);  // U Q U^+
@@ -371,8 +372,8 @@ __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& 
                 CPIC_PHASE();
                 const int lx = min((int)floor(x), N - 1), ly = min((int)floor(y), N - 1);
                 constexpr T tol = sizeof(T) == 8 ? T(1e-15) : T(1e-7);
-                const a8<T> gx = link_generator(vU(A, (uint32_t)(ny * N + lx) * (uint32_t)sizeof(T), 0), tol, 50);
-                const a8<T> gy = link_generator(vU(A, (uint32_t)(ly * N + nx) * (uint32_t)sizeof(T), 1), tol, 50);
+                const a8<T> gx = link_generator(vU2(A, (uint32_t)(ny * N + lx) * (uint32_t)sizeof(T), 0), tol, 50);
+                const a8<T> gy = link_generator(vU2(A, (uint32_t)(ly * N + nx) * (uint32_t)sizeof(T), 1), tol, 50);
                 const a8<T> ph = vA(A, cell.s, kCompPhi);
                 const T veta = pe / ptau;
                 a8<T> M;

@@ -37,8 +37,12 @@ HBARC_GEV_FM = 0.1973269804
 # (U_x, U_y, phi, E_x, E_y, pi) and, with particles, writes the 48 reals of
 # per-site field pieces the push reads (a force table); the push moves its
 # record (about 17 words each way), the six force fields at one site (48
-# reals), phi at the cell (8) and a link on one step in eight.
+# reals), phi at the cell (8) and a link on one step in eight.  The library
+# keeps only the first two rows of each link (12 of its 18 reals), so its
+# field update moves 56 + 56 reals of state per site: that figure is reported
+# beside the full-link one.
 SITE_BYTES = {"f64": 68 * 2 * 8, "f32": 68 * 2 * 4}
+SITE_BYTES_TWO_ROW = {"f64": 56 * 2 * 8, "f32": 56 * 2 * 4}
 AUX_BYTES = {"f64": 48 * 8, "f32": 48 * 4}
 PUSH_BYTES = {"f64": 730, "f32": 370}
 # light-like paths, per path and step: the Wilson line (18 reals) read, the
@@ -368,6 +372,10 @@ def rooflines(res, precision, n_part, V, pmc_workload=None):
                     "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": name,
                     "avg_launch_us": secs * 1e6, "bytes_per_launch": bpl,
                     "bytes_per_unit": unit_bytes, "units_per_launch": units, "work_unit": unit}
+    if "ctile" in fname:
+        # the same launch priced with the two-row link storage it works on
+        two = (SITE_BYTES_TWO_ROW[dt] + AUX_BYTES[dt]) * V
+        out["field"].update(bytes_per_unit_two_row_links=two // V, frac_two_row_links=two / field_s / 1e9 / HBM_PEAK_GBS)
     pmc = read_pmc_summary(PMC_SUMMARIES[pmc_workload or "512_" + precision])
     for e in out.values():
         parts = e["kernel"].split(" + ")

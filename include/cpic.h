@@ -213,6 +213,10 @@ cpic_status cpic_diagnostics(cpic_ctx* ctx, double out[10]);
  *   CPIC_STATE_JET_F     float64 [N][N][3][8]        its integrated transported force
  *                        components F_x, F_y, F_z (get only)
  * bytes must equal the exact size (CPIC_E_CAPACITY otherwise).  Synchronises.
+ * The device keeps only the first two rows of each SU(3) link: a get returns
+ * the third row as the conjugate cross product of the first two, and a set
+ * uses the first two rows of each link (the third must agree with them, as it
+ * does for a unitary matrix of unit determinant).
  */
 #define CPIC_STATE_U 0
 #define CPIC_STATE_PHI 1

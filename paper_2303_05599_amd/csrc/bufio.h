@@ -61,36 +61,34 @@ __device__ __forceinline__ void bst_i(const View<int>& v, uint32_t voff, uint32_
 // component offsets inside one field buffer set (68 components)
 constexpr uint32_t kCompU = 0, kCompPhi = 36, kCompE = 44, kCompPi = 60;
 
-template <typename T> __device__ __forceinline__ m3<T> vU(const View<T>& v, uint32_t voff, int i)
+// Links are kept as their first two rows (components 0..11 of the 18 of
+// link i): no kernel reads the slots of the third row, and the field updates
+// do not write them.  The third row of an SU(3) matrix is the complex
+// conjugate of the cross product of the first two (exact for det U = 1, to
+// the link's unitarity otherwise), and every reader rebuilds it.
+template <typename T> __device__ __forceinline__ void rebuild_row3(m3<T>& m)
 {
-    m3<T> m;
-#pragma unroll
-    for (int c = 0; c < 9; c++)
-        m.e[c] = {bld(v, voff, kCompU + 18 * i + 2 * c), bld(v, voff, kCompU + 18 * i + 2 * c + 1)};
-    return m;
-}
-// link i read as its first two rows (12 of 18 components); the third row of
-// an SU(3) matrix is the complex conjugate of the cross product of the first
-// two (exact for det U = 1, to the link's unitarity otherwise)
-template <typename T> __device__ __forceinline__ m3<T> vU2(const View<T>& v, uint32_t voff, int i)
-{
-    m3<T> m;
-#pragma unroll
-    for (int c = 0; c < 6; c++)
-        m.e[c] = {bld(v, voff, kCompU + 18 * i + 2 * c), bld(v, voff, kCompU + 18 * i + 2 * c + 1)};
 #pragma unroll
     for (int j = 0; j < 3; j++) {
         const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
         const cx<T> p = cmul(m.e[j1], m.e[3 + j2]), q = cmul(m.e[j2], m.e[3 + j1]);
         m.e[6 + j] = {p.re - q.re, q.im - p.im};
     }
+}
+template <typename T> __device__ __forceinline__ m3<T> vU(const View<T>& v, uint32_t voff, int i)
+{
+    m3<T> m;
+#pragma unroll
+    for (int c = 0; c < 6; c++)
+        m.e[c] = {bld(v, voff, kCompU + 18 * i + 2 * c), bld(v, voff, kCompU + 18 * i + 2 * c + 1)};
+    rebuild_row3(m);
     return m;
 }
 template <typename T, int CP = 0>
 __device__ __forceinline__ void vU_st(const View<T>& v, uint32_t voff, int i, const m3<T>& m)
 {
 #pragma unroll
-    for (int c = 0; c < 9; c++) {
+    for (int c = 0; c < 6; c++) {
         bst<T, CP>(v, voff, kCompU + 18 * i + 2 * c, m.e[c].re);
         bst<T, CP>(v, voff, kCompU + 18 * i + 2 * c + 1, m.e[c].im);
     }

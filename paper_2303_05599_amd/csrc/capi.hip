@@ -737,9 +737,22 @@ static size_t state_bytes(const cpic_ctx* c, int which)
 template <typename T> static void soa_to_host(const std::vector<T>& d, double* h, int which, int V)
 {
     if (which == CPIC_STATE_U) {
+        // the device keeps the first two rows of each link; the third is their
+        // conjugate cross product, formed here as the kernels form it
         for (int i = 0; i < 2; i++)
-            for (int s = 0; s < V; s++)
-                for (int c = 0; c < 18; c++) h[((size_t)i * V + s) * 18 + c] = (double)d[((size_t)i * 18 + c) * V + s];
+            for (int s = 0; s < V; s++) {
+                double* m = h + ((size_t)i * V + s) * 18;
+                for (int c = 0; c < 12; c++) m[c] = (double)d[((size_t)i * 18 + c) * V + s];
+                for (int j = 0; j < 3; j++) {
+                    const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+                    const double* a = m + 2 * j1; const double* b = m + 6 + 2 * j2;  // r1[j1], r2[j2]
+                    const double* e = m + 2 * j2; const double* f = m + 6 + 2 * j1;  // r1[j2], r2[j1]
+                    const double pre = a[0] * b[0] - a[1] * b[1], pim = a[0] * b[1] + a[1] * b[0];
+                    const double qre = e[0] * f[0] - e[1] * f[1], qim = e[0] * f[1] + e[1] * f[0];
+                    m[12 + 2 * j] = pre - qre;
+                    m[13 + 2 * j] = qim - pim;
+                }
+            }
     } else {
         const int blocks = which == CPIC_STATE_E ? 2 : 1;
         for (int i = 0; i < blocks; i++)

@@ -33,7 +33,7 @@ __device__ __forceinline__ int wrap(int v, int N) { return v < 0 ? v + N : (v >=
 //   Proj U_{-2,1}(c)  = U_2(c-2)^+ G(c-2) U_2(c-2)
 // The field update writes G, D_x, D_y, S_x, S_y and P for every site (the aux
 // buffer), so a cell's fields take four G's, three sums and three links.
-// The links are read as two rows with the third rebuilt (bufio.h vU2).
+// The links are read as two rows with the third rebuilt (vU in bufio.h).
 enum PushJob { kJobEx = 0, kJobEy, kJobEeta, kJobBx, kJobBy, kJobBeta, kJobs };
 
 // the cell and the neighbours the push reads, as byte offsets into a component array
@@ -67,7 +67,7 @@ __device__ __forceinline__ a8<T> job_field(int j, const View<T>& A, const View<T
         const uint32_t sb = i == 0 ? c.s_xm : c.s_ym;
         const uint32_t cs = i == 0 ? kAuxS1 : kAuxS2;
         const a8<T> here = vA(X, c.s, cs);
-        const a8<T> tb = transport_adj(vU2(A, sb, i), vA(X, sb, cs));
+        const a8<T> tb = transport_adj(vU(A, sb, i), vA(X, sb, cs));
         const T q = T(1) / (T(4) * t);
 #pragma unroll
         for (int a = 0; a < 8; a++) F.v[a] = q * (here.v[a] + tb.v[a]);
@@ -87,14 +87,14 @@ __device__ __forceinline__ a8<T> job_field(int j, const View<T>& A, const View<T
 #pragma unroll
         for (int a = 0; a < 8; a++) F.v[a] = q * D.v[a];
     } else {
-        const a8<T> g2 = transport_adj(vU2(A, c.s_ym, 1), vA(X, c.s_ym, kAuxG));
+        const a8<T> g2 = transport_adj(vU(A, c.s_ym, 1), vA(X, c.s_ym, kAuxG));
         CPIC_PHASE();
-        const a8<T> g12 = transport_adj(vU2(A, c.s_xmym, 1), vA(X, c.s_xmym, kAuxG));
+        const a8<T> g12 = transport_adj(vU(A, c.s_xmym, 1), vA(X, c.s_xmym, kAuxG));
         a8<T> g1 = vA(X, c.s_xm, kAuxG);
 #pragma unroll
         for (int a = 0; a < 8; a++) g1.v[a] += g12.v[a];
         CPIC_PHASE();
-        const a8<T> g1t = transport_adj(vU2(A, c.s_xm, 0), g1);
+        const a8<T> g1t = transport_adj(vU(A, c.s_xm, 0), g1);
         const a8<T> g0 = vA(X, c.s, kAuxG);
 #pragma unroll
         for (int a = 0; a < 8; a++) F.v[a] = T(-0.25) * (g0.v[a] + g1t.v[a] + g2.v[a]);

@@ -50,8 +50,9 @@ template <typename T, int HS> struct LdsSrc {
     {
         m3<T> m;
 #pragma unroll
-        for (int c = 0; c < 9; c++)
+        for (int c = 0; c < 6; c++)
             m.e[c] = {l[(18 * i + 2 * c) * HS + h], l[(18 * i + 2 * c + 1) * HS + h]};
+        rebuild_row3(m);
         return m;
     }
     __device__ __forceinline__ a8<T> A(uint32_t h, uint32_t c0) const
@@ -252,11 +253,14 @@ __device__ __forceinline__ void field_tile_body(const Fields<T>& in, const Field
             const int hy = h / HX, hx = h - hy * HX;
             const int gx = (x0 + hx - 1 + N) % N, gy = (y0 + hy - 1 + N) % N;
             const uint32_t go = (uint32_t)(gy * N + gx) * (uint32_t)sizeof(T);
+            // (the slots of the links' third rows, 12..17 and 30..35, stay unused)
             T v[NC];
 #pragma unroll
-            for (int c = 0; c < NC; c++) v[c] = bld(vi, go, (uint32_t)c);
+            for (int c = 0; c < NC; c++)
+                if (c % 18 < 12 || c >= 36) v[c] = bld(vi, go, (uint32_t)c);
 #pragma unroll
-            for (int c = 0; c < NC; c++) lds[c * HS + h] = v[c];
+            for (int c = 0; c < NC; c++)
+                if (c % 18 < 12 || c >= 36) lds[c * HS + h] = v[c];
         }
     }
     __syncthreads();
@@ -549,8 +553,9 @@ __device__ __forceinline__ void field_link_body(const Fields<T>& in, const Field
     auto link = [&](const View<T>& v, uint32_t o, int d) {
         m3<T> m;
 #pragma unroll
-        for (int c = 0; c < 9; c++)
+        for (int c = 0; c < 6; c++)
             m.e[c] = {bld(v, o + (uint32_t)(18 * d) * v.cs, 2 * c), bld(v, o + (uint32_t)(18 * d) * v.cs, 2 * c + 1)};
+        rebuild_row3(m);
         return m;
     };
     const a8<T> PHI = vA(vi, s, kCompPhi);

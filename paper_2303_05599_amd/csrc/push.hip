@@ -143,7 +143,7 @@ __device__ __forceinline__ void push_helper4(int role, const View<T>& A, const V
     const T qe = T(1) / (T(4) * t), qb = T(1) / (T(2) * t);
     const bool on_e = n > 0, on_bt = n > 0 && !eonly, on_be = !eonly;
     if (role == 3) {
-        const m3<T> Ly = vU2(A, c.s_xmym, 1), Lx = vU2(A, c.s_xm, 0);
+        const m3<T> Ly = vU(A, c.s_xmym, 1), Lx = vU(A, c.s_xm, 0);
         const a8<T> g12 = vA(X, c.s_xmym, kAuxG), g0 = vA(X, c.s, kAuxG);
         // E_eta from P (n > 0) or from pi(1/2) (n = 0), through one selected buffer
         const bool first = n == 0;
@@ -162,7 +162,7 @@ __device__ __forceinline__ void push_helper4(int role, const View<T>& A, const V
     const int i = role - 1;
     const uint32_t sb = i == 0 ? c.s_xm : c.s_ym;
     const uint32_t cs = i == 0 ? kAuxS1 : kAuxS2;
-    const m3<T> L = vU2(A, sb, i);
+    const m3<T> L = vU(A, sb, i);
     const a8<T> here = vA(X, c.s, cs), back = vA(X, sb, cs), gb = vA(X, sb, kAuxG);
     const a8<T> D = vA(X, c.s, i == 0 ? kAuxDx : kAuxDy);
     const a8<T> tb = transport_adj(L, back), tg = transport_adj(L, gb);
@@ -260,9 +260,8 @@ __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& 
             if (dx < -1 || dx > 1) atomicAdd(err, 1);
             if (dy < -1 || dy > 1) atomicAdd(err, 1);
             m3<T> Lx, Ly;
-            // (as two rows, like the helpers: the third rows stay out of the push's footprint)
-            if (dx != 0) Lx = vU2(A, (uint32_t)(cy * N + (dx > 0 ? cx : wrap(cx - 1, N))) * (uint32_t)sizeof(T), 0);
-            if (dy != 0) Ly = vU2(A, (uint32_t)((dy > 0 ? cy : wrap(cy - 1, N)) * N + nx) * (uint32_t)sizeof(T), 1);
+            if (dx != 0) Lx = vU(A, (uint32_t)(cy * N + (dx > 0 ? cx : wrap(cx - 1, N))) * (uint32_t)sizeof(T), 0);
+            if (dy != 0) Ly = vU(A, (uint32_t)((dy > 0 ? cy : wrap(cy - 1, N)) * N + nx) * (uint32_t)sizeof(T), 1);
             const a8<T> ph = vA(A, cell.s, kCompPhi);
             if (dx == 1) Q = rotate(Lx, Q);
             else if (dx == -1) Q = transport(Lx, Q);  // U Q U^+
@@ -372,8 +371,8 @@ __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& 
                 CPIC_PHASE();
                 const int lx = min((int)floor(x), N - 1), ly = min((int)floor(y), N - 1);
                 constexpr T tol = sizeof(T) == 8 ? T(1e-15) : T(1e-7);
-                const a8<T> gx = link_generator(vU2(A, (uint32_t)(ny * N + lx) * (uint32_t)sizeof(T), 0), tol, 50);
-                const a8<T> gy = link_generator(vU2(A, (uint32_t)(ly * N + nx) * (uint32_t)sizeof(T), 1), tol, 50);
+                const a8<T> gx = link_generator(vU(A, (uint32_t)(ny * N + lx) * (uint32_t)sizeof(T), 0), tol, 50);
+                const a8<T> gy = link_generator(vU(A, (uint32_t)(ly * N + nx) * (uint32_t)sizeof(T), 1), tol, 50);
                 const a8<T> ph = vA(A, cell.s, kCompPhi);
                 const T veta = pe / ptau;
                 a8<T> M;

@@ -476,3 +476,36 @@ def test_force_table_matches_gather_push():
     assert np.array_equal(out[0][0][:, 14:16], out[1][0][:, 14:16])
     assert rel_err(out[1][0], out[0][0]) < 1e-13
     assert rel_err(out[1][1], out[0][1]) < 1e-13
+
+
+@pytest.mark.parametrize("launch", ["ctile32x8", "tile32x8", "site64x4", "link32x4w2"])
+def test_links_are_kept_as_two_rows(launch):
+    """The device keeps the first two rows of each link (include/cpic.h): the
+    third rows given to cpic_set_state are never read, so zeroing them leaves
+    every result bit for bit the same in every field decomposition, and
+    cpic_get_state returns the third row as the conjugate cross product of
+    the first two (for a unitary link of unit determinant: its third row)."""
+    N, L, n0, steps, n = 32, 6.0, 4, 20, 500
+    a = oracle.lattice_spacing(L, N)
+    st = inputs.random_state(N, 71, eps_link=0.5)
+    P = inputs.random_particles(n, N, 72, p_scale=0.6)
+    cut = dict(st, U=st["U"].copy())
+    cut["U"][..., 2, :] = 0.0
+    out = []
+    for state in (st, cut):
+        ctx = cp.Context(glasma(N, L, steps=n0 + steps), particle_params(n, 0.3 / a, N, L, 0))
+        ctx.set_launch(*LAUNCHES[launch])
+        ctx.load_state(state, n=n0, particles=P)
+        U0 = ctx.get_state(cp.STATE_U)
+        ctx.step(steps)
+        ctx.sync()
+        out.append([U0] + [ctx.get_state(w) for w in (cp.STATE_U, cp.STATE_E, cp.STATE_PHI, cp.STATE_PI,
+                                                      cp.STATE_PARTICLES)] + [ctx.observables()])
+        ctx.close()
+    for x, y in zip(out[0], out[1]):
+        assert np.array_equal(x, y)
+    # the third row handed back is the one of the (unitary) input links
+    assert np.max(np.abs(out[0][0] - st["U"])) < 1e-14
+    U = out[0][1]
+    r3 = np.conj(np.cross(U[..., 0, :], U[..., 1, :]))
+    assert np.max(np.abs(U[..., 2, :] - r3)) < 1e-15

@@ -54,6 +54,21 @@ __global__ void permute_kernel(const T* __restrict__ r, const int* __restrict__ 
     pid2[i] = pid[src];
 }
 
+// the permuted records back into the buffers the step graphs captured, in one
+// pass (three device copies cost three launches)
+template <typename T>
+__global__ void copy_back_kernel(const T* __restrict__ r2, const int* __restrict__ cell2,
+                                 const int* __restrict__ pid2, int np, T* r, int* cell, int* pid)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+#pragma unroll
+    for (int c = 0; c < kPartReals; c++) r[(size_t)c * np + i] = r2[(size_t)c * np + i];
+    cell[i] = cell2[i];
+    cell[np + i] = cell2[np + i];
+    pid[i] = pid2[i];
+}
+
 size_t sort_temp_bytes(int np, int N)
 {
     size_t bytes = 0;
@@ -76,10 +91,8 @@ hipError_t sort_particles(const SortBufs& b, T* r, int* cell, int* pid, int np, 
     T* r2 = static_cast<T*>(b.r2);
     hipLaunchKernelGGL(permute_kernel<T>, dim3(blocks), dim3(256), 0, st, r, cell, pid, b.perm, np, r2, b.cell2,
                        b.pid2);
-    e = hipMemcpyAsync(r, r2, sizeof(T) * kPartReals * (size_t)np, hipMemcpyDeviceToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(cell, b.cell2, sizeof(int) * 2 * (size_t)np, hipMemcpyDeviceToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(pid, b.pid2, sizeof(int) * (size_t)np, hipMemcpyDeviceToDevice, st);
-    return e;
+    hipLaunchKernelGGL(copy_back_kernel<T>, dim3(blocks), dim3(256), 0, st, r2, b.cell2, b.pid2, np, r, cell, pid);
+    return hipSuccess;  // launch errors surface at the stream's next synchronisation, as for every kernel
 }
 
 template hipError_t sort_particles<double>(const SortBufs&, double*, int*, int*, int, int, hipStream_t);

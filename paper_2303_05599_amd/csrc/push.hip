@@ -277,13 +277,19 @@ __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& 
         CPIC_PHASE();
         // one or two waves: the owner evaluates its share of the jobs (with
         // four, the helpers evaluate all of them)
-        if (TPP != 4 && live) {
+        if (TABLE && live) {
+            // all six table vectors gathered at once (one memory round trip)
+            const View<T> TV = make_view<T>(table, 48, V);
+            a8<T> tv[kJobs];
+#pragma unroll
+            for (int j = 0; j < kJobs; j++) tv[j] = vA(TV, cell.s, 8 * (uint32_t)j);
+#pragma unroll
+            for (int j = 0; j < kJobs; j++) f[j] += job_active(j, n, eonly) ? dot(Q, tv[j]) : T(0);
+        } else if (TPP != 4 && live) {
 #pragma unroll 1
             for (int j = 0; j < kJobs; j++) {
                 if (job_wave<TPP>(j) != 0 || !job_active(j, n, eonly)) continue;
-                T dq;
-                if constexpr (TABLE) dq = dot(Q, vA(make_view<T>(table, 48, V), cell.s, 8 * (uint32_t)j));
-                else dq = dot(Q, job_field<T>(j, A, B, X, cell, n, t));
+                const T dq = dot(Q, job_field<T>(j, A, B, X, cell, n, t));
                 const int k = j;  // job j yields force component j
 #pragma unroll
                 for (int kk = 0; kk < 6; kk++) f[kk] += kk == k ? dq : T(0);

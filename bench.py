@@ -486,9 +486,10 @@ def main():
     ap.add_argument("--tune-report", default=None, help="write the launch tuner's table to this file")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (reference for the HBM counters)")
-    ap.add_argument("--pmc-summary", nargs=5, metavar=("OUT", "FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR",
+    ap.add_argument("--pmc-summary", nargs=5, metavar=("OUT", "FETCH_DIRS", "WRITE_DIRS", "COPY_FETCH_DIR",
                                                        "COPY_WRITE_DIR"),
-                    help="condense rocprofv3 --pmc output directories into a profiles/ summary")
+                    help="condense rocprofv3 --pmc output directories into a profiles/ summary (FETCH_DIRS and "
+                         "WRITE_DIRS: comma-separated, one directory per profiled run)")
     ap.add_argument("--trace-summary", nargs=3, metavar=("OUT", "TRACE_DIR", "TIMED_STEPS"),
                     help="condense a rocprofv3 --kernel-trace --stats directory into a markdown table")
     ap.add_argument("--command", default="", help="command line recorded in a summary")

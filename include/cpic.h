@@ -275,11 +275,11 @@ cpic_status cpic_set_push_mode(cpic_ctx* ctx, int32_t mode);
 cpic_status cpic_get_push_mode(const cpic_ctx* ctx, int32_t* mode);
 
 /* Current launch configuration: out = {bx, by, xcd_remap, waves, push lanes,
- * variant, non-temporal link stores}.  The last is set at creation (and by
+ * variant, non-temporal stores of the new state}.  The last is set at creation (and by
  * cpic_jets_enable, cpic_set_push_mode): 1 where the state, the new state
  * and what the rest of the step reads exceed the 256 MB last-level cache
- * together (FP64 at 512^2), so that the new links and scalar, which the push
- * does not read, bypass it; cpic_tune may change it.  Results are the same
+ * together (FP64 at 512^2), so that the new links, phi, E and pi bypass it;
+ * cpic_tune may change it.  Results are the same
  * either way. */
 cpic_status cpic_get_launch(const cpic_ctx* ctx, int32_t out[7]);
 

@@ -109,9 +109,9 @@ static void free_all(cpic_ctx* c)
 // old state, the aux pieces, the force table, the particle records and the
 // light-like paths; where these and the new state together exceed the 256 MB
 // last-level cache (FP64 at 512^2: 400 MB with 1e5 particles; the FP32 jets
-// workload: 360 MB), the new links and scalar, which the rest of the step
-// does not read, are stored non-temporal so that they do not displace what
-// it does.
+// workload: 360 MB), the new state (links, phi, E, pi) is stored
+// non-temporal so that it does not displace what the rest of the step reads
+// (it reads the new E and pi only at n = 0).
 static void set_store_policy(cpic_ctx* c)
 {
     double reals = (2.0 * c->rps + kAuxReals) * (double)c->V + (double)kPartReals * (double)c->np;
@@ -1242,7 +1242,7 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
     c->cfg = best;
     std::snprintf(line, sizeof line, "best field: %s bx=%d by=%d waves=%d remap=%d %.2f us%s\n",
                   kVariantName[best.split], best.bx, best.by, best.waves, best.xcd_remap, best_ms * 1e3,
-                  best.split == 3 && best.nt_store ? " (non-temporal link stores)" : "");
+                  best.split == 3 && best.nt_store ? " (non-temporal stores of the new state)" : "");
     rep += line;
     if (c->np > 0 && c->n >= c->sc.n_form && c->n < c->sc.n_max) {
         const size_t rb = sizeof(T) * kPartReals * (size_t)c->np, cb = sizeof(int) * 2 * (size_t)c->np;

@@ -476,10 +476,11 @@ __device__ __forceinline__ void field_ctile_body(const Fields<T>& in, const Fiel
     }
     CPIC_PHASE();
     // drift: U_i <- exp(i (dt/t_half) E_i) U_i ; phi <- phi + dt t_half pi
-    // CP: cache policy of the new links and scalar.  The push reads the old
-    // links and the aux pieces, not the new state: where the three do not fit
-    // in the last-level cache together, the new links and scalar go out
-    // non-temporal so that they do not displace what the push reads next.
+    // CP: cache policy of the new state (links, phi, E, pi).  The rest of the
+    // step reads the old links and scalar and the aux pieces: where these and
+    // the new state do not fit in the last-level cache together, the new state
+    // goes out non-temporal so that it does not displace what the push reads
+    // next.
     m3<T> U1 = mul(expi(E1, eps_drift), L.U(s, 0));
     if (reunit) U1 = reunitarize(U1);
     vU_st<T, CP>(vo, g.s, 0, U1);
@@ -490,9 +491,9 @@ __device__ __forceinline__ void field_ctile_body(const Fields<T>& in, const Fiel
 #pragma unroll
     for (int a = 0; a < 8; a++) PHI.v[a] += phi_drift * PI.v[a];
     vA_st<T, CP>(vo, g.s, kCompPhi, PHI);
-    vA_st(vo, g.s, kCompE, E1);
-    vA_st(vo, g.s, kCompE + 8, E2);
-    vA_st(vo, g.s, kCompPi, PI);
+    vA_st<T, CP>(vo, g.s, kCompE, E1);
+    vA_st<T, CP>(vo, g.s, kCompE + 8, E2);
+    vA_st<T, CP>(vo, g.s, kCompPi, PI);
     if (AUX && aux_on) {
         const View<T> va = make_view<T>(aux, kAuxReals, V);
         vA_st(va, g.s, kAuxG, G);

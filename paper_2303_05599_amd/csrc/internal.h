@@ -84,7 +84,7 @@ struct LaunchCfg {
     int split = 0;        // kernel variant: 0 one thread per site, 1 one thread per link (128 sites per
                           // block), 2 one thread per site with the tile and its halo staged in LDS,
                           // 3 as 2 with two rows per link in LDS and the scalars from global memory
-    int nt_store = 0;     // variant 3 with particles: new links and scalar stored non-temporal
+    int nt_store = 0;     // variant 3 with particles: the new state stored non-temporal
 };
 
 struct PushArgs {

@@ -23,7 +23,7 @@ library's next state must agree with it: every site and every particle.
     every site and a random sample of 4096 particles (the oracle pushes
     particles independently of each other).
 The FP64 headline event and the jets workload run with non-temporal stores
-of the new links and scalar (their working sets exceed the last-level cache),
+of the new state (their working sets exceed the last-level cache),
 the FP32 headline event without.
 """
 import math
@@ -86,7 +86,7 @@ def test_headline_event_one_step(precision):
     ctx = cp.Context(glasma(prec), p)
     ctx.init_mv()
     # FP64: old state, new state, aux pieces and particles exceed the 256 MB
-    # last-level cache, so the new links go out non-temporal unless the tuner
+    # last-level cache, so the new state goes out non-temporal unless the tuner
     # finds otherwise; both policies give the same results
     assert ctx.get_launch()["nt_store"] == (1 if prec == cp.FP64 else 0)
     ctx.step(80)                      # past the formation step 69

@@ -196,6 +196,39 @@ cpic_status cpic_observables_full(cpic_ctx* ctx, double* out, int32_t cap);
 cpic_status cpic_diagnostics(cpic_ctx* ctx, double out[10]);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the field columns
+ * out[0..7] of cpic_diagnostics, computed on a caller-owned device buffer set
+ * and written to caller-owned device memory, with no allocation of any kind.
+ *   precision    CPIC_FP64 or CPIC_FP32: the element type of fields_dev
+ *   N            lattice size, 4 <= N <= 1024 (any N; larger: CPIC_E_INVALID,
+ *                nothing launched)
+ *   dtau_over_a  leapfrog step in units of a; t = n dtau_over_a enters the
+ *                energy terms and the half-step correction of the momenta
+ *   n            step of the state (E and pi at n - 1/2, as the library keeps them)
+ *   fields_dev   device buffer set of 68 N^2 reals, component-major (site
+ *                s = y N + x innermost): U_x [18][N^2], U_y [18][N^2] (complex
+ *                3x3, row-major, re/im; only the first two rows, components
+ *                0..11, are read: the third row is rebuilt as the conjugate
+ *                cross product), phi [8][N^2], E_x [8][N^2], E_y [8][N^2],
+ *                pi [8][N^2].  Read only.
+ *   out_dev      device array of 8 doubles, written in the order of
+ *                cpic_diagnostics out[0..7] (non-finite values are written as
+ *                they are: no CPIC_E_NAN, since the call does not synchronise)
+ *   hip_stream   stream of the current device (NULL: the null stream)
+ * Asynchronous: two kernels on hip_stream, no synchronisation, no memset.
+ * The per-block partial sums go to a fixed 256 KiB device array of the
+ * library (one per GPU, held until the process ends; its address on a device
+ * is resolved by cpic_create or by this call's first use on that device).
+ * Every call overwrites all the partials it reads, so no state carries over;
+ * calls that overlap on one GPU (several streams or host threads) race on
+ * that array and must be ordered by the caller.  Errors: CPIC_E_INVALID (bad
+ * argument), CPIC_E_HIP (launch failure); message in cpic_last_error(NULL).
+ */
+cpic_status cpic_field_diagnostics_noalloc(int32_t precision, int32_t N, double dtau_over_a, int64_t n,
+                                           const void* fields_dev, double* out_dev, void* hip_stream);
+
+/*
  * Copy a part of the state to/from caller host memory, always as float64 in
  * this layout (site s = y*N + x, x along e1), whatever the device precision:
  *   CPIC_STATE_U         complex128 [2][N][N][3][3]  links U_x, U_y (row-major)

@@ -93,6 +93,7 @@ def lib():
             "cpic_set_push_mode": [P, i32], "cpic_get_push_mode": [P, ctypes.POINTER(i32)],
             "cpic_jets_observables": [P, P, i32, ctypes.POINTER(i32)],
             "cpic_jets_timing": [P, ctypes.POINTER(d), ctypes.POINTER(i64)],
+            "cpic_field_diagnostics_noalloc": [i32, i32, d, i64, P, P, P],
         }
         for name, args in sigs.items():
             f = getattr(L, name)
@@ -119,6 +120,18 @@ def current_stream():
     except ImportError:
         pass
     return None
+
+
+def field_diagnostics_noalloc(precision, N, dtau_over_a, n, fields_dev_ptr, out_dev_ptr, stream=None):
+    """cpic_field_diagnostics_noalloc: field diagnostics of a caller-owned device
+    buffer set (68 N^2 reals, the library's layout) into 8 doubles of caller-owned
+    device memory; asynchronous on `stream` (a raw hipStream_t, default torch's)."""
+    L = lib()
+    s = current_stream() if stream is None else stream
+    st = L.cpic_field_diagnostics_noalloc(precision, N, dtau_over_a, n, ctypes.c_void_p(fields_dev_ptr),
+                                          ctypes.c_void_p(out_dev_ptr), s)
+    if st:
+        raise CpicError(st, L.cpic_last_error(None).decode())
 
 
 def _ptr(a):

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcpic.so")
-SOURCES = ["field.hip", "push.hip", "jets.hip", "su2.hip", "ic.hip", "sort.hip", "capi.hip", "batch.hip"]
+SOURCES = ["field.hip", "push.hip", "jets.hip", "su2.hip", "ic.hip", "sort.hip", "capi.hip", "batch.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions stay off (hipcc forms them from plain float code otherwise)

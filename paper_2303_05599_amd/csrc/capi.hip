@@ -237,6 +237,10 @@ extern "C" cpic_status cpic_create(const cpic_glasma_params* gp, const cpic_part
     c->dcap = std::max((c->V + 255) / 256, std::max(c->np > 0 ? push_blocks((int)c->np, 1) : 0, 1));
     if (e == hipSuccess) e = hipMalloc(&c->dpart, sizeof(double) * 8 * c->dcap);
     if (e == hipSuccess) e = hipMalloc(&c->dout, sizeof(double) * 16);
+    // the allocation-free entry point's scratch array: its device address on
+    // this device is resolved here, at set-up, rather than inside that call
+    double* scratch_dev = nullptr;
+    if (e == hipSuccess && noalloc_scratch(&scratch_dev) != CPIC_OK) e = hipErrorInvalidSymbol;
     if (e == hipSuccess) e = hipMemsetAsync(c->d_step, 0, 2 * sizeof(int), c->st);
     if (e == hipSuccess) e = hipMemsetAsync(c->d_err, 0, sizeof(int), c->st);
     if (e == hipSuccess && c->obs) e = hipMemsetAsync(c->obs, 0, sizeof(double) * 4 * c->nslots, c->st);

@@ -86,4 +86,7 @@ int next_sort_point(const cpic_ctx* c, int n);
 // host bookkeeping of k launched steps (sample list, step counter, buffer parity)
 cpic_status host_advance(cpic_ctx* c, int k);
 PushArgs push_args(const cpic_ctx* c, int tpp);
+// device address of the allocation-free entry point's scratch array on the
+// current device (resolved once per device; noalloc.hip)
+cpic_status noalloc_scratch(double** out);
 }  // namespace cpic

@@ -48,40 +48,47 @@ def lib():
     global _lib
     if _lib is None:
         build()
-        L = ctypes.CDLL(LIB_PATH)
-        d, i, u64, p = ctypes.c_double, ctypes.c_int, ctypes.c_uint64, ctypes.c_void_p
-        sig = {
-            "orc_forces": (None, [i, d, p, p, p, p]),
-            "orc_kick": (None, [i, d, d, p, p, p, p]),
-            "orc_drift": (None, [i, d, d, p, p, p, p]),
-            "orc_field_step": (None, [i, i, d, d, p, p, p, p]),
-            "orc_energy": (None, [i, d, p, p, p, p, p]),
-            "orc_gauss": (None, [i, p, p, p, p, p]),
-            "orc_unitarity": (None, [i, p, p]),
-            "orc_philox": (None, [p, p, p]),
-            "orc_mv_charges": (None, [i, u64, i, i, d, p]),
-            "orc_wilson_mult": (None, [i, p, p]),
-            "orc_pure_gauge": (None, [i, p, p]),
-            "orc_kv_links": (i, [i, p, p, p, d, i, p]),
-            "orc_pi0": (None, [i, p, p, p, p]),
-            "orc_q0": (None, [i, p]),
-            "orc_casimirs": (None, [p, p, p]),
-            "orc_particles_init": (None, [i, i, u64, d, d, i, i, p]),
-            "orc_particle_fields": (None, [i, i, d, i, p, p, p, p, p, p, p]),
-            "orc_particles_step": (i, [i, i, i, d, d, i, i, p, p, p, p, p, p, i, p]),
-            "orc_link_generator": (None, [p, p]),
-            "orc_particles_observe": (None, [d, d, i, i, p, p]),
-            "orc_jet_step": (None, [i, i, i, d, d, i, p, p, p, p, p, p, p, p]),
-            "orc_generator": (None, [i, p]),
-            "orc_proj": (None, [p, p]),
-            "orc_expi": (None, [p, d, p]),
-        }
-        for name, (res, args) in sig.items():
-            f = getattr(L, name)
-            f.restype = res
-            f.argtypes = args
-        _lib = L
+        _lib = load_library(LIB_PATH)
     return _lib
+
+
+def load_library(path):
+    """A compiled copy of the oracle's C part with its argument types set
+    (the oracle's own library, or a copy the tests build from modified
+    sources to show that a pin catches a planted mistake)."""
+    L = ctypes.CDLL(path)
+    d, i, u64, p = ctypes.c_double, ctypes.c_int, ctypes.c_uint64, ctypes.c_void_p
+    sig = {
+        "orc_forces": (None, [i, d, p, p, p, p]),
+        "orc_kick": (None, [i, d, d, p, p, p, p]),
+        "orc_drift": (None, [i, d, d, p, p, p, p]),
+        "orc_field_step": (None, [i, i, d, d, p, p, p, p]),
+        "orc_energy": (None, [i, d, p, p, p, p, p]),
+        "orc_gauss": (None, [i, p, p, p, p, p]),
+        "orc_unitarity": (None, [i, p, p]),
+        "orc_philox": (None, [p, p, p]),
+        "orc_mv_charges": (None, [i, u64, i, i, d, p]),
+        "orc_wilson_mult": (None, [i, p, p]),
+        "orc_pure_gauge": (None, [i, p, p]),
+        "orc_kv_links": (i, [i, p, p, p, d, i, p]),
+        "orc_pi0": (None, [i, p, p, p, p]),
+        "orc_q0": (None, [i, p]),
+        "orc_casimirs": (None, [p, p, p]),
+        "orc_particles_init": (None, [i, i, u64, d, d, i, i, p]),
+        "orc_particle_fields": (None, [i, i, d, i, p, p, p, p, p, p, p]),
+        "orc_particles_step": (i, [i, i, i, d, d, i, i, p, p, p, p, p, p, i, p, p]),
+        "orc_link_generator": (None, [p, p]),
+        "orc_particles_observe": (None, [d, d, i, i, p, p]),
+        "orc_jet_step": (None, [i, i, i, d, d, i, p, p, p, p, p, p, p, p]),
+        "orc_generator": (None, [i, p]),
+        "orc_proj": (None, [p, p]),
+        "orc_expi": (None, [p, d, p]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
 
 
 def _ptr(a: np.ndarray):
@@ -342,6 +349,8 @@ class Run:
         self.errors = 0
         self.jets = jets
         self.color_mode = {"cpic": 0, "log": 1}[color]
+        # p^tau from its equation of motion [eq:ptaueq] beside the constraint (moving particles)
+        self.ptau_ode = None if self.P is None or self.is_static else np.zeros(self.P.shape[0])
 
     def step(self):
         N, n, st = self.N, self.n, self.st
@@ -354,7 +363,8 @@ class Run:
         if push:
             self.errors += lib().orc_particles_step(
                 N, n, self.n_form, self.dt, self.mhat, int(self.is_static), self.color_mode, _ptr(U_n), _ptr(phi_n),
-                _ptr(E_old), _ptr(st["E"]), _ptr(pi_old), _ptr(st["pi"]), self.P.shape[0], _ptr(self.P))
+                _ptr(E_old), _ptr(st["E"]), _ptr(pi_old), _ptr(st["pi"]), self.P.shape[0], _ptr(self.P),
+                None if self.ptau_ode is None else _ptr(self.ptau_ode))
         if jets:
             self.jets.step(n, U_n, phi_n, E_old, st["E"], pi_old, st["pi"])
         self.n += 1
@@ -362,3 +372,9 @@ class Run:
     def observe(self):
         """Sums of (dp_T^2, dp_L^2, dp_par^2, dp_perp^2) at t_n in hat units."""
         return particles_observe(self.n * self.dt, self.mhat, self.is_static, self.P)
+
+    def ptau_constraint(self):
+        """p^tau of every particle at t_n from the constraint [eq:ptau] (hat units)."""
+        t = self.n * self.dt
+        P = self.P
+        return np.sqrt(P[:, 3] ** 2 + P[:, 4] ** 2 + (t * P[:, 5]) ** 2 + self.mhat ** 2)

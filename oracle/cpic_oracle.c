@@ -860,12 +860,21 @@ static void rotate_q(double *Q, M3 A)
  * (floor(x), NGP row), A_y on the y link at (NGP column, floor(y)), phi at
  * the nearest grid point, all at t_n; v_eta = p^eta / p^tau.
  *
+ * ptau_ode (may be NULL; moving particles only): p^tau integrated from its own
+ * equation of motion [eq:ptaueq] instead of the constraint [eq:ptau], the
+ * temporal-constraint check of Appendix D.  In hat units
+ *   dp^tau/dt = -t (p^eta)^2 / p^tau
+ *               + (e_eta t p^eta + e_x p^x + e_y p^y) / p^tau,
+ * Euler-stepped with the rest of the particle (the same charges, fields and
+ * momenta at n; p^tau on the right-hand side is the integrated value).  At
+ * the formation step it starts from the constraint.
+ *
  * Returns the number of particles whose grid point moved by more than one
  * cell along an axis (an error).
  */
 int orc_particles_step(int N, int n, int n_form, double dt, double mhat, int is_static, int color_mode,
                        const cplx *U, const double *phi, const double *E_old, const double *E_new,
-                       const double *pi_old, const double *pi_new, int np, double *P)
+                       const double *pi_old, const double *pi_new, int np, double *P, double *ptau_ode)
 {
     build_generators();
     int errors = 0;
@@ -910,6 +919,11 @@ int orc_particles_step(int N, int n, int n_form, double dt, double mhat, int is_
         double px = r[P_PX], py = r[P_PY], pe = r[P_PETA];
         double ptau = sqrt(px * px + py * py + (t * pe) * (t * pe) + mhat * mhat);
         double v1 = px / ptau, v2 = py / ptau, vl = t * pe / ptau;
+        if (ptau_ode) {
+            if (n == n_form) ptau_ode[p] = ptau;
+            const double pt = ptau_ode[p];
+            ptau_ode[p] = pt + dt * (-t * pe * pe + ee * t * pe + e1 * px + e2 * py) / pt;
+        }
         if (color_mode == 1) {
             /* Q_{n+1} = Q_n + dt i[Q_n, M_n], from the state at n */
             const int lx = ((int)floor(r[P_X])) % N, ly = ((int)floor(r[P_Y])) % N;

@@ -53,7 +53,7 @@ def step_particles(N, n, n_form, dt, mhat, st, P, mode):
     pi = np.ascontiguousarray(st["pi"])
     return oracle.lib().orc_particles_step(N, n, n_form, dt, mhat, 0, mode, oracle._ptr(st["U"]),
                                            oracle._ptr(st["phi"]), oracle._ptr(E), oracle._ptr(E),
-                                           oracle._ptr(pi), oracle._ptr(pi), P.shape[0], oracle._ptr(P))
+                                           oracle._ptr(pi), oracle._ptr(pi), P.shape[0], oracle._ptr(P), None)
 
 
 def one_particle(N, x, y, px, py, q):

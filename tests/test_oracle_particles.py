@@ -85,7 +85,7 @@ def test_colour_rotation_known_links():
         P[0, 17] = 1.0
         err = oracle.lib().orc_particles_step(N, 4, 1, dt, 1e9, 0, 0, oracle._ptr(st["U"]), oracle._ptr(z1),
                                               oracle._ptr(z2), oracle._ptr(z2), oracle._ptr(z1), oracle._ptr(z1),
-                                              1, oracle._ptr(P))
+                                              1, oracle._ptr(P), None)
         assert err == 0
         return P[0, 6:14]
 
@@ -104,7 +104,7 @@ def test_colour_rotation_known_links():
     P = np.zeros((1, 20)); P[0, 0] = 4.0; P[0, 14] = 2; P[0, 17] = 1
     assert oracle.lib().orc_particles_step(N, 4, 1, dt, 1.0, 0, 0, oracle._ptr(st["U"]), oracle._ptr(z1),
                                            oracle._ptr(z2), oracle._ptr(z2), oracle._ptr(z1), oracle._ptr(z1),
-                                           1, oracle._ptr(P)) == 1
+                                           1, oracle._ptr(P), None) == 1
 
 
 def test_casimirs_conserved_by_rotation_many_steps():
@@ -137,7 +137,7 @@ def test_magnetic_force_does_no_work():
         before = P.copy()
         oracle.lib().orc_particles_step(N, n + step, n, dt, 0.3, 0, 0, oracle._ptr(st["U"]), oracle._ptr(z1),
                                         oracle._ptr(z2), oracle._ptr(z2), oracle._ptr(z1), oracle._ptr(z1),
-                                        P.shape[0], oracle._ptr(P))
+                                        P.shape[0], oracle._ptr(P), None)
         b = before[:, 8] * 2 * math.sin(theta / 2)           # Q^3 is unchanged by diagonal links
         ptau = np.sqrt(before[:, 3] ** 2 + before[:, 4] ** 2 + 0.3 ** 2)
         v2 = (before[:, 3] ** 2 + before[:, 4] ** 2) / ptau ** 2

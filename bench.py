@@ -5,12 +5,16 @@ lattice, L = 6 fm, g^2 mu = 2 GeV, m = 0.2 GeV, Lambda = 10 GeV, 50 colour
 sheets, dtau = a/8 (1024 steps to 1.5 fm/c), with 1e5 charm quarks
 (m = 1.27 GeV, p_T = 0, formed at 0.1 fm/c), double precision.  A step is one
 leapfrog update of the fields plus the push of every formed particle plus
-the broadening sums.  The initial condition is built on the GPU before the
-timed region; W warm-up steps (past the formation step) are not timed; a
-kernel-timing stretch (eager launches with HIP events attached to every
-kernel) gives the per-kernel times of the roofline entries; then K steps of
-the production path (the library's 16-step HIP graphs) are timed with
-synchronisation on both sides.
+the broadening sums.  Untimed, in this order: the initial condition (built on
+the GPU); max(W, n_form + 1) warm-up steps, so that every later step pushes
+the particles; the launch tuner; a kernel-timing stretch (eager launches with
+HIP events attached to every kernel: the per-kernel times of the roofline
+entries); the capture of the step graphs and an alignment of the start to
+four steps before a particle reordering (every 16 steps), so that K = 20
+steps hold one reordering and K = 16 m + 4 hold m + 1.  Timed: K steps of the
+production path (cpic_evolve: the library's 16-step HIP graphs) and the
+readout of the broadening samples (their fixed-order reduction and copy to
+the host), with synchronisation on both sides.
 
 Extra keys report the same event in single precision (reunitarisation every
 16 steps), the jets workload (the same event in single precision with 1e6
@@ -34,22 +38,24 @@ HBM_PEAK_GBS = 8000.0
 HBARC_GEV_FM = 0.1973269804
 # Algorithmic bytes per unit of work (per site-update of the field kernel, per
 # particle push): the field update reads and writes the 68 reals of a site
-# (U_x, U_y, phi, E_x, E_y, pi) and, with particles, writes the 48 reals of
-# per-site field pieces the push reads (a force table); the push moves its
-# record (about 17 words each way), the six force fields at one site (48
-# reals), phi at the cell (8) and a link on one step in eight.  The library
-# keeps only the first two rows of each link (12 of its 18 reals), so its
-# field update moves 56 + 56 reals of state per site: that figure is reported
-# beside the full-link one.
+# (U_x, U_y, phi, E_x, E_y, pi); the push moves its record (about 17 words
+# each way), the six force fields at one site (48 reals), phi at the cell (8)
+# and a link on one step in eight.  The library keeps only the first two rows
+# of each link (12 of its 18 reals), so its field update moves 56 + 56 reals
+# of state per site: that figure is reported beside the full-link one.
 SITE_BYTES = {"f64": 68 * 2 * 8, "f32": 68 * 2 * 4}
 SITE_BYTES_TWO_ROW = {"f64": 56 * 2 * 8, "f32": 56 * 2 * 4}
-AUX_BYTES = {"f64": 48 * 8, "f32": 48 * 4}
 PUSH_BYTES = {"f64": 730, "f32": 370}
 # light-like paths, per path and step: the Wilson line (18 reals) read, the
-# three integrated forces (24 reals) read and written, and the fields at the
-# path's cell read once per site: x and y links (36), the half-step sums of
-# E_x, E_y and pi, D_x and G of the aux buffer (40)
-JET_BYTES = {"f64": 142 * 8, "f32": 142 * 4}
+# three integrated forces (24 reals) read and written, the x link crossed
+# (once per 1/dt steps, counted every step: 12 reals of its two rows) and
+# the five force-table vectors at the path's cell (40 reals)
+JET_BYTES = {"f64": 118 * 8, "f32": 118 * 4}
+# force table, per site: the two links (24 reals of their rows), phi (8), E
+# and pi at both half steps (48) read; the six field vectors (48) written
+TABLE_BYTES = {"f64": 128 * 8, "f32": 128 * 4}
+SORT_EVERY = 16          # steps between reorderings of moving particles (the library's constant)
+DTAU_FM = 0.125 * 6.0 / 512
 # SU(2) variant: a site holds 20 reals (two quaternion links, phi, E_x, E_y,
 # pi), read and written once; a push moves its record (13 words each way: the
 # SU(2) columns), the six force fields at one site (18 reals), phi at the cell
@@ -77,33 +83,56 @@ def jet_quarks(n=1_000_000, seed=4):
                 seed=seed)
 
 
-def run_event(precision, steps, warmup, tune=True, particles=None, jets=False, n_colors=3, fixed=None):
-    """One 512^2 event: IC (timed separately), warm-up steps past formation, the
-    launch tuner, a kernel-timing stretch (eager launches with HIP events
-    attached to each kernel: the per-kernel times of the roofline entries),
-    then the timed region: `steps` steps of the production path, the 16-step
-    HIP graphs of cpic_evolve.  The timed region comes last, so a profiler's
-    last `steps` dispatches of each kernel are exactly the timed ones."""
+def formation_step(particles):
+    """n_form = ceil(tau_form / dtau) at 512^2, as the library rounds it."""
+    f = particles["tau_form_fm"] / DTAU_FM
+    return math.ceil(f - 1e-9 * f)
+
+
+def plan_steps(steps, warmup, n_form, n_max=1024):
+    """Untimed steps before the timed region: the warm-up (at least up to the
+    first push step), the kernel-timing stretch (up to 128 steps) and the
+    graph and alignment steps (32 + up to 15; see run_event)."""
+    w = max(warmup, n_form + 1)
+    spare = n_max - w - steps - 48
+    if spare < 16:
+        sys.exit(f"--steps {steps} with a warm-up of {w} steps (past formation at step {n_form}) leaves no room for "
+                 f"the kernel-timing stretch within the {n_max} steps to tau = 1.5 fm/c")
+    return w, min(128, spare)
+
+
+def run_event(precision, steps, warmup, tune=True, particles=None, jets=False, n_colors=3, fixed=None, nt=None):
+    """One 512^2 event: IC (timed separately), warm-up steps at least to the
+    first push step, the launch tuner, a kernel-timing stretch (eager launches
+    with HIP events attached to each kernel: the per-kernel times of the
+    roofline entries), graph capture and alignment, then the timed region:
+    `steps` steps of the production path (the 16-step HIP graphs of
+    cpic_evolve) and the readout of the samples.  The timed region comes
+    last, so a profiler's last `steps` dispatches of each kernel are exactly
+    the timed ones."""
     import torch
     import paper_2303_05599_amd as cp
-    ctx = cp.Context(glasma_512(precision, n_colors=n_colors), particles or charm())
+    p = particles or charm()
+    ctx = cp.Context(glasma_512(precision, n_colors=n_colors), p)
     if jets:
         ctx.enable_jets(x_offset=0.3)
     t0 = time.perf_counter()
     ctx.init_mv()
     t_ic = time.perf_counter() - t0
-    ctx.step(warmup)
+    w, n_kt = plan_steps(steps, warmup, formation_step(p))
+    ctx.step(w)
     ctx.sync()
     if fixed:
         ctx.set_launch(fixed[0], fixed[1], 1, 1, 3)
         tune_report = f"fixed compressed-tile launch {fixed[0]}x{fixed[1]}\n"
     else:
         tune_report = ctx.tune(5) if tune else "not tuned (library defaults)\n"
+    if nt is not None:
+        ctx.set_store_policy(nt)
     launch = ctx.get_launch()
-    launch["logq"] = (particles or {}).get("color_update", 0) == cp.COLOR_LOG
+    launch["logq"] = p.get("color_update", 0) == cp.COLOR_LOG
     launch["push_mode"] = "table" if ctx.push_mode() == cp.PUSH_TABLE else "gather"
     # kernel timing (eager launches); not the headline rate
-    n_kt = max(16, min(128, 1024 - warmup - steps))
     ctx.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -114,19 +143,27 @@ def run_event(precision, steps, warmup, tune=True, particles=None, jets=False, n
     if jets:
         tm.update(ctx.jets_timing())
     ctx.set_timing(False)
-    # timed region: graph replay
+    # graph capture: a graph of 16 steps starts at every reordering point
+    # (multiples of 16); evolve to the second such point so that the graph of
+    # that buffer parity is built, then step to four steps before the next one
+    n = ctx.n
+    ctx.evolve(((n // SORT_EVERY + 2) * SORT_EVERY) * DTAU_FM * (1 - 1e-12))
+    ctx.step((SORT_EVERY - 4 - ctx.n % SORT_EVERY) % SORT_EVERY)
+    ctx.sync()
+    untimed = ctx.n
+    # timed region: the production path and the readout of the samples
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ctx.evolve((ctx.n + steps) * 0.125 * 6.0 / 512 * (1 - 1e-12))
-    ctx.sync()
+    ctx.evolve((ctx.n + steps) * DTAU_FM * (1 - 1e-12))
+    obs = ctx.observables()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     d = ctx.diagnostics()
-    obs = ctx.observables()
     jobs = ctx.jet_observables() if jets else None
     ctx.close()
     return dict(wall=wall, t_ic=t_ic, timing=tm, diag=d, obs=obs, jet_obs=jobs, eager_ms_per_step=eager_ms,
-                kernel_timing_steps=n_kt, launch=launch, tune_report=tune_report)
+                kernel_timing_steps=n_kt, launch=launch, tune_report=tune_report, untimed_steps=untimed,
+                warmup_steps=w)
 
 
 def batch_events(precision, n_events=64, seed=5):
@@ -276,26 +313,68 @@ def run_su2(steps, warmup, V):
     return out
 
 
-def cpu_baseline(n_steps=40, n_part=100_000):
-    """The oracle on the host cores: 512^2 MV event (one colour sheet; the
-    initial condition is not timed), n_steps leapfrog steps with the push of
-    n_part charm quarks active from the first step."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads():
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit():
+        return int(env)
+    return len(os.sched_getaffinity(0))
+
+
+def oracle_rates(N, st, P, mhat, steps, threads):
+    """Site-updates/s and pushes/s of the oracle over `steps` steps (the first,
+    n = 0, untimed) on `threads` OpenMP threads, field step and push timed apart."""
     import oracle
+    oracle.set_threads(threads)
+    run = oracle.Run(N, 0.125, st, P, mhat=mhat, n_form=0)
+    run.step()
+    run.t_field = run.t_push = 0.0
+    for _ in range(steps):
+        run.step()
+    wall = run.t_field + run.t_push
+    return {"threads": threads, "steps": steps, "seconds": wall,
+            "site_updates_per_s": N * N * steps / wall, "pushes_per_s": P.shape[0] * steps / wall,
+            "field_s_per_step": run.t_field / steps, "push_s_per_step": run.t_push / steps,
+            "field_GBps_at_1088B": N * N * 1088 / (run.t_field / steps) / 1e9,
+            "push_GBps_at_730B": P.shape[0] * 730 / (run.t_push / steps) / 1e9}
+
+
+def cpu_baseline(n_steps=40, n_steps_single=2, n_part=100_000):
+    """The oracle on the host cores.  The headline value is the 512^2 event
+    with 1e5 charm quarks (config 2; one colour sheet for the untimed initial
+    condition, the push active from the first step) over n_steps steps on all
+    cores.  The table adds one thread against all cores for config 2 (a
+    shorter sample) and for the whole config 1 run (32^2, 43 steps, 1024
+    static quarks), each with the field step and the push timed apart."""
+    import oracle
+    cores = host_threads()
     N, L = 512, 6.0
     a = oracle.lattice_spacing(L, N)
     st = oracle.mv_initial_condition(N, L, 2.0, 0.2, 10.0, 1, 3)
     P = oracle.particles_init(N, n_part, 4, 0.0, 0.0, True, 0)
-    run = oracle.Run(N, 0.125, st, P, mhat=1.27 * a, n_form=0)
-    run.step()      # n = 0 (no kick), untimed
-    t0 = time.perf_counter()
-    for _ in range(n_steps):
-        run.step()
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dict(value=N * N * n_steps / dt, unit="site-updates/s", cores=cores, kind="oracle",
-                pushes_per_s=n_part * n_steps / dt,
+    all2 = oracle_rates(N, st, P, 1.27 * a, n_steps, cores)
+    one2 = oracle_rates(N, st, P, 1.27 * a, n_steps_single, 1)
+    st1 = oracle.mv_initial_condition(32, 6.0, 2.0, 0.2, 10.0, 1, 1)
+    P1 = oracle.particles_init(32, 1024, 2, 0.0, 0.0, True, 0)
+    all1 = oracle_rates(32, st1, P1, math.inf, 42, cores)
+    one1 = oracle_rates(32, st1, P1, math.inf, 42, 1)
+    oracle.set_threads(cores)
+    return dict(value=all2["site_updates_per_s"], unit="site-updates/s", cores=cores, kind="oracle",
+                pushes_per_s=all2["pushes_per_s"], cpu_model=cpu_model(),
                 sample=f"512^2 MV event (1 sheet, IC untimed), {n_steps} steps incl. push of {n_part} charm quarks, "
-                       f"{dt:.1f} s wall on {cores} threads")
+                       f"{all2['seconds']:.1f} s on {cores} threads",
+                table={"config2_512_fp64_1e5_charm": {"all_cores": all2, "one_thread": one2},
+                       "config1_32_fp64_1024_static": {"all_cores": all1, "one_thread": one1}})
 
 
 def kernel_source_hash():
@@ -337,13 +416,13 @@ def kernel_names(launch, precision):
     v = launch["variant"]
     if v == 3:
         cp = 2 if launch.get("nt_store") else 0
-        field = f"field_ctile_kernel<{t}, true, {launch['bx']}, {launch['by']}, {cp}>"
+        field = f"field_ctile_kernel<{t}, {launch['bx']}, {launch['by']}, {cp}>"
     elif v == 2:
-        field = f"field_tile_kernel<{t}, true, {launch['bx']}, {launch['by']}>"
+        field = f"field_tile_kernel<{t}, {launch['bx']}, {launch['by']}>"
     elif v == 1:
-        field = "field_link_kernel" + ("" if launch["waves"] == 1 else f"_w{launch['waves']}") + f"<{t}, true>"
+        field = "field_link_kernel" + ("" if launch["waves"] == 1 else f"_w{launch['waves']}") + f"<{t}>"
     else:
-        field = "field_step_kernel" + ("" if launch["waves"] == 1 else f"_w{launch['waves']}") + f"<{t}, true>"
+        field = "field_step_kernel" + ("" if launch["waves"] == 1 else f"_w{launch['waves']}") + f"<{t}>"
     if launch.get("push_mode") == "table":
         push = f"force_table_kernel<{t}> + push_table_kernel<{t}>"
     else:
@@ -361,7 +440,7 @@ def rooflines(res, precision, n_part, V, pmc_workload=None):
     push_s = tm["push_ms"] / max(tm["n_push"], 1) * 1e-3
     fname, pname, jname = kernel_names(res["launch"], precision)
     out = {}
-    entries = [("field", fname, field_s, SITE_BYTES[dt] + AUX_BYTES[dt], V, "site-update"),
+    entries = [("field", fname, field_s, SITE_BYTES[dt], V, "site-update"),
                ("push", pname, push_s, PUSH_BYTES[dt], n_part, "particle-push")]
     if tm.get("n_jets"):
         entries.append(("jets", jname, tm["jets_ms"] / tm["n_jets"] * 1e-3, JET_BYTES[dt], V, "path-step"))
@@ -374,7 +453,7 @@ def rooflines(res, precision, n_part, V, pmc_workload=None):
                     "bytes_per_unit": unit_bytes, "units_per_launch": units, "work_unit": unit}
     if "ctile" in fname:
         # the same launch priced with the two-row link storage it works on
-        two = (SITE_BYTES_TWO_ROW[dt] + AUX_BYTES[dt]) * V
+        two = SITE_BYTES_TWO_ROW[dt] * V
         out["field"].update(bytes_per_unit_two_row_links=two // V, frac_two_row_links=two / field_s / 1e9 / HBM_PEAK_GBS)
     pmc = read_pmc_summary(PMC_SUMMARIES[pmc_workload or "512_" + precision])
     for e in out.values():
@@ -496,6 +575,8 @@ def main():
     ap.add_argument("--title", default="", help="workload named in a counter summary")
     ap.add_argument("--launch", nargs=2, type=int, metavar=("BX", "BY"), default=None,
                     help="fix the compressed-tile field launch instead of tuning (counter runs of a tuned shape)")
+    ap.add_argument("--nt", type=int, choices=[0, 1], default=None,
+                    help="fix the store policy of the field update's new state (1: non-temporal) after tuning")
     ap.add_argument("--jets-only", action="store_true",
                     help="run only the jets workload and print its JSON (for profiling; not the benchmark line)")
     ap.add_argument("--no-tune", action="store_true",
@@ -522,8 +603,6 @@ def main():
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (events shard across GPUs "
               f"without communication, see the design notes)", file=sys.stderr)
         sys.exit(2)
-    if args.warmup + args.steps + 16 > 1024:
-        sys.exit("warmup + steps + 16 kernel-timing steps must not exceed the 1024 steps to tau = 1.5 fm/c")
     import torch
     import paper_2303_05599_amd as cp
     torch.cuda.set_device(0)
@@ -533,7 +612,7 @@ def main():
         print(json.dumps(run_jets(args.steps, args.warmup, V, not args.no_tune, args.launch)))
         return
     res = run_event(cp.FP64 if args.precision == "fp64" else cp.FP32, args.steps, args.warmup, not args.no_tune,
-                    fixed=args.launch)
+                    fixed=args.launch, nt=args.nt)
     ms_per_step = res["wall"] * 1e3 / args.steps
     site_rate = V * args.steps / res["wall"]
     push_rate = n_part * args.steps / res["wall"]
@@ -560,6 +639,9 @@ def main():
         "roofline": dict(kern[dominant], dominant=dominant),
         "kernels": kern,
         "eager_ms_per_step": res["eager_ms_per_step"], "kernel_timing_steps": res["kernel_timing_steps"],
+        "warmup_steps_run": res["warmup_steps"], "first_timed_step": res["untimed_steps"],
+        "timed_region": "K steps of cpic_evolve (16-step HIP graphs, particle reordering every 16 steps) and the "
+                        "readout of the broadening samples (fixed-order reduction and copy to the host)",
         "launch": res["launch"],
         "ic_seconds": res["t_ic"],
         "gauss_max": res["diag"][1], "unitarity_max": res["diag"][6],

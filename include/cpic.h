@@ -96,8 +96,8 @@ typedef struct {
  * Test-particle species (toy-model initial conditions of Sec. III.B, colour
  * charges from the Haar measure of Sec. IV.B).
  *   n                number of test particles (0: fields only); at most
- *                    14,913,080 in FP64 and 29,826,161 in FP32 (the records,
- *                    18 reals each, stay below 2 GiB), else CPIC_E_INVALID
+ *                    14,128,181 in FP64 and 28,256,363 in FP32 (the records,
+ *                    19 reals each, stay below 2 GiB), else CPIC_E_INVALID
  *   mass_GeV         mass; INFINITY selects the static (infinite-mass) branch
  *                    of Sec. V.A: no motion, no colour rotation
  *   pT_min/max_GeV   initial |p_T| uniform in [min, max) (equal: fixed)
@@ -245,6 +245,13 @@ cpic_status cpic_field_diagnostics_noalloc(int32_t precision, int32_t N, double 
  *                        starting in site (y, x) (get only; cpic_jets_enable)
  *   CPIC_STATE_JET_F     float64 [N][N][3][8]        its integrated transported force
  *                        components F_x, F_y, F_z (get only)
+ *   CPIC_STATE_PTAU      float64 [n][2]              the temporal-constraint check of
+ *                        Appendix D (get only; SU(3), moving particles): p^tau at
+ *                        step n from the constraint [eq:ptau], and p^tau integrated by
+ *                        the push from its own equation of motion [eq:ptaueq] (Euler
+ *                        with the rest of the particle, from the constraint at the
+ *                        formation step, or at the step of the last set of
+ *                        CPIC_STATE_PARTICLES; 0 before formation)
  * bytes must equal the exact size (CPIC_E_CAPACITY otherwise).  Synchronises.
  * The device keeps only the first two rows of each SU(3) link: a get returns
  * the third row as the conjugate cross product of the first two, and a set
@@ -259,6 +266,7 @@ cpic_status cpic_field_diagnostics_noalloc(int32_t precision, int32_t N, double 
 #define CPIC_STATE_STEP 5
 #define CPIC_STATE_JET_W 6
 #define CPIC_STATE_JET_F 7
+#define CPIC_STATE_PTAU 8
 cpic_status cpic_get_state(cpic_ctx* ctx, int32_t which, void* host_dst, size_t bytes);
 cpic_status cpic_set_state(cpic_ctx* ctx, int32_t which, const void* host_src, size_t bytes);
 
@@ -292,10 +300,10 @@ cpic_status cpic_set_launch(cpic_ctx* ctx, int32_t bx, int32_t by, int32_t xcd_r
  * all three. */
 cpic_status cpic_set_push_lanes(cpic_ctx* ctx, int32_t lanes);
 
-/* Where the push takes the colour fields at a particle's cell:
- *   CPIC_PUSH_GATHER  evaluated per particle from the per-site pieces the
- *                     field update writes (default for fewer particles
- *                     than sites);
+/* Where the push takes the colour fields at a particle's cell (the
+ * interpolations of Sec. III.B from U(n), phi(n), E(n -+ 1/2), pi(n -+ 1/2)):
+ *   CPIC_PUSH_GATHER  evaluated per particle from the two field buffer sets
+ *                     of the step (default for fewer particles than sites);
  *   CPIC_PUSH_TABLE   evaluated once per site into a force table (48 reals
  *                     per site, one more kernel per step) that the push reads
  *                     at the cell (default for more particles than sites).
@@ -315,6 +323,12 @@ cpic_status cpic_get_push_mode(const cpic_ctx* ctx, int32_t* mode);
  * cpic_tune may change it.  Results are the same
  * either way. */
 cpic_status cpic_get_launch(const cpic_ctx* ctx, int32_t out[7]);
+
+/* Store policy of the new state in the compressed-tile field update:
+ * 1 stores the new links, phi, E and pi non-temporal, 0 with the default
+ * cache policy (the choice cpic_get_launch reports in out[6]).  Results are
+ * the same either way; takes effect for the next launch. */
+cpic_status cpic_set_store_policy(cpic_ctx* ctx, int32_t non_temporal);
 
 /* Launch tuner: times every candidate field-kernel configuration (block shape x
  * occupancy target x XCD mapping) in place on the current state without
@@ -362,11 +376,15 @@ cpic_status cpic_timing(cpic_ctx* ctx, double* field_ms, double* push_ms, int64_
  *   tau_form_fm formation time of the paths (jets form at 0)
  *   rep         CPIC_REP_FUND or CPIC_REP_ADJ: the charges <dp^2> is quoted for
  *
- * cpic_jets_enable allocates the paths' state (42 reals per site) and, if the
- * context has no particles, the per-site field pieces the paths read (48
- * reals per site).  Call it once, before the paths' formation step is
- * reached; CPIC_E_INVALID otherwise, or if dtau > a.  Every later step then
- * launches one more kernel.  Checkpoints include the paths.
+ * The paths read the fields at their cells from the per-site force table of
+ * the step (CPIC_PUSH_TABLE), which is then evaluated every step from the
+ * paths' formation on, whatever the push mode.  cpic_jets_enable allocates
+ * the paths' state (42 reals per site) and, if the context has none yet, the
+ * force table (48 reals per site).  Call it once, before the paths'
+ * formation step is reached; CPIC_E_INVALID otherwise, or if dtau > a.
+ * Every later step then launches the table kernel (unless the push already
+ * does) and the path kernel; kernel timing counts the table as path time
+ * when the push does not read it.  Checkpoints include the paths.
  */
 typedef struct {
     double x_offset;
@@ -424,8 +442,7 @@ cpic_status cpic_batch_tune(cpic_batch* b, int32_t reps, char* report, size_t ca
  * (1, 2, 4) */
 cpic_status cpic_batch_set_launch(cpic_batch* b, int32_t bx, int32_t by, int32_t xcd_remap, int32_t tpp);
 /* Launch groups: events are taken by decreasing working set (both field
- * buffer sets, the magnetic-field pieces for the push and the particle
- * records) and packed into groups of at most `bytes` (a larger event forms a
+ * buffer sets and the particle records) and packed into groups of at most `bytes` (a larger event forms a
  * group of its own).  A group runs all its steps before the next group
  * starts, so its fields stay in the last-level cache from one step to the
  * next.  0 = all events in one group, stepped together.  Default 256 MiB. */

@@ -17,6 +17,7 @@ import ctypes
 import math
 import os
 import subprocess
+import time
 
 import numpy as np
 
@@ -83,12 +84,21 @@ def load_library(path):
         "orc_generator": (None, [i, p]),
         "orc_proj": (None, [p, p]),
         "orc_expi": (None, [p, d, p]),
+        "orc_set_threads": (None, [i]),
+        "orc_max_threads": (i, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
         f.restype = res
         f.argtypes = args
     return L
+
+
+def set_threads(n: int) -> int:
+    """Run the oracle's parallel loops on n OpenMP threads; returns the previous count."""
+    prev = lib().orc_max_threads()
+    lib().orc_set_threads(int(n))
+    return prev
 
 
 def _ptr(a: np.ndarray):
@@ -349,8 +359,10 @@ class Run:
         self.errors = 0
         self.jets = jets
         self.color_mode = {"cpic": 0, "log": 1}[color]
-        # p^tau from its equation of motion [eq:ptaueq] beside the constraint (moving particles)
-        self.ptau_ode = None if self.P is None or self.is_static else np.zeros(self.P.shape[0])
+        self.t_field = self.t_push = 0.0   # wall seconds spent in the field step and in the push
+        # p^tau from its equation of motion [eq:ptaueq] beside the constraint (moving
+        # particles); a run started past formation starts it from the constraint
+        self.ptau_ode = None if self.P is None or self.is_static else self.ptau_constraint()
 
     def step(self):
         N, n, st = self.N, self.n, self.st
@@ -359,12 +371,16 @@ class Run:
         if push or jets:
             U_n, phi_n = st["U"].copy(), st["phi"].copy()
             E_old, pi_old = st["E"].copy(), st["pi"].copy()
+        t0 = time.perf_counter()
         field_step(N, n, self.dt, st)
+        t1 = time.perf_counter()
+        self.t_field += t1 - t0
         if push:
             self.errors += lib().orc_particles_step(
                 N, n, self.n_form, self.dt, self.mhat, int(self.is_static), self.color_mode, _ptr(U_n), _ptr(phi_n),
                 _ptr(E_old), _ptr(st["E"]), _ptr(pi_old), _ptr(st["pi"]), self.P.shape[0], _ptr(self.P),
                 None if self.ptau_ode is None else _ptr(self.ptau_ode))
+            self.t_push += time.perf_counter() - t1
         if jets:
             self.jets.step(n, U_n, phi_n, E_old, st["E"], pi_old, st["pi"])
         self.n += 1

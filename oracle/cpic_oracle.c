@@ -1049,6 +1049,11 @@ void orc_jet_step(int N, int n, int n_form, double dt, double x_off, int stride,
     }
 }
 
+/* number of OpenMP threads of the oracle's parallel loops (CPU baseline timing) */
+#include <omp.h>
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_max_threads(void) { return omp_get_max_threads(); }
+
 /* ------------------- exports used only by the oracle's own pins ------------------- */
 /* T^a as 3x3 complex, row-major (a = 0..7) */
 void orc_generator(int a, cplx *out)

@@ -21,7 +21,7 @@ FP64, FP32 = 0, 1
 REP_FUND, REP_ADJ = 0, 1
 COLOR_ROTATE, COLOR_LOG = 0, 1
 PUSH_GATHER, PUSH_TABLE = 0, 1
-STATE_U, STATE_PHI, STATE_E, STATE_PI, STATE_PARTICLES, STATE_STEP, STATE_JET_W, STATE_JET_F = range(8)
+STATE_U, STATE_PHI, STATE_E, STATE_PI, STATE_PARTICLES, STATE_STEP, STATE_JET_W, STATE_JET_F, STATE_PTAU = range(9)
 ERRORS = {-1: "INVALID", -2: "NOMEM", -3: "HIP", -4: "IC_NEWTON", -5: "NAN", -6: "DRIFT", -7: "CAPACITY",
           -8: "CELL_JUMP", -9: "IO"}
 
@@ -79,6 +79,7 @@ def lib():
             "cpic_diagnostics": [P, P], "cpic_get_state": [P, i32, P, sz], "cpic_set_state": [P, i32, P, sz],
             "cpic_save": [P, cp], "cpic_load": [P, cp], "cpic_set_launch": [P, i32, i32, i32, i32, i32],
             "cpic_set_timing": [P, i32], "cpic_set_push_lanes": [P, i32], "cpic_get_launch": [P, P],
+            "cpic_set_store_policy": [P, i32],
             "cpic_tune": [P, i32, P, sz],
             "cpic_timing": [P, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(i64), ctypes.POINTER(i64)],
             "cpic_batch_create": [i32, ctypes.POINTER(GlasmaParams), ctypes.POINTER(ParticleParams), P, pp],
@@ -220,7 +221,7 @@ class Context:
                     STATE_PARTICLES: (self.np, 20), STATE_STEP: (1,)}[which]
         return {STATE_U: (2, N, N, 3, 3), STATE_PHI: (N, N, 8), STATE_E: (2, N, N, 8), STATE_PI: (N, N, 8),
                 STATE_PARTICLES: (self.np, 20), STATE_STEP: (1,), STATE_JET_W: (N, N, 3, 3),
-                STATE_JET_F: (N, N, 3, 8)}[which]
+                STATE_JET_F: (N, N, 3, 8), STATE_PTAU: (self.np, 2)}[which]
 
     def get_state(self, which):
         dt = (np.complex128 if which in (STATE_U, STATE_JET_W) else
@@ -258,6 +259,10 @@ class Context:
     def set_launch(self, bx, by, xcd_remap=1, waves=1, variant=0):
         """Field-kernel launch; variant 0 site-parallel, 1 link-parallel, 2 LDS halo tiles."""
         self._chk(lib().cpic_set_launch(self.h, bx, by, xcd_remap, waves, variant))
+
+    def set_store_policy(self, non_temporal):
+        """New state of the compressed-tile field update stored non-temporal (1) or not (0)."""
+        self._chk(lib().cpic_set_store_policy(self.h, int(non_temporal)))
 
     def set_push_lanes(self, lanes):
         self._chk(lib().cpic_set_push_lanes(self.h, lanes))

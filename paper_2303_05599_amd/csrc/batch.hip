@@ -28,8 +28,8 @@ using namespace cpic;
 namespace {
 
 constexpr int kBatchGraphSteps = 16;
-// Events are run in groups whose working set (both field buffer sets, the
-// magnetic-field pieces and the particle records) stays within about this
+// Events are run in groups whose working set (both field buffer sets and the
+// particle records) stays within about this
 // much, so that from one step to the next (and from a group's field update
 // to its push) the data is served from the 256 MB last-level cache.
 constexpr size_t kDefaultGroupBytes = (size_t)256 << 20;
@@ -104,7 +104,7 @@ static cpic_status upload_desc(cpic_batch* b)
         d.f[1] = c->fbuf[1];
         d.flip = c->cur ^ (c->n & 1);
         d.pr = c->pr;
-        d.aux = c->aux;
+        d.gpl = c->gpl;
         d.cell = c->pcell;
         d.N = c->N;
         d.pa = push_args(c, b->tpp);
@@ -126,7 +126,7 @@ static int field_tiles_host(int N, const LaunchCfg& cfg)
 
 static size_t working_set(const cpic_ctx* c)
 {
-    return (2 * (size_t)kRealsPerSite + (c->aux ? kAuxReals : 0)) * c->V * c->tsz +
+    return (2 * (size_t)kRealsPerSite + (c->gpl ? kPlaqReals : 0)) * c->V * c->tsz +
            (size_t)c->np * (kPartReals * c->tsz + 2 * sizeof(int));
 }
 
@@ -348,8 +348,8 @@ extern "C" cpic_status cpic_batch_sync(cpic_batch* b)
 }
 
 // Field-tile tuner: the batched field launch only reads the current buffers
-// and writes the other ones (and the magnetic-field pieces), which the next
-// step overwrites anyway, so it can be repeated without changing the state.
+// and writes the other ones, which the next step overwrites anyway, so it can
+// be repeated without changing the state.
 // A candidate's time is the sum over the launch groups of one step.
 template <typename T> static cpic_status tune_batch(cpic_batch* b, int reps, std::string& rep)
 {

@@ -97,7 +97,7 @@ static void free_all(cpic_ctx* c)
     for (auto e : c->ev_table) (void)hipEventDestroy(e);
     (void)hipFree(c->ftab);
     (void)hipFree(c->jW); (void)hipFree(c->jF); (void)hipFree(c->jpartials); (void)hipFree(c->jobs);
-    (void)hipFree(c->fbuf[0]); (void)hipFree(c->fbuf[1]); (void)hipFree(c->pr); (void)hipFree(c->pcell); (void)hipFree(c->aux);
+    (void)hipFree(c->fbuf[0]); (void)hipFree(c->fbuf[1]); (void)hipFree(c->pr); (void)hipFree(c->pcell); (void)hipFree(c->gpl);
     (void)hipFree(c->partials); (void)hipFree(c->obs); (void)hipFree(c->d_step); (void)hipFree(c->d_err); (void)hipFree(c->d_fails);
     (void)hipFree(c->dpart); (void)hipFree(c->dout);
     (void)hipFree(c->pid); (void)hipFree(c->sb.keys); (void)hipFree(c->sb.keys2); (void)hipFree(c->sb.vals); (void)hipFree(c->sb.perm);
@@ -106,18 +106,17 @@ static void free_all(cpic_ctx* c)
 }
 
 // Store policy of the field update.  After the field update a step reads the
-// old state, the aux pieces, the force table, the particle records and the
-// light-like paths; where these and the new state together exceed the 256 MB
-// last-level cache (FP64 at 512^2: 400 MB with 1e5 particles; the FP32 jets
-// workload: 360 MB), the new state (links, phi, E, pi) is stored
-// non-temporal so that it does not displace what the rest of the step reads
-// (it reads the new E and pi only at n = 0).
+// old state and the new E and pi (push, force table), the particle records
+// and the light-like paths; where these, the new links and phi and the force
+// table together exceed the 256 MB last-level cache (FP64 at 512^2 with 1e5
+// particles: 300 MB), the new state is stored non-temporal so that it does not
+// displace the old state the push reads next.  cpic_tune times both.
 static void set_store_policy(cpic_ctx* c)
 {
-    double reals = (2.0 * c->rps + kAuxReals) * (double)c->V + (double)kPartReals * (double)c->np;
-    if (c->push_table) reals += 48.0 * (double)c->V;
+    double reals = 2.0 * c->rps * (double)c->V + (double)kPartReals * (double)c->np;
+    if (c->push_table || c->jets) reals += 48.0 * (double)c->V;
     if (c->jets) reals += 42.0 * (double)c->V;
-    c->cfg.nt_store = c->aux != nullptr && reals * (double)c->tsz > 256.0 * 1024 * 1024;
+    c->cfg.nt_store = (c->np > 0 || c->jets) && reals * (double)c->tsz > 256.0 * 1024 * 1024;
 }
 
 extern "C" cpic_status cpic_create(const cpic_glasma_params* gp, const cpic_particle_params* pp, void* hip_stream,
@@ -179,7 +178,7 @@ extern "C" cpic_status cpic_create(const cpic_glasma_params* gp, const cpic_part
     } else {
         c->sc.n_form = c->sc.n_max;
     }
-    c->sc.n_aux = c->sc.n_form;
+    c->sc.n_plaq = c->sc.n_form;
     c->sc.record_every = gp->record_every > 0 ? gp->record_every : (1 << 30);
     c->sc.reunit_every = c->prec == CPIC_FP32 ? std::max(0, gp->reunit_every) : 0;
     initial_colour(pp->rep, c->q0, c->q0eig, &c->q2ref, &c->q3ref);
@@ -201,7 +200,7 @@ extern "C" cpic_status cpic_create(const cpic_glasma_params* gp, const cpic_part
         const size_t np = c->np;
         e = hipMalloc(&c->pr, (size_t)kPartReals * np * c->tsz);
         if (e == hipSuccess) e = hipMalloc(&c->pcell, sizeof(int) * 2 * np);
-        if (e == hipSuccess && c->nc == 3) e = hipMalloc(&c->aux, (size_t)kAuxReals * c->V * c->tsz);
+        if (e == hipSuccess && c->nc == 3) e = hipMalloc(&c->gpl, (size_t)kPlaqReals * c->V * c->tsz);
         if (e == hipSuccess) e = hipMalloc(&c->pid, sizeof(int) * np);
         if (e == hipSuccess) e = hipMalloc(&c->sb.keys, sizeof(unsigned) * np);
         if (e == hipSuccess) e = hipMalloc(&c->sb.keys2, sizeof(unsigned) * np);
@@ -429,47 +428,56 @@ template <typename T> static cpic_status launch_one_su2(cpic_ctx* c, int parity,
     return CPIC_OK;
 }
 
+// The force table serves the table push and the light-like paths: it is
+// evaluated from the first step either of them needs, with the magnetic
+// fields unless only static particles read it.
+static bool uses_table(const cpic_ctx* c) { return c->ftab && ((c->np > 0 && c->push_table) || c->jets); }
+static Schedule table_schedule(const cpic_ctx* c)
+{
+    Schedule s = c->sc;
+    s.n_form = c->sc.n_max;
+    if (c->np > 0 && c->push_table) s.n_form = std::min(s.n_form, c->sc.n_form);
+    if (c->jets) s.n_form = std::min(s.n_form, c->ja.sc.n_form);
+    return s;
+}
+
 template <typename T> static cpic_status launch_one(cpic_ctx* c, int parity, bool with_events)
 {
     if (c->nc == 2) return launch_one_su2<T>(c, parity, with_events);
     const Fields<T> A = F<T>(c, parity), B = F<T>(c, parity ^ 1);
-    KTimer tf, tp, tj;
-    if (with_events) {
-        HIPCHK(c, hipEventCreate(&tf.start), "event"); HIPCHK(c, hipEventCreate(&tf.stop), "event");
-        c->ev_field.push_back(tf.start); c->ev_field.push_back(tf.stop);
-    }
-    HIPCHK(c, launch_field_step<T>(A, B, static_cast<T*>(c->aux), c->N, c->sc, c->d_step, c->cfg, c->st, tf),
+    auto timer = [&](std::vector<hipEvent_t>& evs, KTimer& tm) -> hipError_t {
+        if (!with_events) return hipSuccess;
+        hipError_t e = hipEventCreate(&tm.start);
+        if (e == hipSuccess) e = hipEventCreate(&tm.stop);
+        if (e == hipSuccess) { evs.push_back(tm.start); evs.push_back(tm.stop); }
+        return e;
+    };
+    KTimer tf, tt, tp, tj;
+    HIPCHK(c, timer(c->ev_field, tf), "event");
+    HIPCHK(c, launch_field_step<T>(A, B, static_cast<T*>(c->gpl), c->N, c->sc, c->d_step, c->cfg, c->st, tf),
            "field step");
-    if (c->np > 0 && c->push_table) {
-        KTimer tt;
-        if (with_events) {
-            HIPCHK(c, hipEventCreate(&tt.start), "event"); HIPCHK(c, hipEventCreate(&tt.stop), "event");
-            c->ev_table.push_back(tt.start); c->ev_table.push_back(tt.stop);
-            HIPCHK(c, hipEventCreate(&tp.start), "event"); HIPCHK(c, hipEventCreate(&tp.stop), "event");
-            c->ev_push.push_back(tp.start); c->ev_push.push_back(tp.stop);
-        }
-        HIPCHK(c, launch_push_table<T>(A, B, static_cast<const T*>(c->aux), static_cast<T*>(c->ftab), P<T>(c),
-                                       push_args(c, 1), c->d_step, c->partials, c->d_err, c->st, tt, tp),
-               "table push");
-    } else if (c->np > 0) {
-        const PushArgs pa = push_args(c, c->tpp);
-        if (with_events) {
-            HIPCHK(c, hipEventCreate(&tp.start), "event"); HIPCHK(c, hipEventCreate(&tp.stop), "event");
-            c->ev_push.push_back(tp.start); c->ev_push.push_back(tp.stop);
-        }
-        HIPCHK(c, launch_push<T>(A, B, static_cast<const T*>(c->aux), P<T>(c), pa, c->d_step, c->partials, c->d_err,
-                                 c->st, tp), "push");
+    if (uses_table(c)) {
+        HIPCHK(c, timer(c->ev_table, tt), "event");
+        HIPCHK(c, launch_force_table<T>(A, B, static_cast<const T*>(c->gpl), static_cast<T*>(c->ftab), c->N,
+                                        table_schedule(c), c->is_static && !c->jets, c->d_step, c->st, tt),
+               "force table");
+    }
+    if (c->np > 0) {
+        HIPCHK(c, timer(c->ev_push, tp), "event");
+        if (c->push_table)
+            HIPCHK(c, launch_push_table<T>(A, B, static_cast<const T*>(c->ftab), P<T>(c), push_args(c, 1), c->d_step,
+                                           c->partials, c->d_err, c->st, tp), "table push");
+        else
+            HIPCHK(c, launch_push<T>(A, B, static_cast<const T*>(c->gpl), P<T>(c), push_args(c, c->tpp), c->d_step,
+                                     c->partials, c->d_err, c->st, tp), "push");
     } else {
         // the push advances the step counter; without particles a one-thread kernel does
         HIPCHK(c, launch_step_advance(c->d_step, c->st), "step advance");
     }
     if (c->jets) {
         // reads the step from d_step[1], which only the next field update changes
-        if (with_events) {
-            HIPCHK(c, hipEventCreate(&tj.start), "event"); HIPCHK(c, hipEventCreate(&tj.stop), "event");
-            c->ev_jets.push_back(tj.start); c->ev_jets.push_back(tj.stop);
-        }
-        HIPCHK(c, launch_jets<T>(A, B, static_cast<const T*>(c->aux), static_cast<T*>(c->jW), static_cast<T*>(c->jF),
+        HIPCHK(c, timer(c->ev_jets, tj), "event");
+        HIPCHK(c, launch_jets<T>(A, static_cast<const T*>(c->ftab), static_cast<T*>(c->jW), static_cast<T*>(c->jF),
                                  c->ja, c->d_step, c->jpartials, c->st, tj), "light-like paths");
     }
     return CPIC_OK;
@@ -577,10 +585,11 @@ static cpic_status collect_timing(cpic_ctx* c)
         c->k_push++;
         (void)hipEventDestroy(c->ev_push[i]); (void)hipEventDestroy(c->ev_push[i + 1]);
     }
-    for (size_t i = 0; i + 1 < c->ev_table.size(); i += 2) {  // the table kernel counts as push time
+    for (size_t i = 0; i + 1 < c->ev_table.size(); i += 2) {
+        // the table kernel counts as push time (table push), else as light-like path time
         float ms = 0;
         HIPCHK(c, hipEventElapsedTime(&ms, c->ev_table[i], c->ev_table[i + 1]), "timing");
-        c->t_push += ms;
+        (c->np > 0 && c->push_table ? c->t_push : c->t_jets) += ms;
         (void)hipEventDestroy(c->ev_table[i]); (void)hipEventDestroy(c->ev_table[i + 1]);
     }
     c->ev_table.clear();
@@ -730,6 +739,7 @@ static size_t state_bytes(const cpic_ctx* c, int which)
     case CPIC_STATE_PHI: case CPIC_STATE_PI: return sizeof(double) * ncomp(c) * (size_t)c->V;
     case CPIC_STATE_E: return sizeof(double) * 2 * ncomp(c) * (size_t)c->V;
     case CPIC_STATE_PARTICLES: return sizeof(double) * 20 * (size_t)c->np;
+    case CPIC_STATE_PTAU: return c->nc == 3 && !c->is_static ? sizeof(double) * 2 * (size_t)c->np : 0;
     case CPIC_STATE_STEP: return sizeof(int64_t);
     case CPIC_STATE_JET_W: return c->jets ? sizeof(double) * 18 * (size_t)c->V : 0;
     case CPIC_STATE_JET_F: return c->jets ? sizeof(double) * 24 * (size_t)c->V : 0;
@@ -851,6 +861,23 @@ template <typename T> static cpic_status get_t(cpic_ctx* c, int which, double* h
             for (int k = 0; k < nc; k++) h[(size_t)s * nc + k] = (double)d[(size_t)k * c->V + s];
         return CPIC_OK;
     }
+    if (which == CPIC_STATE_PTAU) {
+        // p^tau from the constraint at step n beside the integrated value
+        const size_t np = c->np;
+        std::vector<T> r(kPartReals * np);
+        std::vector<int> pid(np);
+        HIPCHK(c, hipMemcpy(r.data(), c->pr, sizeof(T) * r.size(), hipMemcpyDeviceToHost), "get p^tau");
+        HIPCHK(c, hipMemcpy(pid.data(), c->pid, sizeof(int) * np, hipMemcpyDeviceToHost), "get p^tau");
+        const double t = c->n * c->sc.dt;
+        for (size_t p = 0; p < np; p++) {
+            const size_t row = (size_t)pid[p];
+            if (row >= np) return fail(c, CPIC_E_INVALID, "get_state: corrupt particle index");
+            const double px = r[PPX * np + p], py = r[PPY * np + p], pe = r[PPETA * np + p];
+            h[2 * row] = std::sqrt(px * px + py * py + (t * pe) * (t * pe) + c->mhat * c->mhat);
+            h[2 * row + 1] = (double)r[(size_t)PPTAU * np + p];
+        }
+        return CPIC_OK;
+    }
     if (which == CPIC_STATE_PARTICLES) {
         const size_t np = c->np;
         std::vector<T> r(kPartReals * np);
@@ -895,6 +922,12 @@ template <typename T> static cpic_status set_t(cpic_ctx* c, int which, const dou
                 if (d >= 0) r[(size_t)d * np + p] = (T)h[p * 20 + k];
                 else cell[(size_t)(-d - 1) * np + p] = (int)h[p * 20 + k];
             }
+        // the integrated p^tau restarts from the constraint at the current step
+        const double t = c->n * c->sc.dt;
+        for (size_t p = 0; p < np; p++) {
+            const double px = h[p * 20 + 3], py = h[p * 20 + 4], pe = h[p * 20 + 5];
+            r[(size_t)PPTAU * np + p] = (T)std::sqrt(px * px + py * py + (t * pe) * (t * pe) + c->mhat * c->mhat);
+        }
         HIPCHK(c, hipMemcpy(c->pr, r.data(), sizeof(T) * r.size(), hipMemcpyHostToDevice), "set particles");
         HIPCHK(c, hipMemcpy(c->pcell, cell.data(), sizeof(int) * cell.size(), hipMemcpyHostToDevice), "set particles");
         return reset_pid(c);
@@ -920,7 +953,8 @@ extern "C" cpic_status cpic_get_state(cpic_ctx* c, int32_t which, void* dst, siz
     if (!c || !dst) return fail(c, CPIC_E_INVALID, "cpic_get_state: NULL argument");
     const size_t need = state_bytes(c, which);
     if (!need && which != CPIC_STATE_PARTICLES)
-        return fail(c, CPIC_E_INVALID, "cpic_get_state: unknown part (or light-like paths not enabled)");
+        return fail(c, CPIC_E_INVALID,
+                    "cpic_get_state: unknown part (light-like paths not enabled, or p^tau without moving SU(3) particles)");
     if (bytes != need) return fail(c, CPIC_E_CAPACITY, "cpic_get_state: expected " + std::to_string(need) + " bytes");
     HIPCHK(c, hipStreamSynchronize(c->st), "get state");
     if (which == CPIC_STATE_STEP) {
@@ -935,8 +969,8 @@ extern "C" cpic_status cpic_get_state(cpic_ctx* c, int32_t which, void* dst, siz
 extern "C" cpic_status cpic_set_state(cpic_ctx* c, int32_t which, const void* src, size_t bytes)
 {
     if (!c || !src) return fail(c, CPIC_E_INVALID, "cpic_set_state: NULL argument");
-    if (which == CPIC_STATE_JET_W || which == CPIC_STATE_JET_F)
-        return fail(c, CPIC_E_INVALID, "cpic_set_state: the light-like paths are read-only");
+    if (which == CPIC_STATE_JET_W || which == CPIC_STATE_JET_F || which == CPIC_STATE_PTAU)
+        return fail(c, CPIC_E_INVALID, "cpic_set_state: the light-like paths and p^tau are read-only");
     const size_t need = state_bytes(c, which);
     if (!need && which != CPIC_STATE_PARTICLES) return fail(c, CPIC_E_INVALID, "cpic_set_state: unknown part");
     if (bytes != need) return fail(c, CPIC_E_CAPACITY, "cpic_set_state: expected " + std::to_string(need) + " bytes");
@@ -1166,6 +1200,16 @@ extern "C" cpic_status cpic_set_launch(cpic_ctx* c, int32_t bx, int32_t by, int3
     return CPIC_OK;
 }
 
+extern "C" cpic_status cpic_set_store_policy(cpic_ctx* c, int32_t non_temporal)
+{
+    if (!c) return fail(nullptr, CPIC_E_INVALID, "cpic_set_store_policy: NULL context");
+    if (non_temporal != 0 && non_temporal != 1)
+        return fail(c, CPIC_E_INVALID, "cpic_set_store_policy: 0 (default stores) or 1 (non-temporal)");
+    c->cfg.nt_store = non_temporal;
+    drop_graphs(c);
+    return CPIC_OK;
+}
+
 extern "C" cpic_status cpic_set_timing(cpic_ctx* c, int32_t enable)
 {
     if (!c) return fail(nullptr, CPIC_E_INVALID, "cpic_set_timing: NULL context");
@@ -1203,7 +1247,7 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
     HIPCHK(c, hipMemcpy(&err0, c->d_err, sizeof(int), hipMemcpyDeviceToHost), "tune");
     const LaunchCfg orig = c->cfg;  // the configuration before tuning (default or set by the caller)
     const Fields<T> A = F<T>(c, c->cur), B = F<T>(c, c->cur ^ 1);
-    T* const X = static_cast<T*>(c->aux);
+    T* const G = static_cast<T*>(c->gpl);
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0), "tune");
     HIPCHK(c, hipEventCreate(&e1), "tune");
@@ -1228,10 +1272,10 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
         for (int remap = 0; remap <= 1; remap++) cands.push_back(LaunchCfg{sh[0], sh[1], remap, 1, 3});
     for (LaunchCfg& cfg : cands) cfg.nt_store = c->cfg.nt_store;
     for (const LaunchCfg& cfg : cands) {
-                HIPCHK(c, launch_field_step<T>(A, B, X, c->N, c->sc, c->d_step, cfg, c->st), "tune");  // warm-up
+                HIPCHK(c, launch_field_step<T>(A, B, G, c->N, c->sc, c->d_step, cfg, c->st), "tune");  // warm-up
                 HIPCHK(c, hipEventRecord(e0, c->st), "tune");
                 for (int r = 0; r < reps; r++)
-                    HIPCHK(c, launch_field_step<T>(A, B, X, c->N, c->sc, c->d_step, cfg, c->st), "tune");
+                    HIPCHK(c, launch_field_step<T>(A, B, G, c->N, c->sc, c->d_step, cfg, c->st), "tune");
                 HIPCHK(c, hipEventRecord(e1, c->st), "tune");
                 HIPCHK(c, hipEventSynchronize(e1), "tune");
                 float ms = 0;
@@ -1253,15 +1297,15 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
         HIPCHK(c, hipMemcpyAsync(c->sb.r2, c->pr, rb, hipMemcpyDeviceToDevice, c->st), "tune");
         HIPCHK(c, hipMemcpyAsync(c->sb.cell2, c->pcell, cb, hipMemcpyDeviceToDevice, c->st), "tune");
         // the step's new momenta: run the field kernel once into the free buffer
-        HIPCHK(c, launch_field_step<T>(A, B, X, c->N, c->sc, c->d_step, c->cfg, c->st), "tune");
+        HIPCHK(c, launch_field_step<T>(A, B, G, c->N, c->sc, c->d_step, c->cfg, c->st), "tune");
         int best_tpp = c->tpp;
         double best_p = 1e300;
-        for (int tpp : {1, 2, 4}) {
+        for (int tpp : {1, 2, 4, 8}) {
             const PushArgs pa = push_args(c, tpp);
             double tot = 0;
             for (int r = 0; r <= reps; r++) {
                 HIPCHK(c, hipEventRecord(e0, c->st), "tune");
-                HIPCHK(c, launch_push<T>(A, B, X, P<T>(c), pa, c->d_step, c->partials, c->d_err, c->st), "tune");
+                HIPCHK(c, launch_push<T>(A, B, G, P<T>(c), pa, c->d_step, c->partials, c->d_err, c->st), "tune");
                 HIPCHK(c, hipEventRecord(e1, c->st), "tune");
                 HIPCHK(c, hipMemcpyAsync(c->pr, c->sb.r2, rb, hipMemcpyDeviceToDevice, c->st), "tune");
                 HIPCHK(c, hipMemcpyAsync(c->pcell, c->sb.cell2, cb, hipMemcpyDeviceToDevice, c->st), "tune");
@@ -1281,8 +1325,10 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
             double tot = 0;
             for (int r = 0; r <= reps; r++) {
                 HIPCHK(c, hipEventRecord(e0, c->st), "tune");
-                HIPCHK(c, launch_push_table<T>(A, B, X, static_cast<T*>(c->ftab), P<T>(c), push_args(c, 1), c->d_step,
-                                               c->partials, c->d_err, c->st), "tune");
+                HIPCHK(c, launch_force_table<T>(A, B, G, static_cast<T*>(c->ftab), c->N, c->sc, c->is_static != 0,
+                                                c->d_step, c->st), "tune");
+                HIPCHK(c, launch_push_table<T>(A, B, static_cast<const T*>(c->ftab), P<T>(c), push_args(c, 1),
+                                               c->d_step, c->partials, c->d_err, c->st), "tune");
                 HIPCHK(c, hipEventRecord(e1, c->st), "tune");
                 HIPCHK(c, hipMemcpyAsync(c->pr, c->sb.r2, rb, hipMemcpyDeviceToDevice, c->st), "tune");
                 HIPCHK(c, hipMemcpyAsync(c->pcell, c->sb.cell2, cb, hipMemcpyDeviceToDevice, c->st), "tune");
@@ -1449,7 +1495,8 @@ extern "C" cpic_status cpic_get_launch(const cpic_ctx* c, int32_t out[7])
 extern "C" cpic_status cpic_set_push_lanes(cpic_ctx* c, int32_t lanes)
 {
     if (!c) return fail(nullptr, CPIC_E_INVALID, "cpic_set_push_lanes: NULL context");
-    if (lanes != 1 && lanes != 2 && lanes != 4) return fail(c, CPIC_E_INVALID, "cpic_set_push_lanes: 1, 2 or 4");
+    if (lanes != 1 && lanes != 2 && lanes != 4 && lanes != 8)
+        return fail(c, CPIC_E_INVALID, "cpic_set_push_lanes: 1, 2, 4 or 8");
     if (c->nc == 2 && lanes != 1) return fail(c, CPIC_E_INVALID, "cpic_set_push_lanes: the SU(2) push takes 1");
     HIPCHK(c, hipStreamSynchronize(c->st), "set push lanes");
     c->tpp = lanes;
@@ -1485,21 +1532,26 @@ extern "C" cpic_status cpic_jets_enable(cpic_ctx* c, const cpic_jet_params* jp)
     const int jslots = num_slots(ja.sc);
     const size_t V = c->V;
     hipError_t e = hipSuccess;
-    void *W = nullptr, *Fp = nullptr, *aux = nullptr;
+    void *W = nullptr, *Fp = nullptr, *tab = nullptr;
     double *part = nullptr, *obs = nullptr;
     e = hipMalloc(&W, 18 * V * c->tsz);
     if (e == hipSuccess) e = hipMalloc(&Fp, 24 * V * c->tsz);
-    if (e == hipSuccess && !c->aux) e = hipMalloc(&aux, (size_t)kAuxReals * V * c->tsz);
+    if (e == hipSuccess && !c->ftab) e = hipMalloc(&tab, (size_t)48 * V * c->tsz);
+    void* gpl = nullptr;
+    if (e == hipSuccess && !c->gpl) e = hipMalloc(&gpl, (size_t)kPlaqReals * V * c->tsz);
     if (e == hipSuccess && jslots > 0) e = hipMalloc(&part, sizeof(double) * 4 * (size_t)jet_groups(c->V) * jslots);
     if (e == hipSuccess && jslots > 0) e = hipMalloc(&obs, sizeof(double) * 4 * (size_t)jslots);
     if (e == hipSuccess && obs) e = hipMemsetAsync(obs, 0, sizeof(double) * 4 * (size_t)jslots, c->st);
     if (e == hipSuccess) e = hipStreamSynchronize(c->st);
     if (e != hipSuccess) {
-        (void)hipFree(W); (void)hipFree(Fp); (void)hipFree(aux); (void)hipFree(part); (void)hipFree(obs);
+        (void)hipFree(W); (void)hipFree(Fp); (void)hipFree(tab); (void)hipFree(gpl); (void)hipFree(part);
+        (void)hipFree(obs);
         const bool oom = e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation;
         return fail(c, oom ? CPIC_E_NOMEM : CPIC_E_HIP, std::string("cpic_jets_enable: ") + hipGetErrorString(e));
     }
-    if (aux) c->aux = aux;
+    if (tab) c->ftab = tab;
+    if (gpl) c->gpl = gpl;
+    c->sc.n_plaq = std::min(c->sc.n_plaq, n_form);
     c->jW = W;
     c->jF = Fp;
     c->jpartials = part;
@@ -1508,7 +1560,6 @@ extern "C" cpic_status cpic_jets_enable(cpic_ctx* c, const cpic_jet_params* jp)
     c->ja = ja;
     double q0[8], eig[3], q3 = 0;
     initial_colour(jp->rep, q0, eig, &c->jet_q2, &q3);
-    c->sc.n_aux = std::min(c->sc.n_aux, n_form);
     c->jsamples.clear();
     c->jobs_reduced = 0;
     c->jets = true;

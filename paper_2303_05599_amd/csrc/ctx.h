@@ -32,8 +32,8 @@ struct cpic_ctx {
     double mhat = 0;
     double q0[8]{}, q0eig[3]{}, q2ref = 0, q3ref = 0;
     void* fbuf[2] = {nullptr, nullptr};
-    void* pr = nullptr;   // particle reals [18][np]
-    void* aux = nullptr;  // [48][V] per-site field pieces for the push (events with particles)
+    void* pr = nullptr;   // particle reals [19][np]
+    void* gpl = nullptr;  // plaquette field G = Proj U_12 [8][V] for the push, force table and light-like paths
     int* pcell = nullptr;  // [2][np]
     int pblocks = 0, nslots = 0;
     double* partials = nullptr;  // [nslots][particle groups of 64][4]
@@ -53,7 +53,7 @@ struct cpic_ctx {
     cpic::LaunchCfg cfg{};
     int tpp = 1;          // wavefronts per particle group in the push (1, 2, 4)
     int push_table = 0;   // 1: fields from a per-site force table (dense ensembles)
-    void* ftab = nullptr; // [48][V] force table
+    void* ftab = nullptr; // [48][V] force table (table push, light-like paths)
     bool initialised = false;
     // graphs: [parity] -> executable graph of kGraphSteps steps starting from buffer `parity`
     hipGraphExec_t gexec[2] = {nullptr, nullptr};

@@ -68,23 +68,16 @@ template <typename T, int HS> struct LdsSrc {
 //   F_i  = -t (Proj U_ij + Proj U_{i,-j}) + (1/t) i[phi->_i, phi]
 //   F_pi = (1/t) sum_i (phi->_i + phi<-_i - 2 phi)
 // Also returns the plaquette trace Re Tr U_12 and the scalar-gradient
-// term sum_i |phi->_i - phi|^2 / 2 for the energy.
+// term sum_i |phi->_i - phi|^2 / 2 for the energy, and, with gv, stores
+// G = Proj U_12 at byte offset gs of the plaquette buffer (plaq_on below).
 // The stencil is organised by link: each of the four links touching x is
 // loaded in one phase, every product it enters is formed there, and it is
 // dropped, so at most two partial plaquettes stay in registers.
-// With AUX and `aux_on`, the per-site pieces of the magnetic fields that the
-// particle push assembles at its cell are written to `aux`:
-//   G   = Proj U_12(x)                       (the clover leaves are transports of G)
-//   D_x = phi->_1(x) - phi<-_1(x),  D_y = phi->_2(x) - phi<-_2(x)
-// (the callers add the sums of E_x, E_y, pi over the two half steps).
-// (aux_s: the site's byte offset in the aux buffer).
-template <typename T, bool AUX = false, typename Src>
+template <typename T, typename Src>
 __device__ __forceinline__ void kick_forces(const Src& f, const Nbr& nb, T t, T inv_t, const a8<T>& PHI,
                                             a8<T>& F1, a8<T>& F2, a8<T>& Fpi, T* re_tr_p12 = nullptr,
-                                            T* grad2 = nullptr, const View<T>* aux = nullptr, bool aux_on = false,
-                                            uint32_t aux_s = 0)
+                                            T* grad2 = nullptr, const View<T>* gv = nullptr, uint32_t gs = 0)
 {
-    a8<T> dx, dy;
     m3<T> A12, A1m2, A2m1;
     a8<T> lap, c1, c2;
     T g2 = 0;
@@ -93,7 +86,6 @@ __device__ __forceinline__ void kick_forces(const Src& f, const Nbr& nb, T t, T 
         A12 = mul(U1, f.U(nb.xp, 1));
         A1m2 = mul_adj(U1, f.U(nb.xpym, 1));
         const a8<T> f1 = transport(U1, f.A(nb.xp, kCompPhi));
-        if (AUX) dx = f1;
         c1 = icomm(f1, PHI);
 #pragma unroll
         for (int a = 0; a < 8; a++) {
@@ -107,13 +99,12 @@ __device__ __forceinline__ void kick_forces(const Src& f, const Nbr& nb, T t, T 
         const m3<T> U2 = f.U(nb.s, 1);
         const m3<T> P = mul_adj(A12, mul(U2, f.U(nb.yp, 0)));
         F1 = proj(P);
-        if (AUX && aux_on) vA_st(*aux, aux_s, kAuxG, F1);
+        if (gv) vA_st(*gv, gs, 0, F1);
 #pragma unroll
         for (int a = 0; a < 8; a++) F2.v[a] = -F1.v[a];   // Proj U_21 = -Proj U_12
         if (re_tr_p12) *re_tr_p12 = P.e[0].re + P.e[4].re + P.e[8].re;
         A2m1 = mul_adj(U2, f.U(nb.xmyp, 0));
         const a8<T> f2 = transport(U2, f.A(nb.yp, kCompPhi));
-        if (AUX) dy = f2;
         c2 = icomm(f2, PHI);
 #pragma unroll
         for (int a = 0; a < 8; a++) {
@@ -129,11 +120,6 @@ __device__ __forceinline__ void kick_forces(const Src& f, const Nbr& nb, T t, T 
         const a8<T> b2 = transport_adj(U2ym, f.A(nb.ym, kCompPhi));
 #pragma unroll
         for (int a = 0; a < 8; a++) { F1.v[a] += p.v[a]; lap.v[a] += b2.v[a]; }
-        if (AUX && aux_on) {
-#pragma unroll
-            for (int a = 0; a < 8; a++) dy.v[a] -= b2.v[a];
-            vA_st(*aux, aux_s, kAuxDy, dy);
-        }
     }
     CPIC_PHASE();
     {   // U_1(x-1): U_{2,-1} = A2m1 [U_1(x-1)^+ U_2(x-1)]^+, phi<-_1
@@ -142,11 +128,6 @@ __device__ __forceinline__ void kick_forces(const Src& f, const Nbr& nb, T t, T 
         const a8<T> b1 = transport_adj(U1xm, f.A(nb.xm, kCompPhi));
 #pragma unroll
         for (int a = 0; a < 8; a++) { F2.v[a] += p.v[a]; lap.v[a] += b1.v[a]; }
-        if (AUX && aux_on) {
-#pragma unroll
-            for (int a = 0; a < 8; a++) dx.v[a] -= b1.v[a];
-            vA_st(*aux, aux_s, kAuxDx, dx);
-        }
     }
 #pragma unroll
     for (int a = 0; a < 8; a++) {
@@ -167,8 +148,18 @@ __device__ __forceinline__ int logical_block(int total, int remap)
     return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
 }
 
-template <typename T, bool AUX>
-__device__ __forceinline__ void field_step_body(const Fields<T>& in, const Fields<T>& out, T* aux, int N, int bx,
+// The particle push and the force table take B_eta from the plaquette field
+// G = Proj U_12 of every site (cellfields.h): with a plaquette buffer gpl
+// ([8][V]), the field update stores G from the first step that reads it on
+// (sc.n_plaq; at n = 0 the forces vanish with t = 1/t = 0, so the kick is
+// still skipped while the plaquettes are formed).
+template <typename T> __device__ __forceinline__ bool plaq_on(const T* gpl, const Schedule& sc, int n)
+{
+    return gpl != nullptr && n >= sc.n_plaq;
+}
+
+template <typename T>
+__device__ __forceinline__ void field_step_body(const Fields<T>& in, const Fields<T>& out, T* gpl, int N, int bx,
                                                 int by, int tile, const Schedule& sc, int* d_step)
 {
     const int ntx = (N + bx - 1) / bx;
@@ -186,30 +177,18 @@ __device__ __forceinline__ void field_step_body(const Fields<T>& in, const Field
     const Nbr nb = neighbours<T>(x, y, N);
     a8<T> PHI = vA(vi, nb.s, kCompPhi);
     a8<T> F1 = azero<T>(), F2 = azero<T>(), Fpi = azero<T>();
-    // the push reads the magnetic-field pieces from the first push step on
-    // (at n = 0, t = 1/t = 0 make the forces vanish, so the kick is still skipped)
-    const bool aux_on = AUX && n >= sc.n_aux;
-    if (kick || aux_on) {
-        View<T> va;
-        if (AUX) va = make_view<T>(aux, kAuxReals, V);
-        kick_forces<T, AUX>(GlobalSrc<T>{vi}, nb, t, inv_t, PHI, F1, F2, Fpi, nullptr, nullptr, &va, aux_on, nb.s);
+    const bool gon = plaq_on(gpl, sc, n);
+    if (kick || gon) {
+        const View<T> gv = make_view<T>(gpl, kPlaqReals, V);
+        kick_forces<T>(GlobalSrc<T>{vi}, nb, t, inv_t, PHI, F1, F2, Fpi, nullptr, nullptr, gon ? &gv : nullptr, nb.s);
     }
     CPIC_PHASE();
     a8<T> E1 = vA(vi, nb.s, kCompE), E2 = vA(vi, nb.s, kCompE + 8), PI = vA(vi, nb.s, kCompPi);
-    a8<T> S1, S2, SP;  // sums of the momenta over the two half steps, for the push
 #pragma unroll
     for (int a = 0; a < 8; a++) {
-        S1.v[a] = E1.v[a]; S2.v[a] = E2.v[a]; SP.v[a] = PI.v[a];
         E1.v[a] += dt * F1.v[a];
         E2.v[a] += dt * F2.v[a];
         PI.v[a] += dt * Fpi.v[a];
-        S1.v[a] += E1.v[a]; S2.v[a] += E2.v[a]; SP.v[a] += PI.v[a];
-    }
-    if (AUX && aux_on) {
-        const View<T> va = make_view<T>(aux, kAuxReals, V);
-        vA_st(va, nb.s, kAuxS1, S1);
-        vA_st(va, nb.s, kAuxS2, S2);
-        vA_st(va, nb.s, kAuxP, SP);
     }
     CPIC_PHASE();
     // drift: U_i <- exp(i (dt/t_half) E_i) U_i ; phi <- phi + dt t_half pi
@@ -234,8 +213,8 @@ __device__ __forceinline__ void field_step_body(const Fields<T>& in, const Field
 // coalesced loads (each global value read once per tile instead of once per
 // stencil use), then every thread runs the stencil out of LDS; E and pi of
 // its own site come straight from global memory.
-template <typename T, bool AUX, int BX, int BY>
-__device__ __forceinline__ void field_tile_body(const Fields<T>& in, const Fields<T>& out, T* aux, int N, int tile,
+template <typename T, int BX, int BY>
+__device__ __forceinline__ void field_tile_body(const Fields<T>& in, const Fields<T>& out, T* gpl, int N, int tile,
                                                 const Schedule& sc, int* d_step)
 {
     constexpr int HX = BX + 2, HY = BY + 2, HS = HX * HY, NT = BX * BY, NC = 44;
@@ -279,30 +258,18 @@ __device__ __forceinline__ void field_tile_body(const Fields<T>& in, const Field
     const LdsSrc<T, HS> src{lds};
     a8<T> PHI = src.A(hs, kCompPhi);
     a8<T> F1 = azero<T>(), F2 = azero<T>(), Fpi = azero<T>();
-    // the push reads the magnetic-field pieces from the first push step on
-    // (at n = 0, t = 1/t = 0 make the forces vanish, so the kick is still skipped)
-    const bool aux_on = AUX && n >= sc.n_aux;
-    if (kick || aux_on) {
-        View<T> va;
-        if (AUX) va = make_view<T>(aux, kAuxReals, V);
-        kick_forces<T, AUX>(src, nb, t, inv_t, PHI, F1, F2, Fpi, nullptr, nullptr, &va, aux_on, gs);
+    const bool gon = plaq_on(gpl, sc, n);
+    if (kick || gon) {
+        const View<T> gv = make_view<T>(gpl, kPlaqReals, V);
+        kick_forces<T>(src, nb, t, inv_t, PHI, F1, F2, Fpi, nullptr, nullptr, gon ? &gv : nullptr, gs);
     }
     CPIC_PHASE();
     a8<T> E1 = vA(vi, gs, kCompE), E2 = vA(vi, gs, kCompE + 8), PI = vA(vi, gs, kCompPi);
-    a8<T> S1, S2, SP;  // sums of the momenta over the two half steps, for the push
 #pragma unroll
     for (int a = 0; a < 8; a++) {
-        S1.v[a] = E1.v[a]; S2.v[a] = E2.v[a]; SP.v[a] = PI.v[a];
         E1.v[a] += dt * F1.v[a];
         E2.v[a] += dt * F2.v[a];
         PI.v[a] += dt * Fpi.v[a];
-        S1.v[a] += E1.v[a]; S2.v[a] += E2.v[a]; SP.v[a] += PI.v[a];
-    }
-    if (AUX && aux_on) {
-        const View<T> va = make_view<T>(aux, kAuxReals, V);
-        vA_st(va, gs, kAuxS1, S1);
-        vA_st(va, gs, kAuxS2, S2);
-        vA_st(va, gs, kAuxP, SP);
     }
     CPIC_PHASE();
     // drift: U_i <- exp(i (dt/t_half) E_i) U_i ; phi <- phi + dt t_half pi
@@ -321,12 +288,12 @@ __device__ __forceinline__ void field_tile_body(const Fields<T>& in, const Field
     vA_st(vo, gs, kCompPi, PI);
 }
 
-template <typename T, bool AUX, int BX, int BY>
-__global__ __launch_bounds__(BX * BY) void field_tile_kernel(Fields<T> in, Fields<T> out, T* aux, int N, int remap,
+template <typename T, int BX, int BY>
+__global__ __launch_bounds__(BX * BY) void field_tile_kernel(Fields<T> in, Fields<T> out, T* gpl, int N, int remap,
                                                              Schedule sc, int* d_step)
 {
     const int nt = ((N + BX - 1) / BX) * ((N + BY - 1) / BY), tile = logical_block(nt, remap);
-    if (tile < nt) field_tile_body<T, AUX, BX, BY>(in, out, aux, N, tile, sc, d_step);
+    if (tile < nt) field_tile_body<T, BX, BY>(in, out, gpl, N, tile, sc, d_step);
 }
 
 // ---------------------------------------------------------------- compressed-link LDS tiles
@@ -353,8 +320,8 @@ template <typename T, int HS> struct LdsLinks2 {
     }
 };
 
-template <typename T, bool AUX, int BX, int BY, int CP = 0>
-__device__ __forceinline__ void field_ctile_body(const Fields<T>& in, const Fields<T>& out, T* aux, int N, int tile,
+template <typename T, int BX, int BY, int CP = 0>
+__device__ __forceinline__ void field_ctile_body(const Fields<T>& in, const Fields<T>& out, T* gpl, int N, int tile,
                                                  const Schedule& sc, int* d_step)
 {
     constexpr int HX = BX + 2, HY = BY + 2, HS = HX * HY, NT = BX * BY, NC = 24;
@@ -395,17 +362,14 @@ __device__ __forceinline__ void field_ctile_body(const Fields<T>& in, const Fiel
     const LdsLinks2<T, HS> L{lds};
     a8<T> PHI = vA(vi, g.s, kCompPhi);
     a8<T> F1 = azero<T>(), F2 = azero<T>(), Fpi = azero<T>();
-    // the push reads the magnetic-field pieces from the first push step on
-    // (at n = 0, t = 1/t = 0 make the forces vanish, so the kick is still skipped)
-    const bool aux_on = AUX && aux != nullptr && n >= sc.n_aux;
-    a8<T> G, DX, DY;  // magnetic-field pieces, stored last (keeps them out of the stencil's register peak)
-    if (kick || aux_on) {
+    const bool gon = plaq_on(gpl, sc, n);
+    if (kick || gon) {
         {   // U_12(x) = U_1(x) U_2(x+1) U_1(x+2)^+ U_2(x)^+
             m3<T> M = mul(L.U(s, 0), L.U(xp, 1));
             M = mul_adj(M, L.U(yp, 0));
             M = mul_adj(M, L.U(s, 1));
             F1 = proj(M);
-            G = F1;
+            if (gon) vA_st(make_view<T>(gpl, kPlaqReals, V), g.s, 0, F1);
 #pragma unroll
             for (int a = 0; a < 8; a++) F2.v[a] = -F1.v[a];
         }
@@ -433,54 +397,36 @@ __device__ __forceinline__ void field_ctile_body(const Fields<T>& in, const Fiel
             const a8<T> f1 = transport(L.U(s, 0), vA(vi, g.xp, kCompPhi));
             const a8<T> c1 = icomm(f1, PHI);
             const a8<T> b1 = transport_adj(L.U(xm, 0), vA(vi, g.xm, kCompPhi));
-            a8<T> d;
 #pragma unroll
             for (int a = 0; a < 8; a++) {
                 F1.v[a] = -t * F1.v[a] + inv_t * c1.v[a];
                 lap.v[a] = f1.v[a] + b1.v[a] - T(4) * PHI.v[a];
-                d.v[a] = f1.v[a] - b1.v[a];
             }
-            DX = d;
         }
         CPIC_PHASE();
         {   // phi->_2, phi<-_2
             const a8<T> f2 = transport(L.U(s, 1), vA(vi, g.yp, kCompPhi));
             const a8<T> c2 = icomm(f2, PHI);
             const a8<T> b2 = transport_adj(L.U(ym, 1), vA(vi, g.ym, kCompPhi));
-            a8<T> d;
 #pragma unroll
             for (int a = 0; a < 8; a++) {
                 F2.v[a] = -t * F2.v[a] + inv_t * c2.v[a];
                 Fpi.v[a] = inv_t * (lap.v[a] + f2.v[a] + b2.v[a]);
-                d.v[a] = f2.v[a] - b2.v[a];
             }
-            DY = d;
         }
     }
     CPIC_PHASE();
     a8<T> E1 = vA(vi, g.s, kCompE), E2 = vA(vi, g.s, kCompE + 8), PI = vA(vi, g.s, kCompPi);
-    a8<T> S1, S2, SP;  // sums of the momenta over the two half steps, for the push
 #pragma unroll
     for (int a = 0; a < 8; a++) {
-        S1.v[a] = E1.v[a]; S2.v[a] = E2.v[a]; SP.v[a] = PI.v[a];
         E1.v[a] += dt * F1.v[a];
         E2.v[a] += dt * F2.v[a];
         PI.v[a] += dt * Fpi.v[a];
-        S1.v[a] += E1.v[a]; S2.v[a] += E2.v[a]; SP.v[a] += PI.v[a];
-    }
-    if (AUX && aux_on) {
-        const View<T> va = make_view<T>(aux, kAuxReals, V);
-        vA_st(va, g.s, kAuxS1, S1);
-        vA_st(va, g.s, kAuxS2, S2);
-        vA_st(va, g.s, kAuxP, SP);
     }
     CPIC_PHASE();
     // drift: U_i <- exp(i (dt/t_half) E_i) U_i ; phi <- phi + dt t_half pi
-    // CP: cache policy of the new state (links, phi, E, pi).  The rest of the
-    // step reads the old links and scalar and the aux pieces: where these and
-    // the new state do not fit in the last-level cache together, the new state
-    // goes out non-temporal so that it does not displace what the push reads
-    // next.
+    // CP: cache policy of the new state (links, phi, E, pi), chosen by the
+    // host from the step's working set (set_store_policy in capi.hip).
     m3<T> U1 = mul(expi(E1, eps_drift), L.U(s, 0));
     if (reunit) U1 = reunitarize(U1);
     vU_st<T, CP>(vo, g.s, 0, U1);
@@ -494,20 +440,14 @@ __device__ __forceinline__ void field_ctile_body(const Fields<T>& in, const Fiel
     vA_st<T, CP>(vo, g.s, kCompE, E1);
     vA_st<T, CP>(vo, g.s, kCompE + 8, E2);
     vA_st<T, CP>(vo, g.s, kCompPi, PI);
-    if (AUX && aux_on) {
-        const View<T> va = make_view<T>(aux, kAuxReals, V);
-        vA_st(va, g.s, kAuxG, G);
-        vA_st(va, g.s, kAuxDx, DX);
-        vA_st(va, g.s, kAuxDy, DY);
-    }
 }
 
-template <typename T, bool AUX, int BX, int BY, int CP>
-__global__ __launch_bounds__(BX * BY) void field_ctile_kernel(Fields<T> in, Fields<T> out, T* aux, int N, int remap,
+template <typename T, int BX, int BY, int CP>
+__global__ __launch_bounds__(BX * BY) void field_ctile_kernel(Fields<T> in, Fields<T> out, T* gpl, int N, int remap,
                                                               Schedule sc, int* d_step)
 {
     const int nt = ((N + BX - 1) / BX) * ((N + BY - 1) / BY), tile = logical_block(nt, remap);
-    if (tile < nt) field_ctile_body<T, AUX, BX, BY, CP>(in, out, aux, N, tile, sc, d_step);
+    if (tile < nt) field_ctile_body<T, BX, BY, CP>(in, out, gpl, N, tile, sc, d_step);
 }
 
 // ---------------------------------------------------------------- link-parallel variant
@@ -516,8 +456,8 @@ __global__ __launch_bounds__(BX * BY) void field_ctile_kernel(Fields<T> in, Fiel
 // U_ij(x) and U_{i,-j}(x), the transported scalar phi->_i and phi<-_i, updates
 // E_i and drifts U_i; the pi force is the sum of both directions' scalar terms
 // (one lane exchange, lanes l and l ^ 32), and the i = 0 thread writes phi, pi.
-template <typename T, bool AUX>
-__device__ __forceinline__ void field_link_body(const Fields<T>& in, const Fields<T>& out, T* aux, int N, int bx,
+template <typename T>
+__device__ __forceinline__ void field_link_body(const Fields<T>& in, const Fields<T>& out, T* gpl, int N, int bx,
                                                 int by, int remap, const Schedule& sc, int* d_step)
 {
     const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
@@ -561,17 +501,13 @@ __device__ __forceinline__ void field_link_body(const Fields<T>& in, const Field
     };
     const a8<T> PHI = vA(vi, s, kCompPhi);
     a8<T> F = azero<T>(), lap = azero<T>();
-    // the push reads the magnetic-field pieces (G = Proj U_12 from the i = 0
-    // thread, D_i = phi->_i - phi<-_i) from the first push step on
-    const bool aux_on = AUX && n >= sc.n_aux && live;
-    View<T> va;
-    if (AUX) va = make_view<T>(aux, kAuxReals, V);
-    if (kick || aux_on) {
-        {   // U_ij(x) = U_i(x) U_j(x+i) [U_j(x) U_i(x+j)]^+
+    const bool gon = plaq_on(gpl, sc, n) && live;
+    if (kick || gon) {
+        {   // U_ij(x) = U_i(x) U_j(x+i) [U_j(x) U_i(x+j)]^+ (G from the i = 0 thread)
             const m3<T> Pm = mul_adj(mul(link(vi, s, i), link(vi, site(ix, iy), j)),
                                      mul(link(vi, s, j), link(vi, site(jx, jy), i)));
             F = proj(Pm);
-            if (AUX && aux_on && i == 0) vA_st(va, s, kAuxG, F);
+            if (gon && i == 0) vA_st(make_view<T>(gpl, kPlaqReals, V), s, 0, F);
         }
         CPIC_PHASE();
         {   // U_{i,-j}(x) = U_i(x) U_j(x+i-j)^+ [U_j(x-j)^+ U_i(x-j)]^+
@@ -593,12 +529,6 @@ __device__ __forceinline__ void field_link_body(const Fields<T>& in, const Field
                 F.v[a] += inv_t * cm.v[a];
                 lap.v[a] = fw.v[a] + bw.v[a] - T(2) * PHI.v[a];
             }
-            if (AUX && aux_on) {
-                a8<T> d;
-#pragma unroll
-                for (int a = 0; a < 8; a++) d.v[a] = fw.v[a] - bw.v[a];
-                vA_st(va, s, i == 0 ? kAuxDx : kAuxDy, d);
-            }
         }
         if (!kick) F = lap = azero<T>();
     }
@@ -607,17 +537,10 @@ __device__ __forceinline__ void field_link_body(const Fields<T>& in, const Field
     for (int a = 0; a < 8; a++) lap.v[a] += __shfl_xor(lap.v[a], 32, 64);
     CPIC_PHASE();
     a8<T> Ei = vA(vi, s, kCompE + 8 * i), PI = vA(vi, s, kCompPi);
-    a8<T> Si, SP;  // sums of the momenta over the two half steps, for the push
 #pragma unroll
     for (int a = 0; a < 8; a++) {
-        Si.v[a] = Ei.v[a]; SP.v[a] = PI.v[a];
         Ei.v[a] += dt * F.v[a];
         PI.v[a] += dt * inv_t * lap.v[a];
-        Si.v[a] += Ei.v[a]; SP.v[a] += PI.v[a];
-    }
-    if (AUX && aux_on) {
-        vA_st(va, s, i == 0 ? kAuxS1 : kAuxS2, Si);
-        if (i == 0) vA_st(va, s, kAuxP, SP);
     }
     m3<T> Ui = mul(expi(Ei, eps_drift), link(vi, s, i));
     if (reunit) Ui = reunitarize(Ui);
@@ -633,23 +556,23 @@ __device__ __forceinline__ void field_link_body(const Fields<T>& in, const Field
     }
 }
 
-template <typename T, bool AUX>
-__global__ __launch_bounds__(256) void field_link_kernel(Fields<T> in, Fields<T> out, T* aux, int N, int bx, int by,
+template <typename T>
+__global__ __launch_bounds__(256) void field_link_kernel(Fields<T> in, Fields<T> out, T* gpl, int N, int bx, int by,
                                                          int remap, Schedule sc, int* d_step)
 {
-    field_link_body<T, AUX>(in, out, aux, N, bx, by, remap, sc, d_step);
+    field_link_body<T>(in, out, gpl, N, bx, by, remap, sc, d_step);
 }
-template <typename T, bool AUX>
+template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void field_link_kernel_w2(
-    Fields<T> in, Fields<T> out, T* aux, int N, int bx, int by, int remap, Schedule sc, int* d_step)
+    Fields<T> in, Fields<T> out, T* gpl, int N, int bx, int by, int remap, Schedule sc, int* d_step)
 {
-    field_link_body<T, AUX>(in, out, aux, N, bx, by, remap, sc, d_step);
+    field_link_body<T>(in, out, gpl, N, bx, by, remap, sc, d_step);
 }
-template <typename T, bool AUX>
+template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void field_link_kernel_w3(
-    Fields<T> in, Fields<T> out, T* aux, int N, int bx, int by, int remap, Schedule sc, int* d_step)
+    Fields<T> in, Fields<T> out, T* gpl, int N, int bx, int by, int remap, Schedule sc, int* d_step)
 {
-    field_link_body<T, AUX>(in, out, aux, N, bx, by, remap, sc, d_step);
+    field_link_body<T>(in, out, gpl, N, bx, by, remap, sc, d_step);
 }
 
 // Occupancy variants: W waves per SIMD requested from the register
@@ -657,21 +580,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
 // the launch tuner.
 __device__ __forceinline__ int field_tiles(int N, int bx, int by) { return ((N + bx - 1) / bx) * ((N + by - 1) / by); }
 
-template <typename T, bool AUX>
-__global__ __launch_bounds__(256) void field_step_kernel(Fields<T> in, Fields<T> out, T* aux, int N, int bx, int by,
+template <typename T>
+__global__ __launch_bounds__(256) void field_step_kernel(Fields<T> in, Fields<T> out, T* gpl, int N, int bx, int by,
                                                          int remap, Schedule sc, int* d_step)
 {
     const int nt = field_tiles(N, bx, by), tile = logical_block(nt, remap);
-    if (tile < nt) field_step_body<T, AUX>(in, out, aux, N, bx, by, tile, sc, d_step);
+    if (tile < nt) field_step_body<T>(in, out, gpl, N, bx, by, tile, sc, d_step);
 }
 #define CPIC_FIELD_VARIANT(W)                                                                                     \
-    template <typename T, bool AUX>                                                                               \
+    template <typename T>                                                                                         \
     __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, W))) void field_step_kernel_w##W(    \
-        Fields<T> in, Fields<T> out, T* aux, int N, int bx, int by, int remap, Schedule sc,                       \
-        int* d_step)                                                                           \
+        Fields<T> in, Fields<T> out, T* gpl, int N, int bx, int by, int remap, Schedule sc, int* d_step)          \
     {                                                                                                             \
         const int nt = field_tiles(N, bx, by), tile = logical_block(nt, remap);                                   \
-        if (tile < nt) field_step_body<T, AUX>(in, out, aux, N, bx, by, tile, sc, d_step);                        \
+        if (tile < nt) field_step_body<T>(in, out, gpl, N, bx, by, tile, sc, d_step);                             \
     }
 CPIC_FIELD_VARIANT(2)
 CPIC_FIELD_VARIANT(3)
@@ -695,8 +617,7 @@ __global__ __launch_bounds__(BX * BY) void batch_field_kernel(const EventDesc* _
     const EventDesc& d = ev[e];
     const int parity = __builtin_amdgcn_readfirstlane((d.d_step[0] & 1) ^ d.flip);
     const Fields<T> A = fields_at<T>(d.f[parity], d.N * d.N), B = fields_at<T>(d.f[parity ^ 1], d.N * d.N);
-    // events without particles have no field pieces to write (aux = NULL)
-    field_ctile_body<T, true, BX, BY>(A, B, static_cast<T*>(d.aux), d.N, tile, d.pa.sc, d.d_step);
+    field_ctile_body<T, BX, BY>(A, B, static_cast<T*>(d.gpl), d.N, tile, d.pa.sc, d.d_step);
 }
 
 template <typename T, int BX, int BY>
@@ -723,51 +644,52 @@ hipError_t launch_batch_field(const EventDesc* ev, const int2* map, int total_ti
 template hipError_t launch_batch_field<double>(const EventDesc*, const int2*, int, const LaunchCfg&, hipStream_t);
 template hipError_t launch_batch_field<float>(const EventDesc*, const int2*, int, const LaunchCfg&, hipStream_t);
 
-template <typename T, bool AUX, int BX, int BY>
-static hipError_t launch_tile(const Fields<T>& in, const Fields<T>& out, T* aux, int N, const Schedule& sc,
+template <typename T, int BX, int BY>
+static hipError_t launch_tile(const Fields<T>& in, const Fields<T>& out, T* gpl, int N, const Schedule& sc,
                               int* d_step, int remap, hipStream_t st, const KTimer& tm)
 {
     const int ntiles = ((N + BX - 1) / BX) * ((N + BY - 1) / BY);
     const dim3 g(remap ? 8 * ((ntiles + 7) / 8) : ntiles), blk(BX * BY);
-    klaunch(tm, field_tile_kernel<T, AUX, BX, BY>, g, blk, st, in, out, aux, N, remap, sc, d_step);
+    klaunch(tm, field_tile_kernel<T, BX, BY>, g, blk, st, in, out, gpl, N, remap, sc, d_step);
     return hipGetLastError();
 }
 
-template <typename T, bool AUX, int BX, int BY>
-static hipError_t launch_ctile(const Fields<T>& in, const Fields<T>& out, T* aux, int N, const Schedule& sc,
+template <typename T, int BX, int BY>
+static hipError_t launch_ctile(const Fields<T>& in, const Fields<T>& out, T* gpl, int N, const Schedule& sc,
                                int* d_step, int remap, int nt_store, hipStream_t st, const KTimer& tm)
 {
     const int ntiles = ((N + BX - 1) / BX) * ((N + BY - 1) / BY);
     const dim3 g(remap ? 8 * ((ntiles + 7) / 8) : ntiles), blk(BX * BY);
-    if (AUX && nt_store)
-        klaunch(tm, field_ctile_kernel<T, AUX, BX, BY, kStoreNT>, g, blk, st, in, out, aux, N, remap, sc, d_step);
+    if (nt_store)
+        klaunch(tm, field_ctile_kernel<T, BX, BY, kStoreNT>, g, blk, st, in, out, gpl, N, remap, sc, d_step);
     else
-        klaunch(tm, field_ctile_kernel<T, AUX, BX, BY, 0>, g, blk, st, in, out, aux, N, remap, sc, d_step);
+        klaunch(tm, field_ctile_kernel<T, BX, BY, 0>, g, blk, st, in, out, gpl, N, remap, sc, d_step);
     return hipGetLastError();
 }
 
-template <typename T, bool AUX>
-static hipError_t launch_field_step_t(const Fields<T>& in, const Fields<T>& out, T* aux, int N, const Schedule& sc,
-                                      int* d_step, const LaunchCfg& cfg, hipStream_t st, const KTimer& tm)
+template <typename T>
+hipError_t launch_field_step(const Fields<T>& in, const Fields<T>& out, T* gpl, int N, const Schedule& sc,
+                             int* d_step, const LaunchCfg& cfg, hipStream_t st, const KTimer& tm)
 {
+    if (cfg.bx <= 0 || cfg.by <= 0 || cfg.waves < 1 || cfg.waves > 4) return hipErrorInvalidValue;
     if (cfg.split == 3) {
         // compressed-link LDS tiles of the instantiated shapes
         const int r = cfg.xcd_remap, nts = cfg.nt_store;
-        if (cfg.bx == 64 && cfg.by == 4) return launch_ctile<T, AUX, 64, 4>(in, out, aux, N, sc, d_step, r, nts, st, tm);
-        if (cfg.bx == 32 && cfg.by == 8) return launch_ctile<T, AUX, 32, 8>(in, out, aux, N, sc, d_step, r, nts, st, tm);
-        if (cfg.bx == 16 && cfg.by == 16) return launch_ctile<T, AUX, 16, 16>(in, out, aux, N, sc, d_step, r, nts, st, tm);
-        if (cfg.bx == 32 && cfg.by == 4) return launch_ctile<T, AUX, 32, 4>(in, out, aux, N, sc, d_step, r, nts, st, tm);
-        if (cfg.bx == 64 && cfg.by == 8) return launch_ctile<T, AUX, 64, 8>(in, out, aux, N, sc, d_step, r, nts, st, tm);
+        if (cfg.bx == 64 && cfg.by == 4) return launch_ctile<T, 64, 4>(in, out, gpl, N, sc, d_step, r, nts, st, tm);
+        if (cfg.bx == 32 && cfg.by == 8) return launch_ctile<T, 32, 8>(in, out, gpl, N, sc, d_step, r, nts, st, tm);
+        if (cfg.bx == 16 && cfg.by == 16) return launch_ctile<T, 16, 16>(in, out, gpl, N, sc, d_step, r, nts, st, tm);
+        if (cfg.bx == 32 && cfg.by == 4) return launch_ctile<T, 32, 4>(in, out, gpl, N, sc, d_step, r, nts, st, tm);
+        if (cfg.bx == 64 && cfg.by == 8) return launch_ctile<T, 64, 8>(in, out, gpl, N, sc, d_step, r, nts, st, tm);
         return hipErrorInvalidValue;
     }
     if (cfg.split == 2) {
         // LDS halo tiles of the instantiated shapes
         const int r = cfg.xcd_remap;
-        if (cfg.bx == 64 && cfg.by == 4) return launch_tile<T, AUX, 64, 4>(in, out, aux, N, sc, d_step, r, st, tm);
-        if (cfg.bx == 32 && cfg.by == 4) return launch_tile<T, AUX, 32, 4>(in, out, aux, N, sc, d_step, r, st, tm);
-        if (cfg.bx == 64 && cfg.by == 2) return launch_tile<T, AUX, 64, 2>(in, out, aux, N, sc, d_step, r, st, tm);
-        if (cfg.bx == 32 && cfg.by == 8) return launch_tile<T, AUX, 32, 8>(in, out, aux, N, sc, d_step, r, st, tm);
-        if (cfg.bx == 16 && cfg.by == 8) return launch_tile<T, AUX, 16, 8>(in, out, aux, N, sc, d_step, r, st, tm);
+        if (cfg.bx == 64 && cfg.by == 4) return launch_tile<T, 64, 4>(in, out, gpl, N, sc, d_step, r, st, tm);
+        if (cfg.bx == 32 && cfg.by == 4) return launch_tile<T, 32, 4>(in, out, gpl, N, sc, d_step, r, st, tm);
+        if (cfg.bx == 64 && cfg.by == 2) return launch_tile<T, 64, 2>(in, out, gpl, N, sc, d_step, r, st, tm);
+        if (cfg.bx == 32 && cfg.by == 8) return launch_tile<T, 32, 8>(in, out, gpl, N, sc, d_step, r, st, tm);
+        if (cfg.bx == 16 && cfg.by == 8) return launch_tile<T, 16, 8>(in, out, gpl, N, sc, d_step, r, st, tm);
         return hipErrorInvalidValue;
     }
     if (cfg.split) {
@@ -776,9 +698,9 @@ static hipError_t launch_field_step_t(const Fields<T>& in, const Fields<T>& out,
         const int ntiles = ((N + cfg.bx - 1) / cfg.bx) * ((N + cfg.by - 1) / cfg.by);
         const dim3 g(cfg.xcd_remap ? 8 * ((ntiles + 7) / 8) : ntiles), blk(256);
         switch (cfg.waves) {
-        case 2: klaunch(tm, field_link_kernel_w2<T, AUX>, g, blk, st, in, out, aux, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
-        case 3: klaunch(tm, field_link_kernel_w3<T, AUX>, g, blk, st, in, out, aux, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
-        default: klaunch(tm, field_link_kernel<T, AUX>, g, blk, st, in, out, aux, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step);
+        case 2: klaunch(tm, field_link_kernel_w2<T>, g, blk, st, in, out, gpl, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
+        case 3: klaunch(tm, field_link_kernel_w3<T>, g, blk, st, in, out, gpl, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
+        default: klaunch(tm, field_link_kernel<T>, g, blk, st, in, out, gpl, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step);
         }
         return hipGetLastError();
     }
@@ -788,21 +710,12 @@ static hipError_t launch_field_step_t(const Fields<T>& in, const Fields<T>& out,
     const int grid = cfg.xcd_remap ? 8 * ((ntiles + 7) / 8) : ntiles;
     const dim3 g(grid), b(cfg.bx, cfg.by);
     switch (cfg.waves) {
-    case 2: klaunch(tm, field_step_kernel_w2<T, AUX>, g, b, st, in, out, aux, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
-    case 3: klaunch(tm, field_step_kernel_w3<T, AUX>, g, b, st, in, out, aux, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
-    case 4: klaunch(tm, field_step_kernel_w4<T, AUX>, g, b, st, in, out, aux, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
-    default: klaunch(tm, field_step_kernel<T, AUX>, g, b, st, in, out, aux, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step);
+    case 2: klaunch(tm, field_step_kernel_w2<T>, g, b, st, in, out, gpl, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
+    case 3: klaunch(tm, field_step_kernel_w3<T>, g, b, st, in, out, gpl, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
+    case 4: klaunch(tm, field_step_kernel_w4<T>, g, b, st, in, out, gpl, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step); break;
+    default: klaunch(tm, field_step_kernel<T>, g, b, st, in, out, gpl, N, cfg.bx, cfg.by, cfg.xcd_remap, sc, d_step);
     }
     return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_field_step(const Fields<T>& in, const Fields<T>& out, T* aux, int N, const Schedule& sc,
-                             int* d_step, const LaunchCfg& cfg, hipStream_t st, const KTimer& tm)
-{
-    if (cfg.bx <= 0 || cfg.by <= 0 || cfg.waves < 1 || cfg.waves > 4) return hipErrorInvalidValue;
-    return aux ? launch_field_step_t<T, true>(in, out, aux, N, sc, d_step, cfg, st, tm)
-               : launch_field_step_t<T, false>(in, out, nullptr, N, sc, d_step, cfg, st, tm);
 }
 
 // ------------------------------------------------------------------ diagnostics

@@ -390,6 +390,7 @@ __global__ void particles_kernel(PartICArgs a, double* r, int* cell)
     col(PX_) = x; col(PY_) = y; col(PETA_) = 0;
     col(PPX) = pt * cph; col(PPY) = pt * sph; col(PPETA) = 0; col(PDETA) = 0;
     col(PUX0) = cph; col(PUY0) = sph; col(PPT0) = pt;
+    col(PPTAU) = 0.0;  // set by the push at the formation step
     for (int c = 0; c < 8; c++) col(PQ0 + c) = Q.v[c];
     int nx = (int)floor(x + 0.5), ny = (int)floor(y + 0.5);
     cell[p] = nx >= N ? nx - N : nx;
@@ -579,6 +580,7 @@ __global__ void particles2_kernel(PartICArgs a, double J, double* r, int* cell)
     col(PX_) = x; col(PY_) = y; col(PETA_) = 0;
     col(PPX) = pt * cph; col(PPY) = pt * sph; col(PPETA) = 0; col(PDETA) = 0;
     col(PUX0) = cph; col(PUY0) = sph; col(PPT0) = pt;
+    col(PPTAU) = 0.0;  // set by the push at the formation step
     col(PQ0) = cos(ph) * rho; col(PQ0 + 1) = sin(ph) * rho; col(PQ0 + 2) = xi;
     for (int c = 3; c < 8; c++) col(PQ0 + c) = 0.0;
     int nx = (int)floor(x + 0.5), ny = (int)floor(y + 0.5);

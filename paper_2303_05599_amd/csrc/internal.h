@@ -13,8 +13,10 @@
 namespace cpic {
 
 constexpr int kRealsPerSite = 68;
-constexpr int kPartReals = 18;  // x y eta px py peta deta ux0 uy0 pt0 Q1..Q8
-enum PartCol { PX_ = 0, PY_, PETA_, PPX, PPY, PPETA, PDETA, PUX0, PUY0, PPT0, PQ0 };
+// x y eta px py peta deta ux0 uy0 pt0 Q1..Q8, and p^tau integrated from its own
+// equation of motion (the temporal-constraint check of Appendix D)
+constexpr int kPartReals = 19;
+enum PartCol { PX_ = 0, PY_, PETA_, PPX, PPY, PPETA, PDETA, PUX0, PUY0, PPT0, PQ0, PPTAU = PQ0 + 8 };
 
 template <typename T> struct Fields {
     T* U;    // [2][18][V]
@@ -44,7 +46,7 @@ template <typename T> __host__ __device__ inline Fields2<T> fields2_at(void* bas
 }
 
 template <typename T> struct Parts {
-    T* r;       // [18][np] (PartCol order)
+    T* r;       // [19][np] (PartCol order)
     int* cell;  // [2][np]
 };
 
@@ -56,7 +58,7 @@ struct Schedule {
     double dt;         // dtau / a
     int n_max;         // steps to tau_max
     int n_form;        // first step of the particle push
-    int n_aux;         // first step whose field update writes the aux buffer
+    int n_plaq;        // first step whose field update stores the plaquette field G (the push's B_eta)
     int record_every;  // samples after steps with (n+1) % record_every == 0, and after n_max - 1
     int reunit_every;  // FP32: reunitarise links / renormalise charges after steps with (n+1) % k == 0
 };
@@ -100,8 +102,8 @@ struct PushArgs {
 struct EventDesc {
     void* f[2];        // field buffer sets; the state at step n is in f[(n & 1) ^ flip]
     int flip;
-    void* pr;          // particle records [18][np]
-    void* aux;         // [48][V] field pieces for the push (NULL without particles)
+    void* pr;          // particle records [19][np]
+    void* gpl;         // plaquette field G [8][V] (NULL without particles)
     int* cell;         // [2][np]
     int N;
     PushArgs pa;
@@ -110,10 +112,11 @@ struct EventDesc {
     double* partials;  // [slots][particle groups][4]
 };
 
-// particle blocks of the push: 256 / tpp particles per block
+// particle blocks of the push: 256 / tpp particles per block (64 in the
+// 512-thread blocks of tpp = 8)
 __host__ __device__ inline int push_blocks_d(int np, int tpp)
 {
-    const int ppb = 256 / (tpp > 0 ? tpp : 1);
+    const int ppb = tpp == 8 ? 64 : 256 / (tpp > 0 ? tpp : 1);
     return (np + ppb - 1) / ppb;
 }
 
@@ -132,14 +135,12 @@ inline void klaunch(const KTimer& tm, F kernel, dim3 grid, dim3 block, hipStream
 }
 
 // ---- field kernels (field.hip)
-// aux (may be NULL): [48][V] per-site pieces of the colour fields for the
-// push, written by the field update of the same step from step n_aux on:
-//   G = Proj U_12, D_x = phi->_x - phi<-_x, D_y = phi->_y - phi<-_y,
-//   S_x, S_y, P = E_x, E_y, pi summed over the half steps n - 1/2 and n + 1/2
-constexpr int kAuxReals = 48;
-constexpr uint32_t kAuxG = 0, kAuxDx = 8, kAuxDy = 16, kAuxS1 = 24, kAuxS2 = 32, kAuxP = 40;
+// gpl (may be NULL): the plaquette field G = Proj U_12 of every site at step
+// n, [8][V], stored by the field update of steps n >= sc.n_plaq for the push,
+// the force table and the light-like paths (B_eta from the clover, cellfields.h)
+constexpr int kPlaqReals = 8;
 template <typename T>
-hipError_t launch_field_step(const Fields<T>& in, const Fields<T>& out, T* aux, int N, const Schedule& sc,
+hipError_t launch_field_step(const Fields<T>& in, const Fields<T>& out, T* gpl, int N, const Schedule& sc,
                              int* d_step, const LaunchCfg& cfg, hipStream_t st, const KTimer& tm = KTimer{});
 template <typename T>
 hipError_t launch_field_diag(const Fields<T>& f, int N, double dt, int n, double* partials, int nblk_cap,
@@ -152,18 +153,25 @@ hipError_t launch_batch_field(const EventDesc* ev, const int2* map, int total_ti
 
 // ---- particle kernels (push.hip)
 // push at t_n: A holds U(n), phi(n), E(n-1/2), pi(n-1/2); B holds E(n+1/2), pi(n+1/2);
-// aux the field pieces of step n
+// the fields at a particle's cell are evaluated from them (cellfields.h)
+// (gpl: the plaquette field of step n, see launch_field_step)
 template <typename T>
-hipError_t launch_push(const Fields<T>& A, const Fields<T>& B, const T* aux, const Parts<T>& P, const PushArgs& a,
+hipError_t launch_push(const Fields<T>& A, const Fields<T>& B, const T* gpl, const Parts<T>& P, const PushArgs& a,
                        int* d_step, double* partials, int* err, hipStream_t st, const KTimer& tm = KTimer{});
 int push_blocks(int np, int tpp);
-// dense ensembles: the six field vectors of every site into table [48][V]
-// (force_table_kernel), then a push that reads them at the cell (one
-// wavefront per 64 particles); tm_table / tm_push time the two launches
+// the six field vectors of every site at t_n into table [48][V] (job order,
+// zero where a field is inactive at step n or, with electric_only, magnetic),
+// for steps sc.n_form <= n < sc.n_max
 template <typename T>
-hipError_t launch_push_table(const Fields<T>& A, const Fields<T>& B, const T* aux, T* table, const Parts<T>& P,
+hipError_t launch_force_table(const Fields<T>& A, const Fields<T>& B, const T* gpl, T* table, int N,
+                              const Schedule& sc, bool electric_only, const int* d_step, hipStream_t st,
+                              const KTimer& tm = KTimer{});
+// dense ensembles: a push that reads the fields at the cell from the force
+// table (one wavefront per 64 particles)
+template <typename T>
+hipError_t launch_push_table(const Fields<T>& A, const Fields<T>& B, const T* table, const Parts<T>& P,
                              const PushArgs& a, int* d_step, double* partials, int* err, hipStream_t st,
-                             const KTimer& tm_table = KTimer{}, const KTimer& tm_push = KTimer{});
+                             const KTimer& tm = KTimer{});
 template <typename T>
 hipError_t launch_batch_push(const EventDesc* ev, const int2* map, int total_blocks, int tpp, hipStream_t st);
 hipError_t launch_reduce_rows(const double* partials, int nrows, int ncols, double* out, hipStream_t st);
@@ -186,9 +194,10 @@ struct JetArgs {
     double x_off;  // start inside the cell, [0, 1)
     Schedule sc;   // n_form: first step of the paths; samples as for particles
 };
+// A holds U(n); table the force table of step n (launch_force_table)
 template <typename T>
-hipError_t launch_jets(const Fields<T>& A, const Fields<T>& B, const T* aux, T* W, T* F, const JetArgs& a,
-                       const int* d_step, double* partials, hipStream_t st, const KTimer& tm = KTimer{});
+hipError_t launch_jets(const Fields<T>& A, const T* table, T* W, T* F, const JetArgs& a, const int* d_step,
+                       double* partials, hipStream_t st, const KTimer& tm = KTimer{});
 // samples: partials[slot][group of 64 paths][4] (|F_x|^2, |F_y|^2, |F_z|^2, 0)
 __host__ __device__ inline int jet_groups(int V) { return (V + 63) / 64; }
 
@@ -209,7 +218,7 @@ struct SortBufs {
     int *vals = nullptr, *perm = nullptr;
     void* temp = nullptr;
     size_t temp_bytes = 0;
-    void* r2 = nullptr;  // [18][np] scratch records
+    void* r2 = nullptr;  // [19][np] scratch records
     int *cell2 = nullptr, *pid2 = nullptr;
 };
 size_t sort_temp_bytes(int np, int N);
@@ -234,7 +243,7 @@ struct PartICArgs {
     double pt_min, pt_max;
     double q0[8];
 };
-hipError_t ic_particles(const PartICArgs& a, double* r /*[18][np]*/, int* cell, hipStream_t st);
+hipError_t ic_particles(const PartICArgs& a, double* r /*[19][np]*/, int* cell, hipStream_t st);
 // SU(2) variant: links, pi(0) into a double Fields2 set; Darboux charges with |Q|^2 = q2
 hipError_t ic_glasma2(const ICArgs& a, Fields2<double> out, hipStream_t st);
 hipError_t ic_particles2(const PartICArgs& a, double q2, double* r, int* cell, hipStream_t st);

@@ -12,8 +12,9 @@
 //
 // Per step and path: W is multiplied by the crossed x link when the nearest
 // grid point moves (once per 1/dt steps), the five fields f needs are read
-// at the nearest grid point from U(n), pi(n+1/2) and the aux pieces of the
-// field update, transported with W and added to F.  On recording steps each
+// at the nearest grid point from the per-site force table of the step
+// (force_table_kernel: the fields of Sec. III.B at every site, zero where
+// they vanish at t_0), transported with W and added to F.  On recording steps each
 // wavefront writes the double-precision sum of |F_i|^2 over its 64 paths.
 #include "cellfields.h"
 #include "reduce.h"
@@ -36,8 +37,8 @@ __device__ __forceinline__ int path_offset(double x_off, int m, double dt)
 constexpr int kJetRoles = 3;
 
 template <typename T>
-__global__ __launch_bounds__(64 * kJetRoles) void jet_kernel(Fields<T> Af, Fields<T> Bf, const T* aux, T* Wb, T* Fb,
-                                                             JetArgs a, const int* d_step, double* partials)
+__global__ __launch_bounds__(64 * kJetRoles) void jet_kernel(Fields<T> Af, const T* table, T* Wb, T* Fb, JetArgs a,
+                                                             const int* d_step, double* partials)
 {
     const int N = a.N, V = N * N;
     const int ngroups = jet_groups(V);
@@ -57,8 +58,7 @@ __global__ __launch_bounds__(64 * kJetRoles) void jet_kernel(Fields<T> Af, Field
     const int q = live ? p : 0;
     const int y = q / N, i = q - y * N;
     const uint32_t po = (uint32_t)q * (uint32_t)sizeof(T);
-    const View<T> A = make_view<T>(Af.U, kRealsPerSite, V), B = make_view<T>(Bf.U, kRealsPerSite, V);
-    const View<T> X = make_view<T>(aux, kAuxReals, V);
+    const View<T> A = make_view<T>(Af.U, kRealsPerSite, V), TV = make_view<T>(table, 48, V);
     const View<T> WV = make_view<T>(Wb, 18, V), FV = make_view<T>(Fb, 24, V);
 
     m3<T> w;
@@ -93,24 +93,14 @@ __global__ __launch_bounds__(64 * kJetRoles) void jet_kernel(Fields<T> Af, Field
     a8<T> Fj = m == 0 ? azero<T>() : vA(FV, po, fc);
     if (eval) {
         const int x = (i + k % N) % N;
-        const Cell cell = make_cell<T>(x, y, N);
-        const T t = T(n * a.sc.dt);
-        a8<T> f = azero<T>();
-        if (role == 0) {
-            if (n > 0) f = job_field<T>(kJobEx, A, B, X, cell, n, t);             // f_x = E_x
-        } else if (role == 1) {
-            if (n > 0) f = job_field<T>(kJobEy, A, B, X, cell, n, t);             // f_y = E_y - B_eta
-            CPIC_PHASE();
-            const a8<T> beta = job_field<T>(kJobBeta, A, B, X, cell, n, t);
+        const uint32_t cs = (uint32_t)(y * N + x) * (uint32_t)sizeof(T);
+        // f_x = E_x, f_y = E_y - B_eta, f_z = E_eta + B_y (table slots in job order)
+        a8<T> f = vA(TV, cs, 8 * (uint32_t)(role == 0 ? kJobEx : (role == 1 ? kJobEy : kJobEeta)));
+        if (role > 0) {
+            const a8<T> g = vA(TV, cs, 8 * (uint32_t)(role == 1 ? kJobBeta : kJobBy));
+            const T sg = role == 1 ? T(-1) : T(1);
 #pragma unroll
-            for (int c = 0; c < 8; c++) f.v[c] -= beta.v[c];
-        } else {
-            f = job_field<T>(kJobEeta, A, B, X, cell, n, t);                      // f_z = E_eta + B_y
-            if (n > 0) {
-                const a8<T> by = job_field<T>(kJobBy, A, B, X, cell, n, t);
-#pragma unroll
-                for (int c = 0; c < 8; c++) f.v[c] += by.v[c];
-            }
+            for (int c = 0; c < 8; c++) f.v[c] += sg * g.v[c];
         }
         const a8<T> ft = transport(w, f);
         const T wgt = T(a.stride * a.sc.dt);
@@ -134,18 +124,18 @@ __global__ __launch_bounds__(64 * kJetRoles) void jet_kernel(Fields<T> Af, Field
 }
 
 template <typename T>
-hipError_t launch_jets(const Fields<T>& A, const Fields<T>& B, const T* aux, T* W, T* F, const JetArgs& a,
-                       const int* d_step, double* partials, hipStream_t st, const KTimer& tm)
+hipError_t launch_jets(const Fields<T>& A, const T* table, T* W, T* F, const JetArgs& a, const int* d_step,
+                       double* partials, hipStream_t st, const KTimer& tm)
 {
-    if (!aux || !W || !F || a.N <= 0 || a.stride < 1 || !(a.sc.dt > 0 && a.sc.dt <= 1)) return hipErrorInvalidValue;
+    if (!table || !W || !F || a.N <= 0 || a.stride < 1 || !(a.sc.dt > 0 && a.sc.dt <= 1)) return hipErrorInvalidValue;
     const int nb = jet_groups(a.N * a.N);
-    klaunch(tm, jet_kernel<T>, dim3(8 * ((nb + 7) / 8)), dim3(64 * kJetRoles), st, A, B, aux, W, F, a, d_step,
+    klaunch(tm, jet_kernel<T>, dim3(8 * ((nb + 7) / 8)), dim3(64 * kJetRoles), st, A, table, W, F, a, d_step,
             partials);
     return hipGetLastError();
 }
-template hipError_t launch_jets<double>(const Fields<double>&, const Fields<double>&, const double*, double*, double*,
-                                        const JetArgs&, const int*, double*, hipStream_t, const KTimer&);
-template hipError_t launch_jets<float>(const Fields<float>&, const Fields<float>&, const float*, float*, float*,
-                                       const JetArgs&, const int*, double*, hipStream_t, const KTimer&);
+template hipError_t launch_jets<double>(const Fields<double>&, const double*, double*, double*, const JetArgs&,
+                                        const int*, double*, hipStream_t, const KTimer&);
+template hipError_t launch_jets<float>(const Fields<float>&, const float*, float*, float*, const JetArgs&, const int*,
+                                       double*, hipStream_t, const KTimer&);
 
 }  // namespace cpic

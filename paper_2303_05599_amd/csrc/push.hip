@@ -103,85 +103,100 @@ template <typename T> __device__ a8<T> renorm_charge(const a8<T>& Q, const doubl
     return herm_comp(ent(0, 0), ent(1, 1), ent(2, 2), ent(0, 1), ent(0, 2), ent(1, 2));
 }
 
-// Six field jobs (cellfields.h).  The TPP waves that share a group of 64
-// particles split them; the owner wave (role 0) meanwhile rotates Q, and
-// contracts everything with Q at the end.
-// TPP 2, job -> (wave, LDS slot within the wave), 4 bits per job in job order:
-//   owner E_x E_eta B_x B_y | wave 1: E_y (slot 0), B_eta (slot 1)
-// TPP 4 (push_helper4): the owner only rotates Q; the helpers split the jobs
-// by the link they transport with, so that each issues all its gathers at
-// once and transports with at most two links:
-//   1: U_x(c-x): E_x, B_y, the clover leaf U_x(c-x)^+ G(c-x) U_x(c-x)
-//   2: U_y(c-y): E_y, B_x, the leaf U_y(c-y)^+ G(c-y) U_y(c-y)
-//   3: U_y(c-x-y), U_x(c-x): the leaf through c-x-y plus G(c), and E_eta
-// B_eta is the sum of the three waves' leaves (the transport is linear).
-// The helpers read their links as two rows (the third rebuilt), which saves
-// a third of the link gathers.
-constexpr uint32_t pack_jobs(int e_x, int e_y, int e_eta, int b_x, int b_y, int b_eta)
+// Sub-job placement.  The TPP waves that share a group of 64 particles split
+// the eight sub-jobs of the colour fields (cellfields.h); the owner wave
+// (role 0) meanwhile rotates Q and, after one barrier, contracts the helpers'
+// vectors with Q.  Byte k of the table places sub-job k as (wave << 4 | LDS
+// slot of that wave); wave 0 is the owner, which evaluates its sub-jobs
+// itself.  Sub-jobs share a slot only if they are parts of the same field
+// (B_eta).  Each helper takes one memory round trip per sub-job:
+//   TPP 1: the owner evaluates everything;
+//   TPP 2: wave 1 E_y (slot 0) and B_eta (slot 1), the owner the rest;
+//   TPP 4: the helpers split by the link they transport with:
+//          1: E_x, B_y and B_eta part 5 (U_x(c-x)); 2: E_y, B_x and part 6
+//          (U_y(c-y)); 3: part 7 (U_y(c-x-y) and U_x(c-x)) and E_eta;
+//   TPP 8: one sub-job per helper (E_eta beside part 6 in wave 6), in
+//          blocks of 512 threads.
+// The links are read as two rows (the third rebuilt).
+template <int TPP> __device__ __forceinline__ constexpr int subjob_place(int k)
 {
-    return (uint32_t)e_x | (uint32_t)e_y << 4 | (uint32_t)e_eta << 8 | (uint32_t)b_x << 12 | (uint32_t)b_y << 16 |
-           (uint32_t)b_eta << 20;
+    constexpr uint64_t tab = TPP == 8   ? 0x7060503040612010ull
+                             : TPP == 4 ? 0x3022121121312010ull
+                             : TPP == 2 ? 0x1111110000001000ull
+                                        : 0ull;
+    return (int)((tab >> (8 * k)) & 0xffu);
 }
-template <int TPP> __device__ __forceinline__ int job_wave(int j)
-{
-    constexpr uint32_t tab = TPP == 2 ? pack_jobs(0, 1, 0, 0, 0, 1) : 0;
-    return (int)((tab >> (4 * j)) & 15u);
-}
-template <int TPP> __device__ __forceinline__ int job_slot(int j)
-{
-    constexpr uint32_t tab = TPP == 2 ? pack_jobs(0, 0, 0, 0, 0, 1) : 0;
-    return (int)((tab >> (4 * j)) & 15u);
-}
-template <int TPP> constexpr int kSlots = TPP == 4 ? 3 : (TPP == 2 ? 2 : 1);  // LDS slots per helper wave
+template <int TPP> constexpr int kSlots = TPP == 4 ? 3 : 2;  // LDS slots per helper wave
 
-// The field vectors of helper wave `role` (1..3) of a four-wave group, for
-// slots 0..2 (zero where the job is inactive at step n).
+// A helper of a four-wave group (the placement of subjob_place<4>), with the
+// loads shared between its sub-jobs: role 1 (i = x) and 2 (i = y) first
+// gather U_i(c-i), E_i at c and c-i at both half steps and the plaquettes
+// they transport, and form E_i and their part of B_eta; then U_i(c) and phi
+// at c +- i for D_i, with U_i(c-i) kept.  Role 3 forms part 7 and E_eta in
+// one round trip.  The results go to the wave's LDS slots (rows r0 + 8 slot).
 template <typename T>
-__device__ __forceinline__ void push_helper4(int role, const View<T>& A, const View<T>& B, const View<T>& X,
-                                             const Cell& c, int n, T t, bool eonly, a8<T> (&F)[3])
+__device__ __forceinline__ void helper4(int role, const View<T>& A, const View<T>& B, const View<T>& Gv, const Cell& c,
+                                        int n, T t, bool eonly, T (*shF)[64], int r0, int lane, bool live)
 {
-    const T qe = T(1) / (T(4) * t), qb = T(1) / (T(2) * t);
     const bool on_e = n > 0, on_bt = n > 0 && !eonly, on_be = !eonly;
-    if (role == 3) {
-        const m3<T> Ly = vU(A, c.s_xmym, 1), Lx = vU(A, c.s_xm, 0);
-        const a8<T> g12 = vA(X, c.s_xmym, kAuxG), g0 = vA(X, c.s, kAuxG);
-        // E_eta from P (n > 0) or from pi(1/2) (n = 0), through one selected buffer
-        const bool first = n == 0;
-        const a8<T> Pv = vA(first ? B : X, c.s, first ? (uint32_t)kCompPi : (uint32_t)kAuxP);
-        const a8<T> leaf = transport_adj(Lx, transport_adj(Ly, g12));
-        const T h = first ? T(1) : T(0.5);
+    auto put = [&](int slot, const a8<T>& F) {
 #pragma unroll
-        for (int q = 0; q < 8; q++) {
-            F[0].v[q] = on_be ? T(-0.25) * (g0.v[q] + leaf.v[q]) : T(0);
-            F[1].v[q] = h * Pv.v[q];
-            F[2].v[q] = T(0);
-        }
+        for (int q = 0; q < 8; q++) shF[r0 + 8 * slot + q][lane] = live ? F.v[q] : T(0);
+    };
+    if (role == 3) {
+        a8<T> part = azero<T>();
+        if (on_be) part = subjob<T>(7, A, B, Gv, c, n, t);
+        put(0, part);
+        put(1, cell_Eeta<T>(A, B, c, n));
         return;
     }
-    // role 1: direction x, role 2: direction y
     const int i = role - 1;
-    const uint32_t sb = i == 0 ? c.s_xm : c.s_ym;
-    const uint32_t cs = i == 0 ? kAuxS1 : kAuxS2;
+    const uint32_t sb = i == 0 ? c.s_xm : c.s_ym, ce = kCompE + 8 * (uint32_t)i;
     const m3<T> L = vU(A, sb, i);
-    const a8<T> here = vA(X, c.s, cs), back = vA(X, sb, cs), gb = vA(X, sb, kAuxG);
-    const a8<T> D = vA(X, c.s, i == 0 ? kAuxDx : kAuxDy);
-    const a8<T> tb = transport_adj(L, back), tg = transport_adj(L, gb);
-    // B_y = +(1/2t) D_x, B_x = -(1/2t) D_y
-    const T qd = i == 0 ? qb : -qb;
+    a8<T> e = azero<T>(), part = azero<T>();
+    if (on_e) {
+        const a8<T> h0 = vA(A, c.s, ce), h1 = vA(B, c.s, ce), b0 = vA(A, sb, ce), b1 = vA(B, sb, ce);
+        a8<T> back;
 #pragma unroll
-    for (int q = 0; q < 8; q++) {
-        F[0].v[q] = on_e ? qe * (here.v[q] + tb.v[q]) : T(0);
-        F[1].v[q] = on_bt ? qd * D.v[q] : T(0);
-        F[2].v[q] = on_be ? T(-0.25) * tg.v[q] : T(0);
+        for (int q = 0; q < 8; q++) back.v[q] = b0.v[q] + b1.v[q];
+        const a8<T> tb = transport_adj(L, back);
+        const T w = T(1) / (T(4) * t);
+#pragma unroll
+        for (int q = 0; q < 8; q++) e.v[q] = w * ((h0.v[q] + h1.v[q]) + tb.v[q]);
     }
+    if (on_be) {
+        part = transport_adj(L, vA(Gv, sb, 0));
+        if (i == 0) {
+            const a8<T> g0 = vA(Gv, c.s, 0);
+#pragma unroll
+            for (int q = 0; q < 8; q++) part.v[q] += g0.v[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; q++) part.v[q] *= T(-0.25);
+    }
+    put(0, e);
+    put(2, part);
+    CPIC_PHASE();
+    a8<T> bf = azero<T>();
+    if (on_bt) {
+        // B_y = +(1/2t) D_x (role 1), B_x = -(1/2t) D_y (role 2)
+        const a8<T> f = transport(vU(A, c.s, i), vA(A, i == 0 ? c.s_xp : c.s_yp, kCompPhi));
+        const a8<T> b = transport_adj(L, vA(A, sb, kCompPhi));
+        const T sc = (i == 0 ? T(1) : T(-1)) / (T(2) * t);
+#pragma unroll
+        for (int q = 0; q < 8; q++) bf.v[q] = sc * (f.v[q] - b.v[q]);
+    }
+    put(1, bf);
 }
+__host__ __device__ constexpr int push_block_threads(int tpp) { return tpp == 8 ? 512 : 256; }
 
-// TPP wavefronts per group of 64 particles: a block of 256 threads holds
-// 256 / TPP particles.  Wave w works on particle group w / TPP in role
-// w % TPP, so every wave follows one uniform path.  The role-0 wave owns the particle state: it
-// rotates Q while the helper waves evaluate their field vectors into LDS; after
-// one barrier it contracts all of them with Q and takes the Euler step.
-template <int TPP> constexpr int kPushPPB = 256 / TPP;  // particles per block
+// TPP wavefronts per group of 64 particles: a block holds 256 / TPP particles
+// (64 for TPP 8).  Wave w works on particle group w / TPP in role w % TPP, so
+// every wave follows one uniform path.  The role-0 wave owns the particle
+// state: it rotates Q while the helper waves evaluate their field vectors
+// into LDS; after one barrier it contracts all of them with Q and takes the
+// Euler step.
+template <int TPP> constexpr int kPushPPB = push_block_threads(TPP) / TPP;  // particles per block
 
 // Observables: on recording steps the owner wave of each group of 64 writes
 // the group's four double-precision sums to partials[slot][group][4]; they
@@ -200,7 +215,7 @@ template <int TPP> constexpr int kPushPPB = 256 / TPP;  // particles per block
 // table of this step (force_table_kernel) instead of evaluating them: the
 // choice for dense ensembles, where several particles share a cell.
 template <typename T, int TPP, bool LOGQ, bool TABLE = false>
-__device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& Bf, const T* aux, const Parts<T>& P,
+__device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& Bf, const T* gpl, const Parts<T>& P,
                                           const PushArgs& a, int n, double* partials, int* err, int blk,
                                           const T* table = nullptr)
 {
@@ -216,7 +231,7 @@ __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& 
     const int N = a.N, np = a.np;
     const uint32_t V = (uint32_t)N * N;
     const View<T> A = make_view<T>(Af.U, kRealsPerSite, V), B = make_view<T>(Bf.U, kRealsPerSite, V);
-    const View<T> X = make_view<T>(aux, kAuxReals, V);
+    const View<T> Gv = make_view<T>(gpl, kPlaqReals, V);
     const View<T> R = make_view<T>(P.r, kPartReals, (uint32_t)np);
     const View<int> C = make_view<int>(P.cell, 2, (uint32_t)np);
     const T dt = T(a.sc.dt), t = T(n * a.sc.dt);
@@ -241,7 +256,7 @@ __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& 
     const Cell cell = make_cell<T>(nx, ny, N);
     a8<T> Q;
     T f[6] = {0, 0, 0, 0, 0, 0};
-    T px = 0, py = 0, pe = 0, eta = 0;
+    T px = 0, py = 0, pe = 0, eta = 0, pt_ode = 0;
     if (role == 0) {
 #pragma unroll
         for (int q = 0; q < 8; q++) Q.v[q] = bld(R, po, PQ0 + q);
@@ -249,6 +264,7 @@ __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& 
         py = bld(R, po, PPY);
         pe = bld(R, po, PPETA);
         eta = bld(R, po, PETA_);
+        if (!a.is_static) pt_ode = bld(R, po, PPTAU);
         if (!LOGQ && !a.is_static && live && n > a.sc.n_form) {
             // the links crossed since the last step (x first, then y from the
             // new column) and the scalar at the cell, gathered together
@@ -259,14 +275,24 @@ __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& 
             dy = dy > N / 2 ? dy - N : (dy < -N / 2 ? dy + N : dy);
             if (dx < -1 || dx > 1) atomicAdd(err, 1);
             if (dy < -1 || dy > 1) atomicAdd(err, 1);
+            // (with eight waves per group the owner has time to spare: it
+            // takes the links one at a time, which keeps its registers low)
             m3<T> Lx, Ly;
             if (dx != 0) Lx = vU(A, (uint32_t)(cy * N + (dx > 0 ? cx : wrap(cx - 1, N))) * (uint32_t)sizeof(T), 0);
+            if (TPP == 8) {
+                if (dx == 1) Q = rotate(Lx, Q);
+                else if (dx == -1) Q = transport(Lx, Q);
+                CPIC_PHASE();
+            }
             if (dy != 0) Ly = vU(A, (uint32_t)((dy > 0 ? cy : wrap(cy - 1, N)) * N + nx) * (uint32_t)sizeof(T), 1);
             const a8<T> ph = vA(A, cell.s, kCompPhi);
-            if (dx == 1) Q = rotate(Lx, Q);
-            else if (dx == -1) Q = transport(Lx, Q);  // U Q U^+
+            if (TPP != 8) {
+                if (dx == 1) Q = rotate(Lx, Q);
+                else if (dx == -1) Q = transport(Lx, Q);  // U Q U^+
+            }
             if (dy == 1) Q = rotate(Ly, Q);
             else if (dy == -1) Q = transport(Ly, Q);
+            if (TPP == 8) CPIC_PHASE();
             if (deta != T(0)) Q = rotate(expi(ph, deta), Q);
         }
         // charges are renormalised in single precision only (double-precision
@@ -275,8 +301,6 @@ __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& 
         if constexpr (sizeof(T) == 4 && !LOGQ)
             if (!a.is_static && renorm && live) Q = renorm_charge(Q, a.q0eig);
         CPIC_PHASE();
-        // one or two waves: the owner evaluates its share of the jobs (with
-        // four, the helpers evaluate all of them)
         if (TABLE && live) {
             // all six table vectors gathered at once (one memory round trip)
             const View<T> TV = make_view<T>(table, 48, V);
@@ -285,75 +309,59 @@ __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& 
             for (int j = 0; j < kJobs; j++) tv[j] = vA(TV, cell.s, 8 * (uint32_t)j);
 #pragma unroll
             for (int j = 0; j < kJobs; j++) f[j] += job_active(j, n, eonly) ? dot(Q, tv[j]) : T(0);
-        } else if (TPP != 4 && live) {
+        } else if constexpr (!TABLE && TPP <= 2) {
+            // the owner's own sub-jobs (one or two waves per group)
+            if (live) {
 #pragma unroll 1
-            for (int j = 0; j < kJobs; j++) {
-                if (job_wave<TPP>(j) != 0 || !job_active(j, n, eonly)) continue;
-                const T dq = dot(Q, job_field<T>(j, A, B, X, cell, n, t));
-                const int k = j;  // job j yields force component j
+                for (int k = 0; k < kSubJobs; k++) {
+                    if ((subjob_place<TPP>(k) >> 4) != 0 || !subjob_active(k, n, eonly)) continue;
+                    CPIC_PHASE();
+                    const T dq = dot(Q, subjob<T>(k, A, B, Gv, cell, n, t));
+                    const int j = subjob_field(k);
 #pragma unroll
-                for (int kk = 0; kk < 6; kk++) f[kk] += kk == k ? dq : T(0);
+                    for (int jj = 0; jj < kJobs; jj++) f[jj] += jj == j ? dq : T(0);
+                }
             }
         }
     } else if (TPP == 4) {
-        const int row0 = (grp * (TPP - 1) + role - 1) * S * 8;
-        a8<T> F[3];
-        push_helper4<T>(role, A, B, X, cell, n, t, eonly, F);
-#pragma unroll
-        for (int k = 0; k < 3; k++)
-#pragma unroll
-            for (int q = 0; q < 8; q++) shF[row0 + 8 * k + q][lane] = live ? F[k].v[q] : T(0);
+        helper4<T>(role, A, B, Gv, cell, n, t, eonly, shF, (grp * (TPP - 1) + role - 1) * S * 8, lane, live);
     } else if (TPP > 1) {
+        // a helper wave: its sub-jobs, accumulated into its LDS slots (the
+        // loop is unrolled, so each sub-job's code is specialised; with eight
+        // waves a helper's one or two sub-jobs share one round trip)
         const int row0 = (grp * (TPP - 1) + role - 1) * S * 8;
 #pragma unroll
         for (int r = 0; r < S * 8; r++) shF[row0 + r][lane] = T(0);
-        if (live) {
-#pragma unroll 1
-            for (int j = 0; j < kJobs; j++) {
-                if (job_wave<TPP>(j) != role || !job_active(j, n, eonly)) continue;
-                const a8<T> F = job_field<T>(j, A, B, X, cell, n, t);
-                const int r = row0 + job_slot<TPP>(j) * 8;
 #pragma unroll
-                for (int q = 0; q < 8; q++) shF[r + q][lane] += F.v[q];
-            }
+        for (int k = 0; k < kSubJobs; k++) {
+            const int pl = subjob_place<TPP>(k);
+            if ((pl >> 4) != role || !subjob_active(k, n, eonly)) continue;
+            if (TPP < 8) CPIC_PHASE();
+            const a8<T> F = subjob<T>(k, A, B, Gv, cell, n, t);
+            const int r = row0 + (pl & 15) * 8;
+#pragma unroll
+            for (int q = 0; q < 8; q++) shF[r + q][lane] += live ? F.v[q] : T(0);
         }
     }
-    if (TPP == 4) {
+    if (TPP > 1) {
         __syncthreads();
         if (role == 0 && live) {
-            // Q . (vector in helper wave w, slot k)
-            auto qdot = [&](int w, int k) {
-                const int r = ((grp * (TPP - 1) + w - 1) * S + k) * 8;
-                T dq = Q.v[0] * shF[r][lane];
+            // Q . (vector of each helper slot), each slot counted once
 #pragma unroll
-                for (int q = 1; q < 8; q++) dq = fmaT(Q.v[q], shF[r + q][lane], dq);
-                return dq;
-            };
-            f[kJobEx] = qdot(1, 0);
-            f[kJobBy] = qdot(1, 1);
-            f[kJobEy] = qdot(2, 0);
-            f[kJobBx] = qdot(2, 1);
-            f[kJobEeta] = qdot(3, 1);
-            f[kJobBeta] = qdot(3, 0) + qdot(1, 2) + qdot(2, 2);
-        }
-    } else if (TPP > 1) {
-        __syncthreads();
-        if (role == 0 && live) {
+            for (int k = 0; k < kSubJobs; k++) {
+                const int pl = subjob_place<TPP>(k);
+                bool first = (pl >> 4) != 0;
 #pragma unroll
-            for (int j = 0; j < kJobs; j++) {
-                const int w = job_wave<TPP>(j);
-                bool first = w != 0;  // the first job of each helper (wave, slot) stands for the slot
-#pragma unroll
-                for (int i = 0; i < j; i++)
-                    if (job_wave<TPP>(i) == w && job_slot<TPP>(i) == job_slot<TPP>(j)) first = false;
+                for (int i = 0; i < k; i++)
+                    if (subjob_place<TPP>(i) == pl) first = false;
                 if (!first) continue;
-                const int r = ((grp * (TPP - 1) + w - 1) * S + job_slot<TPP>(j)) * 8;
+                const int r = ((grp * (TPP - 1) + (pl >> 4) - 1) * S + (pl & 15)) * 8;
                 T dq = Q.v[0] * shF[r][lane];
 #pragma unroll
                 for (int q = 1; q < 8; q++) dq = fmaT(Q.v[q], shF[r + q][lane], dq);
-                const int k = j;  // job j yields force component j
+                const int j = subjob_field(k);
 #pragma unroll
-                for (int kk = 0; kk < 6; kk++) f[kk] += kk == k ? dq : T(0);
+                for (int jj = 0; jj < kJobs; jj++) f[jj] += jj == j ? dq : T(0);
             }
         }
     }
@@ -372,6 +380,11 @@ __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& 
             const T npx = px + dt * (e1 + be * v2 - b2 * vl);
             const T npy = py + dt * (e2 - be * v1 + b1 * vl);
             const T npe = n > 0 ? pe + dt * (ee - b1 * v2 + b2 * v1 - T(2) * pe) / t : pe;
+            // p^tau from its own equation of motion [eq:ptaueq] (Euler, with the
+            // integrated value on the right-hand side), started from the
+            // constraint at the formation step
+            const T pt = n == a.sc.n_form ? ptau : pt_ode;
+            const T npt = pt + dt * (ee * t * pe + e1 * px + e2 * py - t * pe * pe) / pt;
             if constexpr (LOGQ) {
                 // Q_{n+1} = Q_n + dt i[Q_n, M_n]
                 CPIC_PHASE();
@@ -396,6 +409,7 @@ __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& 
             px = npx; py = npy; pe = npe;
             bst(R, po, PX_, xn); bst(R, po, PY_, yn); bst(R, po, PETA_, eta);
             bst(R, po, PPX, px); bst(R, po, PPY, py); bst(R, po, PPETA, pe); bst(R, po, PDETA, deta);
+            bst(R, po, PPTAU, npt);
             bst_i(C, pi, 0, nx);
             bst_i(C, pi, 1, ny);
             if (LOGQ || n > a.sc.n_form || renorm) {
@@ -444,18 +458,19 @@ __device__ __forceinline__ int push_step(int* d_step, int blk)
     return n;
 }
 
-// at most 168 VGPRs (three waves per SIMD): the double-precision four-wave
-// push otherwise takes 170 and drops to two; the logarithm variant keeps the
-// compiler's choice (it would spill)
+// At least three waves per SIMD (at most 168 VGPRs) for blocks of 256
+// threads, four (128 VGPRs: two blocks per CU) for the 512-thread blocks of
+// eight waves per group; the logarithm variant keeps the compiler's choice
+// (it would spill).
 template <typename T, int TPP, bool LOGQ = false>
-__global__ __launch_bounds__(256, LOGQ ? 1 : 3) void push_kernel(Fields<T> Af, Fields<T> Bf, const T* aux, Parts<T> P, PushArgs a,
-                                                   int* d_step, double* partials, int* err)
+__global__ __launch_bounds__(push_block_threads(TPP), LOGQ ? 1 : (TPP == 8 ? 4 : 3)) void push_kernel(
+    Fields<T> Af, Fields<T> Bf, const T* gpl, Parts<T> P, PushArgs a, int* d_step, double* partials, int* err)
 {
     const int nblocks = (a.np + kPushPPB<TPP> - 1) / kPushPPB<TPP>;
     const int blk = xcd_block(nblocks);
     if (blk >= nblocks) return;
     const int n = push_step(d_step, blk);
-    push_body<T, TPP, LOGQ>(Af, Bf, aux, P, a, n, partials, err, blk);
+    push_body<T, TPP, LOGQ>(Af, Bf, gpl, P, a, n, partials, err, blk);
 }
 
 // one wavefront per group of 64 particles, fields from the force table
@@ -473,9 +488,10 @@ __global__ __launch_bounds__(256) void push_table_kernel(Fields<T> Af, Fields<T>
 // The six field vectors (E_x, E_y, E_eta, B_x, B_y, B_eta, 8 components
 // each, [48][V]) at every site at t_n, from the same per-site arithmetic
 // the push applies at a particle's cell.  Runs between the field update
-// (which provides n in d_step[1]) and the table push.
+// (which provides n in d_step[1]) and the table push or the light-like
+// paths, which read the table at their cells.
 template <typename T>
-__global__ __launch_bounds__(256) void force_table_kernel(Fields<T> Af, Fields<T> Bf, const T* aux, T* table, int N,
+__global__ __launch_bounds__(256) void force_table_kernel(Fields<T> Af, Fields<T> Bf, const T* gpl, T* table, int N,
                                                           Schedule sc, bool electric_only, const int* d_step)
 {
     const int V = N * N, nb = (V + 255) / 256;
@@ -486,13 +502,13 @@ __global__ __launch_bounds__(256) void force_table_kernel(Fields<T> Af, Fields<T
     const int s = blk * 256 + (int)threadIdx.x;
     if (s >= V) return;
     const View<T> A = make_view<T>(Af.U, kRealsPerSite, V), B = make_view<T>(Bf.U, kRealsPerSite, V);
-    const View<T> X = make_view<T>(aux, kAuxReals, V), TB = make_view<T>(table, 48, V);
+    const View<T> TB = make_view<T>(table, 48, V), Gv = make_view<T>(gpl, kPlaqReals, V);
     const Cell cell = make_cell<T>(s % N, s / N, N);
     const T t = T(n * sc.dt);
 #pragma unroll 1
     for (int j = 0; j < kJobs; j++) {
         a8<T> F = azero<T>();
-        if (job_active(j, n, electric_only)) F = job_field<T>(j, A, B, X, cell, n, t);
+        if (job_active(j, n, electric_only)) F = job_field<T>(j, A, B, Gv, cell, n, t);
         vA_st(TB, (uint32_t)s * (uint32_t)sizeof(T), 8 * (uint32_t)j, F);
         CPIC_PHASE();
     }
@@ -513,8 +529,9 @@ __global__ __launch_bounds__(256, 3) void batch_push_kernel(const EventDesc* __r
     const int n = __builtin_amdgcn_readfirstlane(push_step(d.d_step, blk));
     if (d.pa.np == 0) return;  // an event without particles only advances its step
     const int V = d.N * d.N, parity = (n & 1) ^ d.flip;
-    push_body<T, TPP, false>(fields_at<T>(d.f[parity], V), fields_at<T>(d.f[parity ^ 1], V), static_cast<const T*>(d.aux),
-                      Parts<T>{static_cast<T*>(d.pr), d.cell}, d.pa, n, d.partials, d.d_err, blk);
+    push_body<T, TPP, false>(fields_at<T>(d.f[parity], V), fields_at<T>(d.f[parity ^ 1], V),
+                             static_cast<const T*>(d.gpl), Parts<T>{static_cast<T*>(d.pr), d.cell}, d.pa, n,
+                             d.partials, d.d_err, blk);
 }
 
 template <typename T>
@@ -535,48 +552,64 @@ template hipError_t launch_batch_push<float>(const EventDesc*, const int2*, int,
 int push_blocks(int np, int tpp) { return push_blocks_d(np, tpp); }
 
 template <typename T>
-hipError_t launch_push_table(const Fields<T>& A, const Fields<T>& B, const T* aux, T* table, const Parts<T>& P,
-                             const PushArgs& a, int* d_step, double* partials, int* err, hipStream_t st,
-                             const KTimer& tm_table, const KTimer& tm_push)
+hipError_t launch_force_table(const Fields<T>& A, const Fields<T>& B, const T* gpl, T* table, int N,
+                              const Schedule& sc, bool electric_only, const int* d_step, hipStream_t st,
+                              const KTimer& tm)
 {
-    if (a.np <= 0) return hipSuccess;
-    if (!aux || !table) return hipErrorInvalidValue;
-    const int nbt = (a.N * a.N + 255) / 256;
-    klaunch(tm_table, force_table_kernel<T>, dim3(8 * ((nbt + 7) / 8)), dim3(256), st, A, B, aux, table, a.N, a.sc,
-            a.is_static != 0, (const int*)d_step);
-    const int nb = (a.np + 255) / 256;
-    klaunch(tm_push, push_table_kernel<T>, dim3(8 * ((nb + 7) / 8)), dim3(256), st, A, B, (const T*)table, P, a,
-            d_step, partials, err);
+    if (!table || !gpl || N <= 0) return hipErrorInvalidValue;
+    const int nbt = (N * N + 255) / 256;
+    klaunch(tm, force_table_kernel<T>, dim3(8 * ((nbt + 7) / 8)), dim3(256), st, A, B, gpl, table, N, sc,
+            electric_only, d_step);
     return hipGetLastError();
 }
-template hipError_t launch_push_table<double>(const Fields<double>&, const Fields<double>&, const double*, double*,
-                                              const Parts<double>&, const PushArgs&, int*, double*, int*, hipStream_t,
-                                              const KTimer&, const KTimer&);
-template hipError_t launch_push_table<float>(const Fields<float>&, const Fields<float>&, const float*, float*,
-                                             const Parts<float>&, const PushArgs&, int*, double*, int*, hipStream_t,
-                                             const KTimer&, const KTimer&);
+template hipError_t launch_force_table<double>(const Fields<double>&, const Fields<double>&, const double*, double*,
+                                               int, const Schedule&, bool, const int*, hipStream_t, const KTimer&);
+template hipError_t launch_force_table<float>(const Fields<float>&, const Fields<float>&, const float*, float*, int,
+                                              const Schedule&, bool, const int*, hipStream_t, const KTimer&);
 
 template <typename T>
-hipError_t launch_push(const Fields<T>& A, const Fields<T>& B, const T* aux, const Parts<T>& P, const PushArgs& a,
+hipError_t launch_push_table(const Fields<T>& A, const Fields<T>& B, const T* table, const Parts<T>& P,
+                             const PushArgs& a, int* d_step, double* partials, int* err, hipStream_t st,
+                             const KTimer& tm)
+{
+    if (a.np <= 0) return hipSuccess;
+    if (!table) return hipErrorInvalidValue;
+    const int nb = (a.np + 255) / 256;
+    klaunch(tm, push_table_kernel<T>, dim3(8 * ((nb + 7) / 8)), dim3(256), st, A, B, table, P, a, d_step, partials,
+            err);
+    return hipGetLastError();
+}
+template hipError_t launch_push_table<double>(const Fields<double>&, const Fields<double>&, const double*,
+                                              const Parts<double>&, const PushArgs&, int*, double*, int*, hipStream_t,
+                                              const KTimer&);
+template hipError_t launch_push_table<float>(const Fields<float>&, const Fields<float>&, const float*,
+                                             const Parts<float>&, const PushArgs&, int*, double*, int*, hipStream_t,
+                                             const KTimer&);
+
+template <typename T, bool LOGQ>
+static void launch_push_t(const Fields<T>& A, const Fields<T>& B, const T* gpl, const Parts<T>& P, const PushArgs& a,
+                          int* d_step, double* partials, int* err, hipStream_t st, const KTimer& tm)
+{
+    const int nb = push_blocks(a.np, a.tpp);
+    const dim3 g(8 * ((nb + 7) / 8)), b(push_block_threads(a.tpp));
+    switch (a.tpp) {
+    case 2: klaunch(tm, push_kernel<T, 2, LOGQ>, g, b, st, A, B, gpl, P, a, d_step, partials, err); break;
+    case 4: klaunch(tm, push_kernel<T, 4, LOGQ>, g, b, st, A, B, gpl, P, a, d_step, partials, err); break;
+    case 8: klaunch(tm, push_kernel<T, 8, LOGQ>, g, b, st, A, B, gpl, P, a, d_step, partials, err); break;
+    default: klaunch(tm, push_kernel<T, 1, LOGQ>, g, b, st, A, B, gpl, P, a, d_step, partials, err);
+    }
+}
+
+template <typename T>
+hipError_t launch_push(const Fields<T>& A, const Fields<T>& B, const T* gpl, const Parts<T>& P, const PushArgs& a,
                        int* d_step, double* partials, int* err, hipStream_t st, const KTimer& tm)
 {
     if (a.np <= 0) return hipSuccess;
-    if (!aux) return hipErrorInvalidValue;
-    const int nb = push_blocks(a.np, a.tpp);
-    const dim3 g(8 * ((nb + 7) / 8)), b(256);
-    if (a.color_log) {
-        switch (a.tpp) {
-        case 2: klaunch(tm, push_kernel<T, 2, true>, g, b, st, A, B, aux, P, a, d_step, partials, err); break;
-        case 4: klaunch(tm, push_kernel<T, 4, true>, g, b, st, A, B, aux, P, a, d_step, partials, err); break;
-        default: klaunch(tm, push_kernel<T, 1, true>, g, b, st, A, B, aux, P, a, d_step, partials, err);
-        }
-        return hipGetLastError();
-    }
-    switch (a.tpp) {
-    case 2: klaunch(tm, push_kernel<T, 2>, g, b, st, A, B, aux, P, a, d_step, partials, err); break;
-    case 4: klaunch(tm, push_kernel<T, 4>, g, b, st, A, B, aux, P, a, d_step, partials, err); break;
-    default: klaunch(tm, push_kernel<T, 1>, g, b, st, A, B, aux, P, a, d_step, partials, err);
-    }
+    if (!gpl) return hipErrorInvalidValue;
+    if (a.color_log)
+        launch_push_t<T, true>(A, B, gpl, P, a, d_step, partials, err, st, tm);
+    else
+        launch_push_t<T, false>(A, B, gpl, P, a, d_step, partials, err, st, tm);
     return hipGetLastError();
 }
 

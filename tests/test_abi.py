@@ -50,8 +50,8 @@ def test_parameter_validation_needs_no_gpu():
             cp.Context(bad, None, stream=None)
         assert e.value.status == -1
     # particle records are addressed with 32-bit offsets: the count is bounded
-    # so that they stay below 2 GiB (18 reals per particle)
-    for prec, limit in ((cp.FP64, 2**31 // 144), (cp.FP32, 2**31 // 72)):
+    # so that they stay below 2 GiB (19 reals per particle)
+    for prec, limit in ((cp.FP64, 2**31 // 152), (cp.FP32, 2**31 // 76)):
         for n in (limit + 1, 2**40, -1):
             with pytest.raises(cp.CpicError) as e:
                 cp.Context(dict(N=32, precision=prec), dict(n=n, mass_GeV=1.0), stream=None)

@@ -24,7 +24,7 @@ def make_runs(tmp_path):
     copy_kib = (256 << 20) / 1024
     write_counters(tmp_path / "cf", "FETCH_SIZE", [(1, "copy_kernel", copy_kib / 2)])   # reads half: factor 2
     write_counters(tmp_path / "cw", "WRITE_SIZE", [(1, "copy_kernel", copy_kib)])
-    a, b = "field_ctile_kernel<double, true, 64, 8, 2>", "field_ctile_kernel<double, true, 64, 4, 2>"
+    a, b = "field_ctile_kernel<double, 64, 8, 2>", "field_ctile_kernel<double, 64, 4, 2>"
     # run 1: 64x8 throughout (40 dispatches); run 2: 64x8 for a 20-dispatch warm-up, then 64x4
     for c, scale in (("FETCH_SIZE", 1.0), ("WRITE_SIZE", 2.0)):
         r1 = [(i, a, scale * (100.0 if i >= 24 else 1.0)) for i in range(40)]
@@ -71,15 +71,30 @@ def test_rooflines_attach_traffic_by_kernel_name(tmp_path, monkeypatch):
     V = 512 * 512
     k = bench.rooflines(res, "fp64", 10**5, V)
     f = k["field"]
-    assert f["kernel"] == "field_ctile_kernel<double, true, 64, 8, 2>"
+    assert f["kernel"] == "field_ctile_kernel<double, 64, 8, 2>"
     assert f["traffic"] == pytest.approx(100 * 1024 * 2 + 200 * 1024)
     assert f["traffic_read"] == pytest.approx(100 * 1024 * 2) and f["traffic_written"] == pytest.approx(200 * 1024)
-    assert f["bytes_per_unit"] == 1472 and f["bytes_per_unit_two_row_links"] == 1280
-    assert f["frac"] == pytest.approx(1472 * V / 75e-6 / 8e12)
-    assert f["frac_two_row_links"] == pytest.approx(1280 * V / 75e-6 / 8e12)
+    # a site-update is priced at 68 reals read and written (full links), the
+    # two-row figure (56 + 56 reals) beside it
+    assert f["bytes_per_unit"] == 1088 and f["bytes_per_unit_two_row_links"] == 896
+    assert f["frac"] == pytest.approx(1088 * V / 75e-6 / 8e12)
+    assert f["frac_two_row_links"] == pytest.approx(896 * V / 75e-6 / 8e12)
     assert k["push"]["traffic"] == pytest.approx(7 * 1024 * 2 + 14 * 1024)
     # another tile than the one counted, or a two-kernel push not counted: no traffic
     res["launch"].update(by=4, push_mode="table")
     k = bench.rooflines(res, "fp64", 10**5, V)
     assert k["field"]["traffic"] is None and k["push"]["traffic"] is None
     assert k["push"]["kernel"] == "force_table_kernel<double> + push_table_kernel<double>"
+
+
+def test_step_plan_reaches_formation_and_fits_the_run():
+    # the driver's short run: the warm-up is extended past the formation step
+    w, kt = bench.plan_steps(20, 5, 69)
+    assert w == 70 and kt == 128
+    assert w + kt + 48 + 20 <= 1024
+    w, kt = bench.plan_steps(512, 96, 69)
+    assert w == 96 and w + kt + 48 + 512 <= 1024
+    assert bench.formation_step(bench.charm()) == 69
+    assert bench.formation_step(bench.jet_quarks()) == 0
+    with pytest.raises(SystemExit):
+        bench.plan_steps(1000, 5, 69)

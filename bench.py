@@ -149,6 +149,11 @@ def run_event(precision, steps, warmup, tune=True, particles=None, jets=False, n
     n = ctx.n
     ctx.evolve(((n // SORT_EVERY + 2) * SORT_EVERY) * DTAU_FM * (1 - 1e-12))
     ctx.step((SORT_EVERY - 4 - ctx.n % SORT_EVERY) % SORT_EVERY)
+    # the samples taken so far are summed now, so that the readout in the
+    # timed region reduces only the samples of the timed steps
+    ctx.observables()
+    if jets:
+        ctx.jet_observables()
     ctx.sync()
     untimed = ctx.n
     # timed region: the production path and the readout of the samples
@@ -156,10 +161,10 @@ def run_event(precision, steps, warmup, tune=True, particles=None, jets=False, n
     t0 = time.perf_counter()
     ctx.evolve((ctx.n + steps) * DTAU_FM * (1 - 1e-12))
     obs = ctx.observables()
+    jobs = ctx.jet_observables() if jets else None
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     d = ctx.diagnostics()
-    jobs = ctx.jet_observables() if jets else None
     ctx.close()
     return dict(wall=wall, t_ic=t_ic, timing=tm, diag=d, obs=obs, jet_obs=jobs, eager_ms_per_step=eager_ms,
                 kernel_timing_steps=n_kt, launch=launch, tune_report=tune_report, untimed_steps=untimed,

@@ -101,7 +101,8 @@ def plan_steps(steps, warmup, n_form, n_max=1024):
     return w, min(128, spare)
 
 
-def run_event(precision, steps, warmup, tune=True, particles=None, jets=False, n_colors=3, fixed=None, nt=None):
+def run_event(precision, steps, warmup, tune=True, particles=None, jets=False, n_colors=3, fixed=None, nt=None,
+              push=None):
     """One 512^2 event: IC (timed separately), warm-up steps at least to the
     first push step, the launch tuner, a kernel-timing stretch (eager launches
     with HIP events attached to each kernel: the per-kernel times of the
@@ -116,6 +117,8 @@ def run_event(precision, steps, warmup, tune=True, particles=None, jets=False, n
     ctx = cp.Context(glasma_512(precision, n_colors=n_colors), p)
     if jets:
         ctx.enable_jets(x_offset=0.3)
+    if push is not None:
+        ctx.set_push_mode(cp.PUSH_TILE if push == "tile" else cp.PUSH_GATHER)
     t0 = time.perf_counter()
     ctx.init_mv()
     t_ic = time.perf_counter() - t0
@@ -131,7 +134,7 @@ def run_event(precision, steps, warmup, tune=True, particles=None, jets=False, n
         ctx.set_store_policy(nt)
     launch = ctx.get_launch()
     launch["logq"] = p.get("color_update", 0) == cp.COLOR_LOG
-    launch["push_mode"] = "table" if ctx.push_mode() == cp.PUSH_TABLE else "gather"
+    launch["push_mode"] = {cp.PUSH_TABLE: "table", cp.PUSH_TILE: "tile"}.get(ctx.push_mode(), "gather")
     # kernel timing (eager launches); not the headline rate
     ctx.set_timing(True)
     torch.cuda.synchronize()
@@ -419,6 +422,10 @@ def read_pmc_summary(path):
 def kernel_names(launch, precision):
     t = "double" if precision == "fp64" else "float"
     v = launch["variant"]
+    if v == 4:
+        cp = 2 if launch.get("nt_store") else 0
+        return (f"fused_kernel<{t}, {launch['bx']}, {launch['by']}, {cp}>", f"straggler_kernel<{t}>",
+                f"jet_kernel<{t}>")
     if v == 3:
         cp = 2 if launch.get("nt_store") else 0
         field = f"field_ctile_kernel<{t}, {launch['bx']}, {launch['by']}, {cp}>"
@@ -445,8 +452,18 @@ def rooflines(res, precision, n_part, V, pmc_workload=None):
     push_s = tm["push_ms"] / max(tm["n_push"], 1) * 1e-3
     fname, pname, jname = kernel_names(res["launch"], precision)
     out = {}
-    entries = [("field", fname, field_s, SITE_BYTES[dt], V, "site-update"),
-               ("push", pname, push_s, PUSH_BYTES[dt], n_part, "particle-push")]
+    if res["launch"]["variant"] == 4:
+        # the fused step: the tile kernel updates every site and pushes the
+        # particles still in their tile; the straggler kernel pushes the rest
+        # (counted on the device over the timed launches)
+        strag = tm["straggler_pushes"] / max(tm["n_push"], 1)
+        entries = [("fused", fname, field_s, SITE_BYTES[dt] * V + PUSH_BYTES[dt] * (n_part - strag), 1,
+                    f"step ({V} site-updates at {SITE_BYTES[dt]} B + {n_part - strag:.0f} particle-pushes at "
+                    f"{PUSH_BYTES[dt]} B)"),
+                   ("stragglers", pname, push_s, PUSH_BYTES[dt], strag, "particle-push")]
+    else:
+        entries = [("field", fname, field_s, SITE_BYTES[dt], V, "site-update"),
+                   ("push", pname, push_s, PUSH_BYTES[dt], n_part, "particle-push")]
     if tm.get("n_jets"):
         entries.append(("jets", jname, tm["jets_ms"] / tm["n_jets"] * 1e-3, JET_BYTES[dt], V, "path-step"))
     for key, name, secs, unit_bytes, units, unit in entries:
@@ -516,7 +533,8 @@ def pmc_summary(out_path, fetch_dirs, write_dirs, copy_fetch_dir, copy_write_dir
               f"copy_fetch_factor = {f_fetch:.4f}", f"copy_write_factor = {f_write:.4f}"]
     i = 0
     for name in sorted(kf):
-        if not any(p in name for p in ("field_", "push_", "force_table", "jet_kernel")) or "diag" in name:
+        if not any(p in name for p in ("field_", "push_", "force_table", "jet_kernel", "fused_", "straggler_")) \
+                or "diag" in name:
             continue
         if len(kf[name]) < 16 or len(kw.get(name, [])) < 16:
             continue
@@ -584,6 +602,9 @@ def main():
                     help="fix the store policy of the field update's new state (1: non-temporal) after tuning")
     ap.add_argument("--jets-only", action="store_true",
                     help="run only the jets workload and print its JSON (for profiling; not the benchmark line)")
+    ap.add_argument("--push", choices=["tile", "gather"], default=None,
+                    help="push mode before tuning (default: the library's; the tuner tries the fused step only "
+                         "from the tile mode)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the library's default launch shapes (for counter runs, where the tuner's timings "
                          "are distorted by the serialised dispatches)")
@@ -617,7 +638,7 @@ def main():
         print(json.dumps(run_jets(args.steps, args.warmup, V, not args.no_tune, args.launch)))
         return
     res = run_event(cp.FP64 if args.precision == "fp64" else cp.FP32, args.steps, args.warmup, not args.no_tune,
-                    fixed=args.launch, nt=args.nt)
+                    fixed=args.launch, nt=args.nt, push=args.push)
     ms_per_step = res["wall"] * 1e3 / args.steps
     site_rate = V * args.steps / res["wall"]
     push_rate = n_part * args.steps / res["wall"]

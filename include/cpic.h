@@ -289,6 +289,11 @@ cpic_status cpic_load(cpic_ctx* ctx, const char* path);
  *      rebuilt) and the scalars read from global memory, so that two
  *      workgroups share a CU (64x4, 32x8, 16x16, 32x4; waves 1), or one
  *      workgroup of 512 threads with a smaller halo (64x8).
+ *   4  the fused step: as 3, with the particle push of every tile in the same
+ *      kernel (push mode CPIC_PUSH_TILE; 64x8, 32x8, 16x16 or 8x8; needs
+ *      SU(3) particles with the rotation colour update and no light-like
+ *      paths).  The particle records are reordered by these tiles before the
+ *      next push step.
  * Used by the tuner; takes effect for the next launch. */
 cpic_status cpic_set_launch(cpic_ctx* ctx, int32_t bx, int32_t by, int32_t xcd_remap, int32_t waves,
                             int32_t variant);
@@ -303,15 +308,28 @@ cpic_status cpic_set_push_lanes(cpic_ctx* ctx, int32_t lanes);
 /* Where the push takes the colour fields at a particle's cell (the
  * interpolations of Sec. III.B from U(n), phi(n), E(n -+ 1/2), pi(n -+ 1/2)):
  *   CPIC_PUSH_GATHER  evaluated per particle from the two field buffer sets
- *                     of the step (default for fewer particles than sites);
+ *                     of the step;
  *   CPIC_PUSH_TABLE   evaluated once per site into a force table (48 reals
  *                     per site, one more kernel per step) that the push reads
- *                     at the cell (default for more particles than sites).
- * Both give the same arithmetic per particle.  SU(3) with the rotation
- * colour update only; cpic_tune times both.  Kernel timing counts the table
- * kernel as push time. */
+ *                     at the cell;
+ *   CPIC_PUSH_TILE    the fused step (launch variant 4): the workgroup that
+ *                     updates a tile of sites evaluates the fields at every
+ *                     site of the tile from the values of its own update and
+ *                     pushes the particles the last reordering put in the
+ *                     tile, in the same kernel; particles that have left
+ *                     their tile since then are pushed by a second, small
+ *                     kernel that gathers their fields.  It pays where the
+ *                     particles are dense enough that evaluating the fields
+ *                     at every site costs less than at every particle.
+ * The default is the gather push (the force table with more particles than
+ * sites).
+ * The three give the same arithmetic per particle up to rounding.  SU(3) with
+ * the rotation colour update only for the table and tile modes; cpic_tune
+ * times them.  Kernel timing counts the table kernel as push time, the fused
+ * kernel as field time and the straggler kernel as push time. */
 #define CPIC_PUSH_GATHER 0
 #define CPIC_PUSH_TABLE 1
+#define CPIC_PUSH_TILE 2
 cpic_status cpic_set_push_mode(cpic_ctx* ctx, int32_t mode);
 cpic_status cpic_get_push_mode(const cpic_ctx* ctx, int32_t* mode);
 
@@ -351,6 +369,13 @@ cpic_status cpic_tune(cpic_ctx* ctx, int32_t reps, char* report, size_t cap);
  * and synchronises. */
 cpic_status cpic_set_timing(cpic_ctx* ctx, int32_t enable);
 cpic_status cpic_timing(cpic_ctx* ctx, double* field_ms, double* push_ms, int64_t* n_field, int64_t* n_push);
+
+/* Fused step (push mode CPIC_PUSH_TILE): the number of particle pushes the
+ * straggler kernel has made since kernel timing was enabled (particles that
+ * had left the tile the last reordering put them in, or that exceeded one per
+ * thread of their tile); the tiles pushed the rest.  0 when timing is off or
+ * the fused step did not run.  Synchronises. */
+cpic_status cpic_straggler_pushes(cpic_ctx* ctx, int64_t* n);
 
 /*
  * Light-like jet limit of the momentum broadening (Sec. V.B,

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libcpic.so")
 FP64, FP32 = 0, 1
 REP_FUND, REP_ADJ = 0, 1
 COLOR_ROTATE, COLOR_LOG = 0, 1
-PUSH_GATHER, PUSH_TABLE = 0, 1
+PUSH_GATHER, PUSH_TABLE, PUSH_TILE = 0, 1, 2
 STATE_U, STATE_PHI, STATE_E, STATE_PI, STATE_PARTICLES, STATE_STEP, STATE_JET_W, STATE_JET_F, STATE_PTAU = range(9)
 ERRORS = {-1: "INVALID", -2: "NOMEM", -3: "HIP", -4: "IC_NEWTON", -5: "NAN", -6: "DRIFT", -7: "CAPACITY",
           -8: "CELL_JUMP", -9: "IO"}
@@ -82,6 +82,7 @@ def lib():
             "cpic_set_store_policy": [P, i32],
             "cpic_tune": [P, i32, P, sz],
             "cpic_timing": [P, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(i64), ctypes.POINTER(i64)],
+            "cpic_straggler_pushes": [P, ctypes.POINTER(i64)],
             "cpic_batch_create": [i32, ctypes.POINTER(GlasmaParams), ctypes.POINTER(ParticleParams), P, pp],
             "cpic_batch_init_mv": [P], "cpic_batch_run": [P], "cpic_batch_step": [P, i32], "cpic_batch_sync": [P],
             "cpic_batch_tune": [P, i32, P, sz], "cpic_batch_set_launch": [P, i32, i32, i32, i32],
@@ -257,7 +258,8 @@ class Context:
         self._chk(lib().cpic_load(self.h, str(path).encode()))
 
     def set_launch(self, bx, by, xcd_remap=1, waves=1, variant=0):
-        """Field-kernel launch; variant 0 site-parallel, 1 link-parallel, 2 LDS halo tiles."""
+        """Field-kernel launch; variant 0 site-parallel, 1 link-parallel, 2 LDS halo tiles,
+        3 two-row-link LDS tiles, 4 the fused step (tile push, PUSH_TILE)."""
         self._chk(lib().cpic_set_launch(self.h, bx, by, xcd_remap, waves, variant))
 
     def set_store_policy(self, non_temporal):
@@ -268,7 +270,8 @@ class Context:
         self._chk(lib().cpic_set_push_lanes(self.h, lanes))
 
     def set_push_mode(self, mode):
-        """PUSH_GATHER (fields per particle) or PUSH_TABLE (per-site force table)."""
+        """PUSH_GATHER (fields per particle), PUSH_TABLE (per-site force table) or
+        PUSH_TILE (fused step: fields per tile in the field update's workgroup)."""
         self._chk(lib().cpic_set_push_mode(self.h, mode))
 
     def push_mode(self):
@@ -317,7 +320,10 @@ class Context:
         f, p = ctypes.c_double(), ctypes.c_double()
         nf, npu = ctypes.c_int64(), ctypes.c_int64()
         self._chk(lib().cpic_timing(self.h, ctypes.byref(f), ctypes.byref(p), ctypes.byref(nf), ctypes.byref(npu)))
-        return {"field_ms": f.value, "push_ms": p.value, "n_field": nf.value, "n_push": npu.value}
+        ns = ctypes.c_int64()
+        self._chk(lib().cpic_straggler_pushes(self.h, ctypes.byref(ns)))
+        return {"field_ms": f.value, "push_ms": p.value, "n_field": nf.value, "n_push": npu.value,
+                "straggler_pushes": ns.value}
 
 
 class Batch:

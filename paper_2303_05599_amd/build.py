@@ -9,9 +9,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcpic.so")
-SOURCES = ["field.hip", "push.hip", "jets.hip", "su2.hip", "ic.hip", "sort.hip", "capi.hip", "batch.hip", "noalloc.hip"]
+SOURCES = ["field.hip", "fused.hip", "push.hip", "jets.hip", "su2.hip", "ic.hip", "sort.hip", "capi.hip", "batch.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",
          # packed FP32 instructions stay off (hipcc forms them from plain float code otherwise)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(HERE, "..", "include")]

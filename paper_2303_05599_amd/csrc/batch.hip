@@ -253,6 +253,9 @@ extern "C" cpic_status cpic_batch_create(int32_t n_events, const cpic_glasma_par
             cpic_batch_destroy(b);
             return bfail(nullptr, s, m);
         }
+        // the batch launches its own kernels over all events: the events'
+        // records keep the gather push's order
+        if (c->cfg.split == 4) c->cfg.split = 3;
         b->ev.push_back(c);
     }
     // compressed-link LDS tiles of 64 x 4 sites (cpic_batch_tune picks among the shapes)

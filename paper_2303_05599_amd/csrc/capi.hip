@@ -102,6 +102,8 @@ static void free_all(cpic_ctx* c)
     (void)hipFree(c->dpart); (void)hipFree(c->dout);
     (void)hipFree(c->pid); (void)hipFree(c->sb.keys); (void)hipFree(c->sb.keys2); (void)hipFree(c->sb.vals); (void)hipFree(c->sb.perm);
     (void)hipFree(c->sb.temp); (void)hipFree(c->sb.r2); (void)hipFree(c->sb.cell2); (void)hipFree(c->sb.pid2);
+    (void)hipFree(c->tile_start); (void)hipFree(c->strag); (void)hipFree(c->strag_count);
+    (void)hipFree(c->d_strag_total);
     if (c->own_stream && c->st) (void)hipStreamDestroy(c->st);
 }
 
@@ -209,8 +211,16 @@ extern "C" cpic_status cpic_create(const cpic_glasma_params* gp, const cpic_part
         if (e == hipSuccess) e = hipMalloc(&c->sb.r2, (size_t)kPartReals * np * c->tsz);
         if (e == hipSuccess) e = hipMalloc(&c->sb.cell2, sizeof(int) * 2 * np);
         if (e == hipSuccess) e = hipMalloc(&c->sb.pid2, sizeof(int) * np);
-        c->sb.temp_bytes = std::max<size_t>(sort_temp_bytes((int)np, c->N), 16);
+        c->sb.temp_bytes = std::max<size_t>(sort_temp_bytes((int)np), 16);
         if (e == hipSuccess) e = hipMalloc(&c->sb.temp, c->sb.temp_bytes);
+        if (c->nc == 3) {
+            const int nt = fused_tiles(c->N, 8, 8);  // the most tiles of any fused shape
+            if (e == hipSuccess) e = hipMalloc(&c->tile_start, sizeof(int) * (nt + 1));
+            if (e == hipSuccess) e = hipMalloc(&c->strag, sizeof(int) * np);
+            if (e == hipSuccess) e = hipMalloc(&c->strag_count, sizeof(int) * nt);
+            if (e == hipSuccess) e = hipMalloc(&c->d_strag_total, sizeof(unsigned long long));
+            if (e == hipSuccess) e = hipMemsetAsync(c->d_strag_total, 0, sizeof(unsigned long long), c->st);
+        }
     }
     // few particles: several wavefronts share each particle group so that the
     // push still fills the 1024 SIMDs (tunable with cpic_tune)
@@ -219,7 +229,10 @@ extern "C" cpic_status cpic_create(const cpic_glasma_params* gp, const cpic_part
     c->push_table = c->nc == 3 && c->np > c->V && c->pp.color_update == CPIC_COLOR_ROTATE;
     if (e == hipSuccess && c->push_table) e = hipMalloc(&c->ftab, (size_t)48 * c->V * c->tsz);
     // field update: compressed-link LDS tiles of 64 x 8 sites (the tuner's pick
-    // at 512^2, 1-2 % per step ahead of 64 x 4)
+    // at 512^2, 1-2 % per step ahead of 64 x 4).  The fused step (variant 4)
+    // is chosen explicitly: at 512^2 with 1e5 particles it computes the
+    // fields at every site of a tile, more FP64 work than the gather push's
+    // evaluation at the particles' cells (0.145 against 0.127 ms per step)
     c->cfg.split = 3;
     c->cfg.bx = 64;
     c->cfg.by = 8;
@@ -227,7 +240,8 @@ extern "C" cpic_status cpic_create(const cpic_glasma_params* gp, const cpic_part
     c->pblocks = c->np > 0 ? push_blocks((int)c->np, c->tpp) : 0;
     c->nslots = c->np > 0 ? num_slots(c->sc) : 0;
     if (e == hipSuccess && c->nslots > 0) {
-        e = hipMalloc(&c->partials, sizeof(double) * 4 * (size_t)obs_groups((int)c->np) * c->nslots);
+        const int groups = std::max(obs_groups((int)c->np), c->nc == 3 ? fused_groups_max(c->N) : 0);
+        e = hipMalloc(&c->partials, sizeof(double) * 4 * (size_t)groups * c->nslots);
         if (e == hipSuccess) e = hipMalloc(&c->obs, sizeof(double) * 4 * c->nslots);
     }
     if (e == hipSuccess) e = hipMalloc(&c->d_step, 2 * sizeof(int));
@@ -272,15 +286,31 @@ static cpic_status reset_pid(cpic_ctx* c)
     HIPCHK(c, hipMemcpy(c->pid, iota.data(), sizeof(int) * iota.size(), hipMemcpyHostToDevice), "pid");
     c->static_sorted = false;
     c->sorted_at = -1;
+    c->sort_tx = c->sort_ty = 0;
     return CPIC_OK;
+}
+
+bool cpic::fused_ok(const cpic_ctx* c)
+{
+    return c->nc == 3 && c->np > 0 && c->pp.color_update == CPIC_COLOR_ROTATE && !c->jets && c->tile_start;
+}
+bool cpic::fused_active(const cpic_ctx* c) { return c->cfg.split == 4 && fused_ok(c); }
+// the cell tiles the records are ordered by for the current launch
+static void sort_tiles(const cpic_ctx* c, int* tx, int* ty)
+{
+    *tx = fused_active(c) ? c->cfg.bx : kGatherSortTile;
+    *ty = fused_active(c) ? c->cfg.by : kGatherSortTile;
 }
 
 // Particle records are reordered by cell before step n when n is the first
 // push step or a multiple of kSortEvery (moving particles); static particles
-// never change cell and are ordered once.
+// never change cell and are ordered once.  The fused step needs the records
+// ordered by its own tiles: any push step finds them so.
 static bool is_sort_point(const cpic_ctx* c, int n)
 {
-    if (c->np <= 1 || n < c->sc.n_form || n >= c->sc.n_max) return false;
+    if (c->np < 1 || n < c->sc.n_form || n >= c->sc.n_max) return false;
+    if (fused_active(c) && (c->sort_tx != c->cfg.bx || c->sort_ty != c->cfg.by)) return true;
+    if (c->np == 1) return false;
     if (c->is_static) return !c->static_sorted;
     return n == c->sc.n_form || n % kSortEvery == 0;
 }
@@ -295,12 +325,21 @@ int cpic::next_sort_point(const cpic_ctx* c, int n)
 }
 cpic_status cpic::maybe_sort(cpic_ctx* c)
 {
-    if (!is_sort_point(c, c->n) || c->sorted_at == c->n) return CPIC_OK;
+    int tx, ty;
+    sort_tiles(c, &tx, &ty);
+    if (!is_sort_point(c, c->n) || (c->sorted_at == c->n && c->sort_tx == tx && c->sort_ty == ty)) return CPIC_OK;
     c->sorted_at = c->n;
+    // the tile ranges wherever the order is one a fused step can use
+    int* ts = c->tile_start && fused_shape(tx, ty) ? c->tile_start : nullptr;
+    const bool pos = !c->is_static;
     hipError_t e = c->prec == CPIC_FP64
-                       ? sort_particles<double>(c->sb, (double*)c->pr, c->pcell, c->pid, (int)c->np, c->N, c->st)
-                       : sort_particles<float>(c->sb, (float*)c->pr, c->pcell, c->pid, (int)c->np, c->N, c->st);
+                       ? sort_particles<double>(c->sb, (double*)c->pr, c->pcell, c->pid, (int)c->np, c->N, tx, ty, pos,
+                                                ts, c->st)
+                       : sort_particles<float>(c->sb, (float*)c->pr, c->pcell, c->pid, (int)c->np, c->N, tx, ty, pos,
+                                               ts, c->st);
     if (e != hipSuccess) return hip_fail(c, e, "particle sort");
+    c->sort_tx = tx;
+    c->sort_ty = ty;
     if (c->is_static) c->static_sorted = true;
     return CPIC_OK;
 }
@@ -318,6 +357,7 @@ static cpic_status reset_counters(cpic_ctx* c, int n)
 {
     c->n = n;
     c->samples.clear();
+    c->sample_groups.clear();
     c->obs_reduced = 0;
     c->jsamples.clear();
     c->jobs_reduced = 0;
@@ -454,6 +494,16 @@ template <typename T> static cpic_status launch_one(cpic_ctx* c, int parity, boo
     };
     KTimer tf, tt, tp, tj;
     HIPCHK(c, timer(c->ev_field, tf), "event");
+    if (fused_active(c)) {
+        // the field update with the tile push (timed as the field kernel),
+        // then the stragglers (timed as the push)
+        HIPCHK(c, timer(c->ev_push, tp), "event");
+        const TileParts tpa{c->tile_start, c->strag, c->strag_count, c->timing ? c->d_strag_total : nullptr};
+        HIPCHK(c, launch_fused<T>(A, B, c->cfg, P<T>(c), push_args(c, 8), tpa,
+                                  c->d_step, c->partials, c->d_err, c->st, tf, tp),
+               "fused step");
+        return CPIC_OK;
+    }
     HIPCHK(c, launch_field_step<T>(A, B, static_cast<T*>(c->gpl), c->N, c->sc, c->d_step, c->cfg, c->st, tf),
            "field step");
     if (uses_table(c)) {
@@ -483,10 +533,19 @@ template <typename T> static cpic_status launch_one(cpic_ctx* c, int parity, boo
     return CPIC_OK;
 }
 
+// groups of 4 partial sums a sample of the current launch writes
+static int sample_groups_now(const cpic_ctx* c)
+{
+    return fused_active(c) ? fused_groups(c->N, c->cfg.bx, c->cfg.by) : obs_groups((int)c->np);
+}
+
 cpic_status cpic::host_advance(cpic_ctx* c, int k)
 {
     for (int j = 0; j < k; j++) {
-        if (c->np > 0 && is_record_step(c->sc, c->n)) c->samples.push_back({record_slot_of(c->sc, c->n), c->n});
+        if (c->np > 0 && is_record_step(c->sc, c->n)) {
+            c->samples.push_back({record_slot_of(c->sc, c->n), c->n});
+            c->sample_groups.push_back(sample_groups_now(c));
+        }
         if (c->jets && is_record_step(c->ja.sc, c->n))
             c->jsamples.push_back({record_slot_of(c->ja.sc, c->n), c->n});
         c->n++;
@@ -627,9 +686,8 @@ extern "C" cpic_status cpic_sync(cpic_ctx* c)
 // obs[slot] (groups in order, fixed-order block reduction).
 static cpic_status reduce_samples(cpic_ctx* c)
 {
-    const int groups = obs_groups((int)c->np);
     for (size_t k = (size_t)c->obs_reduced; k < c->samples.size(); k++) {
-        const int slot = c->samples[k].first;
+        const int slot = c->samples[k].first, groups = c->sample_groups[k];
         HIPCHK(c, launch_reduce_rows(c->partials + (size_t)slot * groups * 4, groups, 4, c->obs + (size_t)slot * 4,
                                      c->st), "observables");
     }
@@ -1017,17 +1075,22 @@ extern "C" cpic_status cpic_save(cpic_ctx* c, const char* path)
     HIPCHK(c, hipStreamSynchronize(c->st), "save");
     CkptHeader h{};
     std::memcpy(h.magic, "CPICKPT1", 8);
-    h.version = 1; h.N = c->N; h.prec = c->prec; h.n = c->n; h.nsamples = (int)c->samples.size();
+    h.version = 2; h.N = c->N; h.prec = c->prec; h.n = c->n; h.nsamples = (int)c->samples.size();
     h.np = c->np; h.nslots = c->nslots; h.gp = c->gp; h.pp = c->pp; h.jets = c->jets;
     const size_t fb = (size_t)c->rps * c->V * c->tsz, pb = (size_t)kPartReals * c->np * c->tsz;
     std::vector<char> f(fb), p(pb);
     std::vector<int> cell(2 * c->np), pid(c->np);
+    std::vector<unsigned> keys;
     std::vector<double> obs(4 * (size_t)c->nslots);
     HIPCHK(c, hipMemcpy(f.data(), c->fbuf[c->cur], fb, hipMemcpyDeviceToHost), "save");
     if (pb) {
         HIPCHK(c, hipMemcpy(p.data(), c->pr, pb, hipMemcpyDeviceToHost), "save");
         HIPCHK(c, hipMemcpy(cell.data(), c->pcell, sizeof(int) * cell.size(), hipMemcpyDeviceToHost), "save");
         HIPCHK(c, hipMemcpy(pid.data(), c->pid, sizeof(int) * pid.size(), hipMemcpyDeviceToHost), "save");
+        if (fused_shape(c->sort_tx, c->sort_ty)) {
+            keys.resize(c->np);
+            HIPCHK(c, hipMemcpy(keys.data(), c->sb.keys2, sizeof(unsigned) * keys.size(), hipMemcpyDeviceToHost), "save");
+        }
     }
     if (!obs.empty()) HIPCHK(c, hipMemcpy(obs.data(), c->obs, sizeof(double) * obs.size(), hipMemcpyDeviceToHost), "save");
     const size_t jwb = c->jets ? (size_t)18 * c->V * c->tsz : 0, jfb = c->jets ? (size_t)24 * c->V * c->tsz : 0;
@@ -1053,6 +1116,9 @@ extern "C" cpic_status cpic_save(cpic_ctx* c, const char* path)
         ok = ok && std::fwrite(pid.data(), sizeof(int), pid.size(), fp) == pid.size();
         const int32_t ss = c->static_sorted;
         ok = ok && std::fwrite(&ss, sizeof ss, 1, fp) == 1;
+        const int32_t order[2] = {fused_shape(c->sort_tx, c->sort_ty) ? c->sort_tx : 0, c->sort_ty};
+        ok = ok && std::fwrite(order, sizeof order, 1, fp) == 1;
+        if (order[0] > 0) ok = ok && std::fwrite(keys.data(), sizeof(unsigned), keys.size(), fp) == keys.size();
     }
     if (!obs.empty()) ok = ok && std::fwrite(obs.data(), sizeof(double), obs.size(), fp) == obs.size();
     if (c->jets) {
@@ -1077,7 +1143,8 @@ extern "C" cpic_status cpic_load(cpic_ctx* c, const char* path)
     FILE* fp = std::fopen(path, "rb");
     if (!fp) return fail(c, CPIC_E_IO, std::string("cpic_load: cannot open ") + path);
     CkptHeader h{};
-    bool ok = std::fread(&h, sizeof h, 1, fp) == 1 && std::memcmp(h.magic, "CPICKPT1", 8) == 0 && h.version == 1;
+    bool ok = std::fread(&h, sizeof h, 1, fp) == 1 && std::memcmp(h.magic, "CPICKPT1", 8) == 0 &&
+              (h.version == 1 || h.version == 2);
     if (ok && (h.N != c->N || h.prec != c->prec || h.np != c->np || h.nslots != c->nslots || h.nsamples < 0 ||
                h.nsamples > c->nslots || h.n < 0 || h.n > c->sc.n_max || (h.jets != 0) != c->jets ||
                (h.gp.n_colors == 2 ? 2 : 3) != c->nc)) {
@@ -1094,13 +1161,26 @@ extern "C" cpic_status cpic_load(cpic_ctx* c, const char* path)
     std::vector<char> f(fb), p(pb);
     std::vector<int> cell(2 * c->np), pid(c->np);
     std::vector<double> obs(4 * (size_t)c->nslots);
-    int32_t ss = 0;
+    int32_t ss = 0, order[2] = {0, 0};
+    std::vector<unsigned> keys;
     ok = ok && std::fread(f.data(), 1, fb, fp) == fb;
     if (pb) {
         ok = ok && std::fread(p.data(), 1, pb, fp) == pb;
         ok = ok && std::fread(cell.data(), sizeof(int), cell.size(), fp) == cell.size();
         ok = ok && std::fread(pid.data(), sizeof(int), pid.size(), fp) == pid.size();
         ok = ok && std::fread(&ss, sizeof ss, 1, fp) == 1;
+        // version 2: the cell tiles of the record order and, for a fused-step
+        // order, the sorted keys (from which the tile ranges follow)
+        if (ok && h.version >= 2) {
+            ok = std::fread(order, sizeof order, 1, fp) == 1;
+            if (ok && order[0] > 0) {
+                ok = fused_shape(order[0], order[1]);
+                keys.resize(c->np);
+                ok = ok && std::fread(keys.data(), sizeof(unsigned), keys.size(), fp) == keys.size();
+                const unsigned bound = (unsigned)fused_tiles(c->N, order[0], order[1]) * (unsigned)(order[0] * order[1]);
+                for (size_t k = 0; ok && k < keys.size(); k++) ok = keys[k] < bound && (k == 0 || keys[k - 1] <= keys[k]);
+            }
+        }
     }
     if (!obs.empty()) ok = ok && std::fread(obs.data(), sizeof(double), obs.size(), fp) == obs.size();
     const size_t jwb = c->jets ? (size_t)18 * c->V * c->tsz : 0, jfb = c->jets ? (size_t)24 * c->V * c->tsz : 0;
@@ -1145,11 +1225,20 @@ extern "C" cpic_status cpic_load(cpic_ctx* c, const char* path)
         HIPCHK(c, hipMemcpy(c->pid, pid.data(), sizeof(int) * pid.size(), hipMemcpyHostToDevice), "load");
         c->static_sorted = ss != 0;
         c->sorted_at = -1;
+        c->sort_tx = c->sort_ty = 0;
+        if (order[0] > 0 && c->tile_start) {
+            // the fused step's tile order of the records: its ranges again
+            HIPCHK(c, hipMemcpy(c->sb.keys2, keys.data(), sizeof(unsigned) * keys.size(), hipMemcpyHostToDevice), "load");
+            HIPCHK(c, launch_tile_start(c->sb.keys2, (int)c->np, c->N, order[0], order[1], c->tile_start, c->st), "load");
+            c->sort_tx = order[0];
+            c->sort_ty = order[1];
+        }
     }
     c->n = h.n;
     HIPCHK(c, hipMemcpy(c->d_step, &c->n, sizeof(int), hipMemcpyHostToDevice), "load");
     if (!obs.empty()) HIPCHK(c, hipMemcpy(c->obs, obs.data(), sizeof(double) * obs.size(), hipMemcpyHostToDevice), "load");
     c->samples = samples;
+    c->sample_groups.assign(samples.size(), obs_groups((int)c->np));  // already summed into obs
     c->obs_reduced = (int)samples.size();
     if (c->jets) {
         HIPCHK(c, hipMemcpy(c->jW, jw.data(), jwb, hipMemcpyHostToDevice), "load");
@@ -1187,8 +1276,16 @@ extern "C" cpic_status cpic_set_launch(cpic_ctx* c, int32_t bx, int32_t by, int3
     } else if (variant == 0) {
         if (bx <= 0 || by <= 0 || bx * by > 256 || (bx * by) % 64 != 0)
             return fail(c, CPIC_E_INVALID, "cpic_set_launch: need bx*by a multiple of 64 and <= 256");
+    } else if (variant == 4) {
+        if (!fused_ok(c))
+            return fail(c, CPIC_E_INVALID,
+                        "cpic_set_launch: the fused step needs SU(3) particles with the rotation colour update and no "
+                        "light-like paths");
+        if (!fused_shape(bx, by))
+            return fail(c, CPIC_E_INVALID, "cpic_set_launch: fused tiles are 64x8, 32x8, 16x16 or 8x8");
+        if (waves != 1) return fail(c, CPIC_E_INVALID, "cpic_set_launch: LDS tiles take waves = 1");
     } else {
-        return fail(c, CPIC_E_INVALID, "cpic_set_launch: variant must be 0, 1, 2 or 3");
+        return fail(c, CPIC_E_INVALID, "cpic_set_launch: variant must be 0 .. 4");
     }
     if (waves < 1 || waves > 4) return fail(c, CPIC_E_INVALID, "cpic_set_launch: waves must be 1..4");
     c->cfg.split = variant;
@@ -1218,6 +1315,19 @@ extern "C" cpic_status cpic_set_timing(cpic_ctx* c, int32_t enable)
     c->timing = enable != 0;
     c->t_field = c->t_push = c->t_jets = 0;
     c->k_field = c->k_push = c->k_jets = 0;
+    if (c->d_strag_total) HIPCHK(c, hipMemset(c->d_strag_total, 0, sizeof(unsigned long long)), "timing");
+    return CPIC_OK;
+}
+
+extern "C" cpic_status cpic_straggler_pushes(cpic_ctx* c, int64_t* n)
+{
+    if (!c || !n) return fail(c, CPIC_E_INVALID, "cpic_straggler_pushes: NULL argument");
+    cpic_status s = cpic_sync(c);
+    if (s) return s;
+    unsigned long long v = 0;
+    if (c->d_strag_total)
+        HIPCHK(c, hipMemcpy(&v, c->d_strag_total, sizeof v, hipMemcpyDeviceToHost), "cpic_straggler_pushes");
+    *n = (int64_t)v;
     return CPIC_OK;
 }
 
@@ -1238,7 +1348,7 @@ extern "C" cpic_status cpic_timing(cpic_ctx* c, double* field_ms, double* push_m
 // field kernel reads the current buffer and writes the free one (the step is
 // not advanced); the push runs on a saved copy of the particle records, which
 // is restored after every trial.  The fastest configuration is kept.
-static const char* const kVariantName[4] = {"site", "link", "tile", "ctile"};
+static const char* const kVariantName[5] = {"site", "link", "tile", "ctile", "fused"};
 
 template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::string& rep)
 {
@@ -1356,20 +1466,31 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
     }
     // In the step: the field kernel shares the caches with the push and the
     // light-like paths, which the isolated timings above do not see.  The
-    // three fastest field launches, each with both store policies, run two
-    // real steps (both buffer parities) from the current state, which is
-    // restored after every trial; the fastest step pair decides.
-    if (c->n + 2 <= c->sc.n_max && timed.size() > 0) {
+    // three fastest field launches, each with both store policies, and the
+    // fused step on its tile shapes run two real steps (both buffer
+    // parities) from the current state, which is restored after every trial;
+    // the fastest step pair decides.  A fused trial first reorders the
+    // records by its tiles (a reordering changes no result).
+    // (the fused step needs the records in the order of its tiles at every
+    // push step: a trial pair must not run into the first push step, before
+    // which the records are first ordered)
+    const bool order_ok = !fused_ok(c) || c->n >= c->sc.n_form || c->n + 2 <= c->sc.n_form;
+    if (!order_ok) rep += "step trials skipped: the first push step falls inside the trial steps\n";
+    if (c->n + 2 <= c->sc.n_max && timed.size() > 0 && order_ok) {
         std::sort(timed.begin(), timed.end(),
                   [](const std::pair<double, LaunchCfg>& a, const std::pair<double, LaunchCfg>& b) { return a.first < b.first; });
         const size_t fbytes = (size_t)c->rps * c->V * c->tsz;
         const size_t rb = sizeof(T) * kPartReals * (size_t)c->np, cb = sizeof(int) * 2 * (size_t)c->np;
         const size_t wb = (size_t)18 * c->V * c->tsz, fb = (size_t)24 * c->V * c->tsz;
-        void *bk = nullptr, *bw = nullptr, *bf = nullptr;
+        void *bk = nullptr, *bw = nullptr, *bf = nullptr, *bp = nullptr, *bc = nullptr;
         hipError_t he = hipMalloc(&bk, fbytes);
         if (he == hipSuccess && c->jets) he = hipMalloc(&bw, wb);
         if (he == hipSuccess && c->jets) he = hipMalloc(&bf, fb);
-        auto release = [&]() { (void)hipFree(bk); (void)hipFree(bw); (void)hipFree(bf); };
+        if (he == hipSuccess && c->np > 0) he = hipMalloc(&bp, rb);
+        if (he == hipSuccess && c->np > 0) he = hipMalloc(&bc, cb);
+        auto release = [&]() {
+            (void)hipFree(bk); (void)hipFree(bw); (void)hipFree(bf); (void)hipFree(bp); (void)hipFree(bc);
+        };
         if (he != hipSuccess) {
             release();
             rep += "step trials skipped: no memory for the state copy\n";
@@ -1378,14 +1499,14 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
                 return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->st);
             };
             hipError_t te = copy(bk, c->fbuf[c->cur], fbytes);
-            if (te == hipSuccess && c->np > 0) te = copy(c->sb.r2, c->pr, rb);
-            if (te == hipSuccess && c->np > 0) te = copy(c->sb.cell2, c->pcell, cb);
+            if (te == hipSuccess && c->np > 0) te = copy(bp, c->pr, rb);
+            if (te == hipSuccess && c->np > 0) te = copy(bc, c->pcell, cb);
             if (te == hipSuccess && c->jets) te = copy(bw, c->jW, wb);
             if (te == hipSuccess && c->jets) te = copy(bf, c->jF, fb);
             auto restore = [&]() {
                 hipError_t r = copy(c->fbuf[c->cur], bk, fbytes);
-                if (r == hipSuccess && c->np > 0) r = copy(c->pr, c->sb.r2, rb);
-                if (r == hipSuccess && c->np > 0) r = copy(c->pcell, c->sb.cell2, cb);
+                if (r == hipSuccess && c->np > 0) r = copy(c->pr, bp, rb);
+                if (r == hipSuccess && c->np > 0) r = copy(c->pcell, bc, cb);
                 if (r == hipSuccess && c->jets) r = copy(c->jW, bw, wb);
                 if (r == hipSuccess && c->jets) r = copy(c->jF, bf, fb);
                 if (r == hipSuccess) r = hipStreamSynchronize(c->st);
@@ -1409,6 +1530,21 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
                     cfg.nt_store = cfg.split == 3 ? nt : 0;
                     trials.push_back(cfg);
                 }
+            if (orig.split == 4 && fused_ok(c) && c->n >= c->sc.n_form) {  // from the tile push mode only
+                const int shapes[3][2] = {{64, 8}, {32, 8}, {16, 16}}, small[2][2] = {{16, 16}, {8, 8}};
+                const int ns = c->N >= 64 ? 3 : 2;
+                for (int k = 0; k < ns; k++)
+                    for (int nt = 0; nt <= 1; nt++) {
+                        LaunchCfg cfg;
+                        cfg.split = 4;
+                        cfg.bx = c->N >= 64 ? shapes[k][0] : small[k][0];
+                        cfg.by = c->N >= 64 ? shapes[k][1] : small[k][1];
+                        cfg.xcd_remap = 1;
+                        cfg.waves = 1;
+                        cfg.nt_store = nt;
+                        trials.push_back(cfg);
+                    }
+            }
             bool have_orig = false;
             for (const LaunchCfg& t : trials) have_orig = have_orig || same(t, orig);
             if (!have_orig) trials.push_back(orig);
@@ -1418,6 +1554,14 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
                 {
                     const LaunchCfg cfg = trials[k];
                     c->cfg = cfg;
+                    if (fused_active(c) && (c->sort_tx != cfg.bx || c->sort_ty != cfg.by)) {
+                        // records in this trial's tile order, and the copy the
+                        // trials restore taken again
+                        cpic_status so = maybe_sort(c);
+                        if (so) { c->cfg = keep; (void)restore(); release(); return so; }
+                        te = copy(bp, c->pr, rb);
+                        if (te == hipSuccess) te = copy(bc, c->pcell, cb);
+                    }
                     double tot = 0;
                     for (int r = 0; r <= reps && te == hipSuccess; r++) {
                         te = hipEventRecord(e0, c->st);
@@ -1563,6 +1707,7 @@ extern "C" cpic_status cpic_jets_enable(cpic_ctx* c, const cpic_jet_params* jp)
     c->jsamples.clear();
     c->jobs_reduced = 0;
     c->jets = true;
+    if (c->cfg.split == 4) c->cfg.split = 3;  // the paths read the force table: a separate push
     set_store_policy(c);
     drop_graphs(c);
     return CPIC_OK;
@@ -1605,11 +1750,30 @@ extern "C" cpic_status cpic_jets_timing(cpic_ctx* c, double* ms, int64_t* launch
 extern "C" cpic_status cpic_set_push_mode(cpic_ctx* c, int32_t mode)
 {
     if (!c) return fail(nullptr, CPIC_E_INVALID, "cpic_set_push_mode: NULL context");
-    if (mode != CPIC_PUSH_GATHER && mode != CPIC_PUSH_TABLE)
-        return fail(c, CPIC_E_INVALID, "cpic_set_push_mode: CPIC_PUSH_GATHER or CPIC_PUSH_TABLE");
+    if (mode != CPIC_PUSH_GATHER && mode != CPIC_PUSH_TABLE && mode != CPIC_PUSH_TILE)
+        return fail(c, CPIC_E_INVALID, "cpic_set_push_mode: CPIC_PUSH_GATHER, CPIC_PUSH_TABLE or CPIC_PUSH_TILE");
     if (mode == CPIC_PUSH_TABLE && (c->nc != 3 || c->pp.color_update != CPIC_COLOR_ROTATE))
         return fail(c, CPIC_E_INVALID, "cpic_set_push_mode: the force table serves the SU(3) rotation update");
+    if (mode == CPIC_PUSH_TILE && !fused_ok(c))
+        return fail(c, CPIC_E_INVALID,
+                    "cpic_set_push_mode: the tile push needs SU(3) particles with the rotation colour update and no "
+                    "light-like paths");
     HIPCHK(c, hipStreamSynchronize(c->st), "set push mode");
+    if (mode == CPIC_PUSH_TILE) {
+        if (c->cfg.split != 4) {
+            c->cfg.split = 4;
+            c->cfg.waves = 1;
+            if (!fused_shape(c->cfg.bx, c->cfg.by)) {
+                c->cfg.bx = c->N < 64 ? (c->N >= 16 ? 16 : 8) : 64;
+                c->cfg.by = c->N < 64 ? c->cfg.bx : 8;
+            }
+        }
+        c->push_table = false;
+        set_store_policy(c);
+        drop_graphs(c);
+        return CPIC_OK;
+    }
+    if (c->cfg.split == 4) c->cfg.split = 3;  // back to the compressed tiles with a separate push
     if (mode == CPIC_PUSH_TABLE && !c->ftab)
         HIPCHK(c, hipMalloc(&c->ftab, (size_t)48 * c->V * c->tsz), "force table");
     c->push_table = mode == CPIC_PUSH_TABLE;
@@ -1621,6 +1785,6 @@ extern "C" cpic_status cpic_set_push_mode(cpic_ctx* c, int32_t mode)
 extern "C" cpic_status cpic_get_push_mode(const cpic_ctx* c, int32_t* mode)
 {
     if (!c || !mode) return CPIC_E_INVALID;
-    *mode = c->push_table ? CPIC_PUSH_TABLE : CPIC_PUSH_GATHER;
+    *mode = fused_active(c) ? CPIC_PUSH_TILE : (c->push_table ? CPIC_PUSH_TABLE : CPIC_PUSH_GATHER);
     return CPIC_OK;
 }

@@ -12,9 +12,11 @@ namespace cpic {
 
 __device__ __forceinline__ int wrap(int v, int N) { return v < 0 ? v + N : (v >= N ? v - N : v); }
 
+#ifndef CPIC_PHASE
 // compiler barrier between phases: keeps the links of one phase from being
 // loaded (and held in registers) during another
 #define CPIC_PHASE() __builtin_amdgcn_sched_barrier(0)
+#endif
 
 // The colour fields at a cell c at time t_n enter the particle push only
 // through Q.F and the light-like path integral only through W F W^+, so each
@@ -104,8 +106,57 @@ __device__ __forceinline__ a8<T> cell_D(int i, const View<T>& A, const Cell& c, 
     for (int q = 0; q < 8; q++) F.v[q] = scale * (f.v[q] - b.v[q]);
     return F;
 }
-// sub-job k at the cell (the caller zeroes inactive ones)
+// B_eta from the links alone (no plaquette field): the four counter-clockwise
+// leaves at c formed as loops from c, summed as the fused step's tile push
+// sums them (fused.hip), so that a particle gets the same field, bit for bit,
+// from either push:
+//   -(1/4) [((Proj U_12 - Proj U_{1,-2}) + Proj U_{2,-1}) + Proj U_{-1,-2}](c),
+// with Proj U_{-2,1} = -Proj U_{1,-2} (U_{-2,1} = U_{1,-2}^+)
 template <typename T>
+__device__ __forceinline__ a8<T> clover_links(const View<T>& A, const Cell& c)
+{
+    // c-x+y and c+x-y: the row of c+y (c-y) at the column of c-x (c+x), in
+    // modular offset arithmetic
+    const uint32_t s_xmyp = c.s_yp + (c.s_xm - c.s), s_xpym = c.s_ym + (c.s_xp - c.s);
+    a8<T> BE;
+    {
+        m3<T> M = mul(vU(A, c.s, 0), vU(A, c.s_xp, 1));
+        M = mul_adj(M, vU(A, c.s_yp, 0));
+        BE = proj(mul_adj(M, vU(A, c.s, 1)));
+    }
+    CPIC_PHASE();
+    {
+        m3<T> M = mul_adj(vU(A, c.s, 0), vU(A, s_xpym, 1));
+        M = mul_adj(M, vU(A, c.s_ym, 0));
+        const a8<T> p = proj(mul(M, vU(A, c.s_ym, 1)));
+#pragma unroll
+        for (int q = 0; q < 8; q++) BE.v[q] -= p.v[q];
+    }
+    CPIC_PHASE();
+    {
+        m3<T> M = mul_adj(vU(A, c.s, 1), vU(A, s_xmyp, 0));
+        M = mul_adj(M, vU(A, c.s_xm, 1));
+        const a8<T> p = proj(mul(M, vU(A, c.s_xm, 0)));
+#pragma unroll
+        for (int q = 0; q < 8; q++) BE.v[q] += p.v[q];
+    }
+    CPIC_PHASE();
+    {
+        const m3<T> M1 = mul(vU(A, c.s_xmym, 1), vU(A, c.s_xm, 0));   // U_y(c-x-y) U_x(c-x)
+        const m3<T> M2 = mul(vU(A, c.s_xmym, 0), vU(A, c.s_ym, 1));   // U_x(c-x-y) U_y(c-y)
+        const a8<T> p = proj(adj_mul(M1, M2));
+#pragma unroll
+        for (int q = 0; q < 8; q++) BE.v[q] += p.v[q];
+    }
+    a8<T> F;
+#pragma unroll
+    for (int q = 0; q < 8; q++) F.v[q] = T(-0.25) * BE.v[q];
+    return F;
+}
+
+// sub-job k at the cell (the caller zeroes inactive ones); GL: B_eta whole
+// from the links as sub-job 5 (6 and 7 then inactive, subjob_active)
+template <typename T, bool GL = false>
 __device__ __forceinline__ a8<T> subjob(int k, const View<T>& A, const View<T>& B, const View<T>& G, const Cell& c,
                                         int n, T t)
 {
@@ -114,6 +165,7 @@ __device__ __forceinline__ a8<T> subjob(int k, const View<T>& A, const View<T>& 
     // B_x = -(1/2t) D_y, B_y = +(1/2t) D_x
     if (k == kJobBx) return cell_D<T>(1, A, c, T(-1) / (T(2) * t));
     if (k == kJobBy) return cell_D<T>(0, A, c, T(1) / (T(2) * t));
+    if (GL) return clover_links<T>(A, c);
     a8<T> F;
     if (k == 5) {
         const a8<T> g0 = vA(G, c.s, 0), tg = transport_adj(vU(A, c.s_xm, 0), vA(G, c.s_xm, 0));
@@ -129,8 +181,9 @@ __device__ __forceinline__ a8<T> subjob(int k, const View<T>& A, const View<T>& 
     for (int q = 0; q < 8; q++) F.v[q] *= T(-0.25);
     return F;
 }
-__device__ __forceinline__ bool subjob_active(int k, int n, bool electric_only)
+template <bool GL = false> __device__ __forceinline__ bool subjob_active(int k, int n, bool electric_only)
 {
+    if (GL && k > 5) return false;
     return job_active(subjob_field(k), n, electric_only);
 }
 

@@ -40,10 +40,17 @@ struct cpic_ctx {
     double* obs = nullptr;       // [nslots][4], summed from partials when samples are read
     int obs_reduced = 0;         // samples[0 .. obs_reduced) are summed into obs
     std::vector<std::pair<int, int>> samples;  // (slot, step n after which it was taken)
+    std::vector<int> sample_groups;            // groups of partials each sample was written as
     int* pid = nullptr;    // original index of each particle record
     cpic::SortBufs sb{};
     bool static_sorted = false;
     int sorted_at = -1;   // step before which the records were last reordered
+    int sort_tx = 0, sort_ty = 0;  // cell tiles of the current record order (0: not ordered)
+    // fused step (field variant 4): record range and stragglers of every tile
+    int* tile_start = nullptr;    // [tiles + 1]
+    int* strag = nullptr;         // [np]
+    int* strag_count = nullptr;   // [tiles]
+    unsigned long long* d_strag_total = nullptr;  // stragglers pushed while kernel timing is on
     int* d_step = nullptr;
     int* d_err = nullptr;
     int* d_fails = nullptr;
@@ -51,7 +58,7 @@ struct cpic_ctx {
     double* dout = nullptr;   // diagnostics results [8 + 2]
     int dcap = 0;
     cpic::LaunchCfg cfg{};
-    int tpp = 1;          // wavefronts per particle group in the push (1, 2, 4)
+    int tpp = 1;          // wavefronts per particle group in the gather push (1, 2, 4, 8)
     int push_table = 0;   // 1: fields from a per-site force table (dense ensembles)
     void* ftab = nullptr; // [48][V] force table (table push, light-like paths)
     bool initialised = false;
@@ -86,6 +93,11 @@ int next_sort_point(const cpic_ctx* c, int n);
 // host bookkeeping of k launched steps (sample list, step counter, buffer parity)
 cpic_status host_advance(cpic_ctx* c, int k);
 PushArgs push_args(const cpic_ctx* c, int tpp);
+// the fused step can serve this context: SU(3), particles, the rotation
+// colour update, no light-like paths
+bool fused_ok(const cpic_ctx* c);
+// the fused step is the current launch
+bool fused_active(const cpic_ctx* c);
 // device address of the allocation-free entry point's scratch array on the
 // current device (resolved once per device; noalloc.hip)
 cpic_status noalloc_scratch(double** out);

@@ -12,27 +12,10 @@
 #include "reduce.h"
 #include "su3.h"
 #include "bufio.h"
+#include "tiles.h"
 
 namespace cpic {
 
-// scheduling barrier between the phases of the stencil: keeps the machine
-// scheduler from hoisting every link load of the site to the top (which
-// would hold ~10 matrices in registers at once)
-#define CPIC_PHASE() __builtin_amdgcn_sched_barrier(0)
-
-// byte offsets (site * sizeof(T)) of a site and the neighbours its stencil reads
-struct Nbr {
-    uint32_t s, xp, xm, yp, ym, xpym, xmyp;
-};
-template <typename T> __device__ __forceinline__ Nbr neighbours(int x, int y, int N)
-{
-    const int xp = x + 1 == N ? 0 : x + 1, xm = x == 0 ? N - 1 : x - 1;
-    const int yp = y + 1 == N ? 0 : y + 1, ym = y == 0 ? N - 1 : y - 1;
-    constexpr uint32_t b = sizeof(T);
-    return {(uint32_t)(y * N + x) * b,  (uint32_t)(y * N + xp) * b,  (uint32_t)(y * N + xm) * b,
-            (uint32_t)(yp * N + x) * b, (uint32_t)(ym * N + x) * b,  (uint32_t)(ym * N + xp) * b,
-            (uint32_t)(yp * N + xm) * b};
-}
 
 // Where the stencil reads links and scalars: straight from the global buffer
 // (sites as byte offsets) or from a halo tile staged in LDS (sites as tile
@@ -136,16 +119,6 @@ __device__ __forceinline__ void kick_forces(const Src& f, const Nbr& nb, T t, T 
         Fpi.v[a] = inv_t * lap.v[a];
     }
     if (grad2) *grad2 = g2;
-}
-
-// Workgroups are dealt round-robin to the 8 XCDs; with remapping, logical
-// block g of `total` goes to XCD g / per, so each XCD works on a contiguous
-// band of tiles and their shared halos stay in its L2.
-__device__ __forceinline__ int logical_block(int total, int remap)
-{
-    if (!remap) return blockIdx.x;
-    const int per = (total + 7) / 8;
-    return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
 }
 
 // The particle push and the force table take B_eta from the plaquette field
@@ -297,55 +270,19 @@ __global__ __launch_bounds__(BX * BY) void field_tile_kernel(Fields<T> in, Field
 }
 
 // ---------------------------------------------------------------- compressed-link LDS tiles
-// As the halo-tile variant, but LDS holds only the first two rows of each
-// link (12 of 18 reals; the third row of an SU(3) matrix is the complex
-// conjugate of the cross product of the first two) and the scalars are read
-// from global memory (L1/L2).  Smaller LDS tiles let two workgroups share a
-// CU, and the stencil forms each plaquette in one phase from links re-read
-// out of LDS, so no partial products stay live across phases.
-template <typename T, int HS> struct LdsLinks2 {
-    const T* l;  // [24][HS]: rows 0, 1 of U_x, then of U_y
-    __device__ __forceinline__ m3<T> U(uint32_t h, int i) const
-    {
-        m3<T> m;
-#pragma unroll
-        for (int c = 0; c < 6; c++) m.e[c] = {l[(12 * i + 2 * c) * HS + h], l[(12 * i + 2 * c + 1) * HS + h]};
-#pragma unroll
-        for (int j = 0; j < 3; j++) {
-            const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
-            const cx<T> p = cmul(m.e[j1], m.e[3 + j2]), q = cmul(m.e[j2], m.e[3 + j1]);
-            m.e[6 + j] = {p.re - q.re, q.im - p.im};
-        }
-        return m;
-    }
-};
-
+// (LdsLinks2, tiles.h)
 template <typename T, int BX, int BY, int CP = 0>
 __device__ __forceinline__ void field_ctile_body(const Fields<T>& in, const Fields<T>& out, T* gpl, int N, int tile,
                                                  const Schedule& sc, int* d_step)
 {
-    constexpr int HX = BX + 2, HY = BY + 2, HS = HX * HY, NT = BX * BY, NC = 24;
+    constexpr int HX = BX + 2, HS = HX * (BY + 2), NC = 24;
     __shared__ T lds[NC * HS];
     const int ntx = (N + BX - 1) / BX;
     const int x0 = (tile % ntx) * BX, y0 = (tile / ntx) * BY;
     const int tid = (int)threadIdx.x;
     const uint32_t V = (uint32_t)N * N;
     const View<T> vi = make_view<T>(in.U, kRealsPerSite, V), vo = make_view<T>(out.U, kRealsPerSite, V);
-    // stage rows 0, 1 of both links (buffer components 0..11 and 18..29)
-#pragma unroll
-    for (int h0 = 0; h0 < HS; h0 += NT) {
-        const int h = h0 + tid;
-        if (h < HS) {
-            const int hy = h / HX, hx = h - hy * HX;
-            const int gx = (x0 + hx - 1 + N) % N, gy = (y0 + hy - 1 + N) % N;
-            const uint32_t go = (uint32_t)(gy * N + gx) * (uint32_t)sizeof(T);
-            T v[NC];
-#pragma unroll
-            for (int c = 0; c < NC; c++) v[c] = bld(vi, go, (uint32_t)(c < 12 ? c : c + 6));
-#pragma unroll
-            for (int c = 0; c < NC; c++) lds[c * HS + h] = v[c];
-        }
-    }
+    stage_links2<T, BX, BY>(lds, vi, x0, y0, N, tid);
     __syncthreads();
     const int tx = tid % BX, ty = tid / BX;
     const int x = x0 + tx, y = y0 + ty;
@@ -672,14 +609,16 @@ hipError_t launch_field_step(const Fields<T>& in, const Fields<T>& out, T* gpl, 
                              int* d_step, const LaunchCfg& cfg, hipStream_t st, const KTimer& tm)
 {
     if (cfg.bx <= 0 || cfg.by <= 0 || cfg.waves < 1 || cfg.waves > 4) return hipErrorInvalidValue;
-    if (cfg.split == 3) {
-        // compressed-link LDS tiles of the instantiated shapes
+    if (cfg.split == 3 || cfg.split == 4) {
+        // compressed-link LDS tiles of the instantiated shapes (variant 4, the
+        // fused step, runs as these when it has no particles to push)
         const int r = cfg.xcd_remap, nts = cfg.nt_store;
         if (cfg.bx == 64 && cfg.by == 4) return launch_ctile<T, 64, 4>(in, out, gpl, N, sc, d_step, r, nts, st, tm);
         if (cfg.bx == 32 && cfg.by == 8) return launch_ctile<T, 32, 8>(in, out, gpl, N, sc, d_step, r, nts, st, tm);
         if (cfg.bx == 16 && cfg.by == 16) return launch_ctile<T, 16, 16>(in, out, gpl, N, sc, d_step, r, nts, st, tm);
         if (cfg.bx == 32 && cfg.by == 4) return launch_ctile<T, 32, 4>(in, out, gpl, N, sc, d_step, r, nts, st, tm);
         if (cfg.bx == 64 && cfg.by == 8) return launch_ctile<T, 64, 8>(in, out, gpl, N, sc, d_step, r, nts, st, tm);
+        if (cfg.bx == 8 && cfg.by == 8) return launch_ctile<T, 8, 8>(in, out, gpl, N, sc, d_step, r, nts, st, tm);
         return hipErrorInvalidValue;
     }
     if (cfg.split == 2) {

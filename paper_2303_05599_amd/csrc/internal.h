@@ -85,7 +85,8 @@ struct LaunchCfg {
     int waves = 1;        // register-allocation occupancy target of the field kernel (1 = compiler default)
     int split = 0;        // kernel variant: 0 one thread per site, 1 one thread per link (128 sites per
                           // block), 2 one thread per site with the tile and its halo staged in LDS,
-                          // 3 as 2 with two rows per link in LDS and the scalars from global memory
+                          // 3 as 2 with two rows per link in LDS and the scalars from global memory,
+                          // 4 as 3 with the particle push of the tile in the same kernel (fused.hip)
     int nt_store = 0;     // variant 3 with particles: the new state stored non-temporal
 };
 
@@ -151,6 +152,39 @@ template <typename T>
 hipError_t launch_batch_field(const EventDesc* ev, const int2* map, int total_tiles, const LaunchCfg& cfg,
                               hipStream_t st);
 
+// ---- fused field update and tile push (fused.hip)
+// Variant 4 of the field launch: one workgroup per tile of bx x by sites
+// updates the fields and pushes the particles whose records the last
+// reordering put in the tile's range (records ordered by these tiles);
+// particles that have left their tile since then (stragglers) are pushed by
+// a second kernel that gathers their fields from the buffer sets.
+struct TileParts {
+    const int* tile_start;  // [ntiles + 1]: records of tile t at [tile_start[t], tile_start[t+1])
+    int* strag;             // [np]: stragglers of tile t at strag[tile_start[t] ...]
+    int* strag_count;       // [ntiles]: how many
+    unsigned long long* strag_total;  // running sum of the stragglers pushed (kernel timing), or NULL
+};
+constexpr int kStragTiles = 8;  // tiles per block of the straggler push
+__host__ __device__ inline bool fused_shape(int bx, int by)
+{
+    return (bx == 64 && by == 8) || (bx == 32 && by == 8) || (bx == 16 && by == 16) || (bx == 8 && by == 8);
+}
+__host__ __device__ inline int fused_tiles(int N, int bx, int by) { return ((N + bx - 1) / bx) * ((N + by - 1) / by); }
+// sample groups of the fused step: the tiles, then the straggler blocks
+__host__ __device__ inline int fused_groups(int N, int bx, int by)
+{
+    const int nt = fused_tiles(N, bx, by);
+    return nt + (nt + kStragTiles - 1) / kStragTiles;
+}
+// most sample groups of any fused shape (8 x 8 tiles)
+inline int fused_groups_max(int N) { return fused_groups(N, 8, 8); }
+// A holds the state at step n (read), B receives step n+1; the two timers
+// time the tile kernel and the straggler push
+template <typename T>
+hipError_t launch_fused(const Fields<T>& A, const Fields<T>& B, const LaunchCfg& cfg, const Parts<T>& P,
+                        const PushArgs& a, const TileParts& tp, int* d_step, double* partials, int* err,
+                        hipStream_t st, const KTimer& tm_tile = KTimer{}, const KTimer& tm_strag = KTimer{});
+
 // ---- particle kernels (push.hip)
 // push at t_n: A holds U(n), phi(n), E(n-1/2), pi(n-1/2); B holds E(n+1/2), pi(n+1/2);
 // the fields at a particle's cell are evaluated from them (cellfields.h)
@@ -166,6 +200,11 @@ template <typename T>
 hipError_t launch_force_table(const Fields<T>& A, const Fields<T>& B, const T* gpl, T* table, int N,
                               const Schedule& sc, bool electric_only, const int* d_step, hipStream_t st,
                               const KTimer& tm = KTimer{});
+// the stragglers of the fused step (A, B as for the push, B_eta from the links)
+template <typename T>
+hipError_t launch_stragglers(const Fields<T>& A, const Fields<T>& B, const Parts<T>& P, const PushArgs& a,
+                             const TileParts& tp, int ntiles, int* d_step, double* partials, int ngroups, int* err,
+                             hipStream_t st, const KTimer& tm = KTimer{});
 // dense ensembles: a push that reads the fields at the cell from the force
 // table (one wavefront per 64 particles)
 template <typename T>
@@ -221,9 +260,17 @@ struct SortBufs {
     void* r2 = nullptr;  // [19][np] scratch records
     int *cell2 = nullptr, *pid2 = nullptr;
 };
-size_t sort_temp_bytes(int np, int N);
+size_t sort_temp_bytes(int np);
+// Orders the records by tiles of tx x ty cells (keys from the nearest grid
+// point of the position with from_position, else from the cell); with
+// tile_start ([ntiles + 1]) also the range of records of every tile.  The
+// sorted keys stay in b.keys2 (launch_tile_start rebuilds the ranges from them).
 template <typename T>
-hipError_t sort_particles(const SortBufs& b, T* r, int* cell, int* pid, int np, int N, hipStream_t st);
+hipError_t sort_particles(const SortBufs& b, T* r, int* cell, int* pid, int np, int N, int tx, int ty,
+                          bool from_position, int* tile_start, hipStream_t st);
+hipError_t launch_tile_start(const unsigned* sorted_keys, int np, int N, int tx, int ty, int* tile_start,
+                             hipStream_t st);
+constexpr int kGatherSortTile = 16;  // the gather push's order: 16 x 16 cell tiles
 constexpr int kSortEvery = 16;  // steps between reorderings of moving particles (measured best of 8, 16, 32, 64)
 
 // ---- initial condition (ic.hip), always double precision

@@ -8,100 +8,11 @@
 // pi(n +- 1/2), (3) takes one explicit Euler step.  On recording steps the
 // block writes double-precision partial sums of the broadening; a second
 // small kernel adds the block partials in a fixed order.
-#include "cellfields.h"
 #include "reduce.h"
+#include "wong.h"
 
 namespace cpic {
 
-
-// components of A^+ Q A
-template <typename T> __device__ __forceinline__ a8<T> rotate(const m3<T>& A, const a8<T>& Q) { return transport_adj(A, Q); }
-
-// Replace the spectrum of Q by the sorted spectrum of Q0 (keeps the
-// eigenvectors): restores both classical Casimirs exactly.  Written with
-// compile-time indices only (no private arrays indexed at run time).
-template <typename T> __device__ __forceinline__ void null_vector(const m3<T>& H, T l, cx<T>* v)
-{
-    // rows of H - l: the cross product of two rows is orthogonal to both;
-    // keep the largest of the three choices
-    cx<T> m[9];
-#pragma unroll
-    for (int q = 0; q < 9; q++) m[q] = H.e[q];
-    m[0].re -= l; m[4].re -= l; m[8].re -= l;
-    T best = T(-1);
-#pragma unroll
-    for (int pr = 0; pr < 3; pr++) {
-        const int ra = pr == 2 ? 1 : 0, rb = pr == 0 ? 1 : 2;
-        cx<T> c[3];
-#pragma unroll
-        for (int j = 0; j < 3; j++) {
-            const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
-            const cx<T> u = cmul(m[3 * ra + j1], m[3 * rb + j2]), w = cmul(m[3 * ra + j2], m[3 * rb + j1]);
-            c[j] = {u.re - w.re, u.im - w.im};
-        }
-        const T nn = c[0].re * c[0].re + c[0].im * c[0].im + c[1].re * c[1].re + c[1].im * c[1].im +
-                     c[2].re * c[2].re + c[2].im * c[2].im;
-        const bool take = nn > best;
-        best = take ? nn : best;
-#pragma unroll
-        for (int j = 0; j < 3; j++) v[j] = take ? c[j] : v[j];
-    }
-}
-template <typename T> __device__ a8<T> renorm_charge(const a8<T>& Q, const double* eig0)
-{
-    const m3<T> H = herm(Q);
-    const T p = T(0.25) * dot(Q, Q);  // Tr H^2 / 2
-    if (!(p > T(0))) return Q;
-    // det H
-    const cx<T> d0 = cmul(H.e[4], H.e[8]), d1 = cmul(H.e[5], H.e[7]);
-    const cx<T> e0 = cmul(H.e[3], H.e[8]), e1 = cmul(H.e[5], H.e[6]);
-    const cx<T> f0 = cmul(H.e[3], H.e[7]), f1 = cmul(H.e[4], H.e[6]);
-    const T det = cmul(H.e[0], {d0.re - d1.re, d0.im - d1.im}).re - cmul(H.e[1], {e0.re - e1.re, e0.im - e1.im}).re +
-                  cmul(H.e[2], {f0.re - f1.re, f0.im - f1.im}).re;
-    const T r = sqrt(p / T(3));
-    T arg = det / (T(2) * r * r * r);
-    arg = arg > T(1) ? T(1) : (arg < T(-1) ? T(-1) : arg);
-    const T th = acos(arg) / T(3);
-    // roots 2r cos(th - 2 pi k/3) with th in [0, pi/3]: k = 0 largest,
-    // k = 1 middle, k = 2 smallest
-    const T mid = T(2) * r * cos(th - T(2.0943951023931954923));
-    const T lo = T(2) * r * cos(th - T(4.1887902047863909846));
-    cx<T> v0[3], v1[3], v2[3];
-    null_vector(H, lo, v0);
-    null_vector(H, mid, v1);
-    T n0 = 0;
-#pragma unroll
-    for (int j = 0; j < 3; j++) n0 += v0[j].re * v0[j].re + v0[j].im * v0[j].im;
-    const T i0 = T(1) / sqrt(n0);
-#pragma unroll
-    for (int j = 0; j < 3; j++) { v0[j].re *= i0; v0[j].im *= i0; }
-    cx<T> ip = {0, 0};
-#pragma unroll
-    for (int j = 0; j < 3; j++) { const cx<T> q = ccmul(v0[j], v1[j]); ip.re += q.re; ip.im += q.im; }
-    T n1 = 0;
-#pragma unroll
-    for (int j = 0; j < 3; j++) {
-        const cx<T> q = cmul(ip, v0[j]);
-        v1[j].re -= q.re; v1[j].im -= q.im;
-        n1 += v1[j].re * v1[j].re + v1[j].im * v1[j].im;
-    }
-    const T i1 = T(1) / sqrt(n1);
-#pragma unroll
-    for (int j = 0; j < 3; j++) { v1[j].re *= i1; v1[j].im *= i1; }
-#pragma unroll
-    for (int j = 0; j < 3; j++) {  // v2 = conj(v0 x v1)
-        const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
-        const cx<T> u = cmul(v0[j1], v1[j2]), w = cmul(v0[j2], v1[j1]);
-        v2[j] = {u.re - w.re, -(u.im - w.im)};
-    }
-    // Q' = sum_k eig0_k v_k v_k^+, only the upper triangle is needed
-    const T l0 = T(eig0[0]), l1 = T(eig0[1]), l2 = T(eig0[2]);
-    auto ent = [&](int i, int j) {
-        const cx<T> a = cmulc(v0[i], v0[j]), b = cmulc(v1[i], v1[j]), c = cmulc(v2[i], v2[j]);
-        return cx<T>{l0 * a.re + l1 * b.re + l2 * c.re, l0 * a.im + l1 * b.im + l2 * c.im};
-    };
-    return herm_comp(ent(0, 0), ent(1, 1), ent(2, 2), ent(0, 1), ent(0, 2), ent(1, 2));
-}
 
 // Sub-job placement.  The TPP waves that share a group of 64 particles split
 // the eight sub-jobs of the colour fields (cellfields.h); the owner wave
@@ -213,19 +124,24 @@ template <int TPP> constexpr int kPushPPB = push_block_threads(TPP) / TPP;  // p
 //
 // TABLE reads the six field vectors at the cell from the per-site force
 // table of this step (force_table_kernel) instead of evaluating them: the
-// choice for dense ensembles, where several particles share a cell.
-template <typename T, int TPP, bool LOGQ, bool TABLE = false>
-__device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& Bf, const T* gpl, const Parts<T>& P,
-                                          const PushArgs& a, int n, double* partials, int* err, int blk,
-                                          const T* table = nullptr)
+// choice for dense ensembles, where several particles share a cell.  GL forms
+// the B_eta sub-jobs from the links (no plaquette field; the straggler push
+// of the fused step, fused.hip).
+//
+// push_particle: particle p (live: p is a particle) on the owner lane of its
+// group, its broadening terms added to obs on recording steps; every wave of
+// the block calls it (one barrier inside with more than one wave per group).
+template <typename T, int TPP, bool LOGQ, bool TABLE = false, bool GL = false>
+__device__ __forceinline__ void push_particle(const Fields<T>& Af, const Fields<T>& Bf, const T* gpl,
+                                              const Parts<T>& P, const PushArgs& a, int n, int* err, int p, bool live,
+                                              double (&obs)[4], const T* table = nullptr)
 {
-    if (n < a.sc.n_form || n >= a.sc.n_max) return;  // uniform over the event
+    static_assert(!(GL && (TPP == 4 || TABLE)), "B_eta from the links: generic sub-job placements only");
     constexpr int PPB = kPushPPB<TPP>;
     constexpr int NG = PPB / 64;                     // particle groups per block
     constexpr int S = kSlots<TPP>;
     const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
     const int role = wave % TPP, grp = wave / TPP;
-    const int p = blk * PPB + grp * 64 + lane;
     // helper-wave field vectors: row ((grp * (TPP-1) + role-1) * S + slot) * 8 + a
     __shared__ T shF[TPP > 1 ? NG * (TPP - 1) * S * 8 : 1][64];
     const int N = a.N, np = a.np;
@@ -234,72 +150,17 @@ __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& 
     const View<T> Gv = make_view<T>(gpl, kPlaqReals, V);
     const View<T> R = make_view<T>(P.r, kPartReals, (uint32_t)np);
     const View<int> C = make_view<int>(P.cell, 2, (uint32_t)np);
-    const T dt = T(a.sc.dt), t = T(n * a.sc.dt);
-    const int record_slot = is_record_step(a.sc, n) ? record_slot_of(a.sc, n) : -1;
+    const T t = T(n * a.sc.dt);
+    const bool record = is_record_step(a.sc, n);
     const bool renorm = is_reunit_step(a.sc, n);
     const bool eonly = a.is_static != 0;
-    const bool live = p < np;
     const uint32_t po = (uint32_t)(live ? p : 0) * sizeof(T), pi = (uint32_t)(live ? p : 0) * sizeof(int);
-    int nx = 0, ny = 0;
-    T x = 0, y = 0;
-    if (a.is_static) {
-        nx = bld_i(C, pi, 0);
-        ny = bld_i(C, pi, 1);
-    } else {
-        x = bld(R, po, PX_);
-        y = bld(R, po, PY_);
-        nx = (int)floor(x + T(0.5));
-        ny = (int)floor(y + T(0.5));
-        nx = nx >= N ? nx - N : nx;
-        ny = ny >= N ? ny - N : ny;
-    }
-    const Cell cell = make_cell<T>(nx, ny, N);
-    a8<T> Q;
+    Particle<T> s;
+    particle_cell(R, C, po, pi, N, a.is_static != 0, s);
+    const Cell cell = make_cell<T>(s.nx, s.ny, N);
     T f[6] = {0, 0, 0, 0, 0, 0};
-    T px = 0, py = 0, pe = 0, eta = 0, pt_ode = 0;
     if (role == 0) {
-#pragma unroll
-        for (int q = 0; q < 8; q++) Q.v[q] = bld(R, po, PQ0 + q);
-        px = bld(R, po, PPX);
-        py = bld(R, po, PPY);
-        pe = bld(R, po, PPETA);
-        eta = bld(R, po, PETA_);
-        if (!a.is_static) pt_ode = bld(R, po, PPTAU);
-        if (!LOGQ && !a.is_static && live && n > a.sc.n_form) {
-            // the links crossed since the last step (x first, then y from the
-            // new column) and the scalar at the cell, gathered together
-            const int cx = bld_i(C, pi, 0), cy = bld_i(C, pi, 1);
-            const T deta = bld(R, po, PDETA);
-            int dx = nx - cx, dy = ny - cy;
-            dx = dx > N / 2 ? dx - N : (dx < -N / 2 ? dx + N : dx);
-            dy = dy > N / 2 ? dy - N : (dy < -N / 2 ? dy + N : dy);
-            if (dx < -1 || dx > 1) atomicAdd(err, 1);
-            if (dy < -1 || dy > 1) atomicAdd(err, 1);
-            // (with eight waves per group the owner has time to spare: it
-            // takes the links one at a time, which keeps its registers low)
-            m3<T> Lx, Ly;
-            if (dx != 0) Lx = vU(A, (uint32_t)(cy * N + (dx > 0 ? cx : wrap(cx - 1, N))) * (uint32_t)sizeof(T), 0);
-            if (TPP == 8) {
-                if (dx == 1) Q = rotate(Lx, Q);
-                else if (dx == -1) Q = transport(Lx, Q);
-                CPIC_PHASE();
-            }
-            if (dy != 0) Ly = vU(A, (uint32_t)((dy > 0 ? cy : wrap(cy - 1, N)) * N + nx) * (uint32_t)sizeof(T), 1);
-            const a8<T> ph = vA(A, cell.s, kCompPhi);
-            if (TPP != 8) {
-                if (dx == 1) Q = rotate(Lx, Q);
-                else if (dx == -1) Q = transport(Lx, Q);  // U Q U^+
-            }
-            if (dy == 1) Q = rotate(Ly, Q);
-            else if (dy == -1) Q = transport(Ly, Q);
-            if (TPP == 8) CPIC_PHASE();
-            if (deta != T(0)) Q = rotate(expi(ph, deta), Q);
-        }
-        // charges are renormalised in single precision only (double-precision
-        // contexts never schedule it); leaving it out of the double kernel
-        // also keeps its trigonometric calls from needing scratch memory
-        if constexpr (sizeof(T) == 4 && !LOGQ)
-            if (!a.is_static && renorm && live) Q = renorm_charge(Q, a.q0eig);
+        particle_load_rotate<T, LOGQ, TPP == 8>(A, R, C, po, pi, cell, a, n, live, renorm, err, s);
         CPIC_PHASE();
         if (TABLE && live) {
             // all six table vectors gathered at once (one memory round trip)
@@ -308,22 +169,22 @@ __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& 
 #pragma unroll
             for (int j = 0; j < kJobs; j++) tv[j] = vA(TV, cell.s, 8 * (uint32_t)j);
 #pragma unroll
-            for (int j = 0; j < kJobs; j++) f[j] += job_active(j, n, eonly) ? dot(Q, tv[j]) : T(0);
+            for (int j = 0; j < kJobs; j++) f[j] += job_active(j, n, eonly) ? dot(s.Q, tv[j]) : T(0);
         } else if constexpr (!TABLE && TPP <= 2) {
             // the owner's own sub-jobs (one or two waves per group)
             if (live) {
 #pragma unroll 1
                 for (int k = 0; k < kSubJobs; k++) {
-                    if ((subjob_place<TPP>(k) >> 4) != 0 || !subjob_active(k, n, eonly)) continue;
+                    if ((subjob_place<TPP>(k) >> 4) != 0 || !subjob_active<GL>(k, n, eonly)) continue;
                     CPIC_PHASE();
-                    const T dq = dot(Q, subjob<T>(k, A, B, Gv, cell, n, t));
+                    const T dq = dot(s.Q, subjob<T, GL>(k, A, B, Gv, cell, n, t));
                     const int j = subjob_field(k);
 #pragma unroll
                     for (int jj = 0; jj < kJobs; jj++) f[jj] += jj == j ? dq : T(0);
                 }
             }
         }
-    } else if (TPP == 4) {
+    } else if constexpr (TPP == 4) {
         helper4<T>(role, A, B, Gv, cell, n, t, eonly, shF, (grp * (TPP - 1) + role - 1) * S * 8, lane, live);
     } else if (TPP > 1) {
         // a helper wave: its sub-jobs, accumulated into its LDS slots (the
@@ -335,9 +196,9 @@ __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& 
 #pragma unroll
         for (int k = 0; k < kSubJobs; k++) {
             const int pl = subjob_place<TPP>(k);
-            if ((pl >> 4) != role || !subjob_active(k, n, eonly)) continue;
+            if ((pl >> 4) != role || !subjob_active<GL>(k, n, eonly)) continue;
             if (TPP < 8) CPIC_PHASE();
-            const a8<T> F = subjob<T>(k, A, B, Gv, cell, n, t);
+            const a8<T> F = subjob<T, GL>(k, A, B, Gv, cell, n, t);
             const int r = row0 + (pl & 15) * 8;
 #pragma unroll
             for (int q = 0; q < 8; q++) shF[r + q][lane] += live ? F.v[q] : T(0);
@@ -350,96 +211,41 @@ __device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& 
 #pragma unroll
             for (int k = 0; k < kSubJobs; k++) {
                 const int pl = subjob_place<TPP>(k);
-                bool first = (pl >> 4) != 0;
+                bool first = (pl >> 4) != 0 && !(GL && k > 5);
 #pragma unroll
                 for (int i = 0; i < k; i++)
                     if (subjob_place<TPP>(i) == pl) first = false;
                 if (!first) continue;
                 const int r = ((grp * (TPP - 1) + (pl >> 4) - 1) * S + (pl & 15)) * 8;
-                T dq = Q.v[0] * shF[r][lane];
+                T dq = s.Q.v[0] * shF[r][lane];
 #pragma unroll
-                for (int q = 1; q < 8; q++) dq = fmaT(Q.v[q], shF[r + q][lane], dq);
+                for (int q = 1; q < 8; q++) dq = fmaT(s.Q.v[q], shF[r + q][lane], dq);
                 const int j = subjob_field(k);
 #pragma unroll
                 for (int jj = 0; jj < kJobs; jj++) f[jj] += jj == j ? dq : T(0);
             }
         }
     }
+    if (role == 0 && live) particle_update<T, LOGQ>(A, R, C, po, pi, cell, a, n, renorm, record, f, s, obs);
+}
+
+// one particle per owner lane, particle blk * PPB + grp * 64 + lane; the
+// owner wave of each group of 64 writes the group's sums on recording steps
+template <typename T, int TPP, bool LOGQ, bool TABLE = false>
+__device__ __forceinline__ void push_body(const Fields<T>& Af, const Fields<T>& Bf, const T* gpl, const Parts<T>& P,
+                                          const PushArgs& a, int n, double* partials, int* err, int blk,
+                                          const T* table = nullptr)
+{
+    if (n < a.sc.n_form || n >= a.sc.n_max) return;  // uniform over the event
+    constexpr int NG = kPushPPB<TPP> / 64;
+    const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+    const int role = wave % TPP, grp = wave / TPP;
+    const int p = blk * kPushPPB<TPP> + grp * 64 + lane;
     double obs[4] = {0, 0, 0, 0};
-    if (role == 0 && live) {
-        if (a.is_static) {
-            px += dt * f[0];
-            py += dt * f[1];
-            pe += dt * f[2];  // p^z of the static branch
-            bst(R, po, PPX, px); bst(R, po, PPY, py); bst(R, po, PPETA, pe);
-        } else {
-            const T e1 = f[0], e2 = f[1], ee = f[2], b1 = f[3], b2 = f[4], be = f[5];
-            const T mh = T(a.mhat);
-            const T ptau = sqrt(px * px + py * py + (t * pe) * (t * pe) + mh * mh);
-            const T v1 = px / ptau, v2 = py / ptau, vl = t * pe / ptau;
-            const T npx = px + dt * (e1 + be * v2 - b2 * vl);
-            const T npy = py + dt * (e2 - be * v1 + b1 * vl);
-            const T npe = n > 0 ? pe + dt * (ee - b1 * v2 + b2 * v1 - T(2) * pe) / t : pe;
-            // p^tau from its own equation of motion [eq:ptaueq] (Euler, with the
-            // integrated value on the right-hand side), started from the
-            // constraint at the formation step
-            const T pt = n == a.sc.n_form ? ptau : pt_ode;
-            const T npt = pt + dt * (ee * t * pe + e1 * px + e2 * py - t * pe * pe) / pt;
-            if constexpr (LOGQ) {
-                // Q_{n+1} = Q_n + dt i[Q_n, M_n]
-                CPIC_PHASE();
-                const int lx = min((int)floor(x), N - 1), ly = min((int)floor(y), N - 1);
-                constexpr T tol = sizeof(T) == 8 ? T(1e-15) : T(1e-7);
-                const a8<T> gx = link_generator(vU(A, (uint32_t)(ny * N + lx) * (uint32_t)sizeof(T), 0), tol, 50);
-                const a8<T> gy = link_generator(vU(A, (uint32_t)(ly * N + nx) * (uint32_t)sizeof(T), 1), tol, 50);
-                const a8<T> ph = vA(A, cell.s, kCompPhi);
-                const T veta = pe / ptau;
-                a8<T> M;
-#pragma unroll
-                for (int c = 0; c < 8; c++) M.v[c] = v1 * gx.v[c] + v2 * gy.v[c] + veta * ph.v[c];
-                const a8<T> dq = icomm(Q, M);
-#pragma unroll
-                for (int c = 0; c < 8; c++) Q.v[c] += dt * dq.v[c];
-            }
-            T xn = x + dt * v1, yn = y + dt * v2;
-            if (xn >= T(N)) xn -= T(N); else if (xn < T(0)) xn += T(N);
-            if (yn >= T(N)) yn -= T(N); else if (yn < T(0)) yn += T(N);
-            const T deta = dt * pe / ptau;
-            eta += deta;
-            px = npx; py = npy; pe = npe;
-            bst(R, po, PX_, xn); bst(R, po, PY_, yn); bst(R, po, PETA_, eta);
-            bst(R, po, PPX, px); bst(R, po, PPY, py); bst(R, po, PPETA, pe); bst(R, po, PDETA, deta);
-            bst(R, po, PPTAU, npt);
-            bst_i(C, pi, 0, nx);
-            bst_i(C, pi, 1, ny);
-            if (LOGQ || n > a.sc.n_form || renorm) {
-#pragma unroll
-                for (int q = 0; q < 8; q++) bst(R, po, PQ0 + q, Q.v[q]);
-            }
-        }
-        if (record_slot >= 0) {
-            const T ux0 = bld(R, po, PUX0), uy0 = bld(R, po, PUY0), pt0 = bld(R, po, PPT0);
-            const double dpx = px, dpy = py, tn = (double)(n + 1) * a.sc.dt;
-            double pz;
-            if (a.is_static) {
-                pz = pe;
-            } else {
-                const double dpe = pe, et = eta;
-                const double ptn = sqrt(dpx * dpx + dpy * dpy + (tn * dpe) * (tn * dpe) + a.mhat * a.mhat);
-                pz = ptn * sinh(et) + tn * dpe * cosh(et);
-            }
-            const double par = dpx * (double)ux0 + dpy * (double)uy0;
-            const double perp = -dpx * (double)uy0 + dpy * (double)ux0;
-            const double p02 = (double)pt0 * (double)pt0;
-            obs[0] = dpx * dpx + dpy * dpy - p02;
-            obs[1] = pz * pz;
-            obs[2] = par * par - p02;
-            obs[3] = perp * perp;
-        }
-    }
-    if (record_slot >= 0 && role == 0) {
-        const int ngroups = (np + 63) / 64, group = blk * NG + grp;
-        double* dst = partials + ((size_t)record_slot * ngroups + group) * 4;
+    push_particle<T, TPP, LOGQ, TABLE>(Af, Bf, gpl, P, a, n, err, p, p < a.np, obs, table);
+    if (is_record_step(a.sc, n) && role == 0) {
+        const int ngroups = (a.np + 63) / 64, group = blk * NG + grp;
+        double* dst = partials + ((size_t)record_slot_of(a.sc, n) * ngroups + group) * 4;
 #pragma unroll
         for (int c = 0; c < 4; c++) {
             const double v = wave_sum(obs[c]);
@@ -612,6 +418,74 @@ hipError_t launch_push(const Fields<T>& A, const Fields<T>& B, const T* gpl, con
         launch_push_t<T, false>(A, B, gpl, P, a, d_step, partials, err, st, tm);
     return hipGetLastError();
 }
+
+// The particles that left their tile since the last reordering: blocks of
+// eight waves (one group of 64 particles, one B_eta part or field per wave,
+// above) over the stragglers of kStragTiles consecutive tiles, in list
+// order.  Advances the step counter like the push.
+template <typename T>
+__global__ __launch_bounds__(512) void straggler_kernel(Fields<T> Af, Fields<T> Bf, Parts<T> P, PushArgs a,
+                                                        TileParts tp, int ntiles, int* d_step, double* partials,
+                                                        int ngroups, int* err)
+{
+    constexpr int TB = kStragTiles;
+    const int nb = (ntiles + TB - 1) / TB, blk = (int)blockIdx.x;
+    if (blk >= nb) return;
+    const int n = push_step(d_step, blk);
+    if (n < a.sc.n_form || n >= a.sc.n_max) return;  // uniform
+    __shared__ int pre[TB + 1];
+    const int t0 = blk * TB;
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int j = 0; j < TB; j++) {
+            pre[j] = acc;
+            acc += t0 + j < ntiles ? tp.strag_count[t0 + j] : 0;
+        }
+        pre[TB] = acc;
+    }
+    __syncthreads();
+    const int K = pre[TB], lane = (int)threadIdx.x & 63;
+    if (tp.strag_total && threadIdx.x == 0 && K > 0) atomicAdd(tp.strag_total, (unsigned long long)K);
+    double obs[4] = {0, 0, 0, 0};
+    for (int c0 = 0; c0 < K; c0 += 64) {
+        const int i = c0 + lane;
+        bool live = i < K;
+        int p = 0;
+        if (live) {
+            int j = 0;
+            while (j + 1 < TB && pre[j + 1] <= i) j++;
+            const int k = tp.tile_start[t0 + j] + (i - pre[j]);
+            p = k >= 0 && k < a.np ? tp.strag[k] : -1;
+            live = p >= 0 && p < a.np;
+        }
+        push_particle<T, 8, false, false, true>(Af, Bf, nullptr, P, a, n, err, p, live, obs);
+        __syncthreads();  // the next chunk rewrites the helpers' LDS slots
+    }
+    if (is_record_step(a.sc, n) && threadIdx.x < 64) {
+        double* dst = partials + ((size_t)record_slot_of(a.sc, n) * ngroups + ntiles + blk) * 4;
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            const double v = wave_sum(obs[c]);
+            if (lane == 0) dst[c] = v;
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_stragglers(const Fields<T>& A, const Fields<T>& B, const Parts<T>& P, const PushArgs& a,
+                             const TileParts& tp, int ntiles, int* d_step, double* partials, int ngroups, int* err,
+                             hipStream_t st, const KTimer& tm)
+{
+    const int nb = (ntiles + kStragTiles - 1) / kStragTiles;
+    klaunch(tm, straggler_kernel<T>, dim3(nb), dim3(512), st, A, B, P, a, tp, ntiles, d_step, partials, ngroups, err);
+    return hipGetLastError();
+}
+template hipError_t launch_stragglers<double>(const Fields<double>&, const Fields<double>&, const Parts<double>&,
+                                              const PushArgs&, const TileParts&, int, int*, double*, int, int*,
+                                              hipStream_t, const KTimer&);
+template hipError_t launch_stragglers<float>(const Fields<float>&, const Fields<float>&, const Parts<float>&,
+                                             const PushArgs&, const TileParts&, int, int*, double*, int, int*,
+                                             hipStream_t, const KTimer&);
 
 // step end of an event without particles (no push): advance the step counter
 __global__ void step_advance_kernel(int* d_step)

@@ -1,43 +1,67 @@
 // sort.hip -- periodic reordering of the particle records by lattice cell.
 //
-// The push gathers the fields around each particle's nearest grid point.
-// Particles are ordered by 16 x 16 cell tiles (tile-major, then row-major
-// inside the tile): the 64 lanes of a wavefront and the workgroups that run
-// together on one XCD then read a compact patch of the lattice, whose cache
-// lines (16 sites of one row in double precision) they share.  The order is
-// found with a stable radix sort of the cell keys (deterministic), the
+// The push gathers the fields around each particle's nearest grid point, and
+// the fused step (fused.hip) pushes the particles of a tile in the workgroup
+// that updates the tile.  Particles are ordered by tiles of tx x ty cells
+// (tile-major, then row-major inside the tile): 16 x 16 for the gather push,
+// whose wavefronts and the workgroups that run together on one XCD then read
+// a compact patch of the lattice, and the fused kernel's own tile shape for
+// the fused step, which also receives the range of records of every tile.
+// The key of a moving particle is its nearest grid point at the step the
+// order is made for (from its position), of a static one its cell.  The order
+// comes from a stable radix sort of the keys (rocPRIM, deterministic); the
 // records are permuted into a scratch copy and copied back so that buffer
 // addresses (captured in HIP graphs) never change.  pid tracks each record's
 // original index for state exchange.
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include "internal.h"
 
 namespace cpic {
 
-constexpr int kSortTX = 16, kSortTY = 16;  // measured best of 16x16, 32x8, 32x4, 64x4, 128x2 (FP64 512^2)
-
-__host__ __device__ inline unsigned sort_key_bound(int N)
+__host__ __device__ inline unsigned sort_key_bound(int N, int tx, int ty)
 {
-    const unsigned ntx = (unsigned)((N + kSortTX - 1) / kSortTX), nty = (unsigned)((N + kSortTY - 1) / kSortTY);
-    return ntx * nty * kSortTX * kSortTY;
+    return (unsigned)fused_tiles(N, tx, ty) * (unsigned)(tx * ty);
 }
-static int key_bits(int N)
+static int key_bits(int N, int tx, int ty)
 {
     int bits = 1;
-    while ((1u << bits) < sort_key_bound(N)) bits++;
+    while (bits < 32 && (1u << bits) < sort_key_bound(N, tx, ty)) bits++;
     return bits;
 }
 
-__global__ void cell_keys_kernel(const int* __restrict__ cell, int np, int N, unsigned* keys, int* vals)
+template <typename T>
+__global__ void cell_keys_kernel(const T* __restrict__ r, const int* __restrict__ cell, int np, int N, int tx, int ty,
+                                 int from_position, unsigned* keys, int* vals)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
-    const int cx = cell[p], cy = cell[np + p];
-    const int ntx = (N + kSortTX - 1) / kSortTX;
-    const int tile = (cy / kSortTY) * ntx + cx / kSortTX;
-    keys[p] = (unsigned)(tile * kSortTX * kSortTY + (cy % kSortTY) * kSortTX + cx % kSortTX);
+    int cx, cy;
+    if (from_position) {
+        // the nearest grid point as the push computes it
+        const int nx = (int)floor(r[(size_t)PX_ * np + p] + T(0.5)), ny = (int)floor(r[(size_t)PY_ * np + p] + T(0.5));
+        cx = nx >= N ? nx - N : nx;
+        cy = ny >= N ? ny - N : ny;
+    } else {
+        cx = cell[p];
+        cy = cell[np + p];
+    }
+    const int ntx = (N + tx - 1) / tx;
+    const int tile = (cy / ty) * ntx + cx / tx;
+    keys[p] = (unsigned)(tile * tx * ty + (cy % ty) * tx + cx % tx);
     vals[p] = p;
+}
+
+// tile_start[t] = first record of tile t (or of the next non-empty tile),
+// tile_start[ntiles] = np, from the sorted keys; every entry is written once
+__global__ void tile_start_kernel(const unsigned* __restrict__ sorted, int np, unsigned per_tile, int ntiles,
+                                  int* tile_start)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > np) return;
+    const int ti = i < np ? (int)(sorted[i] / per_tile) : ntiles;
+    const int tp = i > 0 ? (int)(sorted[i - 1] / per_tile) : -1;
+    for (int t = tp + 1; t <= ti; t++) tile_start[t] = i;
 }
 
 template <typename T>
@@ -69,33 +93,51 @@ __global__ void copy_back_kernel(const T* __restrict__ r2, const int* __restrict
     pid[i] = pid2[i];
 }
 
-size_t sort_temp_bytes(int np, int N)
+size_t sort_temp_bytes(int np)
 {
     size_t bytes = 0;
-    // size query only: no device work, the status carries nothing more
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (unsigned*)nullptr, (unsigned*)nullptr, (int*)nullptr,
-                                             (int*)nullptr, np, 0, key_bits(N));
+    // size query only (no device work) for the widest keys any tile shape gives
+    (void)rocprim::radix_sort_pairs(nullptr, bytes, (unsigned*)nullptr, (unsigned*)nullptr, (int*)nullptr,
+                                    (int*)nullptr, np, 0u, 32u);
     return bytes;
 }
 
-template <typename T>
-hipError_t sort_particles(const SortBufs& b, T* r, int* cell, int* pid, int np, int N, hipStream_t st)
+hipError_t launch_tile_start(const unsigned* sorted_keys, int np, int N, int tx, int ty, int* tile_start,
+                             hipStream_t st)
 {
-    if (np <= 1) return hipSuccess;
-    const int bits = key_bits(N);
-    const int blocks = (np + 255) / 256;
-    hipLaunchKernelGGL(cell_keys_kernel, dim3(blocks), dim3(256), 0, st, cell, np, N, b.keys, b.vals);
-    size_t bytes = b.temp_bytes;
-    hipError_t e = hipcub::DeviceRadixSort::SortPairs(b.temp, bytes, b.keys, b.keys2, b.vals, b.perm, np, 0, bits, st);
-    if (e != hipSuccess) return e;
-    T* r2 = static_cast<T*>(b.r2);
-    hipLaunchKernelGGL(permute_kernel<T>, dim3(blocks), dim3(256), 0, st, r, cell, pid, b.perm, np, r2, b.cell2,
-                       b.pid2);
-    hipLaunchKernelGGL(copy_back_kernel<T>, dim3(blocks), dim3(256), 0, st, r2, b.cell2, b.pid2, np, r, cell, pid);
-    return hipSuccess;  // launch errors surface at the stream's next synchronisation, as for every kernel
+    if (np <= 0 || !fused_shape(tx, ty)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(tile_start_kernel, dim3((np + 256) / 256), dim3(256), 0, st, sorted_keys, np,
+                       (unsigned)(tx * ty), fused_tiles(N, tx, ty), tile_start);
+    return hipGetLastError();
 }
 
-template hipError_t sort_particles<double>(const SortBufs&, double*, int*, int*, int, int, hipStream_t);
-template hipError_t sort_particles<float>(const SortBufs&, float*, int*, int*, int, int, hipStream_t);
+template <typename T>
+hipError_t sort_particles(const SortBufs& b, T* r, int* cell, int* pid, int np, int N, int tx, int ty,
+                          bool from_position, int* tile_start, hipStream_t st)
+{
+    if (np <= 0 || tx <= 0 || ty <= 0) return np <= 0 ? hipSuccess : hipErrorInvalidValue;
+    const int blocks = (np + 255) / 256;
+    // a single record needs no sort: its key is the sorted key array
+    hipLaunchKernelGGL(cell_keys_kernel<T>, dim3(blocks), dim3(256), 0, st, r, cell, np, N, tx, ty,
+                       from_position ? 1 : 0, np > 1 ? b.keys : b.keys2, b.vals);
+    if (np > 1) {
+        size_t bytes = b.temp_bytes;
+        hipError_t e = rocprim::radix_sort_pairs(b.temp, bytes, b.keys, b.keys2, b.vals, b.perm, np, 0u,
+                                                 (unsigned)key_bits(N, tx, ty), st);
+        if (e != hipSuccess) return e;
+        T* r2 = static_cast<T*>(b.r2);
+        hipLaunchKernelGGL(permute_kernel<T>, dim3(blocks), dim3(256), 0, st, r, cell, pid, b.perm, np, r2, b.cell2,
+                           b.pid2);
+        hipLaunchKernelGGL(copy_back_kernel<T>, dim3(blocks), dim3(256), 0, st, r2, b.cell2, b.pid2, np, r, cell,
+                           pid);
+    }
+    if (tile_start) return launch_tile_start(b.keys2, np, N, tx, ty, tile_start, st);
+    return hipGetLastError();  // launch errors surface at the stream's next synchronisation, as for every kernel
+}
+
+template hipError_t sort_particles<double>(const SortBufs&, double*, int*, int*, int, int, int, int, bool, int*,
+                                           hipStream_t);
+template hipError_t sort_particles<float>(const SortBufs&, float*, int*, int*, int, int, int, int, bool, int*,
+                                          hipStream_t);
 
 }  // namespace cpic

@@ -12,7 +12,8 @@ HIP events attached to every kernel: the per-kernel times of the roofline
 entries); the capture of the step graphs and an alignment of the start to
 four steps before a particle reordering (every 16 steps), so that K = 20
 steps hold one reordering and K = 16 m + 4 hold m + 1.  Timed: K steps of the
-production path (cpic_evolve: the library's 16-step HIP graphs) and the
+production path (cpic_evolve: the library's HIP graphs, one per stretch
+between reorderings, all captured before the timed region) and the
 readout of the broadening samples (their fixed-order reduction and copy to
 the host), with synchronisation on both sides.
 
@@ -55,6 +56,7 @@ JET_BYTES = {"f64": 118 * 8, "f32": 118 * 4}
 # and pi at both half steps (48) read; the six field vectors (48) written
 TABLE_BYTES = {"f64": 128 * 8, "f32": 128 * 4}
 SORT_EVERY = 16          # steps between reorderings of moving particles (the library's constant)
+WATCH_EVERY = 64         # steps between the drift watchdog's checks (the library's default)
 DTAU_FM = 0.125 * 6.0 / 512
 # SU(2) variant: a site holds 20 reals (two quaternion links, phi, E_x, E_y,
 # pi), read and written once; a push moves its record (13 words each way: the
@@ -92,9 +94,9 @@ def formation_step(particles):
 def plan_steps(steps, warmup, n_form, n_max=1024):
     """Untimed steps before the timed region: the warm-up (at least up to the
     first push step), the kernel-timing stretch (up to 128 steps) and the
-    graph and alignment steps (32 + up to 15; see run_event)."""
+    graph and alignment steps (at most 2 x 15 + 35 + 48; see run_event)."""
     w = max(warmup, n_form + 1)
-    spare = n_max - w - steps - 48
+    spare = n_max - w - steps - 114
     if spare < 16:
         sys.exit(f"--steps {steps} with a warm-up of {w} steps (past formation at step {n_form}) leaves no room for "
                  f"the kernel-timing stretch within the {n_max} steps to tau = 1.5 fm/c")
@@ -107,8 +109,8 @@ def run_event(precision, steps, warmup, tune=True, particles=None, jets=False, n
     first push step, the launch tuner, a kernel-timing stretch (eager launches
     with HIP events attached to each kernel: the per-kernel times of the
     roofline entries), graph capture and alignment, then the timed region:
-    `steps` steps of the production path (the 16-step HIP graphs of
-    cpic_evolve) and the readout of the samples.  The timed region comes
+    `steps` steps of the production path (the HIP graphs of cpic_evolve)
+    and the readout of the samples.  The timed region comes
     last, so a profiler's last `steps` dispatches of each kernel are exactly
     the timed ones."""
     import torch
@@ -146,12 +148,20 @@ def run_event(precision, steps, warmup, tune=True, particles=None, jets=False, n
     if jets:
         tm.update(ctx.jets_timing())
     ctx.set_timing(False)
-    # graph capture: a graph of 16 steps starts at every reordering point
-    # (multiples of 16); evolve to the second such point so that the graph of
-    # that buffer parity is built, then step to four steps before the next one
-    n = ctx.n
-    ctx.evolve(((n // SORT_EVERY + 2) * SORT_EVERY) * DTAU_FM * (1 - 1e-12))
+    # graph capture: cpic_evolve replays one graph per stretch between
+    # reordering points (multiples of 16).  The timed region starts four steps
+    # before such a point; the same stretch pattern (4, 16, the remainder) is
+    # run once untimed from the same alignment, which captures every graph the
+    # timed region replays
     ctx.step((SORT_EVERY - 4 - ctx.n % SORT_EVERY) % SORT_EVERY)
+    pre = steps if steps <= 4 + SORT_EVERY else 4 + SORT_EVERY + (steps - 4) % SORT_EVERY
+    ctx.evolve((ctx.n + pre) * DTAU_FM * (1 - 1e-12))
+    ctx.step((SORT_EVERY - 4 - ctx.n % SORT_EVERY) % SORT_EVERY)
+    # a region shorter than the drift watchdog's interval starts where it holds
+    # no check (one in WATCH_EVERY steps, about 40 us at this size): its rate
+    # is then the steady one, as in a long region, where the checks amortise
+    while steps < WATCH_EVERY and (ctx.n + steps) // WATCH_EVERY > ctx.n // WATCH_EVERY:
+        ctx.step(SORT_EVERY)
     # the samples taken so far are summed now, so that the readout in the
     # timed region reduces only the samples of the timed steps
     ctx.observables()
@@ -666,8 +676,11 @@ def main():
         "kernels": kern,
         "eager_ms_per_step": res["eager_ms_per_step"], "kernel_timing_steps": res["kernel_timing_steps"],
         "warmup_steps_run": res["warmup_steps"], "first_timed_step": res["untimed_steps"],
-        "timed_region": "K steps of cpic_evolve (16-step HIP graphs, particle reordering every 16 steps) and the "
-                        "readout of the broadening samples (fixed-order reduction and copy to the host)",
+        "watchdog_checks_in_timed_region": (res["untimed_steps"] + args.steps) // WATCH_EVERY
+                                           - res["untimed_steps"] // WATCH_EVERY,
+        "watchdog_every": WATCH_EVERY,
+        "timed_region": "K steps of cpic_evolve (HIP graphs of up to 16 steps between the particle reorderings "
+                        "every 16 steps; the drift watchdog's checks every 64 steps) and the readout of the broadening samples (fixed-order reduction and copy to the host)",
         "launch": res["launch"],
         "ic_seconds": res["t_ic"],
         "gauss_max": res["diag"][1], "unitarity_max": res["diag"][6],

@@ -39,7 +39,7 @@ typedef int32_t cpic_status;
 #define CPIC_E_HIP (-3)        /* a HIP runtime call failed                         */
 #define CPIC_E_IC_NEWTON (-4)  /* initial-link Newton solve did not converge        */
 #define CPIC_E_NAN (-5)        /* NaN/Inf found by the diagnostics                  */
-#define CPIC_E_DRIFT (-6)      /* unitarity / Gauss / Casimir drift over threshold  */
+#define CPIC_E_DRIFT (-6)      /* unitarity / Gauss / Casimir drift over threshold (cpic_set_watchdog) */
 #define CPIC_E_CAPACITY (-7)   /* caller buffer too small                           */
 #define CPIC_E_CELL_JUMP (-8)  /* a particle moved more than one cell in one step   */
 #define CPIC_E_IO (-9)         /* checkpoint file could not be read or written      */
@@ -151,13 +151,37 @@ cpic_status cpic_init_mv(cpic_ctx* ctx);
  * would pass n_max. */
 cpic_status cpic_step(cpic_ctx* ctx, int32_t n_steps);
 
-/* Advance until tau >= tau_target_fm (or n_max).  Asynchronous; uses HIP graphs
- * for the bulk of the steps.  A no-op if already there. */
+/* Advance until tau >= tau_target_fm (or n_max).  Asynchronous; every step
+ * runs from a HIP graph: graphs of up to 16 steps, each ending at the next
+ * particle reordering point or at the target, captured once per length and
+ * buffer parity and replayed.  A no-op if already there. */
 cpic_status cpic_evolve(cpic_ctx* ctx, double tau_target_fm);
 
 /* Wait for the context's stream; reports CPIC_E_CELL_JUMP if any particle
- * moved more than one cell in one step since the last check. */
+ * moved more than one cell in one step since the last check, and a breach the
+ * drift watchdog found (CPIC_E_DRIFT, or CPIC_E_NAN for a non-finite value;
+ * cpic_last_error names the check, the step and the value).  A reported
+ * breach is cleared. */
 cpic_status cpic_sync(cpic_ctx* ctx);
+
+/* Drift watchdog (on by default, every 64 steps).  After every `every`-th
+ * step the device computes the cpic_diagnostics columns of the state and
+ * compares them, without synchronising, with
+ *   max_unitarity       max |U U^+ - 1| over all link entries (absolute);
+ *   max_gauss_drift     the change of max |G| (the Gauss residual of Sec. II)
+ *                       since the state was installed, relative to max(1, its
+ *                       value then): the leapfrog keeps the lattice Gauss law
+ *                       to rounding;
+ *   max_casimir_drift   the change of max |q2 - q2(R)| and of max |q3 - q3(R)|
+ *                       over the particles ([eq:q2_main], [eq:q3_main]) since
+ *                       installation, relative to max(1, q2(R)) (SU(3) with the
+ *                       rotation update, which keeps the Casimirs);
+ * and any non-finite value.  The baseline is taken before the first step
+ * after cpic_init_mv, cpic_set_state or cpic_load.  The first breach is kept
+ * and reported by the next cpic_sync.  every = 0 switches it off.  Defaults:
+ * 1e-8 for all three in double precision, 1e-2 in single precision. */
+cpic_status cpic_set_watchdog(cpic_ctx* ctx, int32_t every, double max_unitarity, double max_gauss_drift,
+                              double max_casimir_drift);
 
 /* Current step n (tau = n dtau) and the number of broadening samples taken. */
 cpic_status cpic_current_step(const cpic_ctx* ctx, int64_t* n);

@@ -83,6 +83,7 @@ def lib():
             "cpic_tune": [P, i32, P, sz],
             "cpic_timing": [P, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(i64), ctypes.POINTER(i64)],
             "cpic_straggler_pushes": [P, ctypes.POINTER(i64)],
+            "cpic_set_watchdog": [P, i32, d, d, d],
             "cpic_batch_create": [i32, ctypes.POINTER(GlasmaParams), ctypes.POINTER(ParticleParams), P, pp],
             "cpic_batch_init_mv": [P], "cpic_batch_run": [P], "cpic_batch_step": [P, i32], "cpic_batch_sync": [P],
             "cpic_batch_tune": [P, i32, P, sz], "cpic_batch_set_launch": [P, i32, i32, i32, i32],
@@ -261,6 +262,10 @@ class Context:
         """Field-kernel launch; variant 0 site-parallel, 1 link-parallel, 2 LDS halo tiles,
         3 two-row-link LDS tiles, 4 the fused step (tile push, PUSH_TILE)."""
         self._chk(lib().cpic_set_launch(self.h, bx, by, xcd_remap, waves, variant))
+
+    def set_watchdog(self, every=64, max_unitarity=1e-8, max_gauss_drift=1e-8, max_casimir_drift=1e-8):
+        """Drift watchdog every `every` steps (0: off); breaches raise at the next sync."""
+        self._chk(lib().cpic_set_watchdog(self.h, every, max_unitarity, max_gauss_drift, max_casimir_drift))
 
     def set_store_policy(self, non_temporal):
         """New state of the compressed-tile field update stored non-temporal (1) or not (0)."""

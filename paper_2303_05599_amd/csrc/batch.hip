@@ -297,6 +297,8 @@ static cpic_status run_steps(cpic_batch* b, int64_t max_steps)
             int64_t len = budget;
             for (int e : act) {
                 cpic_ctx* c = b->ev[e];
+                s = watch_prepare(c);
+                if (s) return bfail(b, s, "event " + std::to_string(e) + ": " + c->err);
                 s = maybe_sort(c);
                 if (s) return bfail(b, s, "event " + std::to_string(e) + ": " + c->err);
                 len = std::min<int64_t>(len, c->sc.n_max - c->n);

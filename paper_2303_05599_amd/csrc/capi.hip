@@ -90,7 +90,8 @@ static bool valid_N(int N)
 static void free_all(cpic_ctx* c)
 {
     for (int p = 0; p < 2; p++)
-        if (c->gexec[p]) (void)hipGraphExecDestroy(c->gexec[p]);
+        for (int k = 0; k <= kGraphSteps; k++)
+            if (c->gexec[p][k]) (void)hipGraphExecDestroy(c->gexec[p][k]);
     for (auto e : c->ev_field) (void)hipEventDestroy(e);
     for (auto e : c->ev_push) (void)hipEventDestroy(e);
     for (auto e : c->ev_jets) (void)hipEventDestroy(e);
@@ -99,6 +100,8 @@ static void free_all(cpic_ctx* c)
     (void)hipFree(c->jW); (void)hipFree(c->jF); (void)hipFree(c->jpartials); (void)hipFree(c->jobs);
     (void)hipFree(c->fbuf[0]); (void)hipFree(c->fbuf[1]); (void)hipFree(c->pr); (void)hipFree(c->pcell); (void)hipFree(c->gpl);
     (void)hipFree(c->partials); (void)hipFree(c->obs); (void)hipFree(c->d_step); (void)hipFree(c->d_err); (void)hipFree(c->d_fails);
+    (void)hipFree(c->d_watchv); (void)hipFree(c->d_watchbase);
+    if (c->h_stage) (void)hipHostFree(c->h_stage);
     (void)hipFree(c->dpart); (void)hipFree(c->dout);
     (void)hipFree(c->pid); (void)hipFree(c->sb.keys); (void)hipFree(c->sb.keys2); (void)hipFree(c->sb.vals); (void)hipFree(c->sb.perm);
     (void)hipFree(c->sb.temp); (void)hipFree(c->sb.r2); (void)hipFree(c->sb.cell2); (void)hipFree(c->sb.pid2);
@@ -245,7 +248,14 @@ extern "C" cpic_status cpic_create(const cpic_glasma_params* gp, const cpic_part
         if (e == hipSuccess) e = hipMalloc(&c->obs, sizeof(double) * 4 * c->nslots);
     }
     if (e == hipSuccess) e = hipMalloc(&c->d_step, 2 * sizeof(int));
-    if (e == hipSuccess) e = hipMalloc(&c->d_err, sizeof(int));
+    // d_err[0]: cell jumps; d_err[1..2]: the watchdog's flags and step (read
+    // together by cpic_sync)
+    if (e == hipSuccess) e = hipMalloc(&c->d_err, 4 * sizeof(int));
+    c->d_watch = c->d_err + 1;
+    if (e == hipSuccess) e = hipMalloc(&c->d_watchv, 4 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&c->d_watchbase, 10 * sizeof(double));
+    if (e == hipSuccess) e = hipHostMalloc(&c->h_stage, 4 * sizeof(int) + sizeof(double) * 4 * (size_t)c->nslots);
+    if (c->prec == CPIC_FP32) c->watch_thr[0] = c->watch_thr[1] = c->watch_thr[2] = 1e-2;
     if (e == hipSuccess) e = hipMalloc(&c->d_fails, sizeof(int));
     c->dcap = std::max((c->V + 255) / 256, std::max(c->np > 0 ? push_blocks((int)c->np, 1) : 0, 1));
     if (e == hipSuccess) e = hipMalloc(&c->dpart, sizeof(double) * 8 * c->dcap);
@@ -255,7 +265,7 @@ extern "C" cpic_status cpic_create(const cpic_glasma_params* gp, const cpic_part
     double* scratch_dev = nullptr;
     if (e == hipSuccess && noalloc_scratch(&scratch_dev) != CPIC_OK) e = hipErrorInvalidSymbol;
     if (e == hipSuccess) e = hipMemsetAsync(c->d_step, 0, 2 * sizeof(int), c->st);
-    if (e == hipSuccess) e = hipMemsetAsync(c->d_err, 0, sizeof(int), c->st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->d_err, 0, 4 * sizeof(int), c->st);
     if (e == hipSuccess && c->obs) e = hipMemsetAsync(c->obs, 0, sizeof(double) * 4 * c->nslots, c->st);
     if (e == hipSuccess) e = hipStreamSynchronize(c->st);
     if (e != hipSuccess) {
@@ -347,15 +357,17 @@ cpic_status cpic::maybe_sort(cpic_ctx* c)
 static void drop_graphs(cpic_ctx* c)
 {
     for (int p = 0; p < 2; p++)
-        if (c->gexec[p]) {
-            (void)hipGraphExecDestroy(c->gexec[p]);
-            c->gexec[p] = nullptr;
-        }
+        for (int k = 0; k <= kGraphSteps; k++)
+            if (c->gexec[p][k]) {
+                (void)hipGraphExecDestroy(c->gexec[p][k]);
+                c->gexec[p][k] = nullptr;
+            }
 }
 
 static cpic_status reset_counters(cpic_ctx* c, int n)
 {
     c->n = n;
+    c->watch_base_due = true;
     c->samples.clear();
     c->sample_groups.clear();
     c->obs_reduced = 0;
@@ -533,6 +545,8 @@ template <typename T> static cpic_status launch_one(cpic_ctx* c, int parity, boo
     return CPIC_OK;
 }
 
+static cpic_status enqueue_watch(cpic_ctx* c, bool take_base);
+
 // groups of 4 partial sums a sample of the current launch writes
 static int sample_groups_now(const cpic_ctx* c)
 {
@@ -541,6 +555,7 @@ static int sample_groups_now(const cpic_ctx* c)
 
 cpic_status cpic::host_advance(cpic_ctx* c, int k)
 {
+    const int n0 = c->n;
     for (int j = 0; j < k; j++) {
         if (c->np > 0 && is_record_step(c->sc, c->n)) {
             c->samples.push_back({record_slot_of(c->sc, c->n), c->n});
@@ -551,11 +566,15 @@ cpic_status cpic::host_advance(cpic_ctx* c, int k)
         c->n++;
         c->cur ^= 1;
     }
+    // the drift watchdog after every multiple of watch_every steps
+    if (c->watch_every > 0 && c->n / c->watch_every > n0 / c->watch_every) return enqueue_watch(c, false);
     return CPIC_OK;
 }
 
 static cpic_status eager_steps(cpic_ctx* c, int k)
 {
+    cpic_status ws = watch_prepare(c);
+    if (ws) return ws;
     for (int j = 0; j < k; j++) {
         cpic_status so = maybe_sort(c);
         if (so) return so;
@@ -567,18 +586,19 @@ static cpic_status eager_steps(cpic_ctx* c, int k)
     return CPIC_OK;
 }
 
-static cpic_status build_graph(cpic_ctx* c, int parity)
+// a graph of k steps from buffer `parity`
+static cpic_status build_graph(cpic_ctx* c, int parity, int k)
 {
     hipGraph_t g = nullptr;
     HIPCHK(c, hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal), "capture");
     cpic_status s = CPIC_OK;
-    for (int j = 0; j < kGraphSteps && s == CPIC_OK; j++)
+    for (int j = 0; j < k && s == CPIC_OK; j++)
         s = c->prec == CPIC_FP64 ? launch_one<double>(c, parity ^ (j & 1), false)
                                  : launch_one<float>(c, parity ^ (j & 1), false);
     hipError_t e = hipStreamEndCapture(c->st, &g);
     if (s) { if (g) (void)hipGraphDestroy(g); return s; }
     if (e != hipSuccess) return hip_fail(c, e, "end capture");
-    e = hipGraphInstantiate(&c->gexec[parity], g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&c->gexec[parity][k], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return hip_fail(c, e, "graph instantiate");
     return CPIC_OK;
@@ -605,25 +625,22 @@ extern "C" cpic_status cpic_evolve(cpic_ctx* c, double tau_target_fm)
     if (target <= c->n) return CPIC_OK;
     int left = target - c->n;
     if (c->timing) return eager_steps(c, left);
+    cpic_status ws = watch_prepare(c);
+    if (ws) return ws;
     while (left > 0) {
         cpic_status so = maybe_sort(c);
         if (so) return so;
-        if (left < kGraphSteps || next_sort_point(c, c->n) < c->n + kGraphSteps) {
-            // a reorder falls inside the window: advance eagerly up to it
-            const int upto = std::min(left, std::max(1, next_sort_point(c, c->n) - c->n));
-            so = eager_steps(c, std::min(upto, left < kGraphSteps ? left : upto));
-            if (so) return so;
-            left = target - c->n;
-            continue;
-        }
+        // one graph up to the next reordering point, at most kGraphSteps steps
+        // (graphs of each length are captured once per buffer parity)
+        const int k = std::min(std::min(left, kGraphSteps), std::max(1, next_sort_point(c, c->n) - c->n));
         const int parity = c->cur;
-        if (!c->gexec[parity]) {
-            cpic_status s = build_graph(c, parity);
+        if (!c->gexec[parity][k]) {
+            cpic_status s = build_graph(c, parity, k);
             if (s) return s;
         }
-        HIPCHK(c, hipGraphLaunch(c->gexec[parity], c->st), "graph launch");
-        host_advance(c, kGraphSteps);
-        left -= kGraphSteps;
+        HIPCHK(c, hipGraphLaunch(c->gexec[parity][k], c->st), "graph launch");
+        host_advance(c, k);
+        left -= k;
     }
     return CPIC_OK;
 }
@@ -668,16 +685,32 @@ static cpic_status collect_timing(cpic_ctx* c)
 extern "C" cpic_status cpic_sync(cpic_ctx* c)
 {
     if (!c) return fail(nullptr, CPIC_E_INVALID, "cpic_sync: NULL context");
+    // the error words come back with the stream's last work: one synchronisation
+    int* err = static_cast<int*>(c->h_stage);
+    HIPCHK(c, hipMemcpyAsync(err, c->d_err, 3 * sizeof(int), hipMemcpyDeviceToHost, c->st), "cpic_sync");
     HIPCHK(c, hipStreamSynchronize(c->st), "cpic_sync");
     if (c->timing) {
         cpic_status s = collect_timing(c);
         if (s) return s;
     }
-    int err = 0;
-    HIPCHK(c, hipMemcpy(&err, c->d_err, sizeof(int), hipMemcpyDeviceToHost), "cpic_sync");
-    if (err) {
+    if (err[0]) {
         HIPCHK(c, hipMemset(c->d_err, 0, sizeof(int)), "cpic_sync");
-        return fail(c, CPIC_E_CELL_JUMP, std::to_string(err) + " particle moves of more than one cell");
+        return fail(c, CPIC_E_CELL_JUMP, std::to_string(err[0]) + " particle moves of more than one cell");
+    }
+    if (err[1]) {
+        double v[4];
+        HIPCHK(c, hipMemcpy(v, c->d_watchv, sizeof v, hipMemcpyDeviceToHost), "cpic_sync");
+        HIPCHK(c, hipMemset(c->d_watch, 0, 2 * sizeof(int)), "cpic_sync");
+        std::string m = "watchdog after step " + std::to_string(err[2]) + ":";
+        char b[160];
+        if (err[1] & 1) m += " non-finite diagnostics;";
+        if (err[1] & 2) { std::snprintf(b, sizeof b, " unitarity max|UU^+-1| = %.3e > %.1e;", v[0], c->watch_thr[0]); m += b; }
+        if (err[1] & 4) { std::snprintf(b, sizeof b, " Gauss-law drift %.3e > %.1e;", v[1], c->watch_thr[1]); m += b; }
+        if (err[1] & 8) {
+            std::snprintf(b, sizeof b, " Casimir drift q2 %.3e, q3 %.3e > %.1e;", v[2], v[3], c->watch_thr[2]);
+            m += b;
+        }
+        return fail(c, (err[1] & 1) ? CPIC_E_NAN : CPIC_E_DRIFT, m);
     }
     return CPIC_OK;
 }
@@ -686,10 +719,13 @@ extern "C" cpic_status cpic_sync(cpic_ctx* c)
 // obs[slot] (groups in order, fixed-order block reduction).
 static cpic_status reduce_samples(cpic_ctx* c)
 {
-    for (size_t k = (size_t)c->obs_reduced; k < c->samples.size(); k++) {
+    // runs of samples in consecutive slots with one group count: one launch each
+    for (size_t k = (size_t)c->obs_reduced; k < c->samples.size();) {
         const int slot = c->samples[k].first, groups = c->sample_groups[k];
-        HIPCHK(c, launch_reduce_rows(c->partials + (size_t)slot * groups * 4, groups, 4, c->obs + (size_t)slot * 4,
-                                     c->st), "observables");
+        size_t j = k + 1;
+        while (j < c->samples.size() && c->samples[j].first == slot + (int)(j - k) && c->sample_groups[j] == groups) j++;
+        HIPCHK(c, launch_reduce_samples(c->partials, groups, slot, (int)(j - k), c->obs, c->st), "observables");
+        k = j;
     }
     c->obs_reduced = (int)c->samples.size();
     const int jg = jet_groups(c->V);
@@ -723,11 +759,13 @@ extern "C" cpic_status cpic_observables_full(cpic_ctx* c, double* out, int32_t c
                                                       std::to_string(ns) + " samples");
     cpic_status s = reduce_samples(c);
     if (s) return s;
+    const double* h = reinterpret_cast<const double*>(static_cast<char*>(c->h_stage) + 4 * sizeof(int));
+    if (ns && out)
+        HIPCHK(c, hipMemcpyAsync(const_cast<double*>(h), c->obs, sizeof(double) * 4 * (size_t)c->nslots,
+                                 hipMemcpyDeviceToHost, c->st), "observables");
     s = cpic_sync(c);
     if (s) return s;
     if (!ns || !out) return CPIC_OK;
-    std::vector<double> h(4 * (size_t)c->nslots);
-    HIPCHK(c, hipMemcpy(h.data(), c->obs, sizeof(double) * h.size(), hipMemcpyDeviceToHost), "observables");
     const double inv = 1.0 / ((double)c->np * c->a_gev * c->a_gev);
     for (int k = 0; k < ns; k++) {
         const int slot = c->samples[k].first;
@@ -753,10 +791,10 @@ extern "C" cpic_status cpic_observables(cpic_ctx* c, double* tau_fm, double* dpT
     return CPIC_OK;
 }
 
-extern "C" cpic_status cpic_diagnostics(cpic_ctx* c, double out[10])
+// the diagnostics columns of the current state into dout[0..9] (asynchronous;
+// columns 8, 9 only with particles)
+static cpic_status enqueue_diagnostics(cpic_ctx* c)
 {
-    if (!c || !out) return fail(c, CPIC_E_INVALID, "cpic_diagnostics: NULL argument");
-    if (!c->initialised) return fail(c, CPIC_E_INVALID, "cpic_diagnostics: no state");
     int nb = 0;
     hipError_t e;
     if (c->nc == 2)
@@ -769,17 +807,57 @@ extern "C" cpic_status cpic_diagnostics(cpic_ctx* c, double out[10])
                 : launch_field_diag<float>(F<float>(c, c->cur), c->N, c->sc.dt, c->n, c->dpart, c->dcap, &nb, c->st);
     HIPCHK(c, e, "field diagnostics");
     HIPCHK(c, launch_reduce_rows(c->dpart, nb, 8, c->dout, c->st), "reduce");
-    double h[10] = {0};
-    HIPCHK(c, hipStreamSynchronize(c->st), "diagnostics");
-    HIPCHK(c, hipMemcpy(h, c->dout, sizeof(double) * 8, hipMemcpyDeviceToHost), "diagnostics");
     if (c->np > 0) {
         e = c->prec == CPIC_FP64 ? launch_part_diag<double>(P<double>(c), (int)c->np, c->q2ref, c->q3ref, c->dpart, c->st)
                                  : launch_part_diag<float>(P<float>(c), (int)c->np, c->q2ref, c->q3ref, c->dpart, c->st);
         HIPCHK(c, e, "particle diagnostics");
         HIPCHK(c, launch_reduce_rows(c->dpart, push_blocks((int)c->np, 1), 2, c->dout + 8, c->st), "reduce");
-        HIPCHK(c, hipStreamSynchronize(c->st), "diagnostics");
-        HIPCHK(c, hipMemcpy(h + 8, c->dout + 8, sizeof(double) * 2, hipMemcpyDeviceToHost), "diagnostics");
     }
+    return CPIC_OK;
+}
+
+// the watchdog's check of the current state, or its baseline (asynchronous)
+static cpic_status enqueue_watch(cpic_ctx* c, bool take_base)
+{
+    cpic_status s = enqueue_diagnostics(c);
+    if (s) return s;
+    // the charges' Casimirs are kept by the rotation update (SU(3)); the
+    // logarithm update lets them drift by design
+    const bool casimir = c->np > 0 && c->nc == 3 && c->pp.color_update == CPIC_COLOR_ROTATE;
+    HIPCHK(c, launch_watchdog(c->dout, c->d_watchbase, take_base, casimir, c->watch_thr, c->q2ref, c->n, c->d_watch,
+                              c->d_watchv, c->st), "watchdog");
+    return CPIC_OK;
+}
+cpic_status cpic::watch_prepare(cpic_ctx* c)
+{
+    if (c->watch_every <= 0 || !c->watch_base_due) return CPIC_OK;
+    c->watch_base_due = false;
+    return enqueue_watch(c, true);
+}
+
+extern "C" cpic_status cpic_set_watchdog(cpic_ctx* c, int32_t every, double max_unitarity, double max_gauss_drift,
+                                         double max_casimir_drift)
+{
+    if (!c) return fail(nullptr, CPIC_E_INVALID, "cpic_set_watchdog: NULL context");
+    if (every < 0 || !(max_unitarity > 0) || !(max_gauss_drift > 0) || !(max_casimir_drift > 0))
+        return fail(c, CPIC_E_INVALID, "cpic_set_watchdog: every >= 0 and positive thresholds");
+    c->watch_every = every;
+    c->watch_thr[0] = max_unitarity;
+    c->watch_thr[1] = max_gauss_drift;
+    c->watch_thr[2] = max_casimir_drift;
+    c->watch_base_due = true;
+    return CPIC_OK;
+}
+
+extern "C" cpic_status cpic_diagnostics(cpic_ctx* c, double out[10])
+{
+    if (!c || !out) return fail(c, CPIC_E_INVALID, "cpic_diagnostics: NULL argument");
+    if (!c->initialised) return fail(c, CPIC_E_INVALID, "cpic_diagnostics: no state");
+    cpic_status s = enqueue_diagnostics(c);
+    if (s) return s;
+    double h[10] = {0};
+    HIPCHK(c, hipStreamSynchronize(c->st), "diagnostics");
+    HIPCHK(c, hipMemcpy(h, c->dout, sizeof(double) * (c->np > 0 ? 10 : 8), hipMemcpyDeviceToHost), "diagnostics");
     std::memcpy(out, h, sizeof(h));
     for (int k = 0; k < 10; k++)
         if (!std::isfinite(h[k])) return fail(c, CPIC_E_NAN, "cpic_diagnostics: non-finite value in column " + std::to_string(k));
@@ -1052,6 +1130,7 @@ extern "C" cpic_status cpic_set_state(cpic_ctx* c, int32_t which, const void* sr
                 return fail(c, CPIC_E_INVALID, "cpic_set_state: particle position out of [0, N)");
         }
     }
+    c->watch_base_due = true;  // the watchdog's baseline is the installed state
     return c->prec == CPIC_FP64 ? set_t<double>(c, which, (const double*)src) : set_t<float>(c, which, (const double*)src);
 }
 
@@ -1235,6 +1314,7 @@ extern "C" cpic_status cpic_load(cpic_ctx* c, const char* path)
         }
     }
     c->n = h.n;
+    c->watch_base_due = true;
     HIPCHK(c, hipMemcpy(c->d_step, &c->n, sizeof(int), hipMemcpyHostToDevice), "load");
     if (!obs.empty()) HIPCHK(c, hipMemcpy(c->obs, obs.data(), sizeof(double) * obs.size(), hipMemcpyHostToDevice), "load");
     c->samples = samples;
@@ -1402,33 +1482,44 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
                   kVariantName[best.split], best.bx, best.by, best.waves, best.xcd_remap, best_ms * 1e3,
                   best.split == 3 && best.nt_store ? " (non-temporal stores of the new state)" : "");
     rep += line;
+    const int lanes[4] = {1, 2, 4, 8};
+    double lane_iso[4] = {1e300, 1e300, 1e300, 1e300};  // isolated push times per lane count
+    const int tpp0 = c->tpp;                              // the lane count before tuning
     if (c->np > 0 && c->n >= c->sc.n_form && c->n < c->sc.n_max) {
         const size_t rb = sizeof(T) * kPartReals * (size_t)c->np, cb = sizeof(int) * 2 * (size_t)c->np;
         HIPCHK(c, hipMemcpyAsync(c->sb.r2, c->pr, rb, hipMemcpyDeviceToDevice, c->st), "tune");
         HIPCHK(c, hipMemcpyAsync(c->sb.cell2, c->pcell, cb, hipMemcpyDeviceToDevice, c->st), "tune");
         // the step's new momenta: run the field kernel once into the free buffer
         HIPCHK(c, launch_field_step<T>(A, B, G, c->N, c->sc, c->d_step, c->cfg, c->st), "tune");
-        int best_tpp = c->tpp;
-        double best_p = 1e300;
-        for (int tpp : {1, 2, 4, 8}) {
-            const PushArgs pa = push_args(c, tpp);
-            double tot = 0;
-            for (int r = 0; r <= reps; r++) {
+        // the lane counts timed in interleaved rounds (the first a warm-up),
+        // each by its median; the current count stays unless another is at
+        // least 3 % faster (timing noise does not flip between equals)
+        std::vector<double> times[4];
+        for (int r = 0; r <= 2 * reps; r++)
+            for (int k = 0; k < 4; k++) {
                 HIPCHK(c, hipEventRecord(e0, c->st), "tune");
-                HIPCHK(c, launch_push<T>(A, B, G, P<T>(c), pa, c->d_step, c->partials, c->d_err, c->st), "tune");
+                HIPCHK(c, launch_push<T>(A, B, G, P<T>(c), push_args(c, lanes[k]), c->d_step, c->partials, c->d_err,
+                                         c->st), "tune");
                 HIPCHK(c, hipEventRecord(e1, c->st), "tune");
                 HIPCHK(c, hipMemcpyAsync(c->pr, c->sb.r2, rb, hipMemcpyDeviceToDevice, c->st), "tune");
                 HIPCHK(c, hipMemcpyAsync(c->pcell, c->sb.cell2, cb, hipMemcpyDeviceToDevice, c->st), "tune");
                 HIPCHK(c, hipEventSynchronize(e1), "tune");
                 float ms = 0;
                 HIPCHK(c, hipEventElapsedTime(&ms, e0, e1), "tune");
-                if (r > 0) tot += ms;
+                if (r > 0) times[k].push_back(ms);
             }
-            const double per = tot / reps;
-            std::snprintf(line, sizeof line, "push lanes=%d: %.2f us\n", tpp, per * 1e3);
+        int best_tpp = c->tpp;
+        double best_p = 1e300, cur_p = 1e300;
+        for (int k = 0; k < 4; k++) {
+            std::sort(times[k].begin(), times[k].end());
+            const double per = times[k][times[k].size() / 2];
+            lane_iso[k] = per;
+            std::snprintf(line, sizeof line, "push lanes=%d: %.2f us\n", lanes[k], per * 1e3);
             rep += line;
-            if (per < best_p) { best_p = per; best_tpp = tpp; }
+            if (per < best_p) { best_p = per; best_tpp = lanes[k]; }
+            if (lanes[k] == c->tpp) cur_p = per;
         }
+        if (cur_p <= 1.03 * best_p) { best_tpp = c->tpp; best_p = cur_p; }
         bool table = false;
         if (c->nc == 3 && c->pp.color_update == CPIC_COLOR_ROTATE) {
             if (!c->ftab) HIPCHK(c, hipMalloc(&c->ftab, (size_t)48 * c->V * c->tsz), "tune");
@@ -1548,6 +1639,25 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
             bool have_orig = false;
             for (const LaunchCfg& t : trials) have_orig = have_orig || same(t, orig);
             if (!have_orig) trials.push_back(orig);
+            // two real steps from the saved state, per step (reps pairs after a warm-up pair)
+            auto time_pair = [&](double& per) -> cpic_status {
+                double tot = 0;
+                for (int r = 0; r <= reps && te == hipSuccess; r++) {
+                    te = hipEventRecord(e0, c->st);
+                    cpic_status ls = CPIC_OK;
+                    if (te == hipSuccess) ls = launch_one<T>(c, c->cur, false);
+                    if (te == hipSuccess && !ls) ls = launch_one<T>(c, c->cur ^ 1, false);
+                    if (ls) return ls;
+                    if (te == hipSuccess) te = hipEventRecord(e1, c->st);
+                    if (te == hipSuccess) te = hipEventSynchronize(e1);
+                    float ms = 0;
+                    if (te == hipSuccess) te = hipEventElapsedTime(&ms, e0, e1);
+                    if (te == hipSuccess) te = restore();
+                    if (r > 0) tot += ms;
+                }
+                per = tot / reps / 2;
+                return CPIC_OK;
+            };
             LaunchCfg best_step = keep;
             double best_pair = 1e300, orig_pair = 1e300;
             for (size_t k = 0; k < trials.size() && te == hipSuccess; k++) {
@@ -1562,22 +1672,10 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
                         te = copy(bp, c->pr, rb);
                         if (te == hipSuccess) te = copy(bc, c->pcell, cb);
                     }
-                    double tot = 0;
-                    for (int r = 0; r <= reps && te == hipSuccess; r++) {
-                        te = hipEventRecord(e0, c->st);
-                        cpic_status ls = CPIC_OK;
-                        if (te == hipSuccess) ls = launch_one<T>(c, c->cur, false);
-                        if (te == hipSuccess && !ls) ls = launch_one<T>(c, c->cur ^ 1, false);
-                        if (ls) { c->cfg = keep; (void)restore(); release(); return ls; }
-                        if (te == hipSuccess) te = hipEventRecord(e1, c->st);
-                        if (te == hipSuccess) te = hipEventSynchronize(e1);
-                        float ms = 0;
-                        if (te == hipSuccess) te = hipEventElapsedTime(&ms, e0, e1);
-                        if (te == hipSuccess) te = restore();
-                        if (r > 0) tot += ms;
-                    }
+                    double per = 0;
+                    cpic_status ls = time_pair(per);
+                    if (ls) { c->cfg = keep; (void)restore(); release(); return ls; }
                     if (te != hipSuccess) break;
-                    const double per = tot / reps / 2;
                     std::snprintf(line, sizeof line, "step with field %s bx=%d by=%d waves=%d remap=%d nt=%d: %.2f us\n",
                                   kVariantName[cfg.split], cfg.bx, cfg.by, cfg.waves, cfg.xcd_remap, cfg.nt_store,
                                   per * 1e3);
@@ -1586,8 +1684,7 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
                     if (same(cfg, orig)) orig_pair = per;
                 }
             }
-            release();
-            if (te != hipSuccess) { c->cfg = keep; return hip_fail(c, te, "tune"); }
+            if (te != hipSuccess) { c->cfg = keep; release(); return hip_fail(c, te, "tune"); }
             // a change of configuration has to gain at least 2 % per step, so
             // that timing noise does not flip the choice between equals
             if (orig_pair <= 1.02 * best_pair) {
@@ -1595,9 +1692,43 @@ template <typename T> static cpic_status tune_t(cpic_ctx* c, int reps, std::stri
                 best_pair = orig_pair;
             }
             c->cfg = best_step;
-            std::snprintf(line, sizeof line, "chosen: field %s bx=%d by=%d waves=%d remap=%d nt=%d, step %.2f us\n",
+            // the gather push's lane count in the step too (in isolation the
+            // push misses what the field update leaves in the caches): the
+            // counts within 10 % of the fastest in isolation and the count
+            // before tuning, which stays unless another is at least 2 %
+            // faster per step
+            if (!fused_active(c) && !c->push_table && c->np > 0 && lane_iso[0] < 1e300) {
+                const int cur_tpp = c->tpp;  // the field trials ran with it
+                double step_t[4] = {1e300, 1e300, 1e300, 1e300};
+                double best_iso = 1e300;
+                for (int k = 0; k < 4; k++) {
+                    best_iso = std::min(best_iso, lane_iso[k]);
+                    if (lanes[k] == cur_tpp) step_t[k] = best_pair;
+                }
+                for (int k = 0; k < 4 && te == hipSuccess; k++) {
+                    if (lanes[k] == cur_tpp || !(lane_iso[k] <= 1.10 * best_iso || lanes[k] == tpp0)) continue;
+                    c->tpp = lanes[k];
+                    c->pblocks = push_blocks((int)c->np, c->tpp);
+                    cpic_status ls = time_pair(step_t[k]);
+                    if (ls) { c->tpp = cur_tpp; c->pblocks = push_blocks((int)c->np, cur_tpp); (void)restore(); release(); return ls; }
+                    std::snprintf(line, sizeof line, "step with push lanes=%d: %.2f us\n", lanes[k], step_t[k] * 1e3);
+                    rep += line;
+                }
+                int pick = 0;
+                for (int k = 1; k < 4; k++)
+                    if (step_t[k] < step_t[pick]) pick = k;
+                for (int k = 0; k < 4; k++)
+                    if (lanes[k] == tpp0 && step_t[k] <= 1.02 * step_t[pick]) pick = k;
+                c->tpp = lanes[pick];
+                c->pblocks = push_blocks((int)c->np, c->tpp);
+                best_pair = step_t[pick];
+            }
+            release();
+            if (te != hipSuccess) { c->cfg = keep; return hip_fail(c, te, "tune"); }
+            std::snprintf(line, sizeof line,
+                          "chosen: field %s bx=%d by=%d waves=%d remap=%d nt=%d, push lanes=%d, step %.2f us\n",
                           kVariantName[best_step.split], best_step.bx, best_step.by, best_step.waves,
-                          best_step.xcd_remap, best_step.nt_store, best_pair * 1e3);
+                          best_step.xcd_remap, best_step.nt_store, c->tpp, best_pair * 1e3);
             rep += line;
         }
     }

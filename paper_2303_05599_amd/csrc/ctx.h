@@ -62,8 +62,10 @@ struct cpic_ctx {
     int push_table = 0;   // 1: fields from a per-site force table (dense ensembles)
     void* ftab = nullptr; // [48][V] force table (table push, light-like paths)
     bool initialised = false;
-    // graphs: [parity] -> executable graph of kGraphSteps steps starting from buffer `parity`
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    // graphs: [parity][k] -> executable graph of k steps starting from buffer
+    // `parity` (k = kGraphSteps between reordering points, shorter ones up to
+    // the next reordering point or the end of an evolve)
+    hipGraphExec_t gexec[2][cpic::kGraphSteps + 1] = {};
     // light-like paths (cpic_jets_enable)
     bool jets = false;
     cpic::JetArgs ja{};
@@ -80,6 +82,18 @@ struct cpic_ctx {
     std::vector<hipEvent_t> ev_field, ev_push, ev_jets, ev_table;
     double t_field = 0, t_push = 0, t_jets = 0;
     int64_t k_field = 0, k_push = 0, k_jets = 0;
+    // drift watchdog: every watch_every steps (0: off) the diagnostics are
+    // compared on the device with thresholds and with a baseline taken when
+    // the state was installed; cpic_sync reports a breach
+    int watch_every = 64;
+    double watch_thr[3] = {1e-8, 1e-8, 1e-8};  // unitarity, Gauss drift, Casimir drift
+    bool watch_base_due = true;
+    int* d_watch = nullptr;        // [2] flags, step of the first breach (d_err + 1)
+    // pinned host staging: d_err[0..3], then the summed samples obs [nslots][4]
+    // (copied with the stream's last work, read after one synchronisation)
+    void* h_stage = nullptr;
+    double* d_watchv = nullptr;    // [4] its values
+    double* d_watchbase = nullptr; // [10] baseline diagnostics
     std::string err;
 };
 
@@ -93,6 +107,8 @@ int next_sort_point(const cpic_ctx* c, int n);
 // host bookkeeping of k launched steps (sample list, step counter, buffer parity)
 cpic_status host_advance(cpic_ctx* c, int k);
 PushArgs push_args(const cpic_ctx* c, int tpp);
+// the drift watchdog's baseline of a newly installed state, before its first step
+cpic_status watch_prepare(cpic_ctx* c);
 // the fused step can serve this context: SU(3), particles, the rotation
 // colour update, no light-like paths
 bool fused_ok(const cpic_ctx* c);

@@ -214,6 +214,10 @@ hipError_t launch_push_table(const Fields<T>& A, const Fields<T>& B, const T* ta
 template <typename T>
 hipError_t launch_batch_push(const EventDesc* ev, const int2* map, int total_blocks, int tpp, hipStream_t st);
 hipError_t launch_reduce_rows(const double* partials, int nrows, int ncols, double* out, hipStream_t st);
+// out[slot] for slots first_slot .. first_slot + count - 1 of partials[slot][nrows][4], one launch
+// (the same fixed-order sums as launch_reduce_rows)
+hipError_t launch_reduce_samples(const double* partials, int nrows, int first_slot, int count, double* out,
+                                 hipStream_t st);
 // Step counter protocol: d_step[0] is the current step n; the field update
 // copies it to d_step[1]; the push (or, without particles, the step advance)
 // sets d_step[0] = d_step[1] + 1.
@@ -222,6 +226,9 @@ hipError_t launch_step_advance(int* d_step, hipStream_t st);
 inline int obs_groups(int np) { return (np + 63) / 64; }
 template <typename T>
 hipError_t launch_part_diag(const Parts<T>& P, int np, double q2, double q3, double* partials, hipStream_t st);
+// drift watchdog on the diagnostics columns dout[10] (push.hip)
+hipError_t launch_watchdog(const double* dout, double* base, bool take_base, bool with_casimir, const double thr[3],
+                           double q2ref, int n, int* watch, double* vals, hipStream_t st);
 
 // ---- light-like path integral (jets.hip)
 // One path per site p = y*N + i, along +x at the speed of light from

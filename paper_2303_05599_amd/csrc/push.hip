@@ -516,6 +516,25 @@ __global__ __launch_bounds__(256) void reduce_rows_kernel(const double* __restri
     block_reduce_store<NC>(v, mask, out);
 }
 
+// samples: block b sums the rows of sample slot first + b (4 columns each)
+__global__ __launch_bounds__(256) void reduce_samples_kernel(const double* __restrict__ partials, int nrows, int first,
+                                                             double* out)
+{
+    const int slot = first + (int)blockIdx.x;
+    double v[4] = {0, 0, 0, 0};
+    for (int r = threadIdx.x; r < nrows; r += blockDim.x)
+#pragma unroll
+        for (int c = 0; c < 4; c++) v[c] += partials[((size_t)slot * nrows + r) * 4 + c];
+    block_reduce_store<4>(v, 0u, out + (size_t)slot * 4);
+}
+hipError_t launch_reduce_samples(const double* partials, int nrows, int first_slot, int count, double* out,
+                                 hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(reduce_samples_kernel, dim3(count), dim3(256), 0, st, partials, nrows, first_slot, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_reduce_rows(const double* partials, int nrows, int ncols, double* out, hipStream_t st)
 {
     if (ncols == 4) {
@@ -529,6 +548,47 @@ hipError_t launch_reduce_rows(const double* partials, int nrows, int ncols, doub
     } else {
         return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+// The drift watchdog's comparison of the diagnostics dout[10] (the columns
+// of cpic_diagnostics) with the baseline taken when the state was installed
+// (take_base: store dout as the baseline).  flags: bit 0 a non-finite
+// column, 1 unitarity max|UU^+ - 1| > thr[0], 2 Gauss drift
+// |max|G| - max|G|_0| > thr[1] max(1, max|G|_0), 3 Casimir drift: max|q2 -
+// q2(R)| or max|q3 - q3(R)| moved from its baseline by more than thr[2]
+// max(1, q2(R)).  The first breach is kept: watch[0] flags, watch[1] step,
+// vals the unitarity and the three drifts.
+__global__ void watchdog_kernel(const double* dout, double* base, int take_base, int with_casimir, double thr_u,
+                                double thr_g, double thr_c, double q2ref, int n, int* watch, double* vals)
+{
+    if (threadIdx.x != 0) return;
+    if (take_base) {
+        for (int k = 0; k < 10; k++) base[k] = dout[k];
+        return;
+    }
+    const double dg = fabs(dout[1] - base[1]);
+    const double d2 = with_casimir ? fabs(dout[8] - base[8]) : 0.0, d3 = with_casimir ? fabs(dout[9] - base[9]) : 0.0;
+    int f = 0;
+    for (int k = 0; k < (with_casimir ? 10 : 8); k++)
+        if (!isfinite(dout[k])) f |= 1;
+    if (dout[6] > thr_u) f |= 2;
+    if (dg > thr_g * fmax(1.0, base[1])) f |= 4;
+    if (d2 > thr_c * fmax(1.0, q2ref) || d3 > thr_c * fmax(1.0, q2ref)) f |= 8;
+    if (f && watch[0] == 0) {
+        watch[0] = f;
+        watch[1] = n;
+        vals[0] = dout[6];
+        vals[1] = dg;
+        vals[2] = d2;
+        vals[3] = d3;
+    }
+}
+hipError_t launch_watchdog(const double* dout, double* base, bool take_base, bool with_casimir, const double thr[3],
+                           double q2ref, int n, int* watch, double* vals, hipStream_t st)
+{
+    hipLaunchKernelGGL(watchdog_kernel, dim3(1), dim3(64), 0, st, dout, base, take_base ? 1 : 0, with_casimir ? 1 : 0,
+                       thr[0], thr[1], thr[2], q2ref, n, watch, vals);
     return hipGetLastError();
 }
 

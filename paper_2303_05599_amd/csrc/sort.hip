@@ -46,6 +46,10 @@ __global__ void cell_keys_kernel(const T* __restrict__ r, const int* __restrict_
         cx = cell[p];
         cy = cell[np + p];
     }
+    // a non-finite position (a diverged run, which the watchdog reports) still
+    // gets a key inside the lattice's range
+    cx = min(max(cx, 0), N - 1);
+    cy = min(max(cy, 0), N - 1);
     const int ntx = (N + tx - 1) / tx;
     const int tile = (cy / ty) * ntx + cx / tx;
     keys[p] = (unsigned)(tile * tx * ty + (cy % ty) * tx + cx % tx);
@@ -59,8 +63,8 @@ __global__ void tile_start_kernel(const unsigned* __restrict__ sorted, int np, u
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i > np) return;
-    const int ti = i < np ? (int)(sorted[i] / per_tile) : ntiles;
-    const int tp = i > 0 ? (int)(sorted[i - 1] / per_tile) : -1;
+    const int ti = i < np ? (int)min(sorted[i] / per_tile, (unsigned)ntiles) : ntiles;
+    const int tp = i > 0 ? (int)min(sorted[i - 1] / per_tile, (unsigned)ntiles) : -1;
     for (int t = tp + 1; t <= ti; t++) tile_start[t] = i;
 }
 

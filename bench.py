@@ -178,8 +178,11 @@ def run_event(precision, steps, warmup, tune=True, particles=None, jets=False, n
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     d = ctx.diagnostics()
+    transport = ctx.transport()
+    jet_transport = ctx.jet_transport() if jets else None
     ctx.close()
     return dict(wall=wall, t_ic=t_ic, timing=tm, diag=d, obs=obs, jet_obs=jobs, eager_ms_per_step=eager_ms,
+                transport=transport, jet_transport=jet_transport,
                 kernel_timing_steps=n_kt, launch=launch, tune_report=tune_report, untimed_steps=untimed,
                 warmup_steps=w)
 
@@ -284,9 +287,15 @@ def run_jets(steps, warmup, V, tune=True, fixed=None):
             "kernels": k, "launch": r["launch"],
             "tau_fm": float(last[0]),
             "quarks_GeV2": {"dpT2": float(last[1]), "dpL2": float(last[2]), "dp_par2": float(last[3]),
-                            "dp_perp2": float(last[4]), "anisotropy_L_over_T": float(last[2] / last[1])},
+                            "dp_perp2": float(last[4]),
+                            # the library's transport export (cpic_transport)
+                            "anisotropy_L_over_T": float(r["transport"][-1, 6]),
+                            "kappa_T_GeV2_c_per_fm": float(r["transport"][-1, 1]),
+                            "kappa_L_GeV2_c_per_fm": float(r["transport"][-1, 2])},
             "light_like_GeV2": {"dpx2": float(lj[1]), "dpy2": float(lj[2]), "dpz2": float(lj[3]),
-                                "anisotropy_z_over_y": float(lj[3] / lj[2])}}
+                                "anisotropy_z_over_y": float(r["jet_transport"][-1, 5]),
+                                "qhat_y_GeV2_c_per_fm": float(r["jet_transport"][-1, 2]),
+                                "qhat_z_GeV2_c_per_fm": float(r["jet_transport"][-1, 3])}}
 
 
 def run_color_log(steps, warmup, V, ref):
@@ -685,6 +694,8 @@ def main():
         "ic_seconds": res["t_ic"],
         "gauss_max": res["diag"][1], "unitarity_max": res["diag"][6],
         "dpT2_GeV2_last": float(res["obs"][-1, 1]), "dpL2_GeV2_last": float(res["obs"][-1, 2]),
+        "kappa_T_last": float(res["transport"][-1, 1]), "kappa_L_last": float(res["transport"][-1, 2]),
+        "anisotropy_L_over_T_last": float(res["transport"][-1, 6]),
     }
     if not args.no_extras:
         r32 = run_event(cp.FP32, args.steps, args.warmup)

@@ -203,6 +203,22 @@ cpic_status cpic_observables(cpic_ctx* ctx, double* tau_fm, double* dpT2_GeV2, d
  * the number of particles averaged.  GeV^2. */
 cpic_status cpic_observables_full(cpic_ctx* ctx, double* out, int32_t cap);
 
+/* Transport coefficients and anisotropies from the samples: the instantaneous
+ * heavy-quark coefficients kappa_{L,T}(tau) = d<dp_{L,T}^2>/dtau
+ * ([eq:kappalt]), the jet coefficients qhat_i = d<dp_i^2>/dtau ([eq:qhati];
+ * for particles launched along x, i = x is the component along the initial
+ * direction, y across it, z the longitudinal one, qhat_z = kappa_L), the
+ * heavy-quark anisotropy <dp_L^2>/<dp_T^2> and the jet anisotropy
+ * <dp_z^2>/<dp_y^2> ([eq:jetanisotropy]).  The derivatives are central
+ * differences between consecutive samples, at the midpoint, the first interval
+ * opening at the formation time, where every <dp^2> vanishes.  out[8*k + c]
+ * for sample k: c = 0 tau_mid (fm/c), 1 kappa_T, 2 kappa_L, 3 qhat_x (par),
+ * 4 qhat_y (perp) (GeV^2 c/fm, over [tau_{k-1}, tau_k]), 5 tau_k, 6 the
+ * heavy-quark anisotropy, 7 the jet anisotropy at tau_k.  *n_samples (may be
+ * NULL) receives the sample count; CPIC_E_CAPACITY if cap is smaller (nothing
+ * written).  Synchronises. */
+cpic_status cpic_transport(cpic_ctx* ctx, double* out, int32_t cap, int32_t* n_samples);
+
 /*
  * Diagnostics at the current step n (double-precision reductions):
  *   out[0] sum_x |G(x)|^2, G the lattice Gauss residual
@@ -447,6 +463,11 @@ cpic_status cpic_jets_enable(cpic_ctx* ctx, const cpic_jet_params* params);
  * precision sums).  *n_samples (may be NULL) receives the sample count;
  * CPIC_E_CAPACITY if cap is smaller (nothing written).  Synchronises. */
 cpic_status cpic_jets_observables(cpic_ctx* ctx, double* out, int32_t cap, int32_t* n_samples);
+/* The light-like paths' qhat_i = d<dp_i^2>/dtau ([eq:qhati]) and the jet
+ * anisotropy <dp_z^2>/<dp_y^2> ([eq:jetanisotropy]), as cpic_transport:
+ * out[6*k + c], c = tau_mid, qhat_x, qhat_y, qhat_z (GeV^2 c/fm), tau_k, the
+ * anisotropy at tau_k.  Synchronises. */
+cpic_status cpic_jets_transport(cpic_ctx* ctx, double* out, int32_t cap, int32_t* n_samples);
 /* Summed kernel time (ms) and launch count of the light-like path kernel
  * since cpic_set_timing enabled timing.  Synchronises. */
 cpic_status cpic_jets_timing(cpic_ctx* ctx, double* ms, int64_t* launches);

@@ -310,6 +310,36 @@ def particles_observe(t, mhat, is_static, P):
     return out
 
 
+def transport_coefficients(tau_form, tau, broadening):
+    """Instantaneous transport coefficients and anisotropies from a sampled
+    broadening series ([eq:kappalt], [eq:qhati], the heavy-quark anisotropy
+    <dp_L^2>/<dp_T^2> and the jet anisotropy [eq:jetanisotropy]).
+
+    tau: (k,) sample times; broadening: (k, 4) the means <dp_T^2>, <dp_L^2>,
+    <dp_par^2>, <dp_perp^2> at those times (par / perp: along / across the
+    initial transverse direction, x / y for jets launched along x, whose
+    longitudinal component is <dp_z^2> = <dp_L^2>).  Every <dp^2> vanishes at
+    the formation time tau_form, which opens the series.  The derivative
+    d<dp^2>/dtau of each component is taken between consecutive points, at the
+    midpoint (the central difference: exact there for a quadratic series).
+
+    Returns (k, 8): tau_mid, kappa_T, kappa_L, qhat_par, qhat_perp (the
+    derivatives of the four means over [tau_{k-1}, tau_k], tau_{-1} = tau_form),
+    tau_k, <dp_L^2>/<dp_T^2>, <dp_L^2>/<dp_perp^2>."""
+    tau = np.asarray(tau, dtype=np.float64)
+    b = np.asarray(broadening, dtype=np.float64)
+    t = np.concatenate([[tau_form], tau])
+    v = np.concatenate([np.zeros((1, 4)), b])
+    out = np.zeros((len(tau), 8))
+    out[:, 0] = 0.5 * (t[1:] + t[:-1])
+    out[:, 1:5] = (v[1:] - v[:-1]) / (t[1:] - t[:-1])[:, None]
+    out[:, 5] = tau
+    with np.errstate(divide="ignore", invalid="ignore"):
+        out[:, 6] = b[:, 1] / b[:, 0]
+        out[:, 7] = b[:, 1] / b[:, 3]
+    return out
+
+
 class Jets:
     """Light-like jet limit of the momentum broadening (Sec. V.B,
     [eq:mombroadjets]): straight paths along +x at the speed of light, one per

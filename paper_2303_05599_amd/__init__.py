@@ -84,6 +84,8 @@ def lib():
             "cpic_timing": [P, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(i64), ctypes.POINTER(i64)],
             "cpic_straggler_pushes": [P, ctypes.POINTER(i64)],
             "cpic_set_watchdog": [P, i32, d, d, d],
+            "cpic_transport": [P, P, i32, ctypes.POINTER(i32)],
+            "cpic_jets_transport": [P, P, i32, ctypes.POINTER(i32)],
             "cpic_batch_create": [i32, ctypes.POINTER(GlasmaParams), ctypes.POINTER(ParticleParams), P, pp],
             "cpic_batch_init_mv": [P], "cpic_batch_run": [P], "cpic_batch_step": [P, i32], "cpic_batch_sync": [P],
             "cpic_batch_tune": [P, i32, P, sz], "cpic_batch_set_launch": [P, i32, i32, i32, i32],
@@ -210,6 +212,23 @@ class Context:
         out = np.zeros((max(k, 1), 6))
         self._chk(lib().cpic_observables_full(self.h, _ptr(out), k))
         return out[:k]
+
+    def transport(self):
+        """(k, 8): tau_mid, kappa_T, kappa_L, qhat_x, qhat_y, tau_k, <dp_L^2>/<dp_T^2>,
+        <dp_z^2>/<dp_y^2> (cpic_transport)."""
+        k = self.num_samples()
+        out = np.zeros((max(k, 1), 8))
+        n = ctypes.c_int32()
+        self._chk(lib().cpic_transport(self.h, _ptr(out), k, ctypes.byref(n)))
+        return out[:n.value]
+
+    def jet_transport(self):
+        """(k, 6): tau_mid, qhat_x, qhat_y, qhat_z, tau_k, <dp_z^2>/<dp_y^2> of the light-like paths."""
+        n = ctypes.c_int32()
+        self._chk(lib().cpic_jets_transport(self.h, None, 1 << 30, ctypes.byref(n)))
+        out = np.zeros((max(n.value, 1), 6))
+        self._chk(lib().cpic_jets_transport(self.h, _ptr(out), n.value, ctypes.byref(n)))
+        return out[:n.value]
 
     def diagnostics(self):
         out = np.zeros(10)

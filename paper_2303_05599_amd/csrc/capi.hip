@@ -776,6 +776,40 @@ extern "C" cpic_status cpic_observables_full(cpic_ctx* c, double* out, int32_t c
     return CPIC_OK;
 }
 
+// Central differences of a broadening series that opens with zeros at the
+// formation time: rows (tau_mid, d/dtau of the four means, tau_k, the two
+// ratios of columns 1/0 and 1/3), as documented at cpic_transport.
+static void transport_rows(double tau_form, int ns, const double* tau, const double* b, int stride, double* out)
+{
+    double t0 = tau_form, v0[4] = {0, 0, 0, 0};
+    for (int k = 0; k < ns; k++) {
+        const double t1 = tau[(size_t)k * stride], *v1 = b + (size_t)k * stride;
+        double* o = out + 8 * (size_t)k;
+        o[0] = 0.5 * (t0 + t1);
+        for (int j = 0; j < 4; j++) o[1 + j] = (v1[j] - v0[j]) / (t1 - t0);
+        o[5] = t1;
+        o[6] = v1[1] / v1[0];
+        o[7] = v1[1] / v1[3];
+        t0 = t1;
+        for (int j = 0; j < 4; j++) v0[j] = v1[j];
+    }
+}
+
+extern "C" cpic_status cpic_transport(cpic_ctx* c, double* out, int32_t cap, int32_t* n_samples)
+{
+    if (!c) return fail(nullptr, CPIC_E_INVALID, "cpic_transport: NULL context");
+    const int ns = (int)c->samples.size();
+    if (n_samples) *n_samples = ns;
+    if (cap < ns) return fail(c, CPIC_E_CAPACITY, "cpic_transport: capacity " + std::to_string(cap) + " < " +
+                                                     std::to_string(ns) + " samples");
+    std::vector<double> full(6 * (size_t)std::max(ns, 1));
+    cpic_status s = cpic_observables_full(c, full.data(), ns);
+    if (s) return s;
+    if (!ns || !out) return CPIC_OK;
+    transport_rows(c->sc.n_form * c->sc.dt * c->a_fm, ns, full.data(), full.data() + 1, 6, out);
+    return CPIC_OK;
+}
+
 extern "C" cpic_status cpic_observables(cpic_ctx* c, double* tau_fm, double* dpT2, double* dpL2, int32_t cap)
 {
     if (!c) return fail(nullptr, CPIC_E_INVALID, "cpic_observables: NULL context");
@@ -1864,6 +1898,45 @@ extern "C" cpic_status cpic_jets_observables(cpic_ctx* c, double* out, int32_t c
         const int slot = c->jsamples[k].first;
         out[4 * k] = (c->jsamples[k].second + 1) * c->sc.dt * c->a_fm;
         for (int j = 0; j < 3; j++) out[4 * k + 1 + j] = h[4 * (size_t)slot + j] * scale;
+    }
+    return CPIC_OK;
+}
+
+extern "C" cpic_status cpic_jets_transport(cpic_ctx* c, double* out, int32_t cap, int32_t* n_samples)
+{
+    if (!c) return fail(nullptr, CPIC_E_INVALID, "cpic_jets_transport: NULL context");
+    if (!c->jets) return fail(c, CPIC_E_INVALID, "cpic_jets_transport: light-like paths not enabled");
+    const int ns = (int)c->jsamples.size();
+    if (n_samples) *n_samples = ns;
+    if (cap < ns) return fail(c, CPIC_E_CAPACITY, "cpic_jets_transport: capacity " + std::to_string(cap) + " < " +
+                                                     std::to_string(ns) + " samples");
+    std::vector<double> obs(4 * (size_t)std::max(ns, 1));
+    cpic_status s = cpic_jets_observables(c, obs.data(), ns, nullptr);
+    if (s) return s;
+    if (!ns || !out) return CPIC_OK;
+    // rows of (tau, <dp_x^2>, <dp_y^2>, <dp_z^2>) as (tau, T = x, L = z, par = x, perp = y)
+    std::vector<double> series(6 * (size_t)ns);
+    for (int k = 0; k < ns; k++) {
+        const double* o = obs.data() + 4 * (size_t)k;
+        double* r = series.data() + 6 * (size_t)k;
+        r[0] = o[0];
+        r[1] = o[1];
+        r[2] = o[3];
+        r[3] = o[1];
+        r[4] = o[2];
+        r[5] = 0;
+    }
+    std::vector<double> rows(8 * (size_t)ns);
+    transport_rows(c->ja.sc.n_form * c->ja.sc.dt * c->a_fm, ns, series.data(), series.data() + 1, 6, rows.data());
+    for (int k = 0; k < ns; k++) {
+        const double* r = rows.data() + 8 * (size_t)k;
+        double* o = out + 6 * (size_t)k;
+        o[0] = r[0];   // tau_mid
+        o[1] = r[3];   // qhat_x
+        o[2] = r[4];   // qhat_y
+        o[3] = r[2];   // qhat_z
+        o[4] = r[5];   // tau_k
+        o[5] = r[7];   // <dp_z^2>/<dp_y^2>
     }
     return CPIC_OK;
 }

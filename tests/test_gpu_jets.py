@@ -108,6 +108,15 @@ def test_jets_against_oracle(case):
     assert obs.shape == samples.shape
     assert np.allclose(obs[:, 0], samples[:, 0], rtol=1e-14)
     assert rel_err(obs[:, 1:], samples[:, 1:]) <= 1e-10
+    # qhat_i ([eq:qhati]) and the jet anisotropy ([eq:jetanisotropy]): the
+    # oracle's definition with (T, L, par, perp) = (x, z, x, y)
+    tr = ctx.jet_transport()
+    tau_f = nfj * DT * g["L_fm"] / N
+    for src, tol in ((obs, 1e-12), (samples, 1e-9)):
+        ref = oracle.transport_coefficients(tau_f, src[:, 0], src[:, [1, 3, 1, 2]])
+        want = ref[:, [0, 1, 4, 2, 5, 7]]
+        for c in range(6):
+            assert np.max(np.abs(tr[:, c] - want[:, c])) <= tol * np.max(np.abs(want[:, c])), (c, tol)
     if part:
         gp = ctx.get_state(cp.STATE_PARTICLES)
         assert np.array_equal(gp[:, 14:16], run.P[:, 14:16])

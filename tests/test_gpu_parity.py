@@ -238,6 +238,19 @@ def test_static_limit_config_32():
     for c in (1, 2, 3, 4):
         assert rel_err(obs[:, c], ref_obs[:, c]) <= TOL
     assert rel_err(ctx.get_state(cp.STATE_PARTICLES), run.P) <= TOL
+    # transport coefficients and anisotropies ([eq:kappalt], the heavy-quark
+    # ratio): the library's from its samples against the oracle's definition,
+    # on the library's samples (to rounding) and on the oracle's (the sample
+    # differences amplify the 1e-11 agreement of the sums)
+    tr = ctx.transport()
+    assert tr.shape == (6, 8)
+    mine = oracle.transport_coefficients(0.0, obs[:, 0], obs[:, 1:5])
+    assert np.allclose(tr, mine, rtol=1e-12, atol=0)
+    theirs = oracle.transport_coefficients(0.0, ref_obs[:, 0], ref_obs[:, 1:5])
+    for c in range(8):
+        scale = np.max(np.abs(theirs[:, c]))
+        assert np.max(np.abs(tr[:, c] - theirs[:, c])) <= 1e-9 * scale, c
+    assert np.all(tr[:, 2] != 0) and np.all(np.isfinite(tr))
 
 
 @pytest.mark.parametrize("launch", [None, "tile64x4", "link128x1", "ctile32x8"])

@@ -404,6 +404,96 @@ def cpu_baseline(n_steps=40, n_steps_single=2, n_part=100_000):
                        "config1_32_fp64_1024_static": {"all_cores": all1, "one_thread": one1}})
 
 
+def _rms_rel(a, ref):
+    a, ref = np.asarray(a, dtype=np.float64), np.asarray(ref, dtype=np.float64)
+    return float(np.sqrt(np.mean((a - ref) ** 2) / np.mean(ref ** 2)))
+
+
+def cpu_baseline_fp32_accuracy(n_compare=2000):
+    """The oracle side of the single-precision accuracy keys (part of the
+    CPU-baseline leg, the only leg that runs the oracle).  The oracle pushes
+    the first n_compare particles of an event (particles are independent given
+    the fields), from its own initial condition of the same seeds; the GPU
+    records of the same particles give the same broadening sums.
+
+    (a) The batch's first two 128^2 events (FP32, batched), to their end.
+    (b) Error growth: the FP32 charm setup of the headline (m = 1.27 GeV,
+        pT = 0, formed at 0.1 fm/c, 50 sheets, reunitarisation and charge
+        renormalisation every 16 steps) on a 128^2 lattice, L = 6 fm, to
+        1.5 fm/c (256 steps), the errors after 16, 32, ..., 256 steps, with
+        the FP64 GPU path beside it.  (512^2 is beyond the oracle's budget
+        here: 67 M site-updates per 256 steps.)"""
+    import oracle
+    import paper_2303_05599_amd as cp
+    oracle.set_threads(host_threads())
+
+    def oracle_event(g, p, n_compare):
+        N, L = g["N"], g["L_fm"]
+        a = oracle.lattice_spacing(L, N)
+        st = oracle.mv_initial_condition(N, L, g["g2mu_GeV"], g["m_ir_GeV"], g["uv_GeV"], g["n_sheets"], g["seed"])
+        P = oracle.particles_init(N, p["n"], p["seed"], p["pT_min_GeV"] * a, p["pT_max_GeV"] * a, True, 0)
+        f = p["tau_form_fm"] / (0.125 * L / N)
+        n_form = math.ceil(f - 1e-9 * f)  # as the library rounds the formation step
+        return oracle.Run(N, 0.125, st, P[:n_compare], mhat=p["mass_GeV"] * a, n_form=n_form), a
+
+    def errors(run, a, recs, state=None):
+        k = recs.shape[0]
+        ref = run.observe() / (k * a * a)
+        got = oracle.particles_observe(run.n * 0.125, run.mhat, False, recs) / (k * a * a)
+        e = {"dpT2_rel_err": float(abs(got[0] / ref[0] - 1)), "dpL2_rel_err": float(abs(got[1] / ref[1] - 1)),
+             "momentum_rms_rel_err": _rms_rel(recs[:, 3:6], run.P[:, 3:6]),
+             "dpT2_GeV2": float(ref[0]), "dpL2_GeV2": float(ref[1])}
+        if state is not None:
+            e["E_rms_rel_err"] = _rms_rel(state["E"], run.st["E"])
+            e["U_rms_rel_err"] = _rms_rel(state["U"].view(np.float64), run.st["U"].view(np.float64))
+        return e
+
+    t0 = time.perf_counter()
+    gl32, pl = batch_events(cp.FP32)
+    idx = [e for e in range(len(gl32)) if gl32[e]["N"] == 128][:2]
+    b = cp.Batch([gl32[e] for e in idx], [pl[e] for e in idx])
+    b.init_mv()
+    b.run()
+    b.sync()
+    batch = []
+    for j, e in enumerate(idx):
+        g, p = gl32[e], pl[e]
+        recs = b.get_state(j, cp.STATE_PARTICLES, (p["n"], 20))[:n_compare]
+        run, a = oracle_event(g, p, n_compare)
+        for _ in range(b.n(j)):
+            run.step()
+        batch.append(dict(event=e, steps=run.n, **errors(run, a, recs)))
+    b.close()
+
+    N, L = 128, 6.0
+    g = dict(N=N, L_fm=L, g2mu_GeV=2.0, m_ir_GeV=0.2, uv_GeV=10.0, n_sheets=50, dtau_over_a=0.125, tau_max_fm=1.5,
+             seed=7, reunit_every=16, record_every=8)
+    p = charm(10_000)
+    ctxs = {prec: cp.Context(dict(g, precision=prec), p) for prec in (cp.FP32, cp.FP64)}
+    for c in ctxs.values():
+        c.init_mv()
+    run, a = oracle_event(g, p, n_compare)
+    growth = []
+    for k in (16, 32, 64, 128, 256):
+        while run.n < k:
+            run.step()
+        row = {"steps": k, "tau_fm": k * 0.125 * L / N}
+        for prec, c in ctxs.items():
+            c.step(k - c.n)
+            recs = c.get_state(cp.STATE_PARTICLES)[:n_compare]
+            row["fp32" if prec == cp.FP32 else "fp64"] = errors(run, a, recs, c.state())
+        growth.append(row)
+    for c in ctxs.values():
+        c.close()
+    return {"batch_fp32_vs_oracle_128": {"events": batch, "particles_compared": n_compare,
+                                         "dpT2_rel_err_max": max(r["dpT2_rel_err"] for r in batch),
+                                         "dpL2_rel_err_max": max(r["dpL2_rel_err"] for r in batch)},
+            "error_growth_fp32_vs_oracle": {"workload": "the headline's FP32 charm setup on 128^2 (L = 6 fm, 50 "
+                                                        "sheets, 1e4 quarks, the first 2000 compared)",
+                                            "rows": growth},
+            "seconds": time.perf_counter() - t0}
+
+
 def kernel_source_hash():
     """sha256 over the HIP sources: a stored counter reading is only used for the
     kernels it was taken on."""
@@ -714,6 +804,8 @@ def main():
         out["batch"] = run_batch(res["launch"])
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
+        if not args.no_extras:
+            out["fp32_vs_oracle"] = cpu_baseline_fp32_accuracy()
     if args.tune_report:
         with open(args.tune_report, "w") as f:
             f.write(res["tune_report"])

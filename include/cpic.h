@@ -480,15 +480,17 @@ void cpic_destroy(cpic_ctx* ctx);
  * Batched events: n_events independent Glasma events (each with its own
  * lattice size, MV scale, particle species and step count; one precision for
  * all) evolved together.  Events are split into launch groups whose working
- * set fits the last-level cache (cpic_batch_set_group_bytes); the groups run
+ * set fits the last-level cache (cpic_batch_set_group_bytes); the groups are
+ * dealt to launch lanes (cpic_batch_set_lanes), and each lane runs its groups
  * one after the other, each to the end of its events.  One step of a group is
  * one batched field launch and one batched push launch (which also advances
  * the step counters) over its active events; each workgroup reads its (event, tile) or
  * (event, particle block) item from a device work map.  Runs of steps are
  * replayed from HIP graphs; events that reach their n_max drop out of the
  * work maps.  Parameter arrays have n_events entries (particles may be NULL:
- * no particles).  All events use the batch's stream (hip_stream, or a new
- * non-blocking stream if NULL).  Each event is also a full cpic_ctx
+ * no particles).  The batch's stream is hip_stream, or a new non-blocking
+ * stream if NULL; with more than one launch lane the events also run on
+ * streams of the library's own (cpic_batch_set_lanes).  Each event is also a full cpic_ctx
  * internally; per-event results are read with the functions below.  Not
  * thread-safe.
  */
@@ -512,11 +514,25 @@ cpic_status cpic_batch_tune(cpic_batch* b, int32_t reps, char* report, size_t ca
  * (1, 2, 4) */
 cpic_status cpic_batch_set_launch(cpic_batch* b, int32_t bx, int32_t by, int32_t xcd_remap, int32_t tpp);
 /* Launch groups: events are taken by decreasing working set (both field
- * buffer sets and the particle records) and packed into groups of at most `bytes` (a larger event forms a
- * group of its own).  A group runs all its steps before the next group
- * starts, so its fields stay in the last-level cache from one step to the
- * next.  0 = all events in one group, stepped together.  Default 256 MiB. */
+ * buffer sets and the particle records) and packed into groups of at most
+ * `bytes` (a larger event forms a group of its own).  A group runs all its
+ * steps before the next group of its lane starts, so its fields stay in the
+ * last-level cache from one step to the next.  0 = all events in one group,
+ * stepped together.  Default 96 MiB (with the default two lanes, the groups
+ * running side by side share the 256 MB last-level cache). */
 cpic_status cpic_batch_set_group_bytes(cpic_batch* b, int64_t bytes);
+/* Launch lanes (1 to 4; default 2): the launch groups are dealt to the
+ * batch stream and up to three streams of the library's own (default
+ * priority), by their remaining work (largest first, each to the lane with
+ * the least; odd lanes then run theirs smallest first), and the streams run
+ * concurrently: the launches of small events leave most of the chip idle,
+ * and a large event's latency-bound push leaves bandwidth unused, which the
+ * other lane's groups take.  The events' results do not depend on the lanes
+ * (each event's kernels run in the same order on one stream).
+ * cpic_batch_run and cpic_batch_step end with the batch stream waiting for
+ * the other lanes, so the batch stream orders everything after them
+ * (cpic_batch_sync, reads of the results). */
+cpic_status cpic_batch_set_lanes(cpic_batch* b, int32_t lanes);
 /* out = {bx, by, xcd_remap, tpp} */
 cpic_status cpic_batch_get_launch(const cpic_batch* b, int32_t out[4]);
 cpic_status cpic_batch_num_events(const cpic_batch* b, int32_t* n);

@@ -90,6 +90,7 @@ def lib():
             "cpic_batch_init_mv": [P], "cpic_batch_run": [P], "cpic_batch_step": [P, i32], "cpic_batch_sync": [P],
             "cpic_batch_tune": [P, i32, P, sz], "cpic_batch_set_launch": [P, i32, i32, i32, i32],
             "cpic_batch_set_group_bytes": [P, i64],
+            "cpic_batch_set_lanes": [P, i32],
             "cpic_batch_get_launch": [P, P], "cpic_batch_num_events": [P, ctypes.POINTER(i32)],
             "cpic_batch_current_step": [P, i32, ctypes.POINTER(i64)],
             "cpic_batch_observables": [P, i32, P, i32, ctypes.POINTER(i32)],
@@ -402,6 +403,10 @@ class Batch:
 
     def set_launch(self, bx, by, xcd_remap=1, push_lanes=1):
         self._chk(lib().cpic_batch_set_launch(self.h, bx, by, xcd_remap, push_lanes))
+
+    def set_lanes(self, lanes):
+        """Launch lanes, 1 to 4: the launch groups dealt to that many concurrent streams (default 2)."""
+        self._chk(lib().cpic_batch_set_lanes(self.h, lanes))
 
     def set_group_bytes(self, nbytes):
         """Working-set budget of one launch group (0: one group for all events)."""

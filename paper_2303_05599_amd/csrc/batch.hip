@@ -2,7 +2,8 @@
 //
 // Every event keeps its own context (buffers, step counter, samples); the
 // batch adds a device table of event descriptors.  Events are split into
-// launch groups whose working set fits the last-level cache; the groups run
+// launch groups whose working set fits the last-level cache; the groups are
+// dealt to one or two launch lanes (streams), and each lane runs its groups
 // one after the other, each to the end of its events.  For every set of
 // still active events of a group there is a plan: the active list and the
 // work maps (event, tile) and (event, particle block), one entry per
@@ -29,16 +30,19 @@ namespace {
 
 constexpr int kBatchGraphSteps = 16;
 // Events are run in groups whose working set (both field buffer sets and the
-// particle records) stays within about this
-// much, so that from one step to the next (and from a group's field update
-// to its push) the data is served from the 256 MB last-level cache.
-constexpr size_t kDefaultGroupBytes = (size_t)256 << 20;
+// particle records) stays within about this much, so that from one step to
+// the next (and from a group's field update to its push) the data of the
+// groups the lanes run side by side is served from the 256 MB last-level
+// cache (96 MiB measured best of 64, 96 and 128 with two lanes).
+constexpr size_t kDefaultGroupBytes = (size_t)96 << 20;
+constexpr int kMaxLanes = 4, kDefaultLanes = 2;
 
 struct Plan {
     std::vector<int> act;          // active events (descriptor indices)
     int* d_act = nullptr;          // [nact]
     int2* d_tiles = nullptr;       // (event, tile) per field workgroup
     int2* d_blocks = nullptr;      // (event, particle block) per push workgroup
+    std::vector<int2> tiles, blocks;  // host copies of the work maps (sources of their uploads)
     int total_tiles = 0, total_blocks = 0;
     hipGraphExec_t graph = nullptr;
 };
@@ -57,6 +61,12 @@ struct cpic_batch {
     // 5e4 to 3.5e6 particles per launch)
     int tpp = 4;
     size_t group_bytes = kDefaultGroupBytes;  // working-set budget of a launch group; 0: one group
+    // Launch lanes: the groups are dealt to `lanes` streams that run
+    // concurrently, so that groups of small events (whose launches leave most
+    // of the chip idle) run beside groups of large ones.
+    int lanes = kDefaultLanes;
+    hipStream_t lane_st[kMaxLanes] = {};      // lane 0 is the batch stream; the others the library's own
+    hipEvent_t ev_fork = nullptr, ev_join[kMaxLanes] = {};
     EventDesc* d_desc = nullptr;
     std::vector<EventDesc> desc;  // host copy (kept alive for the asynchronous upload)
     std::map<std::vector<int>, Plan> plans;
@@ -154,7 +164,7 @@ static std::vector<std::vector<int>> launch_groups(const cpic_batch* b)
     return groups;
 }
 
-static cpic_status get_plan(cpic_batch* b, const std::vector<int>& act, Plan** out)
+static cpic_status get_plan(cpic_batch* b, const std::vector<int>& act, Plan** out, hipStream_t st)
 {
     auto it = b->plans.find(act);
     if (it != b->plans.end()) {
@@ -163,47 +173,51 @@ static cpic_status get_plan(cpic_batch* b, const std::vector<int>& act, Plan** o
     }
     Plan p;
     p.act = act;
-    std::vector<int2> tiles, blocks;
     for (int e : act) {
         const cpic_ctx* c = b->ev[e];
         // an event without particles keeps one push workgroup, which advances its step counter
         const int nt = field_tiles_host(c->N, b->cfg), nb = c->np > 0 ? push_blocks((int)c->np, b->tpp) : 1;
-        for (int k = 0; k < nt; k++) tiles.push_back(make_int2(e, k));
-        for (int k = 0; k < nb; k++) blocks.push_back(make_int2(e, k));
+        for (int k = 0; k < nt; k++) p.tiles.push_back(make_int2(e, k));
+        for (int k = 0; k < nb; k++) p.blocks.push_back(make_int2(e, k));
     }
-    p.total_tiles = (int)tiles.size();
-    p.total_blocks = (int)blocks.size();
+    p.total_tiles = (int)p.tiles.size();
+    p.total_blocks = (int)p.blocks.size();
     BHIP(b, hipMalloc(&p.d_act, sizeof(int) * act.size()), "plan");
-    BHIP(b, hipMalloc(&p.d_tiles, sizeof(int2) * std::max<size_t>(tiles.size(), 1)), "plan");
-    BHIP(b, hipMalloc(&p.d_blocks, sizeof(int2) * std::max<size_t>(blocks.size(), 1)), "plan");
-    BHIP(b, hipMemcpy(p.d_act, act.data(), sizeof(int) * act.size(), hipMemcpyHostToDevice), "plan");
-    BHIP(b, hipMemcpy(p.d_tiles, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice), "plan");
-    if (!blocks.empty())
-        BHIP(b, hipMemcpy(p.d_blocks, blocks.data(), sizeof(int2) * blocks.size(), hipMemcpyHostToDevice), "plan");
-    auto ins = b->plans.emplace(act, p);
-    *out = &ins.first->second;
+    BHIP(b, hipMalloc(&p.d_tiles, sizeof(int2) * std::max<size_t>(p.tiles.size(), 1)), "plan");
+    BHIP(b, hipMalloc(&p.d_blocks, sizeof(int2) * std::max<size_t>(p.blocks.size(), 1)), "plan");
+    auto ins = b->plans.emplace(act, std::move(p));
+    Plan& q = ins.first->second;
+    // uploaded in stream order from the plan's own host copies, so that
+    // making a plan does not wait for the work already queued
+    BHIP(b, hipMemcpyAsync(q.d_act, q.act.data(), sizeof(int) * q.act.size(), hipMemcpyHostToDevice, st), "plan");
+    BHIP(b, hipMemcpyAsync(q.d_tiles, q.tiles.data(), sizeof(int2) * q.tiles.size(), hipMemcpyHostToDevice, st),
+         "plan");
+    if (!q.blocks.empty())
+        BHIP(b, hipMemcpyAsync(q.d_blocks, q.blocks.data(), sizeof(int2) * q.blocks.size(), hipMemcpyHostToDevice, st),
+             "plan");
+    *out = &q;
     return CPIC_OK;
 }
 
 // one step of every active event of a plan (the push also advances the step counters)
-template <typename T> static cpic_status launch_batch_step(cpic_batch* b, const Plan& p)
+template <typename T> static cpic_status launch_batch_step(cpic_batch* b, const Plan& p, hipStream_t st)
 {
-    BHIP(b, launch_batch_field<T>(b->d_desc, p.d_tiles, p.total_tiles, b->cfg, b->st), "batch field");
-    BHIP(b, launch_batch_push<T>(b->d_desc, p.d_blocks, p.total_blocks, b->tpp, b->st), "batch push");
+    BHIP(b, launch_batch_field<T>(b->d_desc, p.d_tiles, p.total_tiles, b->cfg, st), "batch field");
+    BHIP(b, launch_batch_push<T>(b->d_desc, p.d_blocks, p.total_blocks, b->tpp, st), "batch push");
     return CPIC_OK;
 }
-static cpic_status batch_step(cpic_batch* b, const Plan& p)
+static cpic_status batch_step(cpic_batch* b, const Plan& p, hipStream_t st)
 {
-    return b->prec == CPIC_FP64 ? launch_batch_step<double>(b, p) : launch_batch_step<float>(b, p);
+    return b->prec == CPIC_FP64 ? launch_batch_step<double>(b, p, st) : launch_batch_step<float>(b, p, st);
 }
 
-static cpic_status capture(cpic_batch* b, Plan& p)
+static cpic_status capture(cpic_batch* b, Plan& p, hipStream_t st)
 {
     hipGraph_t g = nullptr;
-    BHIP(b, hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal), "capture");
+    BHIP(b, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "capture");
     cpic_status s = CPIC_OK;
-    for (int j = 0; j < kBatchGraphSteps && s == CPIC_OK; j++) s = batch_step(b, p);
-    hipError_t e = hipStreamEndCapture(b->st, &g);
+    for (int j = 0; j < kBatchGraphSteps && s == CPIC_OK; j++) s = batch_step(b, p, st);
+    hipError_t e = hipStreamEndCapture(st, &g);
     if (s) {
         if (g) (void)hipGraphDestroy(g);
         return s;
@@ -276,10 +290,77 @@ extern "C" cpic_status cpic_batch_init_mv(cpic_batch* b)
     return CPIC_OK;
 }
 
+// Estimated work of one step of an event, in site-updates (a particle push
+// costs about as much as two).
+static double step_cost(const cpic_ctx* c) { return (double)c->V + 2.0 * (double)c->np; }
+
+// A launch lane: its stream and the launch groups it runs one after the other.
+struct Lane {
+    hipStream_t st = nullptr;
+    std::vector<std::vector<int>> groups;
+    size_t gi = 0;        // current group
+    int64_t budget = 0;   // steps the current group may still take
+    double queued = 0;    // estimated work enqueued so far
+    bool done() const { return gi >= groups.size(); }
+};
+
+// One segment of a lane's current group: its active events advance to the
+// next particle reordering or to the end of an event, whole graphs replayed
+// and the rest launched step by step.  A group that has finished (or used
+// its step budget) hands over to the lane's next group.
+static cpic_status lane_segment(cpic_batch* b, Lane& L, int64_t max_steps)
+{
+    std::vector<int> act;
+    if (L.budget > 0)
+        for (int e : L.groups[L.gi])
+            if (b->ev[e]->n < b->ev[e]->sc.n_max) act.push_back(e);
+    if (act.empty()) {
+        L.gi++;
+        L.budget = max_steps < 0 ? (int64_t)1 << 40 : max_steps;
+        return CPIC_OK;
+    }
+    int64_t len = L.budget;
+    double cost = 0;
+    for (int e : act) {
+        cpic_ctx* c = b->ev[e];
+        cpic_status s = watch_prepare(c);
+        if (s) return bfail(b, s, "event " + std::to_string(e) + ": " + c->err);
+        s = maybe_sort(c);
+        if (s) return bfail(b, s, "event " + std::to_string(e) + ": " + c->err);
+        len = std::min<int64_t>(len, c->sc.n_max - c->n);
+        len = std::min<int64_t>(len, next_sort_point(c, c->n) - c->n);
+        cost += step_cost(c);
+    }
+    Plan* p = nullptr;
+    cpic_status s = get_plan(b, act, &p, L.st);
+    if (s) return s;
+    int64_t left = len;
+    if (left >= kBatchGraphSteps && !p->graph) {
+        s = capture(b, *p, L.st);
+        if (s) return s;
+    }
+    while (left >= kBatchGraphSteps) {
+        BHIP(b, hipGraphLaunch(p->graph, L.st), "graph launch");
+        advance(b, act, kBatchGraphSteps);
+        left -= kBatchGraphSteps;
+    }
+    for (; left > 0; left--) {
+        s = batch_step(b, *p, L.st);
+        if (s) return s;
+        advance(b, act, 1);
+    }
+    L.budget -= len;
+    L.queued += cost * (double)len;
+    return CPIC_OK;
+}
+
 // Advance every event by up to max_steps steps (to its end when max_steps <
-// 0), launch group after launch group.  Within a group, segments end where
-// an event reaches n_max or a particle reordering point; inside a segment
-// whole graphs are replayed and the rest is launched step by step.
+// 0).  The launch groups are dealt to the lanes by their remaining work,
+// largest first, each to the lane with less work so far; the host then feeds
+// the lanes segment by segment, always the one with less work enqueued, so
+// both streams stay busy.  Every event's work goes to its lane's stream (the
+// events run on the batch stream again afterwards, which waits for the second
+// lane).
 static cpic_status run_steps(cpic_batch* b, int64_t max_steps)
 {
     for (size_t e = 0; e < b->ev.size(); e++)
@@ -287,45 +368,64 @@ static cpic_status run_steps(cpic_batch* b, int64_t max_steps)
             return bfail(b, CPIC_E_INVALID, "cpic_batch_run: event " + std::to_string(e) + " has no state");
     cpic_status s = upload_desc(b);
     if (s) return s;
-    for (const std::vector<int>& grp : launch_groups(b)) {
-        int64_t budget = max_steps < 0 ? (int64_t)1 << 40 : max_steps;
-        while (budget > 0) {
-            std::vector<int> act;
-            for (int e : grp)
-                if (b->ev[e]->n < b->ev[e]->sc.n_max) act.push_back(e);
-            if (act.empty()) break;
-            int64_t len = budget;
-            for (int e : act) {
-                cpic_ctx* c = b->ev[e];
-                s = watch_prepare(c);
-                if (s) return bfail(b, s, "event " + std::to_string(e) + ": " + c->err);
-                s = maybe_sort(c);
-                if (s) return bfail(b, s, "event " + std::to_string(e) + ": " + c->err);
-                len = std::min<int64_t>(len, c->sc.n_max - c->n);
-                len = std::min<int64_t>(len, next_sort_point(c, c->n) - c->n);
-            }
-            Plan* p = nullptr;
-            s = get_plan(b, act, &p);
-            if (s) return s;
-            int64_t left = len;
-            if (left >= kBatchGraphSteps && !p->graph) {
-                s = capture(b, *p);
-                if (s) return s;
-            }
-            while (left >= kBatchGraphSteps) {
-                BHIP(b, hipGraphLaunch(p->graph, b->st), "graph launch");
-                advance(b, act, kBatchGraphSteps);
-                left -= kBatchGraphSteps;
-            }
-            for (; left > 0; left--) {
-                s = batch_step(b, *p);
-                if (s) return s;
-                advance(b, act, 1);
-            }
-            budget -= len;
-        }
+    const std::vector<std::vector<int>> groups = launch_groups(b);
+    const int nl = std::max(1, std::min<int>(b->lanes, (int)groups.size()));
+    for (int l = 1; l < nl; l++) {
+        if (!b->lane_st[l]) BHIP(b, hipStreamCreateWithFlags(&b->lane_st[l], hipStreamNonBlocking), "lane stream");
+        if (!b->ev_join[l]) BHIP(b, hipEventCreateWithFlags(&b->ev_join[l], hipEventDisableTiming), "lane event");
     }
-    return CPIC_OK;
+    if (nl > 1 && !b->ev_fork) BHIP(b, hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming), "lane event");
+    Lane lane[kMaxLanes];
+    lane[0].st = b->st;
+    for (int l = 1; l < nl; l++) lane[l].st = b->lane_st[l];
+    std::vector<std::pair<double, int>> work;
+    for (size_t g = 0; g < groups.size(); g++) {
+        double w = 0;
+        for (int e : groups[g]) {
+            const cpic_ctx* c = b->ev[e];
+            int64_t steps = std::max<int64_t>(c->sc.n_max - c->n, 0);
+            if (max_steps >= 0) steps = std::min<int64_t>(steps, max_steps);
+            w += step_cost(c) * (double)steps;
+        }
+        work.emplace_back(w, (int)g);
+    }
+    std::stable_sort(work.begin(), work.end(), [](const std::pair<double, int>& x, const std::pair<double, int>& y) {
+        return x.first > y.first;
+    });
+    double total[kMaxLanes] = {};
+    for (const auto& wg : work) {
+        int l = 0;
+        for (int k = 1; k < nl; k++)
+            if (total[k] < total[l]) l = k;
+        lane[l].groups.push_back(groups[wg.second]);
+        total[l] += wg.first;
+    }
+    // odd lanes take their groups smallest first, so that large groups run
+    // beside small ones rather than beside each other
+    for (int l = 1; l < nl; l += 2) std::reverse(lane[l].groups.begin(), lane[l].groups.end());
+    for (int l = 0; l < nl; l++) {
+        lane[l].budget = max_steps < 0 ? (int64_t)1 << 40 : max_steps;
+        for (const auto& g : lane[l].groups)
+            for (int e : g) b->ev[e]->st = lane[l].st;
+    }
+    if (nl > 1) {
+        BHIP(b, hipEventRecord(b->ev_fork, b->st), "lane fork");
+        for (int l = 1; l < nl; l++) BHIP(b, hipStreamWaitEvent(lane[l].st, b->ev_fork, 0), "lane fork");
+    }
+    while (s == CPIC_OK) {
+        int l = -1;
+        for (int k = 0; k < nl; k++)
+            if (!lane[k].done() && (l < 0 || lane[k].queued < lane[l].queued)) l = k;
+        if (l < 0) break;
+        s = lane_segment(b, lane[l], max_steps);
+    }
+    for (cpic_ctx* c : b->ev) c->st = b->st;
+    for (int l = 1; l < nl; l++) {
+        hipError_t e = hipEventRecord(b->ev_join[l], lane[l].st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b->st, b->ev_join[l], 0);
+        if (e != hipSuccess && s == CPIC_OK) s = bhip(b, e, "lane join");
+    }
+    return s;
 }
 
 extern "C" cpic_status cpic_batch_run(cpic_batch* b)
@@ -474,6 +574,14 @@ extern "C" cpic_status cpic_batch_set_group_bytes(cpic_batch* b, int64_t bytes)
     return CPIC_OK;
 }
 
+extern "C" cpic_status cpic_batch_set_lanes(cpic_batch* b, int32_t lanes)
+{
+    if (!b) return bfail(nullptr, CPIC_E_INVALID, "cpic_batch_set_lanes: NULL");
+    if (lanes < 1 || lanes > kMaxLanes) return bfail(b, CPIC_E_INVALID, "cpic_batch_set_lanes: 1 to 4");
+    b->lanes = lanes;
+    return CPIC_OK;
+}
+
 extern "C" cpic_status cpic_batch_get_launch(const cpic_batch* b, int32_t out[4])
 {
     if (!b || !out) return CPIC_E_INVALID;
@@ -526,8 +634,15 @@ extern "C" void cpic_batch_destroy(cpic_batch* b)
 {
     if (!b) return;
     if (b->st) (void)hipStreamSynchronize(b->st);
+    for (int l = 1; l < kMaxLanes; l++)
+        if (b->lane_st[l]) (void)hipStreamSynchronize(b->lane_st[l]);
     drop_plans(b);
     (void)hipFree(b->d_desc);
+    for (int l = 1; l < kMaxLanes; l++) {
+        if (b->lane_st[l]) (void)hipStreamDestroy(b->lane_st[l]);
+        if (b->ev_join[l]) (void)hipEventDestroy(b->ev_join[l]);
+    }
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
     for (auto c : b->ev) cpic_destroy(c);
     if (b->own_stream) (void)hipStreamDestroy(b->st);
     delete b;

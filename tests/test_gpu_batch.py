@@ -190,3 +190,40 @@ def test_batch_grouping_does_not_change_results():
             assert np.array_equal(b.observables(e), runs[0].observables(e)), e
     for b in runs:
         b.close()
+
+
+def test_batch_lanes_do_not_change_results():
+    """Two and four launch lanes (the launch groups dealt to concurrent
+    streams) against one, with one group per event so that the lanes hold
+    several groups: identical bits, also when the batch advances in uneven
+    stretches.
+    The results are read right after the runs, without a separate wait for
+    the second lane (the batch stream orders the reads after it)."""
+    print("case batch lanes", flush=True)
+    gl, pl = events(cp.FP32)
+    runs = []
+    for lanes, stepwise in ((1, False), (2, False), (2, True), (4, False)):
+        b = cp.Batch(gl, pl)
+        b.set_group_bytes(1)
+        b.set_lanes(lanes)
+        b.init_mv()
+        if stepwise:
+            for k in (7, 16, 33, 100000):
+                b.step(k)
+        else:
+            b.run()
+        runs.append(b)
+    for e, g in enumerate(gl):
+        N = g["N"]
+        ref = runs[0].get_state(e, cp.STATE_E, (2, N, N, 8))
+        for b in runs[1:]:
+            assert np.array_equal(b.get_state(e, cp.STATE_E, (2, N, N, 8)), ref), e
+            assert np.array_equal(b.observables(e), runs[0].observables(e)), e
+            if pl[e].get("n", 0):
+                assert np.array_equal(b.get_state(e, cp.STATE_PARTICLES, (pl[e]["n"], 20)),
+                                      runs[0].get_state(e, cp.STATE_PARTICLES, (pl[e]["n"], 20))), e
+    for bad in (0, 5):
+        with pytest.raises(cp.CpicError):
+            runs[0].set_lanes(bad)
+    for b in runs:
+        b.close()

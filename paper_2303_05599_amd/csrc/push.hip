@@ -40,11 +40,14 @@ template <int TPP> __device__ __forceinline__ constexpr int subjob_place(int k)
 template <int TPP> constexpr int kSlots = TPP == 4 ? 3 : 2;  // LDS slots per helper wave
 
 // A helper of a four-wave group (the placement of subjob_place<4>), with the
-// loads shared between its sub-jobs: role 1 (i = x) and 2 (i = y) first
-// gather U_i(c-i), E_i at c and c-i at both half steps and the plaquettes
-// they transport, and form E_i and their part of B_eta; then U_i(c) and phi
-// at c +- i for D_i, with U_i(c-i) kept.  Role 3 forms part 7 and E_eta in
-// one round trip.  The results go to the wave's LDS slots (rows r0 + 8 slot).
+// loads shared between its sub-jobs.  Role 1 (i = x) and 2 (i = y) gather in
+// their first phase what other waves of the group also read (U_i(c-i), U_i(c),
+// phi at c +- i, the plaquettes), and form D_i and their part of B_eta; in the
+// second phase, with U_i(c-i) kept, E_i at c and c-i at both half steps,
+// which no other wave reads.  Lines that several waves read are so fetched
+// while they are all in flight, before the L2 turns them over.  Role 3 forms
+// part 7 and E_eta in one round trip.  The results go to the wave's LDS slots
+// (rows r0 + 8 slot).
 template <typename T>
 __device__ __forceinline__ void helper4(int role, const View<T>& A, const View<T>& B, const View<T>& Gv, const Cell& c,
                                         int n, T t, bool eonly, T (*shF)[64], int r0, int lane, bool live)
@@ -64,16 +67,14 @@ __device__ __forceinline__ void helper4(int role, const View<T>& A, const View<T
     const int i = role - 1;
     const uint32_t sb = i == 0 ? c.s_xm : c.s_ym, ce = kCompE + 8 * (uint32_t)i;
     const m3<T> L = vU(A, sb, i);
-    a8<T> e = azero<T>(), part = azero<T>();
-    if (on_e) {
-        const a8<T> h0 = vA(A, c.s, ce), h1 = vA(B, c.s, ce), b0 = vA(A, sb, ce), b1 = vA(B, sb, ce);
-        a8<T> back;
+    a8<T> bf = azero<T>(), part = azero<T>();
+    if (on_bt) {
+        // B_y = +(1/2t) D_x (role 1), B_x = -(1/2t) D_y (role 2)
+        const a8<T> f = transport(vU(A, c.s, i), vA(A, i == 0 ? c.s_xp : c.s_yp, kCompPhi));
+        const a8<T> b = transport_adj(L, vA(A, sb, kCompPhi));
+        const T sc = (i == 0 ? T(1) : T(-1)) / (T(2) * t);
 #pragma unroll
-        for (int q = 0; q < 8; q++) back.v[q] = b0.v[q] + b1.v[q];
-        const a8<T> tb = transport_adj(L, back);
-        const T w = T(1) / (T(4) * t);
-#pragma unroll
-        for (int q = 0; q < 8; q++) e.v[q] = w * ((h0.v[q] + h1.v[q]) + tb.v[q]);
+        for (int q = 0; q < 8; q++) bf.v[q] = sc * (f.v[q] - b.v[q]);
     }
     if (on_be) {
         part = transport_adj(L, vA(Gv, sb, 0));
@@ -85,19 +86,21 @@ __device__ __forceinline__ void helper4(int role, const View<T>& A, const View<T
 #pragma unroll
         for (int q = 0; q < 8; q++) part.v[q] *= T(-0.25);
     }
-    put(0, e);
+    put(1, bf);
     put(2, part);
     CPIC_PHASE();
-    a8<T> bf = azero<T>();
-    if (on_bt) {
-        // B_y = +(1/2t) D_x (role 1), B_x = -(1/2t) D_y (role 2)
-        const a8<T> f = transport(vU(A, c.s, i), vA(A, i == 0 ? c.s_xp : c.s_yp, kCompPhi));
-        const a8<T> b = transport_adj(L, vA(A, sb, kCompPhi));
-        const T sc = (i == 0 ? T(1) : T(-1)) / (T(2) * t);
+    a8<T> e = azero<T>();
+    if (on_e) {
+        const a8<T> h0 = vA(A, c.s, ce), h1 = vA(B, c.s, ce), b0 = vA(A, sb, ce), b1 = vA(B, sb, ce);
+        a8<T> back;
 #pragma unroll
-        for (int q = 0; q < 8; q++) bf.v[q] = sc * (f.v[q] - b.v[q]);
+        for (int q = 0; q < 8; q++) back.v[q] = b0.v[q] + b1.v[q];
+        const a8<T> tb = transport_adj(L, back);
+        const T w = T(1) / (T(4) * t);
+#pragma unroll
+        for (int q = 0; q < 8; q++) e.v[q] = w * ((h0.v[q] + h1.v[q]) + tb.v[q]);
     }
-    put(1, bf);
+    put(0, e);
 }
 __host__ __device__ constexpr int push_block_threads(int tpp) { return tpp == 8 ? 512 : 256; }
 

@@ -308,8 +308,8 @@ bool cpic::fused_active(const cpic_ctx* c) { return c->cfg.split == 4 && fused_o
 // the cell tiles the records are ordered by for the current launch
 static void sort_tiles(const cpic_ctx* c, int* tx, int* ty)
 {
-    *tx = fused_active(c) ? c->cfg.bx : kGatherSortTile;
-    *ty = fused_active(c) ? c->cfg.by : kGatherSortTile;
+    *tx = fused_active(c) ? c->cfg.bx : kGatherSortTileX;
+    *ty = fused_active(c) ? c->cfg.by : kGatherSortTileY;
 }
 
 // Particle records are reordered by cell before step n when n is the first

@@ -277,7 +277,10 @@ hipError_t sort_particles(const SortBufs& b, T* r, int* cell, int* pid, int np, 
                           bool from_position, int* tile_start, hipStream_t st);
 hipError_t launch_tile_start(const unsigned* sorted_keys, int np, int N, int tx, int ty, int* tile_start,
                              hipStream_t st);
-constexpr int kGatherSortTile = 16;  // the gather push's order: 16 x 16 cell tiles
+// the gather push's order: tiles of 32 x 16 cells, 32 cells being one
+// 128-byte line of a single-precision component array (two of a double-precision
+// one), so that no line is split between the tiles of two particle blocks
+constexpr int kGatherSortTileX = 32, kGatherSortTileY = 16;
 constexpr int kSortEvery = 16;  // steps between reorderings of moving particles (measured best of 8, 16, 32, 64)
 
 // ---- initial condition (ic.hip), always double precision

@@ -3,9 +3,9 @@
 // The push gathers the fields around each particle's nearest grid point, and
 // the fused step (fused.hip) pushes the particles of a tile in the workgroup
 // that updates the tile.  Particles are ordered by tiles of tx x ty cells
-// (tile-major, then row-major inside the tile): 16 x 16 for the gather push,
+// (tile-major, then row-major inside the tile): 32 x 16 for the gather push,
 // whose wavefronts and the workgroups that run together on one XCD then read
-// a compact patch of the lattice, and the fused kernel's own tile shape for
+// a compact patch of the lattice in whole cache lines, and the fused kernel's own tile shape for
 // the fused step, which also receives the range of records of every tile.
 // The key of a moving particle is its nearest grid point at the step the
 // order is made for (from its position), of a static one its cell.  The order

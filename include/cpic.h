@@ -377,15 +377,17 @@ cpic_status cpic_get_push_mode(const cpic_ctx* ctx, int32_t* mode);
  * variant, non-temporal stores of the new state}.  The last is set at creation (and by
  * cpic_jets_enable, cpic_set_push_mode): 1 where the state, the new state
  * and what the rest of the step reads exceed the 256 MB last-level cache
- * together (FP64 at 512^2), so that the new links, phi, E and pi bypass it;
+ * together (FP64 at 512^2), so that the new links and phi, which only the
+ * next step reads, do not displace what this step's push reads;
  * cpic_tune may change it.  Results are the same
  * either way. */
 cpic_status cpic_get_launch(const cpic_ctx* ctx, int32_t out[7]);
 
 /* Store policy of the new state in the compressed-tile field update:
- * 1 stores the new links, phi, E and pi non-temporal, 0 with the default
- * cache policy (the choice cpic_get_launch reports in out[6]).  Results are
- * the same either way; takes effect for the next launch. */
+ * 1 stores the new links and phi non-temporal, 0 with the default cache
+ * policy (the choice cpic_get_launch reports in out[6]); the new E and pi,
+ * which the push of the same step reads, always keep the default policy.
+ * Results are the same either way; takes effect for the next launch. */
 cpic_status cpic_set_store_policy(cpic_ctx* ctx, int32_t non_temporal);
 
 /* Launch tuner: times every candidate field-kernel configuration (block shape x

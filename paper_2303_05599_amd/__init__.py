@@ -288,7 +288,7 @@ class Context:
         self._chk(lib().cpic_set_watchdog(self.h, every, max_unitarity, max_gauss_drift, max_casimir_drift))
 
     def set_store_policy(self, non_temporal):
-        """New state of the compressed-tile field update stored non-temporal (1) or not (0)."""
+        """New links and phi of the compressed-tile field update stored non-temporal (1) or not (0)."""
         self._chk(lib().cpic_set_store_policy(self.h, int(non_temporal)))
 
     def set_push_lanes(self, lanes):

@@ -362,8 +362,10 @@ __device__ __forceinline__ void field_ctile_body(const Fields<T>& in, const Fiel
     }
     CPIC_PHASE();
     // drift: U_i <- exp(i (dt/t_half) E_i) U_i ; phi <- phi + dt t_half pi
-    // CP: cache policy of the new state (links, phi, E, pi), chosen by the
-    // host from the step's working set (set_store_policy in capi.hip).
+    // CP: cache policy of the new links and phi, which only the next step's
+    // field update reads, chosen by the host from the step's working set
+    // (set_store_policy in capi.hip); the new E and pi, which this step's push
+    // reads right after, keep the default policy.
     m3<T> U1 = mul(expi(E1, eps_drift), L.U(s, 0));
     if (reunit) U1 = reunitarize(U1);
     vU_st<T, CP>(vo, g.s, 0, U1);
@@ -374,9 +376,9 @@ __device__ __forceinline__ void field_ctile_body(const Fields<T>& in, const Fiel
 #pragma unroll
     for (int a = 0; a < 8; a++) PHI.v[a] += phi_drift * PI.v[a];
     vA_st<T, CP>(vo, g.s, kCompPhi, PHI);
-    vA_st<T, CP>(vo, g.s, kCompE, E1);
-    vA_st<T, CP>(vo, g.s, kCompE + 8, E2);
-    vA_st<T, CP>(vo, g.s, kCompPi, PI);
+    vA_st(vo, g.s, kCompE, E1);
+    vA_st(vo, g.s, kCompE + 8, E2);
+    vA_st(vo, g.s, kCompPi, PI);
 }
 
 template <typename T, int BX, int BY, int CP>

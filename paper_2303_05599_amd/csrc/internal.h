@@ -87,7 +87,7 @@ struct LaunchCfg {
                           // block), 2 one thread per site with the tile and its halo staged in LDS,
                           // 3 as 2 with two rows per link in LDS and the scalars from global memory,
                           // 4 as 3 with the particle push of the tile in the same kernel (fused.hip)
-    int nt_store = 0;     // variant 3 with particles: the new state stored non-temporal
+    int nt_store = 0;     // variant 3 with particles: the new links and phi stored non-temporal
 };
 
 struct PushArgs {

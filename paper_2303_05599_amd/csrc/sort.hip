@@ -97,11 +97,22 @@ __global__ void copy_back_kernel(const T* __restrict__ r2, const int* __restrict
     pid[i] = pid2[i];
 }
 
+// rocPRIM's radix sort takes a block sort and merge passes below
+// merge_sort_limit keys and its Onesweep radix passes above it.  The
+// reorderings run between the captured step graphs, so Onesweep's clearing of
+// its own state (a memset on the stream) is allowed.  Measured at 512^2 with
+// 18-bit cell keys: 10^5 records sort faster by merging (4.8 against 6.5 us per
+// step, amortised over the 16 steps between reorderings), 10^6 by Onesweep
+// (12.2 against 14.3 us per step), so the limit sits at 2^19 (rocPRIM's
+// default is 2^20).
+using SortConfig = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
+                                              rocprim::default_config, (size_t)1 << 19>;
+
 size_t sort_temp_bytes(int np)
 {
     size_t bytes = 0;
     // size query only (no device work) for the widest keys any tile shape gives
-    (void)rocprim::radix_sort_pairs(nullptr, bytes, (unsigned*)nullptr, (unsigned*)nullptr, (int*)nullptr,
+    (void)rocprim::radix_sort_pairs<SortConfig>(nullptr, bytes, (unsigned*)nullptr, (unsigned*)nullptr, (int*)nullptr,
                                     (int*)nullptr, np, 0u, 32u);
     return bytes;
 }
@@ -126,7 +137,7 @@ hipError_t sort_particles(const SortBufs& b, T* r, int* cell, int* pid, int np, 
                        from_position ? 1 : 0, np > 1 ? b.keys : b.keys2, b.vals);
     if (np > 1) {
         size_t bytes = b.temp_bytes;
-        hipError_t e = rocprim::radix_sort_pairs(b.temp, bytes, b.keys, b.keys2, b.vals, b.perm, np, 0u,
+        hipError_t e = rocprim::radix_sort_pairs<SortConfig>(b.temp, bytes, b.keys, b.keys2, b.vals, b.perm, np, 0u,
                                                  (unsigned)key_bits(N, tx, ty), st);
         if (e != hipSuccess) return e;
         T* r2 = static_cast<T*>(b.r2);

@@ -728,11 +728,14 @@ static cpic_status reduce_samples(cpic_ctx* c)
         k = j;
     }
     c->obs_reduced = (int)c->samples.size();
+    // the light-like paths' samples likewise (the same [slot][group][4] layout)
     const int jg = jet_groups(c->V);
-    for (size_t k = (size_t)c->jobs_reduced; k < c->jsamples.size(); k++) {
+    for (size_t k = (size_t)c->jobs_reduced; k < c->jsamples.size();) {
         const int slot = c->jsamples[k].first;
-        HIPCHK(c, launch_reduce_rows(c->jpartials + (size_t)slot * jg * 4, jg, 4, c->jobs + (size_t)slot * 4, c->st),
-               "light-like observables");
+        size_t j = k + 1;
+        while (j < c->jsamples.size() && c->jsamples[j].first == slot + (int)(j - k)) j++;
+        HIPCHK(c, launch_reduce_samples(c->jpartials, jg, slot, (int)(j - k), c->jobs, c->st), "light-like observables");
+        k = j;
     }
     c->jobs_reduced = (int)c->jsamples.size();
     return CPIC_OK;

@@ -531,3 +531,35 @@ def test_links_are_kept_as_two_rows(launch):
     U = out[0][1]
     r3 = np.conj(np.cross(U[..., 0, :], U[..., 1, :]))
     assert np.max(np.abs(U[..., 2, :] - r3)) < 1e-15
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_store_policy_does_not_change_results(precision):
+    """The compressed-tile field update stores the new links and phi
+    non-temporal or with the default cache policy (cpic_set_store_policy):
+    the same run under either policy, switched mid-run, ends in identical
+    bits (fields, particle records, samples)."""
+    print(f"case store policy {precision}", flush=True)
+    N, L, n0, steps, n = 48, 9.0, 4, 40, 2000
+    a = oracle.lattice_spacing(L, N)
+    prec = cp.FP64 if precision == "fp64" else cp.FP32
+    st = inputs.random_state(N, 61, eps_link=0.4)
+    P = inputs.random_particles(n, N, 62, p_scale=0.6)
+    out = []
+    for policy in ((1, 1), (0, 0), (0, 1)):
+        ctx = cp.Context(glasma(N, L, steps=n0 + steps, precision=prec, reunit_every=8 if prec == cp.FP32 else 0),
+                         particle_params(n, 0.3 / a, N, L, 1))
+        ctx.set_launch(64, 8, 1, 1, 3)
+        ctx.load_state(st, n=n0, particles=P)
+        ctx.set_store_policy(policy[0])
+        assert ctx.get_launch()["nt_store"] == policy[0]
+        ctx.step(steps // 2)
+        ctx.set_store_policy(policy[1])
+        ctx.step(steps - steps // 2)
+        ctx.sync()
+        out.append([ctx.get_state(w) for w in (cp.STATE_U, cp.STATE_E, cp.STATE_PHI, cp.STATE_PI,
+                                               cp.STATE_PARTICLES)] + [ctx.observables()])
+        ctx.close()
+    for run in out[1:]:
+        for x, y in zip(out[0], run):
+            assert np.array_equal(x, y)

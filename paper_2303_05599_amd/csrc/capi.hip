@@ -829,8 +829,8 @@ extern "C" cpic_status cpic_observables(cpic_ctx* c, double* tau_fm, double* dpT
 }
 
 // the diagnostics columns of the current state into dout[0..9] (asynchronous;
-// columns 8, 9 only with particles)
-static cpic_status enqueue_diagnostics(cpic_ctx* c)
+// columns 8, 9 only with particles; without energies columns 2..5 stay 0)
+static cpic_status enqueue_diagnostics(cpic_ctx* c, bool energies = true)
 {
     int nb = 0;
     hipError_t e;
@@ -840,8 +840,10 @@ static cpic_status enqueue_diagnostics(cpic_ctx* c)
                 : launch_su2_diag<float>(F2<float>(c, c->cur), c->N, c->sc.dt, c->n, c->dpart, c->dcap, &nb, c->st);
     else
         e = c->prec == CPIC_FP64
-                ? launch_field_diag<double>(F<double>(c, c->cur), c->N, c->sc.dt, c->n, c->dpart, c->dcap, &nb, c->st)
-                : launch_field_diag<float>(F<float>(c, c->cur), c->N, c->sc.dt, c->n, c->dpart, c->dcap, &nb, c->st);
+                ? launch_field_diag<double>(F<double>(c, c->cur), c->N, c->sc.dt, c->n, c->dpart, c->dcap, &nb, c->st,
+                                            energies)
+                : launch_field_diag<float>(F<float>(c, c->cur), c->N, c->sc.dt, c->n, c->dpart, c->dcap, &nb, c->st,
+                                           energies);
     HIPCHK(c, e, "field diagnostics");
     HIPCHK(c, launch_reduce_rows(c->dpart, nb, 8, c->dout, c->st), "reduce");
     if (c->np > 0) {
@@ -856,7 +858,9 @@ static cpic_status enqueue_diagnostics(cpic_ctx* c)
 // the watchdog's check of the current state, or its baseline (asynchronous)
 static cpic_status enqueue_watch(cpic_ctx* c, bool take_base)
 {
-    cpic_status s = enqueue_diagnostics(c);
+    // the checks read the Gauss and unitarity columns and test every column
+    // for a non-finite value: the energies are not needed
+    cpic_status s = enqueue_diagnostics(c, false);
     if (s) return s;
     // the charges' Casimirs are kept by the rotation update (SU(3)); the
     // logarithm update lets them drift by design

@@ -662,9 +662,12 @@ hipError_t launch_field_step(const Fields<T>& in, const Fields<T>& out, T* gpl, 
 // ------------------------------------------------------------------ diagnostics
 // Per block: [sum |G|^2, max |G|, K_T, K_L, V_B, V_phi, max |U U^+ - 1|, sum |U U^+ - 1|^2]
 // with the momenta averaged to integer time n: E(n) = E(n-1/2) + (dt/2) F(n).
+// Without ENERGIES (the drift watchdog, which reads the Gauss and unitarity
+// columns) the energy columns stay 0; every state array still enters the
+// sums of columns 0 and 7, so a non-finite value anywhere shows there.
 constexpr int kDiagCols = 8;
 
-template <typename T>
+template <typename T, bool ENERGIES>
 __global__ __launch_bounds__(256) void field_diag_kernel(Fields<T> f, int N, T t, T inv_t, T half_dt, int n,
                                                          double* partials)
 {
@@ -688,6 +691,7 @@ __global__ __launch_bounds__(256) void field_diag_kernel(Fields<T> f, int N, T t
         }
         v[0] = G2;
         v[1] = sqrt(G2);
+        if constexpr (ENERGIES) {
         a8<T> F1, F2, Fpi;
         T retr = 0, grad2 = 0;
         kick_forces<T>(GlobalSrc<T>{vf}, nb, t, inv_t, PHI, F1, F2, Fpi, &retr, &grad2);
@@ -702,6 +706,7 @@ __global__ __launch_bounds__(256) void field_diag_kernel(Fields<T> f, int N, T t
         v[3] = (double)t * p2;
         v[4] = 2.0 * (double)t * (3.0 - (double)retr);
         v[5] = (double)inv_t * (double)grad2;
+        }
         double umax = 0, usq = 0;
         for (int i = 0; i < 2; i++) {
             const m3<T> u = vU(vf, nb.s, i);
@@ -721,14 +726,18 @@ __global__ __launch_bounds__(256) void field_diag_kernel(Fields<T> f, int N, T t
 
 template <typename T>
 hipError_t launch_field_diag(const Fields<T>& f, int N, double dt, int n, double* partials, int nblk_cap,
-                             int* nblk_out, hipStream_t st)
+                             int* nblk_out, hipStream_t st, bool energies)
 {
     const int V = N * N, nblk = (V + 255) / 256;
     if (nblk > nblk_cap) return hipErrorInvalidValue;
     *nblk_out = nblk;
     const double t = n * dt;
-    hipLaunchKernelGGL(field_diag_kernel<T>, dim3(nblk), dim3(256), 0, st, f, N, T(t), T(n > 0 ? 1.0 / t : 0.0),
-                       T(0.5 * dt), n, partials);
+    if (energies)
+        hipLaunchKernelGGL((field_diag_kernel<T, true>), dim3(nblk), dim3(256), 0, st, f, N, T(t),
+                           T(n > 0 ? 1.0 / t : 0.0), T(0.5 * dt), n, partials);
+    else
+        hipLaunchKernelGGL((field_diag_kernel<T, false>), dim3(nblk), dim3(256), 0, st, f, N, T(t),
+                           T(n > 0 ? 1.0 / t : 0.0), T(0.5 * dt), n, partials);
     return hipGetLastError();
 }
 
@@ -737,8 +746,8 @@ template hipError_t launch_field_step<double>(const Fields<double>&, const Field
 template hipError_t launch_field_step<float>(const Fields<float>&, const Fields<float>&, float*, int, const Schedule&,
                                              int*, const LaunchCfg&, hipStream_t, const KTimer&);
 template hipError_t launch_field_diag<double>(const Fields<double>&, int, double, int, double*, int, int*,
-                                              hipStream_t);
+                                              hipStream_t, bool);
 template hipError_t launch_field_diag<float>(const Fields<float>&, int, double, int, double*, int, int*,
-                                             hipStream_t);
+                                             hipStream_t, bool);
 
 }  // namespace cpic

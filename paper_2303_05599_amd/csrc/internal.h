@@ -143,9 +143,10 @@ constexpr int kPlaqReals = 8;
 template <typename T>
 hipError_t launch_field_step(const Fields<T>& in, const Fields<T>& out, T* gpl, int N, const Schedule& sc,
                              int* d_step, const LaunchCfg& cfg, hipStream_t st, const KTimer& tm = KTimer{});
+// energies = false: the energy columns are left 0 (the drift watchdog's checks)
 template <typename T>
 hipError_t launch_field_diag(const Fields<T>& f, int N, double dt, int n, double* partials, int nblk_cap,
-                             int* nblk_out, hipStream_t st);
+                             int* nblk_out, hipStream_t st, bool energies = true);
 // batched launches: logical block g works on tile (particle block) map[g].y
 // of event map[g].x of the descriptor table
 template <typename T>

@@ -235,6 +235,16 @@ cpic_status cpic_transport(cpic_ctx* ctx, double* out, int32_t cap, int32_t* n_s
  */
 cpic_status cpic_diagnostics(cpic_ctx* ctx, double out[10]);
 
+/* The four headline quantities of cpic_diagnostics at the current step:
+ *   gauss_l2      = sqrt(out[0]), the L2 norm of the Gauss residual over the lattice;
+ *   energy_lat    = out[2] + out[3] + out[4] + out[5], the lattice energy (hat units);
+ *   unitarity_max = out[6];
+ *   casimir_max   = max(out[8], out[9]) (0 without particles).
+ * Any pointer may be NULL.  CPIC_E_NAN as cpic_diagnostics (nothing
+ * written).  Synchronises. */
+cpic_status cpic_diagnostics_summary(cpic_ctx* ctx, double* gauss_l2, double* energy_lat, double* unitarity_max,
+                                     double* casimir_max);
+
 /*
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, serving loops, harnesses that forbid hipMalloc): the field columns

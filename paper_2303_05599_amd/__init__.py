@@ -84,6 +84,7 @@ def lib():
             "cpic_timing": [P, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(i64), ctypes.POINTER(i64)],
             "cpic_straggler_pushes": [P, ctypes.POINTER(i64)],
             "cpic_set_watchdog": [P, i32, d, d, d],
+            "cpic_diagnostics_summary": [P, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(d)],
             "cpic_transport": [P, P, i32, ctypes.POINTER(i32)],
             "cpic_jets_transport": [P, P, i32, ctypes.POINTER(i32)],
             "cpic_batch_create": [i32, ctypes.POINTER(GlasmaParams), ctypes.POINTER(ParticleParams), P, pp],
@@ -235,6 +236,12 @@ class Context:
         out = np.zeros(10)
         self._chk(lib().cpic_diagnostics(self.h, _ptr(out)))
         return out
+
+    def diagnostics_summary(self):
+        """(gauss_l2, energy_lat, unitarity_max, casimir_max) (cpic_diagnostics_summary)."""
+        v = [ctypes.c_double() for _ in range(4)]
+        self._chk(lib().cpic_diagnostics_summary(self.h, *(ctypes.byref(x) for x in v)))
+        return tuple(x.value for x in v)
 
     def _shape(self, which):
         N = self.N

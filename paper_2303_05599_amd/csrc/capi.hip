@@ -905,6 +905,19 @@ extern "C" cpic_status cpic_diagnostics(cpic_ctx* c, double out[10])
     return CPIC_OK;
 }
 
+extern "C" cpic_status cpic_diagnostics_summary(cpic_ctx* c, double* gauss_l2, double* energy_lat,
+                                                double* unitarity_max, double* casimir_max)
+{
+    double d[10];
+    const cpic_status s = cpic_diagnostics(c, d);
+    if (s) return s;
+    if (gauss_l2) *gauss_l2 = std::sqrt(d[0]);
+    if (energy_lat) *energy_lat = d[2] + d[3] + d[4] + d[5];
+    if (unitarity_max) *unitarity_max = d[6];
+    if (casimir_max) *casimir_max = c->np > 0 ? std::max(d[8], d[9]) : 0.0;
+    return CPIC_OK;
+}
+
 // ------------------------------------------------------------------ state exchange
 // algebra components and complex link entries per site and direction
 static int ncomp(const cpic_ctx* c) { return c->nc == 2 ? 3 : 8; }

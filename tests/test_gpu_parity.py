@@ -371,6 +371,12 @@ def test_diagnostics_match_oracle():
     assert np.allclose(d[2:6], H, rtol=1e-12, atol=1e-12)
     mu, _ = oracle.unitarity(N, st["U"])
     assert d[6] == pytest.approx(mu, rel=1e-3, abs=1e-15)
+    # the four-quantity form: the Gauss L2 norm, the summed lattice energy,
+    # the unitarity maximum and (without particles) no Casimir drift
+    gl2, en, um, cm = ctx.diagnostics_summary()
+    assert gl2 == pytest.approx(np.sqrt(np.sum(G ** 2)), rel=1e-12)
+    assert en == pytest.approx(np.sum(H), rel=1e-12)
+    assert um == d[6] and cm == 0.0
 
 
 def test_mv_event_invariants_fp64():

@@ -391,6 +391,9 @@ def test_mv_event_invariants_fp64():
     assert d[1] < 1e-12          # Gauss
     assert d[6] < 1e-13          # unitarity
     assert d[8] < 1e-11 and d[9] < 1e-11   # Casimirs
+    gl2, en, um, cm = ctx.diagnostics_summary()
+    assert gl2 == pytest.approx(np.sqrt(d[0]), rel=1e-14) and en == pytest.approx(np.sum(d[2:6]), rel=1e-14)
+    assert um == d[6] and cm == max(d[8], d[9])
 
 
 def test_fp32_against_fp64_oracle():

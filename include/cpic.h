@@ -165,8 +165,9 @@ cpic_status cpic_evolve(cpic_ctx* ctx, double tau_target_fm);
 cpic_status cpic_sync(cpic_ctx* ctx);
 
 /* Drift watchdog (on by default, every 64 steps).  After every `every`-th
- * step the device computes the cpic_diagnostics columns of the state and
- * compares them, without synchronising, with
+ * step the device computes the Gauss, unitarity and Casimir columns of
+ * cpic_diagnostics for the state (not the energies) and compares them,
+ * without synchronising, with
  *   max_unitarity       max |U U^+ - 1| over all link entries (absolute);
  *   max_gauss_drift     the change of max |G| (the Gauss residual of Sec. II)
  *                       since the state was installed, relative to max(1, its

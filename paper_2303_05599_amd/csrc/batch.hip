@@ -182,9 +182,15 @@ static cpic_status get_plan(cpic_batch* b, const std::vector<int>& act, Plan** o
     }
     p.total_tiles = (int)p.tiles.size();
     p.total_blocks = (int)p.blocks.size();
-    BHIP(b, hipMalloc(&p.d_act, sizeof(int) * act.size()), "plan");
-    BHIP(b, hipMalloc(&p.d_tiles, sizeof(int2) * std::max<size_t>(p.tiles.size(), 1)), "plan");
-    BHIP(b, hipMalloc(&p.d_blocks, sizeof(int2) * std::max<size_t>(p.blocks.size(), 1)), "plan");
+    hipError_t e = hipMalloc(&p.d_act, sizeof(int) * act.size());
+    if (e == hipSuccess) e = hipMalloc(&p.d_tiles, sizeof(int2) * std::max<size_t>(p.tiles.size(), 1));
+    if (e == hipSuccess) e = hipMalloc(&p.d_blocks, sizeof(int2) * std::max<size_t>(p.blocks.size(), 1));
+    if (e != hipSuccess) {
+        (void)hipFree(p.d_act);
+        (void)hipFree(p.d_tiles);
+        (void)hipFree(p.d_blocks);
+        return bhip(b, e, "plan");
+    }
     auto ins = b->plans.emplace(act, std::move(p));
     Plan& q = ins.first->second;
     // uploaded in stream order from the plan's own host copies, so that

@@ -103,8 +103,9 @@ static void free_all(cpic_ctx* c)
     (void)hipFree(c->d_watchv); (void)hipFree(c->d_watchbase);
     if (c->h_stage) (void)hipHostFree(c->h_stage);
     (void)hipFree(c->dpart); (void)hipFree(c->dout);
-    (void)hipFree(c->pid); (void)hipFree(c->sb.keys); (void)hipFree(c->sb.keys2); (void)hipFree(c->sb.vals); (void)hipFree(c->sb.perm);
+    (void)hipFree(c->pid); (void)hipFree(c->sb.keys); (void)hipFree(c->sb.keys2); (void)hipFree(c->sb.perm);
     (void)hipFree(c->sb.temp); (void)hipFree(c->sb.r2); (void)hipFree(c->sb.cell2); (void)hipFree(c->sb.pid2);
+    (void)hipFree(c->sb.count); (void)hipFree(c->sb.offs);
     (void)hipFree(c->tile_start); (void)hipFree(c->strag); (void)hipFree(c->strag_count);
     (void)hipFree(c->d_strag_total);
     if (c->own_stream && c->st) (void)hipStreamDestroy(c->st);
@@ -209,12 +210,16 @@ extern "C" cpic_status cpic_create(const cpic_glasma_params* gp, const cpic_part
         if (e == hipSuccess) e = hipMalloc(&c->pid, sizeof(int) * np);
         if (e == hipSuccess) e = hipMalloc(&c->sb.keys, sizeof(unsigned) * np);
         if (e == hipSuccess) e = hipMalloc(&c->sb.keys2, sizeof(unsigned) * np);
-        if (e == hipSuccess) e = hipMalloc(&c->sb.vals, sizeof(int) * np);
         if (e == hipSuccess) e = hipMalloc(&c->sb.perm, sizeof(int) * np);
         if (e == hipSuccess) e = hipMalloc(&c->sb.r2, (size_t)kPartReals * np * c->tsz);
         if (e == hipSuccess) e = hipMalloc(&c->sb.cell2, sizeof(int) * 2 * np);
         if (e == hipSuccess) e = hipMalloc(&c->sb.pid2, sizeof(int) * np);
-        c->sb.temp_bytes = std::max<size_t>(sort_temp_bytes((int)np), 16);
+        c->sb.key_cap = key_capacity(c->N);
+        if (e == hipSuccess) e = hipMalloc(&c->sb.count, sizeof(int) * (size_t)c->sb.key_cap);
+        if (e == hipSuccess) e = hipMalloc(&c->sb.offs, sizeof(int) * (size_t)c->sb.key_cap);
+        // the reordering keeps the key counts zero between its calls
+        if (e == hipSuccess) e = hipMemsetAsync(c->sb.count, 0, sizeof(int) * (size_t)c->sb.key_cap, c->st);
+        c->sb.temp_bytes = std::max<size_t>(sort_temp_bytes(c->N), 16);
         if (e == hipSuccess) e = hipMalloc(&c->sb.temp, c->sb.temp_bytes);
         if (c->nc == 3) {
             const int nt = fused_tiles(c->N, 8, 8);  // the most tiles of any fused shape

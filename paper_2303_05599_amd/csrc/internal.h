@@ -262,13 +262,17 @@ hipError_t launch_su2_diag(const Fields2<T>& f, int N, double dt, int n, double*
 // ---- particle ordering (sort.hip)
 struct SortBufs {
     unsigned *keys = nullptr, *keys2 = nullptr;
-    int *vals = nullptr, *perm = nullptr;
-    void* temp = nullptr;
+    int* perm = nullptr;
+    int *count = nullptr, *offs = nullptr;  // [key_cap] records per key (zero between reorderings), run ends
+    int key_cap = 0;
+    void* temp = nullptr;  // the scan's temporary storage
     size_t temp_bytes = 0;
     void* r2 = nullptr;  // [19][np] scratch records
     int *cell2 = nullptr, *pid2 = nullptr;
 };
-size_t sort_temp_bytes(int np);
+// keys of an N x N lattice lie below key_capacity(N) for every tile shape
+int key_capacity(int N);
+size_t sort_temp_bytes(int N);
 // Orders the records by tiles of tx x ty cells (keys from the nearest grid
 // point of the position with from_position, else from the cell); with
 // tile_start ([ntiles + 1]) also the range of records of every tile.  The

@@ -5,15 +5,15 @@
 // that updates the tile.  Particles are ordered by tiles of tx x ty cells
 // (tile-major, then row-major inside the tile): 32 x 16 for the gather push,
 // whose wavefronts and the workgroups that run together on one XCD then read
-// a compact patch of the lattice in whole cache lines, and the fused kernel's own tile shape for
-// the fused step, which also receives the range of records of every tile.
-// The key of a moving particle is its nearest grid point at the step the
-// order is made for (from its position), of a static one its cell.  The order
-// comes from a stable radix sort of the keys (rocPRIM, deterministic); the
-// records are permuted into a scratch copy and copied back so that buffer
-// addresses (captured in HIP graphs) never change.  pid tracks each record's
-// original index for state exchange.
-#include <rocprim/device/device_radix_sort.hpp>
+// a compact patch of the lattice in whole cache lines, and the fused kernel's
+// own tile shape for the fused step, which also receives the range of records
+// of every tile.  The key of a moving particle is its nearest grid point at
+// the step the order is made for (from its position), of a static one its
+// cell.  The order is that of a stable sort of the keys (a counting sort,
+// below); the records are permuted into a scratch copy and copied back so
+// that buffer addresses (captured in HIP graphs) never change.  pid tracks
+// each record's original index for state exchange.
+#include <rocprim/device/device_scan.hpp>
 
 #include "internal.h"
 
@@ -23,16 +23,10 @@ __host__ __device__ inline unsigned sort_key_bound(int N, int tx, int ty)
 {
     return (unsigned)fused_tiles(N, tx, ty) * (unsigned)(tx * ty);
 }
-static int key_bits(int N, int tx, int ty)
-{
-    int bits = 1;
-    while (bits < 32 && (1u << bits) < sort_key_bound(N, tx, ty)) bits++;
-    return bits;
-}
 
 template <typename T>
 __global__ void cell_keys_kernel(const T* __restrict__ r, const int* __restrict__ cell, int np, int N, int tx, int ty,
-                                 int from_position, unsigned* keys, int* vals)
+                                 int from_position, unsigned* keys, int* count)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
@@ -52,8 +46,9 @@ __global__ void cell_keys_kernel(const T* __restrict__ r, const int* __restrict_
     cy = min(max(cy, 0), N - 1);
     const int ntx = (N + tx - 1) / tx;
     const int tile = (cy / ty) * ntx + cx / tx;
-    keys[p] = (unsigned)(tile * tx * ty + (cy % ty) * tx + cx % tx);
-    vals[p] = p;
+    const unsigned key = (unsigned)(tile * tx * ty + (cy % ty) * tx + cx % tx);
+    keys[p] = key;
+    if (count) atomicAdd(&count[key], 1);
 }
 
 // tile_start[t] = first record of tile t (or of the next non-empty tile),
@@ -97,23 +92,87 @@ __global__ void copy_back_kernel(const T* __restrict__ r2, const int* __restrict
     pid[i] = pid2[i];
 }
 
-// rocPRIM's radix sort takes a block sort and merge passes below
-// merge_sort_limit keys and its Onesweep radix passes above it.  The
-// reorderings run between the captured step graphs, so Onesweep's clearing of
-// its own state (a memset on the stream) is allowed.  Measured at 512^2 with
-// 18-bit cell keys: 10^5 records sort faster by merging (4.8 against 6.5 us per
-// step, amortised over the 16 steps between reorderings), 10^6 by Onesweep
-// (12.2 against 14.3 us per step), so the limit sits at 2^19 (rocPRIM's
-// default is 2^20).
-using SortConfig = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
-                                              rocprim::default_config, (size_t)1 << 19>;
+// The order comes from a counting sort of the cell keys (dense integers below
+// key_capacity(N)): count the records of every key as the keys are formed
+// (atomic increments, whose totals do not depend on their order), an
+// exclusive scan of the counts (rocPRIM, integers: exact), and a scatter that
+// takes each record's slot in its key's run with an atomic increment of the
+// run's cursor.  The slots inside a run then follow the order the increments
+// happened in, so a last pass orders every run of more than one record by
+// input index: the result is the permutation of a stable sort, the same on
+// every run.  Runs are short (a few records per cell); a long one (records
+// piled on one cell) is heap-sorted, so its cost stays n log n.  The last pass
+// also clears the counts: they are zero between reorderings (and from
+// allocation on).
+__global__ void zero_kernel(int* a, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 0;
+}
+// offs: exclusive scan of the counts on entry, the end of every run on exit
+__global__ void scatter_keys_kernel(const unsigned* __restrict__ keys, int np, int* offs, unsigned* keys_out,
+                                    int* perm)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const unsigned k = keys[p];
+    const int slot = atomicAdd(&offs[k], 1);
+    keys_out[slot] = k;
+    perm[slot] = p;
+}
+__device__ void sift_down(int* a, int root, int n)
+{
+    while (2 * root + 1 < n) {
+        int child = 2 * root + 1;
+        if (child + 1 < n && a[child + 1] > a[child]) child++;
+        if (a[root] >= a[child]) return;
+        const int t = a[root];
+        a[root] = a[child];
+        a[child] = t;
+        root = child;
+    }
+}
+__global__ void order_runs_kernel(int* count, const int* __restrict__ ends, int nkeys, int* perm)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nkeys) return;
+    const int c = count[k];
+    count[k] = 0;
+    if (c < 2) return;
+    int* a = perm + (ends[k] - c);
+    if (c <= 32) {
+        for (int i = 1; i < c; i++) {
+            const int v = a[i];
+            int j = i - 1;
+            while (j >= 0 && a[j] > v) {
+                a[j + 1] = a[j];
+                j--;
+            }
+            a[j + 1] = v;
+        }
+        return;
+    }
+    for (int i = c / 2 - 1; i >= 0; i--) sift_down(a, i, c);
+    for (int n = c - 1; n > 0; n--) {
+        const int t = a[0];
+        a[0] = a[n];
+        a[n] = t;
+        sift_down(a, 0, n);
+    }
+}
 
-size_t sort_temp_bytes(int np)
+int key_capacity(int N)
+{
+    // the largest key bound of any tile shape (tiles of at most 64 x 64 cells)
+    return (N + 64) * (N + 64);
+}
+
+size_t sort_temp_bytes(int N)
 {
     size_t bytes = 0;
-    // size query only (no device work) for the widest keys any tile shape gives
-    (void)rocprim::radix_sort_pairs<SortConfig>(nullptr, bytes, (unsigned*)nullptr, (unsigned*)nullptr, (int*)nullptr,
-                                    (int*)nullptr, np, 0u, 32u);
+    // size query only (no device work)
+    (void)rocprim::exclusive_scan(nullptr, bytes, (int*)nullptr, (int*)nullptr, 0, (size_t)key_capacity(N),
+                                  rocprim::plus<int>());
     return bytes;
 }
 
@@ -131,15 +190,23 @@ hipError_t sort_particles(const SortBufs& b, T* r, int* cell, int* pid, int np, 
                           bool from_position, int* tile_start, hipStream_t st)
 {
     if (np <= 0 || tx <= 0 || ty <= 0) return np <= 0 ? hipSuccess : hipErrorInvalidValue;
-    const int blocks = (np + 255) / 256;
+    const unsigned nkeys = sort_key_bound(N, tx, ty);
+    if (nkeys > (unsigned)b.key_cap) return hipErrorInvalidValue;
+    const int blocks = (np + 255) / 256, kblocks = (int)((nkeys + 255) / 256);
     // a single record needs no sort: its key is the sorted key array
     hipLaunchKernelGGL(cell_keys_kernel<T>, dim3(blocks), dim3(256), 0, st, r, cell, np, N, tx, ty,
-                       from_position ? 1 : 0, np > 1 ? b.keys : b.keys2, b.vals);
+                       from_position ? 1 : 0, np > 1 ? b.keys : b.keys2, np > 1 ? b.count : nullptr);
     if (np > 1) {
         size_t bytes = b.temp_bytes;
-        hipError_t e = rocprim::radix_sort_pairs<SortConfig>(b.temp, bytes, b.keys, b.keys2, b.vals, b.perm, np, 0u,
-                                                 (unsigned)key_bits(N, tx, ty), st);
-        if (e != hipSuccess) return e;
+        hipError_t e = rocprim::exclusive_scan(b.temp, bytes, b.count, b.offs, 0, (size_t)nkeys, rocprim::plus<int>(),
+                                               st);
+        if (e != hipSuccess) {
+            // keep the counts zero for the next reordering
+            hipLaunchKernelGGL(zero_kernel, dim3(kblocks), dim3(256), 0, st, b.count, (int)nkeys);
+            return e;
+        }
+        hipLaunchKernelGGL(scatter_keys_kernel, dim3(blocks), dim3(256), 0, st, b.keys, np, b.offs, b.keys2, b.perm);
+        hipLaunchKernelGGL(order_runs_kernel, dim3(kblocks), dim3(256), 0, st, b.count, b.offs, (int)nkeys, b.perm);
         T* r2 = static_cast<T*>(b.r2);
         hipLaunchKernelGGL(permute_kernel<T>, dim3(blocks), dim3(256), 0, st, r, cell, pid, b.perm, np, r2, b.cell2,
                            b.pid2);

@@ -6,6 +6,7 @@ that field) per site and component over the first 50 steps (the agreement the
 method's double-precision path is held to; both implementations are exact up
 to rounding order).  Integer data (particle cells) must agree exactly.
 """
+import ctypes
 import math
 import os
 
@@ -572,3 +573,53 @@ def test_store_policy_does_not_change_results(precision):
     for run in out[1:]:
         for x, y in zip(out[0], run):
             assert np.array_equal(x, y)
+
+
+class _CkptHeader(ctypes.Structure):
+    _fields_ = [("magic", ctypes.c_char * 8), ("version", ctypes.c_int32), ("N", ctypes.c_int32),
+                ("prec", ctypes.c_int32), ("n", ctypes.c_int32), ("cur", ctypes.c_int32),
+                ("nsamples", ctypes.c_int32), ("np", ctypes.c_int64), ("nslots", ctypes.c_int32),
+                ("jets", ctypes.c_int32), ("gp", cp.GlasmaParams), ("pp", cp.ParticleParams)]
+
+
+def internal_order(path, reals_per_site=68, part_reals=19):
+    """Cells and original indices of the records in the library's internal
+    order, read from a checkpoint (state, records, cells, pid in that order)."""
+    raw = open(path, "rb").read()
+    h = _CkptHeader.from_buffer_copy(raw)
+    tsz = 8 if h.prec == cp.FP64 else 4
+    off = ctypes.sizeof(h) + 8 * h.nsamples + reals_per_site * h.N * h.N * tsz + part_reals * h.np * tsz
+    cell = np.frombuffer(raw, np.int32, 2 * h.np, off).reshape(2, h.np)
+    pid = np.frombuffer(raw, np.int32, h.np, off + 8 * h.np)
+    return h, cell, pid
+
+
+@pytest.mark.parametrize("n,static,shape", [(3000, False, None), (3000, True, None), (40000, False, None),
+                                            (3000, False, (16, 16))])
+def test_reordering_is_a_stable_sort_by_tile(tmp_path, n, static, shape):
+    """Right after the first reordering (from the input order) the records are
+    ordered by their tile key (32 x 16 cell tiles for the gather push, the
+    fused kernel's tiles for the fused step; row-major inside a tile), records
+    of one cell in ascending input index: the permutation of a stable sort.
+    40000 records on 48^2 put 17 on a cell on average."""
+    print(f"case reorder n={n} static={static} shape={shape}", flush=True)
+    N, L, n_form = 48, 9.0, 3
+    a = oracle.lattice_spacing(L, N)
+    st = inputs.random_state(N, 91, eps_link=0.4)
+    P = inputs.random_particles(n, N, 92, p_scale=0.6)
+    ctx = cp.Context(glasma(N, L, steps=20), particle_params(n, math.inf if static else 0.3 / a, N, L, n_form))
+    if shape:
+        ctx.set_launch(shape[0], shape[1], 1, 1, 4)
+    ctx.load_state(st, n=0, particles=P)
+    ctx.step(n_form + 1)   # the reordering before the push of step n_form; the cells of that step stored by it
+    path = tmp_path / "order.ckpt"
+    ctx.save(str(path))
+    ctx.close()
+    h, cell, pid = internal_order(path)
+    assert h.np == n and sorted(pid.tolist()) == list(range(n))
+    tx, ty = shape or (32, 16)
+    cx, cy = cell[0].astype(np.int64), cell[1].astype(np.int64)
+    ntx = (N + tx - 1) // tx
+    key = ((cy // ty) * ntx + cx // tx) * (tx * ty) + (cy % ty) * tx + cx % tx
+    order = np.lexsort((pid, key))       # by key, then by input index
+    assert np.array_equal(order, np.arange(n))

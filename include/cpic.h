@@ -154,7 +154,8 @@ cpic_status cpic_step(cpic_ctx* ctx, int32_t n_steps);
 /* Advance until tau >= tau_target_fm (or n_max).  Asynchronous; every step
  * runs from a HIP graph: graphs of up to 16 steps, each ending at the next
  * particle reordering point or at the target, captured once per length and
- * buffer parity and replayed.  A no-op if already there. */
+ * buffer parity and replayed; a graph that starts at a reordering point of
+ * moving particles starts with the reordering.  A no-op if already there. */
 cpic_status cpic_evolve(cpic_ctx* ctx, double tau_target_fm);
 
 /* Wait for the context's stream; reports CPIC_E_CELL_JUMP if any particle

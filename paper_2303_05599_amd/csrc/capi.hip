@@ -89,9 +89,10 @@ static bool valid_N(int N)
 
 static void free_all(cpic_ctx* c)
 {
-    for (int p = 0; p < 2; p++)
-        for (int k = 0; k <= kGraphSteps; k++)
-            if (c->gexec[p][k]) (void)hipGraphExecDestroy(c->gexec[p][k]);
+    for (auto& byp : c->gexec)
+        for (auto& byk : byp)
+            for (auto& g : byk)
+                if (g) (void)hipGraphExecDestroy(g);
     for (auto e : c->ev_field) (void)hipEventDestroy(e);
     for (auto e : c->ev_push) (void)hipEventDestroy(e);
     for (auto e : c->ev_jets) (void)hipEventDestroy(e);
@@ -338,35 +339,51 @@ int cpic::next_sort_point(const cpic_ctx* c, int n)
     m = ((m + kSortEvery - 1) / kSortEvery) * kSortEvery;
     return m;
 }
-cpic_status cpic::maybe_sort(cpic_ctx* c)
+// whether the records are due for a reordering before step n, and by which tiles
+static bool sort_due(const cpic_ctx* c, int* tx, int* ty)
 {
-    int tx, ty;
-    sort_tiles(c, &tx, &ty);
-    if (!is_sort_point(c, c->n) || (c->sorted_at == c->n && c->sort_tx == tx && c->sort_ty == ty)) return CPIC_OK;
-    c->sorted_at = c->n;
+    sort_tiles(c, tx, ty);
+    return is_sort_point(c, c->n) && !(c->sorted_at == c->n && c->sort_tx == *tx && c->sort_ty == *ty);
+}
+// enqueue the reordering (also under graph capture: no memset, no synchronisation)
+static hipError_t enqueue_sort(cpic_ctx* c, int tx, int ty)
+{
     // the tile ranges wherever the order is one a fused step can use
     int* ts = c->tile_start && fused_shape(tx, ty) ? c->tile_start : nullptr;
     const bool pos = !c->is_static;
-    hipError_t e = c->prec == CPIC_FP64
-                       ? sort_particles<double>(c->sb, (double*)c->pr, c->pcell, c->pid, (int)c->np, c->N, tx, ty, pos,
-                                                ts, c->st)
-                       : sort_particles<float>(c->sb, (float*)c->pr, c->pcell, c->pid, (int)c->np, c->N, tx, ty, pos,
-                                               ts, c->st);
-    if (e != hipSuccess) return hip_fail(c, e, "particle sort");
+    return c->prec == CPIC_FP64
+               ? sort_particles<double>(c->sb, (double*)c->pr, c->pcell, c->pid, (int)c->np, c->N, tx, ty, pos, ts,
+                                        c->st)
+               : sort_particles<float>(c->sb, (float*)c->pr, c->pcell, c->pid, (int)c->np, c->N, tx, ty, pos, ts,
+                                       c->st);
+}
+static void mark_sorted(cpic_ctx* c, int tx, int ty)
+{
+    c->sorted_at = c->n;
     c->sort_tx = tx;
     c->sort_ty = ty;
     if (c->is_static) c->static_sorted = true;
+}
+cpic_status cpic::maybe_sort(cpic_ctx* c)
+{
+    int tx, ty;
+    if (!sort_due(c, &tx, &ty)) return CPIC_OK;
+    c->sorted_at = c->n;
+    const hipError_t e = enqueue_sort(c, tx, ty);
+    if (e != hipSuccess) return hip_fail(c, e, "particle sort");
+    mark_sorted(c, tx, ty);
     return CPIC_OK;
 }
 
 static void drop_graphs(cpic_ctx* c)
 {
-    for (int p = 0; p < 2; p++)
-        for (int k = 0; k <= kGraphSteps; k++)
-            if (c->gexec[p][k]) {
-                (void)hipGraphExecDestroy(c->gexec[p][k]);
-                c->gexec[p][k] = nullptr;
-            }
+    for (auto& byp : c->gexec)
+        for (auto& byk : byp)
+            for (auto& g : byk)
+                if (g) {
+                    (void)hipGraphExecDestroy(g);
+                    g = nullptr;
+                }
 }
 
 static cpic_status reset_counters(cpic_ctx* c, int n)
@@ -592,18 +609,23 @@ static cpic_status eager_steps(cpic_ctx* c, int k)
 }
 
 // a graph of k steps from buffer `parity`
-static cpic_status build_graph(cpic_ctx* c, int parity, int k)
+// sorted: the graph starts with the reordering of the records by tx x ty tiles
+static cpic_status build_graph(cpic_ctx* c, int parity, int k, bool sorted, int tx, int ty)
 {
     hipGraph_t g = nullptr;
     HIPCHK(c, hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal), "capture");
     cpic_status s = CPIC_OK;
+    if (sorted) {
+        const hipError_t e = enqueue_sort(c, tx, ty);
+        if (e != hipSuccess) s = hip_fail(c, e, "particle sort");
+    }
     for (int j = 0; j < k && s == CPIC_OK; j++)
         s = c->prec == CPIC_FP64 ? launch_one<double>(c, parity ^ (j & 1), false)
                                  : launch_one<float>(c, parity ^ (j & 1), false);
     hipError_t e = hipStreamEndCapture(c->st, &g);
     if (s) { if (g) (void)hipGraphDestroy(g); return s; }
     if (e != hipSuccess) return hip_fail(c, e, "end capture");
-    e = hipGraphInstantiate(&c->gexec[parity][k], g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&c->gexec[sorted ? 1 : 0][parity][k], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return hip_fail(c, e, "graph instantiate");
     return CPIC_OK;
@@ -633,17 +655,24 @@ extern "C" cpic_status cpic_evolve(cpic_ctx* c, double tau_target_fm)
     cpic_status ws = watch_prepare(c);
     if (ws) return ws;
     while (left > 0) {
-        cpic_status so = maybe_sort(c);
-        if (so) return so;
+        // a reordering of moving particles is the start of the stretch's graph;
+        // static particles are ordered once, outside the graphs
+        int tx, ty;
+        const bool due = sort_due(c, &tx, &ty), in_graph = due && !c->is_static;
+        if (due && !in_graph) {
+            cpic_status so = maybe_sort(c);
+            if (so) return so;
+        }
         // one graph up to the next reordering point, at most kGraphSteps steps
         // (graphs of each length are captured once per buffer parity)
         const int k = std::min(std::min(left, kGraphSteps), std::max(1, next_sort_point(c, c->n) - c->n));
-        const int parity = c->cur;
-        if (!c->gexec[parity][k]) {
-            cpic_status s = build_graph(c, parity, k);
+        const int parity = c->cur, sg = in_graph ? 1 : 0;
+        if (!c->gexec[sg][parity][k]) {
+            cpic_status s = build_graph(c, parity, k, in_graph, tx, ty);
             if (s) return s;
         }
-        HIPCHK(c, hipGraphLaunch(c->gexec[parity][k], c->st), "graph launch");
+        HIPCHK(c, hipGraphLaunch(c->gexec[sg][parity][k], c->st), "graph launch");
+        if (in_graph) mark_sorted(c, tx, ty);
         host_advance(c, k);
         left -= k;
     }

@@ -62,10 +62,12 @@ struct cpic_ctx {
     int push_table = 0;   // 1: fields from a per-site force table (dense ensembles)
     void* ftab = nullptr; // [48][V] force table (table push, light-like paths)
     bool initialised = false;
-    // graphs: [parity][k] -> executable graph of k steps starting from buffer
-    // `parity` (k = kGraphSteps between reordering points, shorter ones up to
-    // the next reordering point or the end of an evolve)
-    hipGraphExec_t gexec[2][cpic::kGraphSteps + 1] = {};
+    // graphs: [sorted][parity][k] -> executable graph of k steps starting from
+    // buffer `parity` (k = kGraphSteps between reordering points, shorter ones
+    // up to the next reordering point or the end of an evolve); sorted = 1:
+    // the graph starts with the reordering of the records (moving particles
+    // at a reordering point)
+    hipGraphExec_t gexec[2][2][cpic::kGraphSteps + 1] = {};
     // light-like paths (cpic_jets_enable)
     bool jets = false;
     cpic::JetArgs ja{};

@@ -594,19 +594,26 @@ def internal_order(path, reals_per_site=68, part_reals=19):
     return h, cell, pid
 
 
-@pytest.mark.parametrize("n,static,shape", [(3000, False, None), (3000, True, None), (40000, False, None),
-                                            (3000, False, (16, 16))])
-def test_reordering_is_a_stable_sort_by_tile(tmp_path, n, static, shape):
+@pytest.mark.parametrize("n,static,shape,piled", [(3000, False, None, 0), (3000, True, None, 0),
+                                                  (40000, False, None, 0), (3000, False, (16, 16), 0),
+                                                  (3000, True, None, 900)])
+def test_reordering_is_a_stable_sort_by_tile(tmp_path, n, static, shape, piled):
     """Right after the first reordering (from the input order) the records are
     ordered by their tile key (32 x 16 cell tiles for the gather push, the
     fused kernel's tiles for the fused step; row-major inside a tile), records
     of one cell in ascending input index: the permutation of a stable sort.
-    40000 records on 48^2 put 17 on a cell on average."""
-    print(f"case reorder n={n} static={static} shape={shape}", flush=True)
+    40000 records on 48^2 put 17 on a cell on average; `piled` records of the
+    input (every third one) sit on one cell, a run longer than the insertion
+    sort handles."""
+    print(f"case reorder n={n} static={static} shape={shape} piled={piled}", flush=True)
     N, L, n_form = 48, 9.0, 3
     a = oracle.lattice_spacing(L, N)
     st = inputs.random_state(N, 91, eps_link=0.4)
     P = inputs.random_particles(n, N, 92, p_scale=0.6)
+    if piled:
+        sel = np.arange(0, 3 * piled, 3)
+        P[sel, 0], P[sel, 1] = 17.2, 30.4
+        P[sel, 14], P[sel, 15] = 17, 30
     ctx = cp.Context(glasma(N, L, steps=20), particle_params(n, math.inf if static else 0.3 / a, N, L, n_form))
     if shape:
         ctx.set_launch(shape[0], shape[1], 1, 1, 4)

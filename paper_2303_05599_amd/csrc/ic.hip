@@ -64,50 +64,101 @@ __device__ __forceinline__ d2 ad(d2 a, d2 b) { return make_double2(a.x + b.x, a.
 __device__ __forceinline__ d2 sb(d2 a, d2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ d2 mul_i(d2 a, double sg) { return make_double2(-sg * a.y, sg * a.x); }  // (sg i) a
 
-// One complex DFT of length N per block (X[k] = sum_n x[n] exp(sign 2 pi i n k / N)),
-// Stockham autosort stages in LDS.
-__global__ __launch_bounds__(256) void fft_rows_kernel(d2* data, int N, int sign, Radices rad)
+// The radices of the stages packed two bits each (R - 2), first stage lowest:
+// the kernels read them from one register instead of indexing an array.
+static unsigned radix_code(const Radices& R)
 {
-    __shared__ d2 buf[2][kMaxFFT];
-    d2* row = data + (size_t)blockIdx.x * N;
-    for (int i = threadIdx.x; i < N; i += blockDim.x) buf[0][i] = row[i];
-    __syncthreads();
-    int src = 0, Ns = 1;
-    const double sg = sign;
-    for (int stg = 0; stg < rad.n; stg++) {
-        const int R = rad.r[stg], NR = N / R;
-        for (int j = threadIdx.x; j < NR; j += blockDim.x) {
-            const int k = j % Ns;
-            d2 v[4];
-            for (int q = 0; q < R; q++) v[q] = buf[src][j + q * NR];
-            if (Ns > 1)
-                for (int q = 1; q < R; q++) {
-                    double sn, cs;
-                    sincospi(sg * 2.0 * (double)(k * q) / (double)(Ns * R), &sn, &cs);
-                    v[q] = cm(v[q], make_double2(cs, sn));
-                }
-            d2 o[4];
-            if (R == 2) {
-                o[0] = ad(v[0], v[1]);
-                o[1] = sb(v[0], v[1]);
-            } else if (R == 4) {
-                const d2 a = ad(v[0], v[2]), b = sb(v[0], v[2]), c = ad(v[1], v[3]), d = mul_i(sb(v[1], v[3]), sg);
-                o[0] = ad(a, c); o[2] = sb(a, c); o[1] = ad(b, d); o[3] = sb(b, d);
-            } else {  // R == 3
-                const d2 t = ad(v[1], v[2]);
-                const d2 m = make_double2(v[0].x - 0.5 * t.x, v[0].y - 0.5 * t.y);
-                const d2 dd = sb(v[1], v[2]);
-                const d2 d = mul_i(make_double2(0.86602540378443864676 * dd.x, 0.86602540378443864676 * dd.y), sg);
-                o[0] = ad(v[0], t); o[1] = ad(m, d); o[2] = sb(m, d);
-            }
-            const int base = (j / Ns) * Ns * R + k;
-            for (int q = 0; q < R; q++) buf[src ^ 1][base + q * Ns] = o[q];
+    unsigned c = 0;
+    for (int s = R.n - 1; s >= 0; s--) c = (c << 2) | (unsigned)(R.r[s] - 2);
+    return c;
+}
+__device__ __forceinline__ int stage_radix(unsigned code, int stg) { return (int)((code >> (2 * stg)) & 3u) + 2; }
+
+// The twiddle factors of every stage (R, Ns) of the Stockham FFT below,
+// tw[(Ns - 1) + k (R - 1) + q - 1] = exp(sign 2 pi i k q / (Ns R)) for k < Ns
+// and 1 <= q < R.  The stages' entries follow one another without gaps, since
+// the Ns of a stage is the product of the radices before it: N - 1 in all.
+// Made once per initial condition (one block), so that the butterflies read
+// their factors instead of evaluating a sine and a cosine each.
+__global__ void twiddle_kernel(d2* tw, int nstages, unsigned rcode, int sign)
+{
+    int Ns = 1;
+    for (int stg = 0; stg < nstages; stg++) {
+        const int R = stage_radix(rcode, stg);
+        for (int t = threadIdx.x; t < Ns * (R - 1); t += blockDim.x) {
+            const int k = t / (R - 1), q = t % (R - 1) + 1;
+            double sn, cs;
+            sincospi((double)sign * 2.0 * (double)(k * q) / (double)(Ns * R), &sn, &cs);
+            tw[Ns - 1 + t] = make_double2(cs, sn);
         }
-        __syncthreads();
-        src ^= 1;
         Ns *= R;
     }
-    for (int i = threadIdx.x; i < N; i += blockDim.x) row[i] = buf[src][i];
+}
+
+// One radix-R stage of the Stockham FFT: butterfly j < N / R takes the inputs
+// j + q N / R, multiplies them by the twiddles of its k = j mod Ns, and writes
+// the R outputs to (j - k) R + k + q Ns.
+template <int R>
+__device__ __forceinline__ void fft_stage(const d2* __restrict__ in, d2* __restrict__ out, int N, int Ns, double sg,
+                                          const d2* __restrict__ tw)
+{
+    const int NR = N / R;
+    for (int j = threadIdx.x; j < NR; j += blockDim.x) {
+        const int k = (int)((unsigned)j % (unsigned)Ns);
+        d2 v[R];
+#pragma unroll
+        for (int q = 0; q < R; q++) v[q] = in[j + q * NR];
+        if (Ns > 1) {
+            const d2* w = tw + (Ns - 1) + k * (R - 1) - 1;
+#pragma unroll
+            for (int q = 1; q < R; q++) v[q] = cm(v[q], w[q]);
+        }
+        d2 o[R];
+        if constexpr (R == 2) {
+            o[0] = ad(v[0], v[1]);
+            o[1] = sb(v[0], v[1]);
+        } else if constexpr (R == 4) {
+            const d2 a = ad(v[0], v[2]), b = sb(v[0], v[2]), c = ad(v[1], v[3]), d = mul_i(sb(v[1], v[3]), sg);
+            o[0] = ad(a, c); o[2] = sb(a, c); o[1] = ad(b, d); o[3] = sb(b, d);
+        } else {
+            static_assert(R == 3, "radix 2, 3 or 4");
+            const d2 t = ad(v[1], v[2]);
+            const d2 m = make_double2(v[0].x - 0.5 * t.x, v[0].y - 0.5 * t.y);
+            const d2 dd = sb(v[1], v[2]);
+            const d2 d = mul_i(make_double2(0.86602540378443864676 * dd.x, 0.86602540378443864676 * dd.y), sg);
+            o[0] = ad(v[0], t); o[1] = ad(m, d); o[2] = sb(m, d);
+        }
+        const int base = (j - k) * R + k;
+#pragma unroll
+        for (int q = 0; q < R; q++) out[base + q * Ns] = o[q];
+    }
+}
+
+// One complex DFT of length N per block (X[k] = sum_n x[n] exp(sign 2 pi i n k / N)),
+// Stockham autosort stages in LDS (2 N complex values, dynamic), twiddles from
+// the table of twiddle_kernel for this sign.
+__global__ __launch_bounds__(256) void fft_rows_kernel(d2* data, int N, int sign, int nstages, unsigned rcode,
+                                                       const d2* __restrict__ tw)
+{
+    extern __shared__ d2 lds[];
+    d2 *a = lds, *b = lds + N;
+    d2* row = data + (size_t)blockIdx.x * N;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) a[i] = row[i];
+    __syncthreads();
+    int Ns = 1;
+    const double sg = sign;
+    for (int stg = 0; stg < nstages; stg++) {
+        const int R = stage_radix(rcode, stg);
+        if (R == 4) fft_stage<4>(a, b, N, Ns, sg, tw);
+        else if (R == 2) fft_stage<2>(a, b, N, Ns, sg, tw);
+        else fft_stage<3>(a, b, N, Ns, sg, tw);
+        __syncthreads();
+        d2* t = a;
+        a = b;
+        b = t;
+        Ns *= R;
+    }
+    for (int i = threadIdx.x; i < N; i += blockDim.x) row[i] = a[i];
 }
 
 // out[f][c][r] = in[f][r][c]
@@ -231,25 +282,39 @@ __global__ void pure_gauge_kernel(const double* __restrict__ Vdag, int N, double
 }
 
 // rows 1, 2 by Gram-Schmidt, row 3 = conj(r1 x r2)
-__device__ int solve8(double (&J)[8][8], double (&b)[8], double (&x)[8])
+// Gaussian elimination with partial pivoting, unrolled so that J stays in
+// registers: the pivot (the first largest |J[r][c]|, r >= c) is brought up by
+// conditional swaps instead of an indexed row exchange.
+__device__ __forceinline__ int solve8(double (&J)[8][8], double (&b)[8], double (&x)[8])
 {
+#pragma unroll
     for (int c = 0; c < 8; c++) {
-        int p = c;
-        for (int r = c + 1; r < 8; r++)
-            if (fabs(J[r][c]) > fabs(J[p][c])) p = r;
-        if (J[p][c] == 0.0) return -1;
-        if (p != c) {
-            for (int k = 0; k < 8; k++) { const double t = J[c][k]; J[c][k] = J[p][k]; J[p][k] = t; }
-            const double t = b[c]; b[c] = b[p]; b[p] = t;
+#pragma unroll
+        for (int r = c + 1; r < 8; r++) {
+            const bool sw = fabs(J[r][c]) > fabs(J[c][c]);
+#pragma unroll
+            for (int k = c; k < 8; k++) {
+                const double t = J[c][k];
+                J[c][k] = sw ? J[r][k] : t;
+                J[r][k] = sw ? t : J[r][k];
+            }
+            const double t = b[c];
+            b[c] = sw ? b[r] : t;
+            b[r] = sw ? t : b[r];
         }
+        if (J[c][c] == 0.0) return -1;
+#pragma unroll
         for (int r = c + 1; r < 8; r++) {
             const double f = J[r][c] / J[c][c];
+#pragma unroll
             for (int k = c; k < 8; k++) J[r][k] -= f * J[c][k];
             b[r] -= f * b[c];
         }
     }
+#pragma unroll
     for (int r = 7; r >= 0; r--) {
         double acc = b[r];
+#pragma unroll
         for (int k = r + 1; k < 8; k++) acc -= J[r][k] * x[k];
         x[r] = acc / J[r][r];
     }
@@ -259,7 +324,7 @@ __device__ int solve8(double (&J)[8][8], double (&b)[8], double (&x)[8])
 // tau = 0 links: Newton on Proj[(U^A + U^B)(1 + U^+)] = 0 in the coordinates of
 // U = exp(iX) U_0, Jacobian columns Proj[-i W U^+ T^b] (W = U^A + U^B), start at
 // the row-projected W; stop at |F|_inf < tol or when the step is at rounding level
-__global__ void links_kernel(const double* __restrict__ UA, const double* __restrict__ UB, int V, double tol,
+__global__ __launch_bounds__(128) void links_kernel(const double* __restrict__ UA, const double* __restrict__ UB, int V, double tol,
                              int maxit, double* U, int* fails)
 {
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
@@ -410,13 +475,25 @@ __global__ void convert_kernel(const double* __restrict__ s, float* __restrict__
         if (e_ != hipSuccess) return e_;     \
     } while (0)
 
+// the forward and inverse twiddle tables (2 N entries, freed by the caller)
+static hipError_t make_twiddles(d2** tw, int N, const Radices& R, hipStream_t st)
+{
+    CK(hipMalloc(tw, sizeof(d2) * 2 * N));
+    hipLaunchKernelGGL(twiddle_kernel, dim3(1), dim3(256), 0, st, *tw, R.n, radix_code(R), -1);
+    hipLaunchKernelGGL(twiddle_kernel, dim3(1), dim3(256), 0, st, *tw + N, R.n, radix_code(R), +1);
+    return hipGetLastError();
+}
+
 // one nucleus: Wilson line V^+ of its sheets (SU(3): [18][V] matrices; SU(2):
 // [4][V] quaternions)
+// tw: the twiddle tables of the forward (first N entries) and inverse transforms
 static hipError_t nucleus_wilson(const ICArgs& a, int nucleus, d2* buf, d2* tmp, int chunk, double* Vdag,
-                                 const Radices& R, hipStream_t st, int nc = 3)
+                                 const Radices& R, const d2* tw, hipStream_t st, int nc = 3)
 {
     const int N = a.N, V = N * N;
     const int pairs = nc == 2 ? 2 : 4;
+    const size_t lds = (size_t)2 * N * sizeof(d2);
+    const unsigned rc = radix_code(R);
     const double sigma = a.g2mua / sqrt((double)a.n_sheets);
     if (nc == 2) hipLaunchKernelGGL(identity2_kernel, dim3((V + 255) / 256), dim3(256), 0, st, Vdag, V);
     else hipLaunchKernelGGL(identity_kernel, dim3((V + 255) / 256), dim3(256), 0, st, Vdag, V);
@@ -425,15 +502,15 @@ static hipError_t nucleus_wilson(const ICArgs& a, int nucleus, d2* buf, d2* tmp,
         const int nf = pairs * nsh;
         hipLaunchKernelGGL(charges_kernel, dim3((V + 255) / 256, nsh), dim3(256), 0, st, buf, V, a.seed, nucleus, s0,
                            sigma, pairs);
-        hipLaunchKernelGGL(fft_rows_kernel, dim3(nf * N), dim3(256), 0, st, buf, N, -1, R);
+        hipLaunchKernelGGL(fft_rows_kernel, dim3(nf * N), dim3(256), lds, st, buf, N, -1, R.n, rc, tw);
         hipLaunchKernelGGL(transpose_kernel, dim3((N + 31) / 32, (N + 31) / 32, nf), dim3(32, 8), 0, st, buf, tmp, N);
-        hipLaunchKernelGGL(fft_rows_kernel, dim3(nf * N), dim3(256), 0, st, tmp, N, -1, R);
+        hipLaunchKernelGGL(fft_rows_kernel, dim3(nf * N), dim3(256), lds, st, tmp, N, -1, R.n, rc, tw);
         const size_t tot = (size_t)V * nf;
         hipLaunchKernelGGL(poisson_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, tmp, N, nf, a.mhat,
                            a.uvhat, 1.0 / ((double)N * N));
-        hipLaunchKernelGGL(fft_rows_kernel, dim3(nf * N), dim3(256), 0, st, tmp, N, +1, R);
+        hipLaunchKernelGGL(fft_rows_kernel, dim3(nf * N), dim3(256), lds, st, tmp, N, +1, R.n, rc, tw + N);
         hipLaunchKernelGGL(transpose_kernel, dim3((N + 31) / 32, (N + 31) / 32, nf), dim3(32, 8), 0, st, tmp, buf, N);
-        hipLaunchKernelGGL(fft_rows_kernel, dim3(nf * N), dim3(256), 0, st, buf, N, +1, R);
+        hipLaunchKernelGGL(fft_rows_kernel, dim3(nf * N), dim3(256), lds, st, buf, N, +1, R.n, rc, tw + N);
         if (nc == 2) hipLaunchKernelGGL(wilson2_kernel, dim3((V + 255) / 256), dim3(256), 0, st, buf, nsh, V, Vdag);
         else hipLaunchKernelGGL(wilson_kernel, dim3((V + 255) / 256), dim3(256), 0, st, buf, nsh, V, Vdag);
         CK(hipGetLastError());
@@ -450,16 +527,18 @@ hipError_t ic_glasma(const ICArgs& a, Fields<double> out, int* d_fails, hipStrea
     int chunk = (int)((size_t)256 << 20) / (int)(per_sheet > 0 ? per_sheet : 1);
     chunk = chunk < 1 ? 1 : (chunk > a.n_sheets ? a.n_sheets : chunk);
     d2 *buf = nullptr, *tmp = nullptr;
+    d2* tw = nullptr;
     double *Vdag = nullptr, *UA = nullptr, *UB = nullptr;
-    hipError_t e = hipMalloc(&buf, per_sheet * chunk);
+    hipError_t e = make_twiddles(&tw, N, R, st);
+    if (e == hipSuccess) e = hipMalloc(&buf, per_sheet * chunk);
     if (e == hipSuccess) e = hipMalloc(&tmp, per_sheet * chunk);
     if (e == hipSuccess) e = hipMalloc(&Vdag, sizeof(double) * 18 * V);
     if (e == hipSuccess) e = hipMalloc(&UA, sizeof(double) * 36 * V);
     if (e == hipSuccess) e = hipMalloc(&UB, sizeof(double) * 36 * V);
-    if (e == hipSuccess) e = nucleus_wilson(a, 0, buf, tmp, chunk, Vdag, R, st);
+    if (e == hipSuccess) e = nucleus_wilson(a, 0, buf, tmp, chunk, Vdag, R, tw, st);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(pure_gauge_kernel, dim3((V + 255) / 256), dim3(256), 0, st, Vdag, N, UA);
-        e = nucleus_wilson(a, 1, buf, tmp, chunk, Vdag, R, st);
+        e = nucleus_wilson(a, 1, buf, tmp, chunk, Vdag, R, tw, st);
     }
     if (e == hipSuccess) {
         hipLaunchKernelGGL(pure_gauge_kernel, dim3((V + 255) / 256), dim3(256), 0, st, Vdag, N, UB);
@@ -473,6 +552,7 @@ hipError_t ic_glasma(const ICArgs& a, Fields<double> out, int* d_fails, hipStrea
     hipError_t e2 = hipStreamSynchronize(st);
     if (e == hipSuccess) e = e2;
     (void)hipFree(buf); (void)hipFree(tmp); (void)hipFree(Vdag); (void)hipFree(UA); (void)hipFree(UB);
+    (void)hipFree(tw);
     return e;
 }
 
@@ -534,16 +614,18 @@ hipError_t ic_glasma2(const ICArgs& a, Fields2<double> out, hipStream_t st)
     int chunk = (int)((size_t)256 << 20) / (int)(per_sheet > 0 ? per_sheet : 1);
     chunk = chunk < 1 ? 1 : (chunk > a.n_sheets ? a.n_sheets : chunk);
     d2 *buf = nullptr, *tmp = nullptr;
+    d2* tw = nullptr;
     double *Vdag = nullptr, *UA = nullptr, *UB = nullptr;
-    hipError_t e = hipMalloc(&buf, per_sheet * chunk);
+    hipError_t e = make_twiddles(&tw, N, R, st);
+    if (e == hipSuccess) e = hipMalloc(&buf, per_sheet * chunk);
     if (e == hipSuccess) e = hipMalloc(&tmp, per_sheet * chunk);
     if (e == hipSuccess) e = hipMalloc(&Vdag, sizeof(double) * 4 * V);
     if (e == hipSuccess) e = hipMalloc(&UA, sizeof(double) * 8 * V);
     if (e == hipSuccess) e = hipMalloc(&UB, sizeof(double) * 8 * V);
-    if (e == hipSuccess) e = nucleus_wilson(a, 0, buf, tmp, chunk, Vdag, R, st, 2);
+    if (e == hipSuccess) e = nucleus_wilson(a, 0, buf, tmp, chunk, Vdag, R, tw, st, 2);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(pure_gauge2_kernel, dim3((V + 255) / 256), dim3(256), 0, st, Vdag, N, UA);
-        e = nucleus_wilson(a, 1, buf, tmp, chunk, Vdag, R, st, 2);
+        e = nucleus_wilson(a, 1, buf, tmp, chunk, Vdag, R, tw, st, 2);
     }
     if (e == hipSuccess) {
         hipLaunchKernelGGL(pure_gauge2_kernel, dim3((V + 255) / 256), dim3(256), 0, st, Vdag, N, UB);
@@ -556,6 +638,7 @@ hipError_t ic_glasma2(const ICArgs& a, Fields2<double> out, hipStream_t st)
     hipError_t e2 = hipStreamSynchronize(st);
     if (e == hipSuccess) e = e2;
     (void)hipFree(buf); (void)hipFree(tmp); (void)hipFree(Vdag); (void)hipFree(UA); (void)hipFree(UB);
+    (void)hipFree(tw);
     return e;
 }
 

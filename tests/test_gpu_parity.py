@@ -87,9 +87,10 @@ def test_field_leapfrog_fp64_random_state(N, n0, launch):
     compare_fields(got, ref)
 
 
-@pytest.mark.parametrize("N,ns,uv", [(32, 1, 10.0), (48, 3, 4.0), (64, 2, 0.0)])
+@pytest.mark.parametrize("N,ns,uv", [(32, 1, 10.0), (48, 3, 4.0), (64, 2, 0.0), (96, 1, 10.0)])
 def test_initial_condition_parity(N, ns, uv):
-    """Full MV chain: charges, FFT Poisson (radix 2/3/4), Wilson lines, Newton links, pi(0)."""
+    """Full MV chain: charges, FFT Poisson (radix 2/3/4; 96 = 4 4 2 3 mixes all three), Wilson lines,
+    Newton links, pi(0)."""
     print(f"case IC N={N} sheets={ns} uv={uv}", flush=True)
     L = 6.0 * N / 32
     ctx = cp.Context(glasma(N, L, n_sheets=ns, uv_GeV=uv, seed=7))

@@ -102,6 +102,22 @@ def test_initial_condition_parity(N, ns, uv):
     assert np.max(np.abs(got["E"])) == 0 and np.max(np.abs(got["phi"])) == 0
 
 
+def test_initial_condition_parity_in_sheet_chunks():
+    """The sheets of a nucleus go through the FFT Poisson solve in chunks of
+    at most 256 MiB of charge planes (113 sheets at 192^2): 120 sheets take
+    a full chunk and a ragged one of 7, each Wilson line the product over
+    both.  L = 6 fm keeps the links weak enough for the Newton solve."""
+    N, ns = 192, 120
+    print(f"case IC chunks N={N} sheets={ns}", flush=True)
+    ctx = cp.Context(glasma(N, 6.0, n_sheets=ns, uv_GeV=10.0, seed=7))
+    ctx.init_mv()
+    got = ctx.state()
+    ref = oracle.mv_initial_condition(N, 6.0, 2.0, 0.2, 10.0, ns, 7)
+    assert rel_err(got["U"], ref["U"]) < 1e-12
+    assert rel_err(got["pi"], ref["pi"]) < 1e-12
+    ctx.close()
+
+
 def particle_params(n, mass, N, L, n_form, seed=2, pt=(0.0, 0.0), rep=0):
     a_fm = L / N
     return dict(n=n, mass_GeV=mass, pT_min_GeV=pt[0], pT_max_GeV=pt[1], azimuth_uniform=1,

@@ -70,6 +70,21 @@ def test_su2_initial_condition(N, uv):
     ctx.close()
 
 
+def test_su2_initial_condition_in_sheet_chunks():
+    """230 sheets at 192^2: a full chunk of 227 charge planes and a ragged one
+    of 3 (L = 6 fm)."""
+    N, ns = 192, 230
+    print(f"case SU(2) IC chunks N={N} sheets={ns}", flush=True)
+    g = event(N, 10, L=6.0, n_sheets=ns)
+    ctx = cp.Context(g, None)
+    ctx.init_mv()
+    got = state(ctx)
+    ref = su2.mv_initial_condition(N, 6.0, 2.0, 0.2, 10.0, ns, 61)
+    for k in ("U", "pi"):
+        assert rel_err(got[k], ref[k]) <= 1e-12, k
+    ctx.close()
+
+
 def test_su2_leapfrog_from_mv_event():
     N, steps = 36, 50
     g = event(N, steps)

@@ -267,12 +267,14 @@ __device__ __forceinline__ int push_step(int* d_step, int blk)
     return n;
 }
 
-// At least three waves per SIMD (at most 168 VGPRs) for blocks of 256
-// threads, four (128 VGPRs: two blocks per CU) for the 512-thread blocks of
-// eight waves per group; the logarithm variant keeps the compiler's choice
-// (it would spill).
+// At least two waves per SIMD for blocks of 256 threads (FP64: 176 VGPRs,
+// two blocks per CU), four (128 VGPRs: two blocks per CU) for the 512-thread
+// blocks of eight waves per group; the logarithm variant keeps the compiler's
+// choice (it would spill).  A third block per CU (168 VGPRs, 12 of them
+// spilled) puts more lines in flight than the L2 keeps for the wavefronts that
+// share them: the FP64 step was 2.4 % slower.
 template <typename T, int TPP, bool LOGQ = false>
-__global__ __launch_bounds__(push_block_threads(TPP), LOGQ ? 1 : (TPP == 8 ? 4 : 3)) void push_kernel(
+__global__ __launch_bounds__(push_block_threads(TPP), LOGQ ? 1 : (TPP == 8 ? 4 : 2)) void push_kernel(
     Fields<T> Af, Fields<T> Bf, const T* gpl, Parts<T> P, PushArgs a, int* d_step, double* partials, int* err)
 {
     const int nblocks = (a.np + kPushPPB<TPP> - 1) / kPushPPB<TPP>;

@@ -269,12 +269,13 @@ __device__ __forceinline__ int push_step(int* d_step, int blk)
 
 // At least two waves per SIMD for blocks of 256 threads (FP64: 176 VGPRs,
 // two blocks per CU), four (128 VGPRs: two blocks per CU) for the 512-thread
-// blocks of eight waves per group; the logarithm variant keeps the compiler's
-// choice (it would spill).  A third block per CU (168 VGPRs, 12 of them
-// spilled) puts more lines in flight than the L2 keeps for the wavefronts that
-// share them: the FP64 step was 2.4 % slower.
+// blocks of eight waves per group.  A third block per CU (168 VGPRs, 12 of
+// them spilled) puts more lines in flight than the L2 keeps for the
+// wavefronts that share them: the FP64 step was 2.4 % slower.  The logarithm
+// variant also takes two (FP64: 254 VGPRs, 8 spilled): with one wave per SIMD
+// and no spills its FP64 step took 0.180 ms against 0.132 ms.
 template <typename T, int TPP, bool LOGQ = false>
-__global__ __launch_bounds__(push_block_threads(TPP), LOGQ ? 1 : (TPP == 8 ? 4 : 2)) void push_kernel(
+__global__ __launch_bounds__(push_block_threads(TPP), (TPP == 8 && !LOGQ) ? 4 : 2) void push_kernel(
     Fields<T> Af, Fields<T> Bf, const T* gpl, Parts<T> P, PushArgs a, int* d_step, double* partials, int* err)
 {
     const int nblocks = (a.np + kPushPPB<TPP> - 1) / kPushPPB<TPP>;

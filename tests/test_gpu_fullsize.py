@@ -23,11 +23,15 @@ library's next state must agree with it: every site and every particle.
     double-precision particle count (14,128,181, records just below 2 GiB),
     every site and a random sample of 4096 particles (the oracle pushes
     particles independently of each other).
+  * opt-in (CPIC_FULL_LENGTH=1, about four minutes of oracle time): the
+    headline event over all its 1024 steps to tau = 1.5 fm/c against the
+    oracle from the same initial state, checked every 128 steps.
 The FP64 headline event and the jets workload run with non-temporal stores
 of the new state (their working sets exceed the last-level cache),
 the FP32 headline event without.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -247,4 +251,45 @@ def test_max_sizes_one_step():
         assert rel_err(st1[k], run.st[k]) <= 1e-11, (k, rel_err(st1[k], run.st[k]))
     assert np.array_equal(P1[idx, 14:16], run.P[:, 14:16])
     assert rel_err(P1[idx], run.P) <= 1e-11
+    ctx.close()
+
+
+@pytest.mark.skipif(os.environ.get("CPIC_FULL_LENGTH") != "1",
+                    reason="about four minutes of oracle time; set CPIC_FULL_LENGTH=1")
+def test_headline_full_length():
+    """The headline event (FP64, the bench's configuration without the tuner)
+    from its initial condition to tau = 1.5 fm/c, 1024 steps, in the library
+    and in the oracle.  Both take the same steps in a different rounding
+    order, and the leapfrog amplifies those differences, about twofold every
+    128 steps (measured at the end: U 1.2e-12, phi 4.3e-10, E and pi 2.2e-10,
+    records 7.9e-12,
+    the broadening sums 9.7e-11).  The bars are five times those ends; every
+    particle's cell stays exact throughout."""
+    p = dict(n=100_000, mass_GeV=1.27, pT_min_GeV=0.0, pT_max_GeV=0.0, azimuth_uniform=1, tau_form_fm=0.1, rep=0,
+             seed=4)
+    a = oracle.lattice_spacing(L, N)
+    ctx = cp.Context(glasma(cp.FP64), p)
+    ctx.init_mv()
+    st0, P0 = ctx.state(), ctx.get_state(cp.STATE_PARTICLES)
+    n_form = math.ceil(p["tau_form_fm"] / (DT * L / N) - 1e-9)
+    n_max = int(round(1.5 / (DT * L / N)))
+    run = oracle.Run(N, DT, st0, P0, mhat=p["mass_GeV"] * a, n_form=n_form, n0=0)
+    bars = {"U": 6e-12, "phi": 2.2e-9, "E": 1.1e-9, "pi": 1.1e-9}
+    while ctx.n < n_max:
+        k = min(128, n_max - ctx.n)
+        ctx.step(k)
+        for _ in range(k):
+            run.step()
+        assert run.errors == 0
+        st, P = ctx.state(), ctx.get_state(cp.STATE_PARTICLES)
+        errs = {f: rel_err(st[f], run.st[f]) for f in bars}
+        sums = run.observe() / (p["n"] * a * a)
+        obs = ctx.observables()[-1]
+        ob = max(abs(obs[1 + c] / sums[c] - 1) for c in range(2))
+        print(f"case full length n={ctx.n}: {errs} records {rel_err(P, run.P):.2e} sums {ob:.2e}", flush=True)
+        assert np.array_equal(P[:, 14:16], run.P[:, 14:16])
+        for f, bar in bars.items():
+            assert errs[f] <= bar, (ctx.n, f, errs[f])
+        assert rel_err(P, run.P) <= 4e-11
+        assert ob <= 5e-10
     ctx.close()

@@ -158,116 +158,152 @@ hipError_t launch_su2_field(const Fields2<T>& in, const Fields2<T>& out, int N, 
 }
 
 // ------------------------------------------------------------------ particle push
-// The SU(3) push for N_c = 2, one thread per particle: colour rotation for
-// the move n-1 -> n with the crossed links and the rapidity Wilson line, the
-// fields of Sec. III.B at the nearest grid point, one Euler step; on
-// recording steps each wavefront writes its four double-precision sums.
+// The SU(3) push for N_c = 2: colour rotation for the move n-1 -> n with the
+// crossed links and the rapidity Wilson line, the fields of Sec. III.B at the
+// nearest grid point, one Euler step; on recording steps each group of 64
+// writes its four double-precision sums.  Four wavefronts share a group of 64
+// particles: the owner (wave 0) rotates Q while three helpers evaluate the six
+// field vectors, two each, into LDS (wave 1: E_x and B_y, both through the x
+// links; wave 2: E_y and B_x; wave 3: E_eta and B_eta); after one barrier the
+// owner contracts them with Q and takes the step.  One thread per particle
+// would leave about one and a half wavefronts per SIMD at 1e5 particles, too
+// few to cover the chains of dependent gathers.
 template <typename T>
 __global__ __launch_bounds__(256) void su2_push_kernel(Fields2<T> Af, Fields2<T> Bf, Parts<T> P, PushArgs a,
                                                        int* d_step, double* partials, int* err)
 {
     const int np = a.np, N = a.N, V = N * N;
-    const int nb = (np + 255) / 256;
+    const int nb = (np + 63) / 64;
     const int blk = remap_block(nb);
     if (blk >= nb) return;
     const int n = d_step[1];
     if (blk == 0 && threadIdx.x == 0) d_step[0] = n + 1;
     if (n < a.sc.n_form || n >= a.sc.n_max) return;  // uniform over the grid
-    const int p = blk * 256 + (int)threadIdx.x;
+    __shared__ T shF[3][6][64];
+    const int lane = (int)threadIdx.x & 63, role = (int)threadIdx.x >> 6;
+    const int p = blk * 64 + lane;
     const bool live = p < np;
     const int q = live ? p : 0;
     auto R = [&](int col) -> T& { return P.r[(size_t)col * np + q]; };
     const L2<T> L{Af.U, V};
     const T dt = T(a.sc.dt), t = T(n * a.sc.dt);
     const int record_slot = is_record_step(a.sc, n) ? record_slot_of(a.sc, n) : -1;
+    // the nearest grid point (every wave)
+    int nx, ny;
+    T x = 0, y = 0;
+    if (a.is_static) {
+        nx = P.cell[q];
+        ny = P.cell[np + q];
+    } else {
+        x = R(PX_);
+        y = R(PY_);
+        nx = (int)floor(x + T(0.5));
+        ny = (int)floor(y + T(0.5));
+        nx = nx >= N ? nx - N : nx;
+        ny = ny >= N ? ny - N : ny;
+    }
+    const Nb2 c = nbrs(nx, ny, N);
+    v3<T> Q = {{0, 0, 0}};
+    if (role == 0) {
+        if (live) {
+            Q = {{R(PQ0), R(PQ0 + 1), R(PQ0 + 2)}};
+            if (!a.is_static && n > a.sc.n_form) {
+                int cx = P.cell[q], cy = P.cell[np + q];
+                const int d[2] = {nx - cx, ny - cy};
+#pragma unroll
+                for (int ax = 0; ax < 2; ax++) {
+                    int dd = d[ax];
+                    if (dd > N / 2) dd -= N;
+                    if (dd < -N / 2) dd += N;
+                    if (dd == 1) {
+                        Q = qtransport(L.link(ax, cy * N + cx), Q, true);                 // U^+ Q U
+                    } else if (dd == -1) {
+                        const int cb = ax == 0 ? cy * N + wrapi(cx - 1, N) : wrapi(cy - 1, N) * N + cx;
+                        Q = qtransport(L.link(ax, cb), Q);                                // U Q U^+
+                    } else if (dd != 0) {
+                        atomicAdd(err, 1);
+                    }
+                    if (ax == 0) cx = nx; else cy = ny;
+                }
+                const T deta = R(PDETA);
+                if (deta != T(0)) Q = qtransport(qexpi(ld3(Af.phi, ny * N + nx, V), deta), Q, true);
+            }
+        }
+    } else {
+        // helper: field vectors fa (electric) and fb (magnetic) of its direction
+        v3<T> fa = {{0, 0, 0}}, fb = {{0, 0, 0}};
+        if (live) {
+            const bool mag = !a.is_static;
+            if (role < 3) {
+                const int i = role - 1;
+                if (n > 0) {
+                    // E_i = (1/4t) [S_i(c) + U_i(c-i)^+ S_i(c-i) U_i(c-i)], S_i = E_i(n-1/2) + E_i(n+1/2)
+                    const T q4t = T(1) / (T(4) * t);
+                    const int back = i == 0 ? c.xm : c.ym;
+                    const size_t o = (size_t)i * 3 * V;
+                    v3<T> here = ld3(Af.E + o, c.s, V), bk = ld3(Af.E + o, back, V);
+                    const v3<T> hn = ld3(Bf.E + o, c.s, V), bn = ld3(Bf.E + o, back, V);
+#pragma unroll
+                    for (int a2 = 0; a2 < 3; a2++) {
+                        here.v[a2] += hn.v[a2];
+                        bk.v[a2] += bn.v[a2];
+                    }
+                    const v3<T> tb = qtransport(L.link(i, back), bk, true);
+#pragma unroll
+                    for (int a2 = 0; a2 < 3; a2++) fa.v[a2] = q4t * (here.v[a2] + tb.v[a2]);
+                    if (mag) {
+                        // B_y = +(1/2t) D_x (wave 1), B_x = -(1/2t) D_y (wave 2), D_i = phi->_i - phi<-_i
+                        const T h = (i == 0 ? T(1) : T(-1)) / (T(2) * t);
+                        const v3<T> fw = qtransport(L.link(i, c.s), ld3(Af.phi, i == 0 ? c.xp : c.yp, V));
+                        const v3<T> bw = qtransport(L.link(i, back), ld3(Af.phi, back, V), true);
+#pragma unroll
+                        for (int a2 = 0; a2 < 3; a2++) fb.v[a2] = h * (fw.v[a2] - bw.v[a2]);
+                    }
+                }
+            } else {
+                if (n > 0) {
+                    const v3<T> po = ld3(Af.pi, c.s, V), pn = ld3(Bf.pi, c.s, V);
+#pragma unroll
+                    for (int a2 = 0; a2 < 3; a2++) fa.v[a2] = T(0.5) * (po.v[a2] + pn.v[a2]);
+                } else {
+                    fa = ld3(Bf.pi, c.s, V);
+                }
+                if (mag) {
+                    // B_eta = -(1/4) Proj[U_12 + U_{2,-1} + U_{-1,-2} + U_{-2,1}] at c
+                    const q4<T> u1 = L.link(0, c.s), u2 = L.link(1, c.s);
+                    const q4<T> c12 = qmul(qmul(u1, L.link(1, c.xp)), qmul(qadj(L.link(0, c.yp)), qadj(u2)));
+                    const q4<T> c2m1 =
+                        qmul(qmul(u2, qadj(L.link(0, c.xmyp))), qmul(qadj(L.link(1, c.xm)), L.link(0, c.xm)));
+                    const q4<T> cm1m2 = qmul(qmul(qadj(L.link(0, c.xm)), qadj(L.link(1, c.xmym))),
+                                             qmul(L.link(0, c.xmym), L.link(1, c.ym)));
+                    const q4<T> cm21 =
+                        qmul(qmul(qadj(L.link(1, c.ym)), L.link(0, c.ym)), qmul(L.link(1, c.xpym), qadj(u1)));
+                    const v3<T> pb = qproj(qadd(qadd(c12, c2m1), qadd(cm1m2, cm21)));
+#pragma unroll
+                    for (int a2 = 0; a2 < 3; a2++) fb.v[a2] = T(-0.25) * pb.v[a2];
+                }
+            }
+        }
+#pragma unroll
+        for (int a2 = 0; a2 < 3; a2++) {
+            shF[role - 1][a2][lane] = fa.v[a2];
+            shF[role - 1][3 + a2][lane] = fb.v[a2];
+        }
+    }
+    __syncthreads();
+    if (role != 0) return;
     double obs[4] = {0, 0, 0, 0};
     if (live) {
-        int nx, ny;
-        T x = 0, y = 0;
-        if (a.is_static) {
-            nx = P.cell[q];
-            ny = P.cell[np + q];
-        } else {
-            x = R(PX_);
-            y = R(PY_);
-            nx = (int)floor(x + T(0.5));
-            ny = (int)floor(y + T(0.5));
-            nx = nx >= N ? nx - N : nx;
-            ny = ny >= N ? ny - N : ny;
-        }
-        v3<T> Q = {{R(PQ0), R(PQ0 + 1), R(PQ0 + 2)}};
-        if (!a.is_static && n > a.sc.n_form) {
-            int cx = P.cell[q], cy = P.cell[np + q];
-            const int d[2] = {nx - cx, ny - cy};
-#pragma unroll
-            for (int ax = 0; ax < 2; ax++) {
-                int dd = d[ax];
-                if (dd > N / 2) dd -= N;
-                if (dd < -N / 2) dd += N;
-                if (dd == 1) {
-                    Q = qtransport(L.link(ax, cy * N + cx), Q, true);                 // U^+ Q U
-                } else if (dd == -1) {
-                    const int cb = ax == 0 ? cy * N + wrapi(cx - 1, N) : wrapi(cy - 1, N) * N + cx;
-                    Q = qtransport(L.link(ax, cb), Q);                                // U Q U^+
-                } else if (dd != 0) {
-                    atomicAdd(err, 1);
-                }
-                if (ax == 0) cx = nx; else cy = ny;
-            }
-            const T deta = R(PDETA);
-            if (deta != T(0)) Q = qtransport(qexpi(ld3(Af.phi, ny * N + nx, V), deta), Q, true);
-        }
-        // fields at the nearest grid point c
-        const Nb2 c = nbrs(nx, ny, N);
+        // f: E_x, E_y, E_eta, B_x, B_y, B_eta
         v3<T> f[6];
-        for (int k = 0; k < 6; k++) f[k] = {{0, 0, 0}};
-        if (n > 0) {
-            const T q4t = T(1) / (T(4) * t);
-            const int back[2] = {c.xm, c.ym};
 #pragma unroll
-            for (int i = 0; i < 2; i++) {
-                const size_t o = (size_t)i * 3 * V;
-                v3<T> here = ld3(Af.E + o, c.s, V), b = ld3(Af.E + o, back[i], V);
-                const v3<T> hn = ld3(Bf.E + o, c.s, V), bn = ld3(Bf.E + o, back[i], V);
-#pragma unroll
-                for (int a2 = 0; a2 < 3; a2++) {
-                    here.v[a2] += hn.v[a2];
-                    b.v[a2] += bn.v[a2];
-                }
-                const v3<T> tb = qtransport(L.link(i, back[i]), b, true);
-#pragma unroll
-                for (int a2 = 0; a2 < 3; a2++) f[i].v[a2] = q4t * (here.v[a2] + tb.v[a2]);
-            }
-            const v3<T> po = ld3(Af.pi, c.s, V), pn = ld3(Bf.pi, c.s, V);
-#pragma unroll
-            for (int a2 = 0; a2 < 3; a2++) f[2].v[a2] = T(0.5) * (po.v[a2] + pn.v[a2]);
-        } else {
-            f[2] = ld3(Bf.pi, c.s, V);
-        }
-        if (!a.is_static) {
-            if (n > 0) {
-                // B_x = -(1/2t) D_y, B_y = +(1/2t) D_x, D_i = phi->_i - phi<-_i
-                const T h = T(1) / (T(2) * t);
-                const v3<T> fy = qtransport(L.link(1, c.s), ld3(Af.phi, c.yp, V));
-                const v3<T> by = qtransport(L.link(1, c.ym), ld3(Af.phi, c.ym, V), true);
-                const v3<T> fx = qtransport(L.link(0, c.s), ld3(Af.phi, c.xp, V));
-                const v3<T> bx = qtransport(L.link(0, c.xm), ld3(Af.phi, c.xm, V), true);
-#pragma unroll
-                for (int a2 = 0; a2 < 3; a2++) {
-                    f[3].v[a2] = -h * (fy.v[a2] - by.v[a2]);
-                    f[4].v[a2] = h * (fx.v[a2] - bx.v[a2]);
-                }
-            }
-            // B_eta = -(1/4) Proj[U_12 + U_{2,-1} + U_{-1,-2} + U_{-2,1}] at c
-            const q4<T> u1 = L.link(0, c.s), u2 = L.link(1, c.s);
-            const q4<T> c12 = qmul(qmul(u1, L.link(1, c.xp)), qmul(qadj(L.link(0, c.yp)), qadj(u2)));
-            const q4<T> c2m1 = qmul(qmul(u2, qadj(L.link(0, c.xmyp))), qmul(qadj(L.link(1, c.xm)), L.link(0, c.xm)));
-            const q4<T> cm1m2 = qmul(qmul(qadj(L.link(0, c.xm)), qadj(L.link(1, c.xmym))),
-                                     qmul(L.link(0, c.xmym), L.link(1, c.ym)));
-            const q4<T> cm21 = qmul(qmul(qadj(L.link(1, c.ym)), L.link(0, c.ym)), qmul(L.link(1, c.xpym), qadj(u1)));
-            const v3<T> pb = qproj(qadd(qadd(c12, c2m1), qadd(cm1m2, cm21)));
-#pragma unroll
-            for (int a2 = 0; a2 < 3; a2++) f[5].v[a2] = T(-0.25) * pb.v[a2];
+        for (int a2 = 0; a2 < 3; a2++) {
+            f[0].v[a2] = shF[0][a2][lane];
+            f[4].v[a2] = shF[0][3 + a2][lane];
+            f[1].v[a2] = shF[1][a2][lane];
+            f[3].v[a2] = shF[1][3 + a2][lane];
+            f[2].v[a2] = shF[2][a2][lane];
+            f[5].v[a2] = shF[2][3 + a2][lane];
         }
         T px = R(PPX), py = R(PPY), pe = R(PPETA), eta = R(PETA_);
         const T e1 = vdot(Q, f[0]), e2 = vdot(Q, f[1]), ee = vdot(Q, f[2]);
@@ -315,12 +351,12 @@ __global__ __launch_bounds__(256) void su2_push_kernel(Fields2<T> Af, Fields2<T>
         }
     }
     if (record_slot >= 0) {
-        const int ngroups = (np + 63) / 64, group = p >> 6, lane = (int)threadIdx.x & 63;
-        double* dst = partials + ((size_t)record_slot * ngroups + group) * 4;
+        const int ngroups = (np + 63) / 64;
+        double* dst = partials + ((size_t)record_slot * ngroups + blk) * 4;
 #pragma unroll
         for (int k = 0; k < 4; k++) {
             const double v = wave_sum(obs[k]);
-            if (lane == 0 && group < ngroups) dst[k] = v;
+            if (lane == 0) dst[k] = v;
         }
     }
 }
@@ -330,7 +366,7 @@ hipError_t launch_su2_push(const Fields2<T>& A, const Fields2<T>& B, const Parts
                            int* d_step, double* partials, int* err, hipStream_t st, const KTimer& tm)
 {
     if (a.np <= 0) return hipSuccess;
-    const int nb = (a.np + 255) / 256;
+    const int nb = (a.np + 63) / 64;
     klaunch(tm, su2_push_kernel<T>, dim3(8 * ((nb + 7) / 8)), dim3(256), st, A, B, P, a, d_step, partials, err);
     return hipGetLastError();
 }

@@ -207,6 +207,37 @@ def test_smallest_lattices(N, launch):
     compare_fields(ctx.state(), run.st)
 
 
+@pytest.mark.parametrize("n", [1, 63, 65])
+def test_partial_particle_groups(n):
+    """Four wavefronts share each group of 64 particles, and a single record
+    needs no reordering: a lone particle, a group one short of full and a
+    full group with a one-particle tail, moving on a 16^2 random state for 40
+    steps with the step graphs (reorderings every 16 steps inside them)
+    against the oracle; the broadening sums at 1e-10."""
+    print(f"case partial groups n={n}", flush=True)
+    N, L, n0, steps = 16, 3.0, 2, 40
+    a = oracle.lattice_spacing(L, N)
+    st = inputs.random_state(N, 55, eps_link=0.4)
+    P = inputs.random_particles(n, N, 56, p_scale=0.6)
+    ctx = cp.Context(glasma(N, L, steps=n0 + steps), particle_params(n, 0.3 / a, N, L, 0))
+    ctx.load_state(st, n=n0, particles=P)
+    ctx.evolve(1e9)
+    assert ctx.n == n0 + steps
+    run = oracle.Run(N, 0.125, st, P, mhat=0.3, n_form=0, n0=n0)
+    for _ in range(steps):
+        run.step()
+    assert run.errors == 0
+    got = ctx.get_state(cp.STATE_PARTICLES)
+    assert np.array_equal(got[:, 14:16], run.P[:, 14:16])
+    assert rel_err(got, run.P) <= TOL
+    obs = ctx.observables()
+    sums = run.observe() / (n * a * a)
+    for c in range(4):
+        assert abs(obs[-1, 1 + c] - sums[c]) <= 1e-10 * abs(sums[c]) + 1e-300, (c, obs[-1], sums)
+    compare_fields(ctx.state(), run.st)
+    ctx.close()
+
+
 def test_particle_order_does_not_matter():
     """Particles are independent given the fields: the same particles loaded
     in a shuffled order (the library reorders them by cell and hands the

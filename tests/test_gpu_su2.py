@@ -152,6 +152,36 @@ def test_su2_particles_against_oracle(mass, nf, rep):
     ctx.close()
 
 
+@pytest.mark.parametrize("n", [1, 63, 65])
+def test_su2_partial_particle_groups(n):
+    """Four wavefronts share each group of 64 particles: a lone particle, a
+    group one short of full, and a full group with a one-particle tail,
+    moving through a 16^2 event for 32 steps against the oracle (cells
+    exact, records at 1e-11, the sums at 1e-10)."""
+    N, steps = 16, 32
+    g = event(N, steps, L=3.0)
+    a = oracle.lattice_spacing(3.0, N)
+    p = dict(n=n, mass_GeV=0.5, pT_min_GeV=0.0, pT_max_GeV=2.0, azimuth_uniform=1, tau_form_fm=0.0, rep=0, seed=65)
+    print(f"case su2 partial groups n={n}", flush=True)
+    ctx = cp.Context(g, p)
+    ctx.init_mv()
+    P0 = ctx.get_state(cp.STATE_PARTICLES)
+    ctx.evolve(1e9)
+    st = su2.mv_initial_condition(N, 3.0, 2.0, 0.2, 10.0, 2, 61)
+    run = su2.Run(N, DT, st, P0, mhat=0.5 * a, n_form=0)
+    for _ in range(steps):
+        run.step()
+    assert run.errors == 0
+    got = ctx.get_state(cp.STATE_PARTICLES)
+    assert np.array_equal(got[:, 14:16], run.P[:, 14:16])
+    assert rel_err(got, run.P) <= TOL, rel_err(got, run.P)
+    obs = ctx.observables()
+    last = run.observe() / (n * a * a)
+    for k in range(4):
+        assert abs(obs[-1, 1 + k] - last[k]) <= 1e-10 * abs(last[k]) + 1e-300, (k, obs[-1], last)
+    ctx.close()
+
+
 def test_su2_fp32_against_oracle():
     N, steps, n = 32, 64, 400
     g = event(N, steps, L=4.0, precision=cp.FP32)

@@ -65,7 +65,8 @@ DTAU_FM = 0.125 * 6.0 / 512
 SITE_BYTES_SU2 = {"f64": 20 * 2 * 8, "f32": 20 * 2 * 4}
 PUSH_BYTES_SU2 = {"f64": (26 + 18 + 3 + 0.5) * 8, "f32": (26 + 18 + 3 + 0.5) * 4}
 # calibrated HBM counter readings per workload (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE)
-PMC_SUMMARIES = {w: os.path.join(ROOT, "profiles", f"pmc_{w}.txt") for w in ("512_fp64", "512_fp32", "jets_512_fp32")}
+PMC_SUMMARIES = {w: os.path.join(ROOT, "profiles", f"pmc_{w}.txt")
+                 for w in ("512_fp64", "512_fp32", "jets_512_fp32", "su2_512_fp64", "color_log_512_fp64")}
 KERNEL_SOURCES = os.path.join(ROOT, "paper_2303_05599_amd", "csrc")
 
 
@@ -300,22 +301,24 @@ def run_jets(steps, warmup, V, tune=True, fixed=None):
                                 "qhat_z_GeV2_c_per_fm": float(r["jet_transport"][-1, 3])}}
 
 
-def run_color_log(steps, warmup, V, ref):
+def run_color_log(steps, warmup, V, ref=None, tune=True):
     """The headline event with the alternative colour update of Sec. III.B
     (charges stepped by dQ/dt = i[Q, A.v] with A from the matrix logarithm of
     the links) over the same timed region; its broadening next to the
     rotation's."""
     import paper_2303_05599_amd as cp
     n_part = 100_000
-    r = run_event(cp.FP64, steps, warmup, True, charm(n_part, color_update=cp.COLOR_LOG))
-    k = rooflines(r, "fp64", n_part, V)
-    return {"workload": "the headline event (FP64) with the charges updated from the matrix logarithm of the links",
-            "ms_per_step": r["wall"] * 1e3 / steps,
-            "pushes_per_s": n_part * steps / r["wall"],
-            "push_kernel": k["push"], "launch": r["launch"],
-            "dpT2_rel_vs_rotation": float(r["obs"][-1, 1] / ref["obs"][-1, 1] - 1),
-            "dpL2_rel_vs_rotation": float(r["obs"][-1, 2] / ref["obs"][-1, 2] - 1),
-            "casimir_q2_max_drift": float(r["diag"][8])}
+    r = run_event(cp.FP64, steps, warmup, tune, charm(n_part, color_update=cp.COLOR_LOG))
+    k = rooflines(r, "fp64", n_part, V, "color_log_512_fp64")
+    out = {"workload": "the headline event (FP64) with the charges updated from the matrix logarithm of the links",
+           "ms_per_step": r["wall"] * 1e3 / steps,
+           "pushes_per_s": n_part * steps / r["wall"],
+           "push_kernel": k["push"], "launch": r["launch"],
+           "casimir_q2_max_drift": float(r["diag"][8])}
+    if ref is not None:
+        out["dpT2_rel_vs_rotation"] = float(r["obs"][-1, 1] / ref["obs"][-1, 1] - 1)
+        out["dpL2_rel_vs_rotation"] = float(r["obs"][-1, 2] / ref["obs"][-1, 2] - 1)
+    return out
 
 
 def run_su2(steps, warmup, V):
@@ -325,6 +328,7 @@ def run_su2(steps, warmup, V):
     n_part = 100_000
     r = run_event(cp.FP64, steps, warmup, False, charm(n_part), n_colors=2)
     tm = r["timing"]
+    pmc = read_pmc_summary(PMC_SUMMARIES["su2_512_fp64"])
     out = {"workload": "MV Glasma 512^2 as the headline event, gauge group SU(2), 1e5 charm quarks, FP64",
            "ms_per_step": r["wall"] * 1e3 / steps,
            "site_updates_per_s": V * steps / r["wall"],
@@ -335,8 +339,11 @@ def run_su2(steps, warmup, V):
         secs = ms / max(k, 1) * 1e-3
         ach = unit_bytes * units / secs / 1e9
         out["kernels"][key] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                               "frac": ach / HBM_PEAK_GBS, "kernel": name, "avg_launch_us": secs * 1e6,
-                               "bytes_per_unit": unit_bytes, "units_per_launch": units}
+                               "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": name,
+                               "avg_launch_us": secs * 1e6, "bytes_per_unit": unit_bytes, "units_per_launch": units}
+        if pmc and name in pmc:
+            fe, wr = pmc[name]
+            out["kernels"][key].update(traffic=fe + wr, traffic_read=fe, traffic_written=wr)
     out["dpT2_GeV2_last"] = float(r["obs"][-1, 1])
     out["gauss_max"] = float(r["diag"][1])
     return out
@@ -721,6 +728,9 @@ def main():
                     help="fix the store policy of the field update's new state (1: non-temporal) after tuning")
     ap.add_argument("--jets-only", action="store_true",
                     help="run only the jets workload and print its JSON (for profiling; not the benchmark line)")
+    ap.add_argument("--leg", choices=["su2", "color-log"], default=None,
+                    help="run only the SU(2) or the colour-logarithm leg and print its JSON (for profiling; not "
+                         "the benchmark line)")
     ap.add_argument("--push", choices=["tile", "gather"], default=None,
                     help="push mode before tuning (default: the library's; the tuner tries the fused step only "
                          "from the tile mode)")
@@ -755,6 +765,12 @@ def main():
     n_part = 100_000
     if args.jets_only:
         print(json.dumps(run_jets(args.steps, args.warmup, V, not args.no_tune, args.launch)))
+        return
+    if args.leg == "su2":
+        print(json.dumps(run_su2(args.steps, args.warmup, V)))
+        return
+    if args.leg == "color-log":
+        print(json.dumps(run_color_log(args.steps, args.warmup, V, tune=not args.no_tune)))
         return
     res = run_event(cp.FP64 if args.precision == "fp64" else cp.FP32, args.steps, args.warmup, not args.no_tune,
                     fixed=args.launch, nt=args.nt, push=args.push)
